@@ -1,0 +1,163 @@
+"""Seeded synthetic inputs shaped like the paper's two test-bed models (Sec. 3).
+
+This module only draws and assembles inputs: it holds none of the method's
+arithmetic (no basis expansion, no structure constants, no Q/K contraction,
+no integration). Both the GPU path and the CPU oracle receive exactly the
+arrays produced here.
+
+Models:
+  * Random Lindbladian (Sec. 3, second model): a Kossakowski matrix drawn from
+    the complex Wishart ensemble, gamma = N W W^dagger / Tr(W W^dagger) with W
+    an M x M complex Ginibre matrix (M = N^2 - 1), given directly in the
+    generator basis. A GUE Hamiltonian is added (the paper's model has H = 0;
+    ``hamiltonian="zero"`` reproduces that).
+  * Bosonic dimer (Sec. 3, first model, static drive): N-1 bosons on two
+    sites in the Fock basis |n, N-1-n>, n = 0..N-1. Hopping -J(b1^+ b2 + h.c.),
+    on-site interaction 2U/(N-1) sum_j n_j(n_j - 1), static offset eps(n2 - n1),
+    and one jump operator.
+
+Conventions: complex Gaussians have Re, Im ~ N(0, 1/2) (E|z|^2 = 1). Host
+draws use numpy's PCG64 ``default_rng(seed)``. The largest Kossakowski
+matrices (N = 200, 25.6 GB) are drawn on the device with torch's seeded
+generator; they are exactly Hermitian (gamma_kj == conj(gamma_jk) bit for bit),
+which the GPU library relies on.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.default_rng(seed)
+
+
+def ginibre(g: np.random.Generator, n: int, m: int | None = None) -> np.ndarray:
+    m = n if m is None else m
+    return (g.standard_normal((n, m)) + 1j * g.standard_normal((n, m))) * np.sqrt(0.5)
+
+
+def hermitize(A: np.ndarray) -> np.ndarray:
+    """(A + A^dagger)/2, exactly Hermitian elementwise."""
+    return (A + A.conj().T) * 0.5
+
+
+def gue_hamiltonian(N: int, seed: int) -> np.ndarray:
+    """H = (G + G^dagger)/sqrt(2N): E|H_ij|^2 = 1/N, spectrum on [-2, 2]."""
+    G = ginibre(rng(seed), N)
+    return hermitize(G) * np.sqrt(2.0 / N)
+
+
+def plain_hamiltonian(N: int, seed: int) -> np.ndarray:
+    """H = (G + G^dagger)/2 with G an N x N complex Gaussian matrix."""
+    return hermitize(ginibre(rng(seed), N))
+
+
+def wishart_kossakowski(N: int, seed: int) -> np.ndarray:
+    """gamma = N W W^dagger / Tr(W W^dagger), W an M x M complex Ginibre matrix."""
+    M = N * N - 1
+    W = ginibre(rng(seed), M)
+    A = hermitize(W @ W.conj().T)
+    return A * (N / np.trace(A).real)
+
+
+def random_lindbladian(N: int, seed: int, hamiltonian: str = "gue"):
+    """(H, gamma) for the dense random model. Seeds: H from seed, gamma from seed + 1."""
+    if hamiltonian == "gue":
+        H = gue_hamiltonian(N, seed)
+    elif hamiltonian == "plain":
+        H = plain_hamiltonian(N, seed)
+    elif hamiltonian == "zero":
+        H = np.zeros((N, N), np.complex128)
+    else:
+        raise ValueError(hamiltonian)
+    return H, wishart_kossakowski(N, seed + 1)
+
+
+def random_pure_state(N: int, seed: int) -> np.ndarray:
+    g = rng(seed)
+    psi = (g.standard_normal(N) + 1j * g.standard_normal(N)) * np.sqrt(0.5)
+    return psi / np.linalg.norm(psi)
+
+
+def random_pure_states(N: int, B: int, seed: int) -> np.ndarray:
+    """(B, N) complex128, each row a normalised complex Gaussian vector."""
+    g = rng(seed)
+    psi = (g.standard_normal((B, N)) + 1j * g.standard_normal((B, N))) * np.sqrt(0.5)
+    return psi / np.linalg.norm(psi, axis=1, keepdims=True)
+
+
+# ---------------------------------------------------------------------------
+# Bosonic dimer (Sec. 3, first model)
+# ---------------------------------------------------------------------------
+
+def dimer_hamiltonian(N: int, J: float = 1.0, U: float = 0.5, eps: float = 0.0) -> np.ndarray:
+    """N-1 bosons on two sites; basis |n1 = n, n2 = N-1-n>. Tridiagonal, real."""
+    nb = N - 1
+    n1 = np.arange(N, dtype=np.float64)
+    n2 = nb - n1
+    H = np.zeros((N, N), np.complex128)
+    diag = (2.0 * U / max(nb, 1)) * (n1 * (n1 - 1) + n2 * (n2 - 1)) + eps * (n2 - n1)
+    H[np.arange(N), np.arange(N)] = diag
+    # b1^+ b2 |n1, n2> = sqrt((n1+1) n2) |n1+1, n2-1>
+    amp = np.sqrt((n1[:-1] + 1) * n2[:-1])
+    H[np.arange(1, N), np.arange(N - 1)] += -J * amp
+    H[np.arange(N - 1), np.arange(1, N)] += -J * amp
+    return H
+
+
+def dimer_jump_a1dag_a2(N: int) -> np.ndarray:
+    """L = b1^+ b2: L_{n+1, n} = sqrt((n+1)(N-1-n)). Traceless, non-Hermitian."""
+    nb = N - 1
+    n = np.arange(N - 1, dtype=np.float64)
+    L = np.zeros((N, N), np.complex128)
+    L[np.arange(1, N), np.arange(N - 1)] = np.sqrt((n + 1) * (nb - n))
+    return L
+
+
+def dimer_model(N: int, J: float = 1.0, U: float = 0.5, eps: float = 0.0, gamma: float = 0.1):
+    """(H, rates, [L]) for the static dimer with one jump operator b1^+ b2 at rate gamma/(N-1)."""
+    H = dimer_hamiltonian(N, J, U, eps)
+    L = dimer_jump_a1dag_a2(N)
+    return H, np.array([gamma / max(N - 1, 1)]), [L]
+
+
+def to_csr(A: np.ndarray):
+    """Dense N x N complex -> (rowptr int64, col int64, val complex128), zeros dropped."""
+    A = np.asarray(A)
+    nz = A != 0
+    rowptr = np.zeros(A.shape[0] + 1, np.int64)
+    rowptr[1:] = np.cumsum(nz.sum(axis=1))
+    r, c = np.nonzero(nz)
+    return rowptr, c.astype(np.int64), A[r, c].astype(np.complex128)
+
+
+# ---------------------------------------------------------------------------
+# Device-side draw for the largest Kossakowski matrices
+# ---------------------------------------------------------------------------
+
+def wishart_kossakowski_device(N: int, seed: int, device="cuda", block: int = 4096):
+    """gamma = N W W^dagger / Tr(W W^dagger) drawn on the GPU (torch), complex128.
+
+    W is drawn in complex64 and W W^dagger is formed by the vendor GEMM; the
+    product is promoted to complex128 and Hermitized block by block so that
+    gamma is exactly Hermitian. Deterministic for a given seed and device.
+    """
+    import torch
+
+    M = N * N - 1
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    W = torch.randn(M, M, dtype=torch.complex64, device=device, generator=gen)
+    A = W @ W.mH
+    del W
+    out = torch.empty(M, M, dtype=torch.complex128, device=device)
+    for i0 in range(0, M, block):
+        i1 = min(M, i0 + block)
+        top = A[i0:i1, :].to(torch.complex128)
+        left = A[:, i0:i1].mH.to(torch.complex128)
+        out[i0:i1, :] = (top + left) * 0.5
+        del top, left
+    del A
+    tr = out.diagonal().real.sum()
+    out *= (N / tr)
+    return out
