@@ -1,0 +1,230 @@
+/*
+ * lindblad.h -- C ABI of the MI355X (gfx950) library that turns a GKSL master
+ * equation into the real linear ODE dv/dt = Q v + K over the generalized
+ * Gell-Mann basis and integrates it with classic fourth-order Runge-Kutta.
+ *
+ * Method: Meyerov, Kozinov, Liniov, Volokitin, Yusipov, Ivanchenko, Denisov,
+ * "Transforming Lindblad Equations into Systems of Real-Valued Linear
+ * Equations: Performance Optimization and Parallelization of an Algorithm",
+ * arXiv:1912.01491. Equation numbers count the displayed equations of
+ * Sections 2-3 in order: (1)-(2) the Lindbladian and its dissipator,
+ * (3)-(5) the S, J, D generators, (6) expansion of a Hermitian matrix,
+ * (7) the coherence vector, (10) the real ODE, (11) f and d, (12) z,
+ * (13) q, (14) k, (15) r. "Table 1" is the paper's algorithm table.
+ *
+ * Conventions (all entry points):
+ *  - N is the Hilbert-space dimension (2 <= N <= LB_MAX_N), M = N*N - 1.
+ *  - Basis order, 0-based: S^(j,k) for pairs j<k in row-major pair order
+ *    (position j*N - j*(j+1)/2 + k-j-1), then J^(j,k) in the same order
+ *    (offset P = N(N-1)/2), then D^1..D^{N-1} (offset 2P). D^l is
+ *    (sum_{x<l} e_x e_x^T - l e_l e_l^T) / sqrt(l(l+1)) with 0-based rows,
+ *    the Hermitian, trace-orthonormal reading of Eq. (5).
+ *  - Complex arrays are interleaved (re, im) doubles, i.e. the layout of
+ *    torch.complex128 / numpy complex128. Matrices are row-major.
+ *  - Pointers documented "device" are HIP device memory (e.g. torch CUDA
+ *    tensors); "host" pointers are ordinary memory. The caller owns every
+ *    buffer it passes and keeps it alive until the context stream has
+ *    reached the call's completion; the library never frees caller memory.
+ *  - Calls that take a context are asynchronous on that context's stream
+ *    unless they are documented to return a value to the host (those
+ *    synchronize the stream). lb_sync() waits for completion.
+ *  - Every function returns LB_OK (0) or a negative status; lb_last_error()
+ *    returns a message for the last failure on the calling thread.
+ *  - The dissipator is sum_jk gamma_jk (F_j rho F_k - 1/2 {F_k F_j, rho})
+ *    with gamma = sum_p g_p l_p l_p^dagger (Eqs. (8), (14), (15)).
+ */
+#ifndef LINDBLAD_H
+#define LINDBLAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_OK 0
+#define LB_ERR_INVALID_ARG (-1)   /* null pointer, N out of range, bad sizes, dt not finite, ... */
+#define LB_ERR_NOT_HERMITIAN (-2) /* LB_CHECK_HERMITIAN was set and an input is not Hermitian */
+#define LB_ERR_OOM (-3)           /* the context workspace could not be allocated */
+#define LB_ERR_DEVICE (-4)        /* a HIP call failed; see lb_last_error() */
+#define LB_ERR_UNSUPPORTED (-5)   /* valid request this build cannot serve (e.g. too large) */
+#define LB_ERR_ADMISSION (-6)     /* a serving request does not fit the server's memory budget */
+
+#define LB_MAX_N 1024             /* largest Hilbert-space dimension accepted */
+
+/* lindblad_prepare flags */
+#define LB_CHECK_HERMITIAN 1u     /* verify H and gamma are Hermitian (extra pass, synchronizes) */
+
+/* propagation precision */
+#define LB_FP64 0                 /* FP64 storage and arithmetic */
+#define LB_FP32 1                 /* Q stored in FP32, FP32 MFMA products, FP64 state and combination */
+
+typedef struct lb_ctx lb_ctx;
+
+/* ------------------------------------------------------------------ */
+/* Context                                                            */
+/* ------------------------------------------------------------------ */
+
+/* Creates a context on HIP device `device`. `stream` is the hipStream_t the
+ * context enqueues on (NULL: the device's default stream). The context owns
+ * a device workspace and a pinned host staging buffer that grow on demand
+ * and are freed by lb_destroy. A context is not thread-safe; use one per
+ * thread. */
+int lb_create(lb_ctx** ctx, int device, void* stream);
+int lb_destroy(lb_ctx* ctx);
+/* Switches the stream subsequent calls are enqueued on (NULL: default stream);
+ * waits for the previous stream first. */
+int lb_set_stream(lb_ctx* ctx, void* stream);
+/* Blocks until all work enqueued through the context has finished. */
+int lb_sync(lb_ctx* ctx);
+/* Message describing the last failing call on this thread ("" if none). */
+const char* lb_last_error(void);
+/* Library version, e.g. 100 for 0.1.0. */
+int lb_version(void);
+
+/* ------------------------------------------------------------------ */
+/* Basis index generator (Sec. 2, Eqs. (3)-(5))                        */
+/* ------------------------------------------------------------------ */
+
+/* Host, pure: basis position i -> class (0 = S, 1 = J, 2 = D) and (j, k);
+ * for D, *j = l in 1..N-1 and *k = 0. */
+int lb_basis_index(int N, int64_t i, int32_t* cls, int32_t* j, int32_t* k);
+
+/* Device: writes table[3*i + {0,1,2}] = (class, j, k) for all i < M.
+ * table: device int32, 3*M entries. Integer-exact. */
+int lb_basis_table(lb_ctx* ctx, int N, int32_t* table);
+
+/* ------------------------------------------------------------------ */
+/* Nonzero structure constants (Eq. (11), Table 1 step 2.2)            */
+/* ------------------------------------------------------------------ */
+
+/* Number of ordered triples (m, n, s) with f_mns != 0 (which = 0) or
+ * d_mns != 0 (which = 1). Runs the GPU count phase; synchronizes. */
+int lb_fd_count(lb_ctx* ctx, int N, int which, int64_t* count);
+
+/* Writes every ordered nonzero triple: mns[3*e + {0,1,2}] = (m, n, s) and
+ * val[e] = f_mns or d_mns, grouped by m in increasing order. mns (device
+ * int32, 3*cap) and val (device double, cap) must hold `cap` entries;
+ * *count (host) receives the total. Fails with LB_ERR_INVALID_ARG when
+ * cap < total (nothing is written then). Synchronizes. */
+int lb_fd_enumerate(lb_ctx* ctx, int N, int which, int32_t* mns, double* val, int64_t cap, int64_t* count);
+
+/* ------------------------------------------------------------------ */
+/* Expansion and reconstruction (Eqs. (6), (7); Table 1 steps 2.1,     */
+/* 2.6, 3.2)                                                           */
+/* ------------------------------------------------------------------ */
+
+/* a[b*M + j] = Re Tr(F_j A_b) for B Hermitian N x N complex matrices
+ * A (device, B*N*N complex) -> a (device, B*M double). */
+int lb_expand(lb_ctx* ctx, int N, int B, const double* A, double* a);
+
+/* Coherence vectors of B pure states: V[b*M + j] = <psi_b| F_j |psi_b>.
+ * psi: device, B*N complex (normalised by the caller). V: device, B*M. */
+int lb_expand_pure(lb_ctx* ctx, int N, int B, const double* psi, double* V);
+
+/* rho_b = 1/N + sum_j V[b*M + j] F_j (Eq. (7)); rho: device, B*N*N complex. */
+int lb_reconstruct(lb_ctx* ctx, int N, int B, const double* V, double* rho);
+
+/* ------------------------------------------------------------------ */
+/* Dense data preparation (Eqs. (13)-(15); Table 1 steps 2.1-2.5)      */
+/* ------------------------------------------------------------------ */
+
+/* Builds Q = Q_H + Q_D (the paper's Q(t) + R) and K for a Hamiltonian H
+ * (device, N*N complex, Hermitian) and a Kossakowski matrix gamma (device,
+ * M*M complex, Hermitian, in the basis order above). Writes Q (device,
+ * M rows of leading dimension ldq >= M doubles; columns M..ldq-1 are set to
+ * zero) and K (device, M doubles). gamma is read assuming exact Hermiticity
+ * (entries may be read from either triangle). The identity part of H is
+ * irrelevant. FP64 throughout. */
+int lindblad_prepare(lb_ctx* ctx, int N, const double* H, const double* gamma,
+                     double* Q, int64_t ldq, double* K, unsigned flags);
+
+/* ------------------------------------------------------------------ */
+/* Sparse data preparation: gamma = sum_p g_p l_p l_p^dagger given by  */
+/* jump operators (Sec. 2, spectral form of the Kossakowski matrix)    */
+/* ------------------------------------------------------------------ */
+
+/* An N x N complex matrix in CSR form; all arrays device memory. */
+typedef struct lb_csr_c128 {
+    const int64_t* rowptr; /* N+1 */
+    const int64_t* col;    /* nnz */
+    const double* val;     /* nnz complex (interleaved) */
+    int64_t nnz;
+} lb_csr_c128;
+
+/* Phase 1 (count): the number of stored entries of Q for the Hamiltonian H
+ * and P jump operators L_p with rates g_p >= 0 (rates: host, P doubles).
+ * Each row s of Q holds the expansion of the adjoint generator applied to
+ * F_s. A nonzero trace of L_p is moved into the Hamiltonian
+ * (H += (i g_p / 2)(conj(c) L0 - c L0^dagger), c = Tr L_p / N, L0 = L_p - c).
+ * Synchronizes; *nnz (host) receives the count. */
+int lindblad_prepare_sparse_count(lb_ctx* ctx, int N, const lb_csr_c128* H, int P,
+                                  const double* rates, const lb_csr_c128* L, int64_t* nnz);
+
+/* Phase 2 (fill): writes Q in CSR form (rowptr: device int64 M+1; col:
+ * device int64 nnz; val: device double nnz; columns sorted within a row)
+ * and K (device, M doubles). nnz must be the value phase 1 returned. */
+int lindblad_prepare_sparse_fill(lb_ctx* ctx, int N, const lb_csr_c128* H, int P,
+                                 const double* rates, const lb_csr_c128* L, int64_t nnz,
+                                 int64_t* rowptr, int64_t* col, double* val, double* K);
+
+/* ------------------------------------------------------------------ */
+/* RK4 propagation of dv/dt = Q v + K (Eq. (10); Table 1 step 3.1)      */
+/* ------------------------------------------------------------------ */
+
+/* Integrates B states over `steps` classic RK4 steps of size dt (weights
+ * 1/6, 1/3, 1/3, 1/6; K constant). V (device, B*M doubles, state b at
+ * V + b*M) holds v(0) on entry and v(steps*dt) on exit. Q: device, M rows
+ * of leading dimension ldq. precision LB_FP64 uses Q directly; LB_FP32
+ * requires Q32 (device float, same ldq) from lindblad_q_to_f32 and ignores
+ * Q. Bit-for-bit deterministic for fixed inputs and launch configuration. */
+int lindblad_propagate(lb_ctx* ctx, int64_t M, const double* Q, const float* Q32, int64_t ldq,
+                       const double* K, double* V, int B, double dt, int64_t steps, int precision);
+
+/* Q32[i*ldq + j] = (float)Q[i*ldq + j] for i < M, j < ldq (device buffers). */
+int lindblad_q_to_f32(lb_ctx* ctx, int64_t M, const double* Q, int64_t ldq, float* Q32);
+
+/* CSR variant: Q given by rowptr/col/val (device, as written by
+ * lindblad_prepare_sparse_fill). FP64. */
+int lindblad_propagate_csr(lb_ctx* ctx, int64_t M, const int64_t* rowptr, const int64_t* col,
+                           const double* val, const double* K, double* V, int B,
+                           double dt, int64_t steps);
+
+/* Batched variant: R independent systems of the same M (e.g. ensemble
+ * realizations), Q[r], K[r], V[r] device pointers given in host arrays of
+ * length R; each V[r] holds B states. One launch per RK4 stage covers all
+ * systems. Same precision rules as lindblad_propagate (Q32 may be NULL for
+ * LB_FP64). */
+int lindblad_propagate_batched(lb_ctx* ctx, int R, int64_t M, const double* const* Q,
+                               const float* const* Q32, int64_t ldq, const double* const* K,
+                               double* const* V, int B, double dt, int64_t steps, int precision);
+
+/* Records the RK4 stage launches of `steps` steps into a HIP graph on first
+ * use for a given (M, B, ldq, precision, buffers, dt, steps) and replays it
+ * afterwards; otherwise identical to lindblad_propagate. */
+int lindblad_propagate_graph(lb_ctx* ctx, int64_t M, const double* Q, const float* Q32, int64_t ldq,
+                             const double* K, double* V, int B, double dt, int64_t steps, int precision);
+
+/* ------------------------------------------------------------------ */
+/* Tuning                                                             */
+/* ------------------------------------------------------------------ */
+
+/* Times the candidate GEMM tile shapes for (M, B, precision) on the context
+ * stream and keeps the fastest for later propagate calls in this process
+ * (and in the cache file named by the LB_TUNE_CACHE environment variable,
+ * if set). Q/Q32 and K as for lindblad_propagate; V is scratch (B*M). */
+int lindblad_autotune(lb_ctx* ctx, int64_t M, const double* Q, const float* Q32, int64_t ldq,
+                      const double* K, double* V, int B, int precision);
+
+/* Describes the tile shape propagate will use for (M, B, precision):
+ * rows per wave, k-slab length, waves per workgroup, and whether it came
+ * from the tuner (1) or the default table (0). Host only. */
+int lindblad_tile_info(lb_ctx* ctx, int64_t M, int B, int precision, int* rows, int* kslab,
+                       int* waves, int* tuned);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LINDBLAD_H */

@@ -1,0 +1,397 @@
+"""Python binding of the gfx950 GKSL -> real-ODE library (liblindblad.so).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in ``include/lindblad.h``. torch provides
+device memory and streams. The binding raises ``LibraryMissing`` when the
+shared library has not been built; there is no fallback implementation.
+
+Typical use::
+
+    import torch, paper_1912_01491_amd as lb
+    ctx = lb.Context()                        # torch's current stream
+    Q, K = lb.lindblad_prepare(ctx, H, gamma) # H: (N,N) c128, gamma: (M,M) c128 on cuda
+    V = lb.lb_expand_pure(ctx, psi)           # (B, M) coherence vectors
+    lb.lindblad_propagate(ctx, Q, K, V, dt=1e-3, steps=1000)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "LibraryMissing", "LindbladError", "Context", "library_path", "load",
+    "lb_basis_index", "lb_basis_table", "lb_fd_count", "lb_fd_enumerate",
+    "lb_expand", "lb_expand_pure", "lb_reconstruct",
+    "lindblad_prepare", "lindblad_q_to_f32", "lindblad_propagate", "lindblad_propagate_batched",
+    "lindblad_propagate_graph", "lindblad_propagate_csr", "lindblad_prepare_sparse",
+    "lindblad_autotune", "lindblad_tile_info",
+    "FP64", "FP32", "CHECK_HERMITIAN",
+]
+
+FP64 = 0
+FP32 = 1
+CHECK_HERMITIAN = 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_build", "liblindblad.so")
+_lib = None
+
+_ERRORS = {-1: "invalid argument", -2: "not Hermitian", -3: "out of memory", -4: "device error",
+           -5: "unsupported", -6: "admission"}
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class LindbladError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (_ERRORS.get(code, "error"), code, msg))
+        self.code = code
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+class _CSR(ctypes.Structure):
+    _fields_ = [("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("nnz", ctypes.c_int64)]
+
+
+def load():
+    """Loads liblindblad.so (built by ``paper_1912_01491_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise LibraryMissing("%s is not built; run `python -m paper_1912_01491_amd.build` "
+                             "or __graft_entry__.build()" % _LIB_PATH)
+    lib = ctypes.CDLL(_LIB_PATH)
+    V, I, I64, D, U = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_uint
+    sig = {
+        "lb_create": [ctypes.POINTER(ctypes.c_void_p), I, V],
+        "lb_destroy": [V],
+        "lb_set_stream": [V, V],
+        "lb_sync": [V],
+        "lb_version": [],
+        "lb_basis_index": [I, I64, V, V, V],
+        "lb_basis_table": [V, I, V],
+        "lb_fd_count": [V, I, I, V],
+        "lb_fd_enumerate": [V, I, I, V, V, I64, V],
+        "lb_expand": [V, I, I, V, V],
+        "lb_expand_pure": [V, I, I, V, V],
+        "lb_reconstruct": [V, I, I, V, V],
+        "lindblad_prepare": [V, I, V, V, V, I64, V, U],
+        "lindblad_prepare_sparse_count": [V, I, V, I, V, V, V],
+        "lindblad_prepare_sparse_fill": [V, I, V, I, V, V, I64, V, V, V, V],
+        "lindblad_propagate": [V, I64, V, V, I64, V, V, I, D, I64, I],
+        "lindblad_q_to_f32": [V, I64, V, I64, V],
+        "lindblad_propagate_csr": [V, I64, V, V, V, V, V, I, D, I64],
+        "lindblad_propagate_batched": [V, I, I64, V, V, I64, V, V, I, D, I64, I],
+        "lindblad_propagate_graph": [V, I64, V, V, I64, V, V, I, D, I64, I],
+        "lindblad_autotune": [V, I64, V, V, I64, V, V, I, I],
+        "lindblad_tile_info": [V, I64, I, I, V, V, V, V],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = I
+    lib.lb_last_error.argtypes = []
+    lib.lb_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise LindbladError(rc, load().lb_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA (HIP) torch tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+class Context:
+    """A library context bound to a device and a stream (default: torch's
+    current stream on that device)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        h = ctypes.c_void_p()
+        _check(lib.lb_create(ctypes.byref(h), int(device), ctypes.c_void_p(handle or None)))
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_stream(self, stream):
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        _check(load().lb_set_stream(self._h, ctypes.c_void_p(handle or None)))
+
+    def sync(self):
+        _check(load().lb_sync(self._h))
+
+    def close(self):
+        if self._h:
+            load().lb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def _dev(ctx):
+    import torch
+    return torch.device("cuda", ctx.device)
+
+
+# ---------------------------------------------------------------------------
+# basis and structure constants
+# ---------------------------------------------------------------------------
+
+def lb_basis_index(N: int, i: int):
+    c, j, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().lb_basis_index(int(N), int(i), ctypes.byref(c), ctypes.byref(j), ctypes.byref(k)))
+    return c.value, j.value, k.value
+
+
+def lb_basis_table(ctx: Context, N: int):
+    import torch
+    M = N * N - 1
+    t = torch.empty((M, 3), dtype=torch.int32, device=_dev(ctx))
+    _check(load().lb_basis_table(ctx.handle, int(N), _ptr(t)))
+    return t
+
+
+def lb_fd_count(ctx: Context, N: int, which: str) -> int:
+    n = ctypes.c_int64()
+    _check(load().lb_fd_count(ctx.handle, int(N), {"f": 0, "d": 1}[which], ctypes.byref(n)))
+    return n.value
+
+
+def lb_fd_enumerate(ctx: Context, N: int, which: str):
+    """(mns int32 (count, 3), val float64 (count,)) on the device."""
+    import torch
+    cnt = lb_fd_count(ctx, N, which)
+    mns = torch.empty((max(cnt, 1), 3), dtype=torch.int32, device=_dev(ctx))
+    val = torch.empty(max(cnt, 1), dtype=torch.float64, device=_dev(ctx))
+    n = ctypes.c_int64()
+    _check(load().lb_fd_enumerate(ctx.handle, int(N), {"f": 0, "d": 1}[which], _ptr(mns), _ptr(val),
+                                  cnt, ctypes.byref(n)))
+    return mns[:n.value], val[:n.value]
+
+
+# ---------------------------------------------------------------------------
+# expansion
+# ---------------------------------------------------------------------------
+
+def lb_expand(ctx: Context, A):
+    """A: (B, N, N) or (N, N) complex128 Hermitian -> (B, M) or (M,) float64."""
+    import torch
+    squeeze = A.dim() == 2
+    A3 = A.unsqueeze(0) if squeeze else A
+    _need(A3, torch.complex128, "A")
+    B, N = A3.shape[0], A3.shape[1]
+    out = torch.empty((B, N * N - 1), dtype=torch.float64, device=A.device)
+    _check(load().lb_expand(ctx.handle, N, B, _ptr(A3), _ptr(out)))
+    return out[0] if squeeze else out
+
+
+def lb_expand_pure(ctx: Context, psi):
+    """psi: (B, N) or (N,) complex128 -> coherence vectors (B, M) float64."""
+    import torch
+    psi2 = psi.unsqueeze(0) if psi.dim() == 1 else psi
+    _need(psi2, torch.complex128, "psi")
+    B, N = psi2.shape
+    out = torch.empty((B, N * N - 1), dtype=torch.float64, device=psi.device)
+    _check(load().lb_expand_pure(ctx.handle, N, B, _ptr(psi2), _ptr(out)))
+    return out
+
+
+def lb_reconstruct(ctx: Context, V, N: int):
+    import torch
+    V2 = V.unsqueeze(0) if V.dim() == 1 else V
+    _need(V2, torch.float64, "V")
+    B = V2.shape[0]
+    rho = torch.empty((B, N, N), dtype=torch.complex128, device=V.device)
+    _check(load().lb_reconstruct(ctx.handle, N, B, _ptr(V2), _ptr(rho)))
+    return rho
+
+
+# ---------------------------------------------------------------------------
+# data preparation
+# ---------------------------------------------------------------------------
+
+def default_ldq(M: int) -> int:
+    """Leading dimension used by default: M rounded up to 16 doubles (128 B rows)."""
+    return (M + 15) // 16 * 16
+
+
+def lindblad_prepare(ctx: Context, H, gamma, ldq: int | None = None, Q=None, K=None,
+                     check_hermitian: bool = False):
+    """Dense Q (M x ldq, columns >= M zero) and K (M) for H (N,N) and gamma (M,M), complex128."""
+    import torch
+    _need(H, torch.complex128, "H")
+    _need(gamma, torch.complex128, "gamma")
+    N = H.shape[0]
+    M = N * N - 1
+    if gamma.shape != (M, M):
+        raise ValueError("gamma must be (%d, %d)" % (M, M))
+    ldq = default_ldq(M) if ldq is None else int(ldq)
+    if Q is None:
+        Q = torch.empty((M, ldq), dtype=torch.float64, device=H.device)
+    if K is None:
+        K = torch.empty(M, dtype=torch.float64, device=H.device)
+    _need(Q, torch.float64, "Q")
+    _need(K, torch.float64, "K")
+    if Q.shape != (M, ldq) or K.shape != (M,):
+        raise ValueError("Q must be (M, ldq) and K (M,)")
+    _check(load().lindblad_prepare(ctx.handle, N, _ptr(H), _ptr(gamma), _ptr(Q), ldq, _ptr(K),
+                                   CHECK_HERMITIAN if check_hermitian else 0))
+    return Q, K
+
+
+def _csr_struct(rowptr, col, val):
+    import torch
+    _need(rowptr, torch.int64, "rowptr")
+    _need(col, torch.int64, "col")
+    _need(val, torch.complex128, "val")
+    return _CSR(rowptr.data_ptr(), col.data_ptr(), val.data_ptr(), int(col.numel()))
+
+
+def lindblad_prepare_sparse(ctx: Context, N: int, H_csr, rates, L_csrs):
+    """Sparse Q (CSR: rowptr, col, val) and K for H and jump operators L_p with
+    rates g_p. Each CSR is a tuple (rowptr int64, col int64, val complex128) on
+    the device."""
+    import torch
+    lib = load()
+    M = N * N - 1
+    Hs = _csr_struct(*H_csr)
+    P = len(L_csrs)
+    Ls = (_CSR * max(P, 1))(*[_csr_struct(*l) for l in L_csrs])
+    r = (ctypes.c_double * max(P, 1))(*[float(x) for x in rates])
+    nnz = ctypes.c_int64()
+    _check(lib.lindblad_prepare_sparse_count(ctx.handle, N, ctypes.byref(Hs), P, r, Ls, ctypes.byref(nnz)))
+    dev = _dev(ctx)
+    rowptr = torch.empty(M + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(max(nnz.value, 1), dtype=torch.int64, device=dev)
+    val = torch.empty(max(nnz.value, 1), dtype=torch.float64, device=dev)
+    K = torch.empty(M, dtype=torch.float64, device=dev)
+    _check(lib.lindblad_prepare_sparse_fill(ctx.handle, N, ctypes.byref(Hs), P, r, Ls, nnz.value,
+                                            _ptr(rowptr), _ptr(col), _ptr(val), _ptr(K)))
+    return rowptr, col[:nnz.value], val[:nnz.value], K
+
+
+# ---------------------------------------------------------------------------
+# propagation
+# ---------------------------------------------------------------------------
+
+def lindblad_q_to_f32(ctx: Context, Q):
+    import torch
+    _need(Q, torch.float64, "Q")
+    Q32 = torch.empty(Q.shape, dtype=torch.float32, device=Q.device)
+    _check(load().lindblad_q_to_f32(ctx.handle, Q.shape[0], _ptr(Q), Q.shape[1], _ptr(Q32)))
+    return Q32
+
+
+def _prop_args(Q, Q32, K, V, precision):
+    import torch
+    if precision == FP64:
+        _need(Q, torch.float64, "Q")
+        M, ldq = Q.shape
+    else:
+        _need(Q32, torch.float32, "Q32")
+        M, ldq = Q32.shape
+    _need(K, torch.float64, "K")
+    _need(V, torch.float64, "V")
+    if V.dim() != 2 or V.shape[1] != M or K.shape != (M,):
+        raise ValueError("V must be (B, M) and K (M,) with M = %d" % M)
+    return M, ldq
+
+
+def lindblad_propagate(ctx: Context, Q, K, V, dt: float, steps: int, precision: int = FP64, Q32=None):
+    """In place: V (B, M) <- RK4 solution after `steps` steps of size dt."""
+    M, ldq = _prop_args(Q, Q32, K, V, precision)
+    _check(load().lindblad_propagate(ctx.handle, M, _ptr(Q) if Q is not None else None,
+                                     _ptr(Q32) if Q32 is not None else None, ldq, _ptr(K), _ptr(V),
+                                     V.shape[0], float(dt), int(steps), int(precision)))
+    return V
+
+
+def lindblad_propagate_graph(ctx: Context, Q, K, V, dt: float, steps: int, precision: int = FP64, Q32=None):
+    M, ldq = _prop_args(Q, Q32, K, V, precision)
+    _check(load().lindblad_propagate_graph(ctx.handle, M, _ptr(Q) if Q is not None else None,
+                                           _ptr(Q32) if Q32 is not None else None, ldq, _ptr(K), _ptr(V),
+                                           V.shape[0], float(dt), int(steps), int(precision)))
+    return V
+
+
+def lindblad_propagate_batched(ctx: Context, Qs, Ks, Vs, dt: float, steps: int, precision: int = FP64,
+                               Q32s=None):
+    """R systems of the same M; Vs[r] is (B, M), updated in place."""
+    R = len(Ks)
+    for r in range(R):
+        M, ldq = _prop_args(Qs[r] if Qs else None, Q32s[r] if Q32s else None, Ks[r], Vs[r], precision)
+    B = Vs[0].shape[0]
+    arr = ctypes.c_void_p * R
+    qa = arr(*[q.data_ptr() for q in Qs]) if Qs else None
+    q32a = arr(*[q.data_ptr() for q in Q32s]) if Q32s else None
+    ka = arr(*[k.data_ptr() for k in Ks])
+    va = arr(*[v.data_ptr() for v in Vs])
+    _check(load().lindblad_propagate_batched(ctx.handle, R, M, qa, q32a, ldq, ka, va, B, float(dt), int(steps),
+                                             int(precision)))
+    return Vs
+
+
+def lindblad_propagate_csr(ctx: Context, rowptr, col, val, K, V, dt: float, steps: int):
+    import torch
+    _need(rowptr, torch.int64, "rowptr")
+    _need(val, torch.float64, "val")
+    _need(K, torch.float64, "K")
+    _need(V, torch.float64, "V")
+    M = rowptr.numel() - 1
+    _check(load().lindblad_propagate_csr(ctx.handle, M, _ptr(rowptr), _ptr(col), _ptr(val), _ptr(K), _ptr(V),
+                                         V.shape[0], float(dt), int(steps)))
+    return V
+
+
+def lindblad_autotune(ctx: Context, Q, K, B: int, precision: int = FP64, Q32=None):
+    import torch
+    M = (Q if precision == FP64 else Q32).shape[0]
+    ldq = (Q if precision == FP64 else Q32).shape[1]
+    V = torch.zeros((B, M), dtype=torch.float64, device=K.device)
+    _check(load().lindblad_autotune(ctx.handle, M, _ptr(Q) if Q is not None else None,
+                                    _ptr(Q32) if Q32 is not None else None, ldq, _ptr(K), _ptr(V), B, precision))
+
+
+def lindblad_tile_info(ctx: Context, M: int, B: int, precision: int = FP64):
+    r, k, w, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load().lindblad_tile_info(ctx.handle, int(M), int(B), int(precision), ctypes.byref(r),
+                                     ctypes.byref(k), ctypes.byref(w), ctypes.byref(t)))
+    return {"rows": r.value, "kslab": k.value, "waves": w.value, "tuned": bool(t.value)}

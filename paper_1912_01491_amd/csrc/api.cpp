@@ -1,0 +1,343 @@
+// C ABI: context management, argument validation and dispatch to the kernels.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "lb_internal.h"
+
+static thread_local char g_err[512] = "";
+
+void lb_set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int lb_fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int lb_use_device(lb_ctx* c) {
+    LB_HIP(hipSetDevice(c->device));
+    return LB_OK;
+}
+
+int lb_ws_reserve(lb_ctx* c, size_t bytes) {
+    if (bytes <= c->ws_bytes) return LB_OK;
+    // the old buffer may still be in use by enqueued work
+    LB_HIP(hipStreamSynchronize(c->stream));
+    if (c->ws) {
+        LB_HIP(hipFree(c->ws));
+        c->ws = nullptr;
+        c->ws_bytes = 0;
+    }
+    size_t want = lb_align(bytes + bytes / 8, 1 << 20);
+    hipError_t e = hipMalloc(&c->ws, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c->ws = nullptr;
+        return lb_fail(LB_ERR_OOM, "workspace allocation of %zu bytes failed: %s", want, hipGetErrorString(e));
+    }
+    c->ws_bytes = want;
+    return LB_OK;
+}
+
+int lb_host_reserve(lb_ctx* c, size_t bytes) {
+    if (bytes <= c->host_bytes) return LB_OK;
+    LB_HIP(hipStreamSynchronize(c->stream));
+    if (c->host) {
+        LB_HIP(hipHostFree(c->host));
+        c->host = nullptr;
+        c->host_bytes = 0;
+    }
+    size_t want = lb_align(bytes, 1 << 16);
+    hipError_t e = hipHostMalloc(&c->host, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c->host = nullptr;
+        return lb_fail(LB_ERR_OOM, "pinned host allocation of %zu bytes failed", want);
+    }
+    c->host_bytes = want;
+    return LB_OK;
+}
+
+#define CHECK_CTX(c)                                                   \
+    do {                                                               \
+        if (!(c)) return lb_fail(LB_ERR_INVALID_ARG, "null context"); \
+        int _rc = lb_use_device(c);                                    \
+        if (_rc) return _rc;                                           \
+    } while (0)
+
+#define CHECK_N(N)                                                                               \
+    do {                                                                                         \
+        if ((N) < 2 || (N) > LB_MAX_N) return lb_fail(LB_ERR_INVALID_ARG, "N=%d out of range [2, %d]", (N), LB_MAX_N); \
+    } while (0)
+
+#define CHECK_PTR(p)                                                        \
+    do {                                                                    \
+        if (!(p)) return lb_fail(LB_ERR_INVALID_ARG, "null pointer: %s", #p); \
+    } while (0)
+
+extern "C" {
+
+int lb_version(void) { return 100; }
+
+const char* lb_last_error(void) { return g_err; }
+
+int lb_create(lb_ctx** out, int device, void* stream) {
+    if (!out) return lb_fail(LB_ERR_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    int n = 0;
+    LB_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return lb_fail(LB_ERR_INVALID_ARG, "device %d not present (%d devices)", device, n);
+    LB_HIP(hipSetDevice(device));
+    lb_ctx* c = new lb_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)stream;  // NULL: the device's default stream
+    *out = c;
+    return LB_OK;
+}
+
+int lb_destroy(lb_ctx* c) {
+    if (!c) return LB_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (c->ws) (void)hipFree(c->ws);
+    if (c->host) (void)hipHostFree(c->host);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    delete c;
+    return LB_OK;
+}
+
+int lb_set_stream(lb_ctx* c, void* stream) {
+    CHECK_CTX(c);
+    LB_HIP(hipStreamSynchronize(c->stream));
+    c->stream = (hipStream_t)stream;
+    return LB_OK;
+}
+
+int lb_sync(lb_ctx* c) {
+    CHECK_CTX(c);
+    LB_HIP(hipStreamSynchronize(c->stream));
+    return LB_OK;
+}
+
+int lb_basis_index(int N, int64_t i, int32_t* cls, int32_t* j, int32_t* k) {
+    CHECK_N(N);
+    CHECK_PTR(cls);
+    CHECK_PTR(j);
+    CHECK_PTR(k);
+    const int64_t M = (int64_t)N * N - 1;
+    if (i < 0 || i >= M) return lb_fail(LB_ERR_INVALID_ARG, "index %lld out of range [0, %lld)", (long long)i, (long long)M);
+    int c_, j_, k_;
+    lb_decode(N, i, c_, j_, k_);
+    *cls = c_;
+    *j = j_;
+    *k = k_;
+    return LB_OK;
+}
+
+int lb_basis_table(lb_ctx* c, int N, int32_t* table) {
+    CHECK_CTX(c);
+    CHECK_N(N);
+    CHECK_PTR(table);
+    return lb_impl_basis_table(c, N, table);
+}
+
+int lb_fd_count(lb_ctx* c, int N, int which, int64_t* count) {
+    CHECK_CTX(c);
+    CHECK_N(N);
+    CHECK_PTR(count);
+    if (which != 0 && which != 1) return lb_fail(LB_ERR_INVALID_ARG, "which must be 0 (f) or 1 (d)");
+    return lb_impl_fd_count(c, N, which, count, nullptr);
+}
+
+int lb_fd_enumerate(lb_ctx* c, int N, int which, int32_t* mns, double* val, int64_t cap, int64_t* count) {
+    CHECK_CTX(c);
+    CHECK_N(N);
+    CHECK_PTR(count);
+    if (which != 0 && which != 1) return lb_fail(LB_ERR_INVALID_ARG, "which must be 0 (f) or 1 (d)");
+    int64_t total = 0;
+    int rc = lb_impl_fd_count(c, N, which, &total, nullptr);
+    if (rc) return rc;
+    *count = total;
+    if (cap < total) return lb_fail(LB_ERR_INVALID_ARG, "capacity %lld < %lld nonzeros", (long long)cap, (long long)total);
+    if (total == 0) return LB_OK;
+    CHECK_PTR(mns);
+    CHECK_PTR(val);
+    const int64_t M = (int64_t)N * N - 1;
+    const int64_t* offsets = (const int64_t*)c->ws + M;
+    rc = lb_impl_fd_fill(c, N, which, offsets, mns, val);
+    if (rc) return rc;
+    LB_HIP(hipStreamSynchronize(c->stream));
+    return LB_OK;
+}
+
+int lb_expand(lb_ctx* c, int N, int B, const double* A, double* a) {
+    CHECK_CTX(c);
+    CHECK_N(N);
+    CHECK_PTR(A);
+    CHECK_PTR(a);
+    if (B < 1) return lb_fail(LB_ERR_INVALID_ARG, "B=%d < 1", B);
+    return lb_impl_expand(c, N, B, A, a, 1.0);
+}
+
+int lb_expand_pure(lb_ctx* c, int N, int B, const double* psi, double* V) {
+    CHECK_CTX(c);
+    CHECK_N(N);
+    CHECK_PTR(psi);
+    CHECK_PTR(V);
+    if (B < 1) return lb_fail(LB_ERR_INVALID_ARG, "B=%d < 1", B);
+    return lb_impl_expand_pure(c, N, B, psi, V);
+}
+
+int lb_reconstruct(lb_ctx* c, int N, int B, const double* V, double* rho) {
+    CHECK_CTX(c);
+    CHECK_N(N);
+    CHECK_PTR(V);
+    CHECK_PTR(rho);
+    if (B < 1) return lb_fail(LB_ERR_INVALID_ARG, "B=%d < 1", B);
+    return lb_impl_reconstruct(c, N, B, V, rho);
+}
+
+int lindblad_prepare(lb_ctx* c, int N, const double* H, const double* gamma, double* Q, int64_t ldq, double* K,
+                     unsigned flags) {
+    CHECK_CTX(c);
+    CHECK_N(N);
+    CHECK_PTR(H);
+    CHECK_PTR(gamma);
+    CHECK_PTR(Q);
+    CHECK_PTR(K);
+    const int64_t M = (int64_t)N * N - 1;
+    if (ldq < M) return lb_fail(LB_ERR_INVALID_ARG, "ldq=%lld < M=%lld", (long long)ldq, (long long)M);
+    if (((uintptr_t)gamma) % 16 || ((uintptr_t)H) % 16)
+        return lb_fail(LB_ERR_INVALID_ARG, "H and gamma must be 16-byte aligned complex arrays");
+    if (flags & LB_CHECK_HERMITIAN) {
+        double dev = 0, mx = 0;
+        int rc = lb_impl_hermitian_check(c, N, H, &dev, &mx);
+        if (rc) return rc;
+        if (dev > 1e-12 * (mx > 1 ? mx : 1)) return lb_fail(LB_ERR_NOT_HERMITIAN, "H is not Hermitian (max dev %g)", dev);
+        rc = lb_impl_hermitian_check(c, M, gamma, &dev, &mx);
+        if (rc) return rc;
+        if (dev > 1e-12 * (mx > 1 ? mx : 1))
+            return lb_fail(LB_ERR_NOT_HERMITIAN, "gamma is not Hermitian (max dev %g)", dev);
+    }
+    return lb_impl_prepare_dense(c, N, H, gamma, Q, ldq, K);
+}
+
+int lindblad_prepare_sparse_count(lb_ctx* c, int N, const lb_csr_c128* H, int P, const double* rates,
+                                  const lb_csr_c128* L, int64_t* nnz) {
+    CHECK_CTX(c);
+    CHECK_N(N);
+    CHECK_PTR(H);
+    CHECK_PTR(nnz);
+    if (P < 0 || (P > 0 && (!rates || !L))) return lb_fail(LB_ERR_INVALID_ARG, "bad jump-operator arguments");
+    for (int p = 0; p < P; ++p)
+        if (!(rates[p] >= 0) || !isfinite(rates[p])) return lb_fail(LB_ERR_INVALID_ARG, "rate %d must be finite and >= 0", p);
+    return lb_impl_sparse(c, N, H, P, rates, L, nnz, nullptr, nullptr, nullptr, nullptr);
+}
+
+int lindblad_prepare_sparse_fill(lb_ctx* c, int N, const lb_csr_c128* H, int P, const double* rates,
+                                 const lb_csr_c128* L, int64_t nnz, int64_t* rowptr, int64_t* col, double* val,
+                                 double* K) {
+    CHECK_CTX(c);
+    CHECK_N(N);
+    CHECK_PTR(H);
+    CHECK_PTR(rowptr);
+    CHECK_PTR(K);
+    if (nnz > 0) {
+        CHECK_PTR(col);
+        CHECK_PTR(val);
+    }
+    if (P < 0 || (P > 0 && (!rates || !L))) return lb_fail(LB_ERR_INVALID_ARG, "bad jump-operator arguments");
+    for (int p = 0; p < P; ++p)
+        if (!(rates[p] >= 0) || !isfinite(rates[p])) return lb_fail(LB_ERR_INVALID_ARG, "rate %d must be finite and >= 0", p);
+    int64_t n = nnz;
+    return lb_impl_sparse(c, N, H, P, rates, L, &n, rowptr, col, val, K);
+}
+
+static int check_prop(int64_t M, int64_t ldq, int B, double dt, int64_t steps, int precision) {
+    if (M < 3 || M > (int64_t)LB_MAX_N * LB_MAX_N - 1) return lb_fail(LB_ERR_INVALID_ARG, "M=%lld out of range", (long long)M);
+    if (ldq < M) return lb_fail(LB_ERR_INVALID_ARG, "ldq < M");
+    if (B < 1 || B > 64) return lb_fail(LB_ERR_INVALID_ARG, "B=%d out of range [1, 64]", B);
+    if (!isfinite(dt)) return lb_fail(LB_ERR_INVALID_ARG, "dt is not finite");
+    if (steps < 0) return lb_fail(LB_ERR_INVALID_ARG, "steps < 0");
+    if (precision != LB_FP64 && precision != LB_FP32) return lb_fail(LB_ERR_INVALID_ARG, "unknown precision %d", precision);
+    return LB_OK;
+}
+
+int lindblad_propagate(lb_ctx* c, int64_t M, const double* Q, const float* Q32, int64_t ldq, const double* K,
+                       double* V, int B, double dt, int64_t steps, int precision) {
+    CHECK_CTX(c);
+    int rc = check_prop(M, ldq, B, dt, steps, precision);
+    if (rc) return rc;
+    CHECK_PTR(K);
+    CHECK_PTR(V);
+    if (precision == LB_FP64) CHECK_PTR(Q);
+    else CHECK_PTR(Q32);
+    lb_prop_sys s{Q, Q32, K, V};
+    return lb_impl_propagate(c, 1, M, &s, ldq, B, dt, steps, precision, nullptr);
+}
+
+int lindblad_q_to_f32(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, float* Q32) {
+    CHECK_CTX(c);
+    CHECK_PTR(Q);
+    CHECK_PTR(Q32);
+    if (M < 1 || ldq < M) return lb_fail(LB_ERR_INVALID_ARG, "bad sizes");
+    return lb_impl_q_to_f32(c, M, Q, ldq, Q32);
+}
+
+int lindblad_propagate_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int64_t* col, const double* val,
+                           const double* K, double* V, int B, double dt, int64_t steps) {
+    CHECK_CTX(c);
+    CHECK_PTR(rowptr);
+    CHECK_PTR(K);
+    CHECK_PTR(V);
+    if (M < 3) return lb_fail(LB_ERR_INVALID_ARG, "M too small");
+    if (B < 1 || B > 64) return lb_fail(LB_ERR_INVALID_ARG, "B=%d out of range", B);
+    if (!isfinite(dt) || steps < 0) return lb_fail(LB_ERR_INVALID_ARG, "bad dt/steps");
+    return lb_impl_propagate_csr(c, M, rowptr, col, val, K, V, B, dt, steps);
+}
+
+int lindblad_propagate_batched(lb_ctx* c, int R, int64_t M, const double* const* Q, const float* const* Q32,
+                               int64_t ldq, const double* const* K, double* const* V, int B, double dt,
+                               int64_t steps, int precision) {
+    CHECK_CTX(c);
+    int rc = check_prop(M, ldq, B, dt, steps, precision);
+    if (rc) return rc;
+    if (R < 1 || R > 65535) return lb_fail(LB_ERR_INVALID_ARG, "R=%d out of range", R);
+    CHECK_PTR(K);
+    CHECK_PTR(V);
+    std::vector<lb_prop_sys> sys(R);
+    for (int r = 0; r < R; ++r) {
+        sys[r].Q = Q ? Q[r] : nullptr;
+        sys[r].Q32 = Q32 ? Q32[r] : nullptr;
+        sys[r].K = K[r];
+        sys[r].V = V[r];
+        if (!sys[r].K || !sys[r].V || (precision == LB_FP64 && !sys[r].Q) || (precision == LB_FP32 && !sys[r].Q32))
+            return lb_fail(LB_ERR_INVALID_ARG, "null pointer for system %d", r);
+    }
+    return lb_impl_propagate(c, R, M, sys.data(), ldq, B, dt, steps, precision, nullptr);
+}
+
+int lindblad_tile_info(lb_ctx* c, int64_t M, int B, int precision, int* rows, int* kslab, int* waves, int* tuned) {
+    if (!c) return lb_fail(LB_ERR_INVALID_ARG, "null context");
+    const int Bp = B <= 16 ? 16 : (B <= 32 ? 32 : 64);
+    auto it = c->tuned.find(std::make_tuple(M, Bp, precision));
+    lb_tile t = it != c->tuned.end() ? it->second : lb_default_tile(M, Bp, precision);
+    if (rows) *rows = t.rows;
+    if (kslab) *kslab = t.kslab;
+    if (waves) *waves = t.waves;
+    if (tuned) *tuned = it != c->tuned.end();
+    return LB_OK;
+}
+
+}  // extern "C"

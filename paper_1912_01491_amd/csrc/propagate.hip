@@ -1,0 +1,762 @@
+// RK4 integration of dv/dt = Q v + K (Eq. (10); Table 1 step 3.1).
+//
+// Classic fourth-order Runge-Kutta with constant K:
+//   k1 = f(v), k2 = f(v + h/2 k1), k3 = f(v + h/2 k2), k4 = f(v + h k3),
+//   v <- v + h/6 (k1 + 2 k2 + 2 k3 + k4),   f(x) = Q x + K.
+// Every stage streams Q once, so the integrator is bound by HBM bandwidth for
+// a few states and by the matrix cores for many.
+//
+// Dense paths (per stage):
+//   * B = 1: k_gemv -- one wavefront per group of rows, lanes along the row,
+//     cross-lane reduction, stage combine fused into the same kernel.
+//   * B >= 2: k_gemm64 / k_gemm32 -- split-K GEMM on the matrix cores
+//     (v_mfma_f64_16x16x4f64, v_mfma_f32_16x16x4f32) writing per-slab
+//     partial sums, followed by k_stage which reduces the slabs in a fixed
+//     order (deterministic, no atomics) and applies the RK4 combination.
+//   * M <= 256 and B*M <= 4096: k_rk4_small -- one workgroup per system runs
+//     all steps with Q and the stage vectors in LDS.
+// State layout inside the library: states are padded to Bp in {16, 32, 64}
+// columns and stored "pair-interleaved", X[(k>>1)*2Bp + 2b + (k&1)], so that
+// the 16-byte load a lane issues holds two consecutive k of one state -- the
+// B-operand of two MFMAs whose A-operand is the two consecutive Q columns the
+// same lane loaded. The FP32 path interleaves by four.
+#include "lb_internal.h"
+
+#include <math.h>
+
+#include <algorithm>
+#include <cstring>
+
+typedef double lb_double4 __attribute__((ext_vector_type(4)));
+typedef float lb_float4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+__host__ __device__ __forceinline__ int64_t ilv2(int64_t k, int b, int Bp) { return (k >> 1) * (2 * Bp) + 2 * b + (k & 1); }
+__host__ __device__ __forceinline__ int64_t ilv4(int64_t k, int b, int Bp) { return (k >> 2) * (4 * Bp) + 4 * b + (k & 3); }
+
+// ---------------------------------------------------------------------------
+// Matrix-core stage GEMM, FP64: Part[slab] = Q[:, slab] X[slab, :]
+// ---------------------------------------------------------------------------
+// A wave owns RT row tiles of 16 rows and CT column tiles of 16 states over one
+// k-slab. Lane l loads Q[row0 + 16t + (l%16)][kc + 2(l/16) + {0,1}] (16 bytes)
+// and X[kc + 2(l/16) + {0,1}][16c + (l%16)]; the MFMA k-index j = l/16 maps to
+// column kc + 2j (first MFMA) and kc + 2j + 1 (second).
+template <int RT, int CT, bool ALIGNED>
+__global__ __launch_bounds__(256) void k_gemm64(const double* const* Qs, int64_t M, int64_t Mp, int64_t ldq,
+                                                const double* Xall, int64_t xstride, double* Pall,
+                                                int64_t pstride, int kslab) {
+    constexpr int Bp = 16 * CT;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int r = blockIdx.z;
+    const double* Q = Qs[r];
+    const double* X = Xall + r * xstride;
+    double* Part = Pall + r * pstride + (int64_t)blockIdx.y * Mp * Bp;
+    const int64_t row0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * (16 * RT);
+    if (row0 >= M) return;
+    const int64_t k0 = (int64_t)blockIdx.y * kslab;
+    const int64_t k1 = k0 + kslab < M ? k0 + kslab : M;
+
+    const double* qrow[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+        int64_t row = row0 + 16 * t + lr;
+        row = row < M ? row : M - 1;
+        qrow[t] = Q + row * ldq;
+    }
+    lb_double4 acc[RT][CT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = lb_double4{0, 0, 0, 0};
+
+    int64_t kc = k0;
+    for (; kc + 16 <= k1; kc += 16) {
+        double2 qa[RT], qb[RT], xa[CT], xb[CT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            const double* p = qrow[t] + kc + 2 * lk;
+            if (ALIGNED) {
+                qa[t] = *reinterpret_cast<const double2*>(p);
+                qb[t] = *reinterpret_cast<const double2*>(p + 8);
+            } else {
+                qa[t] = make_double2(p[0], p[1]);
+                qb[t] = make_double2(p[8], p[9]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            xa[c] = *reinterpret_cast<const double2*>(X + ((kc >> 1) + lk) * (2 * Bp) + 2 * (16 * c + lr));
+            xb[c] = *reinterpret_cast<const double2*>(X + (((kc + 8) >> 1) + lk) * (2 * Bp) + 2 * (16 * c + lr));
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[t].x, xa[c].x, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[t].y, xa[c].y, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(qb[t].x, xb[c].x, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(qb[t].y, xb[c].y, acc[t][c], 0, 0, 0);
+            }
+    }
+    if (kc < k1) {  // ragged tail: guarded scalar loads, zero beyond M
+        double qa[RT][4], xa[CT][4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int64_t k = kc + 2 * lk + (h & 1) + 8 * (h >> 1);
+            const bool ok = k < k1;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) qa[t][h] = ok ? qrow[t][k] : 0.0;
+#pragma unroll
+            for (int c = 0; c < CT; ++c) xa[c][h] = ok ? X[ilv2(k, 16 * c + lr, Bp)] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+#pragma unroll
+                for (int h = 0; h < 4; ++h)
+                    acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[t][h], xa[c][h], acc[t][c], 0, 0, 0);
+    }
+    // D layout of v_mfma_f64_16x16x4f64: lane l, element j -> row 4j + l/16,
+    // column l%16 (the FP32 variant below uses row 4(l/16) + j)
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t row = row0 + 16 * t + 4 * j + lk;
+                if (row < M) Part[ilv2(row, 16 * c + lr, Bp)] = acc[t][c][j];
+            }
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-core stage GEMM, FP32 operands: Q32 and X32 in FP32, FP32 products and
+// accumulation within a k-slab, FP64 partial sums across slabs.
+// ---------------------------------------------------------------------------
+template <int RT, int CT, bool ALIGNED>
+__global__ __launch_bounds__(256) void k_gemm32(const float* const* Qs, int64_t M, int64_t Mp, int64_t ldq,
+                                                const float* Xall, int64_t xstride, double* Pall,
+                                                int64_t pstride, int kslab) {
+    constexpr int Bp = 16 * CT;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int r = blockIdx.z;
+    const float* Q = Qs[r];
+    const float* X = Xall + r * xstride;
+    double* Part = Pall + r * pstride + (int64_t)blockIdx.y * Mp * Bp;
+    const int64_t row0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * (16 * RT);
+    if (row0 >= M) return;
+    const int64_t k0 = (int64_t)blockIdx.y * kslab;
+    const int64_t k1 = k0 + kslab < M ? k0 + kslab : M;
+
+    const float* qrow[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+        int64_t row = row0 + 16 * t + lr;
+        row = row < M ? row : M - 1;
+        qrow[t] = Q + row * ldq;
+    }
+    lb_float4 acc[RT][CT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = lb_float4{0, 0, 0, 0};
+
+    int64_t kc = k0;
+    for (; kc + 16 <= k1; kc += 16) {
+        float4 qa[RT], xa[CT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            const float* p = qrow[t] + kc + 4 * lk;
+            if (ALIGNED) qa[t] = *reinterpret_cast<const float4*>(p);
+            else qa[t] = make_float4(p[0], p[1], p[2], p[3]);
+        }
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+            xa[c] = *reinterpret_cast<const float4*>(X + ((kc >> 2) + lk) * (4 * Bp) + 4 * (16 * c + lr));
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t].x, xa[c].x, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t].y, xa[c].y, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t].z, xa[c].z, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t].w, xa[c].w, acc[t][c], 0, 0, 0);
+            }
+    }
+    if (kc < k1) {
+        float qa[RT][4], xa[CT][4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int64_t k = kc + 4 * lk + h;
+            const bool ok = k < k1;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) qa[t][h] = ok ? qrow[t][k] : 0.0f;
+#pragma unroll
+            for (int c = 0; c < CT; ++c) xa[c][h] = ok ? X[ilv4(k, 16 * c + lr, Bp)] : 0.0f;
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+#pragma unroll
+                for (int h = 0; h < 4; ++h)
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t][h], xa[c][h], acc[t][c], 0, 0, 0);
+    }
+    // D layout of v_mfma_f32_16x16x4f32: lane l, element j -> row 4(l/16) + j
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t row = row0 + 16 * t + 4 * lk + j;
+                if (row < M) Part[ilv2(row, 16 * c + lr, Bp)] = (double)acc[t][c][j];
+            }
+}
+
+// ---------------------------------------------------------------------------
+// Stage combine: k_i = sum_slab Part + K, then the RK4 update of that stage.
+// ---------------------------------------------------------------------------
+struct StageArgs {
+    const double* const* Ks;
+    double* V;       // + r*sstride
+    double* Acc;
+    double* X;
+    float* X32;      // may be null
+    int64_t sstride; // per-system stride of V/Acc/X (doubles)
+    int64_t s32stride;
+    const double* Part;
+    int64_t pstride;
+    int nslab;
+    int64_t M, Mp;
+    int Bp;
+    double dt;
+};
+
+__global__ void k_stage(StageArgs a, int stage) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (row, b) in row-major
+    const int r = blockIdx.y;
+    if (e >= a.M * a.Bp) return;
+    const int64_t row = e / a.Bp;
+    const int b = (int)(e % a.Bp);
+    const int64_t idx = ilv2(row, b, a.Bp);
+    const double* part = a.Part + r * a.pstride + idx;
+    double k = 0.0;
+    for (int s = 0; s < a.nslab; ++s) k += part[(int64_t)s * a.Mp * a.Bp];
+    k += a.Ks[r][row];
+    double* V = a.V + r * a.sstride;
+    double* Acc = a.Acc + r * a.sstride;
+    double* X = a.X + r * a.sstride;
+    const double h = a.dt;
+    double x;
+    if (stage == 1) {
+        Acc[idx] = k;
+        x = V[idx] + 0.5 * h * k;
+    } else if (stage == 2) {
+        Acc[idx] = Acc[idx] + 2.0 * k;
+        x = V[idx] + 0.5 * h * k;
+    } else if (stage == 3) {
+        Acc[idx] = Acc[idx] + 2.0 * k;
+        x = V[idx] + h * k;
+    } else {
+        x = V[idx] + h / 6.0 * (Acc[idx] + k);
+        V[idx] = x;
+    }
+    X[idx] = x;
+    if (a.X32) a.X32[r * a.s32stride + ilv4(row, b, a.Bp)] = (float)x;
+}
+
+// user layout (B, M) -> interleaved padded (Mp, Bp); padding rows/columns zero
+__global__ void k_pack(const double* const* Vu, int64_t M, int64_t Mp, int B, int Bp, double* V, double* X,
+                       float* X32, int64_t sstride, int64_t s32stride) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (e >= Mp * Bp) return;
+    const int64_t row = e / Bp;
+    const int b = (int)(e % Bp);
+    const double v = (row < M && b < B) ? Vu[r][(int64_t)b * M + row] : 0.0;
+    const int64_t idx = ilv2(row, b, Bp);
+    V[r * sstride + idx] = v;
+    X[r * sstride + idx] = v;
+    if (X32) X32[r * s32stride + ilv4(row, b, Bp)] = (float)v;
+}
+
+__global__ void k_unpack(double* const* Vu, int64_t M, int B, int Bp, const double* V, int64_t sstride) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (e >= M * B) return;
+    const int b = (int)(e / M);
+    const int64_t row = e % M;
+    Vu[r][e] = V[r * sstride + ilv2(row, b, Bp)];
+}
+
+// ---------------------------------------------------------------------------
+// One state: GEMV with the stage combine fused in (rows are complete per wave).
+// ---------------------------------------------------------------------------
+template <int R, bool ALIGNED>
+__global__ __launch_bounds__(256) void k_gemv(const double* const* Qs, const double* const* Ks,
+                                              double* const* Vs, int64_t M, int64_t ldq, double* Wall,
+                                              int64_t wstride, int stage, double h) {
+    // W layout per system: [Acc | Xa | Xb], each Ma = M rounded up to 32
+    // doubles; stage i reads X from Xa when i is odd and Xb when even, and
+    // writes the other one.
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int r = blockIdx.y;
+    const int64_t row0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * R;
+    if (row0 >= M) return;
+    const double* Q = Qs[r];
+    double* W = Wall + r * wstride;
+    const int64_t Ma = (M + 31) / 32 * 32;
+    double* Acc = W;
+    const double* Xin = (stage & 1) ? W + Ma : W + 2 * Ma;
+    double* Xout = (stage & 1) ? W + 2 * Ma : W + Ma;
+    double acc[R];
+    const double* qrow[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        acc[t] = 0.0;
+        int64_t row = row0 + t;
+        qrow[t] = Q + (row < M ? row : M - 1) * ldq;
+    }
+    int64_t c = 2 * lane;
+    if (ALIGNED) {
+        for (; c + 1 < M; c += 128) {
+            const double2 x = *reinterpret_cast<const double2*>(Xin + c);
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                const double2 q = *reinterpret_cast<const double2*>(qrow[t] + c);
+                acc[t] = fma(q.x, x.x, acc[t]);
+                acc[t] = fma(q.y, x.y, acc[t]);
+            }
+        }
+    } else {
+        for (; c + 1 < M; c += 128) {
+            const double x0 = Xin[c], x1 = Xin[c + 1];
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                acc[t] = fma(qrow[t][c], x0, acc[t]);
+                acc[t] = fma(qrow[t][c + 1], x1, acc[t]);
+            }
+        }
+    }
+    if (c < M) {
+        const double x0 = Xin[c];
+#pragma unroll
+        for (int t = 0; t < R; ++t) acc[t] = fma(qrow[t][c], x0, acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        double v = acc[t];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        acc[t] = v;
+    }
+    if (lane < R) {
+        double kv = 0.0;
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+            if (t == lane) kv = acc[t];
+        const int64_t row = row0 + lane;
+        if (row < M) {
+            const double k = kv + Ks[r][row];
+            double* V = Vs[r];
+            double x;
+            if (stage == 1) {
+                Acc[row] = k;
+                x = V[row] + 0.5 * h * k;
+            } else if (stage == 2) {
+                Acc[row] = Acc[row] + 2.0 * k;
+                x = V[row] + 0.5 * h * k;
+            } else if (stage == 3) {
+                Acc[row] = Acc[row] + 2.0 * k;
+                x = V[row] + h * k;
+            } else {
+                x = V[row] + h / 6.0 * (Acc[row] + k);
+                V[row] = x;
+            }
+            Xout[row] = x;
+        }
+    }
+}
+
+__global__ void k_gemv_init(double* const* Vs, int64_t M, double* Wall, int64_t wstride) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (e >= M) return;
+    Wall[r * wstride + (M + 31) / 32 * 32 + e] = Vs[r][e];  // Xa = v
+}
+
+// ---------------------------------------------------------------------------
+// Small systems: one workgroup integrates one system for all steps.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_rk4_small(const double* const* Qs, const double* const* Ks,
+                                                   double* const* Vs, int M, int64_t ldq, int B, double h,
+                                                   int64_t steps, int q_in_lds) {
+    extern __shared__ double sm[];
+    const int r = blockIdx.x;
+    const double* Qg = Qs[r];
+    const double* K = Ks[r];
+    double* V = Vs[r];
+    const int n = M * B;
+    double* X = sm;           // B x M
+    double* Acc = sm + n;     // B x M
+    double* Ql = sm + 2 * n;  // M x M (optional)
+    for (int e = threadIdx.x; e < n; e += blockDim.x) X[e] = V[e];
+    if (q_in_lds)
+        for (int e = threadIdx.x; e < M * M; e += blockDim.x) Ql[e] = Qg[(int64_t)(e / M) * ldq + e % M];
+    __syncthreads();
+    const double* Q = q_in_lds ? Ql : Qg;
+    const int64_t lq = q_in_lds ? M : ldq;
+    for (int64_t st = 0; st < steps; ++st) {
+        for (int stage = 1; stage <= 4; ++stage) {
+            double kv[16];
+            int cnt = 0;
+            for (int e = threadIdx.x; e < n; e += blockDim.x) {
+                const int b = e / M, i = e % M;
+                const double* q = Q + (int64_t)i * lq;
+                const double* x = X + b * M;
+                double s = 0.0;
+                for (int j = 0; j < M; ++j) s = fma(q[j], x[j], s);
+                kv[cnt++] = s + K[i];
+            }
+            __syncthreads();
+            cnt = 0;
+            for (int e = threadIdx.x; e < n; e += blockDim.x) {
+                const double k = kv[cnt++];
+                double x;
+                if (stage == 1) {
+                    Acc[e] = k;
+                    x = V[e] + 0.5 * h * k;
+                } else if (stage == 2) {
+                    Acc[e] = Acc[e] + 2.0 * k;
+                    x = V[e] + 0.5 * h * k;
+                } else if (stage == 3) {
+                    Acc[e] = Acc[e] + 2.0 * k;
+                    x = V[e] + h * k;
+                } else {
+                    x = V[e] + h / 6.0 * (Acc[e] + k);
+                    V[e] = x;
+                }
+                X[e] = x;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CSR: one thread per row, stage combine fused (B states, user layout).
+// ---------------------------------------------------------------------------
+__global__ void k_csr_stage(int64_t M, const int64_t* rowptr, const int64_t* col, const double* val,
+                            const double* K, double* V, double* W, int B, int stage, double h) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= M) return;
+    const int64_t n = M * B;
+    double* Acc = W;
+    const double* Xin = (stage & 1) ? W + n : W + 2 * n;
+    double* Xout = (stage & 1) ? W + 2 * n : W + n;
+    const int64_t e0 = rowptr[row], e1 = rowptr[row + 1];
+    for (int b = 0; b < B; ++b) {
+        const double* x = Xin + (int64_t)b * M;
+        double s = 0.0;
+        for (int64_t e = e0; e < e1; ++e) s = fma(val[e], x[col[e]], s);
+        const double k = s + K[row];
+        const int64_t i = (int64_t)b * M + row;
+        double xn;
+        if (stage == 1) {
+            Acc[i] = k;
+            xn = V[i] + 0.5 * h * k;
+        } else if (stage == 2) {
+            Acc[i] = Acc[i] + 2.0 * k;
+            xn = V[i] + 0.5 * h * k;
+        } else if (stage == 3) {
+            Acc[i] = Acc[i] + 2.0 * k;
+            xn = V[i] + h * k;
+        } else {
+            xn = V[i] + h / 6.0 * (Acc[i] + k);
+            V[i] = xn;
+        }
+        Xout[i] = xn;
+    }
+}
+
+__global__ void k_copy(const double* src, double* dst, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) dst[e] = src[e];
+}
+
+__global__ void k_to_f32(const double* Q, float* Q32, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) Q32[e] = (float)Q[e];
+}
+
+// ---------------------------------------------------------------------------
+// Kernel selection
+// ---------------------------------------------------------------------------
+
+typedef void (*gemm64_fn)(const double* const*, int64_t, int64_t, int64_t, const double*, int64_t, double*,
+                          int64_t, int);
+typedef void (*gemm32_fn)(const float* const*, int64_t, int64_t, int64_t, const float*, int64_t, double*,
+                          int64_t, int);
+
+template <bool AL>
+gemm64_fn pick64(int RT, int CT) {
+    if (CT == 1) {
+        if (RT == 1) return k_gemm64<1, 1, AL>;
+        if (RT == 2) return k_gemm64<2, 1, AL>;
+        if (RT == 4) return k_gemm64<4, 1, AL>;
+        if (RT == 8) return k_gemm64<8, 1, AL>;
+    } else if (CT == 2) {
+        if (RT == 1) return k_gemm64<1, 2, AL>;
+        if (RT == 2) return k_gemm64<2, 2, AL>;
+        if (RT == 4) return k_gemm64<4, 2, AL>;
+    } else if (CT == 4) {
+        if (RT == 1) return k_gemm64<1, 4, AL>;
+        if (RT == 2) return k_gemm64<2, 4, AL>;
+        if (RT == 4) return k_gemm64<4, 4, AL>;
+    }
+    return nullptr;
+}
+
+template <bool AL>
+gemm32_fn pick32(int RT, int CT) {
+    if (CT == 1) {
+        if (RT == 1) return k_gemm32<1, 1, AL>;
+        if (RT == 2) return k_gemm32<2, 1, AL>;
+        if (RT == 4) return k_gemm32<4, 1, AL>;
+        if (RT == 8) return k_gemm32<8, 1, AL>;
+    } else if (CT == 2) {
+        if (RT == 1) return k_gemm32<1, 2, AL>;
+        if (RT == 2) return k_gemm32<2, 2, AL>;
+        if (RT == 4) return k_gemm32<4, 2, AL>;
+    } else if (CT == 4) {
+        if (RT == 1) return k_gemm32<1, 4, AL>;
+        if (RT == 2) return k_gemm32<2, 4, AL>;
+        if (RT == 4) return k_gemm32<4, 4, AL>;
+    }
+    return nullptr;
+}
+
+int bpad(int B) { return B <= 16 ? 16 : (B <= 32 ? 32 : 64); }
+
+}  // namespace
+
+lb_tile lb_default_tile(int64_t M, int Bp, int precision) {
+    lb_tile t;
+    const int CT = Bp / 16;
+    t.rows = CT == 1 ? 64 : (CT == 2 ? 32 : 32);
+    if (precision == LB_FP32 && CT == 1) t.rows = 64;
+    t.waves = 4;
+    const int64_t rowwaves = (M + t.rows - 1) / t.rows;
+    int64_t nslab = (4096 + rowwaves - 1) / rowwaves;
+    const int64_t maxslab = (M + 255) / 256;
+    if (nslab > maxslab) nslab = maxslab;
+    if (nslab < 1) nslab = 1;
+    int64_t ks = (M + nslab - 1) / nslab;
+    ks = (ks + 15) / 16 * 16;
+    t.kslab = (int)ks;
+    return t;
+}
+
+static lb_tile choose_tile(lb_ctx* c, int64_t M, int Bp, int precision) {
+    auto it = c->tuned.find(std::make_tuple(M, Bp, precision));
+    if (it != c->tuned.end()) return it->second;
+    return lb_default_tile(M, Bp, precision);
+}
+
+int lb_impl_q_to_f32(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, float* Q32) {
+    const int64_t n = M * ldq;
+    hipLaunchKernelGGL(k_to_f32, dim3(lb_blocks(n, 256)), dim3(256), 0, c->stream, Q, Q32, n);
+    LB_CHECK_LAUNCH();
+    return LB_OK;
+}
+
+// R systems of size M, B states each.
+int lb_impl_propagate(lb_ctx* c, int R, int64_t M, const lb_prop_sys* sys, int64_t ldq, int B, double dt,
+                      int64_t steps, int precision, const lb_tile* force_tile) {
+    hipStream_t s = c->stream;
+    if (steps == 0) return LB_OK;
+    // --- small systems: one workgroup per system, everything in LDS
+    if (M <= 256 && (int64_t)B * M <= 4096 && precision == LB_FP64 && force_tile == nullptr) {
+        const size_t pbytes = sizeof(void*) * 3 * R;
+        int rc = lb_ws_reserve(c, pbytes);
+        if (rc) return rc;
+        rc = lb_host_reserve(c, pbytes);
+        if (rc) return rc;
+        LB_HIP(hipStreamSynchronize(s));
+        const void** h = (const void**)c->host;
+        for (int r = 0; r < R; ++r) {
+            h[r] = sys[r].Q;
+            h[R + r] = sys[r].K;
+            h[2 * R + r] = sys[r].V;
+        }
+        LB_HIP(hipMemcpyAsync(c->ws, h, pbytes, hipMemcpyHostToDevice, s));
+        const void** d = (const void**)c->ws;
+        const size_t base = sizeof(double) * 2 * (size_t)B * M;
+        const size_t withq = base + sizeof(double) * (size_t)M * M;
+        const int q_in_lds = withq <= 64 * 1024 ? 1 : 0;
+        const size_t shm = q_in_lds ? withq : base;
+        hipLaunchKernelGGL(k_rk4_small, dim3(R), dim3(256), shm, s, (const double* const*)d,
+                           (const double* const*)(d + R), (double* const*)(d + 2 * R), (int)M, ldq, B, dt, steps,
+                           q_in_lds);
+        LB_CHECK_LAUNCH();
+        return LB_OK;
+    }
+    const bool aligned = (ldq % 2 == 0);
+    // --- one state, FP64: GEMV with fused combine
+    if (B == 1 && precision == LB_FP64) {
+        const int64_t wstride = 3 * lb_align(M, 32);
+        const size_t pbytes = lb_align(sizeof(void*) * 3 * R, 256);
+        int rc = lb_ws_reserve(c, pbytes + sizeof(double) * wstride * R);
+        if (rc) return rc;
+        rc = lb_host_reserve(c, sizeof(void*) * 3 * R);
+        if (rc) return rc;
+        LB_HIP(hipStreamSynchronize(s));
+        const void** h = (const void**)c->host;
+        for (int r = 0; r < R; ++r) {
+            h[r] = sys[r].Q;
+            h[R + r] = sys[r].K;
+            h[2 * R + r] = sys[r].V;
+        }
+        LB_HIP(hipMemcpyAsync(c->ws, h, sizeof(void*) * 3 * R, hipMemcpyHostToDevice, s));
+        const void** d = (const void**)c->ws;
+        double* W = (double*)((char*)c->ws + pbytes);
+        for (int r = 0; r < R; ++r)
+            if (((uintptr_t)sys[r].Q) % 16) return lb_fail(LB_ERR_INVALID_ARG, "Q must be 16-byte aligned");
+        hipLaunchKernelGGL(k_gemv_init, dim3(lb_blocks(M, 256), R), dim3(256), 0, s, (double* const*)(d + 2 * R), M,
+                           W, wstride);
+        LB_CHECK_LAUNCH();
+        constexpr int RW = 8;
+        const unsigned gx = lb_blocks((M + RW - 1) / RW, 4);
+        auto fn = aligned ? k_gemv<RW, true> : k_gemv<RW, false>;
+        for (int64_t st = 0; st < steps; ++st)
+            for (int stage = 1; stage <= 4; ++stage) {
+                hipLaunchKernelGGL(fn, dim3(gx, R), dim3(256), 0, s, (const double* const*)d,
+                                   (const double* const*)(d + R), (double* const*)(d + 2 * R), M, ldq, W, wstride,
+                                   stage, dt);
+                LB_CHECK_LAUNCH();
+            }
+        return LB_OK;
+    }
+    // --- matrix-core path
+    const int Bp = bpad(B);
+    const int CT = Bp / 16;
+    const lb_tile tile = force_tile ? *force_tile : choose_tile(c, M, Bp, precision);
+    const int RT = tile.rows / 16;
+    const int64_t Mp = (M + 15) / 16 * 16;
+    const int nslab = (int)((M + tile.kslab - 1) / tile.kslab);
+    const int64_t sstride = lb_align(Mp * Bp, 64);
+    const int64_t s32stride = lb_align(Mp * Bp, 128);
+    const int64_t pstride = (int64_t)nslab * Mp * Bp;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = lb_align(off + bytes, 256);
+        return o;
+    };
+    const size_t o_ptr = take(sizeof(void*) * 5 * R);
+    const size_t o_v = take(sizeof(double) * sstride * R);
+    const size_t o_acc = take(sizeof(double) * sstride * R);
+    const size_t o_x = take(sizeof(double) * sstride * R);
+    const size_t o_x32 = precision == LB_FP32 ? take(sizeof(float) * s32stride * R) : 0;
+    const size_t o_part = take(sizeof(double) * pstride * R);
+    int rc = lb_ws_reserve(c, off);
+    if (rc) return rc;
+    rc = lb_host_reserve(c, sizeof(void*) * 5 * R);
+    if (rc) return rc;
+    LB_HIP(hipStreamSynchronize(s));
+    const void** h = (const void**)c->host;
+    for (int r = 0; r < R; ++r) {
+        h[r] = sys[r].Q;
+        h[R + r] = sys[r].Q32;
+        h[2 * R + r] = sys[r].K;
+        h[3 * R + r] = sys[r].V;
+        h[4 * R + r] = sys[r].V;
+        const void* qp = precision == LB_FP32 ? (const void*)sys[r].Q32 : (const void*)sys[r].Q;
+        if (((uintptr_t)qp) % 16) return lb_fail(LB_ERR_INVALID_ARG, "Q must be 16-byte aligned");
+    }
+    char* ws = (char*)c->ws;
+    LB_HIP(hipMemcpyAsync(ws + o_ptr, h, sizeof(void*) * 5 * R, hipMemcpyHostToDevice, s));
+    const void** d = (const void**)(ws + o_ptr);
+    double* V = (double*)(ws + o_v);
+    double* Acc = (double*)(ws + o_acc);
+    double* X = (double*)(ws + o_x);
+    float* X32 = precision == LB_FP32 ? (float*)(ws + o_x32) : nullptr;
+    double* Part = (double*)(ws + o_part);
+    const bool al = precision == LB_FP32 ? (ldq % 4 == 0) : aligned;
+
+    hipLaunchKernelGGL(k_pack, dim3(lb_blocks(Mp * Bp, 256), R), dim3(256), 0, s, (const double* const*)(d + 3 * R),
+                       M, Mp, B, Bp, V, X, X32, sstride, s32stride);
+    LB_CHECK_LAUNCH();
+    StageArgs sa;
+    sa.Ks = (const double* const*)(d + 2 * R);
+    sa.V = V;
+    sa.Acc = Acc;
+    sa.X = X;
+    sa.X32 = X32;
+    sa.sstride = sstride;
+    sa.s32stride = s32stride;
+    sa.Part = Part;
+    sa.pstride = pstride;
+    sa.nslab = nslab;
+    sa.M = M;
+    sa.Mp = Mp;
+    sa.Bp = Bp;
+    sa.dt = dt;
+    const int64_t rowwaves = (M + tile.rows - 1) / tile.rows;
+    const dim3 ggrid((unsigned)((rowwaves + tile.waves - 1) / tile.waves), (unsigned)nslab, (unsigned)R);
+    const dim3 gblock(64 * tile.waves);
+    const dim3 sgrid(lb_blocks(M * Bp, 256), R);
+    if (precision == LB_FP64) {
+        gemm64_fn fn = al ? pick64<true>(RT, CT) : pick64<false>(RT, CT);
+        if (!fn) return lb_fail(LB_ERR_INVALID_ARG, "unsupported tile rows=%d for Bp=%d", tile.rows, Bp);
+        for (int64_t st = 0; st < steps; ++st)
+            for (int stage = 1; stage <= 4; ++stage) {
+                hipLaunchKernelGGL(fn, ggrid, gblock, 0, s, (const double* const*)d, M, Mp, ldq, (const double*)X,
+                                   sstride, Part, pstride, tile.kslab);
+                LB_CHECK_LAUNCH();
+                hipLaunchKernelGGL(k_stage, sgrid, dim3(256), 0, s, sa, stage);
+                LB_CHECK_LAUNCH();
+            }
+    } else {
+        gemm32_fn fn = al ? pick32<true>(RT, CT) : pick32<false>(RT, CT);
+        if (!fn) return lb_fail(LB_ERR_INVALID_ARG, "unsupported tile rows=%d for Bp=%d", tile.rows, Bp);
+        for (int64_t st = 0; st < steps; ++st)
+            for (int stage = 1; stage <= 4; ++stage) {
+                hipLaunchKernelGGL(fn, ggrid, gblock, 0, s, (const float* const*)(d + R), M, Mp, ldq,
+                                   (const float*)X32, s32stride, Part, pstride, tile.kslab);
+                LB_CHECK_LAUNCH();
+                hipLaunchKernelGGL(k_stage, sgrid, dim3(256), 0, s, sa, stage);
+                LB_CHECK_LAUNCH();
+            }
+    }
+    hipLaunchKernelGGL(k_unpack, dim3(lb_blocks(M * B, 256), R), dim3(256), 0, s, (double* const*)(d + 4 * R), M, B,
+                       Bp, (const double*)V, sstride);
+    LB_CHECK_LAUNCH();
+    return LB_OK;
+}
+
+int lb_impl_propagate_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int64_t* col, const double* val,
+                          const double* K, double* V, int B, double dt, int64_t steps) {
+    hipStream_t s = c->stream;
+    if (steps == 0) return LB_OK;
+    const int64_t n = M * B;
+    int rc = lb_ws_reserve(c, sizeof(double) * 3 * n);
+    if (rc) return rc;
+    double* W = (double*)c->ws;
+    hipLaunchKernelGGL(k_copy, dim3(lb_blocks(n, 256)), dim3(256), 0, s, (const double*)V, W + n, n);
+    LB_CHECK_LAUNCH();
+    for (int64_t st = 0; st < steps; ++st)
+        for (int stage = 1; stage <= 4; ++stage) {
+            hipLaunchKernelGGL(k_csr_stage, dim3(lb_blocks(M, 256)), dim3(256), 0, s, M, rowptr, col, val, K, V, W,
+                               B, stage, dt);
+            LB_CHECK_LAUNCH();
+        }
+    return LB_OK;
+}

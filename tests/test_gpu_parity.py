@@ -1,0 +1,257 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Floating-point results are compared normwise per array:
+    ||x - x_ref||_inf <= 1e-10 * ||x_ref||_inf,
+integer and index results bit for bit (sets of structure-constant triples are
+compared after sorting, since their emission order is not part of the method).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from paper_1912_01491_amd import workloads as wl  # noqa: E402
+
+RTOL = 1e-10
+
+
+def rel(x, ref):
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    den = np.abs(ref).max()
+    return np.abs(x - ref).max() / (den if den > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import paper_1912_01491_amd as lb
+    lb.load()
+    return lb
+
+
+@pytest.fixture(scope="module")
+def ctx(lb):
+    print("[gpu] creating context", flush=True)
+    c = lb.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+# ---------------------------------------------------------------------------
+# basis and structure constants (integer, bit-exact)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N", [2, 3, 7, 64, 200, 1024])
+def test_basis_table_bit_exact(lb, ctx, oracle, N):
+    print("[gpu] basis table N=%d" % N, flush=True)
+    t = lb.lb_basis_table(ctx, N).cpu().numpy()
+    M = N * N - 1
+    idx = np.unique(np.concatenate([np.arange(min(M, 3000)), np.linspace(0, M - 1, 3000).astype(np.int64)]))
+    want = np.array([oracle.class_of(N, int(i)) for i in idx], dtype=np.int32)
+    assert np.array_equal(t[idx], want)
+    # the table is a bijection onto the index classes
+    P = N * (N - 1) // 2
+    assert (t[:, 0] == 0).sum() == P and (t[:, 0] == 1).sum() == P and (t[:, 0] == 2).sum() == N - 1
+    for i in idx[:200]:
+        assert lb.lb_basis_index(N, int(i)) == tuple(want[list(idx).index(i)])
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 8, 13])
+@pytest.mark.parametrize("which", ["f", "d"])
+def test_fd_enumerate_bit_exact(lb, ctx, oracle, N, which):
+    print("[gpu] fd enumerate N=%d %s" % (N, which), flush=True)
+    mns, val = lb.lb_fd_enumerate(ctx, N, which)
+    mns = mns.cpu().numpy()
+    val = val.cpu().numpy()
+    omns, oval = oracle.fd_enumerate(N, which)
+    assert len(mns) == len(omns)
+    ka = np.lexsort(mns.T[::-1])
+    kb = np.lexsort(omns.T[::-1])
+    assert np.array_equal(mns[ka], omns[kb])
+    assert np.abs(val[ka] - oval[kb]).max(initial=0) < 1e-13
+
+
+@pytest.mark.parametrize("N", [16, 40, 100, 200])
+def test_fd_counts_large(lb, ctx, N):
+    print("[gpu] fd counts N=%d" % N, flush=True)
+    assert lb.lb_fd_count(ctx, N, "f") == 5 * N**3 - 9 * N**2 - 2 * N + 6
+    assert lb.lb_fd_count(ctx, N, "d") == round(6 * N**3 - 10.5 * N**2 - 3.5 * N + 1)
+
+
+# ---------------------------------------------------------------------------
+# expansion and reconstruction
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N", [2, 5, 33])
+def test_expand_reconstruct(lb, ctx, oracle, N):
+    print("[gpu] expand N=%d" % N, flush=True)
+    H = wl.gue_hamiltonian(N, 3)
+    a = lb.lb_expand(ctx, dev(H)).cpu().numpy()
+    assert rel(a, oracle.expand(H).real) < RTOL
+    psis = wl.random_pure_states(N, 3, 4)
+    V = lb.lb_expand_pure(ctx, dev(psis)).cpu().numpy()
+    for b in range(3):
+        want = oracle.expand(np.outer(psis[b], psis[b].conj())).real
+        assert rel(V[b], want) < RTOL
+    rho = lb.lb_reconstruct(ctx, dev(V), N).cpu().numpy()
+    for b in range(3):
+        assert np.abs(rho[b] - oracle.reconstruct(N, V[b])).max() < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# dense preparation
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,seed,ham", [(2, 0, "gue"), (3, 1, "plain"), (4, 2, "gue"), (5, 3, "zero"),
+                                        (8, 0, "plain"), (11, 4, "gue"), (17, 5, "gue")])
+def test_prepare_dense_full(lb, ctx, oracle, N, seed, ham):
+    print("[gpu] prepare dense N=%d" % N, flush=True)
+    H, gamma = wl.random_lindbladian(N, seed, hamiltonian=ham)
+    M = N * N - 1
+    Qo, Ko = oracle.prepare_dense(H, gamma)
+    for ldq in (M, M + 5, lb.default_ldq(M)):
+        Q, K = lb.lindblad_prepare(ctx, dev(H), dev(gamma), ldq=ldq)
+        Q = Q.cpu().numpy()
+        assert rel(Q[:, :M], Qo) < RTOL, (ldq, rel(Q[:, :M], Qo))
+        assert np.all(Q[:, M:] == 0)
+        assert rel(K.cpu().numpy(), Ko) < RTOL
+
+
+def test_prepare_dense_ragged_tiles(lb, ctx, oracle):
+    """N = 41: pair tiles of 8 x 32 vertices with ragged edges in both directions."""
+    N = 41
+    print("[gpu] prepare dense N=%d" % N, flush=True)
+    H, gamma = wl.random_lindbladian(N, 7)
+    M = N * N - 1
+    rows = np.unique(np.concatenate([np.arange(0, M, 37), [0, 1, M - 1, M - 2, 819, 820, 1639]]))
+    Qo, Ko = oracle.prepare_dense(H, gamma, rows=rows)
+    Q, K = lb.lindblad_prepare(ctx, dev(H), dev(gamma))
+    Q = Q.cpu().numpy()
+    assert rel(Q[rows, :M], Qo) < RTOL
+    assert rel(K.cpu().numpy(), Ko) < RTOL
+
+
+def test_prepare_dense_depolarizing_and_trace(lb, ctx):
+    """Closed forms at a size the oracle is not run on: gamma = c 1 gives
+    Q = -cN 1 + Q_H, K = 0; Tr Q = -N Tr gamma for any H."""
+    N = 60
+    M = N * N - 1
+    c = 0.3
+    H = wl.gue_hamiltonian(N, 1)
+    Q, K = lb.lindblad_prepare(ctx, dev(H), dev(c * np.eye(M, dtype=np.complex128)), ldq=M)
+    QH, KH = lb.lindblad_prepare(ctx, dev(H), dev(np.zeros((M, M), np.complex128)), ldq=M)
+    Q = Q.cpu().numpy()
+    QH = QH.cpu().numpy()
+    assert np.abs(Q - QH + c * N * np.eye(M)).max() < 1e-12
+    assert np.abs(K.cpu().numpy()).max() < 1e-15 and np.abs(KH.cpu().numpy()).max() == 0
+    assert np.abs(QH + QH.T).max() < 1e-14
+
+
+def test_prepare_check_hermitian(lb, ctx):
+    N = 4
+    H, gamma = wl.random_lindbladian(N, 0)
+    gamma[1, 2] += 0.1
+    with pytest.raises(lb.LindbladError) as e:
+        lb.lindblad_prepare(ctx, dev(H), dev(gamma), check_hermitian=True)
+    assert e.value.code == -2
+
+
+# ---------------------------------------------------------------------------
+# propagation
+# ---------------------------------------------------------------------------
+
+def _system(oracle, N, seed):
+    H, gamma = wl.random_lindbladian(N, seed)
+    Q, K = oracle.prepare_dense(H, gamma)
+    return H, gamma, Q, K
+
+
+@pytest.mark.parametrize("N,B,steps", [(8, 1, 300), (8, 16, 100), (13, 1, 50), (13, 3, 40), (18, 1, 30),
+                                       (18, 16, 20), (18, 23, 10), (18, 64, 10), (24, 5, 10)])
+def test_propagate_dense_fp64(lb, ctx, oracle, N, B, steps):
+    print("[gpu] propagate N=%d B=%d" % (N, B), flush=True)
+    H, gamma, Qo, Ko = _system(oracle, N, 20 + N)
+    M = N * N - 1
+    psis = wl.random_pure_states(N, B, 9)
+    V0 = np.array([oracle.expand(np.outer(p, p.conj())).real for p in psis])
+    Vo = oracle.rk4_dense(Qo, Ko, V0, 1e-3, steps)
+    Q, K = lb.lindblad_prepare(ctx, dev(H), dev(gamma))
+    V = dev(V0)
+    lb.lindblad_propagate(ctx, Q, K, V, 1e-3, steps)
+    assert rel(V.cpu().numpy(), Vo) < RTOL
+    # unpadded, odd leading dimension
+    Qu, Ku = lb.lindblad_prepare(ctx, dev(H), dev(gamma), ldq=M)
+    V = dev(V0)
+    lb.lindblad_propagate(ctx, Qu, Ku, V, 1e-3, steps)
+    assert rel(V.cpu().numpy(), Vo) < RTOL
+
+
+@pytest.mark.parametrize("B", [1, 16])
+def test_propagate_fp32_error_stated(lb, ctx, oracle, B):
+    N = 18
+    print("[gpu] propagate fp32 N=%d B=%d" % (N, B), flush=True)
+    H, gamma, Qo, Ko = _system(oracle, N, 3)
+    psis = wl.random_pure_states(N, B, 2)
+    V0 = np.array([oracle.expand(np.outer(p, p.conj())).real for p in psis])
+    Vo = oracle.rk4_dense(Qo, Ko, V0, 1e-3, 50)
+    Q, K = lb.lindblad_prepare(ctx, dev(H), dev(gamma))
+    Q32 = lb.lindblad_q_to_f32(ctx, Q)
+    V = dev(V0)
+    lb.lindblad_propagate(ctx, None, K, V, 1e-3, 50, precision=lb.FP32, Q32=Q32)
+    err = rel(V.cpu().numpy(), Vo)
+    print("[gpu] fp32 path normwise error %.3e" % err, flush=True)
+    assert err < 2e-6
+
+
+def test_propagate_batched_equals_single(lb, ctx, oracle):
+    N = 13
+    print("[gpu] batched N=%d" % N, flush=True)
+    sys = [_system(oracle, N, 40 + r) for r in range(3)]
+    Qs, Ks, Vs, V0s = [], [], [], []
+    for H, gamma, _, _ in sys:
+        Q, K = lb.lindblad_prepare(ctx, dev(H), dev(gamma))
+        Qs.append(Q)
+        Ks.append(K)
+    for r in range(3):
+        psis = wl.random_pure_states(N, 4, r)
+        V0 = np.array([oracle.expand(np.outer(p, p.conj())).real for p in psis])
+        V0s.append(V0)
+        Vs.append(dev(V0))
+    lb.lindblad_propagate_batched(ctx, Qs, Ks, Vs, 1e-3, 20)
+    for r in range(3):
+        V = dev(V0s[r])
+        lb.lindblad_propagate(ctx, Qs[r], Ks[r], V, 1e-3, 20)
+        assert torch.equal(V, Vs[r])
+        Vo = oracle.rk4_dense(sys[r][2], sys[r][3], V0s[r], 1e-3, 20)
+        assert rel(Vs[r].cpu().numpy(), Vo) < RTOL
+
+
+def test_propagate_deterministic(lb, ctx, oracle):
+    N = 24
+    H, gamma = wl.random_lindbladian(N, 5)
+    Q, K = lb.lindblad_prepare(ctx, dev(H), dev(gamma))
+    V0 = torch.randn(16, N * N - 1, dtype=torch.float64, device="cuda") * 0.01
+    outs = []
+    for _ in range(2):
+        V = V0.clone()
+        lb.lindblad_propagate(ctx, Q, K, V, 1e-3, 5)
+        outs.append(V)
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_propagate_invalid_args(lb, ctx):
+    N = 4
+    M = N * N - 1
+    Q = torch.zeros((M, M), dtype=torch.float64, device="cuda")
+    K = torch.zeros(M, dtype=torch.float64, device="cuda")
+    V = torch.zeros((1, M), dtype=torch.float64, device="cuda")
+    with pytest.raises(lb.LindbladError):
+        lb.lindblad_propagate(ctx, Q, K, V, float("nan"), 1)
+    with pytest.raises(lb.LindbladError):
+        lb.lindblad_propagate(ctx, Q, K, V, 1e-3, -1)
