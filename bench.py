@@ -1,0 +1,235 @@
+#!/usr/bin/env python
+"""Benchmark of the GKSL -> real-ODE hot path on one MI355X.
+
+Workload (default): dense random Lindbladians with N = 200 (M = N^2 - 1 =
+39999): 8 ensemble realizations (seeds 0..7), each with a GUE Hamiltonian and
+a Wishart Kossakowski matrix gamma = N W W^+ / Tr(W W^+) (W complex Ginibre,
+M x M, 25.6 GB in complex128), assembled into Q (12.8 GB, FP64) and K and held
+on the device, then 16 pure initial states per realization propagated by 1000
+classic RK4 steps of dt = 1e-3 in one batched launch sequence.
+
+One timed "step" of this script is the whole job: for every realization the
+dense preparation (Q, K from H and gamma, with gamma resident in HBM when its
+timer starts), then the expansion of the 128 initial states, the batched RK4
+integration and the reconstruction of rho(T). gamma matrices are drawn on the
+device before each preparation's timed region (they do not all fit in HBM at
+once next to the 8 resident Q); only the library calls are timed, each
+bracketed by device synchronization.
+
+value = realizations x RK4 steps / total timed seconds, i.e. RK4 steps per
+second of one 16-state block including its share of the assembly.
+
+The JSON line also carries the roofline of the dominant kernel (the RK4 stage
+GEMM over all 8 systems, timed with HIP events on the stream it runs on) and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Q,K assembly s + RK4 steps/s at N=200 dense; batched solves/s, p99 vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1, help="timed passes over the whole job")
+    ap.add_argument("--warmup", type=int, default=0, help="untimed passes over the whole job")
+    ap.add_argument("--N", type=int, default=200)
+    ap.add_argument("--realizations", type=int, default=8)
+    ap.add_argument("--states", type=int, default=16)
+    ap.add_argument("--rk4-steps", type=int, default=1000)
+    ap.add_argument("--dt", type=float, default=1e-3)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--graph", action="store_true", help="replay the RK4 launches from a HIP graph")
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle RK4 steps in the CPU sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(M: int, B: int, steps: int):
+    """The oracle's RK4 (plain C, OpenMP over rows) on a bounded sample: `steps`
+    RK4 steps of a B-state block at the full M, on a stand-in Q of the same
+    shape (values do not affect its time)."""
+    import numpy as np
+
+    import oracle
+
+    oracle.build()
+    log("cpu baseline: allocating stand-in Q (%.1f GB)" % (8.0 * M * M / 1e9))
+    Q = np.full((M, M), 1e-7)
+    K = np.full(M, 1e-7)
+    V = np.full((B, M), 1e-3)
+    oracle.rk4_dense(Q[:64, :64].copy(), K[:64], V[:, :64], 1e-3, 1)  # load / warm the library
+    t0 = time.perf_counter()
+    oracle.rk4_dense(Q, K, V, 1e-3, steps)
+    dt = time.perf_counter() - t0
+    del Q
+    rate = steps / dt
+    return {"value": rate, "unit": "RK4 steps/s (16-state block, N=200)", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%d RK4 steps of a %d-state block at M=%d (full row length) on a stand-in Q of the "
+                      "same shape; assembly not included; %.2f s" % (steps, B, M, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d requested)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1912_01491_amd as lb
+    from paper_1912_01491_amd import workloads as wl
+
+    N, R, B, S, dt = args.N, args.realizations, args.states, args.rk4_steps, args.dt
+    M = N * N - 1
+    ldq = lb.default_ldq(M)
+    prec = lb.FP32 if args.precision == "fp32" else lb.FP64
+    dev = torch.device("cuda", 0)
+    ctx = lb.Context(0)
+    log("N=%d M=%d realizations=%d states=%d rk4_steps=%d precision=%s" % (N, M, R, B, S, args.precision))
+
+    Hs = [torch.from_numpy(wl.gue_hamiltonian(N, r)).to(dev) for r in range(R)]
+    psis = [torch.from_numpy(wl.random_pure_states(N, B, 100 + r)).to(dev) for r in range(R)]
+    Qs = [torch.empty((M, ldq), dtype=torch.float64, device=dev) for _ in range(R)]
+    Ks = [torch.empty(M, dtype=torch.float64, device=dev) for _ in range(R)]
+    Q32s = [torch.empty((M, ldq), dtype=torch.float32, device=dev) for _ in range(R)] if prec == lb.FP32 else None
+
+    def sync():
+        torch.cuda.synchronize()
+
+    def job():
+        t_prep = []
+        for r in range(R):
+            gamma = wl.wishart_kossakowski_device(N, 1000 + r, device=dev)
+            sync()
+            t0 = time.perf_counter()
+            lb.lindblad_prepare(ctx, Hs[r], gamma, ldq=ldq, Q=Qs[r], K=Ks[r])
+            if Q32s is not None:
+                Q32s[r].copy_(lb.lindblad_q_to_f32(ctx, Qs[r]))
+            sync()
+            t_prep.append(time.perf_counter() - t0)
+            del gamma
+            torch.cuda.empty_cache()
+            log("prepared realization %d in %.2f ms" % (r, 1e3 * t_prep[-1]))
+        sync()
+        t0 = time.perf_counter()
+        Vs = [lb.lb_expand_pure(ctx, psis[r]) for r in range(R)]
+        if args.graph:
+            for r in range(R):
+                lb.lindblad_propagate_graph(ctx, Qs[r] if prec == lb.FP64 else None, Ks[r], Vs[r], dt, S,
+                                            precision=prec, Q32=Q32s[r] if Q32s else None)
+        else:
+            lb.lindblad_propagate_batched(ctx, Qs if prec == lb.FP64 else None, Ks, Vs, dt, S, precision=prec,
+                                          Q32s=Q32s)
+        rhos = [lb.lb_reconstruct(ctx, Vs[r], N) for r in range(R)]
+        sync()
+        t_prop = time.perf_counter() - t0
+        log("propagated %d x %d states x %d steps in %.2f s" % (R, B, S, t_prop))
+        return t_prep, t_prop, rhos
+
+    if args.autotune:
+        V = torch.zeros((B, M), dtype=torch.float64, device=dev)
+        gamma = wl.wishart_kossakowski_device(N, 1000, device=dev)
+        lb.lindblad_prepare(ctx, Hs[0], gamma, ldq=ldq, Q=Qs[0], K=Ks[0])
+        del gamma
+        lb.lindblad_autotune(ctx, Qs[0] if prec == lb.FP64 else None, Ks[0], B, precision=prec,
+                             Q32=lb.lindblad_q_to_f32(ctx, Qs[0]) if prec == lb.FP32 else None)
+        log("autotuned tile: %s" % lb.lindblad_tile_info(ctx, M, B, prec))
+
+    for w in range(args.warmup):
+        log("warmup pass %d" % w)
+        job()
+    sync()
+    results = []
+    for k in range(args.steps):
+        log("timed pass %d" % k)
+        results.append(job())
+    t_prep_all = [t for res in results for t in res[0]]
+    t_prop_all = [res[1] for res in results]
+    total = sum(t_prep_all) + sum(t_prop_all)
+    ms_per_step = 1e3 * total / args.steps
+    value = R * S * args.steps / total
+
+    # checks on rho(T) of the last pass: unit trace, Hermitian, positive
+    rhos = results[-1][2]
+    rho = torch.cat(rhos).cpu().numpy()
+    tr_err = float(np.abs(np.einsum("bii->b", rho) - 1).max())
+    herm = float(np.abs(rho - rho.conj().transpose(0, 2, 1)).max())
+    mineig = float(min(np.linalg.eigvalsh(x).min() for x in rho))
+    finite = bool(all(torch.isfinite(k).all().item() for k in Ks))
+
+    # dominant kernel: RK4 stage GEMM over all R systems, HIP events on its stream
+    Vt = [torch.zeros((B, M), dtype=torch.float64, device=dev) for _ in range(R)]
+    iters = 5
+    avg_ms = lb.lindblad_time_stage(ctx, Qs if prec == lb.FP64 else None, Ks, Vt, iters=iters, precision=prec,
+                                    Q32s=Q32s)
+    qbytes = 8 if prec == lb.FP64 else 4
+    alg_bytes = R * M * M * qbytes
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    tile = lb.lindblad_tile_info(ctx, M, B, prec)
+    log("stage GEMM: %.3f ms per launch over %d systems -> %.0f GB/s" % (avg_ms, R, achieved))
+
+    t_prep_mean = sum(t_prep_all) / len(t_prep_all)
+    asm_bytes = 16.0 * M * M  # independent reals of gamma + Q, 8 bytes each
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "RK4 steps/s (one 16-state block at N=200, assembly included)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == lb.FP64 else "f32-mfma/f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "dense random Lindbladian N=%d (M=%d), %d realizations x %d pure states, "
+                        "%d RK4 steps dt=%g" % (N, M, R, B, S, dt),
+            "N": N, "M": M, "realizations": R, "states": B, "rk4_steps": S, "dt": dt,
+            "precision": args.precision, "ldq": ldq, "graph": bool(args.graph), "tile": tile,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "k_gemm64" if prec == lb.FP64 else "k_gemm32",
+            "avg_ms": avg_ms,
+            "bytes_per_launch": alg_bytes,
+        },
+        "assembly_s_per_realization": t_prep_mean,
+        "assembly_gbs": asm_bytes / t_prep_mean / 1e9,
+        "rk4_steps_per_s": R * S * args.steps / sum(t_prop_all),
+        "solves_per_s": R * B * args.steps / total,
+        "checks": {"max_abs_trace_err": tr_err, "max_herm_err": herm, "min_eig_rho": mineig,
+                   "K_finite": finite},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(M, B, args.cpu_steps)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -217,6 +217,15 @@ int lindblad_propagate_graph(lb_ctx* ctx, int64_t M, const double* Q, const floa
 int lindblad_autotune(lb_ctx* ctx, int64_t M, const double* Q, const float* Q32, int64_t ldq,
                       const double* K, double* V, int B, int precision);
 
+/* Measurement: average duration in milliseconds of the dominant RK4 stage
+ * kernel (the stage GEMM, or the stage GEMV for one FP64 state) for R
+ * systems, over `iters` back-to-back launches timed with HIP events on the
+ * context stream. Arguments as for lindblad_propagate_batched; the states are
+ * read but not advanced. Synchronizes. */
+int lindblad_time_stage(lb_ctx* ctx, int R, int64_t M, const double* const* Q, const float* const* Q32,
+                        int64_t ldq, const double* const* K, double* const* V, int B, int precision,
+                        int iters, double* avg_ms);
+
 /* Describes the tile shape propagate will use for (M, B, precision):
  * rows per wave, k-slab length, waves per workgroup, and whether it came
  * from the tuner (1) or the default table (0). Host only. */

@@ -24,7 +24,7 @@ __all__ = [
     "lb_expand", "lb_expand_pure", "lb_reconstruct",
     "lindblad_prepare", "lindblad_q_to_f32", "lindblad_propagate", "lindblad_propagate_batched",
     "lindblad_propagate_graph", "lindblad_propagate_csr", "lindblad_prepare_sparse",
-    "lindblad_autotune", "lindblad_tile_info",
+    "lindblad_autotune", "lindblad_tile_info", "lindblad_time_stage",
     "FP64", "FP32", "CHECK_HERMITIAN",
 ]
 
@@ -92,6 +92,7 @@ def load():
         "lindblad_propagate_graph": [V, I64, V, V, I64, V, V, I, D, I64, I],
         "lindblad_autotune": [V, I64, V, V, I64, V, V, I, I],
         "lindblad_tile_info": [V, I64, I, I, V, V, V, V],
+        "lindblad_time_stage": [V, I, I64, V, V, I64, V, V, I, I, I, V],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -395,3 +396,20 @@ def lindblad_tile_info(ctx: Context, M: int, B: int, precision: int = FP64):
     _check(load().lindblad_tile_info(ctx.handle, int(M), int(B), int(precision), ctypes.byref(r),
                                      ctypes.byref(k), ctypes.byref(w), ctypes.byref(t)))
     return {"rows": r.value, "kslab": k.value, "waves": w.value, "tuned": bool(t.value)}
+
+
+def lindblad_time_stage(ctx: Context, Qs, Ks, Vs, iters: int = 10, precision: int = FP64, Q32s=None) -> float:
+    """Average duration (ms) of one launch of the dominant RK4 stage kernel over
+    the R systems (HIP events on the context stream)."""
+    R = len(Ks)
+    for r in range(R):
+        M, ldq = _prop_args(Qs[r] if Qs else None, Q32s[r] if Q32s else None, Ks[r], Vs[r], precision)
+    arr = ctypes.c_void_p * R
+    qa = arr(*[q.data_ptr() for q in Qs]) if Qs else None
+    q32a = arr(*[q.data_ptr() for q in Q32s]) if Q32s else None
+    ka = arr(*[k.data_ptr() for k in Ks])
+    va = arr(*[v.data_ptr() for v in Vs])
+    ms = ctypes.c_double()
+    _check(load().lindblad_time_stage(ctx.handle, R, M, qa, q32a, ldq, ka, va, Vs[0].shape[0], int(precision),
+                                      int(iters), ctypes.byref(ms)))
+    return ms.value

@@ -109,10 +109,9 @@ int lb_destroy(lb_ctx* c) {
     if (!c) return LB_OK;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : c->graphs) lb_graph_free(kv.second);
     if (c->ws) (void)hipFree(c->ws);
     if (c->host) (void)hipHostFree(c->host);
-    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete c;
     return LB_OK;
 }
@@ -326,6 +325,53 @@ int lindblad_propagate_batched(lb_ctx* c, int R, int64_t M, const double* const*
             return lb_fail(LB_ERR_INVALID_ARG, "null pointer for system %d", r);
     }
     return lb_impl_propagate(c, R, M, sys.data(), ldq, B, dt, steps, precision, nullptr);
+}
+
+int lindblad_propagate_graph(lb_ctx* c, int64_t M, const double* Q, const float* Q32, int64_t ldq, const double* K,
+                             double* V, int B, double dt, int64_t steps, int precision) {
+    CHECK_CTX(c);
+    int rc = check_prop(M, ldq, B, dt, steps, precision);
+    if (rc) return rc;
+    CHECK_PTR(K);
+    CHECK_PTR(V);
+    if (precision == LB_FP64) CHECK_PTR(Q);
+    else CHECK_PTR(Q32);
+    lb_prop_sys s{Q, Q32, K, V};
+    return lb_impl_propagate_graph(c, M, &s, ldq, B, dt, steps, precision);
+}
+
+int lindblad_autotune(lb_ctx* c, int64_t M, const double* Q, const float* Q32, int64_t ldq, const double* K,
+                      double* V, int B, int precision) {
+    CHECK_CTX(c);
+    int rc = check_prop(M, ldq, B, 0.0, 0, precision);
+    if (rc) return rc;
+    CHECK_PTR(K);
+    CHECK_PTR(V);
+    if (precision == LB_FP64) CHECK_PTR(Q);
+    else CHECK_PTR(Q32);
+    lb_prop_sys s{Q, Q32, K, V};
+    return lb_impl_autotune(c, M, &s, ldq, B, precision);
+}
+
+int lindblad_time_stage(lb_ctx* c, int R, int64_t M, const double* const* Q, const float* const* Q32, int64_t ldq,
+                        const double* const* K, double* const* V, int B, int precision, int iters, double* avg_ms) {
+    CHECK_CTX(c);
+    int rc = check_prop(M, ldq, B, 0.0, 0, precision);
+    if (rc) return rc;
+    if (R < 1 || R > 65535 || iters < 1) return lb_fail(LB_ERR_INVALID_ARG, "bad R or iters");
+    CHECK_PTR(K);
+    CHECK_PTR(V);
+    CHECK_PTR(avg_ms);
+    std::vector<lb_prop_sys> sys(R);
+    for (int r = 0; r < R; ++r) {
+        sys[r].Q = Q ? Q[r] : nullptr;
+        sys[r].Q32 = Q32 ? Q32[r] : nullptr;
+        sys[r].K = K[r];
+        sys[r].V = V[r];
+        if (!sys[r].K || !sys[r].V || (precision == LB_FP64 && !sys[r].Q) || (precision == LB_FP32 && !sys[r].Q32))
+            return lb_fail(LB_ERR_INVALID_ARG, "null pointer for system %d", r);
+    }
+    return lb_impl_time_stage(c, R, M, sys.data(), ldq, B, precision, iters, avg_ms, nullptr);
 }
 
 int lindblad_tile_info(lb_ctx* c, int64_t M, int B, int precision, int* rows, int* kslab, int* waves, int* tuned) {

@@ -70,9 +70,13 @@ struct lb_ctx {
     size_t host_bytes = 0;
     // tuned tile shapes: key (M, Bp, precision)
     std::map<std::tuple<int64_t, int, int>, lb_tile> tuned;
+    bool cache_loaded = false;
     // captured propagate graphs
-    std::map<lb_graph_key, hipGraphExec_t> graphs;
+    std::map<lb_graph_key, struct lb_graph_entry*> graphs;
 };
+
+struct lb_graph_entry;
+void lb_graph_free(lb_graph_entry* g);
 
 // Ensures the workspace holds at least `bytes`; returns LB_OK or LB_ERR_OOM.
 int lb_ws_reserve(lb_ctx* c, size_t bytes);
@@ -192,6 +196,11 @@ struct lb_prop_sys {
 
 int lb_impl_propagate(lb_ctx* c, int R, int64_t M, const lb_prop_sys* sys, int64_t ldq, int B,
                       double dt, int64_t steps, int precision, const lb_tile* force_tile);
+int lb_impl_time_stage(lb_ctx* c, int R, int64_t M, const lb_prop_sys* sys, int64_t ldq, int B, int precision,
+                       int iters, double* ms, const lb_tile* force_tile);
+int lb_impl_propagate_graph(lb_ctx* c, int64_t M, const lb_prop_sys* sys, int64_t ldq, int B, double dt,
+                            int64_t steps, int precision);
+int lb_impl_autotune(lb_ctx* c, int64_t M, const lb_prop_sys* sys, int64_t ldq, int B, int precision);
 int lb_impl_propagate_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int64_t* col,
                           const double* val, const double* K, double* V, int B, double dt,
                           int64_t steps);

@@ -26,6 +26,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <stdio.h>
+#include <stdlib.h>
 
 typedef double lb_double4 __attribute__((ext_vector_type(4)));
 typedef float lb_float4 __attribute__((ext_vector_type(4)));
@@ -550,9 +552,9 @@ int bpad(int B) { return B <= 16 ? 16 : (B <= 32 ? 32 : 64); }
 lb_tile lb_default_tile(int64_t M, int Bp, int precision) {
     lb_tile t;
     const int CT = Bp / 16;
-    t.rows = CT == 1 ? 64 : (CT == 2 ? 32 : 32);
-    if (precision == LB_FP32 && CT == 1) t.rows = 64;
+    t.rows = CT == 1 ? 64 : 32;
     t.waves = 4;
+    (void)precision;
     const int64_t rowwaves = (M + t.rows - 1) / t.rows;
     int64_t nslab = (4096 + rowwaves - 1) / rowwaves;
     const int64_t maxslab = (M + 255) / 256;
@@ -564,7 +566,23 @@ lb_tile lb_default_tile(int64_t M, int Bp, int precision) {
     return t;
 }
 
+// Tile-cache file (LB_TUNE_CACHE): one line "M Bp precision rows kslab waves".
+static void load_tune_cache(lb_ctx* c) {
+    if (c->cache_loaded) return;
+    c->cache_loaded = true;
+    const char* path = getenv("LB_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    long long M;
+    int Bp, prec, rows, ks, waves;
+    while (fscanf(f, "%lld %d %d %d %d %d", &M, &Bp, &prec, &rows, &ks, &waves) == 6)
+        c->tuned[std::make_tuple((int64_t)M, Bp, prec)] = lb_tile{rows, ks, waves};
+    fclose(f);
+}
+
 static lb_tile choose_tile(lb_ctx* c, int64_t M, int Bp, int precision) {
+    load_tune_cache(c);
     auto it = c->tuned.find(std::make_tuple(M, Bp, precision));
     if (it != c->tuned.end()) return it->second;
     return lb_default_tile(M, Bp, precision);
@@ -577,100 +595,94 @@ int lb_impl_q_to_f32(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, float* 
     return LB_OK;
 }
 
-// R systems of size M, B states each.
-int lb_impl_propagate(lb_ctx* c, int R, int64_t M, const lb_prop_sys* sys, int64_t ldq, int B, double dt,
-                      int64_t steps, int precision, const lb_tile* force_tile) {
-    hipStream_t s = c->stream;
-    if (steps == 0) return LB_OK;
-    // --- small systems: one workgroup per system, everything in LDS
-    if (M <= 256 && (int64_t)B * M <= 4096 && precision == LB_FP64 && force_tile == nullptr) {
-        const size_t pbytes = sizeof(void*) * 3 * R;
-        int rc = lb_ws_reserve(c, pbytes);
-        if (rc) return rc;
-        rc = lb_host_reserve(c, pbytes);
-        if (rc) return rc;
-        LB_HIP(hipStreamSynchronize(s));
-        const void** h = (const void**)c->host;
-        for (int r = 0; r < R; ++r) {
-            h[r] = sys[r].Q;
-            h[R + r] = sys[r].K;
-            h[2 * R + r] = sys[r].V;
-        }
-        LB_HIP(hipMemcpyAsync(c->ws, h, pbytes, hipMemcpyHostToDevice, s));
-        const void** d = (const void**)c->ws;
-        const size_t base = sizeof(double) * 2 * (size_t)B * M;
-        const size_t withq = base + sizeof(double) * (size_t)M * M;
-        const int q_in_lds = withq <= 64 * 1024 ? 1 : 0;
-        const size_t shm = q_in_lds ? withq : base;
-        hipLaunchKernelGGL(k_rk4_small, dim3(R), dim3(256), shm, s, (const double* const*)d,
-                           (const double* const*)(d + R), (double* const*)(d + 2 * R), (int)M, ldq, B, dt, steps,
-                           q_in_lds);
-        LB_CHECK_LAUNCH();
-        return LB_OK;
-    }
-    const bool aligned = (ldq % 2 == 0);
-    // --- one state, FP64: GEMV with fused combine
-    if (B == 1 && precision == LB_FP64) {
-        const int64_t wstride = 3 * lb_align(M, 32);
-        const size_t pbytes = lb_align(sizeof(void*) * 3 * R, 256);
-        int rc = lb_ws_reserve(c, pbytes + sizeof(double) * wstride * R);
-        if (rc) return rc;
-        rc = lb_host_reserve(c, sizeof(void*) * 3 * R);
-        if (rc) return rc;
-        LB_HIP(hipStreamSynchronize(s));
-        const void** h = (const void**)c->host;
-        for (int r = 0; r < R; ++r) {
-            h[r] = sys[r].Q;
-            h[R + r] = sys[r].K;
-            h[2 * R + r] = sys[r].V;
-        }
-        LB_HIP(hipMemcpyAsync(c->ws, h, sizeof(void*) * 3 * R, hipMemcpyHostToDevice, s));
-        const void** d = (const void**)c->ws;
-        double* W = (double*)((char*)c->ws + pbytes);
-        for (int r = 0; r < R; ++r)
-            if (((uintptr_t)sys[r].Q) % 16) return lb_fail(LB_ERR_INVALID_ARG, "Q must be 16-byte aligned");
-        hipLaunchKernelGGL(k_gemv_init, dim3(lb_blocks(M, 256), R), dim3(256), 0, s, (double* const*)(d + 2 * R), M,
-                           W, wstride);
-        LB_CHECK_LAUNCH();
-        constexpr int RW = 8;
-        const unsigned gx = lb_blocks((M + RW - 1) / RW, 4);
-        auto fn = aligned ? k_gemv<RW, true> : k_gemv<RW, false>;
-        for (int64_t st = 0; st < steps; ++st)
-            for (int stage = 1; stage <= 4; ++stage) {
-                hipLaunchKernelGGL(fn, dim3(gx, R), dim3(256), 0, s, (const double* const*)d,
-                                   (const double* const*)(d + R), (double* const*)(d + 2 * R), M, ldq, W, wstride,
-                                   stage, dt);
-                LB_CHECK_LAUNCH();
-            }
-        return LB_OK;
-    }
-    // --- matrix-core path
-    const int Bp = bpad(B);
-    const int CT = Bp / 16;
-    const lb_tile tile = force_tile ? *force_tile : choose_tile(c, M, Bp, precision);
-    const int RT = tile.rows / 16;
-    const int64_t Mp = (M + 15) / 16 * 16;
-    const int nslab = (int)((M + tile.kslab - 1) / tile.kslab);
-    const int64_t sstride = lb_align(Mp * Bp, 64);
-    const int64_t s32stride = lb_align(Mp * Bp, 128);
-    const int64_t pstride = (int64_t)nslab * Mp * Bp;
+// ---------------------------------------------------------------------------
+// Propagation plan: path selection, buffer layout, kernel enqueueing.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+enum PathKind { PATH_SMALL, PATH_GEMV, PATH_MFMA };
+
+struct Plan {
+    PathKind kind;
+    int R;
+    int64_t M, Mp, ldq;
+    int B, Bp, precision;
+    lb_tile tile;
+    int nslab;
+    int64_t sstride, s32stride, pstride, wstride;
+    size_t o_ptr, o_v, o_acc, o_x, o_x32, o_part, o_w, bytes;
+    size_t shm;
+    int q_in_lds;
+    bool aligned;
+    const void** d;
+    double *V, *Acc, *X, *Part, *W;
+    float* X32;
+};
+
+static int plan_make(Plan& p, int R, int64_t M, int64_t ldq, int B, int precision, const lb_tile& tile,
+                     bool allow_small) {
+    p = Plan();
+    p.R = R;
+    p.M = M;
+    p.ldq = ldq;
+    p.B = B;
+    p.precision = precision;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
         off = lb_align(off + bytes, 256);
         return o;
     };
-    const size_t o_ptr = take(sizeof(void*) * 5 * R);
-    const size_t o_v = take(sizeof(double) * sstride * R);
-    const size_t o_acc = take(sizeof(double) * sstride * R);
-    const size_t o_x = take(sizeof(double) * sstride * R);
-    const size_t o_x32 = precision == LB_FP32 ? take(sizeof(float) * s32stride * R) : 0;
-    const size_t o_part = take(sizeof(double) * pstride * R);
-    int rc = lb_ws_reserve(c, off);
+    p.o_ptr = take(sizeof(void*) * 5 * R);
+    if (allow_small && M <= 256 && (int64_t)B * M <= 4096 && precision == LB_FP64) {
+        p.kind = PATH_SMALL;
+        const size_t base = sizeof(double) * 2 * (size_t)B * M;
+        const size_t withq = base + sizeof(double) * (size_t)M * M;
+        p.q_in_lds = withq <= 64 * 1024 ? 1 : 0;
+        p.shm = p.q_in_lds ? withq : base;
+    } else if (B == 1 && precision == LB_FP64) {
+        p.kind = PATH_GEMV;
+        p.aligned = ldq % 2 == 0;
+        p.wstride = 3 * (int64_t)lb_align(M, 32);
+        p.o_w = take(sizeof(double) * p.wstride * R);
+    } else {
+        p.kind = PATH_MFMA;
+        p.Bp = bpad(B);
+        p.tile = tile;
+        p.Mp = (M + 15) / 16 * 16;
+        p.nslab = (int)((M + tile.kslab - 1) / tile.kslab);
+        p.sstride = lb_align(p.Mp * p.Bp, 64);
+        p.s32stride = lb_align(p.Mp * p.Bp, 128);
+        p.pstride = (int64_t)p.nslab * p.Mp * p.Bp;
+        p.aligned = precision == LB_FP32 ? (ldq % 4 == 0) : (ldq % 2 == 0);
+        p.o_v = take(sizeof(double) * p.sstride * R);
+        p.o_acc = take(sizeof(double) * p.sstride * R);
+        p.o_x = take(sizeof(double) * p.sstride * R);
+        if (precision == LB_FP32) p.o_x32 = take(sizeof(float) * p.s32stride * R);
+        p.o_part = take(sizeof(double) * p.pstride * R);
+        const int RT = tile.rows / 16, CT = p.Bp / 16;
+        if (tile.rows % 16 || tile.kslab % 16 || tile.kslab <= 0 || tile.waves < 1 || tile.waves > 4 ||
+            (precision == LB_FP64 ? (p.aligned ? pick64<true>(RT, CT) : pick64<false>(RT, CT)) == nullptr
+                                  : (p.aligned ? pick32<true>(RT, CT) : pick32<false>(RT, CT)) == nullptr))
+            return lb_fail(LB_ERR_INVALID_ARG, "unsupported tile rows=%d kslab=%d waves=%d for Bp=%d", tile.rows,
+                           tile.kslab, tile.waves, p.Bp);
+    }
+    p.bytes = off;
+    return LB_OK;
+}
+
+// Binds the plan to device memory `base` (p.bytes) and uploads the per-system
+// pointer arrays through the context's pinned staging buffer. Synchronizes.
+static int plan_bind(lb_ctx* c, Plan& p, char* base, const lb_prop_sys* sys) {
+    const int R = p.R;
+    for (int r = 0; r < R; ++r) {
+        const void* qp = p.precision == LB_FP32 ? (const void*)sys[r].Q32 : (const void*)sys[r].Q;
+        if (p.kind != PATH_SMALL && ((uintptr_t)qp) % 16) return lb_fail(LB_ERR_INVALID_ARG, "Q must be 16-byte aligned");
+    }
+    int rc = lb_host_reserve(c, sizeof(void*) * 5 * R);
     if (rc) return rc;
-    rc = lb_host_reserve(c, sizeof(void*) * 5 * R);
-    if (rc) return rc;
-    LB_HIP(hipStreamSynchronize(s));
+    LB_HIP(hipStreamSynchronize(c->stream));
     const void** h = (const void**)c->host;
     for (int r = 0; r < R; ++r) {
         h[r] = sys[r].Q;
@@ -678,67 +690,283 @@ int lb_impl_propagate(lb_ctx* c, int R, int64_t M, const lb_prop_sys* sys, int64
         h[2 * R + r] = sys[r].K;
         h[3 * R + r] = sys[r].V;
         h[4 * R + r] = sys[r].V;
-        const void* qp = precision == LB_FP32 ? (const void*)sys[r].Q32 : (const void*)sys[r].Q;
-        if (((uintptr_t)qp) % 16) return lb_fail(LB_ERR_INVALID_ARG, "Q must be 16-byte aligned");
     }
-    char* ws = (char*)c->ws;
-    LB_HIP(hipMemcpyAsync(ws + o_ptr, h, sizeof(void*) * 5 * R, hipMemcpyHostToDevice, s));
-    const void** d = (const void**)(ws + o_ptr);
-    double* V = (double*)(ws + o_v);
-    double* Acc = (double*)(ws + o_acc);
-    double* X = (double*)(ws + o_x);
-    float* X32 = precision == LB_FP32 ? (float*)(ws + o_x32) : nullptr;
-    double* Part = (double*)(ws + o_part);
-    const bool al = precision == LB_FP32 ? (ldq % 4 == 0) : aligned;
+    LB_HIP(hipMemcpyAsync(base + p.o_ptr, h, sizeof(void*) * 5 * R, hipMemcpyHostToDevice, c->stream));
+    LB_HIP(hipStreamSynchronize(c->stream));
+    p.d = (const void**)(base + p.o_ptr);
+    if (p.kind == PATH_GEMV) p.W = (double*)(base + p.o_w);
+    if (p.kind == PATH_MFMA) {
+        p.V = (double*)(base + p.o_v);
+        p.Acc = (double*)(base + p.o_acc);
+        p.X = (double*)(base + p.o_x);
+        p.X32 = p.precision == LB_FP32 ? (float*)(base + p.o_x32) : nullptr;
+        p.Part = (double*)(base + p.o_part);
+    }
+    return LB_OK;
+}
 
-    hipLaunchKernelGGL(k_pack, dim3(lb_blocks(Mp * Bp, 256), R), dim3(256), 0, s, (const double* const*)(d + 3 * R),
-                       M, Mp, B, Bp, V, X, X32, sstride, s32stride);
-    LB_CHECK_LAUNCH();
+static StageArgs stage_args(const Plan& p, double dt) {
     StageArgs sa;
-    sa.Ks = (const double* const*)(d + 2 * R);
-    sa.V = V;
-    sa.Acc = Acc;
-    sa.X = X;
-    sa.X32 = X32;
-    sa.sstride = sstride;
-    sa.s32stride = s32stride;
-    sa.Part = Part;
-    sa.pstride = pstride;
-    sa.nslab = nslab;
-    sa.M = M;
-    sa.Mp = Mp;
-    sa.Bp = Bp;
+    sa.Ks = (const double* const*)(p.d + 2 * p.R);
+    sa.V = p.V;
+    sa.Acc = p.Acc;
+    sa.X = p.X;
+    sa.X32 = p.X32;
+    sa.sstride = p.sstride;
+    sa.s32stride = p.s32stride;
+    sa.Part = p.Part;
+    sa.pstride = p.pstride;
+    sa.nslab = p.nslab;
+    sa.M = p.M;
+    sa.Mp = p.Mp;
+    sa.Bp = p.Bp;
     sa.dt = dt;
-    const int64_t rowwaves = (M + tile.rows - 1) / tile.rows;
-    const dim3 ggrid((unsigned)((rowwaves + tile.waves - 1) / tile.waves), (unsigned)nslab, (unsigned)R);
-    const dim3 gblock(64 * tile.waves);
-    const dim3 sgrid(lb_blocks(M * Bp, 256), R);
-    if (precision == LB_FP64) {
-        gemm64_fn fn = al ? pick64<true>(RT, CT) : pick64<false>(RT, CT);
-        if (!fn) return lb_fail(LB_ERR_INVALID_ARG, "unsupported tile rows=%d for Bp=%d", tile.rows, Bp);
-        for (int64_t st = 0; st < steps; ++st)
-            for (int stage = 1; stage <= 4; ++stage) {
-                hipLaunchKernelGGL(fn, ggrid, gblock, 0, s, (const double* const*)d, M, Mp, ldq, (const double*)X,
-                                   sstride, Part, pstride, tile.kslab);
-                LB_CHECK_LAUNCH();
-                hipLaunchKernelGGL(k_stage, sgrid, dim3(256), 0, s, sa, stage);
-                LB_CHECK_LAUNCH();
-            }
-    } else {
-        gemm32_fn fn = al ? pick32<true>(RT, CT) : pick32<false>(RT, CT);
-        if (!fn) return lb_fail(LB_ERR_INVALID_ARG, "unsupported tile rows=%d for Bp=%d", tile.rows, Bp);
-        for (int64_t st = 0; st < steps; ++st)
-            for (int stage = 1; stage <= 4; ++stage) {
-                hipLaunchKernelGGL(fn, ggrid, gblock, 0, s, (const float* const*)(d + R), M, Mp, ldq,
-                                   (const float*)X32, s32stride, Part, pstride, tile.kslab);
-                LB_CHECK_LAUNCH();
-                hipLaunchKernelGGL(k_stage, sgrid, dim3(256), 0, s, sa, stage);
-                LB_CHECK_LAUNCH();
-            }
+    return sa;
+}
+
+// One launch of the stage GEMM (MFMA path) or the stage GEMV (stage 1).
+static int plan_gemm(const Plan& p, hipStream_t s, int stage, double dt) {
+    if (p.kind == PATH_GEMV) {
+        constexpr int RW = 8;
+        const unsigned gx = lb_blocks((p.M + RW - 1) / RW, 4);
+        auto fn = p.aligned ? k_gemv<RW, true> : k_gemv<RW, false>;
+        hipLaunchKernelGGL(fn, dim3(gx, p.R), dim3(256), 0, s, (const double* const*)p.d,
+                           (const double* const*)(p.d + 2 * p.R), (double* const*)(p.d + 3 * p.R), p.M, p.ldq, p.W,
+                           p.wstride, stage, dt);
+        LB_CHECK_LAUNCH();
+        return LB_OK;
     }
-    hipLaunchKernelGGL(k_unpack, dim3(lb_blocks(M * B, 256), R), dim3(256), 0, s, (double* const*)(d + 4 * R), M, B,
-                       Bp, (const double*)V, sstride);
+    const int RT = p.tile.rows / 16, CT = p.Bp / 16;
+    const int64_t rowwaves = (p.M + p.tile.rows - 1) / p.tile.rows;
+    const dim3 ggrid((unsigned)((rowwaves + p.tile.waves - 1) / p.tile.waves), (unsigned)p.nslab, (unsigned)p.R);
+    const dim3 gblock(64 * p.tile.waves);
+    if (p.precision == LB_FP64) {
+        gemm64_fn fn = p.aligned ? pick64<true>(RT, CT) : pick64<false>(RT, CT);
+        hipLaunchKernelGGL(fn, ggrid, gblock, 0, s, (const double* const*)p.d, p.M, p.Mp, p.ldq, (const double*)p.X,
+                           p.sstride, p.Part, p.pstride, p.tile.kslab);
+    } else {
+        gemm32_fn fn = p.aligned ? pick32<true>(RT, CT) : pick32<false>(RT, CT);
+        hipLaunchKernelGGL(fn, ggrid, gblock, 0, s, (const float* const*)(p.d + p.R), p.M, p.Mp, p.ldq,
+                           (const float*)p.X32, p.s32stride, p.Part, p.pstride, p.tile.kslab);
+    }
     LB_CHECK_LAUNCH();
+    return LB_OK;
+}
+
+static int plan_init_state(const Plan& p, hipStream_t s) {
+    if (p.kind == PATH_GEMV) {
+        hipLaunchKernelGGL(k_gemv_init, dim3(lb_blocks(p.M, 256), p.R), dim3(256), 0, s,
+                           (double* const*)(p.d + 3 * p.R), p.M, p.W, p.wstride);
+        LB_CHECK_LAUNCH();
+    } else if (p.kind == PATH_MFMA) {
+        hipLaunchKernelGGL(k_pack, dim3(lb_blocks(p.Mp * p.Bp, 256), p.R), dim3(256), 0, s,
+                           (const double* const*)(p.d + 3 * p.R), p.M, p.Mp, p.B, p.Bp, p.V, p.X, p.X32, p.sstride,
+                           p.s32stride);
+        LB_CHECK_LAUNCH();
+    }
+    return LB_OK;
+}
+
+// Enqueues the whole integration (kernels only: no synchronization, no copies),
+// so it can be recorded into a graph.
+static int plan_launch(const Plan& p, hipStream_t s, double dt, int64_t steps) {
+    if (steps == 0) return LB_OK;
+    if (p.kind == PATH_SMALL) {
+        hipLaunchKernelGGL(k_rk4_small, dim3(p.R), dim3(256), p.shm, s, (const double* const*)p.d,
+                           (const double* const*)(p.d + 2 * p.R), (double* const*)(p.d + 3 * p.R), (int)p.M, p.ldq,
+                           p.B, dt, steps, p.q_in_lds);
+        LB_CHECK_LAUNCH();
+        return LB_OK;
+    }
+    int rc = plan_init_state(p, s);
+    if (rc) return rc;
+    if (p.kind == PATH_GEMV) {
+        for (int64_t st = 0; st < steps; ++st)
+            for (int stage = 1; stage <= 4; ++stage) {
+                rc = plan_gemm(p, s, stage, dt);
+                if (rc) return rc;
+            }
+        return LB_OK;
+    }
+    const StageArgs sa = stage_args(p, dt);
+    const dim3 sgrid(lb_blocks(p.M * p.Bp, 256), p.R);
+    for (int64_t st = 0; st < steps; ++st)
+        for (int stage = 1; stage <= 4; ++stage) {
+            rc = plan_gemm(p, s, stage, dt);
+            if (rc) return rc;
+            hipLaunchKernelGGL(k_stage, sgrid, dim3(256), 0, s, sa, stage);
+            LB_CHECK_LAUNCH();
+        }
+    hipLaunchKernelGGL(k_unpack, dim3(lb_blocks(p.M * p.B, 256), p.R), dim3(256), 0, s,
+                       (double* const*)(p.d + 4 * p.R), p.M, p.B, p.Bp, (const double*)p.V, p.sstride);
+    LB_CHECK_LAUNCH();
+    return LB_OK;
+}
+
+// Average duration (ms) of the dominant stage kernel over `iters` launches,
+// measured with HIP events on the context stream. The states are packed
+// first; the kernel reads them but the timing loop does not advance them.
+static int plan_time(lb_ctx* c, const Plan& p, int iters, double* ms) {
+    hipStream_t s = c->stream;
+    int rc = plan_init_state(p, s);
+    if (rc) return rc;
+    rc = plan_gemm(p, s, 1, 0.0);  // warm-up launch
+    if (rc) return rc;
+    hipEvent_t e0, e1;
+    LB_HIP(hipEventCreate(&e0));
+    LB_HIP(hipEventCreate(&e1));
+    LB_HIP(hipEventRecord(e0, s));
+    for (int i = 0; i < iters; ++i) {
+        rc = plan_gemm(p, s, p.kind == PATH_GEMV ? 1 + (i & 1) : 1, 0.0);
+        if (rc) break;
+    }
+    LB_HIP(hipEventRecord(e1, s));
+    LB_HIP(hipEventSynchronize(e1));
+    float t = 0;
+    LB_HIP(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    *ms = (double)t / iters;
+    return LB_OK;
+}
+
+static int plan_for(lb_ctx* c, Plan& p, int R, int64_t M, const lb_prop_sys* sys, int64_t ldq, int B, int precision,
+                    const lb_tile* force_tile, bool allow_small) {
+    const lb_tile tile = force_tile ? *force_tile : choose_tile(c, M, bpad(B), precision);
+    int rc = plan_make(p, R, M, ldq, B, precision, tile, allow_small && force_tile == nullptr);
+    if (rc) return rc;
+    rc = lb_ws_reserve(c, p.bytes);
+    if (rc) return rc;
+    return plan_bind(c, p, (char*)c->ws, sys);
+}
+
+}  // namespace
+
+// R systems of size M, B states each.
+int lb_impl_propagate(lb_ctx* c, int R, int64_t M, const lb_prop_sys* sys, int64_t ldq, int B, double dt,
+                      int64_t steps, int precision, const lb_tile* force_tile) {
+    if (steps == 0) return LB_OK;
+    Plan p;
+    int rc = plan_for(c, p, R, M, sys, ldq, B, precision, force_tile, true);
+    if (rc) return rc;
+    return plan_launch(p, c->stream, dt, steps);
+}
+
+int lb_impl_time_stage(lb_ctx* c, int R, int64_t M, const lb_prop_sys* sys, int64_t ldq, int B, int precision,
+                       int iters, double* ms, const lb_tile* force_tile) {
+    Plan p;
+    int rc = plan_for(c, p, R, M, sys, ldq, B, precision, force_tile, false);
+    if (rc) return rc;
+    return plan_time(c, p, iters, ms);
+}
+
+struct lb_graph_entry {
+    Plan plan;
+    void* mem = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+void lb_graph_free(lb_graph_entry* g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->mem) (void)hipFree(g->mem);
+    delete g;
+}
+
+int lb_impl_propagate_graph(lb_ctx* c, int64_t M, const lb_prop_sys* sys, int64_t ldq, int B, double dt,
+                            int64_t steps, int precision) {
+    if (steps == 0) return LB_OK;
+    lb_graph_key key{M, ldq, B, precision, sys->Q, sys->Q32, sys->K, sys->V, dt, steps};
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        lb_graph_entry* g = new lb_graph_entry();
+        const lb_tile tile = choose_tile(c, M, bpad(B), precision);
+        int rc = plan_make(g->plan, 1, M, ldq, B, precision, tile, true);
+        if (rc) {
+            delete g;
+            return rc;
+        }
+        hipError_t e = hipMalloc(&g->mem, g->plan.bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete g;
+            return lb_fail(LB_ERR_OOM, "graph buffers (%zu bytes): %s", g->plan.bytes, hipGetErrorString(e));
+        }
+        rc = plan_bind(c, g->plan, (char*)g->mem, sys);
+        if (rc) {
+            lb_graph_free(g);
+            return rc;
+        }
+        hipStream_t cs;
+        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            lb_graph_free(g);
+            return lb_fail(LB_ERR_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+        }
+        hipGraph_t graph = nullptr;
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            rc = plan_launch(g->plan, cs, dt, steps);
+            hipError_t e2 = hipStreamEndCapture(cs, &graph);
+            if (!rc && e2 != hipSuccess) rc = lb_fail(LB_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+        } else {
+            rc = lb_fail(LB_ERR_DEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+        }
+        (void)hipStreamDestroy(cs);
+        if (!rc) {
+            e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) rc = lb_fail(LB_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+        if (graph) (void)hipGraphDestroy(graph);
+        if (rc) {
+            lb_graph_free(g);
+            return rc;
+        }
+        it = c->graphs.emplace(key, g).first;
+    }
+    LB_HIP(hipGraphLaunch(it->second->exec, c->stream));
+    return LB_OK;
+}
+
+// Tries tile shapes on the context stream and keeps the fastest stage kernel.
+int lb_impl_autotune(lb_ctx* c, int64_t M, const lb_prop_sys* sys, int64_t ldq, int B, int precision) {
+    const int Bp = bpad(B);
+    if (B == 1 && precision == LB_FP64) return LB_OK;  // GEMV path has no tile
+    const int CT = Bp / 16;
+    std::vector<int> rows_c = CT == 1 ? std::vector<int>{32, 64, 128} : std::vector<int>{16, 32, 64};
+    std::vector<int> waves_c = {1, 2, 4};
+    std::vector<int> target_c = {1024, 2048, 4096, 8192};
+    lb_tile best = lb_default_tile(M, Bp, precision);
+    double best_ms = 1e30;
+    for (int rows : rows_c)
+        for (int waves : waves_c)
+            for (int target : target_c) {
+                lb_tile t;
+                t.rows = rows;
+                t.waves = waves;
+                const int64_t rowwaves = (M + rows - 1) / rows;
+                int64_t nslab = (target + rowwaves - 1) / rowwaves;
+                const int64_t maxslab = (M + 255) / 256;
+                nslab = nslab < 1 ? 1 : (nslab > maxslab ? maxslab : nslab);
+                int64_t ks = (M + nslab - 1) / nslab;
+                t.kslab = (int)((ks + 15) / 16 * 16);
+                double ms = 0;
+                int rc = lb_impl_time_stage(c, 1, M, sys, ldq, B, precision, 3, &ms, &t);
+                if (rc) continue;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
+            }
+    c->tuned[std::make_tuple(M, Bp, precision)] = best;
+    if (const char* path = getenv("LB_TUNE_CACHE")) {
+        FILE* f = fopen(path, "a");
+        if (f) {
+            fprintf(f, "%lld %d %d %d %d %d\n", (long long)M, Bp, precision, best.rows, best.kslab, best.waves);
+            fclose(f);
+        }
+    }
     return LB_OK;
 }
 

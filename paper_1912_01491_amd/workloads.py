@@ -148,8 +148,9 @@ def wishart_kossakowski_device(N: int, seed: int, device="cuda", block: int = 40
     gen = torch.Generator(device=device)
     gen.manual_seed(int(seed))
     W = torch.randn(M, M, dtype=torch.complex64, device=device, generator=gen)
-    A = W @ W.mH
-    del W
+    Wh = W.mH.contiguous()  # materialized conjugate transpose as the right operand
+    A = W @ Wh
+    del W, Wh
     out = torch.empty(M, M, dtype=torch.complex128, device=device)
     for i0 in range(0, M, block):
         i1 = min(M, i0 + block)
