@@ -255,3 +255,45 @@ def test_propagate_invalid_args(lb, ctx):
         lb.lindblad_propagate(ctx, Q, K, V, float("nan"), 1)
     with pytest.raises(lb.LindbladError):
         lb.lindblad_propagate(ctx, Q, K, V, 1e-3, -1)
+
+
+@pytest.mark.parametrize("N,B", [(18, 1), (18, 16), (8, 2)])
+def test_propagate_graph_replays(lb, ctx, oracle, N, B):
+    """The captured graph, replayed three times with eager work and
+    synchronization between replays, equals the eager integration each time."""
+    print("[gpu] graph N=%d B=%d" % (N, B), flush=True)
+    H, gamma, Qo, Ko = _system(oracle, N, 60 + N)
+    psis = wl.random_pure_states(N, B, 7)
+    V0 = np.array([oracle.expand(np.outer(p, p.conj())).real for p in psis])
+    Q, K = lb.lindblad_prepare(ctx, dev(H), dev(gamma))
+    ref = dev(V0)
+    lb.lindblad_propagate(ctx, Q, K, ref, 1e-3, 15)
+    V = dev(V0)
+    for rep in range(3):
+        V.copy_(dev(V0))
+        junk = torch.randn(1000, device="cuda").sum()  # unrelated eager work
+        torch.cuda.synchronize()
+        lb.lindblad_propagate_graph(ctx, Q, K, V, 1e-3, 15)
+        torch.cuda.synchronize()
+        assert torch.equal(V, ref), "replay %d" % rep
+        del junk
+    Vo = oracle.rk4_dense(Qo, Ko, V0, 1e-3, 15)
+    assert rel(V.cpu().numpy(), Vo) < RTOL
+
+
+def test_autotune_then_propagate(lb, ctx, oracle):
+    N = 30
+    print("[gpu] autotune N=%d" % N, flush=True)
+    H, gamma = wl.random_lindbladian(N, 8)
+    M = N * N - 1
+    Q, K = lb.lindblad_prepare(ctx, dev(H), dev(gamma))
+    before = lb.lindblad_tile_info(ctx, M, 16)
+    lb.lindblad_autotune(ctx, Q, K, 16)
+    after = lb.lindblad_tile_info(ctx, M, 16)
+    assert after["tuned"] and not before["tuned"]
+    psis = wl.random_pure_states(N, 16, 2)
+    V0 = np.array([oracle.expand(np.outer(p, p.conj())).real for p in psis])
+    V = dev(V0)
+    lb.lindblad_propagate(ctx, Q, K, V, 1e-3, 5)
+    Qo, Ko = oracle.prepare_dense(H, gamma)
+    assert rel(V.cpu().numpy(), oracle.rk4_dense(Qo, Ko, V0, 1e-3, 5)) < RTOL
