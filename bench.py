@@ -57,7 +57,124 @@ def parse():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle RK4 steps in the CPU sample")
+    ap.add_argument("--serving", action="store_true", help="run the serving mix instead of the dense workload")
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--arrival", choices=["burst", "poisson"], default="burst")
+    ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrival rate (requests/s)")
+    ap.add_argument("--slots", type=int, default=6)
+    ap.add_argument("--max-batch", type=int, default=8)
+    ap.add_argument("--budget-gb", type=float, default=48.0)
+    ap.add_argument("--serve-steps", type=int, default=500)
     return ap.parse_args()
+
+
+def serving(args):
+    """Serving mix: N uniform in {16, 32, 64, 96, 128}; 70% dense random
+    Lindbladians (gamma from a device-resident pool of 4 realizations per N),
+    30% static dimers (sparse path); each request is a preparation plus
+    `serve-steps` RK4 steps of one pure state. The same request list runs
+    through the continuous-batching server and through the plain path (one
+    slot, no batching: first-in first-out, one request at a time)."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_1912_01491_amd as lb
+    from paper_1912_01491_amd import workloads as wl
+
+    dev = torch.device("cuda", 0)
+    ctx = lb.Context(0)
+    g = wl.rng(2024)
+    Ns = [16, 32, 64, 96, 128]
+    pool = {}
+    for N in Ns:
+        for r in range(4):
+            H = torch.from_numpy(wl.gue_hamiltonian(N, 500 + 10 * N + r)).to(dev)
+            if N <= 32:
+                gamma = torch.from_numpy(wl.wishart_kossakowski(N, 600 + 10 * N + r)).to(dev)
+            else:
+                gamma = wl.wishart_kossakowski_device(N, 600 + 10 * N + r, device=dev)
+            pool[(N, r)] = (H, gamma)
+        log("gamma pool for N=%d ready" % N)
+    dimers = {}
+    for N in Ns:
+        H, rates, Ls = wl.dimer_model(N)
+        dimers[N] = (tuple(torch.from_numpy(x).to(dev) for x in wl.to_csr(H)), rates,
+                     [tuple(torch.from_numpy(x).to(dev) for x in wl.to_csr(L)) for L in Ls])
+    reqs = []
+    for i in range(args.requests):
+        N = int(g.choice(Ns))
+        kind = "dense" if g.random() < 0.7 else "sparse"
+        psi = torch.from_numpy(wl.random_pure_state(N, 1000 + i)[None, :]).to(dev)
+        V0 = lb.lb_expand_pure(ctx, psi)
+        reqs.append((kind, N, int(g.integers(0, 4)), V0))
+    if args.arrival == "poisson":
+        if args.rate <= 0:
+            raise SystemExit("--arrival poisson needs --rate")
+        arrivals = np.cumsum(g.exponential(1.0 / args.rate, size=len(reqs)))
+    else:
+        arrivals = np.zeros(len(reqs))
+    torch.cuda.synchronize()
+    log("%d requests ready (%d dense)" % (len(reqs), sum(r[0] == "dense" for r in reqs)))
+
+    def run(slots, max_batch, label):
+        srv = lb.Server(0, budget_bytes=int(args.budget_gb * (1 << 30)), slots=slots, max_batch=max_batch,
+                        max_N=max(Ns))
+        tickets = [None] * len(reqs)
+
+        def feeder():
+            t0 = time.perf_counter()
+            for i, (kind, N, r, V0) in enumerate(reqs):
+                d = arrivals[i] - (time.perf_counter() - t0)
+                if d > 0:
+                    time.sleep(d)
+                if kind == "dense":
+                    H, gamma = pool[(N, r)]
+                    tickets[i] = srv.submit_dense(H, gamma, V0, args.dt, args.serve_steps)
+                else:
+                    Hc, rates, Lc = dimers[N]
+                    tickets[i] = srv.submit_sparse(N, Hc, rates, Lc, V0, args.dt, args.serve_steps)
+
+        t_start = time.perf_counter()
+        th = threading.Thread(target=feeder)
+        th.start()
+        th.join()
+        for i in range(len(reqs)):
+            srv.wait(tickets[i][0])
+        wall = time.perf_counter() - t_start
+        lat = np.array([srv.times(t)[2] - srv.times(t)[0] for t, _ in tickets])
+        st = srv.stats()
+        outs = [v for _, v in tickets]
+        srv.close()
+        log("%s: %d requests in %.2f s (%.2f solves/s), p50 %.3f s, p99 %.3f s, %s"
+            % (label, len(reqs), wall, len(reqs) / wall, np.percentile(lat, 50), np.percentile(lat, 99), st))
+        return wall, lat, st, outs
+
+    w_s, lat_s, st_s, out_s = run(args.slots, args.max_batch, "served")
+    w_p, lat_p, st_p, out_p = run(1, 1, "plain")
+    same = all(torch.equal(a, b) for a, b in zip(out_s, out_p))
+    out = {
+        "metric": "batched solves/s, p99 vs plain (serving mix)",
+        "value": len(reqs) / w_s,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "serving mix: %d requests, N uniform in %s, 70%% dense random / 30%% sparse dimer, "
+                               "prepare + %d RK4 steps dt=%g, one pure state each, %s arrivals"
+                               % (len(reqs), Ns, args.serve_steps, args.dt, args.arrival),
+                   "slots": args.slots, "max_batch": args.max_batch, "budget_gb": args.budget_gb,
+                   "rate": args.rate},
+        "served": {"solves_per_s": len(reqs) / w_s, "p50_s": float(np.percentile(lat_s, 50)),
+                   "p99_s": float(np.percentile(lat_s, 99)), "wall_s": w_s, "stats": st_s},
+        "plain": {"solves_per_s": len(reqs) / w_p, "p50_s": float(np.percentile(lat_p, 50)),
+                  "p99_s": float(np.percentile(lat_p, 99)), "wall_s": w_p, "stats": st_p},
+        "served_equals_plain_bitwise": bool(same),
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(M: int, B: int, steps: int):
@@ -91,6 +208,8 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d requested)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.serving:
+        return serving(args)
     import numpy as np
     import torch
 

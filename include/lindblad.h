@@ -232,6 +232,59 @@ int lindblad_time_stage(lb_ctx* ctx, int R, int64_t M, const double* const* Q, c
 int lindblad_tile_info(lb_ctx* ctx, int64_t M, int B, int precision, int* rows, int* kslab,
                        int* waves, int* tuned);
 
+/* ------------------------------------------------------------------ */
+/* Serving: continuous batching of prepare + propagate requests         */
+/* ------------------------------------------------------------------ */
+
+#define LB_REQ_DENSE 0
+#define LB_REQ_SPARSE 1
+#define LB_REQ_MAX_JUMPS 8
+
+/* One request: prepare the ODE system of a Lindbladian of dimension N and
+ * integrate B states for `steps` RK4 steps. All pointers are device memory
+ * owned by the caller and must stay valid until the request completes. */
+typedef struct lb_request {
+    int kind;                         /* LB_REQ_DENSE or LB_REQ_SPARSE */
+    int N;
+    const double* H;                  /* dense: N*N complex Hamiltonian */
+    const double* gamma;              /* dense: M*M complex Kossakowski matrix */
+    lb_csr_c128 Hs;                   /* sparse: Hamiltonian (CSR) */
+    int P;                            /* sparse: number of jump operators */
+    double rates[LB_REQ_MAX_JUMPS];   /* sparse: rates g_p */
+    lb_csr_c128 L[LB_REQ_MAX_JUMPS];  /* sparse: jump operators (CSR) */
+    const double* V0;                 /* B*M initial coherence vectors */
+    double* Vout;                     /* B*M results v(steps*dt) */
+    int B;
+    double dt;
+    int64_t steps;
+    int precision;                    /* dense: LB_FP64 or LB_FP32; sparse: LB_FP64 */
+} lb_request;
+
+typedef struct lb_server lb_server;
+
+/* Starts a server on `device` with `max_slots` worker slots (each a thread with
+ * its own stream and context, workspace pre-sized for N <= max_N), an HBM
+ * budget for the per-request buffers (Q/CSR, K), and batches of up to
+ * `max_batch` same-shape dense requests integrated together. Admission keeps
+ * submission order: the oldest waiting request starts as soon as a slot is
+ * free and its footprint fits in the budget. */
+int lindblad_server_create(int device, size_t hbm_budget_bytes, int max_slots, int max_batch, int max_N,
+                           lb_server** srv);
+/* Queues a request (thread-safe; copies the descriptor, not the data).
+ * LB_ERR_ADMISSION if its footprint can never fit in the budget. */
+int lindblad_server_submit(lb_server* srv, const lb_request* req, int64_t* ticket);
+/* *done = 1 once the request has finished (successfully or not). */
+int lindblad_server_poll(lb_server* srv, int64_t ticket, int* done);
+/* Blocks until the request has finished; returns its status. */
+int lindblad_server_wait(lb_server* srv, int64_t ticket);
+/* Submission, start and completion times of a request (seconds, steady clock). */
+int lindblad_server_times(lb_server* srv, int64_t ticket, double* t_submit, double* t_start, double* t_end);
+/* Completed requests, peak budget use (bytes), batches run, requests that ran in batches of > 1. */
+int lindblad_server_stats(lb_server* srv, int64_t* completed, size_t* peak_bytes, int64_t* batches,
+                          int64_t* batched_requests);
+/* Waits for every submitted request, then releases the server. */
+int lindblad_server_destroy(lb_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

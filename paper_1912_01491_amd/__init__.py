@@ -24,7 +24,7 @@ __all__ = [
     "lb_expand", "lb_expand_pure", "lb_reconstruct",
     "lindblad_prepare", "lindblad_q_to_f32", "lindblad_propagate", "lindblad_propagate_batched",
     "lindblad_propagate_graph", "lindblad_propagate_csr", "lindblad_prepare_sparse",
-    "lindblad_autotune", "lindblad_tile_info", "lindblad_time_stage",
+    "lindblad_autotune", "lindblad_tile_info", "lindblad_time_stage", "Server",
     "FP64", "FP32", "CHECK_HERMITIAN",
 ]
 
@@ -93,6 +93,13 @@ def load():
         "lindblad_autotune": [V, I64, V, V, I64, V, V, I, I],
         "lindblad_tile_info": [V, I64, I, I, V, V, V, V],
         "lindblad_time_stage": [V, I, I64, V, V, I64, V, V, I, I, I, V],
+        "lindblad_server_create": [I, ctypes.c_size_t, I, I, I, ctypes.POINTER(ctypes.c_void_p)],
+        "lindblad_server_submit": [V, V, V],
+        "lindblad_server_poll": [V, I64, V],
+        "lindblad_server_wait": [V, I64],
+        "lindblad_server_times": [V, I64, V, V, V],
+        "lindblad_server_stats": [V, V, V, V, V],
+        "lindblad_server_destroy": [V],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -413,3 +420,100 @@ def lindblad_time_stage(ctx: Context, Qs, Ks, Vs, iters: int = 10, precision: in
     _check(load().lindblad_time_stage(ctx.handle, R, M, qa, q32a, ldq, ka, va, Vs[0].shape[0], int(precision),
                                       int(iters), ctypes.byref(ms)))
     return ms.value
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+
+MAX_JUMPS = 8
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("N", ctypes.c_int), ("H", ctypes.c_void_p), ("gamma", ctypes.c_void_p),
+                ("Hs", _CSR), ("P", ctypes.c_int), ("rates", ctypes.c_double * MAX_JUMPS),
+                ("L", _CSR * MAX_JUMPS), ("V0", ctypes.c_void_p), ("Vout", ctypes.c_void_p), ("B", ctypes.c_int),
+                ("dt", ctypes.c_double), ("steps", ctypes.c_int64), ("precision", ctypes.c_int)]
+
+
+class Server:
+    """Continuous-batching server over the library (see lindblad_server_* in
+    include/lindblad.h). Submitted tensors are kept referenced until the
+    request's completion has been observed through wait()."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 16 << 30, slots: int = 4, max_batch: int = 8,
+                 max_N: int = 128):
+        h = ctypes.c_void_p()
+        _check(load().lindblad_server_create(int(device), int(budget_bytes), int(slots), int(max_batch),
+                                             int(max_N), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit_dense(self, H, gamma, V0, dt: float, steps: int, precision: int = FP64):
+        import torch
+        _need(H, torch.complex128, "H")
+        _need(gamma, torch.complex128, "gamma")
+        _need(V0, torch.float64, "V0")
+        Vout = torch.empty_like(V0)
+        r = _Request()
+        r.kind, r.N = 0, H.shape[0]
+        r.H, r.gamma = H.data_ptr(), gamma.data_ptr()
+        r.V0, r.Vout, r.B = V0.data_ptr(), Vout.data_ptr(), V0.shape[0]
+        r.dt, r.steps, r.precision = float(dt), int(steps), int(precision)
+        return self._submit(r, (H, gamma, V0, Vout), Vout)
+
+    def submit_sparse(self, N: int, H_csr, rates, L_csrs, V0, dt: float, steps: int):
+        import torch
+        _need(V0, torch.float64, "V0")
+        if len(L_csrs) > MAX_JUMPS:
+            raise ValueError("at most %d jump operators" % MAX_JUMPS)
+        Vout = torch.empty_like(V0)
+        r = _Request()
+        r.kind, r.N = 1, int(N)
+        r.Hs = _csr_struct(*H_csr)
+        r.P = len(L_csrs)
+        for p, (g, l) in enumerate(zip(rates, L_csrs)):
+            r.rates[p] = float(g)
+            r.L[p] = _csr_struct(*l)
+        r.V0, r.Vout, r.B = V0.data_ptr(), Vout.data_ptr(), V0.shape[0]
+        r.dt, r.steps, r.precision = float(dt), int(steps), FP64
+        return self._submit(r, (H_csr, L_csrs, V0, Vout), Vout)
+
+    def _submit(self, r, keep, Vout):
+        t = ctypes.c_int64()
+        _check(load().lindblad_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        self._keep[t.value] = keep
+        return t.value, Vout
+
+    def wait(self, ticket: int):
+        rc = load().lindblad_server_wait(self._h, int(ticket))
+        self._keep.pop(ticket, None)
+        _check(rc)
+
+    def done(self, ticket: int) -> bool:
+        d = ctypes.c_int()
+        _check(load().lindblad_server_poll(self._h, int(ticket), ctypes.byref(d)))
+        return bool(d.value)
+
+    def times(self, ticket: int):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(load().lindblad_server_times(self._h, int(ticket), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def stats(self):
+        c, b, n, m = ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_int64(), ctypes.c_int64()
+        _check(load().lindblad_server_stats(self._h, ctypes.byref(c), ctypes.byref(b), ctypes.byref(n),
+                                            ctypes.byref(m)))
+        return {"completed": c.value, "peak_bytes": b.value, "batches": n.value, "batched_requests": m.value}
+
+    def close(self):
+        if self._h:
+            load().lindblad_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
