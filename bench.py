@@ -57,7 +57,10 @@ def parse():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle RK4 steps in the CPU sample")
-    ap.add_argument("--serving", action="store_true", help="run the serving mix instead of the dense workload")
+    ap.add_argument("--config", choices=["c1", "c2", "c3", "c4", "c5"], default="c4",
+                    help="c4: the N=200 dense headline (default); c1: N=8 dense; c2: N=1000 sparse dimer; "
+                         "c3: N=100 dense, 64 states, FP64 vs FP32; c5: serving mix")
+    ap.add_argument("--serving", action="store_true", help="same as --config c5")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--arrival", choices=["burst", "poisson"], default="burst")
     ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrival rate (requests/s)")
@@ -202,14 +205,192 @@ def cpu_baseline(M: int, B: int, steps: int):
                       "same shape; assembly not included; %.2f s" % (steps, B, M, dt)}
 
 
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, out
+
+
+def config_c1(args):
+    """N=8 (M=63) dense random Lindbladian, H = (G+G^+)/2, Wishart gamma; one
+    random pure state (and a 16-state block), 1000 RK4 steps dt=1e-3. Latency
+    bound: Q (31.8 KB) stays in one workgroup's LDS for the whole run."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1912_01491_amd as lb
+    from paper_1912_01491_amd import workloads as wl
+
+    N, S, dt = 8, 1000, 1e-3
+    H, gamma = wl.random_lindbladian(N, 0, hamiltonian="plain")
+    ctx = lb.Context(0)
+    Hd, Gd = torch.from_numpy(H).cuda(), torch.from_numpy(gamma).cuda()
+    res = {}
+    for B in (1, 16):
+        psis = torch.from_numpy(wl.random_pure_states(N, B, 1)).cuda()
+        lb.lindblad_prepare(ctx, Hd, Gd)
+        t_prep = min(_timed(lambda: lb.lindblad_prepare(ctx, Hd, Gd))[0] for _ in range(20))
+        Q, K = lb.lindblad_prepare(ctx, Hd, Gd)
+        V0 = lb.lb_expand_pure(ctx, psis)
+        V = V0.clone()
+        lb.lindblad_propagate(ctx, Q, K, V, dt, S)
+        ts = []
+        for _ in range(5):
+            V = V0.clone()
+            ts.append(_timed(lambda: lb.lindblad_propagate(ctx, Q, K, V, dt, S))[0])
+        t_prop = min(ts)
+        Qo, Ko = oracle.prepare_dense(H, gamma)
+        Vo = oracle.rk4_dense(Qo, Ko, V0.cpu().numpy(), dt, S)
+        err = float(np.abs(V.cpu().numpy() - Vo).max() / np.abs(Vo).max())
+        t0 = time.perf_counter()
+        oracle.rk4_dense(Qo, Ko, V0.cpu().numpy(), dt, S)
+        t_cpu = time.perf_counter() - t0
+        res[B] = {"assembly_us": 1e6 * t_prep, "rk4_steps_per_s": S / t_prop, "run_ms": 1e3 * t_prop,
+                  "rel_err_vs_oracle": err, "oracle_rk4_steps_per_s": S / t_cpu}
+        log("C1 B=%d: assembly %.1f us, %.0f RK4 steps/s, err %.1e" % (B, 1e6 * t_prep, S / t_prop, err))
+    out = {"metric": "C1: N=8 dense assembly us and RK4 steps/s", "value": res[1]["rk4_steps_per_s"],
+           "unit": "RK4 steps/s (1 state, N=8)", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "dense random Lindbladian N=8 (M=63), H=(G+G^+)/2, Wishart gamma, "
+                                  "1000 RK4 steps dt=1e-3", "states": [1, 16]},
+           "results": {str(k): v for k, v in res.items()},
+           "cpu_baseline": {"value": res[1]["oracle_rk4_steps_per_s"], "unit": "RK4 steps/s (1 state, N=8)",
+                            "cores": oracle.num_threads(), "kind": "oracle", "sample": "the whole 1000-step run"}}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def config_c2(args):
+    """Bosonic dimer, N=1000 (M=999999), J=1, U=0.5, static, one jump b1^+ b2
+    at rate 0.1/(N-1): sparse preparation (CSR) and 1000 RK4 steps dt=1e-3
+    of one random pure state."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1912_01491_amd as lb
+    from paper_1912_01491_amd import workloads as wl
+
+    N, S, dt = 1000, 1000, 1e-3
+    M = N * N - 1
+    H, rates, Ls = wl.dimer_model(N)
+    ctx = lb.Context(0)
+    Hc = tuple(torch.from_numpy(x).cuda() for x in wl.to_csr(H))
+    Lc = [tuple(torch.from_numpy(x).cuda() for x in wl.to_csr(L)) for L in Ls]
+    lb.lindblad_prepare_sparse(ctx, N, Hc, rates, Lc)
+    t_prep, (rp, col, val, K) = min((_timed(lambda: lb.lindblad_prepare_sparse(ctx, N, Hc, rates, Lc))
+                                     for _ in range(3)), key=lambda x: x[0])
+    nnz = int(col.numel())
+    psi = torch.from_numpy(wl.random_pure_state(N, 0)[None, :]).cuda()
+    V0 = lb.lb_expand_pure(ctx, psi)
+    V = V0.clone()
+    lb.lindblad_propagate_csr(ctx, rp, col, val, K, V, dt, 10)
+    V = V0.clone()
+    t_prop, _ = _timed(lambda: lb.lindblad_propagate_csr(ctx, rp, col, val, K, V, dt, S))
+    # algorithmic bytes per stage: values + column indices + row pointers + the gathered x (8 B per entry,
+    # counted once per row entry) + K, v, acc, x in/out
+    bytes_stage = nnz * (8 + 8 + 8) + (M + 1) * 8 + 5 * M * 8
+    gbs = 4 * S * bytes_stage / t_prop / 1e9
+    rho = lb.lb_reconstruct(ctx, V, N)[0].cpu().numpy()
+    tr = abs(np.trace(rho) - 1)
+    # oracle parity on sampled rows
+    rows = np.array([0, 1, 777, 499499, 499500, 998999, 999000, M - 1])
+    Qo, Ko = oracle.prepare_factored(H, rates, Ls, rows)
+    rpc, colc, valc = rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy()
+    Qg = np.zeros((len(rows), M))
+    for t, r in enumerate(rows):
+        Qg[t, colc[rpc[r]:rpc[r + 1]]] = valc[rpc[r]:rpc[r + 1]]
+    err = float(np.abs(Qg - Qo).max() / np.abs(Qo).max())
+    log("C2: prepare %.1f ms (nnz %d = %.2f N^2), %d RK4 steps in %.3f s (%.1f us/step, %.0f GB/s)"
+        % (1e3 * t_prep, nnz, nnz / N**2, S, t_prop, 1e6 * t_prop / S, gbs))
+    out = {"metric": "C2: N=1000 sparse dimer prepare s and RK4 steps/s", "value": S / t_prop,
+           "unit": "RK4 steps/s (1 state, N=1000)", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "bosonic dimer N=1000 (M=999999), J=1, U=0.5, eps=0, L=b1^+ b2 at rate "
+                                  "0.1/999, 1000 RK4 steps dt=1e-3"},
+           "prepare_s": t_prep, "nnz": nnz, "us_per_step": 1e6 * t_prop / S,
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_csr_stage",
+                        "bytes_per_stage": bytes_stage},
+           "checks": {"trace_err": float(tr), "sampled_rows_rel_err_vs_oracle": err}}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def config_c3(args):
+    """N=100 (M=9999) dense random Lindbladian, GUE H, Wishart gamma; 64 random
+    pure states, 2000 RK4 steps dt=1e-3, FP64 (matrix cores) and FP32 matrix
+    core path; the FP32 error is stated per state against the FP64 result, and
+    both against the FP64 oracle over the first 20 steps."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1912_01491_amd as lb
+    from paper_1912_01491_amd import workloads as wl
+
+    N, B, S, dt = 100, 64, 2000, 1e-3
+    M = N * N - 1
+    H, gamma = wl.random_lindbladian(N, 0)
+    ctx = lb.Context(0)
+    Hd, Gd = torch.from_numpy(H).cuda(), torch.from_numpy(gamma).cuda()
+    lb.lindblad_prepare(ctx, Hd, Gd)
+    t_prep, (Q, K) = min((_timed(lambda: lb.lindblad_prepare(ctx, Hd, Gd)) for _ in range(3)), key=lambda x: x[0])
+    Q32 = lb.lindblad_q_to_f32(ctx, Q)
+    psis = torch.from_numpy(wl.random_pure_states(N, B, 0)).cuda()
+    V0 = lb.lb_expand_pure(ctx, psis)
+    res = {}
+    for name, prec in (("fp64", lb.FP64), ("fp32", lb.FP32)):
+        V = V0.clone()
+        lb.lindblad_propagate(ctx, Q, K, V, dt, 2, precision=prec, Q32=Q32)
+        V = V0.clone()
+        t, _ = _timed(lambda: lb.lindblad_propagate(ctx, Q, K, V, dt, S, precision=prec, Q32=Q32))
+        flops = 4 * S * 2.0 * M * M * B
+        res[name] = {"seconds": t, "rk4_steps_per_s": S / t, "tflops": flops / t / 1e12, "V": V}
+        log("C3 %s: %d steps in %.2f s (%.1f TFLOP/s)" % (name, S, t, flops / t / 1e12))
+    V64, V32 = res["fp64"].pop("V"), res["fp32"].pop("V")
+    per_state = ((V32 - V64).abs().amax(dim=1) / V64.abs().amax(dim=1)).cpu().numpy()
+    # oracle parity over 20 steps (full oracle assembly at N=100)
+    Qo, Ko = oracle.prepare_dense(H, gamma)
+    Vo = oracle.rk4_dense(Qo, Ko, V0.cpu().numpy(), dt, 20)
+    errs = {}
+    for name, prec in (("fp64", lb.FP64), ("fp32", lb.FP32)):
+        V = V0.clone()
+        lb.lindblad_propagate(ctx, Q, K, V, dt, 20, precision=prec, Q32=Q32)
+        errs[name] = float(np.abs(V.cpu().numpy() - Vo).max() / np.abs(Vo).max())
+    qerr = float(np.abs(Q.cpu().numpy()[:, :M] - Qo).max() / np.abs(Qo).max())
+    peak64, peak32 = 78.6, 157.3
+    out = {"metric": "C3: N=100 dense, 64 states x 2000 RK4 steps, FP64 vs FP32-MFMA", "value": res["fp64"]["rk4_steps_per_s"],
+           "unit": "RK4 steps/s (64-state block, N=100, FP64)", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "dense random Lindbladian N=100 (M=9999), GUE H, Wishart gamma, 64 pure states, "
+                                  "2000 RK4 steps dt=1e-3"},
+           "assembly_s": t_prep, "assembly_rel_err_vs_oracle": qerr,
+           "fp64": dict(res["fp64"], roofline={"bound": "mfma", "achieved": res["fp64"]["tflops"], "peak": peak64,
+                                                "unit": "TFLOP/s", "frac": res["fp64"]["tflops"] / peak64}),
+           "fp32": dict(res["fp32"], roofline={"bound": "mfma", "achieved": res["fp32"]["tflops"], "peak": peak32,
+                                                "unit": "TFLOP/s", "frac": res["fp32"]["tflops"] / peak32}),
+           "fp32_rel_err_vs_fp64_per_state_at_T": {"max": float(per_state.max()), "median": float(np.median(per_state)),
+                                                    "all": [float(x) for x in per_state]},
+           "rel_err_vs_oracle_20_steps": errs}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d requested)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
-    if args.serving:
+    if args.serving or args.config == "c5":
         return serving(args)
+    if args.config in ("c1", "c2", "c3"):
+        return {"c1": config_c1, "c2": config_c2, "c3": config_c3}[args.config](args)
     import numpy as np
     import torch
 

@@ -226,6 +226,12 @@ int lindblad_time_stage(lb_ctx* ctx, int R, int64_t M, const double* const* Q, c
                         int64_t ldq, const double* const* K, double* const* V, int B, int precision,
                         int iters, double* avg_ms);
 
+/* Sets the tile shape propagate uses for (M, B, precision) in this context:
+ * rows per wave (16..128, multiple of 16; combinations without a compiled
+ * kernel are rejected at propagate time), k-slab length (multiple of 16) and
+ * waves per workgroup (1..4). */
+int lindblad_set_tile(lb_ctx* ctx, int64_t M, int B, int precision, int rows, int kslab, int waves);
+
 /* Describes the tile shape propagate will use for (M, B, precision):
  * rows per wave, k-slab length, waves per workgroup, and whether it came
  * from the tuner (1) or the default table (0). Host only. */

@@ -24,7 +24,7 @@ __all__ = [
     "lb_expand", "lb_expand_pure", "lb_reconstruct",
     "lindblad_prepare", "lindblad_q_to_f32", "lindblad_propagate", "lindblad_propagate_batched",
     "lindblad_propagate_graph", "lindblad_propagate_csr", "lindblad_prepare_sparse",
-    "lindblad_autotune", "lindblad_tile_info", "lindblad_time_stage", "Server",
+    "lindblad_autotune", "lindblad_tile_info", "lindblad_set_tile", "lindblad_time_stage", "Server",
     "FP64", "FP32", "CHECK_HERMITIAN",
 ]
 
@@ -92,6 +92,7 @@ def load():
         "lindblad_propagate_graph": [V, I64, V, V, I64, V, V, I, D, I64, I],
         "lindblad_autotune": [V, I64, V, V, I64, V, V, I, I],
         "lindblad_tile_info": [V, I64, I, I, V, V, V, V],
+        "lindblad_set_tile": [V, I64, I, I, I, I, I],
         "lindblad_time_stage": [V, I, I64, V, V, I64, V, V, I, I, I, V],
         "lindblad_server_create": [I, ctypes.c_size_t, I, I, I, ctypes.POINTER(ctypes.c_void_p)],
         "lindblad_server_submit": [V, V, V],
@@ -396,6 +397,10 @@ def lindblad_autotune(ctx: Context, Q, K, B: int, precision: int = FP64, Q32=Non
     V = torch.zeros((B, M), dtype=torch.float64, device=K.device)
     _check(load().lindblad_autotune(ctx.handle, M, _ptr(Q) if Q is not None else None,
                                     _ptr(Q32) if Q32 is not None else None, ldq, _ptr(K), _ptr(V), B, precision))
+
+
+def lindblad_set_tile(ctx: Context, M: int, B: int, rows: int, kslab: int, waves: int, precision: int = FP64):
+    _check(load().lindblad_set_tile(ctx.handle, int(M), int(B), int(precision), int(rows), int(kslab), int(waves)))
 
 
 def lindblad_tile_info(ctx: Context, M: int, B: int, precision: int = FP64):

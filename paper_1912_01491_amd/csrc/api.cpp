@@ -374,11 +374,20 @@ int lindblad_time_stage(lb_ctx* c, int R, int64_t M, const double* const* Q, con
     return lb_impl_time_stage(c, R, M, sys.data(), ldq, B, precision, iters, avg_ms, nullptr);
 }
 
+int lindblad_set_tile(lb_ctx* c, int64_t M, int B, int precision, int rows, int kslab, int waves) {
+    if (!c) return lb_fail(LB_ERR_INVALID_ARG, "null context");
+    if (rows < 16 || rows % 16 || rows > 128 || kslab < 16 || kslab % 16 || waves < 1 || waves > 4)
+        return lb_fail(LB_ERR_INVALID_ARG, "tile rows=%d kslab=%d waves=%d out of range", rows, kslab, waves);
+    const int Bp = B <= 16 ? 16 : (B <= 32 ? 32 : 64);
+    c->tuned[std::make_tuple(M, Bp, precision)] = lb_tile{rows, kslab, waves};
+    return LB_OK;
+}
+
 int lindblad_tile_info(lb_ctx* c, int64_t M, int B, int precision, int* rows, int* kslab, int* waves, int* tuned) {
     if (!c) return lb_fail(LB_ERR_INVALID_ARG, "null context");
     const int Bp = B <= 16 ? 16 : (B <= 32 ? 32 : 64);
     auto it = c->tuned.find(std::make_tuple(M, Bp, precision));
-    lb_tile t = it != c->tuned.end() ? it->second : lb_default_tile(M, Bp, precision);
+    lb_tile t = it != c->tuned.end() ? it->second : lb_default_tile(M, Bp, precision, 1);
     if (rows) *rows = t.rows;
     if (kslab) *kslab = t.kslab;
     if (waves) *waves = t.waves;

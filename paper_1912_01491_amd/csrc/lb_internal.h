@@ -205,4 +205,4 @@ int lb_impl_propagate_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int
                           const double* val, const double* K, double* V, int B, double dt,
                           int64_t steps);
 int lb_impl_q_to_f32(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, float* Q32);
-lb_tile lb_default_tile(int64_t M, int Bp, int precision);
+lb_tile lb_default_tile(int64_t M, int Bp, int precision, int R);

@@ -37,6 +37,28 @@ namespace {
 __host__ __device__ __forceinline__ int64_t ilv2(int64_t k, int b, int Bp) { return (k >> 1) * (2 * Bp) + 2 * b + (k & 1); }
 __host__ __device__ __forceinline__ int64_t ilv4(int64_t k, int b, int Bp) { return (k >> 2) * (4 * Bp) + 4 * b + (k & 3); }
 
+// Work decomposition of a stage GEMM launch: gx row blocks x nslab k-slabs x R
+// systems, launched as a 1-D grid. Workgroups are handed to the 8 XCDs round
+// robin by workgroup id, so workgroup b runs on XCD b % 8; it is given work item
+// w = (b % 8) * per_xcd + b / 8, i.e. each XCD walks one contiguous range of
+// the slab-major work list and keeps the few X slabs it is reading resident in
+// its own L2.
+struct GemmGrid {
+    int gx, nslab, R;
+    int64_t per_xcd;
+};
+
+__device__ __forceinline__ bool gemm_work(const GemmGrid& g, int& x, int& slab, int& r) {
+    const int64_t b = blockIdx.x;
+    const int64_t w = (b & 7) * g.per_xcd + (b >> 3);
+    if (w >= (int64_t)g.gx * g.nslab * g.R) return false;
+    x = (int)(w % g.gx);
+    const int64_t cmb = w / g.gx;
+    slab = (int)(cmb % g.nslab);
+    r = (int)(cmb / g.nslab);
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // Matrix-core stage GEMM, FP64: Part[slab] = Q[:, slab] X[slab, :]
 // ---------------------------------------------------------------------------
@@ -47,18 +69,19 @@ __host__ __device__ __forceinline__ int64_t ilv4(int64_t k, int b, int Bp) { ret
 template <int RT, int CT, bool ALIGNED>
 __global__ __launch_bounds__(256) void k_gemm64(const double* const* Qs, int64_t M, int64_t Mp, int64_t ldq,
                                                 const double* Xall, int64_t xstride, double* Pall,
-                                                int64_t pstride, int kslab) {
+                                                int64_t pstride, int kslab, GemmGrid gg) {
     constexpr int Bp = 16 * CT;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int r = blockIdx.z;
+    int bx, slab, r;
+    if (!gemm_work(gg, bx, slab, r)) return;
     const double* Q = Qs[r];
     const double* X = Xall + r * xstride;
-    double* Part = Pall + r * pstride + (int64_t)blockIdx.y * Mp * Bp;
-    const int64_t row0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * (16 * RT);
+    double* Part = Pall + r * pstride + (int64_t)slab * Mp * Bp;
+    const int64_t row0 = ((int64_t)bx * (blockDim.x >> 6) + wave) * (16 * RT);
     if (row0 >= M) return;
-    const int64_t k0 = (int64_t)blockIdx.y * kslab;
+    const int64_t k0 = (int64_t)slab * kslab;
     const int64_t k1 = k0 + kslab < M ? k0 + kslab : M;
 
     const double* qrow[RT];
@@ -142,18 +165,19 @@ __global__ __launch_bounds__(256) void k_gemm64(const double* const* Qs, int64_t
 template <int RT, int CT, bool ALIGNED>
 __global__ __launch_bounds__(256) void k_gemm32(const float* const* Qs, int64_t M, int64_t Mp, int64_t ldq,
                                                 const float* Xall, int64_t xstride, double* Pall,
-                                                int64_t pstride, int kslab) {
+                                                int64_t pstride, int kslab, GemmGrid gg) {
     constexpr int Bp = 16 * CT;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int r = blockIdx.z;
+    int bx, slab, r;
+    if (!gemm_work(gg, bx, slab, r)) return;
     const float* Q = Qs[r];
     const float* X = Xall + r * xstride;
-    double* Part = Pall + r * pstride + (int64_t)blockIdx.y * Mp * Bp;
-    const int64_t row0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * (16 * RT);
+    double* Part = Pall + r * pstride + (int64_t)slab * Mp * Bp;
+    const int64_t row0 = ((int64_t)bx * (blockDim.x >> 6) + wave) * (16 * RT);
     if (row0 >= M) return;
-    const int64_t k0 = (int64_t)blockIdx.y * kslab;
+    const int64_t k0 = (int64_t)slab * kslab;
     const int64_t k1 = k0 + kslab < M ? k0 + kslab : M;
 
     const float* qrow[RT];
@@ -169,7 +193,41 @@ __global__ __launch_bounds__(256) void k_gemm32(const float* const* Qs, int64_t 
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[t][c] = lb_float4{0, 0, 0, 0};
 
+    // 32 columns (128 bytes of each row) per iteration, as two 16-byte loads per
+    // lane: columns kc + 4(l/16) + {0..3} and kc + 16 + 4(l/16) + {0..3}
     int64_t kc = k0;
+    for (; kc + 32 <= k1; kc += 32) {
+        float4 qa[RT], qb[RT], xa[CT], xb[CT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            const float* p = qrow[t] + kc + 4 * lk;
+            if (ALIGNED) {
+                qa[t] = *reinterpret_cast<const float4*>(p);
+                qb[t] = *reinterpret_cast<const float4*>(p + 16);
+            } else {
+                qa[t] = make_float4(p[0], p[1], p[2], p[3]);
+                qb[t] = make_float4(p[16], p[17], p[18], p[19]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            xa[c] = *reinterpret_cast<const float4*>(X + ((kc >> 2) + lk) * (4 * Bp) + 4 * (16 * c + lr));
+            xb[c] = *reinterpret_cast<const float4*>(X + (((kc + 16) >> 2) + lk) * (4 * Bp) + 4 * (16 * c + lr));
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t].x, xa[c].x, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t].y, xa[c].y, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t].z, xa[c].z, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t].w, xa[c].w, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qb[t].x, xb[c].x, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qb[t].y, xb[c].y, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qb[t].z, xb[c].z, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qb[t].w, xb[c].w, acc[t][c], 0, 0, 0);
+            }
+    }
     for (; kc + 16 <= k1; kc += 16) {
         float4 qa[RT], xa[CT];
 #pragma unroll
@@ -503,9 +561,9 @@ __global__ void k_to_f32(const double* Q, float* Q32, int64_t n) {
 // ---------------------------------------------------------------------------
 
 typedef void (*gemm64_fn)(const double* const*, int64_t, int64_t, int64_t, const double*, int64_t, double*,
-                          int64_t, int);
+                          int64_t, int, GemmGrid);
 typedef void (*gemm32_fn)(const float* const*, int64_t, int64_t, int64_t, const float*, int64_t, double*,
-                          int64_t, int);
+                          int64_t, int, GemmGrid);
 
 template <bool AL>
 gemm64_fn pick64(int RT, int CT) {
@@ -549,15 +607,23 @@ int bpad(int B) { return B <= 16 ? 16 : (B <= 32 ? 32 : 64); }
 
 }  // namespace
 
-lb_tile lb_default_tile(int64_t M, int Bp, int precision) {
+// Default tile from sweeps on MI355X: 64 rows per wave for 16-state blocks
+// (32 for 32/64 states), and k-slabs sized so that one system alone gives a
+// launch of about 8192 waves (4096 for FP32), with slabs of at least 384 columns for 64-state
+// blocks (compute-bound) and 256 otherwise. The slab length fixes the
+// summation order, so it depends on (M, Bp) only and never on how many systems
+// share a launch: a system's result is bit-identical alone and batched.
+lb_tile lb_default_tile(int64_t M, int Bp, int precision, int R) {
     lb_tile t;
     const int CT = Bp / 16;
     t.rows = CT == 1 ? 64 : 32;
-    t.waves = 4;
-    (void)precision;
+    t.waves = CT == 1 ? 2 : 1;
+    (void)R;
     const int64_t rowwaves = (M + t.rows - 1) / t.rows;
-    int64_t nslab = (4096 + rowwaves - 1) / rowwaves;
-    const int64_t maxslab = (M + 255) / 256;
+    const int64_t target = precision == LB_FP32 ? 4096 : 8192;
+    int64_t nslab = (target + rowwaves - 1) / rowwaves;
+    const int64_t minslab = CT == 4 ? 384 : 256;
+    const int64_t maxslab = std::max<int64_t>(1, M / minslab);
     if (nslab > maxslab) nslab = maxslab;
     if (nslab < 1) nslab = 1;
     int64_t ks = (M + nslab - 1) / nslab;
@@ -581,11 +647,11 @@ static void load_tune_cache(lb_ctx* c) {
     fclose(f);
 }
 
-static lb_tile choose_tile(lb_ctx* c, int64_t M, int Bp, int precision) {
+static lb_tile choose_tile(lb_ctx* c, int64_t M, int Bp, int precision, int R) {
     load_tune_cache(c);
     auto it = c->tuned.find(std::make_tuple(M, Bp, precision));
     if (it != c->tuned.end()) return it->second;
-    return lb_default_tile(M, Bp, precision);
+    return lb_default_tile(M, Bp, precision, R);
 }
 
 int lb_impl_q_to_f32(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, float* Q32) {
@@ -738,16 +804,22 @@ static int plan_gemm(const Plan& p, hipStream_t s, int stage, double dt) {
     }
     const int RT = p.tile.rows / 16, CT = p.Bp / 16;
     const int64_t rowwaves = (p.M + p.tile.rows - 1) / p.tile.rows;
-    const dim3 ggrid((unsigned)((rowwaves + p.tile.waves - 1) / p.tile.waves), (unsigned)p.nslab, (unsigned)p.R);
+    GemmGrid gg;
+    gg.gx = (int)((rowwaves + p.tile.waves - 1) / p.tile.waves);
+    gg.nslab = p.nslab;
+    gg.R = p.R;
+    const int64_t total = (int64_t)gg.gx * gg.nslab * gg.R;
+    gg.per_xcd = (total + 7) / 8;
+    const dim3 ggrid((unsigned)(8 * gg.per_xcd));
     const dim3 gblock(64 * p.tile.waves);
     if (p.precision == LB_FP64) {
         gemm64_fn fn = p.aligned ? pick64<true>(RT, CT) : pick64<false>(RT, CT);
         hipLaunchKernelGGL(fn, ggrid, gblock, 0, s, (const double* const*)p.d, p.M, p.Mp, p.ldq, (const double*)p.X,
-                           p.sstride, p.Part, p.pstride, p.tile.kslab);
+                           p.sstride, p.Part, p.pstride, p.tile.kslab, gg);
     } else {
         gemm32_fn fn = p.aligned ? pick32<true>(RT, CT) : pick32<false>(RT, CT);
         hipLaunchKernelGGL(fn, ggrid, gblock, 0, s, (const float* const*)(p.d + p.R), p.M, p.Mp, p.ldq,
-                           (const float*)p.X32, p.s32stride, p.Part, p.pstride, p.tile.kslab);
+                           (const float*)p.X32, p.s32stride, p.Part, p.pstride, p.tile.kslab, gg);
     }
     LB_CHECK_LAUNCH();
     return LB_OK;
@@ -833,7 +905,7 @@ static int plan_time(lb_ctx* c, const Plan& p, int iters, double* ms) {
 
 static int plan_for(lb_ctx* c, Plan& p, int R, int64_t M, const lb_prop_sys* sys, int64_t ldq, int B, int precision,
                     const lb_tile* force_tile, bool allow_small) {
-    const lb_tile tile = force_tile ? *force_tile : choose_tile(c, M, bpad(B), precision);
+    const lb_tile tile = force_tile ? *force_tile : choose_tile(c, M, bpad(B), precision, R);
     int rc = plan_make(p, R, M, ldq, B, precision, tile, allow_small && force_tile == nullptr);
     if (rc) return rc;
     rc = lb_ws_reserve(c, p.bytes);
@@ -881,7 +953,7 @@ int lb_impl_propagate_graph(lb_ctx* c, int64_t M, const lb_prop_sys* sys, int64_
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
         lb_graph_entry* g = new lb_graph_entry();
-        const lb_tile tile = choose_tile(c, M, bpad(B), precision);
+        const lb_tile tile = choose_tile(c, M, bpad(B), precision, 1);
         int rc = plan_make(g->plan, 1, M, ldq, B, precision, tile, true);
         if (rc) {
             delete g;
@@ -937,7 +1009,7 @@ int lb_impl_autotune(lb_ctx* c, int64_t M, const lb_prop_sys* sys, int64_t ldq, 
     std::vector<int> rows_c = CT == 1 ? std::vector<int>{32, 64, 128} : std::vector<int>{16, 32, 64};
     std::vector<int> waves_c = {1, 2, 4};
     std::vector<int> target_c = {1024, 2048, 4096, 8192};
-    lb_tile best = lb_default_tile(M, Bp, precision);
+    lb_tile best = lb_default_tile(M, Bp, precision, 1);
     double best_ms = 1e30;
     for (int rows : rows_c)
         for (int waves : waves_c)
