@@ -26,6 +26,7 @@ the CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -40,6 +41,30 @@ HBM_PEAK_GBS = 8000.0
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def gemm64_digest():
+    """Digest of the FP64 stage-GEMM source (its work mapping and kernel body)."""
+    src = open(os.path.join(ROOT, "paper_1912_01491_amd", "csrc", "propagate.hip")).read()
+    a = src.index("struct GemmGrid")
+    b = src.index("template <int RT, int CT, bool ALIGNED>", src.index("void k_gemm64"))
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def measured_traffic(M, R, B, tile):
+    """HBM bytes per launch of k_gemm64 from the FETCH_SIZE / WRITE_SIZE counter
+    runs summarised under profiles/, scaled by the copy-kernel factors recorded
+    there; None unless kernel source, shape and tile are those of the counter run."""
+    path = os.path.join(ROOT, "profiles", "k_gemm64_traffic_N200_dense.md")
+    try:
+        line = next(x for x in open(path) if x.startswith("traffic-record:"))
+    except (OSError, StopIteration):
+        return None
+    rec = json.loads(line.split(":", 1)[1])
+    same_tile = all(rec["tile"][k] == tile[k] for k in ("rows", "kslab", "waves"))
+    if (rec["M"], rec["systems"], rec["states"]) != (M, R, B) or not same_tile or rec["source_digest"] != gemm64_digest():
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
 
 
 def parse():
@@ -61,6 +86,8 @@ def parse():
                     help="c4: the N=200 dense headline (default); c1: N=8 dense; c2: N=1000 sparse dimer; "
                          "c3: N=100 dense, 64 states, FP64 vs FP32; c5: serving mix")
     ap.add_argument("--serving", action="store_true", help="same as --config c5")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="for rocprofv3 --pmc runs: one plain 4 GiB copy, then the C4 stage GEMM on stand-in Q")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--arrival", choices=["burst", "poisson"], default="burst")
     ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrival rate (requests/s)")
@@ -291,10 +318,11 @@ def config_c2(args):
     lb.lindblad_propagate_csr(ctx, rp, col, val, K, V, dt, 10)
     V = V0.clone()
     t_prop, _ = _timed(lambda: lb.lindblad_propagate_csr(ctx, rp, col, val, K, V, dt, S))
-    # algorithmic bytes per stage: values + column indices + row pointers + the gathered x (8 B per entry,
-    # counted once per row entry) + K, v, acc, x in/out
-    bytes_stage = nnz * (8 + 8 + 8) + (M + 1) * 8 + 5 * M * 8
-    gbs = 4 * S * bytes_stage / t_prop / 1e9
+    # algorithmic bytes per RK4 step: four passes over the stored entries (8 B value + 4 B column index,
+    # the kernel's format) and the row pointers, plus the M-vectors touched once each: per step x in (4),
+    # K (4), v read (4) and written (1), accumulator read (3) and written (3), stage output (4)
+    bytes_step = 4 * (nnz * (8 + 4) + (M + 1) * 8) + 23 * M * 8
+    gbs = S * bytes_step / t_prop / 1e9
     rho = lb.lb_reconstruct(ctx, V, N)[0].cpu().numpy()
     tr = abs(np.trace(rho) - 1)
     # oracle parity on sampled rows
@@ -314,8 +342,8 @@ def config_c2(args):
                                   "0.1/999, 1000 RK4 steps dt=1e-3"},
            "prepare_s": t_prep, "nnz": nnz, "us_per_step": 1e6 * t_prop / S,
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_csr_stage",
-                        "bytes_per_stage": bytes_stage},
+                        "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_csr_short+k_csr_long",
+                        "bytes_per_step": bytes_step},
            "checks": {"trace_err": float(tr), "sampled_rows_rel_err_vs_oracle": err}}
     ctx.close()
     print(json.dumps(out), flush=True)
@@ -381,12 +409,43 @@ def config_c3(args):
     print(json.dumps(out), flush=True)
 
 
+def pmc_probe(args):
+    """Kernels for the HBM traffic counters: a plain copy of 4 GiB (reads and
+    writes 4 GiB: the scale for FETCH_SIZE / WRITE_SIZE), then the stage GEMM at
+    the C4 shape (8 systems, M = 39999, 16 states) on stand-in Q matrices
+    (traffic does not depend on the values)."""
+    import torch
+
+    import paper_1912_01491_amd as lb
+
+    n = 1 << 29  # doubles: 4 GiB
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    N, R, B = args.N, args.realizations, args.states
+    M = N * N - 1
+    ldq = lb.default_ldq(M)
+    ctx = lb.Context(0)
+    Qs = [torch.full((M, ldq), 1e-3, dtype=torch.float64, device="cuda") for _ in range(R)]
+    Ks = [torch.zeros(M, dtype=torch.float64, device="cuda") for _ in range(R)]
+    Vs = [torch.ones(B, M, dtype=torch.float64, device="cuda") for _ in range(R)]
+    ms = lb.lindblad_time_stage(ctx, Qs, Ks, Vs, iters=2)
+    log("copy 4 GiB done; stage GEMM %.3f ms per launch, %d systems, %d bytes of Q per launch"
+        % (ms, R, R * M * M * 8))
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d requested)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.pmc_probe:
+        return pmc_probe(args)
     if args.serving or args.config == "c5":
         return serving(args)
     if args.config in ("c1", "c2", "c3"):
@@ -513,7 +572,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(M, R, B, tile) if prec == lb.FP64 else None,
             "kernel": "k_gemm64" if prec == lb.FP64 else "k_gemm32",
             "avg_ms": avg_ms,
             "bytes_per_launch": alg_bytes,

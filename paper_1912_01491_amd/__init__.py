@@ -31,6 +31,7 @@ __all__ = [
 FP64 = 0
 FP32 = 1
 CHECK_HERMITIAN = 1
+MAX_N = 1024
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "_build", "liblindblad.so")
@@ -68,8 +69,19 @@ def load():
         raise LibraryMissing("%s is not built; run `python -m paper_1912_01491_amd.build` "
                              "or __graft_entry__.build()" % _LIB_PATH)
     lib = ctypes.CDLL(_LIB_PATH)
+    for name, args in signatures().items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_char_p if name == "lb_last_error" else ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def signatures():
+    """ctypes argument types of every C entry point."""
     V, I, I64, D, U = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_uint
-    sig = {
+    return {
+        "lb_last_error": [],
         "lb_create": [ctypes.POINTER(ctypes.c_void_p), I, V],
         "lb_destroy": [V],
         "lb_set_stream": [V, V],
@@ -102,14 +114,6 @@ def load():
         "lindblad_server_stats": [V, V, V, V, V],
         "lindblad_server_destroy": [V],
     }
-    for name, args in sig.items():
-        f = getattr(lib, name)
-        f.argtypes = args
-        f.restype = I
-    lib.lb_last_error.argtypes = []
-    lib.lb_last_error.restype = ctypes.c_char_p
-    _lib = lib
-    return lib
 
 
 def _check(rc: int):

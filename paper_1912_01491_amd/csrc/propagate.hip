@@ -511,12 +511,75 @@ __global__ __launch_bounds__(256) void k_rk4_small(const double* const* Qs, cons
 }
 
 // ---------------------------------------------------------------------------
-// CSR: one thread per row, stage combine fused (B states, user layout).
+// CSR: rows with at most kLongRow entries are handled by groups of kShortLanes
+// lanes (coalesced reads of the row, shuffle reduction); longer rows (the
+// diagonal-generator rows and the rows they couple to, ~N entries) by one
+// wavefront each. The stage combination is fused: the lane that ends up with a
+// row's sum updates that row. Column indices are read as 32-bit integers
+// converted once per call.
 // ---------------------------------------------------------------------------
-__global__ void k_csr_stage(int64_t M, const int64_t* rowptr, const int64_t* col, const double* val,
-                            const double* K, double* V, double* W, int B, int stage, double h) {
-    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= M) return;
+constexpr int kShortLanes = 8;
+constexpr int kLongRow = 64;
+
+__device__ __forceinline__ void rk4_update(int stage, double h, double k, int64_t i, double* V, double* Acc,
+                                           double* Xout) {
+    double x;
+    if (stage == 1) {
+        Acc[i] = k;
+        x = V[i] + 0.5 * h * k;
+    } else if (stage == 2) {
+        Acc[i] = Acc[i] + 2.0 * k;
+        x = V[i] + 0.5 * h * k;
+    } else if (stage == 3) {
+        Acc[i] = Acc[i] + 2.0 * k;
+        x = V[i] + h * k;
+    } else {
+        x = V[i] + h / 6.0 * (Acc[i] + k);
+        V[i] = x;
+    }
+    Xout[i] = x;
+}
+
+__global__ void k_csr_prep(int64_t M, int64_t nnz, const int64_t* rowptr, const int64_t* col, int* col32,
+                           int* longrows, int* nlong) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nnz) col32[t] = (int)col[t];
+    if (t < M && rowptr[t + 1] - rowptr[t] > kLongRow) longrows[atomicAdd(nlong, 1)] = (int)t;
+}
+
+__global__ __launch_bounds__(256) void k_csr_short(int64_t M, const int64_t* rowptr, const int* col,
+                                                   const double* val, const double* K, double* V, double* W,
+                                                   int B, int stage, double h) {
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kShortLanes;
+    const int sub = threadIdx.x % kShortLanes;
+    const int64_t n = M * B;
+    double* Acc = W;
+    const double* Xin = (stage & 1) ? W + n : W + 2 * n;
+    double* Xout = (stage & 1) ? W + 2 * n : W + n;
+    int64_t e0 = 0, e1 = 0;
+    if (row < M) {
+        e0 = rowptr[row];
+        e1 = rowptr[row + 1];
+    }
+    const bool mine = row < M && e1 - e0 <= kLongRow;
+    for (int b = 0; b < B; ++b) {
+        const double* x = Xin + (int64_t)b * M;
+        double s = 0.0;
+        if (mine)
+            for (int64_t e = e0 + sub; e < e1; e += kShortLanes) s = fma(val[e], x[col[e]], s);
+        for (int o = kShortLanes / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kShortLanes);
+        if (mine && sub == 0) rk4_update(stage, h, s + K[row], (int64_t)b * M + row, V, Acc, Xout);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_csr_long(int64_t M, const int64_t* rowptr, const int* col,
+                                                  const double* val, const double* K, double* V, double* W,
+                                                  int B, int stage, double h, const int* longrows,
+                                                  const int* nlong) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (wid >= *nlong) return;
+    const int64_t row = longrows[wid];
     const int64_t n = M * B;
     double* Acc = W;
     const double* Xin = (stage & 1) ? W + n : W + 2 * n;
@@ -525,24 +588,9 @@ __global__ void k_csr_stage(int64_t M, const int64_t* rowptr, const int64_t* col
     for (int b = 0; b < B; ++b) {
         const double* x = Xin + (int64_t)b * M;
         double s = 0.0;
-        for (int64_t e = e0; e < e1; ++e) s = fma(val[e], x[col[e]], s);
-        const double k = s + K[row];
-        const int64_t i = (int64_t)b * M + row;
-        double xn;
-        if (stage == 1) {
-            Acc[i] = k;
-            xn = V[i] + 0.5 * h * k;
-        } else if (stage == 2) {
-            Acc[i] = Acc[i] + 2.0 * k;
-            xn = V[i] + 0.5 * h * k;
-        } else if (stage == 3) {
-            Acc[i] = Acc[i] + 2.0 * k;
-            xn = V[i] + h * k;
-        } else {
-            xn = V[i] + h / 6.0 * (Acc[i] + k);
-            V[i] = xn;
-        }
-        Xout[i] = xn;
+        for (int64_t e = e0 + lane; e < e1; e += 64) s = fma(val[e], x[col[e]], s);
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (lane == 0) rk4_update(stage, h, s + K[row], (int64_t)b * M + row, V, Acc, Xout);
     }
 }
 
@@ -1046,17 +1094,51 @@ int lb_impl_propagate_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int
                           const double* K, double* V, int B, double dt, int64_t steps) {
     hipStream_t s = c->stream;
     if (steps == 0) return LB_OK;
+    // number of stored entries, for the index conversion
+    int64_t nnz = 0;
+    LB_HIP(hipMemcpyAsync(&nnz, rowptr + M, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LB_HIP(hipStreamSynchronize(s));
+    if (nnz < 0 || nnz >= ((int64_t)1 << 31)) return lb_fail(LB_ERR_UNSUPPORTED, "nnz=%lld out of range", (long long)nnz);
     const int64_t n = M * B;
-    int rc = lb_ws_reserve(c, sizeof(double) * 3 * n);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = lb_align(off + bytes, 256);
+        return o;
+    };
+    const size_t o_w = take(sizeof(double) * 3 * n);
+    const size_t o_col = take(sizeof(int) * (size_t)(nnz > 0 ? nnz : 1));
+    const size_t o_long = take(sizeof(int) * (size_t)M);
+    const size_t o_nl = take(sizeof(int));
+    int rc = lb_ws_reserve(c, off);
     if (rc) return rc;
-    double* W = (double*)c->ws;
+    char* ws = (char*)c->ws;
+    double* W = (double*)(ws + o_w);
+    int* col32 = (int*)(ws + o_col);
+    int* longrows = (int*)(ws + o_long);
+    int* nlong = (int*)(ws + o_nl);
+    LB_HIP(hipMemsetAsync(nlong, 0, sizeof(int), s));
+    const int64_t nt = nnz > M ? nnz : M;
+    hipLaunchKernelGGL(k_csr_prep, dim3(lb_blocks(nt, 256)), dim3(256), 0, s, M, nnz, rowptr, col, col32, longrows,
+                       nlong);
+    LB_CHECK_LAUNCH();
+    int hl = 0;
+    LB_HIP(hipMemcpyAsync(&hl, nlong, sizeof(int), hipMemcpyDeviceToHost, s));
     hipLaunchKernelGGL(k_copy, dim3(lb_blocks(n, 256)), dim3(256), 0, s, (const double*)V, W + n, n);
     LB_CHECK_LAUNCH();
+    LB_HIP(hipStreamSynchronize(s));
+    const unsigned gs = lb_blocks(M * kShortLanes, 256);
+    const unsigned gl = lb_blocks((int64_t)hl * 64, 256);
     for (int64_t st = 0; st < steps; ++st)
         for (int stage = 1; stage <= 4; ++stage) {
-            hipLaunchKernelGGL(k_csr_stage, dim3(lb_blocks(M, 256)), dim3(256), 0, s, M, rowptr, col, val, K, V, W,
-                               B, stage, dt);
+            hipLaunchKernelGGL(k_csr_short, dim3(gs), dim3(256), 0, s, M, rowptr, (const int*)col32, val, K, V, W, B,
+                               stage, dt);
             LB_CHECK_LAUNCH();
+            if (hl > 0) {
+                hipLaunchKernelGGL(k_csr_long, dim3(gl), dim3(256), 0, s, M, rowptr, (const int*)col32, val, K, V, W,
+                                   B, stage, dt, (const int*)longrows, (const int*)nlong);
+                LB_CHECK_LAUNCH();
+            }
         }
     return LB_OK;
 }

@@ -1,0 +1,88 @@
+"""The C-ABI library without a GPU: it loads, exports every entry point the
+header declares, and its host-only functions (the basis index generator of
+Sec. 2, argument checking) behave as documented. No device work runs here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1912_01491_amd as lb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lindblad.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:int|const\s+char\s*\*|void)\s+\**\s*((?:lb|lindblad)_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("lindblad_prepare", "lindblad_propagate", "lindblad_prepare_sparse_count",
+                 "lindblad_prepare_sparse_fill", "lindblad_propagate_csr", "lindblad_propagate_batched",
+                 "lindblad_server_create", "lb_fd_enumerate", "lb_basis_index"):
+        assert must in names
+    assert len(names) >= 30
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(lb.library_path())
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    sigs = lb.signatures()
+    missing = [n for n in declared_functions() if n not in sigs]
+    assert not missing, missing
+
+
+def test_version():
+    assert lb.load().lb_version() >= 100
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 7, 16, 45])
+def test_basis_index_matches_oracle(oracle, N):
+    L = lb.load()
+    M = N * N - 1
+    c, j, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    for i in range(M):
+        assert L.lb_basis_index(N, i, ctypes.byref(c), ctypes.byref(j), ctypes.byref(k)) == 0
+        oc, oj, ok = oracle.class_of(N, i)
+        assert (c.value, j.value, k.value) == (oc, oj, ok), i
+        assert oracle.index_of(N, oc, oj, ok) == i
+
+
+def test_basis_index_large_n_round_trip(oracle):
+    """N = 1024 (the largest N): every class boundary and a spread of interior indices."""
+    L = lb.load()
+    N = 1024
+    M = N * N - 1
+    P = N * (N - 1) // 2
+    c, j, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    idx = sorted(set([0, 1, N - 2, N - 1, P - 1, P, P + 1, 2 * P - 1, 2 * P, M - 1] + list(range(0, M, 9973))))
+    for i in idx:
+        assert L.lb_basis_index(N, i, ctypes.byref(c), ctypes.byref(j), ctypes.byref(k)) == 0
+        assert (c.value, j.value, k.value) == oracle.class_of(N, i)
+
+
+def test_basis_index_rejects_bad_arguments():
+    L = lb.load()
+    c, j, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    for N, i in [(1, 0), (0, 0), (lb.MAX_N + 1, 0), (3, -1), (3, 8)]:
+        assert L.lb_basis_index(N, i, ctypes.byref(c), ctypes.byref(j), ctypes.byref(k)) == -1
+        assert L.lb_last_error()
+    assert L.lb_basis_index(3, 0, None, ctypes.byref(j), ctypes.byref(k)) == -1
+    assert b"null pointer" in L.lb_last_error()
+
+
+def test_null_context_is_rejected_before_any_device_call():
+    L = lb.load()
+    assert L.lb_sync(None) == -1
+    assert L.lindblad_prepare(None, 4, None, None, None, 0, None, 0) == -1
+    assert L.lindblad_propagate(None, 15, None, None, 16, None, None, 1, ctypes.c_double(1e-3), 1, 0) == -1
+    assert b"null context" in L.lb_last_error()

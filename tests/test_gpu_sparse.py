@@ -132,3 +132,22 @@ def test_sparse_rejects_dense_operators(lb, ctx):
     with pytest.raises(lb.LindbladError) as e:
         lb.lindblad_prepare_sparse(ctx, N, dcsr(H), [0.1], [dcsr(wl.ginibre(wl.rng(1), N))])
     assert e.value.code == -5
+
+
+def test_csr_rk4_long_rows(lb, ctx, oracle):
+    """N = 70: rows of the diagonal generators hold more than 64 entries and go
+    through the one-wavefront-per-row kernel."""
+    N, B, steps = 70, 2, 60
+    print("[gpu] csr rk4 long rows N=%d" % N, flush=True)
+    H, rates, Ls = wl.dimer_model(N)
+    M = N * N - 1
+    rp, col, val, K = lb.lindblad_prepare_sparse(ctx, N, dcsr(H), rates, [dcsr(L) for L in Ls])
+    lens = np.diff(rp.cpu().numpy())
+    assert lens.max() > 64
+    Qo, Ko = oracle.prepare_factored(H, rates, Ls, np.arange(M))
+    psis = wl.random_pure_states(N, B, 4)
+    V0 = np.array([oracle.expand(np.outer(p, p.conj())).real for p in psis])
+    Vo = oracle.rk4_dense(Qo, Ko, V0, 1e-3, steps)
+    V = torch.from_numpy(V0).cuda()
+    lb.lindblad_propagate_csr(ctx, rp, col, val, K, V, 1e-3, steps)
+    assert rel(V.cpu().numpy(), Vo) < RTOL
