@@ -342,7 +342,7 @@ def config_c2(args):
                                   "0.1/999, 1000 RK4 steps dt=1e-3"},
            "prepare_s": t_prep, "nnz": nnz, "us_per_step": 1e6 * t_prop / S,
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_csr_short+k_csr_long",
+                        "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_csr_stage",
                         "bytes_per_step": bytes_step},
            "checks": {"trace_err": float(tr), "sampled_rows_rel_err_vs_oracle": err}}
     ctx.close()

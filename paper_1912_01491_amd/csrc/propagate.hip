@@ -511,30 +511,38 @@ __global__ __launch_bounds__(256) void k_rk4_small(const double* const* Qs, cons
 }
 
 // ---------------------------------------------------------------------------
-// CSR: rows with at most kLongRow entries are handled by groups of kShortLanes
-// lanes (coalesced reads of the row, shuffle reduction); longer rows (the
-// diagonal-generator rows and the rows they couple to, ~N entries) by one
-// wavefront each. The stage combination is fused: the lane that ends up with a
-// row's sum updates that row. Column indices are read as 32-bit integers
-// converted once per call.
+// CSR stage: one launch per RK4 stage with the stage combination fused in.
+// The first nlong blocks take one long row each (more than kLongRow entries:
+// the diagonal-generator rows and the rows coupled to them, ~N entries), 256
+// threads with a fixed-order block reduction. The other blocks take 128 short
+// rows each: a group of kLanes lanes per row and kSlots rows per group, with the
+// row's update operands (K, v, accumulator) loaded before the dot product and
+// the first 2*kLanes entries of every row loaded at once, so that each wave has
+// several independent loads in flight. Column indices are 32-bit, converted
+// once per call.
 // ---------------------------------------------------------------------------
-constexpr int kShortLanes = 8;
-constexpr int kLongRow = 64;
+constexpr int kLanes = 4;
+constexpr int kSlots = 2;
+constexpr int kLongRow = 32;
+constexpr int kGroups = 256 / kLanes;
+constexpr int kRowsPerBlock = kGroups * kSlots;
 
-__device__ __forceinline__ void rk4_update(int stage, double h, double k, int64_t i, double* V, double* Acc,
-                                           double* Xout) {
+// RK4 stage combination for one element, given k = (Q x + K)_i and the values
+// of v and of the accumulator loaded beforehand.
+__device__ __forceinline__ void rk4_update(int stage, double h, double k, double v, double acc, int64_t i, double* V,
+                                           double* Acc, double* Xout) {
     double x;
     if (stage == 1) {
         Acc[i] = k;
-        x = V[i] + 0.5 * h * k;
+        x = v + 0.5 * h * k;
     } else if (stage == 2) {
-        Acc[i] = Acc[i] + 2.0 * k;
-        x = V[i] + 0.5 * h * k;
+        Acc[i] = acc + 2.0 * k;
+        x = v + 0.5 * h * k;
     } else if (stage == 3) {
-        Acc[i] = Acc[i] + 2.0 * k;
-        x = V[i] + h * k;
+        Acc[i] = acc + 2.0 * k;
+        x = v + h * k;
     } else {
-        x = V[i] + h / 6.0 * (Acc[i] + k);
+        x = v + h / 6.0 * (acc + k);
         V[i] = x;
     }
     Xout[i] = x;
@@ -547,50 +555,112 @@ __global__ void k_csr_prep(int64_t M, int64_t nnz, const int64_t* rowptr, const 
     if (t < M && rowptr[t + 1] - rowptr[t] > kLongRow) longrows[atomicAdd(nlong, 1)] = (int)t;
 }
 
-__global__ __launch_bounds__(256) void k_csr_short(int64_t M, const int64_t* rowptr, const int* col,
-                                                   const double* val, const double* K, double* V, double* W,
-                                                   int B, int stage, double h) {
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kShortLanes;
-    const int sub = threadIdx.x % kShortLanes;
-    const int64_t n = M * B;
-    double* Acc = W;
-    const double* Xin = (stage & 1) ? W + n : W + 2 * n;
-    double* Xout = (stage & 1) ? W + 2 * n : W + n;
-    int64_t e0 = 0, e1 = 0;
-    if (row < M) {
-        e0 = rowptr[row];
-        e1 = rowptr[row + 1];
-    }
-    const bool mine = row < M && e1 - e0 <= kLongRow;
-    for (int b = 0; b < B; ++b) {
-        const double* x = Xin + (int64_t)b * M;
-        double s = 0.0;
-        if (mine)
-            for (int64_t e = e0 + sub; e < e1; e += kShortLanes) s = fma(val[e], x[col[e]], s);
-        for (int o = kShortLanes / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kShortLanes);
-        if (mine && sub == 0) rk4_update(stage, h, s + K[row], (int64_t)b * M + row, V, Acc, Xout);
-    }
-}
+struct CsrArgs {
+    int64_t M;
+    const int64_t* rowptr;
+    const int* col;
+    const double* val;
+    const double* K;
+    double* V;
+    double* W;  // [accumulator | x ping | x pong], M*B each
+    const int* longrows;
+    int nlong;
+    int B;
+};
 
-__global__ __launch_bounds__(256) void k_csr_long(int64_t M, const int64_t* rowptr, const int* col,
-                                                  const double* val, const double* K, double* V, double* W,
-                                                  int B, int stage, double h, const int* longrows,
-                                                  const int* nlong) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (wid >= *nlong) return;
-    const int64_t row = longrows[wid];
-    const int64_t n = M * B;
-    double* Acc = W;
-    const double* Xin = (stage & 1) ? W + n : W + 2 * n;
-    double* Xout = (stage & 1) ? W + 2 * n : W + n;
-    const int64_t e0 = rowptr[row], e1 = rowptr[row + 1];
-    for (int b = 0; b < B; ++b) {
+__global__ __launch_bounds__(256) void k_csr_stage(CsrArgs a, int stage, double h) {
+    const int64_t M = a.M;
+    const int64_t n = M * a.B;
+    double* Acc = a.W;
+    const double* Xin = (stage & 1) ? a.W + n : a.W + 2 * n;
+    double* Xout = (stage & 1) ? a.W + 2 * n : a.W + n;
+    if ((int)blockIdx.x < a.nlong) {
+        __shared__ double red[4];
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int64_t row = a.longrows[blockIdx.x];
+        const int64_t e0 = a.rowptr[row], e1 = a.rowptr[row + 1];
+        for (int b = 0; b < a.B; ++b) {
+            const double* x = Xin + (int64_t)b * M;
+            double s0 = 0.0, s1 = 0.0;
+            int64_t e = e0 + threadIdx.x;
+            for (; e + 256 < e1; e += 512) {
+                s0 = fma(a.val[e], x[a.col[e]], s0);
+                s1 = fma(a.val[e + 256], x[a.col[e + 256]], s1);
+            }
+            if (e < e1) s0 = fma(a.val[e], x[a.col[e]], s0);
+            double sum = s0 + s1;
+            for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+            if (lane == 0) red[wave] = sum;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const int64_t i = (int64_t)b * M + row;
+                const double k = (red[0] + red[1]) + (red[2] + red[3]) + a.K[row];
+                rk4_update(stage, h, k, a.V[i], stage > 1 ? Acc[i] : 0.0, i, a.V, Acc, Xout);
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    // rows, entry offsets: 32-bit (M < 2^31 and nnz < 2^31 are checked by the host)
+    const int g = threadIdx.x / kLanes, sub = threadIdx.x % kLanes;
+    const int base = (int)(blockIdx.x - a.nlong) * kRowsPerBlock + g;
+    int row[kSlots], e0[kSlots], e1[kSlots];
+    bool mine[kSlots];
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+        row[s] = base + s * kGroups;
+        e0[s] = e1[s] = 0;
+        if (row[s] < M) {
+            e0[s] = (int)a.rowptr[row[s]];
+            e1[s] = (int)a.rowptr[row[s] + 1];
+        }
+        mine[s] = row[s] < M && e1[s] - e0[s] <= kLongRow;
+    }
+    for (int b = 0; b < a.B; ++b) {
         const double* x = Xin + (int64_t)b * M;
-        double s = 0.0;
-        for (int64_t e = e0 + lane; e < e1; e += 64) s = fma(val[e], x[col[e]], s);
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-        if (lane == 0) rk4_update(stage, h, s + K[row], (int64_t)b * M + row, V, Acc, Xout);
+        double kk[kSlots], vv[kSlots], aa[kSlots], acc[kSlots];
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) {
+            kk[s] = vv[s] = aa[s] = 0.0;
+            if (mine[s] && sub == 0) {
+                const int64_t i = (int64_t)b * M + row[s];
+                kk[s] = a.K[row[s]];
+                vv[s] = a.V[i];
+                if (stage > 1) aa[s] = Acc[i];
+            }
+        }
+        int c[kSlots][2];
+        double v[kSlots][2];
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int e = e0[s] + sub + u * kLanes;
+                c[s][u] = 0;
+                v[s][u] = 0.0;
+                if (mine[s] && e < e1[s]) {
+                    c[s][u] = a.col[e];
+                    v[s][u] = a.val[e];
+                }
+            }
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) {
+            acc[s] = 0.0;
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (mine[s] && e0[s] + sub + u * kLanes < e1[s]) acc[s] = fma(v[s][u], x[c[s][u]], acc[s]);
+            if (mine[s])
+                for (int e = e0[s] + sub + 2 * kLanes; e < e1[s]; e += kLanes)
+                    acc[s] = fma(a.val[e], x[a.col[e]], acc[s]);
+        }
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) {
+            for (int o = kLanes / 2; o > 0; o >>= 1) acc[s] += __shfl_xor(acc[s], o, kLanes);
+            if (mine[s] && sub == 0) {
+                const int64_t i = (int64_t)b * M + row[s];
+                rk4_update(stage, h, acc[s] + kk[s], vv[s], aa[s], i, a.V, Acc, Xout);
+            }
+        }
     }
 }
 
@@ -1127,18 +1197,12 @@ int lb_impl_propagate_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int
     hipLaunchKernelGGL(k_copy, dim3(lb_blocks(n, 256)), dim3(256), 0, s, (const double*)V, W + n, n);
     LB_CHECK_LAUNCH();
     LB_HIP(hipStreamSynchronize(s));
-    const unsigned gs = lb_blocks(M * kShortLanes, 256);
-    const unsigned gl = lb_blocks((int64_t)hl * 64, 256);
+    CsrArgs ca{M, rowptr, (const int*)col32, val, K, V, W, (const int*)longrows, hl, B};
+    const unsigned grid = (unsigned)hl + lb_blocks(M, kRowsPerBlock);
     for (int64_t st = 0; st < steps; ++st)
         for (int stage = 1; stage <= 4; ++stage) {
-            hipLaunchKernelGGL(k_csr_short, dim3(gs), dim3(256), 0, s, M, rowptr, (const int*)col32, val, K, V, W, B,
-                               stage, dt);
+            hipLaunchKernelGGL(k_csr_stage, dim3(grid), dim3(256), 0, s, ca, stage, dt);
             LB_CHECK_LAUNCH();
-            if (hl > 0) {
-                hipLaunchKernelGGL(k_csr_long, dim3(gl), dim3(256), 0, s, M, rowptr, (const int*)col32, val, K, V, W,
-                                   B, stage, dt, (const int*)longrows, (const int*)nlong);
-                LB_CHECK_LAUNCH();
-            }
         }
     return LB_OK;
 }

@@ -22,9 +22,11 @@
 //   densify H, L_p -> trace shift -> G = sum_p g_p L0^+ L0, A = i H - G/2
 //   column lists of A and L0_p, row lists of L0_p (ELL, width = max degree)
 //   pair rows:   one thread per row, L^+(F_s) in registers, merged and expanded
-//   diag lists:  diag(L(F_n)) per column n (count, scan, fill)
-//   D rows:      one thread per row, scan over the columns that carry a diagonal
-// Rows are written with sorted column indices (S block, J block, D block).
+//   diag lists:  diag(L(F_n)) per column n (count, scan, fill), then their
+//                exclusive prefix sums
+//   D rows:      one wavefront per row over the columns that carry a diagonal
+// Rows are written with sorted column indices (S block, J block, D block);
+// entries whose value is exactly zero are not stored.
 #include "lb_internal.h"
 
 #include <string.h>
@@ -263,16 +265,13 @@ __global__ void k_pair_rows(PairArgs g, int fill) {
         if (m > 0 && key(E[m - 1]) == key(E[i])) E[m - 1].v = cadd(E[m - 1].v, E[i].v);
         else E[m++] = E[i];
     }
-    // distinct pairs, diagonal range, trace
-    int npairs = 0, first_diag = -1;
+    // diagonal range and trace
+    int first_diag = -1;
     cd tr = cmk(0, 0);
     for (int i = 0; i < m; ++i) {
         if (E[i].a == E[i].c) {
             if (first_diag < 0) first_diag = i;
             tr = cadd(tr, E[i].v);
-        } else if (i == 0 || lb_upair(N, E[i - 1].a, E[i - 1].c) != lb_upair(N, E[i].a, E[i].c) ||
-                   E[i - 1].a == E[i - 1].c) {
-            ++npairs;
         }
     }
     // D columns m from max(1, xmin) to xmax, or to N-1 when Tr(Y) != 0: beyond the
@@ -287,34 +286,35 @@ __global__ void k_pair_rows(PairArgs g, int fill) {
         const int lo = xmin > 1 ? xmin : 1;
         nd = xhi >= lo ? xhi - lo + 1 : 0;
     }
-    if (!fill) {
-        g.cnt[s] = 2 * (int64_t)npairs + nd;
-        return;
-    }
-    g.K[s] = tr.re / N;
-    int64_t o = g.rowptr[s];
-    const int64_t oA = o + npairs;
-    int ip = 0;
-    for (int i = 0; i < m; ++i) {
-        if (E[i].a == E[i].c) break;
-        const int64_t pp = lb_upair(N, E[i].a, E[i].c);
-        cd ypq = cmk(0, 0), yqp = cmk(0, 0);  // (p,q) with p < q
-        if (E[i].a < E[i].c) ypq = E[i].v;
-        else yqp = E[i].v;
-        if (i + 1 < m && E[i + 1].a != E[i + 1].c && lb_upair(N, E[i + 1].a, E[i + 1].c) == pp) {
-            ++i;
-            if (E[i].a < E[i].c) ypq = cadd(ypq, E[i].v);
-            else yqp = cadd(yqp, E[i].v);
+    // Entries are emitted in column order (S block, J block, D block); values
+    // that are exactly zero (e.g. the S part of i[H, S_pq] for real H) are not
+    // stored. Count and fill run the same arithmetic, so they agree on which
+    // entries are kept.
+    int64_t o = fill ? g.rowptr[s] : 0;
+    if (fill) g.K[s] = tr.re / N;
+    for (int part = 0; part < 2; ++part) {
+        for (int i = 0; i < m; ++i) {
+            if (E[i].a == E[i].c) break;
+            const int64_t pp = lb_upair(N, E[i].a, E[i].c);
+            cd ypq = cmk(0, 0), yqp = cmk(0, 0);  // (p,q) with p < q
+            if (E[i].a < E[i].c) ypq = E[i].v;
+            else yqp = E[i].v;
+            if (i + 1 < m && E[i + 1].a != E[i + 1].c && lb_upair(N, E[i + 1].a, E[i + 1].c) == pp) {
+                ++i;
+                if (E[i].a < E[i].c) ypq = cadd(ypq, E[i].v);
+                else yqp = cadd(yqp, E[i].v);
+            }
+            // Tr(Y S_pq) = r (Y_pq + Y_qp); Tr(Y J_pq) = i r (Y_pq - Y_qp)
+            const double q = part == 0 ? kR * (ypq.re + yqp.re) : -kR * (ypq.im - yqp.im);
+            if (q == 0.0) continue;
+            if (fill) {
+                g.col[o] = part * Pp + pp;
+                g.val[o] = q;
+            }
+            ++o;
         }
-        // Tr(Y S_pq) = r (Y_pq + Y_qp); Tr(Y J_pq) = i r (Y_pq - Y_qp)
-        g.col[o + ip] = pp;
-        g.val[o + ip] = kR * (ypq.re + yqp.re);
-        g.col[oA + ip] = Pp + pp;
-        g.val[oA + ip] = -kR * (ypq.im - yqp.im);
-        ++ip;
     }
     if (nd > 0) {
-        int64_t od = oA + npairs;
         cd pre = cmk(0, 0);
         int di = first_diag;
         for (int x = 0; x < N; ++x) {
@@ -324,13 +324,19 @@ __global__ void k_pair_rows(PairArgs g, int fill) {
                 ++di;
             }
             if (x >= 1 && x >= xmin && x <= xhi) {
-                g.col[od] = 2 * Pp + x - 1;
-                g.val[od] = (pre.re - (double)x * yx.re) / sqrt((double)x * (x + 1));
-                ++od;
+                const double q = (pre.re - (double)x * yx.re) / sqrt((double)x * (x + 1));
+                if (q != 0.0) {
+                    if (fill) {
+                        g.col[o] = 2 * Pp + x - 1;
+                        g.val[o] = q;
+                    }
+                    ++o;
+                }
             }
             pre = cadd(pre, yx);
         }
     }
+    if (!fill) g.cnt[s] = o;
 }
 
 // ---------------------------------------------------------------------------
@@ -454,7 +460,8 @@ __global__ void k_diag_dcols(DiagArgs g, int fill) {
     if (!fill) g.cnt[nidx] = n;
 }
 
-// D rows: Q[D^m][n] = sum_x w_m(x) diag_n(x) over carrying columns n with key(n) <= m
+// D rows: Q[D^m][n] = sum_x w_m(x) diag_n(x) = (pre_n(m) - m diag_n(m)) / sqrt(m(m+1)),
+// pre_n(m) = sum_{x<m} diag_n(x), over carrying columns n with key(n) <= m.
 struct DRowArgs {
     int N;
     int64_t Pp, M;
@@ -463,6 +470,7 @@ struct DRowArgs {
     const int64_t* off;     // per column offsets into pos/val (M+1)
     const int* pos;
     const double* val;
+    const double* pref;     // exclusive prefix of Re val within each column's list
     const double* l1diag;
     int64_t* cnt;
     const int64_t* rowptr;
@@ -471,35 +479,62 @@ struct DRowArgs {
     double* K;
 };
 
-__global__ void k_drows_sparse(DRowArgs g, int fill) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x + 1;
+// Exclusive prefix sums of the diagonal lists, one thread per carrying column.
+__global__ void k_diag_prefix(int64_t ncarry, const int64_t* carry, const int64_t* off, const double* val,
+                              double* pref) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ncarry) return;
+    const int64_t c = carry[t];
+    double run = 0;
+    for (int64_t e = off[c]; e < off[c + 1]; ++e) {
+        pref[e] = run;
+        run += val[2 * e];
+    }
+}
+
+// One wavefront per D row: lanes take 64 carrying columns at a time; a column
+// contributes when its list reaches row m (key <= m <= last position: the list
+// sums to Tr L(F_n) = 0, so rows beyond its last position vanish) and the value
+// is not exactly zero. A ballot keeps the columns in increasing order.
+__global__ __launch_bounds__(256) void k_drows_sparse(DRowArgs g, int fill) {
+    const int lane = threadIdx.x & 63;
+    const int m = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) + 1;
     const int N = g.N;
     if (m >= N) return;
     const int64_t row = 2 * g.Pp + m - 1;
     const double nrm = 1.0 / sqrt((double)m * (m + 1));
-    int64_t n = 0;
     int64_t o = fill ? g.rowptr[row] : 0;
-    for (int64_t t = 0; t < g.ncarry; ++t) {
-        const int64_t c = g.carry[t];
-        const int64_t e0 = g.off[c], e1 = g.off[c + 1];
-        // diag(L(F_n)) sums to Tr L(F_n) = 0, so rows beyond its last position vanish
-        int key = g.pos[e0];
-        key = key > 1 ? key : 1;
-        if (key > m || g.pos[e1 - 1] < m) continue;
-        if (fill) {
-            double pre = 0, at = 0;
-            for (int64_t e = e0; e < e1; ++e) {
-                const int x = g.pos[e];
-                if (x < m) pre += g.val[2 * e];
-                else if (x == m) at = g.val[2 * e];
+    for (int64_t t0 = 0; t0 < g.ncarry; t0 += 64) {
+        const int64_t t = t0 + lane;
+        int64_t c = 0;
+        double q = 0.0;
+        bool keep = false;
+        if (t < g.ncarry) {
+            c = g.carry[t];
+            int64_t lo = g.off[c], hi = g.off[c + 1] - 1;
+            const int key = g.pos[lo] > 1 ? g.pos[lo] : 1;
+            if (key <= m && g.pos[hi] >= m) {
+                while (lo < hi) {  // first entry at position >= m
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (g.pos[mid] < m) lo = mid + 1;
+                    else hi = mid;
+                }
+                const double at = g.pos[lo] == m ? g.val[2 * lo] : 0.0;
+                q = (g.pref[lo] - (double)m * at) * nrm;
+                keep = q != 0.0;
             }
-            g.col[o + n] = c;
-            g.qv[o + n] = (pre - (double)m * at) * nrm;
         }
-        ++n;
+        const unsigned long long mask = __ballot(keep);
+        if (keep && fill) {
+            const int64_t r = o + __popcll(mask & ((1ull << lane) - 1ull));
+            g.col[r] = c;
+            g.qv[r] = q;
+        }
+        o += __popcll(mask);
     }
+    if (lane != 0) return;
     if (!fill) {
-        g.cnt[row] = n;
+        g.cnt[row] = o;
         return;
     }
     double k = 0;
@@ -742,6 +777,7 @@ static int sparse_body(lb_ctx* c, int N, const lb_csr_c128* H, int P, const doub
     const size_t o_pos = take3(sizeof(int) * (size_t)std::max<int64_t>(dtotal, 1));
     const size_t o_dval = take3(sizeof(double) * 2 * (size_t)std::max<int64_t>(dtotal, 1));
     const size_t o_clist = take3(sizeof(int64_t) * (size_t)std::max<int64_t>(ncarry, 1));
+    const size_t o_pref = take3(sizeof(double) * (size_t)std::max<int64_t>(dtotal, 1));
     if (o3 > c->ws_bytes) {
         *want = o3 + (o3 >> 3);
         return 1;
@@ -754,6 +790,12 @@ static int sparse_body(lb_ctx* c, int N, const lb_csr_c128* H, int P, const doub
     LB_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_diag_dcols, dim3(lb_blocks(N - 1, 64)), dim3(64), 0, s, da, 1);
     LB_CHECK_LAUNCH();
+    if (ncarry > 0) {
+        hipLaunchKernelGGL(k_diag_prefix, dim3(lb_blocks(ncarry, 64)), dim3(64), 0, s, ncarry,
+                           (const int64_t*)(ws + o_clist), (const int64_t*)dcnt, (const double*)da.val,
+                           (double*)(ws + o_pref));
+        LB_CHECK_LAUNCH();
+    }
 
     // row counts
     PairArgs pa;
@@ -778,6 +820,7 @@ static int sparse_body(lb_ctx* c, int N, const lb_csr_c128* H, int P, const doub
     dr.off = dcnt;
     dr.pos = da.pos;
     dr.val = da.val;
+    dr.pref = (const double*)(ws + o_pref);
     dr.l1diag = l1;
     dr.cnt = rowcnt;
     dr.rowptr = rowptr;
@@ -788,7 +831,7 @@ static int sparse_body(lb_ctx* c, int N, const lb_csr_c128* H, int P, const doub
         hipLaunchKernelGGL(k_pair_rows, dim3(lb_blocks(2 * Pp, 64)), dim3(64), 0, s, pa, 0);
         LB_CHECK_LAUNCH();
     }
-    hipLaunchKernelGGL(k_drows_sparse, dim3(lb_blocks(N - 1, 64)), dim3(64), 0, s, dr, 0);
+    hipLaunchKernelGGL(k_drows_sparse, dim3(lb_blocks((int64_t)(N - 1) * 64, 256)), dim3(256), 0, s, dr, 0);
     LB_CHECK_LAUNCH();
     int hovf[2] = {0, 0};
     LB_HIP(hipMemcpyAsync(hovf, ovf, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
@@ -826,7 +869,7 @@ static int sparse_body(lb_ctx* c, int N, const lb_csr_c128* H, int P, const doub
         hipLaunchKernelGGL(k_pair_rows, dim3(lb_blocks(2 * Pp, 64)), dim3(64), 0, s, pa, 1);
         LB_CHECK_LAUNCH();
     }
-    hipLaunchKernelGGL(k_drows_sparse, dim3(lb_blocks(N - 1, 64)), dim3(64), 0, s, dr, 1);
+    hipLaunchKernelGGL(k_drows_sparse, dim3(lb_blocks((int64_t)(N - 1) * 64, 256)), dim3(256), 0, s, dr, 1);
     LB_CHECK_LAUNCH();
     return LB_OK;
 }

@@ -151,3 +151,16 @@ def test_csr_rk4_long_rows(lb, ctx, oracle):
     V = torch.from_numpy(V0).cuda()
     lb.lindblad_propagate_csr(ctx, rp, col, val, K, V, 1e-3, steps)
     assert rel(V.cpu().numpy(), Vo) < RTOL
+
+
+@pytest.mark.parametrize("N", [5, 8, 12])
+def test_dimer_csr_stores_no_zeros(lb, ctx, oracle, N):
+    """Entries that are exactly zero (the S or J half of a pair for real H and
+    real L) are not stored: nnz equals the number of nonzero entries of the
+    oracle's Q (threshold 1e-13 of the largest), and no stored value is zero."""
+    H, rates, Ls = wl.dimer_model(N)
+    M = N * N - 1
+    rp, col, val, K = gpu_sparse(lb, ctx, H, rates, Ls)
+    Qo, _ = oracle.prepare_factored(H, rates, Ls, np.arange(M))
+    assert np.all(val != 0.0)
+    assert len(val) == int((np.abs(Qo) > 1e-13 * np.abs(Qo).max()).sum())
