@@ -44,18 +44,26 @@ def log(msg):
 
 
 def gemm64_digest():
-    """Digest of the FP64 stage-GEMM source (its work mapping and kernel body)."""
+    """Digest of the FP64 stage-GEMM source: its work mapping and the direct and
+    LDS-staged kernel bodies."""
     src = open(os.path.join(ROOT, "paper_1912_01491_amd", "csrc", "propagate.hip")).read()
     a = src.index("struct GemmGrid")
     b = src.index("template <int RT, int CT, bool ALIGNED>", src.index("void k_gemm64"))
-    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+    c = src.index("// LDS-staged variants")
+    d = src.index("template <int RT, int CT>", src.index("void k_gemm64s"))
+    return hashlib.sha256((src[a:b] + src[c:d]).encode()).hexdigest()[:16]
+
+
+def staged(Qs, ldq, elem):
+    """True when the stage GEMM runs its LDS-staged form (128-byte rows)."""
+    return (ldq * elem) % 128 == 0 and all(q.data_ptr() % 128 == 0 for q in Qs)
 
 
 def measured_traffic(M, R, B, tile):
     """HBM bytes per launch of k_gemm64 from the FETCH_SIZE / WRITE_SIZE counter
     runs summarised under profiles/, scaled by the copy-kernel factors recorded
     there; None unless kernel source, shape and tile are those of the counter run."""
-    path = os.path.join(ROOT, "profiles", "k_gemm64_traffic_N200_dense.md")
+    path = os.path.join(ROOT, "profiles", "k_gemm64s_traffic_N200_dense.md")
     try:
         line = next(x for x in open(path) if x.startswith("traffic-record:"))
     except (OSError, StopIteration):
@@ -573,7 +581,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(M, R, B, tile) if prec == lb.FP64 else None,
-            "kernel": "k_gemm64" if prec == lb.FP64 else "k_gemm32",
+            "kernel": ("k_gemm64" if prec == lb.FP64 else "k_gemm32")
+                      + ("s" if staged(Qs if prec == lb.FP64 else Q32s, ldq, qbytes) else ""),
             "avg_ms": avg_ms,
             "bytes_per_launch": alg_bytes,
         },

@@ -178,7 +178,11 @@ int lindblad_prepare_sparse_fill(lb_ctx* ctx, int N, const lb_csr_c128* H, int P
  * V + b*M) holds v(0) on entry and v(steps*dt) on exit. Q: device, M rows
  * of leading dimension ldq. precision LB_FP64 uses Q directly; LB_FP32
  * requires Q32 (device float, same ldq) from lindblad_q_to_f32 and ignores
- * Q. Bit-for-bit deterministic for fixed inputs and launch configuration. */
+ * Q. Bit-for-bit deterministic for fixed inputs and launch configuration.
+ * When Q (or Q32) starts on a 128-byte boundary and its rows are 128-byte
+ * multiples (ldq a multiple of 16 in FP64, 32 in FP32), the stage GEMM stages
+ * Q through LDS with full-line streaming loads; otherwise it loads the matrix
+ * core operands directly. Both give identical results. */
 int lindblad_propagate(lb_ctx* ctx, int64_t M, const double* Q, const float* Q32, int64_t ldq,
                        const double* K, double* V, int B, double dt, int64_t steps, int precision);
 

@@ -262,8 +262,10 @@ def lb_reconstruct(ctx: Context, V, N: int):
 # ---------------------------------------------------------------------------
 
 def default_ldq(M: int) -> int:
-    """Leading dimension used by default: M rounded up to 16 doubles (128 B rows)."""
-    return (M + 15) // 16 * 16
+    """Leading dimension used by default: M rounded up to 32 elements, so that
+    rows of Q (FP64) and of Q32 (FP32) start on 128-byte boundaries, which the
+    LDS-staged stage GEMMs need."""
+    return (M + 31) // 32 * 32
 
 
 def lindblad_prepare(ctx: Context, H, gamma, ldq: int | None = None, Q=None, K=None,

@@ -167,6 +167,9 @@ __device__ static inline void cstore(double* p, int64_t idx, cd v) {
 // ---------------------------------------------------------------------------
 
 static inline unsigned lb_blocks(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+// Leading dimension of the library's own Q buffers: M rounded up to 32 elements
+// (128-byte aligned rows in FP64 and FP32).
+static inline int64_t lb_default_ldq(int64_t M) { return (M + 31) / 32 * 32; }
 
 // ---------------------------------------------------------------------------
 // Entry points implemented in the kernel translation units

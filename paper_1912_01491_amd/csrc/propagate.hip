@@ -31,6 +31,8 @@
 
 typedef double lb_double4 __attribute__((ext_vector_type(4)));
 typedef float lb_float4 __attribute__((ext_vector_type(4)));
+typedef double lb_double2v __attribute__((ext_vector_type(2)));
+typedef unsigned int lb_u4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -269,6 +271,346 @@ __global__ __launch_bounds__(256) void k_gemm32(const float* const* Qs, int64_t 
                     acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t][h], xa[c][h], acc[t][c], 0, 0, 0);
     }
     // D layout of v_mfma_f32_16x16x4f32: lane l, element j -> row 4(l/16) + j
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t row = row0 + 16 * t + 4 * lk + j;
+                if (row < M) Part[ilv2(row, 16 * c + lr, Bp)] = (double)acc[t][c][j];
+            }
+}
+
+// ---------------------------------------------------------------------------
+// LDS-staged variants of the two stage GEMMs (rows of Q 128-byte aligned).
+// ---------------------------------------------------------------------------
+// The matrix-core A operand wants lane l to hold row l%16 of a 16-row tile, so
+// a direct 16-byte load per lane touches 16 rows per quarter-wave and splits
+// every 128-byte line of Q between two load instructions. Here a wave instead
+// reads its 16*RT rows x 128 bytes (16 FP64 / 32 FP32 columns) as 2*RT loads of
+// 8 complete lines (lane L: row L/8 of the group, 16-byte piece (L%8) ^ (L/8)),
+// with the nontemporal hint since Q is streamed once per stage, writes the
+// pieces to a wave-private LDS buffer (slot g*64 + L), and reads the operands
+// back in the matrix-core layout: row r, piece c sits in slot
+// (r/8)*64 + (r%8)*8 + (c ^ (r%8)), which keeps each group of 8 lanes of a
+// 16-byte LDS read on distinct banks. Two chunks of loads are kept in flight.
+// The columns each MFMA consumes are the same as in the direct kernels, so the
+// results are bit-identical to theirs.
+
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Per-lane byte offsets (from the wave's first row) of the lane's 16-byte piece
+// in each of the 2*RT groups of 8 rows; rows past M re-read row M-1.
+template <int G>
+__device__ __forceinline__ void stage_offsets(uint32_t (&off)[G], int64_t row0, int64_t M, int64_t rowbytes,
+                                              int lane) {
+    const int wr = lane >> 3, wc = (lane & 7) ^ wr;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        int64_t row = row0 + 8 * g + wr;
+        row = row < M ? row : M - 1;
+        off[g] = (uint32_t)((row - row0) * rowbytes + 16 * wc);
+    }
+}
+
+typedef const lb_u4 __attribute__((address_space(1)))* lb_gu4;
+
+template <int G>
+__device__ __forceinline__ void stage_load(lb_u4 (&q)[G], const char* p, const uint32_t (&off)[G]) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) q[g] = __builtin_nontemporal_load((lb_gu4)(p + off[g]));
+}
+
+// The B operand (states) of one chunk for CT column tiles, loaded together with
+// the chunk's Q so that waiting for it never waits for a later prefetch.
+template <int CT>
+__device__ __forceinline__ void stage_xload(lb_u4 (&xa)[CT], lb_u4 (&xb)[CT], const char* x0, const char* x1) {
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+        xa[c] = *(lb_gu4)(x0 + 256 * c);
+        xb[c] = *(lb_gu4)(x1 + 256 * c);
+    }
+}
+
+template <int G>
+__device__ __forceinline__ void stage_put(lb_u4* lds, const lb_u4 (&q)[G], int lane) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) lds[g * 64 + lane] = q[g];
+}
+
+template <int RT, int CT>
+__global__ __launch_bounds__(256) void k_gemm64s(const double* const* Qs, int64_t M, int64_t Mp, int64_t ldq,
+                                                 const double* Xall, int64_t xstride, double* Pall,
+                                                 int64_t pstride, int kslab, GemmGrid gg) {
+    extern __shared__ lb_u4 stage_lds[];
+    constexpr int Bp = 16 * CT;
+    constexpr int G = 2 * RT;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    int bx, slab, r;
+    if (!gemm_work(gg, bx, slab, r)) return;
+    const double* Q = Qs[r];
+    const double* X = Xall + r * xstride;
+    double* Part = Pall + r * pstride + (int64_t)slab * Mp * Bp;
+    const int64_t row0 = ((int64_t)bx * (blockDim.x >> 6) + wave) * (16 * RT);
+    if (row0 >= M) return;
+    const int64_t k0 = (int64_t)slab * kslab;
+    const int64_t k1 = k0 + kslab < M ? k0 + kslab : M;
+    lb_u4* lds = stage_lds + wave * (G * 64);
+    const char* qbase = reinterpret_cast<const char*>(Q + row0 * ldq);
+    uint32_t off[G];
+    stage_offsets<G>(off, row0, M, ldq * 8, lane);
+    const int rr = lr & 7;
+    const int s0 = (lr >> 3) * 64 + rr * 8 + (lk ^ rr);
+
+    lb_double4 acc[RT][CT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = lb_double4{0, 0, 0, 0};
+
+    // X of chunk kc for column tile c: lane's double2 at ((kc>>1) + lk)*2Bp + 2(16c + lr); the
+    // chunk's second half (columns kc+8..) starts 4*2Bp doubles later.
+    const char* xlane = reinterpret_cast<const char*>(X + lk * (2 * Bp) + 2 * lr);
+    auto xaddr = [&](int64_t kc) { return xlane + (kc >> 1) * (2 * Bp) * 8; };
+    auto mma = [&](const lb_u4 (&xa)[CT], const lb_u4 (&xb)[CT]) {
+        lb_double2v qa[RT], qb[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            qa[t] = __builtin_bit_cast(lb_double2v, lds[128 * t + s0]);
+            qb[t] = __builtin_bit_cast(lb_double2v, lds[(128 * t + s0) ^ 4]);
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const lb_double2v x0 = __builtin_bit_cast(lb_double2v, xa[c]);
+                const lb_double2v x1 = __builtin_bit_cast(lb_double2v, xb[c]);
+                acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[t].x, x0.x, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[t].y, x0.y, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(qb[t].x, x1.x, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(qb[t].y, x1.y, acc[t][c], 0, 0, 0);
+            }
+    };
+
+    // two chunks in flight: (qA, xA) holds chunk j, (qB, xB) chunk j+1
+    const int64_t nch = (k1 - k0) / 16;
+    lb_u4 qA[G], qB[G], xA0[CT], xA1[CT], xB0[CT], xB1[CT];
+    // the scheduling barriers keep each chunk's loads where they are issued here,
+    // ahead of the next chunk's, instead of next to their first use
+    auto fetch = [&](lb_u4 (&q)[G], lb_u4 (&x0)[CT], lb_u4 (&x1)[CT], int64_t kc) {
+        __builtin_amdgcn_sched_barrier(0);
+        stage_xload<CT>(x0, x1, xaddr(kc), xaddr(kc + 8));
+        stage_load<G>(q, qbase + kc * 8, off);
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    // Every pass issues both prefetches (chunk indices past the end re-read the
+    // last chunk), so the same loads are in flight at every loop iteration.
+    auto kcl = [&](int64_t ch) { return k0 + 16 * (ch < nch ? ch : nch - 1); };
+    if (nch > 0) {
+        fetch(qA, xA0, xA1, kcl(0));
+        fetch(qB, xB0, xB1, kcl(1));
+        int64_t j = 0;
+        for (; j + 1 < nch; j += 2) {
+            stage_put<G>(lds, qA, lane);
+            wave_lds_fence();
+            mma(xA0, xA1);
+            wave_lds_fence();
+            fetch(qA, xA0, xA1, kcl(j + 2));
+            stage_put<G>(lds, qB, lane);
+            wave_lds_fence();
+            mma(xB0, xB1);
+            wave_lds_fence();
+            fetch(qB, xB0, xB1, kcl(j + 3));
+        }
+        if (j < nch) {
+            stage_put<G>(lds, qA, lane);
+            wave_lds_fence();
+            mma(xA0, xA1);
+            wave_lds_fence();
+        }
+    }
+    const int64_t kc = k0 + 16 * nch;
+    if (kc < k1) {  // ragged tail: guarded scalar loads, zero beyond M
+        double qa[RT][4], xa[CT][4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int64_t k = kc + 2 * lk + (h & 1) + 8 * (h >> 1);
+            const bool ok = k < k1;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                int64_t row = row0 + 16 * t + lr;
+                row = row < M ? row : M - 1;
+                qa[t][h] = ok ? Q[row * ldq + k] : 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < CT; ++c) xa[c][h] = ok ? X[ilv2(k, 16 * c + lr, Bp)] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+#pragma unroll
+                for (int h = 0; h < 4; ++h)
+                    acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[t][h], xa[c][h], acc[t][c], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t row = row0 + 16 * t + 4 * j + lk;
+                if (row < M) Part[ilv2(row, 16 * c + lr, Bp)] = acc[t][c][j];
+            }
+}
+
+template <int RT, int CT>
+__global__ __launch_bounds__(256) void k_gemm32s(const float* const* Qs, int64_t M, int64_t Mp, int64_t ldq,
+                                                 const float* Xall, int64_t xstride, double* Pall,
+                                                 int64_t pstride, int kslab, GemmGrid gg) {
+    extern __shared__ lb_u4 stage_lds[];
+    constexpr int Bp = 16 * CT;
+    constexpr int G = 2 * RT;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    int bx, slab, r;
+    if (!gemm_work(gg, bx, slab, r)) return;
+    const float* Q = Qs[r];
+    const float* X = Xall + r * xstride;
+    double* Part = Pall + r * pstride + (int64_t)slab * Mp * Bp;
+    const int64_t row0 = ((int64_t)bx * (blockDim.x >> 6) + wave) * (16 * RT);
+    if (row0 >= M) return;
+    const int64_t k0 = (int64_t)slab * kslab;
+    const int64_t k1 = k0 + kslab < M ? k0 + kslab : M;
+    lb_u4* lds = stage_lds + wave * (G * 64);
+    const char* qbase = reinterpret_cast<const char*>(Q + row0 * ldq);
+    uint32_t off[G];
+    stage_offsets<G>(off, row0, M, ldq * 4, lane);
+    const int rr = lr & 7;
+    const int s0 = (lr >> 3) * 64 + rr * 8 + (lk ^ rr);
+
+    lb_float4 acc[RT][CT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = lb_float4{0, 0, 0, 0};
+
+    // X of chunk kc for column tile c: lane's float4 at ((kc>>2) + lk)*4Bp + 4(16c + lr); the
+    // chunk's second half (columns kc+16..) starts 4*4Bp floats later.
+    const char* xlane = reinterpret_cast<const char*>(X + lk * (4 * Bp) + 4 * lr);
+    auto xaddr = [&](int64_t kc) { return xlane + (kc >> 2) * (4 * Bp) * 4; };
+    auto mma = [&](const lb_u4 (&xa)[CT], const lb_u4 (&xb)[CT]) {
+        lb_float4 qa[RT], qb[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            qa[t] = __builtin_bit_cast(lb_float4, lds[128 * t + s0]);
+            qb[t] = __builtin_bit_cast(lb_float4, lds[(128 * t + s0) ^ 4]);
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const lb_float4 x0 = __builtin_bit_cast(lb_float4, xa[c]);
+                const lb_float4 x1 = __builtin_bit_cast(lb_float4, xb[c]);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t].x, x0.x, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t].y, x0.y, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t].z, x0.z, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t].w, x0.w, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qb[t].x, x1.x, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qb[t].y, x1.y, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qb[t].z, x1.z, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qb[t].w, x1.w, acc[t][c], 0, 0, 0);
+            }
+    };
+
+    const int64_t nch = (k1 - k0) / 32;
+    lb_u4 qA[G], qB[G], xA0[CT], xA1[CT], xB0[CT], xB1[CT];
+    auto fetch = [&](lb_u4 (&q)[G], lb_u4 (&x0)[CT], lb_u4 (&x1)[CT], int64_t kc) {
+        __builtin_amdgcn_sched_barrier(0);
+        stage_xload<CT>(x0, x1, xaddr(kc), xaddr(kc + 16));
+        stage_load<G>(q, qbase + kc * 4, off);
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    // Every pass issues both prefetches (chunk indices past the end re-read the
+    // last chunk), so the same loads are in flight at every loop iteration.
+    auto kcl = [&](int64_t ch) { return k0 + 32 * (ch < nch ? ch : nch - 1); };
+    if (nch > 0) {
+        fetch(qA, xA0, xA1, kcl(0));
+        fetch(qB, xB0, xB1, kcl(1));
+        int64_t j = 0;
+        for (; j + 1 < nch; j += 2) {
+            stage_put<G>(lds, qA, lane);
+            wave_lds_fence();
+            mma(xA0, xA1);
+            wave_lds_fence();
+            fetch(qA, xA0, xA1, kcl(j + 2));
+            stage_put<G>(lds, qB, lane);
+            wave_lds_fence();
+            mma(xB0, xB1);
+            wave_lds_fence();
+            fetch(qB, xB0, xB1, kcl(j + 3));
+        }
+        if (j < nch) {
+            stage_put<G>(lds, qA, lane);
+            wave_lds_fence();
+            mma(xA0, xA1);
+            wave_lds_fence();
+        }
+    }
+    // remainder (< 32 columns, last slab only): direct loads as in k_gemm32
+    const float* qrow[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+        int64_t row = row0 + 16 * t + lr;
+        row = row < M ? row : M - 1;
+        qrow[t] = Q + row * ldq;
+    }
+    int64_t kc = k0 + 32 * nch;
+    if (kc + 16 <= k1) {
+        float4 qa[RT], xa[CT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) qa[t] = *reinterpret_cast<const float4*>(qrow[t] + kc + 4 * lk);
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+            xa[c] = *reinterpret_cast<const float4*>(X + ((kc >> 2) + lk) * (4 * Bp) + 4 * (16 * c + lr));
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t].x, xa[c].x, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t].y, xa[c].y, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t].z, xa[c].z, acc[t][c], 0, 0, 0);
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t].w, xa[c].w, acc[t][c], 0, 0, 0);
+            }
+        kc += 16;
+    }
+    if (kc < k1) {
+        float qa[RT][4], xa[CT][4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int64_t k = kc + 4 * lk + h;
+            const bool ok = k < k1;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) qa[t][h] = ok ? qrow[t][k] : 0.0f;
+#pragma unroll
+            for (int c = 0; c < CT; ++c) xa[c][h] = ok ? X[ilv4(k, 16 * c + lr, Bp)] : 0.0f;
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+#pragma unroll
+                for (int h = 0; h < 4; ++h)
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[t][h], xa[c][h], acc[t][c], 0, 0, 0);
+    }
 #pragma unroll
     for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -721,31 +1063,68 @@ gemm32_fn pick32(int RT, int CT) {
     return nullptr;
 }
 
+gemm64_fn pick64s(int RT, int CT) {
+    if (CT == 1) {
+        if (RT == 1) return k_gemm64s<1, 1>;
+        if (RT == 2) return k_gemm64s<2, 1>;
+        if (RT == 4) return k_gemm64s<4, 1>;
+    } else if (CT == 2) {
+        if (RT == 1) return k_gemm64s<1, 2>;
+        if (RT == 2) return k_gemm64s<2, 2>;
+        if (RT == 4) return k_gemm64s<4, 2>;
+    } else if (CT == 4) {
+        if (RT == 1) return k_gemm64s<1, 4>;
+        if (RT == 2) return k_gemm64s<2, 4>;
+    }
+    return nullptr;
+}
+
+gemm32_fn pick32s(int RT, int CT) {
+    if (CT == 1) {
+        if (RT == 1) return k_gemm32s<1, 1>;
+        if (RT == 2) return k_gemm32s<2, 1>;
+        if (RT == 4) return k_gemm32s<4, 1>;
+    } else if (CT == 2) {
+        if (RT == 1) return k_gemm32s<1, 2>;
+        if (RT == 2) return k_gemm32s<2, 2>;
+        if (RT == 4) return k_gemm32s<4, 2>;
+    } else if (CT == 4) {
+        if (RT == 1) return k_gemm32s<1, 4>;
+        if (RT == 2) return k_gemm32s<2, 4>;
+    }
+    return nullptr;
+}
+
 int bpad(int B) { return B <= 16 ? 16 : (B <= 32 ? 32 : 64); }
 
 }  // namespace
 
-// Default tile from sweeps on MI355X: 64 rows per wave for 16-state blocks
-// (32 for 32/64 states), and k-slabs sized so that one system alone gives a
-// launch of about 8192 waves (4096 for FP32), with slabs of at least 384 columns for 64-state
-// blocks (compute-bound) and 256 otherwise. The slab length fixes the
-// summation order, so it depends on (M, Bp) only and never on how many systems
-// share a launch: a system's result is bit-identical alone and batched.
+// Default tile from sweeps on MI355X (LDS-staged kernels): 64 rows per wave for
+// 16-state blocks (32 rows, one wave per block for 32/64 states), and k-slabs
+// sized so that one system alone gives about 2500 row-waves x slabs (5000 for
+// 32/64 states): long slabs keep the streaming loads of a wave going, and at
+// N = 200 a single system still fills the chip. Slabs are a multiple of 32
+// columns (128 bytes of FP32, 256 of FP64) so that every slab starts on a line,
+// and at least 256 (384 for 64 states) long. The slab length fixes the
+// summation order, so it depends on (M, Bp) only and never on the precision
+// or on how many systems share a launch: a system's result is bit-identical
+// alone and batched.
 lb_tile lb_default_tile(int64_t M, int Bp, int precision, int R) {
     lb_tile t;
     const int CT = Bp / 16;
     t.rows = CT == 1 ? 64 : 32;
     t.waves = CT == 1 ? 2 : 1;
     (void)R;
+    (void)precision;
     const int64_t rowwaves = (M + t.rows - 1) / t.rows;
-    const int64_t target = precision == LB_FP32 ? 4096 : 8192;
+    const int64_t target = CT == 1 ? 2500 : 5000;
     int64_t nslab = (target + rowwaves - 1) / rowwaves;
     const int64_t minslab = CT == 4 ? 384 : 256;
     const int64_t maxslab = std::max<int64_t>(1, M / minslab);
     if (nslab > maxslab) nslab = maxslab;
     if (nslab < 1) nslab = 1;
     int64_t ks = (M + nslab - 1) / nslab;
-    ks = (ks + 15) / 16 * 16;
+    ks = (ks + 31) / 32 * 32;
     t.kslab = (int)ks;
     return t;
 }
@@ -799,6 +1178,7 @@ struct Plan {
     size_t shm;
     int q_in_lds;
     bool aligned;
+    bool staged;  // LDS-staged GEMM: every Q and every row of Q 128-byte aligned
     const void** d;
     double *V, *Acc, *X, *Part, *W;
     float* X32;
@@ -860,9 +1240,16 @@ static int plan_make(Plan& p, int R, int64_t M, int64_t ldq, int B, int precisio
 // pointer arrays through the context's pinned staging buffer. Synchronizes.
 static int plan_bind(lb_ctx* c, Plan& p, char* base, const lb_prop_sys* sys) {
     const int R = p.R;
+    const int64_t es = p.precision == LB_FP32 ? 4 : 8;
+    p.staged = p.kind == PATH_MFMA && (p.ldq * es) % 128 == 0;
     for (int r = 0; r < R; ++r) {
         const void* qp = p.precision == LB_FP32 ? (const void*)sys[r].Q32 : (const void*)sys[r].Q;
         if (p.kind != PATH_SMALL && ((uintptr_t)qp) % 16) return lb_fail(LB_ERR_INVALID_ARG, "Q must be 16-byte aligned");
+        if (((uintptr_t)qp) % 128) p.staged = false;
+    }
+    if (p.staged) {
+        const int RT = p.tile.rows / 16, CT = p.Bp / 16;
+        if (p.precision == LB_FP64 ? pick64s(RT, CT) == nullptr : pick32s(RT, CT) == nullptr) p.staged = false;
     }
     int rc = lb_host_reserve(c, sizeof(void*) * 5 * R);
     if (rc) return rc;
@@ -930,13 +1317,15 @@ static int plan_gemm(const Plan& p, hipStream_t s, int stage, double dt) {
     gg.per_xcd = (total + 7) / 8;
     const dim3 ggrid((unsigned)(8 * gg.per_xcd));
     const dim3 gblock(64 * p.tile.waves);
+    // staged kernels: 2*RT KiB of LDS per wave
+    const size_t shm = p.staged ? (size_t)p.tile.waves * 2 * RT * 1024 : 0;
     if (p.precision == LB_FP64) {
-        gemm64_fn fn = p.aligned ? pick64<true>(RT, CT) : pick64<false>(RT, CT);
-        hipLaunchKernelGGL(fn, ggrid, gblock, 0, s, (const double* const*)p.d, p.M, p.Mp, p.ldq, (const double*)p.X,
+        gemm64_fn fn = p.staged ? pick64s(RT, CT) : (p.aligned ? pick64<true>(RT, CT) : pick64<false>(RT, CT));
+        hipLaunchKernelGGL(fn, ggrid, gblock, shm, s, (const double* const*)p.d, p.M, p.Mp, p.ldq, (const double*)p.X,
                            p.sstride, p.Part, p.pstride, p.tile.kslab, gg);
     } else {
-        gemm32_fn fn = p.aligned ? pick32<true>(RT, CT) : pick32<false>(RT, CT);
-        hipLaunchKernelGGL(fn, ggrid, gblock, 0, s, (const float* const*)(p.d + p.R), p.M, p.Mp, p.ldq,
+        gemm32_fn fn = p.staged ? pick32s(RT, CT) : (p.aligned ? pick32<true>(RT, CT) : pick32<false>(RT, CT));
+        hipLaunchKernelGGL(fn, ggrid, gblock, shm, s, (const float* const*)(p.d + p.R), p.M, p.Mp, p.ldq,
                            (const float*)p.X32, p.s32stride, p.Part, p.pstride, p.tile.kslab, gg);
     }
     LB_CHECK_LAUNCH();
@@ -1124,9 +1513,9 @@ int lb_impl_autotune(lb_ctx* c, int64_t M, const lb_prop_sys* sys, int64_t ldq, 
     const int Bp = bpad(B);
     if (B == 1 && precision == LB_FP64) return LB_OK;  // GEMV path has no tile
     const int CT = Bp / 16;
-    std::vector<int> rows_c = CT == 1 ? std::vector<int>{32, 64, 128} : std::vector<int>{16, 32, 64};
+    std::vector<int> rows_c = CT == 1 ? std::vector<int>{32, 64} : std::vector<int>{16, 32};
     std::vector<int> waves_c = {1, 2, 4};
-    std::vector<int> target_c = {1024, 2048, 4096, 8192};
+    std::vector<int> target_c = {1, 1250, 2500, 5000, 10000};  // 1: one slab per row block
     lb_tile best = lb_default_tile(M, Bp, precision, 1);
     double best_ms = 1e30;
     for (int rows : rows_c)
@@ -1140,7 +1529,7 @@ int lb_impl_autotune(lb_ctx* c, int64_t M, const lb_prop_sys* sys, int64_t ldq, 
                 const int64_t maxslab = (M + 255) / 256;
                 nslab = nslab < 1 ? 1 : (nslab > maxslab ? maxslab : nslab);
                 int64_t ks = (M + nslab - 1) / nslab;
-                t.kslab = (int)((ks + 15) / 16 * 16);
+                t.kslab = (int)((ks + 31) / 32 * 32);
                 double ms = 0;
                 int rc = lb_impl_time_stage(c, 1, M, sys, ldq, B, precision, 3, &ms, &t);
                 if (rc) continue;

@@ -71,7 +71,7 @@ struct lb_server {
 
 static size_t dense_q_bytes(int N, int precision) {
     const int64_t M = (int64_t)N * N - 1;
-    const int64_t ldq = (M + 15) / 16 * 16;
+    const int64_t ldq = lb_default_ldq(M);
     size_t b = sizeof(double) * (size_t)M * ldq + sizeof(double) * M;
     if (precision == LB_FP32) b += sizeof(float) * (size_t)M * ldq;
     return b;
@@ -112,7 +112,7 @@ static int run_batch(lb_server* s, int slot, std::vector<Ticket*>& batch) {
         return LB_OK;
     };
     if (r0.kind == LB_REQ_DENSE) {
-        const int64_t ldq = (M + 15) / 16 * 16;
+        const int64_t ldq = lb_default_ldq(M);
         const int R = (int)batch.size();
         std::vector<lb_prop_sys> sys(R);
         for (int i = 0; i < R && !rc; ++i) {

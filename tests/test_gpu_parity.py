@@ -209,6 +209,34 @@ def test_propagate_fp32_error_stated(lb, ctx, oracle, B):
     assert err < 2e-6
 
 
+@pytest.mark.parametrize("N,B", [(30, 2), (30, 16), (45, 40), (45, 64), (64, 16)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_staged_gemm_equals_direct(lb, ctx, N, B, prec):
+    """Rows of Q on 128-byte boundaries select the LDS-staged stage GEMM; a
+    leading dimension that breaks that alignment selects the direct-load one.
+    Both consume the same columns in the same order, so the results agree bit
+    for bit (ragged column tails, odd chunk counts per slab, 1-4 column tiles)."""
+    print("[gpu] staged vs direct N=%d B=%d %s" % (N, B, prec), flush=True)
+    M = N * N - 1
+    H, gamma = wl.random_lindbladian(N, 7)
+    Q, K = lb.lindblad_prepare(ctx, dev(H), dev(gamma))
+    assert Q.shape[1] % 32 == 0 and Q.data_ptr() % 128 == 0
+    ldq2 = (M + 31) // 32 * 32 + (2 if prec == "fp64" else 4)
+    Qd = torch.zeros((M, ldq2), dtype=torch.float64, device="cuda")
+    Qd[:, :M] = Q[:, :M]
+    V0 = dev(wl.rng(11).standard_normal((B, M)) * 0.01)
+    outs = []
+    for QQ in (Q, Qd):
+        V = V0.clone()
+        if prec == "fp64":
+            lb.lindblad_propagate(ctx, QQ, K, V, 1e-3, 3)
+        else:
+            lb.lindblad_propagate(ctx, None, K, V, 1e-3, 3, precision=lb.FP32, Q32=lb.lindblad_q_to_f32(ctx, QQ))
+        outs.append(V)
+    assert torch.equal(outs[0], outs[1])
+    assert torch.isfinite(outs[0]).all()
+
+
 def test_propagate_batched_equals_single(lb, ctx, oracle):
     N = 13
     print("[gpu] batched N=%d" % N, flush=True)

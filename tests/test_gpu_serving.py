@@ -107,7 +107,7 @@ def test_budget_respected_and_admission(lb):
     # room for about two of the largest dense requests at a time
     N = 18
     M = N * N - 1
-    ldq = (M + 15) // 16 * 16
+    ldq = lb.default_ldq(M)
     budget = 2 * (8 * M * ldq + 8 * M) + 1024
     srv = lb.Server(0, budget_bytes=budget, slots=4, max_batch=2, max_N=32)
     tickets = [submit(srv, r) for r in reqs if r[0] == "dense"]
