@@ -700,8 +700,12 @@ __global__ void k_unpack(double* const* Vu, int64_t M, int B, int Bp, const doub
 
 // ---------------------------------------------------------------------------
 // One state: GEMV with the stage combine fused in (rows are complete per wave).
+// A wave owns R rows; lanes read 16 bytes each along the row, so one load
+// instruction covers 1 KB of a row (full lines when rows are 128-byte aligned,
+// then read with the nontemporal hint: Q is streamed once per stage). A row's
+// sum does not depend on R, so R only trades waves for loads in flight.
 // ---------------------------------------------------------------------------
-template <int R, bool ALIGNED>
+template <int R, bool ALIGNED, bool NT>
 __global__ __launch_bounds__(256) void k_gemv(const double* const* Qs, const double* const* Ks,
                                               double* const* Vs, int64_t M, int64_t ldq, double* Wall,
                                               int64_t wstride, int stage, double h) {
@@ -733,7 +737,9 @@ __global__ __launch_bounds__(256) void k_gemv(const double* const* Qs, const dou
             const double2 x = *reinterpret_cast<const double2*>(Xin + c);
 #pragma unroll
             for (int t = 0; t < R; ++t) {
-                const double2 q = *reinterpret_cast<const double2*>(qrow[t] + c);
+                lb_double2v q;
+                if (NT) q = __builtin_nontemporal_load((const lb_double2v __attribute__((address_space(1)))*)(qrow[t] + c));
+                else q = *reinterpret_cast<const lb_double2v*>(qrow[t] + c);
                 acc[t] = fma(q.x, x.x, acc[t]);
                 acc[t] = fma(q.y, x.y, acc[t]);
             }
@@ -1178,7 +1184,7 @@ struct Plan {
     size_t shm;
     int q_in_lds;
     bool aligned;
-    bool staged;  // LDS-staged GEMM: every Q and every row of Q 128-byte aligned
+    bool staged;  // every Q and every row of Q 128-byte aligned: LDS-staged GEMM, streaming GEMV loads
     const void** d;
     double *V, *Acc, *X, *Part, *W;
     float* X32;
@@ -1241,13 +1247,13 @@ static int plan_make(Plan& p, int R, int64_t M, int64_t ldq, int B, int precisio
 static int plan_bind(lb_ctx* c, Plan& p, char* base, const lb_prop_sys* sys) {
     const int R = p.R;
     const int64_t es = p.precision == LB_FP32 ? 4 : 8;
-    p.staged = p.kind == PATH_MFMA && (p.ldq * es) % 128 == 0;
+    p.staged = (p.kind == PATH_MFMA || p.kind == PATH_GEMV) && (p.ldq * es) % 128 == 0;
     for (int r = 0; r < R; ++r) {
         const void* qp = p.precision == LB_FP32 ? (const void*)sys[r].Q32 : (const void*)sys[r].Q;
         if (p.kind != PATH_SMALL && ((uintptr_t)qp) % 16) return lb_fail(LB_ERR_INVALID_ARG, "Q must be 16-byte aligned");
         if (((uintptr_t)qp) % 128) p.staged = false;
     }
-    if (p.staged) {
+    if (p.staged && p.kind == PATH_MFMA) {
         const int RT = p.tile.rows / 16, CT = p.Bp / 16;
         if (p.precision == LB_FP64 ? pick64s(RT, CT) == nullptr : pick32s(RT, CT) == nullptr) p.staged = false;
     }
@@ -1298,9 +1304,19 @@ static StageArgs stage_args(const Plan& p, double dt) {
 // One launch of the stage GEMM (MFMA path) or the stage GEMV (stage 1).
 static int plan_gemm(const Plan& p, hipStream_t s, int stage, double dt) {
     if (p.kind == PATH_GEMV) {
-        constexpr int RW = 8;
+        // rows per wave: as many as keep at least ~8192 waves in the launch
+        const int64_t rows_total = p.M * p.R;
+        const int RW = rows_total >= 8 * 8192 ? 8 : rows_total >= 4 * 8192 ? 4 : rows_total >= 2 * 8192 ? 2 : 1;
         const unsigned gx = lb_blocks((p.M + RW - 1) / RW, 4);
-        auto fn = p.aligned ? k_gemv<RW, true> : k_gemv<RW, false>;
+        typedef void (*gemv_fn)(const double* const*, const double* const*, double* const*, int64_t, int64_t,
+                                double*, int64_t, int, double);
+        gemv_fn fn;
+        if (!p.aligned) fn = RW == 8 ? k_gemv<8, false, false> : RW == 4 ? k_gemv<4, false, false>
+                           : RW == 2 ? k_gemv<2, false, false> : k_gemv<1, false, false>;
+        else if (p.staged) fn = RW == 8 ? k_gemv<8, true, true> : RW == 4 ? k_gemv<4, true, true>
+                              : RW == 2 ? k_gemv<2, true, true> : k_gemv<1, true, true>;
+        else fn = RW == 8 ? k_gemv<8, true, false> : RW == 4 ? k_gemv<4, true, false>
+                : RW == 2 ? k_gemv<2, true, false> : k_gemv<1, true, false>;
         hipLaunchKernelGGL(fn, dim3(gx, p.R), dim3(256), 0, s, (const double* const*)p.d,
                            (const double* const*)(p.d + 2 * p.R), (double* const*)(p.d + 3 * p.R), p.M, p.ldq, p.W,
                            p.wstride, stage, dt);

@@ -162,3 +162,17 @@ def wishart_kossakowski_device(N: int, seed: int, device="cuda", block: int = 40
     tr = out.diagonal().real.sum()
     out *= (N / tr)
     return out
+
+
+def random_dense_device(M: int, ldq: int, seed: int, scale: float = 1.0, device="cuda"):
+    """A dense M x ldq FP64 matrix with N(0, scale^2 / M) entries in columns < M
+    and zeros in the padding columns, drawn on the GPU (torch) for a given seed:
+    a stand-in operand for integrator tests at full size (the integrator does not
+    depend on Q being a Lindbladian)."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    Q = torch.zeros(M, ldq, dtype=torch.float64, device=device)
+    Q[:, :M] = torch.randn(M, M, dtype=torch.float64, device=device, generator=gen) * (scale / M ** 0.5)
+    return Q

@@ -237,6 +237,34 @@ def test_staged_gemm_equals_direct(lb, ctx, N, B, prec):
     assert torch.isfinite(outs[0]).all()
 
 
+def test_gemv_rows_per_wave_and_loads_invariant(lb, ctx, oracle):
+    """One state per system takes the GEMV path; its rows per wave grow with the
+    number of rows in the launch (1 alone, 4 for 16 systems here) and aligned
+    rows are streamed with the nontemporal hint. A row's sum is the same in
+    every variant, so all of them agree bit for bit, and with the oracle."""
+    N = 64
+    M = N * N - 1
+    print("[gpu] gemv variants N=%d" % N, flush=True)
+    H, gamma = wl.random_lindbladian(N, 12)
+    Q, K = lb.lindblad_prepare(ctx, dev(H), dev(gamma))
+    Qu = torch.zeros((M, M + 1), dtype=torch.float64, device="cuda")  # odd ldq: unaligned loads
+    Qu[:, :M] = Q[:, :M]
+    psi = wl.random_pure_states(N, 1, 4)
+    V0 = dev(np.array([oracle.expand(np.outer(p, p.conj())).real for p in psi]))
+    alone = V0.clone()
+    lb.lindblad_propagate(ctx, Q, K, alone, 1e-3, 4)
+    Vs = [V0.clone() for _ in range(16)]
+    lb.lindblad_propagate_batched(ctx, [Q] * 16, [K] * 16, Vs, 1e-3, 4)
+    unal = V0.clone()
+    lb.lindblad_propagate(ctx, Qu, K, unal, 1e-3, 4)
+    for V in Vs:
+        assert torch.equal(V, alone)
+    assert torch.equal(unal, alone)
+    Qo, Ko = oracle.prepare_dense(H, gamma)
+    Vo = oracle.rk4_dense(Qo, Ko, V0.cpu().numpy(), 1e-3, 4)
+    assert rel(alone.cpu().numpy(), Vo) < RTOL
+
+
 def test_propagate_batched_equals_single(lb, ctx, oracle):
     N = 13
     print("[gpu] batched N=%d" % N, flush=True)
