@@ -90,10 +90,12 @@ def parse():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle RK4 steps in the CPU sample")
-    ap.add_argument("--config", choices=["c1", "c2", "c3", "c4", "c5"], default="c4",
+    ap.add_argument("--config", choices=["c1", "c2", "c3", "c4", "c5", "c5r"], default="c4",
                     help="c4: the N=200 dense headline (default); c1: N=8 dense; c2: N=1000 sparse dimer; "
-                         "c3: N=100 dense, 64 states, FP64 vs FP32; c5: serving mix")
+                         "c3: N=100 dense, 64 states, FP64 vs FP32; c5: serving mix (prepare per request); "
+                         "c5r: serving mix on resident systems")
     ap.add_argument("--serving", action="store_true", help="same as --config c5")
+    ap.add_argument("--resident", action="store_true", help="with --serving: same as --config c5r")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for rocprofv3 --pmc runs: one plain 4 GiB copy, then the C4 stage GEMM on stand-in Q")
     ap.add_argument("--requests", type=int, default=2000)
@@ -106,23 +108,12 @@ def parse():
     return ap.parse_args()
 
 
-def serving(args):
-    """Serving mix: N uniform in {16, 32, 64, 96, 128}; 70% dense random
-    Lindbladians (gamma from a device-resident pool of 4 realizations per N),
-    30% static dimers (sparse path); each request is a preparation plus
-    `serve-steps` RK4 steps of one pure state. The same request list runs
-    through the continuous-batching server and through the plain path (one
-    slot, no batching: first-in first-out, one request at a time)."""
-    import threading
-
-    import numpy as np
-    import torch
-
-    import paper_1912_01491_amd as lb
-    from paper_1912_01491_amd import workloads as wl
-
+def _serving_inputs(args, ctx, lb, wl, torch, np):
+    """The serving mix of configuration C5: a device-resident pool of 4 dense
+    random Lindbladians per N (gamma drawn on the device for N >= 64), one
+    static dimer per N, and `requests` requests (N uniform in {16, 32, 64, 96,
+    128}, 70 % dense / 30 % dimer, one pure state each, seed 1000 + i)."""
     dev = torch.device("cuda", 0)
-    ctx = lb.Context(0)
     g = wl.rng(2024)
     Ns = [16, 32, 64, 96, 128]
     pool = {}
@@ -155,43 +146,100 @@ def serving(args):
         arrivals = np.zeros(len(reqs))
     torch.cuda.synchronize()
     log("%d requests ready (%d dense)" % (len(reqs), sum(r[0] == "dense" for r in reqs)))
+    return Ns, pool, dimers, reqs, arrivals
 
-    def run(slots, max_batch, label):
-        srv = lb.Server(0, budget_bytes=int(args.budget_gb * (1 << 30)), slots=slots, max_batch=max_batch,
-                        max_N=max(Ns))
-        tickets = [None] * len(reqs)
 
-        def feeder():
+def _serve(args, lb, np, reqs, arrivals, slots, max_batch, label, Ns, submit, setup=None):
+    """Runs the request list through one server: a feeder thread submits at the
+    arrival times, the main thread waits in order. Returns wall time, latencies
+    (completion - submission), stats and outputs."""
+    import threading
+
+    srv = lb.Server(0, budget_bytes=int(args.budget_gb * (1 << 30)), slots=slots, max_batch=max_batch,
+                    max_N=max(Ns))
+    ctxinfo = setup(srv) if setup else None
+    tickets = [None] * len(reqs)
+
+    def feeder():
+        t0 = time.perf_counter()
+        for i, req in enumerate(reqs):
+            d = arrivals[i] - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+            tickets[i] = submit(srv, ctxinfo, req)
+
+    t_start = time.perf_counter()
+    th = threading.Thread(target=feeder)
+    th.start()
+    th.join()
+    for i in range(len(reqs)):
+        srv.wait(tickets[i][0])
+        if (i + 1) % 100 == 0:
+            log("%s: %d of %d requests done after %.1f s" % (label, i + 1, len(reqs), time.perf_counter() - t_start))
+    wall = time.perf_counter() - t_start
+    lat = np.array([srv.times(t)[2] - srv.times(t)[0] for t, _ in tickets])
+    st = srv.stats()
+    outs = [v for _, v in tickets]
+    srv.close()
+    log("%s: %d requests in %.2f s (%.2f solves/s), p50 %.3f s, p99 %.3f s, %s"
+        % (label, len(reqs), wall, len(reqs) / wall, np.percentile(lat, 50), np.percentile(lat, 99), st))
+    return wall, lat, st, outs
+
+
+def serving(args):
+    """Serving mix (configuration C5): N uniform in {16, 32, 64, 96, 128}; 70%
+    dense random Lindbladians (gamma from a device-resident pool of 4
+    realizations per N), 30% static dimers (sparse path); each request is one
+    pure state integrated for `serve-steps` RK4 steps. Two modes:
+      * c5 (default): every request carries its Lindbladian and is prepared
+        (Q, K) and integrated by the server;
+      * c5r (--resident): the 25 distinct Lindbladians of the pool are
+        registered once (Q, K resident) and requests only carry states, so the
+        server integrates up to 16 requests on the same system per pass over Q.
+    The same request list runs through the continuous-batching server and
+    through the plain path (one slot, no batching: first-in first-out, one
+    request at a time); their results must agree bit for bit."""
+    import numpy as np
+    import torch
+
+    import paper_1912_01491_amd as lb
+    from paper_1912_01491_amd import workloads as wl
+
+    resident = args.config == "c5r" or args.resident
+    ctx = lb.Context(0)
+    Ns, pool, dimers, reqs, arrivals = _serving_inputs(args, ctx, lb, wl, torch, np)
+
+    if resident:
+        def setup(srv):
             t0 = time.perf_counter()
-            for i, (kind, N, r, V0) in enumerate(reqs):
-                d = arrivals[i] - (time.perf_counter() - t0)
-                if d > 0:
-                    time.sleep(d)
-                if kind == "dense":
-                    H, gamma = pool[(N, r)]
-                    tickets[i] = srv.submit_dense(H, gamma, V0, args.dt, args.serve_steps)
-                else:
-                    Hc, rates, Lc = dimers[N]
-                    tickets[i] = srv.submit_sparse(N, Hc, rates, Lc, V0, args.dt, args.serve_steps)
+            sids = {}
+            for (N, r), (H, gamma) in pool.items():
+                sids[("dense", N, r)] = srv.register_dense(H, gamma)
+            for N, (Hc, rates, Lc) in dimers.items():
+                sids[("sparse", N, 0)] = srv.register_sparse(N, Hc, rates, Lc)
+            log("registered %d systems in %.2f s" % (len(sids), time.perf_counter() - t0))
+            return sids
 
-        t_start = time.perf_counter()
-        th = threading.Thread(target=feeder)
-        th.start()
-        th.join()
-        for i in range(len(reqs)):
-            srv.wait(tickets[i][0])
-        wall = time.perf_counter() - t_start
-        lat = np.array([srv.times(t)[2] - srv.times(t)[0] for t, _ in tickets])
-        st = srv.stats()
-        outs = [v for _, v in tickets]
-        srv.close()
-        log("%s: %d requests in %.2f s (%.2f solves/s), p50 %.3f s, p99 %.3f s, %s"
-            % (label, len(reqs), wall, len(reqs) / wall, np.percentile(lat, 50), np.percentile(lat, 99), st))
-        return wall, lat, st, outs
+        def submit(srv, sids, req):
+            kind, N, r, V0 = req
+            return srv.submit_system(sids[(kind, N, r if kind == "dense" else 0)], V0, args.dt, args.serve_steps)
+    else:
+        setup = None
 
-    w_s, lat_s, st_s, out_s = run(args.slots, args.max_batch, "served")
-    w_p, lat_p, st_p, out_p = run(1, 1, "plain")
+        def submit(srv, _, req):
+            kind, N, r, V0 = req
+            if kind == "dense":
+                H, gamma = pool[(N, r)]
+                return srv.submit_dense(H, gamma, V0, args.dt, args.serve_steps)
+            Hc, rates, Lc = dimers[N]
+            return srv.submit_sparse(N, Hc, rates, Lc, V0, args.dt, args.serve_steps)
+
+    mb = max(args.max_batch, 16) if resident else args.max_batch
+    w_s, lat_s, st_s, out_s = _serve(args, lb, np, reqs, arrivals, args.slots, mb, "served", Ns, submit, setup)
+    w_p, lat_p, st_p, out_p = _serve(args, lb, np, reqs, arrivals, 1, 1, "plain", Ns, submit, setup)
     same = all(torch.equal(a, b) for a, b in zip(out_s, out_p))
+    mode = ("resident systems (25 registered Lindbladians, requests carry states only)" if resident
+            else "prepare per request")
     out = {
         "metric": "batched solves/s, p99 vs plain (serving mix)",
         "value": len(reqs) / w_s,
@@ -201,10 +249,10 @@ def serving(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "serving mix: %d requests, N uniform in %s, 70%% dense random / 30%% sparse dimer, "
-                               "prepare + %d RK4 steps dt=%g, one pure state each, %s arrivals"
-                               % (len(reqs), Ns, args.serve_steps, args.dt, args.arrival),
-                   "slots": args.slots, "max_batch": args.max_batch, "budget_gb": args.budget_gb,
-                   "rate": args.rate},
+                               "%d RK4 steps dt=%g, one pure state each, %s arrivals, %s"
+                               % (len(reqs), Ns, args.serve_steps, args.dt, args.arrival, mode),
+                   "slots": args.slots, "max_batch": mb, "budget_gb": args.budget_gb,
+                   "rate": args.rate, "resident": bool(resident)},
         "served": {"solves_per_s": len(reqs) / w_s, "p50_s": float(np.percentile(lat_s, 50)),
                    "p99_s": float(np.percentile(lat_s, 99)), "wall_s": w_s, "stats": st_s},
         "plain": {"solves_per_s": len(reqs) / w_p, "p50_s": float(np.percentile(lat_p, 50)),
@@ -454,7 +502,7 @@ def main():
         sys.exit(2)
     if args.pmc_probe:
         return pmc_probe(args)
-    if args.serving or args.config == "c5":
+    if args.serving or args.config in ("c5", "c5r"):
         return serving(args)
     if args.config in ("c1", "c2", "c3"):
         return {"c1": config_c1, "c2": config_c2, "c3": config_c3}[args.config](args)

@@ -248,11 +248,16 @@ int lindblad_tile_info(lb_ctx* ctx, int64_t M, int B, int precision, int* rows, 
 
 #define LB_REQ_DENSE 0
 #define LB_REQ_SPARSE 1
+#define LB_REQ_SYSTEM 2
 #define LB_REQ_MAX_JUMPS 8
+#define LB_SYSTEM_BATCH 16            /* states integrated together on one registered system */
 
 /* One request: prepare the ODE system of a Lindbladian of dimension N and
- * integrate B states for `steps` RK4 steps. All pointers are device memory
- * owned by the caller and must stay valid until the request completes. */
+ * integrate B states for `steps` RK4 steps (kinds LB_REQ_DENSE, LB_REQ_SPARSE),
+ * or integrate B <= LB_SYSTEM_BATCH states on a system registered with
+ * lindblad_server_register (kind LB_REQ_SYSTEM: only system, V0, Vout, B, dt,
+ * steps and precision are read). All pointers are device memory owned by the
+ * caller and must stay valid until the request completes. */
 typedef struct lb_request {
     int kind;                         /* LB_REQ_DENSE or LB_REQ_SPARSE */
     int N;
@@ -268,6 +273,7 @@ typedef struct lb_request {
     double dt;
     int64_t steps;
     int precision;                    /* dense: LB_FP64 or LB_FP32; sparse: LB_FP64 */
+    int64_t system;                   /* LB_REQ_SYSTEM: id from lindblad_server_register */
 } lb_request;
 
 typedef struct lb_server lb_server;
@@ -283,6 +289,22 @@ int lindblad_server_create(int device, size_t hbm_budget_bytes, int max_slots, i
 /* Queues a request (thread-safe; copies the descriptor, not the data).
  * LB_ERR_ADMISSION if its footprint can never fit in the budget. */
 int lindblad_server_submit(lb_server* srv, const lb_request* req, int64_t* ticket);
+/* Resident systems: many initial states integrated on the same Lindbladian
+ * (an ensemble of initial conditions). Prepares Q and K of the Lindbladian in
+ * `req` (kind LB_REQ_DENSE with H, gamma, precision; or LB_REQ_SPARSE with
+ * Hs, P, rates, L) once, synchronously, and keeps them in device memory
+ * (counted against the budget) until released. Queued LB_REQ_SYSTEM requests
+ * on the same system with the same dt, steps and precision are integrated
+ * together, up to LB_SYSTEM_BATCH states per pass over Q; each state's result
+ * is the same bit for bit whichever requests share its pass (dense systems
+ * always run the 16-state matrix-core path, sparse ones the CSR kernel, whose
+ * per-state arithmetic does not depend on the other states).
+ * LB_ERR_ADMISSION when the system cannot fit in the budget next to the
+ * systems already registered (it waits while running requests hold memory). */
+int lindblad_server_register(lb_server* srv, const lb_request* req, int64_t* system);
+/* Releases a registered system; its memory is freed once no queued or
+ * running request uses it. Further requests on it fail with LB_ERR_INVALID_ARG. */
+int lindblad_server_release(lb_server* srv, int64_t system);
 /* *done = 1 once the request has finished (successfully or not). */
 int lindblad_server_poll(lb_server* srv, int64_t ticket, int* done);
 /* Blocks until the request has finished; returns its status. */

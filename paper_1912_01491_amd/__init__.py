@@ -113,6 +113,8 @@ def signatures():
         "lindblad_server_times": [V, I64, V, V, V],
         "lindblad_server_stats": [V, V, V, V, V],
         "lindblad_server_destroy": [V],
+        "lindblad_server_register": [V, V, V],
+        "lindblad_server_release": [V, I64],
     }
 
 
@@ -444,7 +446,8 @@ class _Request(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("N", ctypes.c_int), ("H", ctypes.c_void_p), ("gamma", ctypes.c_void_p),
                 ("Hs", _CSR), ("P", ctypes.c_int), ("rates", ctypes.c_double * MAX_JUMPS),
                 ("L", _CSR * MAX_JUMPS), ("V0", ctypes.c_void_p), ("Vout", ctypes.c_void_p), ("B", ctypes.c_int),
-                ("dt", ctypes.c_double), ("steps", ctypes.c_int64), ("precision", ctypes.c_int)]
+                ("dt", ctypes.c_double), ("steps", ctypes.c_int64), ("precision", ctypes.c_int),
+                ("system", ctypes.c_int64)]
 
 
 class Server:
@@ -489,6 +492,48 @@ class Server:
         r.V0, r.Vout, r.B = V0.data_ptr(), Vout.data_ptr(), V0.shape[0]
         r.dt, r.steps, r.precision = float(dt), int(steps), FP64
         return self._submit(r, (H_csr, L_csrs, V0, Vout), Vout)
+
+    def register_dense(self, H, gamma, precision: int = FP64) -> int:
+        """Prepares Q and K of a dense Lindbladian once and keeps them resident;
+        returns the system id for submit_system()."""
+        import torch
+        _need(H, torch.complex128, "H")
+        _need(gamma, torch.complex128, "gamma")
+        r = _Request()
+        r.kind, r.N = 0, H.shape[0]
+        r.H, r.gamma, r.precision = H.data_ptr(), gamma.data_ptr(), int(precision)
+        sid = ctypes.c_int64()
+        _check(load().lindblad_server_register(self._h, ctypes.byref(r), ctypes.byref(sid)))
+        return sid.value
+
+    def register_sparse(self, N: int, H_csr, rates, L_csrs) -> int:
+        if len(L_csrs) > MAX_JUMPS:
+            raise ValueError("at most %d jump operators" % MAX_JUMPS)
+        r = _Request()
+        r.kind, r.N = 1, int(N)
+        r.Hs = _csr_struct(*H_csr)
+        r.P = len(L_csrs)
+        for p, (g, l) in enumerate(zip(rates, L_csrs)):
+            r.rates[p] = float(g)
+            r.L[p] = _csr_struct(*l)
+        r.precision = FP64
+        sid = ctypes.c_int64()
+        _check(load().lindblad_server_register(self._h, ctypes.byref(r), ctypes.byref(sid)))
+        return sid.value
+
+    def submit_system(self, system: int, V0, dt: float, steps: int, precision: int = FP64):
+        """Integrates the states V0 (B, M) on a registered system."""
+        import torch
+        _need(V0, torch.float64, "V0")
+        Vout = torch.empty_like(V0)
+        r = _Request()
+        r.kind, r.system = 2, int(system)
+        r.V0, r.Vout, r.B = V0.data_ptr(), Vout.data_ptr(), V0.shape[0]
+        r.dt, r.steps, r.precision = float(dt), int(steps), int(precision)
+        return self._submit(r, (V0, Vout), Vout)
+
+    def release(self, system: int):
+        _check(load().lindblad_server_release(self._h, int(system)))
 
     def _submit(self, r, keep, Vout):
         t = ctypes.c_int64()

@@ -86,3 +86,23 @@ def test_null_context_is_rejected_before_any_device_call():
     assert L.lindblad_prepare(None, 4, None, None, None, 0, None, 0) == -1
     assert L.lindblad_propagate(None, 15, None, None, 16, None, None, 1, ctypes.c_double(1e-3), 1, 0) == -1
     assert b"null context" in L.lb_last_error()
+
+
+def test_request_struct_layout_matches_header(tmp_path):
+    """The binding's request descriptor has the size and field offsets that a C
+    compiler gives the header's lb_request (host gcc, no device code)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "lindblad.h"\n'
+                   'int main(void) { printf("%zu %zu %zu %zu %zu\\n", sizeof(lb_request), '
+                   'offsetof(lb_request, L), offsetof(lb_request, V0), offsetof(lb_request, precision), '
+                   'offsetof(lb_request, system)); return 0; }\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    R = lb._Request
+    want = [ctypes.sizeof(R), R.L.offset, R.V0.offset, R.precision.offset, R.system.offset]
+    assert got == want

@@ -123,3 +123,94 @@ def test_budget_respected_and_admission(lb):
     assert e.value.code == -6
     srv.close()
     ctx.close()
+
+
+def _resident_setup(lb, seed=0):
+    g = wl.rng(seed)
+    ctx = lb.Context(0)
+    srv = lb.Server(0, budget_bytes=1 << 30, slots=3, max_batch=16, max_N=32)
+    systems = []  # (sid, kind, N, oracle inputs)
+    for N in (6, 12, 18):
+        H, gamma = wl.random_lindbladian(N, 300 + N)
+        sid = srv.register_dense(torch.from_numpy(H).cuda(), torch.from_numpy(gamma).cuda())
+        systems.append((sid, "dense", N, (H, gamma)))
+    for N in (9, 14):
+        H, rates, Ls = wl.dimer_model(N)
+        sid = srv.register_sparse(N, dcsr(H), rates, [dcsr(L) for L in Ls])
+        systems.append((sid, "sparse", N, (H, rates, Ls)))
+    reqs = []
+    for i in range(40):
+        sid, kind, N, _ = systems[int(g.integers(0, len(systems)))]
+        B = int(g.choice([1, 1, 2, 3]))
+        psis = wl.random_pure_states(N, B, 700 + i)
+        reqs.append((sid, N, lb.lb_expand_pure(ctx, torch.from_numpy(psis).cuda())))
+    torch.cuda.synchronize()
+    return ctx, srv, systems, reqs
+
+
+def test_resident_systems_mix_equals_alone(lb, oracle):
+    """Requests on registered systems: each result is the same bit for bit
+    whether it ran alone or packed with others into one pass over Q, and
+    matches the oracle (normwise 1e-10)."""
+    print("[gpu] resident systems: mix vs alone", flush=True)
+    ctx, srv, systems, reqs = _resident_setup(lb)
+    alone = []
+    for sid, N, V0 in reqs:
+        t, Vout = srv.submit_system(sid, V0, 1e-3, 40)
+        srv.wait(t)
+        alone.append(Vout)
+    tickets = [srv.submit_system(sid, V0, 1e-3, 40) for sid, N, V0 in reqs]
+    for t, _ in tickets:
+        srv.wait(t)
+    st = srv.stats()
+    assert st["batched_requests"] > 0
+    for (t, Vout), ref in zip(tickets, alone):
+        assert torch.equal(Vout, ref)
+    info = {sid: (kind, N, inp) for sid, kind, N, inp in systems}
+    checked = set()
+    for (sid, N, V0), (t, Vout) in zip(reqs, tickets):
+        if sid in checked:
+            continue
+        checked.add(sid)
+        kind, N, inp = info[sid]
+        M = N * N - 1
+        if kind == "dense":
+            Qo, Ko = oracle.prepare_dense(*inp)
+        else:
+            Qo, Ko = oracle.prepare_factored(inp[0], inp[1], inp[2], np.arange(M))
+        Vo = oracle.rk4_dense(Qo, Ko, V0.cpu().numpy(), 1e-3, 40)
+        err = np.abs(Vout.cpu().numpy() - Vo).max() / np.abs(Vo).max()
+        assert err < 1e-10, (kind, N, err)
+    print("[gpu] resident stats %s" % st, flush=True)
+    for sid, _, _, _ in systems:
+        srv.release(sid)
+    with pytest.raises(lb.LindbladError):
+        srv.submit_system(systems[0][0], reqs[0][2], 1e-3, 5)
+    srv.close()
+    ctx.close()
+
+
+def test_resident_release_while_queued_and_admission(lb):
+    ctx = lb.Context(0)
+    N = 18
+    M = N * N - 1
+    H, gamma = wl.random_lindbladian(N, 5)
+    one = 8 * M * lb.default_ldq(M) + 8 * M
+    stage = 2 * 16 * M * 8  # state staging of one pass
+    srv = lb.Server(0, budget_bytes=one + 2 * stage, slots=1, max_batch=16, max_N=32)
+    sid = srv.register_dense(torch.from_numpy(H).cuda(), torch.from_numpy(gamma).cuda())
+    # a second system of the same size cannot fit next to the first
+    with pytest.raises(lb.LindbladError) as e:
+        srv.register_dense(torch.from_numpy(H).cuda(), torch.from_numpy(gamma).cuda())
+    assert e.value.code == -6
+    V0 = torch.zeros((1, M), dtype=torch.float64, device="cuda")
+    tickets = [srv.submit_system(sid, V0, 1e-3, 20) for _ in range(6)]
+    srv.release(sid)  # freed once the queued requests have run
+    for t, _ in tickets:
+        srv.wait(t)
+    sid2 = srv.register_dense(torch.from_numpy(H).cuda(), torch.from_numpy(gamma).cuda())
+    t, V = srv.submit_system(sid2, V0, 1e-3, 20)
+    srv.wait(t)
+    assert torch.equal(V, tickets[0][1])
+    srv.close()
+    ctx.close()
