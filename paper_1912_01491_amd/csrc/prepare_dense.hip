@@ -23,7 +23,10 @@
 //   k_cdd      Cdd[a][c] = C(a,a,c,c)                              (N x N)
 //   k_gtheta   G, Theta = sum_jk gamma_jk F_j F_k, Z, Lambda = L(1) (N x N)
 //   k_expand   K_s = Tr(F_s Lambda)/N
-//   k_pairpair Q[pair][pair]       (the bulk: ~M^2 elements)
+//   k_fourset  Q[pair][pair] for disjoint pairs (the bulk: ~M^2 elements),
+//              mirror half into a transposed scratch
+//   k_mirror   transposes the mirror half into Q
+//   k_pp_shared Q[pair][pair] for pairs sharing a vertex
 //   k_drows    Q[D][pair]          (prefix sums over the diagonal)
 //   k_dcols    Q[pair][D]
 //   k_dd1/2    Q[D][D]
@@ -156,75 +159,208 @@ __global__ void k_gtheta(GV v, const double* H, double* Z, double* Lam) {
 // ---------------------------------------------------------------------------
 // Pair x pair block
 // ---------------------------------------------------------------------------
+// An element with row pair {u,v} (u < v) and column pair {x,y} (x < y) on four
+// distinct vertices needs two 2x2 blocks of gamma: B1 between the pairs {u,x}
+// and {v,y}, B2 between {u,y} and {v,x}. Grouping the elements by their vertex
+// set {a < b < c < d}: its three pairings {ab|cd}, {ac|bd}, {ad|bc} give three
+// blocks G1, G2, G3 of gamma (one of each Hermitian pair), and the six elements
+// whose row and column pairs partition the set each use two of them. k_fourset
+// gives every set to one lane (lanes along d: each block read and the three
+// "direct" elements, whose column pair holds d, are contiguous in memory) and
+// writes the three "mirror" elements (row pair holds d) transposed into a
+// scratch matrix T; k_mirror moves them to their place with a tiled
+// transpose. Every disjoint element is written once, gamma's blocks are read
+// once each. Elements whose pairs share a vertex are O(N^3) and come from
+// k_pp_shared.
 
-// Grid: blockIdx.x -> (u, v0) with v in [v0, v0+8), blockIdx.y -> (x, y0) with
-// y in [y0, y0+32). Thread (tv, ty) = (threadIdx.x / 32, threadIdx.x % 32)
-// owns s in {S,J}(u, v) x n in {S,J}(x, y): four elements of Q.
-__global__ __launch_bounds__(256) void k_pairpair(GV v, const double* Zm, const int2* uvt, const int2* xyt,
-                                                  double* Q, int64_t ldq) {
-    const int2 uv = uvt[blockIdx.x];
-    const int2 xy = xyt[blockIdx.y];
-    const int u = uv.x, vv = uv.y + (int)(threadIdx.x >> 5);
-    const int x = xy.x, y = xy.y + (int)(threadIdx.x & 31);
-    const int N = v.N;
-    if (vv >= N || y >= N) return;
-    const int64_t P = v.P;
+// A 2x2 block of gamma between a row pair and a column pair: entries (S,S),
+// (S,J), (J,S), (J,J).
+struct Blk {
+    cd ss, sa, as, aa;
+};
+
+__device__ __forceinline__ Blk blk_load(const GV& v, int64_t pr, int64_t pc) {
+    return Blk{gam(v, pr, pc), gam(v, pr, v.P + pc), gam(v, v.P + pr, pc), gam(v, v.P + pr, v.P + pc)};
+}
+
+// The block between the column pair and the row pair (gamma is Hermitian).
+__device__ __forceinline__ Blk blk_t(const Blk& b) { return Blk{cconj(b.ss), cconj(b.as), cconj(b.sa), cconj(b.aa)}; }
+
+// Four outputs (S|J row) x (S|J column) of the disjoint element ({u,v}, {x,y})
+// from B1 (pairs {u,x} x {v,y}) and B2 (pairs {u,y} x {v,x}).
+__device__ __forceinline__ Acc4 pp_disjoint(int u, int vv, int x, int y, const Blk& B1, const Blk& B2) {
+    // C(u,x,y,v) from B1; C(v,y,x,u) from B1^H; C(u,y,x,v) from B2; C(v,x,y,u) from B2^H
+    const cd c_uxyv = blk_c(B1.ss, B1.sa, B1.as, B1.aa, sgn(u, x), sgn(y, vv));
+    const cd c_vyxu = blk_c(cconj(B1.ss), cconj(B1.as), cconj(B1.sa), cconj(B1.aa), sgn(vv, y), sgn(x, u));
+    const cd c_uyxv = blk_c(B2.ss, B2.sa, B2.as, B2.aa, sgn(u, y), sgn(x, vv));
+    const cd c_vxyu = blk_c(cconj(B2.ss), cconj(B2.as), cconj(B2.sa), cconj(B2.aa), sgn(vv, x), sgn(y, u));
+    // (d,a) = (u,v): s_da = +1; (v,u): -1. (b,c) = (x,y): +1; (y,x): -1. Term C(a,b,c,d).
     Acc4 acc;
-    if (vv != x && vv != y && u != x && u != y) {
-        // B1 = gamma[{u,x}][{v,y}], read with row {u,x} fixed
-        const int64_t p_ux = lb_upair(N, u, x), p_vy = lb_upair(N, vv, y);
-        const cd b1ss = gam(v, p_ux, p_vy), b1sa = gam(v, p_ux, P + p_vy);
-        const cd b1as = gam(v, P + p_ux, p_vy), b1aa = gam(v, P + p_ux, P + p_vy);
-        // B2 = gamma[{u,y}][{v,x}]
-        const int64_t p_uy = lb_upair(N, u, y), p_vx = lb_upair(N, vv, x);
-        cd b2ss, b2sa, b2as, b2aa;
-        if (y > u) {  // conj(gamma[{v,x}][{u,y}]): column contiguous in y
-            b2ss = cconj(gam(v, p_vx, p_uy));
-            b2as = cconj(gam(v, p_vx, P + p_uy));
-            b2sa = cconj(gam(v, P + p_vx, p_uy));
-            b2aa = cconj(gam(v, P + p_vx, P + p_uy));
-        } else {
-            b2ss = gam(v, p_uy, p_vx);
-            b2sa = gam(v, p_uy, P + p_vx);
-            b2as = gam(v, P + p_uy, p_vx);
-            b2aa = gam(v, P + p_uy, P + p_vx);
-        }
-        // C(u,x,y,v) from B1; C(v,y,x,u) from B1^H; C(u,y,x,v) from B2; C(v,x,y,u) from B2^H
-        const cd c_uxyv = blk_c(b1ss, b1sa, b1as, b1aa, sgn(u, x), sgn(y, vv));
-        const cd c_vyxu = blk_c(cconj(b1ss), cconj(b1as), cconj(b1sa), cconj(b1aa), sgn(vv, y), sgn(x, u));
-        const cd c_uyxv = blk_c(b2ss, b2sa, b2as, b2aa, sgn(u, y), sgn(x, vv));
-        const cd c_vxyu = blk_c(cconj(b2ss), cconj(b2as), cconj(b2sa), cconj(b2aa), sgn(vv, x), sgn(y, u));
-        // (d,a) = (u,v): s_da = +1; (v,u): -1. (b,c) = (x,y): +1; (y,x): -1. Term C(a,b,c,d).
-        acc.add(+1, +1, c_vxyu);
-        acc.add(+1, -1, c_vyxu);
-        acc.add(-1, +1, c_uxyv);
-        acc.add(-1, -1, c_uyxv);
-    } else {
-        const int sv[2][2] = {{u, vv}, {vv, u}};  // (d, a)
-        const int nv[2][2] = {{x, y}, {y, x}};    // (b, c)
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 2; ++j) {
-                const int d = sv[i][0], a = sv[i][1], b = nv[j][0], c = nv[j][1];
-                acc.add(sgn(d, a), sgn(b, c), chat(v, a, b, c, d));
-            }
-        // Tr(F_s Z F_n): shared vertex d, a = s\d, b = n\d: e(d,a) Z_ab e(b,d)
-        // Tr(F_s F_n Z^+): shared vertex a, d = s\a, b = n\a: e(d,a) conj(Z_db) e(a,b)
-        const int sv2[2] = {u, vv}, nv2[2] = {x, y};
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 2; ++j) {
-                if (sv2[i] != nv2[j]) continue;
-                const int w = sv2[i], so = sv2[1 - i], no = nv2[1 - j];
-                acc.add(sgn(w, so), sgn(no, w), cload(Zm, (int64_t)so * N + no));
-                acc.add(sgn(so, w), sgn(w, no), cconj(cload(Zm, (int64_t)so * N + no)));
-            }
+    acc.add(+1, +1, c_vxyu);
+    acc.add(+1, -1, c_vyxu);
+    acc.add(-1, +1, c_uxyv);
+    acc.add(-1, -1, c_uyxv);
+    return acc;
+}
+
+__device__ __forceinline__ void pp_store(double* Q, int64_t ldq, int64_t P, int64_t rs, int64_t cn, const Acc4& acc) {
+    __builtin_nontemporal_store(0.5 * acc.ss, Q + rs * ldq + cn);
+    __builtin_nontemporal_store(0.5 * acc.sa, Q + rs * ldq + P + cn);
+    __builtin_nontemporal_store(0.5 * acc.as, Q + (P + rs) * ldq + cn);
+    __builtin_nontemporal_store(0.5 * acc.aa, Q + (P + rs) * ldq + P + cn);
+}
+
+// The element at Q[(rs, cn)] stored at T's transposed position: T[j][i] = Q[i][j].
+__device__ __forceinline__ void pp_store_t(double* T, int64_t ldt, int64_t P, int64_t rs, int64_t cn, const Acc4& acc) {
+    __builtin_nontemporal_store(0.5 * acc.ss, T + cn * ldt + rs);
+    __builtin_nontemporal_store(0.5 * acc.sa, T + (P + cn) * ldt + rs);
+    __builtin_nontemporal_store(0.5 * acc.as, T + cn * ldt + P + rs);
+    __builtin_nontemporal_store(0.5 * acc.aa, T + (P + cn) * ldt + P + rs);
+}
+
+// Block (blockIdx.x = pair index of {a,b}, blockIdx.y = chunk of kFourChunk
+// column pairs); lane q runs over the pairs {c,d} with b < c < d, which are the
+// pair indices from p(b+1, b+2) to P-1.
+constexpr int kFourChunk = 4096;
+
+__global__ __launch_bounds__(256) void k_fourset(GV v, const int2* pairs, double* Q, int64_t ldq, double* T,
+                                                 int64_t ldt) {
+    const int64_t pab = blockIdx.x;
+    const int a = pairs[pab].x, b = pairs[pab].y;
+    const int N = v.N;
+    if (b > N - 3) return;
+    const int64_t P = v.P;
+    const int64_t qb = lb_pair(N, b + 1, b + 2) + (int64_t)blockIdx.y * kFourChunk;
+    const int64_t qe = qb + kFourChunk < P ? qb + kFourChunk : P;
+    for (int64_t q = qb + threadIdx.x; q < qe; q += blockDim.x) {
+        const int c = pairs[q].x, d = pairs[q].y;
+        const int64_t pac = lb_pair(N, a, c), pbd = lb_pair(N, b, d);
+        const int64_t pbc = lb_pair(N, b, c), pad = lb_pair(N, a, d);
+        const Blk G1 = blk_load(v, pab, q);    // {a,b} x {c,d}
+        const Blk G2 = blk_load(v, pac, pbd);  // {a,c} x {b,d}
+        const Blk G3 = blk_load(v, pbc, pad);  // {b,c} x {a,d}
+        const Blk G2t = blk_t(G2), G3t = blk_t(G3);
+        pp_store(Q, ldq, P, pab, q, pp_disjoint(a, b, c, d, G2, G3t));
+        pp_store(Q, ldq, P, pac, pbd, pp_disjoint(a, c, b, d, G1, G3t));
+        pp_store(Q, ldq, P, pbc, pad, pp_disjoint(b, c, a, d, G1, G2t));
+        pp_store_t(T, ldt, P, q, pab, pp_disjoint(c, d, a, b, G2, G3));
+        pp_store_t(T, ldt, P, pbd, pac, pp_disjoint(b, d, a, c, G1, G3));
+        pp_store_t(T, ldt, P, pad, pbc, pp_disjoint(a, d, b, c, G1, G2));
     }
-    const int64_t rs = lb_pair(N, u, vv), cn = lb_pair(N, x, y);
-    double* q0 = Q + rs * ldq;
-    double* q1 = Q + (P + rs) * ldq;
-    __builtin_nontemporal_store(0.5 * acc.ss, q0 + cn);
-    __builtin_nontemporal_store(0.5 * acc.sa, q0 + P + cn);
-    __builtin_nontemporal_store(0.5 * acc.as, q1 + cn);
-    __builtin_nontemporal_store(0.5 * acc.aa, q1 + P + cn);
+}
+
+// Q[i][j] = T[j][i] for i, j < 2P whose pairs are disjoint with the larger
+// vertex in the row pair (the mirror elements). 64 x 64 tiles through LDS,
+// 16-byte loads along T's rows and 16-byte stores along Q's rows; the tile's
+// row and column pairs are read once into LDS. Tiles whose rows' largest
+// vertex never exceeds its columns' smallest are skipped (ymax/ymin: per run
+// of 64 indices).
+constexpr int kMirrorTile = 64;
+
+__global__ __launch_bounds__(256) void k_mirror(const double* T, int64_t ldt, const int2* pairs, const int* ymin,
+                                                const int* ymax, int64_t P, double* Q, int64_t ldq) {
+    __shared__ double tile[kMirrorTile][kMirrorTile + 1];
+    __shared__ int2 rp[kMirrorTile], cp[kMirrorTile];
+    const int64_t ti = blockIdx.x, tj = blockIdx.y;  // row tile of Q, column tile of Q
+    if (ymax[ti] <= ymin[tj]) return;
+    const int64_t n2 = 2 * P;
+    const int64_t i0 = ti * kMirrorTile, j0 = tj * kMirrorTile;
+    const int t = threadIdx.x;
+    if (t < kMirrorTile) {
+        const int64_t i = i0 + t;
+        rp[t] = i < n2 ? pairs[i < P ? i : i - P] : make_int2(-1, -1);
+    } else if (t < 2 * kMirrorTile) {
+        const int64_t j = j0 + t - kMirrorTile;
+        cp[t - kMirrorTile] = j < n2 ? pairs[j < P ? j : j - P] : make_int2(-2, 1 << 30);  // never below a row pair
+    }
+    __syncthreads();
+    // mirror element: disjoint pairs, larger vertex in the row pair; the padding
+    // pairs (row: upper vertex -1, column: upper vertex 2^30) never qualify, so
+    // nothing past row or column 2P - 1 of T or Q is touched
+    auto mirror = [](int2 R, int2 C) { return R.x != C.x && R.x != C.y && R.y != C.x && R.y != C.y && R.y > C.y; };
+    const int c2 = 2 * (t & 31), r0 = t >> 5;  // column pair within a row, first row
+    // T rows j0.. (Q columns), two consecutive i per thread; only mirror elements
+    // are loaded, so lines of T outside the mirror region are not fetched
+    for (int r = r0; r < kMirrorTile; r += 8) {
+        const int64_t j = j0 + r, i = i0 + c2;
+        const int2 C = cp[r];
+        const bool m0 = mirror(rp[c2], C), m1 = mirror(rp[c2 + 1], C);
+        const double* src = T + j * ldt + i;
+        double2 x = make_double2(0.0, 0.0);
+        if (m0 && m1 && (((uintptr_t)src) & 15) == 0) {
+            x = *reinterpret_cast<const double2*>(src);
+        } else {
+            if (m0) x.x = src[0];
+            if (m1) x.y = src[1];
+        }
+        tile[r][c2] = x.x;
+        tile[r][c2 + 1] = x.y;
+    }
+    __syncthreads();
+    for (int r = r0; r < kMirrorTile; r += 8) {
+        const int64_t i = i0 + r, j = j0 + c2;
+        if (i >= n2 || j >= n2) continue;
+        const int2 R = rp[r];
+        const bool m0 = mirror(R, cp[c2]);
+        const bool m1 = mirror(R, cp[c2 + 1]);
+        double* q = Q + i * ldq + j;
+        if (m0 && m1 && (((uintptr_t)q) & 15) == 0) {
+            *reinterpret_cast<double2*>(q) = make_double2(tile[c2][r], tile[c2 + 1][r]);
+        } else {
+            if (m0) q[0] = tile[c2][r];
+            if (m1) q[1] = tile[c2 + 1][r];
+        }
+    }
+}
+
+// Elements whose row pair {u,v} and column pair share a vertex (including the
+// diagonal element): thread (row pair, k) with column pair {u, w_k} for
+// k < N-1 (w over the vertices other than u) and {v, w} for the N-2 vertices
+// w other than u and v.
+__global__ __launch_bounds__(256) void k_pp_shared(GV v, const double* Zm, const int2* pairs, double* Q,
+                                                   int64_t ldq) {
+    const int N = v.N;
+    const int64_t P = v.P;
+    const int64_t per = 2 * N - 3;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= P * per) return;
+    const int64_t rs = t / per;
+    const int k = (int)(t % per);
+    const int u = pairs[rs].x, vv = pairs[rs].y;
+    int p1, w;
+    if (k < N - 1) {
+        p1 = u;
+        w = k < u ? k : k + 1;
+    } else {
+        p1 = vv;
+        w = k - (N - 1);
+        if (w >= u) ++w;  // u < vv: skip u, then vv
+        if (w >= vv) ++w;
+    }
+    const int x = p1 < w ? p1 : w, y = p1 < w ? w : p1;
+    Acc4 acc;
+    const int sv[2][2] = {{u, vv}, {vv, u}};  // (d, a)
+    const int nv[2][2] = {{x, y}, {y, x}};    // (b, c)
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            const int d = sv[i][0], a = sv[i][1], b = nv[j][0], c = nv[j][1];
+            acc.add(sgn(d, a), sgn(b, c), chat(v, a, b, c, d));
+        }
+    // Tr(F_s Z F_n): shared vertex d, a = s\d, b = n\d: e(d,a) Z_ab e(b,d)
+    // Tr(F_s F_n Z^+): shared vertex a, d = s\a, b = n\a: e(d,a) conj(Z_db) e(a,b)
+    const int sv2[2] = {u, vv}, nv2[2] = {x, y};
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            if (sv2[i] != nv2[j]) continue;
+            const int wv = sv2[i], so = sv2[1 - i], no = nv2[1 - j];
+            acc.add(sgn(wv, so), sgn(no, wv), cload(Zm, (int64_t)so * N + no));
+            acc.add(sgn(so, wv), sgn(wv, no), cconj(cload(Zm, (int64_t)so * N + no)));
+        }
+    const int64_t cn = lb_pair(N, x, y);
+    Q[rs * ldq + cn] = 0.5 * acc.ss;
+    Q[rs * ldq + P + cn] = 0.5 * acc.sa;
+    Q[(P + rs) * ldq + cn] = 0.5 * acc.as;
+    Q[(P + rs) * ldq + P + cn] = 0.5 * acc.aa;
 }
 
 // ---------------------------------------------------------------------------
@@ -517,13 +653,12 @@ int lb_impl_prepare_dense(lb_ctx* c, int N, const double* H, const double* gamma
                           double* K) {
     const int64_t M = (int64_t)N * N - 1;
     const int64_t P = lb_npairs(N);
-    // tile lists for the pair x pair kernel and the pair list
-    std::vector<int2> uvt, xyt;
-    for (int u = 0; u + 1 < N; ++u)
-        for (int v0 = u + 1; v0 < N; v0 += 8) uvt.push_back(make_int2(u, v0));
-    for (int x = 0; x + 1 < N; ++x)
-        for (int y0 = x + 1; y0 < N; y0 += 32) xyt.push_back(make_int2(x, y0));
-    if (xyt.size() > 65535) return lb_fail(LB_ERR_UNSUPPORTED, "N=%d too large for the pair grid", N);
+    // pair list, and per run of 64 pair-block indices (0..2P-1) the smallest and
+    // largest upper vertex, for the mirror transpose's tile skipping
+    const int64_t n2 = 2 * P;
+    const int64_t nt = (n2 + kMirrorTile - 1) / kMirrorTile;
+    const int64_t ldt = (n2 + 31) / 32 * 32;
+    if (nt > 65535) return lb_fail(LB_ERR_UNSUPPORTED, "N=%d too large for the mirror grid", N);
     // workspace layout
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -536,27 +671,32 @@ int lb_impl_prepare_dense(lb_ctx* c, int N, const double* H, const double* gamma
     const size_t o_z = take(sizeof(double) * 2 * (size_t)N * N);
     const size_t o_lam = take(sizeof(double) * 2 * (size_t)N * N);
     const size_t o_t = take(sizeof(double) * 2 * (size_t)N * N);
-    const size_t o_uv = take(sizeof(int2) * uvt.size());
-    const size_t o_xy = take(sizeof(int2) * xyt.size());
-    const size_t o_pairs = take(sizeof(int2) * (size_t)P);
+    const size_t o_pairs = take(sizeof(int2) * (size_t)P + sizeof(int) * 2 * (size_t)nt + 8);  // pairs, ymin, ymax
+    const size_t o_mt = take(sizeof(double) * (size_t)n2 * ldt);
     int rc = lb_ws_reserve(c, off);
     if (rc) return rc;
-    const size_t hb = sizeof(int2) * (uvt.size() + xyt.size() + P);
+    const size_t hb = sizeof(int2) * P + sizeof(int) * 2 * nt;
     rc = lb_host_reserve(c, hb);
     if (rc) return rc;
     char* ws = (char*)c->ws;
     int2* h = (int2*)c->host;
     // the pinned staging buffer may still be read by an earlier copy on this stream
     LB_HIP(hipStreamSynchronize(c->stream));
-    size_t hp = 0;
-    for (auto t : uvt) h[hp++] = t;
-    for (auto t : xyt) h[hp++] = t;
+    int64_t hp = 0;
     for (int a = 0; a + 1 < N; ++a)
         for (int b = a + 1; b < N; ++b) h[hp++] = make_int2(a, b);
-    LB_HIP(hipMemcpyAsync(ws + o_uv, h, sizeof(int2) * uvt.size(), hipMemcpyHostToDevice, c->stream));
-    LB_HIP(hipMemcpyAsync(ws + o_xy, h + uvt.size(), sizeof(int2) * xyt.size(), hipMemcpyHostToDevice, c->stream));
-    LB_HIP(hipMemcpyAsync(ws + o_pairs, h + uvt.size() + xyt.size(), sizeof(int2) * P, hipMemcpyHostToDevice,
-                          c->stream));
+    int* hy = (int*)(h + P);
+    for (int64_t t = 0; t < nt; ++t) {
+        int lo = N, hi = -1;
+        for (int64_t i = kMirrorTile * t; i < kMirrorTile * (t + 1) && i < n2; ++i) {
+            const int y = h[i < P ? i : i - P].y;
+            lo = y < lo ? y : lo;
+            hi = y > hi ? y : hi;
+        }
+        hy[t] = lo;
+        hy[nt + t] = hi;
+    }
+    LB_HIP(hipMemcpyAsync(ws + o_pairs, h, hb, hipMemcpyHostToDevice, c->stream));
 
     GV v;
     v.g = gamma;
@@ -568,9 +708,10 @@ int lb_impl_prepare_dense(lb_ctx* c, int N, const double* H, const double* gamma
     double* Zm = (double*)(ws + o_z);
     double* Lam = (double*)(ws + o_lam);
     double* T = (double*)(ws + o_t);
-    const int2* uvd = (const int2*)(ws + o_uv);
-    const int2* xyd = (const int2*)(ws + o_xy);
     const int2* pd = (const int2*)(ws + o_pairs);
+    const int* ymin = (const int*)(ws + o_pairs + sizeof(int2) * P);
+    const int* ymax = ymin + nt;
+    double* MT = (double*)(ws + o_mt);
     hipStream_t s = c->stream;
 
     hipLaunchKernelGGL(k_pt, dim3(lb_blocks(M, 256)), dim3(256), 0, s, v, (double*)(ws + o_pt));
@@ -582,8 +723,16 @@ int lb_impl_prepare_dense(lb_ctx* c, int N, const double* H, const double* gamma
     hipLaunchKernelGGL(k_expand, dim3(lb_blocks(M, 256)), dim3(256), 0, s, N, 1, (const double*)Lam, K, 1.0 / N);
     LB_CHECK_LAUNCH();
     if (P > 0) {
-        hipLaunchKernelGGL(k_pairpair, dim3((unsigned)uvt.size(), (unsigned)xyt.size()), dim3(256), 0, s, v,
-                           (const double*)Zm, uvd, xyd, Q, ldq);
+        if (N >= 4) {
+            hipLaunchKernelGGL(k_fourset, dim3((unsigned)P, (unsigned)((P + kFourChunk - 1) / kFourChunk)), dim3(256),
+                               0, s, v, pd, Q, ldq, MT, ldt);
+            LB_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_mirror, dim3((unsigned)nt, (unsigned)nt), dim3(256), 0, s, (const double*)MT, ldt, pd,
+                               ymin, ymax, P, Q, ldq);
+            LB_CHECK_LAUNCH();
+        }
+        hipLaunchKernelGGL(k_pp_shared, dim3(lb_blocks(P * (2 * N - 3), 256)), dim3(256), 0, s, v, (const double*)Zm,
+                           pd, Q, ldq);
         LB_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_drows, dim3(lb_blocks(P, 64)), dim3(64), 0, s, v, (const double*)Zm, pd, Q, ldq);
         LB_CHECK_LAUNCH();
