@@ -313,31 +313,10 @@ __global__ __launch_bounds__(256) void k_mirror(const double* T, int64_t ldt, co
     }
 }
 
-// Elements whose row pair {u,v} and column pair share a vertex (including the
-// diagonal element): thread (row pair, k) with column pair {u, w_k} for
-// k < N-1 (w over the vertices other than u) and {v, w} for the N-2 vertices
-// w other than u and v.
-__global__ __launch_bounds__(256) void k_pp_shared(GV v, const double* Zm, const int2* pairs, double* Q,
-                                                   int64_t ldq) {
+// Elements whose row pair {u,v} and column pair {x,y} share a vertex
+// (including the diagonal element u = x, v = y): the general form.
+__device__ __forceinline__ Acc4 pp_shared(const GV& v, const double* Zm, int u, int vv, int x, int y) {
     const int N = v.N;
-    const int64_t P = v.P;
-    const int64_t per = 2 * N - 3;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= P * per) return;
-    const int64_t rs = t / per;
-    const int k = (int)(t % per);
-    const int u = pairs[rs].x, vv = pairs[rs].y;
-    int p1, w;
-    if (k < N - 1) {
-        p1 = u;
-        w = k < u ? k : k + 1;
-    } else {
-        p1 = vv;
-        w = k - (N - 1);
-        if (w >= u) ++w;  // u < vv: skip u, then vv
-        if (w >= vv) ++w;
-    }
-    const int x = p1 < w ? p1 : w, y = p1 < w ? w : p1;
     Acc4 acc;
     const int sv[2][2] = {{u, vv}, {vv, u}};  // (d, a)
     const int nv[2][2] = {{x, y}, {y, x}};    // (b, c)
@@ -356,11 +335,43 @@ __global__ __launch_bounds__(256) void k_pp_shared(GV v, const double* Zm, const
             acc.add(sgn(wv, so), sgn(no, wv), cload(Zm, (int64_t)so * N + no));
             acc.add(sgn(so, wv), sgn(wv, no), cconj(cload(Zm, (int64_t)so * N + no)));
         }
-    const int64_t cn = lb_pair(N, x, y);
+    return acc;
+}
+
+__device__ __forceinline__ void pp_store_plain(double* Q, int64_t ldq, int64_t P, int64_t rs, int64_t cn,
+                                               const Acc4& acc) {
     Q[rs * ldq + cn] = 0.5 * acc.ss;
     Q[rs * ldq + P + cn] = 0.5 * acc.sa;
     Q[(P + rs) * ldq + cn] = 0.5 * acc.as;
     Q[(P + rs) * ldq + P + cn] = 0.5 * acc.aa;
+}
+
+// Elements of pairs sharing a vertex, grouped by vertex set {a<b<c}: its
+// pairs ab, ac, bc give the six off-diagonal elements, which read the same
+// three gamma blocks and Pt entries. One wavefront per pair {a,b}, lanes
+// along c; lane 0 also writes the pair's diagonal element. All six values
+// are formed before any store, so repeated reads need not be issued twice.
+__global__ __launch_bounds__(256) void k_pp_shared(GV v, const double* Zm, const int2* pairs, double* Q,
+                                                   int64_t ldq) {
+    const int N = v.N;
+    const int64_t P = v.P;
+    const int64_t pab = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (pab >= P) return;
+    const int a = pairs[pab].x, b = pairs[pab].y;
+    if (lane == 0) pp_store_plain(Q, ldq, P, pab, pab, pp_shared(v, Zm, a, b, a, b));
+    for (int c = b + 1 + lane; c < N; c += 64) {
+        const int64_t pac = lb_pair(N, a, c), pbc = lb_pair(N, b, c);
+        const Acc4 e1 = pp_shared(v, Zm, a, b, a, c), e2 = pp_shared(v, Zm, a, b, b, c);
+        const Acc4 e3 = pp_shared(v, Zm, a, c, a, b), e4 = pp_shared(v, Zm, a, c, b, c);
+        const Acc4 e5 = pp_shared(v, Zm, b, c, a, b), e6 = pp_shared(v, Zm, b, c, a, c);
+        pp_store_plain(Q, ldq, P, pab, pac, e1);
+        pp_store_plain(Q, ldq, P, pab, pbc, e2);
+        pp_store_plain(Q, ldq, P, pac, pab, e3);
+        pp_store_plain(Q, ldq, P, pac, pbc, e4);
+        pp_store_plain(Q, ldq, P, pbc, pab, e5);
+        pp_store_plain(Q, ldq, P, pbc, pac, e6);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -731,8 +742,8 @@ int lb_impl_prepare_dense(lb_ctx* c, int N, const double* H, const double* gamma
                                ymin, ymax, P, Q, ldq);
             LB_CHECK_LAUNCH();
         }
-        hipLaunchKernelGGL(k_pp_shared, dim3(lb_blocks(P * (2 * N - 3), 256)), dim3(256), 0, s, v, (const double*)Zm,
-                           pd, Q, ldq);
+        hipLaunchKernelGGL(k_pp_shared, dim3(lb_blocks(P * 64, 256)), dim3(256), 0, s, v, (const double*)Zm, pd, Q,
+                           ldq);
         LB_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_drows, dim3(lb_blocks(P, 64)), dim3(64), 0, s, v, (const double*)Zm, pd, Q, ldq);
         LB_CHECK_LAUNCH();
