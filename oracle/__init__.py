@@ -75,6 +75,13 @@ def _L():
         lib.or_rk4_dense.argtypes = [i64, P, P, P, ctypes.c_int, ctypes.c_double, i64]
         lib.or_rk4_csr.restype = None
         lib.or_rk4_csr.argtypes = [i64, P, P, P, P, P, ctypes.c_int, ctypes.c_double, i64]
+        D = ctypes.c_double
+        lib.or_drive.restype = D
+        lib.or_drive.argtypes = [D, D, D, D]
+        lib.or_drive_left.restype = D
+        lib.or_drive_left.argtypes = [D, D, D, D]
+        lib.or_rk4_drive.restype = None
+        lib.or_rk4_drive.argtypes = [i64, P, P, P, P, ctypes.c_int, D, i64, D, D, D, D]
         lib.or_num_threads.restype = ctypes.c_int
         lib.or_num_threads.argtypes = []
         _lib = lib
@@ -203,6 +210,30 @@ def rk4_dense(Q: np.ndarray, K: np.ndarray, V: np.ndarray, dt: float, steps: int
         V = V[None, :]
     M = Q.shape[0]
     _L().or_rk4_dense(M, _p(Q), _p(K), _p(V), V.shape[0], float(dt), int(steps))
+    return V
+
+
+def drive(t: float, E: float, A: float, T: float) -> float:
+    """The square-wave modulation eps(t) = E + A Theta(t) of the driven dimer."""
+    return float(_L().or_drive(float(t), float(E), float(A), float(T)))
+
+
+def drive_left(t: float, E: float, A: float, T: float) -> float:
+    """eps(t-), the limit from the left (at a switch: the half period ending there)."""
+    return float(_L().or_drive_left(float(t), float(E), float(A), float(T)))
+
+
+def rk4_drive(Q0, Q1, K, V, dt: float, steps: int, t0: float, E: float, A: float, T: float) -> np.ndarray:
+    """Classic RK4 on dv/dt = (Q0 + eps(t) Q1) v + K (dense Q0, Q1); V is (B, M)."""
+    Q0 = _c(Q0, np.float64)
+    Q1 = _c(Q1, np.float64)
+    K = _c(K, np.float64)
+    V = np.array(V, dtype=np.float64, order="C", copy=True)
+    if V.ndim == 1:
+        V = V[None, :]
+    M = Q0.shape[0]
+    _L().or_rk4_drive(M, _p(Q0), _p(Q1), _p(K), _p(V), V.shape[0], float(dt), int(steps), float(t0), float(E),
+                      float(A), float(T))
     return V
 
 

@@ -791,6 +791,82 @@ void or_rk4_csr(long M, const int64_t* rowptr, const int64_t* col, const double*
     rk4_generic(M, B, dt, steps, V, mv_csr, &c);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Periodically driven dimer (Sec. 3, Eq. (16)): H(t) = H0 + eps(t) H1 with   */
+/* the square wave eps(t) = E + A Theta(t), Theta = +1 for 0 <= t < T/2 and   */
+/* -1 for T/2 <= t < T, period T. Q_H is linear in H and K does not involve H */
+/* (L(1) has no Hamiltonian part), so the ODE of Eq. (10) becomes             */
+/*     dv/dt = (Q0 + eps(t) Q1) v + K,                                        */
+/* Q0 from (H0, dissipator), Q1 = Q_H of H1 alone. Classic RK4 evaluates eps  */
+/* at the stage times t_k, t_k + dt/2, t_k + dt (t_k = t0 + k dt) as seen from */
+/* inside the step: the first two from the right, the last as the limit from */
+/* the left, so a step that ends on a switch integrates one constant system.  */
+/* ------------------------------------------------------------------------ */
+
+double or_drive(double t, double E, double A, double T) {
+    double r = fmod(t, T);
+    if (r < 0) r += T;
+    return r < 0.5 * T ? E + A : E - A;
+}
+
+/* The limit from the left, eps(t-): at a switch time it is the value of the   */
+/* half period that ends there.                                               */
+double or_drive_left(double t, double E, double A, double T) {
+    double r = fmod(t, T);
+    if (r <= 0) r += T;
+    return r <= 0.5 * T ? E + A : E - A;
+}
+
+/* t0 + (k + c) dt, c in {0, 1/2, 1}: one product and one sum */
+static double stage_time(double t0, long k, double c, double dt) {
+    const double kc = (double)k + c;
+    const double p = kc * dt;
+    return t0 + p;
+}
+
+/* y = (Q0 + e Q1) x + K for dense M x M Q0, Q1; B states */
+static void matvec_drive(long M, const double* Q0, const double* Q1, double e, const double* K, const double* x,
+                         double* y, int B) {
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < M; i++) {
+        const double* q0 = Q0 + (size_t)i * M;
+        const double* q1 = Q1 + (size_t)i * M;
+        for (int b = 0; b < B; b++) {
+            const double* xb = x + (size_t)b * M;
+            double a0 = K[i], a1 = 0.0;
+            for (long j = 0; j < M; j++) {
+                a0 += q0[j] * xb[j];
+                a1 += q1[j] * xb[j];
+            }
+            y[(size_t)b * M + i] = a0 + e * a1;
+        }
+    }
+}
+
+void or_rk4_drive(long M, const double* Q0, const double* Q1, const double* K, double* V, int B, double dt,
+                  long steps, double t0, double E, double A, double T) {
+    size_t n = (size_t)M * B;
+    double* k1 = malloc(sizeof(double) * n);
+    double* k2 = malloc(sizeof(double) * n);
+    double* k3 = malloc(sizeof(double) * n);
+    double* k4 = malloc(sizeof(double) * n);
+    double* x = malloc(sizeof(double) * n);
+    for (long st = 0; st < steps; st++) {
+        const double e1 = or_drive(stage_time(t0, st, 0.0, dt), E, A, T);
+        const double e2 = or_drive(stage_time(t0, st, 0.5, dt), E, A, T);
+        const double e4 = or_drive_left(stage_time(t0, st, 1.0, dt), E, A, T);
+        matvec_drive(M, Q0, Q1, e1, K, V, k1, B);
+        for (size_t t = 0; t < n; t++) x[t] = V[t] + 0.5 * dt * k1[t];
+        matvec_drive(M, Q0, Q1, e2, K, x, k2, B);
+        for (size_t t = 0; t < n; t++) x[t] = V[t] + 0.5 * dt * k2[t];
+        matvec_drive(M, Q0, Q1, e2, K, x, k3, B);
+        for (size_t t = 0; t < n; t++) x[t] = V[t] + dt * k3[t];
+        matvec_drive(M, Q0, Q1, e4, K, x, k4, B);
+        for (size_t t = 0; t < n; t++) V[t] += dt / 6.0 * (k1[t] + 2.0 * k2[t] + 2.0 * k3[t] + k4[t]);
+    }
+    free(k1); free(k2); free(k3); free(k4); free(x);
+}
+
 int or_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

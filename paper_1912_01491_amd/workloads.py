@@ -121,6 +121,33 @@ def dimer_model(N: int, J: float = 1.0, U: float = 0.5, eps: float = 0.0, gamma:
     return H, np.array([gamma / max(N - 1, 1)]), [L]
 
 
+def dimer_jump_sync(N: int) -> np.ndarray:
+    """L = (b1^+ + b2^+)(b1 - b2) = n1 - n2 + b2^+ b1 - b1^+ b2 on |n, N-1-n>:
+    traceless and not Hermitian (the synchronising jump of the rocked dimer)."""
+    nb = N - 1
+    n = np.arange(N, dtype=np.float64)
+    L = np.zeros((N, N), np.complex128)
+    L[np.arange(N), np.arange(N)] = n - (nb - n)
+    # b1^+ b2 |n, nb-n> = sqrt((n+1)(nb-n)) |n+1, nb-n-1>
+    up = np.sqrt((n[:-1] + 1) * (nb - n[:-1]))
+    L[np.arange(1, N), np.arange(N - 1)] -= up
+    # b2^+ b1 |n, nb-n> = sqrt(n (nb-n+1)) |n-1, nb-n+1>
+    L[np.arange(N - 1), np.arange(1, N)] += up
+    return L
+
+
+def rocked_dimer_model(N: int, J: float = -1.0, U: float = 2.2, gamma: float = 0.1):
+    """The periodically rocked dimer of the sparse test model with its published
+    parameters: (H0, H1, rates, [L]) with H(t) = H0 + eps(t) H1, H0 the hopping
+    and interaction part, H1 = n2 - n1, one jump L = (b1^+ + b2^+)(b1 - b2) at
+    rate gamma/(N-1). The drive eps(t) (E = -1, A = -1.5, T = 2 pi) is applied
+    by the integrator."""
+    H0 = dimer_hamiltonian(N, J, U, 0.0)
+    n1 = np.arange(N, dtype=np.float64)
+    H1 = np.diag((N - 1 - n1) - n1).astype(np.complex128)
+    return H0, H1, np.array([gamma / max(N - 1, 1)]), [dimer_jump_sync(N)]
+
+
 def to_csr(A: np.ndarray):
     """Dense N x N complex -> (rowptr int64, col int64, val complex128), zeros dropped."""
     A = np.asarray(A)
