@@ -820,7 +820,7 @@ double or_drive_left(double t, double E, double A, double T) {
 /* t0 + (k + c) dt, c in {0, 1/2, 1}: one product and one sum */
 static double stage_time(double t0, long k, double c, double dt) {
     const double kc = (double)k + c;
-    const double p = kc * dt;
+    volatile double p = kc * dt; /* rounded on its own, never fused with the sum */
     return t0 + p;
 }
 

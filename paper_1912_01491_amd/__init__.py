@@ -24,7 +24,7 @@ __all__ = [
     "lb_expand", "lb_expand_pure", "lb_reconstruct",
     "lindblad_prepare", "lindblad_q_to_f32", "lindblad_propagate", "lindblad_propagate_batched",
     "lindblad_propagate_graph", "lindblad_propagate_csr", "lindblad_prepare_sparse",
-    "lindblad_autotune", "lindblad_tile_info", "lindblad_set_tile", "lindblad_time_stage", "Server",
+    "lindblad_propagate_csr_drive", "lindblad_autotune", "lindblad_tile_info", "lindblad_set_tile", "lindblad_time_stage", "Server",
     "FP64", "FP32", "CHECK_HERMITIAN",
 ]
 
@@ -100,6 +100,7 @@ def signatures():
         "lindblad_propagate": [V, I64, V, V, I64, V, V, I, D, I64, I],
         "lindblad_q_to_f32": [V, I64, V, I64, V],
         "lindblad_propagate_csr": [V, I64, V, V, V, V, V, I, D, I64],
+        "lindblad_propagate_csr_drive": [V, I64, V, V, V, V, V, V, V, V, I, D, I64, D, D, D, D],
         "lindblad_propagate_batched": [V, I, I64, V, V, I64, V, V, I, D, I64, I],
         "lindblad_propagate_graph": [V, I64, V, V, I64, V, V, I, D, I64, I],
         "lindblad_autotune": [V, I64, V, V, I64, V, V, I, I],
@@ -395,6 +396,26 @@ def lindblad_propagate_csr(ctx: Context, rowptr, col, val, K, V, dt: float, step
     M = rowptr.numel() - 1
     _check(load().lindblad_propagate_csr(ctx.handle, M, _ptr(rowptr), _ptr(col), _ptr(val), _ptr(K), _ptr(V),
                                          V.shape[0], float(dt), int(steps)))
+    return V
+
+
+def lindblad_propagate_csr_drive(ctx: Context, Q0, Q1, K, V, dt: float, steps: int, t0: float, E: float, A: float,
+                                 T: float):
+    """In place: RK4 of dv/dt = (Q0 + eps(t) Q1) v + K with the square-wave
+    drive eps(t) = E + A Theta(t); Q0, Q1 are (rowptr, col, val) CSR triples."""
+    import torch
+    for name, (rp, c, v) in (("Q0", Q0), ("Q1", Q1)):
+        _need(rp, torch.int64, name + " rowptr")
+        _need(c, torch.int64, name + " col")
+        _need(v, torch.float64, name + " val")
+    _need(K, torch.float64, "K")
+    _need(V, torch.float64, "V")
+    M = Q0[0].numel() - 1
+    if Q1[0].numel() != M + 1:
+        raise ValueError("Q0 and Q1 must have the same number of rows")
+    _check(load().lindblad_propagate_csr_drive(ctx.handle, M, _ptr(Q0[0]), _ptr(Q0[1]), _ptr(Q0[2]), _ptr(Q1[0]),
+                                               _ptr(Q1[1]), _ptr(Q1[2]), _ptr(K), _ptr(V), V.shape[0], float(dt),
+                                               int(steps), float(t0), float(E), float(A), float(T)))
     return V
 
 

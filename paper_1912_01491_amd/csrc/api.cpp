@@ -306,6 +306,24 @@ int lindblad_propagate_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const in
     return lb_impl_propagate_csr(c, M, rowptr, col, val, K, V, B, dt, steps);
 }
 
+int lindblad_propagate_csr_drive(lb_ctx* c, int64_t M, const int64_t* rowptr0, const int64_t* col0,
+                                 const double* val0, const int64_t* rowptr1, const int64_t* col1, const double* val1,
+                                 const double* K, double* V, int B, double dt, int64_t steps, double t0, double E,
+                                 double A, double T) {
+    CHECK_CTX(c);
+    CHECK_PTR(rowptr0);
+    CHECK_PTR(rowptr1);
+    CHECK_PTR(K);
+    CHECK_PTR(V);
+    if (M < 3) return lb_fail(LB_ERR_INVALID_ARG, "M too small");
+    if (B < 1 || B > 64) return lb_fail(LB_ERR_INVALID_ARG, "B=%d out of range", B);
+    if (!isfinite(dt) || steps < 0) return lb_fail(LB_ERR_INVALID_ARG, "bad dt/steps");
+    if (!isfinite(t0) || !isfinite(E) || !isfinite(A) || !(T > 0) || !isfinite(T))
+        return lb_fail(LB_ERR_INVALID_ARG, "drive needs finite t0, E, A and a period T > 0");
+    return lb_impl_propagate_csr_drive(c, M, rowptr0, col0, val0, rowptr1, col1, val1, K, V, B, dt, steps, t0, E, A,
+                                       T);
+}
+
 int lindblad_propagate_batched(lb_ctx* c, int R, int64_t M, const double* const* Q, const float* const* Q32,
                                int64_t ldq, const double* const* K, double* const* V, int B, double dt,
                                int64_t steps, int precision) {

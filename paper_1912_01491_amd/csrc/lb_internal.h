@@ -207,5 +207,9 @@ int lb_impl_autotune(lb_ctx* c, int64_t M, const lb_prop_sys* sys, int64_t ldq, 
 int lb_impl_propagate_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int64_t* col,
                           const double* val, const double* K, double* V, int B, double dt,
                           int64_t steps);
+int lb_impl_propagate_csr_drive(lb_ctx* c, int64_t M, const int64_t* rowptr0, const int64_t* col0,
+                                const double* val0, const int64_t* rowptr1, const int64_t* col1, const double* val1,
+                                const double* K, double* V, int B, double dt, int64_t steps, double t0, double E,
+                                double A, double T);
 int lb_impl_q_to_f32(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, float* Q32);
 lb_tile lb_default_tile(int64_t M, int Bp, int precision, int R);

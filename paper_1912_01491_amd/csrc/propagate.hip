@@ -914,16 +914,22 @@ struct CsrArgs {
     const int* longrows;
     int nlong;
     int B;
+    // driven systems: second matrix Q1 (rows and 32-bit columns), scaled by eps per stage
+    const int64_t* rowptr1;
+    const int* col1;
+    const double* val1;
 };
 
-__global__ __launch_bounds__(256) void k_csr_stage(CsrArgs a, int stage, double h) {
+// DRIVE: k = (Q0 x) + eps (Q1 x) + K, the two sums formed separately.
+template <bool DRIVE>
+__global__ __launch_bounds__(256) void k_csr_stage(CsrArgs a, int stage, double h, double eps) {
     const int64_t M = a.M;
     const int64_t n = M * a.B;
     double* Acc = a.W;
     const double* Xin = (stage & 1) ? a.W + n : a.W + 2 * n;
     double* Xout = (stage & 1) ? a.W + 2 * n : a.W + n;
     if ((int)blockIdx.x < a.nlong) {
-        __shared__ double red[4];
+        __shared__ double red[4], red1[4];
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         const int64_t row = a.longrows[blockIdx.x];
         const int64_t e0 = a.rowptr[row], e1 = a.rowptr[row + 1];
@@ -938,11 +944,22 @@ __global__ __launch_bounds__(256) void k_csr_stage(CsrArgs a, int stage, double 
             if (e < e1) s0 = fma(a.val[e], x[a.col[e]], s0);
             double sum = s0 + s1;
             for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
-            if (lane == 0) red[wave] = sum;
+            double sd = 0.0;
+            if (DRIVE) {
+                for (int64_t f = a.rowptr1[row] + threadIdx.x; f < a.rowptr1[row + 1]; f += 256)
+                    sd = fma(a.val1[f], x[a.col1[f]], sd);
+                for (int o = 32; o > 0; o >>= 1) sd += __shfl_xor(sd, o, 64);
+            }
+            if (lane == 0) {
+                red[wave] = sum;
+                red1[wave] = sd;
+            }
             __syncthreads();
             if (threadIdx.x == 0) {
                 const int64_t i = (int64_t)b * M + row;
-                const double k = (red[0] + red[1]) + (red[2] + red[3]) + a.K[row];
+                double k = (red[0] + red[1]) + (red[2] + red[3]);
+                if (DRIVE) k += eps * ((red1[0] + red1[1]) + (red1[2] + red1[3]));
+                k += a.K[row];
                 rk4_update(stage, h, k, a.V[i], stage > 1 ? Acc[i] : 0.0, i, a.V, Acc, Xout);
             }
             __syncthreads();
@@ -1001,15 +1018,32 @@ __global__ __launch_bounds__(256) void k_csr_stage(CsrArgs a, int stage, double 
                 for (int e = e0[s] + sub + 2 * kLanes; e < e1[s]; e += kLanes)
                     acc[s] = fma(a.val[e], x[a.col[e]], acc[s]);
         }
+        double accd[kSlots];
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) {
+            accd[s] = 0.0;
+            if (DRIVE && mine[s])
+                for (int64_t f = a.rowptr1[row[s]] + sub; f < a.rowptr1[row[s] + 1]; f += kLanes)
+                    accd[s] = fma(a.val1[f], x[a.col1[f]], accd[s]);
+        }
 #pragma unroll
         for (int s = 0; s < kSlots; ++s) {
             for (int o = kLanes / 2; o > 0; o >>= 1) acc[s] += __shfl_xor(acc[s], o, kLanes);
+            if (DRIVE)
+                for (int o = kLanes / 2; o > 0; o >>= 1) accd[s] += __shfl_xor(accd[s], o, kLanes);
             if (mine[s] && sub == 0) {
                 const int64_t i = (int64_t)b * M + row[s];
-                rk4_update(stage, h, acc[s] + kk[s], vv[s], aa[s], i, a.V, Acc, Xout);
+                double k = acc[s];
+                if (DRIVE) k += eps * accd[s];
+                rk4_update(stage, h, k + kk[s], vv[s], aa[s], i, a.V, Acc, Xout);
             }
         }
     }
+}
+
+__global__ void k_col32(int64_t nnz, const int64_t* col, int* col32) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nnz) col32[t] = (int)col[t];
 }
 
 __global__ void k_copy(const double* src, double* dst, int64_t n) {
@@ -1565,15 +1599,39 @@ int lb_impl_autotune(lb_ctx* c, int64_t M, const lb_prop_sys* sys, int64_t ldq, 
     return LB_OK;
 }
 
-int lb_impl_propagate_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int64_t* col, const double* val,
-                          const double* K, double* V, int B, double dt, int64_t steps) {
+// The square-wave drive eps(t) = E + A Theta(t), Theta = +1 on [0, T/2) and
+// -1 on [T/2, T), of the rocked dimer (Sec. 3). `left` gives the limit from
+// the left (at a switch: the half period that ends there).
+static double drive_value(double t, double E, double A, double T, bool left) {
+    double r = fmod(t, T);
+    if (left) {
+        if (r <= 0) r += T;
+        return r <= 0.5 * T ? E + A : E - A;
+    }
+    if (r < 0) r += T;
+    return r < 0.5 * T ? E + A : E - A;
+}
+
+// Stage time t0 + (k + c) dt as one product and one sum.
+static double stage_time(double t0, int64_t k, double c, double dt) {
+    const double kc = (double)k + c;
+    volatile double p = kc * dt;
+    return t0 + p;
+}
+
+static int csr_propagate(lb_ctx* c, int64_t M, const int64_t* rowptr, const int64_t* col, const double* val,
+                         const int64_t* rowptr1, const int64_t* col1, const double* val1, const double* K, double* V,
+                         int B, double dt, int64_t steps, double t0, double E, double A, double T) {
     hipStream_t s = c->stream;
     if (steps == 0) return LB_OK;
-    // number of stored entries, for the index conversion
-    int64_t nnz = 0;
+    const bool drive = rowptr1 != nullptr;
+    // numbers of stored entries, for the index conversion
+    int64_t nnz = 0, nnz1 = 0;
     LB_HIP(hipMemcpyAsync(&nnz, rowptr + M, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (drive) LB_HIP(hipMemcpyAsync(&nnz1, rowptr1 + M, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     LB_HIP(hipStreamSynchronize(s));
-    if (nnz < 0 || nnz >= ((int64_t)1 << 31)) return lb_fail(LB_ERR_UNSUPPORTED, "nnz=%lld out of range", (long long)nnz);
+    if (nnz < 0 || nnz >= ((int64_t)1 << 31) || nnz1 < 0 || nnz1 >= ((int64_t)1 << 31))
+        return lb_fail(LB_ERR_UNSUPPORTED, "nnz=%lld / %lld out of range", (long long)nnz, (long long)nnz1);
     const int64_t n = M * B;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -1583,6 +1641,7 @@ int lb_impl_propagate_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int
     };
     const size_t o_w = take(sizeof(double) * 3 * n);
     const size_t o_col = take(sizeof(int) * (size_t)(nnz > 0 ? nnz : 1));
+    const size_t o_col1 = take(sizeof(int) * (size_t)(nnz1 > 0 ? nnz1 : 1));
     const size_t o_long = take(sizeof(int) * (size_t)M);
     const size_t o_nl = take(sizeof(int));
     int rc = lb_ws_reserve(c, off);
@@ -1590,6 +1649,7 @@ int lb_impl_propagate_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int
     char* ws = (char*)c->ws;
     double* W = (double*)(ws + o_w);
     int* col32 = (int*)(ws + o_col);
+    int* col32b = (int*)(ws + o_col1);
     int* longrows = (int*)(ws + o_long);
     int* nlong = (int*)(ws + o_nl);
     LB_HIP(hipMemsetAsync(nlong, 0, sizeof(int), s));
@@ -1597,17 +1657,41 @@ int lb_impl_propagate_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int
     hipLaunchKernelGGL(k_csr_prep, dim3(lb_blocks(nt, 256)), dim3(256), 0, s, M, nnz, rowptr, col, col32, longrows,
                        nlong);
     LB_CHECK_LAUNCH();
+    if (drive && nnz1 > 0) {
+        hipLaunchKernelGGL(k_col32, dim3(lb_blocks(nnz1, 256)), dim3(256), 0, s, nnz1, col1, col32b);
+        LB_CHECK_LAUNCH();
+    }
     int hl = 0;
     LB_HIP(hipMemcpyAsync(&hl, nlong, sizeof(int), hipMemcpyDeviceToHost, s));
     hipLaunchKernelGGL(k_copy, dim3(lb_blocks(n, 256)), dim3(256), 0, s, (const double*)V, W + n, n);
     LB_CHECK_LAUNCH();
     LB_HIP(hipStreamSynchronize(s));
-    CsrArgs ca{M, rowptr, (const int*)col32, val, K, V, W, (const int*)longrows, hl, B};
+    CsrArgs ca{M, rowptr, (const int*)col32, val, K, V, W, (const int*)longrows, hl, B,
+               rowptr1, (const int*)col32b, val1};
     const unsigned grid = (unsigned)hl + lb_blocks(M, kRowsPerBlock);
     for (int64_t st = 0; st < steps; ++st)
         for (int stage = 1; stage <= 4; ++stage) {
-            hipLaunchKernelGGL(k_csr_stage, dim3(grid), dim3(256), 0, s, ca, stage, dt);
+            if (drive) {
+                // stages seen from inside the step: t_k and t_k + dt/2 from the right, t_k + dt from the left
+                const double cst = stage == 1 ? 0.0 : (stage == 4 ? 1.0 : 0.5);
+                const double eps = drive_value(stage_time(t0, st, cst, dt), E, A, T, stage == 4);
+                hipLaunchKernelGGL(k_csr_stage<true>, dim3(grid), dim3(256), 0, s, ca, stage, dt, eps);
+            } else {
+                hipLaunchKernelGGL(k_csr_stage<false>, dim3(grid), dim3(256), 0, s, ca, stage, dt, 0.0);
+            }
             LB_CHECK_LAUNCH();
         }
     return LB_OK;
+}
+
+int lb_impl_propagate_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int64_t* col, const double* val,
+                          const double* K, double* V, int B, double dt, int64_t steps) {
+    return csr_propagate(c, M, rowptr, col, val, nullptr, nullptr, nullptr, K, V, B, dt, steps, 0.0, 0.0, 0.0, 1.0);
+}
+
+int lb_impl_propagate_csr_drive(lb_ctx* c, int64_t M, const int64_t* rowptr0, const int64_t* col0,
+                                const double* val0, const int64_t* rowptr1, const int64_t* col1, const double* val1,
+                                const double* K, double* V, int B, double dt, int64_t steps, double t0, double E,
+                                double A, double T) {
+    return csr_propagate(c, M, rowptr0, col0, val0, rowptr1, col1, val1, K, V, B, dt, steps, t0, E, A, T);
 }

@@ -1,0 +1,129 @@
+"""GPU parity of the periodically rocked dimer (Sec. 3, Eq. (16)) against the
+oracle: the system dv/dt = (Q0 + eps(t) Q1) v + K with the square-wave drive,
+Q0 and Q1 prepared on the device by the sparse path, integrated over windows
+that cross the switches at T/2 and T. Normwise tolerance 1e-10."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from paper_1912_01491_amd import workloads as wl  # noqa: E402
+
+RTOL = 1e-10
+E, A, T = -1.0, -1.5, 2 * math.pi
+
+
+def rel(x, ref):
+    den = np.abs(ref).max()
+    return np.abs(np.asarray(x) - np.asarray(ref)).max() / (den if den > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import paper_1912_01491_amd as lb
+    lb.load()
+    return lb
+
+
+@pytest.fixture(scope="module")
+def ctx(lb):
+    c = lb.Context(0)
+    yield c
+    c.close()
+
+
+def dcsr(A_):
+    rp, c, v = wl.to_csr(A_)
+    return (torch.from_numpy(rp).cuda(), torch.from_numpy(c).cuda(), torch.from_numpy(v).cuda())
+
+
+def gpu_system(lb, ctx, N):
+    H0, H1, rates, Ls = wl.rocked_dimer_model(N)
+    rp0, c0, v0, K = lb.lindblad_prepare_sparse(ctx, N, dcsr(H0), rates, [dcsr(L) for L in Ls])
+    rp1, c1, v1, K1 = lb.lindblad_prepare_sparse(ctx, N, dcsr(H1), [], [])
+    return (rp0, c0, v0), (rp1, c1, v1), K, K1
+
+
+def oracle_system(oracle, N):
+    H0, H1, rates, Ls = wl.rocked_dimer_model(N)
+    M = N * N - 1
+    Q0, K = oracle.prepare_factored(H0, rates, Ls, np.arange(M))
+    Q1, _ = oracle.prepare_factored(H1, [0.0], [np.zeros((N, N))], np.arange(M))
+    return Q0, Q1, K
+
+
+def initial(oracle, N, B, seed):
+    psis = wl.random_pure_states(N, B, seed)
+    return np.array([oracle.expand(np.outer(p, p.conj())).real for p in psis])
+
+
+@pytest.mark.parametrize("N,B,steps,t0", [(5, 1, 230, 0.0), (9, 3, 130, 0.37), (9, 2, 60, math.pi - 0.5)])
+def test_drive_matches_oracle(lb, ctx, oracle, N, B, steps, t0):
+    """dt = T/200: the switches at T/2 and T fall on step boundaries for t0 = 0."""
+    print("[gpu] rocked dimer N=%d B=%d steps=%d t0=%.3f" % (N, B, steps, t0), flush=True)
+    dt = T / 200
+    Q0, Q1, K, K1 = gpu_system(lb, ctx, N)
+    assert np.abs(K1.cpu().numpy()).max() == 0.0
+    Q0o, Q1o, Ko = oracle_system(oracle, N)
+    V0 = initial(oracle, N, B, 30 + N)
+    Vo = oracle.rk4_drive(Q0o, Q1o, Ko, V0, dt, steps, t0, E, A, T)
+    V = torch.from_numpy(V0).cuda()
+    lb.lindblad_propagate_csr_drive(ctx, Q0, Q1, K, V, dt, steps, t0, E, A, T)
+    assert rel(V.cpu().numpy(), Vo) < RTOL
+
+
+def test_drive_long_rows(lb, ctx, oracle):
+    """N = 70: the rows of the diagonal generators take the one-block-per-row branch."""
+    N, B, steps = 70, 2, 24
+    print("[gpu] rocked dimer N=%d (long rows)" % N, flush=True)
+    dt = T / 64
+    t0 = T / 2 - 10 * dt  # crosses the switch at T/2 after 10 steps
+    Q0, Q1, K, _ = gpu_system(lb, ctx, N)
+    assert int(torch.diff(Q0[0]).max()) > 32
+    Q0o, Q1o, Ko = oracle_system(oracle, N)
+    V0 = initial(oracle, N, B, 5)
+    Vo = oracle.rk4_drive(Q0o, Q1o, Ko, V0, dt, steps, t0, E, A, T)
+    V = torch.from_numpy(V0).cuda()
+    lb.lindblad_propagate_csr_drive(ctx, Q0, Q1, K, V, dt, steps, t0, E, A, T)
+    assert rel(V.cpu().numpy(), Vo) < RTOL
+
+
+def test_zero_drive_is_the_static_integrator(lb, ctx, oracle):
+    N = 9
+    Q0, Q1, K, _ = gpu_system(lb, ctx, N)
+    V0 = torch.from_numpy(initial(oracle, N, 2, 8)).cuda()
+    a = V0.clone()
+    lb.lindblad_propagate_csr_drive(ctx, Q0, Q1, K, a, 1e-3, 50, 0.0, 0.0, 0.0, T)
+    b = V0.clone()
+    lb.lindblad_propagate_csr(ctx, Q0[0], Q0[1], Q0[2], K, b, 1e-3, 50)
+    assert torch.equal(a, b)
+
+
+def test_drive_operator_structure(lb, ctx, oracle):
+    """Q1 couples only S and J of the same pair (H1 is diagonal), two entries per
+    pair row where the diagonal values differ, and matches the oracle."""
+    N = 12
+    M = N * N - 1
+    P = N * (N - 1) // 2
+    _, Q1, _, _ = gpu_system(lb, ctx, N)
+    rp, col, val = (x.cpu().numpy() for x in Q1)
+    _, Q1o, _ = oracle_system(oracle, N)
+    dense = np.zeros((M, M))
+    for r in range(M):
+        dense[r, col[rp[r]:rp[r + 1]]] = val[rp[r]:rp[r + 1]]
+    assert rel(dense, Q1o) < RTOL
+    rows, cols = np.nonzero(dense)
+    assert np.all(np.abs(rows - cols) == P)
+    assert np.all(np.diff(rp)[2 * P:] == 0)
+
+
+def test_drive_rejects_bad_period(lb, ctx):
+    N = 5
+    Q0, Q1, K, _ = gpu_system(lb, ctx, N)
+    V = torch.zeros((1, N * N - 1), dtype=torch.float64, device="cuda")
+    with pytest.raises(lb.LindbladError):
+        lb.lindblad_propagate_csr_drive(ctx, Q0, Q1, K, V, 1e-3, 5, 0.0, E, A, 0.0)
