@@ -90,10 +90,12 @@ def parse():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle RK4 steps in the CPU sample")
-    ap.add_argument("--config", choices=["c1", "c2", "c3", "c4", "c5", "c5r"], default="c4",
+    ap.add_argument("--config", choices=["c1", "c2", "c2p", "c3", "c4", "c5", "c5r"], default="c4",
                     help="c4: the N=200 dense headline (default); c1: N=8 dense; c2: N=1000 sparse dimer; "
                          "c3: N=100 dense, 64 states, FP64 vs FP32; c5: serving mix (prepare per request); "
-                         "c5r: serving mix on resident systems")
+                         "c5r: serving mix on resident systems; c2p: the periodically rocked dimer (one period)")
+    ap.add_argument("--drive-N", type=int, default=1000, help="c2p: Hilbert-space dimension")
+    ap.add_argument("--drive-steps", type=int, default=20000, help="c2p: RK4 steps per drive period")
     ap.add_argument("--serving", action="store_true", help="same as --config c5")
     ap.add_argument("--resident", action="store_true", help="with --serving: same as --config c5r")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -375,7 +377,8 @@ def config_c2(args):
     V = V0.clone()
     t_prop, _ = _timed(lambda: lb.lindblad_propagate_csr(ctx, rp, col, val, K, V, dt, S))
     # algorithmic bytes per RK4 step: four passes over the stored entries (8 B value + 4 B column index,
-    # the kernel's format) and the row pointers, plus the M-vectors touched once each: per step x in (4),
+    # the kernel's format; its slice padding is not counted) and the CSR row pointers, plus the M-vectors
+    # touched once each: per step x in (4),
     # K (4), v read (4) and written (1), accumulator read (3) and written (3), stage output (4)
     bytes_step = 4 * (nnz * (8 + 4) + (M + 1) * 8) + 23 * M * 8
     gbs = S * bytes_step / t_prop / 1e9
@@ -398,9 +401,91 @@ def config_c2(args):
                                   "0.1/999, 1000 RK4 steps dt=1e-3"},
            "prepare_s": t_prep, "nnz": nnz, "us_per_step": 1e6 * t_prop / S,
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_csr_stage",
+                        "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sell_stage<false, 1>",
                         "bytes_per_step": bytes_step},
            "checks": {"trace_err": float(tr), "sampled_rows_rel_err_vs_oracle": err}}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def config_c2p(args):
+    """The periodically rocked dimer of the paper's sparse model (Sec. 3): H(t)
+    = H0 + eps(t)(n2 - n1), J = -1, U = 2.2, eps(t) = E + A Theta(t) with
+    E = -1, A = -1.5, T = 2 pi; one jump (b1^+ + b2^+)(b1 - b2) at rate
+    0.1/(N-1); one period of 20000 RK4 steps from a random pure state. Q0 (H0
+    and the dissipator) and Q1 (n2 - n1) are prepared on the device in CSR."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1912_01491_amd as lb
+    from paper_1912_01491_amd import workloads as wl
+
+    N = args.drive_N
+    M = N * N - 1
+    E, A, T = -1.0, -1.5, 2 * math.pi
+    S = args.drive_steps
+    dt = T / S
+    H0, H1, rates, Ls = wl.rocked_dimer_model(N)
+    ctx = lb.Context(0)
+
+    def dev_csr(X):
+        return tuple(torch.from_numpy(x).cuda() for x in wl.to_csr(X))
+
+    H0c, H1c, Lc = dev_csr(H0), dev_csr(H1), [dev_csr(L) for L in Ls]
+
+    def prep():
+        rp0, c0, v0, K = lb.lindblad_prepare_sparse(ctx, N, H0c, rates, Lc)
+        rp1, c1, v1, _ = lb.lindblad_prepare_sparse(ctx, N, H1c, [], [])
+        return (rp0, c0, v0), (rp1, c1, v1), K
+
+    prep()
+    t_prep, (Q0, Q1, K) = min((_timed(prep) for _ in range(3)), key=lambda x: x[0])
+    nnz0, nnz1 = int(Q0[1].numel()), int(Q1[1].numel())
+    psi = torch.from_numpy(wl.random_pure_state(N, 0)[None, :]).cuda()
+    V0 = lb.lb_expand_pure(ctx, psi)
+    V = V0.clone()
+    lb.lindblad_propagate_csr_drive(ctx, Q0, Q1, K, V, dt, 20, 0.0, E, A, T)
+    V = V0.clone()
+    t_prop, _ = _timed(lambda: lb.lindblad_propagate_csr_drive(ctx, Q0, Q1, K, V, dt, S, 0.0, E, A, T))
+    # algorithmic bytes per RK4 step: four passes over both matrices (8 B value + 4 B column per stored
+    # entry, row pointers) and the M-vectors touched once each (as for the static sparse path)
+    bytes_step = 4 * ((nnz0 + nnz1) * (8 + 4) + 2 * (M + 1) * 8) + 23 * M * 8
+    gbs = S * bytes_step / t_prop / 1e9
+    rho = lb.lb_reconstruct(ctx, V, N)[0].cpu().numpy()
+    # oracle parity on sampled rows of both matrices
+    P = N * (N - 1) // 2
+    rows = np.array([0, 1, N - 2, P - 1, P, 2 * P - 1, 2 * P, M - 1])
+    Q0o, Ko = oracle.prepare_factored(H0, rates, Ls, rows)
+    Q1o, _ = oracle.prepare_factored(H1, [0.0], [np.zeros((N, N))], rows)
+
+    def rows_dense(Q):
+        rp, c, v = (x.cpu().numpy() for x in Q)
+        out = np.zeros((len(rows), M))
+        for t, r in enumerate(rows):
+            out[t, c[rp[r]:rp[r + 1]]] = v[rp[r]:rp[r + 1]]
+        return out
+
+    err0 = float(np.abs(rows_dense(Q0) - Q0o).max() / np.abs(Q0o).max())
+    err1 = float(np.abs(rows_dense(Q1) - Q1o).max() / np.abs(Q1o).max())
+    log("C2p: N=%d prepare %.1f ms (nnz %d + %d), one period of %d RK4 steps in %.3f s (%.1f us/step, %.0f GB/s)"
+        % (N, 1e3 * t_prep, nnz0, nnz1, S, t_prop, 1e6 * t_prop / S, gbs))
+    out = {"metric": "rocked dimer: RK4 steps/s over one drive period", "value": S / t_prop,
+           "unit": "RK4 steps/s (1 state, N=%d)" % N, "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "periodically rocked dimer N=%d (M=%d), J=-1, U=2.2, E=-1, A=-1.5, T=2pi, "
+                                  "L=(b1^+ + b2^+)(b1 - b2) at rate 0.1/%d, %d RK4 steps per period"
+                                  % (N, M, N - 1, S)},
+           "prepare_s": t_prep, "nnz_Q0": nnz0, "nnz_Q1": nnz1, "us_per_step": 1e6 * t_prop / S,
+           "period_s": t_prop,
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sell_stage<true, 1>",
+                        "bytes_per_step": bytes_step},
+           "checks": {"trace_err": float(abs(np.trace(rho) - 1)),
+                      "herm_err": float(np.abs(rho - rho.conj().T).max()),
+                      "sampled_rows_rel_err_vs_oracle": {"Q0": err0, "Q1": err1}}}
     ctx.close()
     print(json.dumps(out), flush=True)
 
@@ -504,8 +589,8 @@ def main():
         return pmc_probe(args)
     if args.serving or args.config in ("c5", "c5r"):
         return serving(args)
-    if args.config in ("c1", "c2", "c3"):
-        return {"c1": config_c1, "c2": config_c2, "c3": config_c3}[args.config](args)
+    if args.config in ("c1", "c2", "c2p", "c3"):
+        return {"c1": config_c1, "c2": config_c2, "c2p": config_c2p, "c3": config_c3}[args.config](args)
     import numpy as np
     import torch
 

@@ -51,7 +51,8 @@ extern "C" {
 #define LB_ERR_UNSUPPORTED (-5)   /* valid request this build cannot serve (e.g. too large) */
 #define LB_ERR_ADMISSION (-6)     /* a serving request does not fit the server's memory budget */
 
-#define LB_MAX_N 1024             /* largest Hilbert-space dimension accepted */
+#define LB_MAX_N 2048             /* largest Hilbert-space dimension accepted (dense inputs of that
+                                     size would not fit in memory; the sparse path reaches it) */
 
 /* lindblad_prepare flags */
 #define LB_CHECK_HERMITIAN 1u     /* verify H and gamma are Hermitian (extra pass, synchronizes) */

@@ -31,7 +31,7 @@ __all__ = [
 FP64 = 0
 FP32 = 1
 CHECK_HERMITIAN = 1
-MAX_N = 1024
+MAX_N = 2048
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "_build", "liblindblad.so")

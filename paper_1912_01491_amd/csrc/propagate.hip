@@ -859,21 +859,21 @@ __global__ __launch_bounds__(256) void k_rk4_small(const double* const* Qs, cons
 }
 
 // ---------------------------------------------------------------------------
-// CSR stage: one launch per RK4 stage with the stage combination fused in.
-// The first nlong blocks take one long row each (more than kLongRow entries:
-// the diagonal-generator rows and the rows coupled to them, ~N entries), 256
-// threads with a fixed-order block reduction. The other blocks take 128 short
-// rows each: a group of kLanes lanes per row and kSlots rows per group, with the
-// row's update operands (K, v, accumulator) loaded before the dot product and
-// the first 2*kLanes entries of every row loaded at once, so that each wave has
-// several independent loads in flight. Column indices are 32-bit, converted
-// once per call.
+// Sparse RK4 stage: one launch per stage with the stage combination fused in.
+// The CSR rows the caller passes are regrouped once per call into slices of 64
+// consecutive rows (one wavefront, one row per lane), each slice stored entry-
+// major: entry k of the slice's rows sits at [k * 64 + lane], padded to the
+// slice's longest row with zero values whose column is the lane's own row. A
+// wavefront's column and value loads are then full contiguous lines, no
+// cross-lane reduction is needed, and entry k of neighbouring rows, which in
+// the pair ordering are neighbouring pairs, tends to gather neighbouring x.
+// Rows with more than kLongRow entries (the diagonal-generator rows and the
+// rows coupled to them, ~N entries) are left out of the slices and take one
+// block of 256 threads each, with a fixed-order block reduction.
 // ---------------------------------------------------------------------------
-constexpr int kLanes = 4;
-constexpr int kSlots = 2;
 constexpr int kLongRow = 32;
-constexpr int kGroups = 256 / kLanes;
-constexpr int kRowsPerBlock = kGroups * kSlots;
+constexpr int kSlice = 64;
+constexpr int kChunk = 8;  // slice entries per lane loaded before their products
 
 // RK4 stage combination for one element, given k = (Q x + K)_i and the values
 // of v and of the accumulator loaded beforehand.
@@ -896,33 +896,162 @@ __device__ __forceinline__ void rk4_update(int stage, double h, double k, double
     Xout[i] = x;
 }
 
-__global__ void k_csr_prep(int64_t M, int64_t nnz, const int64_t* rowptr, const int64_t* col, int* col32,
-                           int* longrows, int* nlong) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < nnz) col32[t] = (int)col[t];
-    if (t < M && rowptr[t + 1] - rowptr[t] > kLongRow) longrows[atomicAdd(nlong, 1)] = (int)t;
+// Slice widths (as 64 * entries, later scanned into offsets), the long-row
+// mask of each slice and the list of long rows. One wavefront per slice.
+__global__ __launch_bounds__(256) void k_sell_widths(int64_t M, int64_t S, const int64_t* rowptr,
+                                                     const int64_t* rowptr1, int64_t* off0, int64_t* off1,
+                                                     uint64_t* lmask, int* longrows, int* nlong) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t sl = r / kSlice;
+    if (sl >= S) return;  // whole wavefronts
+    int64_t len0 = 0, len1 = 0;
+    if (r < M) {
+        len0 = rowptr[r + 1] - rowptr[r];
+        if (rowptr1) len1 = rowptr1[r + 1] - rowptr1[r];
+    }
+    const bool lng = len0 > kLongRow;
+    if (lng) {
+        len0 = 0;
+        len1 = 0;
+        longrows[atomicAdd(nlong, 1)] = (int)r;
+    }
+    for (int o = kSlice / 2; o > 0; o >>= 1) {
+        len0 = max(len0, (int64_t)__shfl_xor(len0, o, kSlice));
+        len1 = max(len1, (int64_t)__shfl_xor(len1, o, kSlice));
+    }
+    const uint64_t mask = __ballot(lng);
+    if ((r & (kSlice - 1)) == 0) {
+        off0[sl] = kSlice * len0;
+        off1[sl] = kSlice * len1;
+        lmask[sl] = mask;
+    }
 }
 
-struct CsrArgs {
-    int64_t M;
-    const int64_t* rowptr;
-    const int* col;
+// Exclusive scan of n sizes in place, total in a[n]; one block of 1024 threads.
+__device__ void block_scan_inplace(int64_t n, int64_t* a, int64_t* part) {
+    const int t = threadIdx.x;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t b0 = min(n, t * per), b1 = min(n, b0 + per);
+    int64_t sum = 0;
+    for (int64_t i = b0; i < b1; ++i) sum += a[i];
+    part[t] = sum;
+    __syncthreads();
+    if (t == 0) {
+        int64_t run = 0;
+        for (int i = 0; i < 1024; ++i) {
+            const int64_t v = part[i];
+            part[i] = run;
+            run += v;
+        }
+        a[n] = run;
+    }
+    __syncthreads();
+    int64_t run = part[t];
+    for (int64_t i = b0; i < b1; ++i) {
+        const int64_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void k_sell_scan(int64_t S, int64_t* off0, int64_t* off1) {
+    __shared__ int64_t part[1024];
+    block_scan_inplace(S, off0, part);
+    if (off1) block_scan_inplace(S, off1, part);
+}
+
+// One matrix into the slice layout: thread per row (rows past M and long rows
+// are all padding).
+__device__ __forceinline__ void sell_put(int64_t r, int64_t M, int64_t sl, bool lng, const int64_t* rowptr,
+                                         const int64_t* col, const double* val, const int64_t* off, int* scol,
+                                         double* sval) {
+    const int64_t o = off[sl], w = (off[sl + 1] - o) / kSlice;
+    int64_t e0 = 0, len = 0;
+    if (r < M && !lng) {
+        e0 = rowptr[r];
+        len = rowptr[r + 1] - e0;
+    }
+    const int pad = (int)(r < M ? r : M - 1);
+    const int lane = (int)(r & (kSlice - 1));
+    for (int64_t k = 0; k < w; ++k) {
+        const int64_t d = o + k * kSlice + lane;
+        scol[d] = k < len ? (int)col[e0 + k] : pad;
+        sval[d] = k < len ? val[e0 + k] : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sell_fill(int64_t M, int64_t S, const uint64_t* lmask, const int64_t* rowptr,
+                                                   const int64_t* col, const double* val, const int64_t* off0,
+                                                   int* scol0, double* sval0, const int64_t* rowptr1,
+                                                   const int64_t* col1, const double* val1, const int64_t* off1,
+                                                   int* scol1, double* sval1) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t sl = r / kSlice;
+    if (sl >= S) return;
+    const bool lng = (lmask[sl] >> (r & (kSlice - 1))) & 1;
+    sell_put(r, M, sl, lng, rowptr, col, val, off0, scol0, sval0);
+    if (rowptr1) sell_put(r, M, sl, lng, rowptr1, col1, val1, off1, scol1, sval1);
+}
+
+struct SellArgs {
+    int64_t M, S;
+    const int64_t* rowptr;  // CSR of Q0 and Q1, read by the long rows
+    const int64_t* col;
     const double* val;
-    const double* K;
-    double* V;
-    double* W;  // [accumulator | x ping | x pong], M*B each
+    const int64_t* rowptr1;
+    const int64_t* col1;
+    const double* val1;
+    const int64_t* off0;  // slice layout of Q0 and Q1
+    const int* scol0;
+    const double* sval0;
+    const int64_t* off1;
+    const int* scol1;
+    const double* sval1;
+    const uint64_t* lmask;
     const int* longrows;
     int nlong;
     int B;
-    // driven systems: second matrix Q1 (rows and 32-bit columns), scaled by eps per stage
-    const int64_t* rowptr1;
-    const int* col1;
-    const double* val1;
+    const double* K;
+    double* V;
+    double* W;  // [accumulator | x ping | x pong], M*B each
 };
 
+// acc[j] += sum over slice entries [k, k + n) of value * x_j[column], in entry
+// order, for the first nb of SB states; FULL: n == kChunk.
+template <int SB, bool FULL>
+__device__ __forceinline__ void sell_chunk(const int* c0, const double* v0, int k, int n, const double* Xin,
+                                           int64_t M, int nb, double* acc) {
+    int cc[kChunk];
+    double vv[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u)
+        if (FULL || u < n) {
+            cc[u] = c0[(int64_t)(k + u) * kSlice];
+            vv[u] = v0[(int64_t)(k + u) * kSlice];
+        }
+#pragma unroll
+    for (int j = 0; j < SB; ++j)
+        if (j < nb) {
+            const double* x = Xin + (int64_t)j * M;
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u)
+                if (FULL || u < n) acc[j] = fma(vv[u], x[cc[u]], acc[j]);
+        }
+}
+
+template <int SB>
+__device__ __forceinline__ void sell_row(const int* c0, const double* v0, int w, const double* Xin, int64_t M,
+                                         int nb, double* acc) {
+    int k = 0;
+    for (; k + kChunk <= w; k += kChunk) sell_chunk<SB, true>(c0, v0, k, kChunk, Xin, M, nb, acc);
+    if (k < w) sell_chunk<SB, false>(c0, v0, k, w - k, Xin, M, nb, acc);
+}
+
 // DRIVE: k = (Q0 x) + eps (Q1 x) + K, the two sums formed separately.
-template <bool DRIVE>
-__global__ __launch_bounds__(256) void k_csr_stage(CsrArgs a, int stage, double h, double eps) {
+// SB: states per pass over a slice (1, or 4 for batches).
+template <bool DRIVE, int SB>
+__global__ __launch_bounds__(256) void k_sell_stage(SellArgs a, int stage, double h, double eps) {
     const int64_t M = a.M;
     const int64_t n = M * a.B;
     double* Acc = a.W;
@@ -966,84 +1095,49 @@ __global__ __launch_bounds__(256) void k_csr_stage(CsrArgs a, int stage, double 
         }
         return;
     }
-    // rows, entry offsets: 32-bit (M < 2^31 and nnz < 2^31 are checked by the host)
-    const int g = threadIdx.x / kLanes, sub = threadIdx.x % kLanes;
-    const int base = (int)(blockIdx.x - a.nlong) * kRowsPerBlock + g;
-    int row[kSlots], e0[kSlots], e1[kSlots];
-    bool mine[kSlots];
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-        row[s] = base + s * kGroups;
-        e0[s] = e1[s] = 0;
-        if (row[s] < M) {
-            e0[s] = (int)a.rowptr[row[s]];
-            e1[s] = (int)a.rowptr[row[s] + 1];
-        }
-        mine[s] = row[s] < M && e1[s] - e0[s] <= kLongRow;
+    // one slice per wavefront; the slice index is wave-uniform
+    const int sl = __builtin_amdgcn_readfirstlane((int)((blockIdx.x - a.nlong) * 4 + (threadIdx.x >> 6)));
+    if (sl >= a.S) return;
+    const int lane = threadIdx.x & (kSlice - 1);
+    const int64_t r = (int64_t)sl * kSlice + lane;
+    const bool mine = r < M && !((a.lmask[sl] >> lane) & 1);
+    const int64_t o0 = a.off0[sl];
+    const int w0 = (int)((a.off0[sl + 1] - o0) / kSlice);
+    const int* c0 = a.scol0 + o0 + lane;
+    const double* v0 = a.sval0 + o0 + lane;
+    int w1 = 0;
+    const int* c1 = nullptr;
+    const double* v1 = nullptr;
+    if (DRIVE) {
+        const int64_t o1 = a.off1[sl];
+        w1 = (int)((a.off1[sl + 1] - o1) / kSlice);
+        c1 = a.scol1 + o1 + lane;
+        v1 = a.sval1 + o1 + lane;
     }
-    for (int b = 0; b < a.B; ++b) {
-        const double* x = Xin + (int64_t)b * M;
-        double kk[kSlots], vv[kSlots], aa[kSlots], acc[kSlots];
+    const double kr = mine ? a.K[r] : 0.0;
+    for (int b0 = 0; b0 < a.B; b0 += SB) {
+        const int nb = min(SB, a.B - b0);
+        double vv[SB], aa[SB], acc[SB], accd[SB];
 #pragma unroll
-        for (int s = 0; s < kSlots; ++s) {
-            kk[s] = vv[s] = aa[s] = 0.0;
-            if (mine[s] && sub == 0) {
-                const int64_t i = (int64_t)b * M + row[s];
-                kk[s] = a.K[row[s]];
-                vv[s] = a.V[i];
-                if (stage > 1) aa[s] = Acc[i];
+        for (int j = 0; j < SB; ++j) {
+            vv[j] = aa[j] = acc[j] = accd[j] = 0.0;
+            if (j < nb && mine) {
+                const int64_t i = (int64_t)(b0 + j) * M + r;
+                vv[j] = a.V[i];
+                if (stage > 1) aa[j] = Acc[i];
             }
         }
-        int c[kSlots][2];
-        double v[kSlots][2];
+        const double* xb = Xin + (int64_t)b0 * M;
+        sell_row<SB>(c0, v0, w0, xb, M, nb, acc);
+        if (DRIVE) sell_row<SB>(c1, v1, w1, xb, M, nb, accd);
 #pragma unroll
-        for (int s = 0; s < kSlots; ++s)
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int e = e0[s] + sub + u * kLanes;
-                c[s][u] = 0;
-                v[s][u] = 0.0;
-                if (mine[s] && e < e1[s]) {
-                    c[s][u] = a.col[e];
-                    v[s][u] = a.val[e];
-                }
+        for (int j = 0; j < SB; ++j)
+            if (j < nb && mine) {
+                double k = acc[j];
+                if (DRIVE) k += eps * accd[j];
+                rk4_update(stage, h, k + kr, vv[j], aa[j], (int64_t)(b0 + j) * M + r, a.V, Acc, Xout);
             }
-#pragma unroll
-        for (int s = 0; s < kSlots; ++s) {
-            acc[s] = 0.0;
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-                if (mine[s] && e0[s] + sub + u * kLanes < e1[s]) acc[s] = fma(v[s][u], x[c[s][u]], acc[s]);
-            if (mine[s])
-                for (int e = e0[s] + sub + 2 * kLanes; e < e1[s]; e += kLanes)
-                    acc[s] = fma(a.val[e], x[a.col[e]], acc[s]);
-        }
-        double accd[kSlots];
-#pragma unroll
-        for (int s = 0; s < kSlots; ++s) {
-            accd[s] = 0.0;
-            if (DRIVE && mine[s])
-                for (int64_t f = a.rowptr1[row[s]] + sub; f < a.rowptr1[row[s] + 1]; f += kLanes)
-                    accd[s] = fma(a.val1[f], x[a.col1[f]], accd[s]);
-        }
-#pragma unroll
-        for (int s = 0; s < kSlots; ++s) {
-            for (int o = kLanes / 2; o > 0; o >>= 1) acc[s] += __shfl_xor(acc[s], o, kLanes);
-            if (DRIVE)
-                for (int o = kLanes / 2; o > 0; o >>= 1) accd[s] += __shfl_xor(accd[s], o, kLanes);
-            if (mine[s] && sub == 0) {
-                const int64_t i = (int64_t)b * M + row[s];
-                double k = acc[s];
-                if (DRIVE) k += eps * accd[s];
-                rk4_update(stage, h, k + kk[s], vv[s], aa[s], i, a.V, Acc, Xout);
-            }
-        }
     }
-}
-
-__global__ void k_col32(int64_t nnz, const int64_t* col, int* col32) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < nnz) col32[t] = (int)col[t];
 }
 
 __global__ void k_copy(const double* src, double* dst, int64_t n) {
@@ -1625,7 +1719,7 @@ static int csr_propagate(lb_ctx* c, int64_t M, const int64_t* rowptr, const int6
     hipStream_t s = c->stream;
     if (steps == 0) return LB_OK;
     const bool drive = rowptr1 != nullptr;
-    // numbers of stored entries, for the index conversion
+    // numbers of stored entries: 32-bit slice columns
     int64_t nnz = 0, nnz1 = 0;
     LB_HIP(hipMemcpyAsync(&nnz, rowptr + M, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     if (drive) LB_HIP(hipMemcpyAsync(&nnz1, rowptr1 + M, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1633,52 +1727,88 @@ static int csr_propagate(lb_ctx* c, int64_t M, const int64_t* rowptr, const int6
     if (nnz < 0 || nnz >= ((int64_t)1 << 31) || nnz1 < 0 || nnz1 >= ((int64_t)1 << 31))
         return lb_fail(LB_ERR_UNSUPPORTED, "nnz=%lld / %lld out of range", (long long)nnz, (long long)nnz1);
     const int64_t n = M * B;
+    const int64_t S = (M + kSlice - 1) / kSlice;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
-        off = lb_align(off + bytes, 256);
+        off = lb_align(off + (bytes > 0 ? bytes : 1), 256);
         return o;
     };
-    const size_t o_w = take(sizeof(double) * 3 * n);
-    const size_t o_col = take(sizeof(int) * (size_t)(nnz > 0 ? nnz : 1));
-    const size_t o_col1 = take(sizeof(int) * (size_t)(nnz1 > 0 ? nnz1 : 1));
+    // phase 1 (sizes known from M): slice offsets, long-row masks and list
+    const size_t o_off0 = take(sizeof(int64_t) * (size_t)(S + 1));
+    const size_t o_off1 = take(sizeof(int64_t) * (size_t)(S + 1));
+    const size_t o_mask = take(sizeof(uint64_t) * (size_t)S);
     const size_t o_long = take(sizeof(int) * (size_t)M);
     const size_t o_nl = take(sizeof(int));
-    int rc = lb_ws_reserve(c, off);
+    const size_t o_w = take(sizeof(double) * 3 * n);
+    const size_t fixed = off;
+    int rc = lb_ws_reserve(c, fixed);
     if (rc) return rc;
-    char* ws = (char*)c->ws;
-    double* W = (double*)(ws + o_w);
-    int* col32 = (int*)(ws + o_col);
-    int* col32b = (int*)(ws + o_col1);
-    int* longrows = (int*)(ws + o_long);
-    int* nlong = (int*)(ws + o_nl);
-    LB_HIP(hipMemsetAsync(nlong, 0, sizeof(int), s));
-    const int64_t nt = nnz > M ? nnz : M;
-    hipLaunchKernelGGL(k_csr_prep, dim3(lb_blocks(nt, 256)), dim3(256), 0, s, M, nnz, rowptr, col, col32, longrows,
-                       nlong);
-    LB_CHECK_LAUNCH();
-    if (drive && nnz1 > 0) {
-        hipLaunchKernelGGL(k_col32, dim3(lb_blocks(nnz1, 256)), dim3(256), 0, s, nnz1, col1, col32b);
-        LB_CHECK_LAUNCH();
-    }
     int hl = 0;
-    LB_HIP(hipMemcpyAsync(&hl, nlong, sizeof(int), hipMemcpyDeviceToHost, s));
+    int64_t tot0 = 0, tot1 = 0;
+    const unsigned rgrid = (unsigned)lb_blocks(S * kSlice, 256);
+    for (int pass = 0; pass < 2; ++pass) {
+        char* ws = (char*)c->ws;
+        int64_t* off0 = (int64_t*)(ws + o_off0);
+        int64_t* off1 = (int64_t*)(ws + o_off1);
+        int* nlong = (int*)(ws + o_nl);
+        LB_HIP(hipMemsetAsync(nlong, 0, sizeof(int), s));
+        hipLaunchKernelGGL(k_sell_widths, dim3(rgrid), dim3(256), 0, s, M, S, rowptr, drive ? rowptr1 : nullptr,
+                           off0, off1, (uint64_t*)(ws + o_mask), (int*)(ws + o_long), nlong);
+        LB_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_sell_scan, dim3(1), dim3(1024), 0, s, S, off0, drive ? off1 : nullptr);
+        LB_CHECK_LAUNCH();
+        LB_HIP(hipMemcpyAsync(&hl, nlong, sizeof(int), hipMemcpyDeviceToHost, s));
+        LB_HIP(hipMemcpyAsync(&tot0, off0 + S, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        if (drive) LB_HIP(hipMemcpyAsync(&tot1, off1 + S, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        LB_HIP(hipStreamSynchronize(s));
+        off = fixed;
+        take(sizeof(int) * (size_t)tot0);
+        take(sizeof(double) * (size_t)tot0);
+        take(sizeof(int) * (size_t)tot1);
+        take(sizeof(double) * (size_t)tot1);
+        const size_t need = off;
+        if (need <= c->ws_bytes) break;
+        // the workspace grows: its contents go, so the offsets are formed again
+        rc = lb_ws_reserve(c, need);
+        if (rc) return rc;
+    }
+    off = fixed;
+    const size_t o_sc0 = take(sizeof(int) * (size_t)tot0);
+    const size_t o_sv0 = take(sizeof(double) * (size_t)tot0);
+    const size_t o_sc1 = take(sizeof(int) * (size_t)tot1);
+    const size_t o_sv1 = take(sizeof(double) * (size_t)tot1);
+    if (off > c->ws_bytes) return lb_fail(LB_ERR_DEVICE, "slice layout exceeds the workspace");
+    char* ws = (char*)c->ws;
+    const int64_t* off0 = (const int64_t*)(ws + o_off0);
+    const int64_t* off1 = (const int64_t*)(ws + o_off1);
+    const uint64_t* lmask = (const uint64_t*)(ws + o_mask);
+    int* scol0 = (int*)(ws + o_sc0);
+    double* sval0 = (double*)(ws + o_sv0);
+    int* scol1 = (int*)(ws + o_sc1);
+    double* sval1 = (double*)(ws + o_sv1);
+    double* W = (double*)(ws + o_w);
+    hipLaunchKernelGGL(k_sell_fill, dim3(rgrid), dim3(256), 0, s, M, S, lmask, rowptr, col, val, off0, scol0, sval0,
+                       drive ? rowptr1 : nullptr, col1, val1, off1, scol1, sval1);
+    LB_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_copy, dim3(lb_blocks(n, 256)), dim3(256), 0, s, (const double*)V, W + n, n);
     LB_CHECK_LAUNCH();
-    LB_HIP(hipStreamSynchronize(s));
-    CsrArgs ca{M, rowptr, (const int*)col32, val, K, V, W, (const int*)longrows, hl, B,
-               rowptr1, (const int*)col32b, val1};
-    const unsigned grid = (unsigned)hl + lb_blocks(M, kRowsPerBlock);
+    SellArgs sa{M,     S,     rowptr, col,   val,   rowptr1,        col1,       val1, off0, scol0,
+                sval0, off1,  scol1,  sval1, lmask, (const int*)(ws + o_long), hl,   B,    K,    V,
+                W};
+    const unsigned grid = (unsigned)hl + (unsigned)((S + 3) / 4);
+    typedef void (*stage_fn)(SellArgs, int, double, double);
+    const stage_fn fn = drive ? (B == 1 ? k_sell_stage<true, 1> : k_sell_stage<true, 4>)
+                              : (B == 1 ? k_sell_stage<false, 1> : k_sell_stage<false, 4>);
     for (int64_t st = 0; st < steps; ++st)
         for (int stage = 1; stage <= 4; ++stage) {
+            double eps = 0.0;
             if (drive) {
                 // stages seen from inside the step: t_k and t_k + dt/2 from the right, t_k + dt from the left
                 const double cst = stage == 1 ? 0.0 : (stage == 4 ? 1.0 : 0.5);
-                const double eps = drive_value(stage_time(t0, st, cst, dt), E, A, T, stage == 4);
-                hipLaunchKernelGGL(k_csr_stage<true>, dim3(grid), dim3(256), 0, s, ca, stage, dt, eps);
-            } else {
-                hipLaunchKernelGGL(k_csr_stage<false>, dim3(grid), dim3(256), 0, s, ca, stage, dt, 0.0);
+                eps = drive_value(stage_time(t0, st, cst, dt), E, A, T, stage == 4);
             }
+            hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, s, sa, stage, dt, eps);
             LB_CHECK_LAUNCH();
         }
     return LB_OK;

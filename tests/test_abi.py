@@ -57,10 +57,10 @@ def test_basis_index_matches_oracle(oracle, N):
         assert oracle.index_of(N, oc, oj, ok) == i
 
 
-def test_basis_index_large_n_round_trip(oracle):
-    """N = 1024 (the largest N): every class boundary and a spread of interior indices."""
+@pytest.mark.parametrize("N", [1024, 2048])
+def test_basis_index_large_n_round_trip(oracle, N):
+    """Large N (2048 is the largest accepted): every class boundary and a spread of interior indices."""
     L = lb.load()
-    N = 1024
     M = N * N - 1
     P = N * (N - 1) // 2
     c, j, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

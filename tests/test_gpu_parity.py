@@ -47,7 +47,7 @@ def dev(x):
 # basis and structure constants (integer, bit-exact)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("N", [2, 3, 7, 64, 200, 1024])
+@pytest.mark.parametrize("N", [2, 3, 7, 64, 200, 1024, 2048])
 def test_basis_table_bit_exact(lb, ctx, oracle, N):
     print("[gpu] basis table N=%d" % N, flush=True)
     t = lb.lb_basis_table(ctx, N).cpu().numpy()
