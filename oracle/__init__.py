@@ -17,6 +17,8 @@ Functions (all arrays numpy, complex matrices as complex128):
   prepare_dense               Q = Q_H + Q_D rows and K (Eqs. (13)-(15))
   jump_setup, prepare_factored   the same for gamma = sum_p g_p l_p l_p^dagger
   rk4_dense, rk4_csr          classic RK4 for dv/dt = Qv + K (Eq. (10), step 3.1)
+  drive, drive_left, rk4_drive   the rocked dimer's square-wave drive and its RK4 (Sec. 3)
+  steady_state                Qv = -K, the asymptotic state rho_inf of Sec. 3 (dense solve)
 """
 from __future__ import annotations
 
@@ -248,3 +250,12 @@ def rk4_csr(rowptr, col, val, K, V, dt: float, steps: int) -> np.ndarray:
     M = len(rowptr) - 1
     _L().or_rk4_csr(M, _p(rowptr), _p(col), _p(val), _p(K), _p(V), V.shape[0], float(dt), int(steps))
     return V
+
+
+def steady_state(Q: np.ndarray, K: np.ndarray) -> np.ndarray:
+    """Stationary point of dv/dt = Qv + K (Eq. (10) with dv/dt = 0): the v with
+    Qv = -K, i.e. the expansion (Eq. (7)) of the asymptotic state rho_inf with
+    L(rho_inf) = 0 of Sec. 3. A dense LU solve (LAPACK through numpy)."""
+    Q = _c(Q, np.float64)
+    K = _c(K, np.float64)
+    return np.linalg.solve(Q, -K)
