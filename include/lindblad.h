@@ -50,6 +50,8 @@ extern "C" {
 #define LB_ERR_DEVICE (-4)        /* a HIP call failed; see lb_last_error() */
 #define LB_ERR_UNSUPPORTED (-5)   /* valid request this build cannot serve (e.g. too large) */
 #define LB_ERR_ADMISSION (-6)     /* a serving request does not fit the server's memory budget */
+#define LB_ERR_NO_CONVERGENCE (-7) /* an iterative solve stopped at its iteration limit before its
+                                      tolerance; the outputs hold the last iterate */
 
 #define LB_MAX_N 2048             /* largest Hilbert-space dimension accepted (dense inputs of that
                                      size would not fit in memory; the sparse path reaches it) */
@@ -228,6 +230,38 @@ int lindblad_propagate_batched(lb_ctx* ctx, int R, int64_t M, const double* cons
  * afterwards; otherwise identical to lindblad_propagate. */
 int lindblad_propagate_graph(lb_ctx* ctx, int64_t M, const double* Q, const float* Q32, int64_t ldq,
                              const double* K, double* V, int B, double dt, int64_t steps, int precision);
+
+/* ------------------------------------------------------------------ */
+/* Steady state (Sec. 3: the asymptotic state rho_inf, L(rho_inf) = 0) */
+/* ------------------------------------------------------------------ */
+
+/* Outcome of an iterative solve. */
+typedef struct lb_solve_info {
+    int64_t iterations; /* Krylov iterations (one operator application each) over all cycles */
+    int64_t restarts;   /* cycles after the first */
+    double residual;    /* ||Q v + K||_2 / ||K||_2 of the returned v, recomputed from v */
+    int converged;      /* 1 if residual <= tol */
+} lb_solve_info;
+
+/* The stationary point of Eq. (10): v with Q v = -K, the coherence vector
+ * (Eq. (7)) of rho_inf. Dense Q (M rows, leading dimension ldq >= M) and K as
+ * written by lindblad_prepare; v (M doubles, device) receives the solution.
+ * FP64 restarted GMRES from v = 0 with classical Gram-Schmidt applied twice;
+ * the Krylov basis (restart + 1 vectors of M doubles) is allocated for the
+ * call and freed before it returns. Stops when ||Q v + K||_2 <= tol ||K||_2
+ * (K = 0 gives v = 0 at once) or after maxit iterations, restarting every
+ * `restart` iterations (1 <= restart <= 8192). Errors: LB_ERR_INVALID_ARG
+ * (null pointers, sizes, tol not in (0, 1), maxit < 1), LB_ERR_OOM (basis does
+ * not fit), LB_ERR_NO_CONVERGENCE (v holds the last iterate, *info filled).
+ * info may be NULL. Results are deterministic (fixed-order reductions). */
+int lindblad_steady_state(lb_ctx* ctx, int64_t M, const double* Q, int64_t ldq, const double* K,
+                          double* v, double tol, int64_t maxit, int64_t restart,
+                          lb_solve_info* info);
+
+/* The same for Q in CSR form (as written by lindblad_prepare_sparse_fill). */
+int lindblad_steady_state_csr(lb_ctx* ctx, int64_t M, const int64_t* rowptr, const int64_t* col,
+                              const double* val, const double* K, double* v, double tol,
+                              int64_t maxit, int64_t restart, lb_solve_info* info);
 
 /* ------------------------------------------------------------------ */
 /* Tuning                                                             */

@@ -24,7 +24,7 @@ __all__ = [
     "lb_expand", "lb_expand_pure", "lb_reconstruct",
     "lindblad_prepare", "lindblad_q_to_f32", "lindblad_propagate", "lindblad_propagate_batched",
     "lindblad_propagate_graph", "lindblad_propagate_csr", "lindblad_prepare_sparse",
-    "lindblad_propagate_csr_drive", "lindblad_autotune", "lindblad_tile_info", "lindblad_set_tile", "lindblad_time_stage", "Server",
+    "lindblad_propagate_csr_drive", "lindblad_steady_state", "lindblad_steady_state_csr", "lindblad_autotune", "lindblad_tile_info", "lindblad_set_tile", "lindblad_time_stage", "Server",
     "FP64", "FP32", "CHECK_HERMITIAN",
 ]
 
@@ -38,7 +38,7 @@ _LIB_PATH = os.path.join(_HERE, "_build", "liblindblad.so")
 _lib = None
 
 _ERRORS = {-1: "invalid argument", -2: "not Hermitian", -3: "out of memory", -4: "device error",
-           -5: "unsupported", -6: "admission"}
+           -5: "unsupported", -6: "admission", -7: "no convergence"}
 
 
 class LibraryMissing(RuntimeError):
@@ -101,6 +101,8 @@ def signatures():
         "lindblad_q_to_f32": [V, I64, V, I64, V],
         "lindblad_propagate_csr": [V, I64, V, V, V, V, V, I, D, I64],
         "lindblad_propagate_csr_drive": [V, I64, V, V, V, V, V, V, V, V, I, D, I64, D, D, D, D],
+        "lindblad_steady_state": [V, I64, V, I64, V, V, D, I64, I64, V],
+        "lindblad_steady_state_csr": [V, I64, V, V, V, V, V, D, I64, I64, V],
         "lindblad_propagate_batched": [V, I, I64, V, V, I64, V, V, I, D, I64, I],
         "lindblad_propagate_graph": [V, I64, V, V, I64, V, V, I, D, I64, I],
         "lindblad_autotune": [V, I64, V, V, I64, V, V, I, I],
@@ -397,6 +399,53 @@ def lindblad_propagate_csr(ctx: Context, rowptr, col, val, K, V, dt: float, step
     _check(load().lindblad_propagate_csr(ctx.handle, M, _ptr(rowptr), _ptr(col), _ptr(val), _ptr(K), _ptr(V),
                                          V.shape[0], float(dt), int(steps)))
     return V
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("restarts", ctypes.c_int64), ("residual", ctypes.c_double),
+                ("converged", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _steady_call(fn, args, check):
+    info = SolveInfo()
+    rc = fn(*args, ctypes.byref(info))
+    if rc != 0 and not (rc == -7 and not check):
+        _check(rc)
+    return info.as_dict()
+
+
+def lindblad_steady_state(ctx: Context, Q, K, tol: float = 1e-12, maxit: int = 4000, restart: int | None = None,
+                          check: bool = True):
+    """v with Q v = -K (dense Q, M x ldq), by FP64 GMRES on the device. Returns
+    (v, info) with info = {iterations, restarts, residual, converged}; a solve
+    that stops at maxit raises unless check is False."""
+    import torch
+    _need(Q, torch.float64, "Q")
+    _need(K, torch.float64, "K")
+    M = K.numel()
+    v = torch.empty(M, dtype=torch.float64, device=K.device)
+    info = _steady_call(load().lindblad_steady_state,
+                        (ctx.handle, M, _ptr(Q), Q.stride(0), _ptr(K), _ptr(v), float(tol), int(maxit),
+                         int(restart or min(maxit, 8192))), check)
+    return v, info
+
+
+def lindblad_steady_state_csr(ctx: Context, rowptr, col, val, K, tol: float = 1e-12, maxit: int = 4000,
+                              restart: int | None = None, check: bool = True):
+    """As lindblad_steady_state for Q in CSR form."""
+    import torch
+    _need(rowptr, torch.int64, "rowptr")
+    _need(val, torch.float64, "val")
+    _need(K, torch.float64, "K")
+    M = rowptr.numel() - 1
+    v = torch.empty(M, dtype=torch.float64, device=K.device)
+    info = _steady_call(load().lindblad_steady_state_csr,
+                        (ctx.handle, M, _ptr(rowptr), _ptr(col), _ptr(val), _ptr(K), _ptr(v), float(tol), int(maxit),
+                         int(restart or min(maxit, 8192))), check)
+    return v, info
 
 
 def lindblad_propagate_csr_drive(ctx: Context, Q0, Q1, K, V, dt: float, steps: int, t0: float, E: float, A: float,

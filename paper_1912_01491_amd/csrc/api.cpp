@@ -324,6 +324,37 @@ int lindblad_propagate_csr_drive(lb_ctx* c, int64_t M, const int64_t* rowptr0, c
                                        T);
 }
 
+static int steady_args(int64_t M, const double* K, const double* v, double tol, int64_t maxit, int64_t restart) {
+    if (!K || !v) return lb_fail(LB_ERR_INVALID_ARG, "null pointer");
+    if (M < 3) return lb_fail(LB_ERR_INVALID_ARG, "M too small");
+    if (!(tol > 0 && tol < 1)) return lb_fail(LB_ERR_INVALID_ARG, "tol must lie in (0, 1)");
+    if (maxit < 1 || restart < 1 || restart > 8192)
+        return lb_fail(LB_ERR_INVALID_ARG, "maxit >= 1 and 1 <= restart <= 8192 required");
+    return LB_OK;
+}
+
+int lindblad_steady_state(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, const double* K, double* v, double tol,
+                          int64_t maxit, int64_t restart, lb_solve_info* info) {
+    CHECK_CTX(c);
+    CHECK_PTR(Q);
+    int rc = steady_args(M, K, v, tol, maxit, restart);
+    if (rc) return rc;
+    if (ldq < M) return lb_fail(LB_ERR_INVALID_ARG, "ldq < M");
+    lb_solve_info local;
+    return lb_impl_steady_dense(c, M, Q, ldq, K, v, tol, maxit, restart, info ? info : &local);
+}
+
+int lindblad_steady_state_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int64_t* col, const double* val,
+                              const double* K, double* v, double tol, int64_t maxit, int64_t restart,
+                              lb_solve_info* info) {
+    CHECK_CTX(c);
+    CHECK_PTR(rowptr);
+    int rc = steady_args(M, K, v, tol, maxit, restart);
+    if (rc) return rc;
+    lb_solve_info local;
+    return lb_impl_steady_csr(c, M, rowptr, col, val, K, v, tol, maxit, restart, info ? info : &local);
+}
+
 int lindblad_propagate_batched(lb_ctx* c, int R, int64_t M, const double* const* Q, const float* const* Q32,
                                int64_t ldq, const double* const* K, double* const* V, int B, double dt,
                                int64_t steps, int precision) {

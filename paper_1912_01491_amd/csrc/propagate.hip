@@ -21,6 +21,8 @@
 // B-operand of two MFMAs whose A-operand is the two consecutive Q columns the
 // same lane loaded. The FP32 path interleaves by four.
 #include "lb_internal.h"
+#include "rowdot.h"
+#include "sell.h"
 
 #include <math.h>
 
@@ -31,7 +33,6 @@
 
 typedef double lb_double4 __attribute__((ext_vector_type(4)));
 typedef float lb_float4 __attribute__((ext_vector_type(4)));
-typedef double lb_double2v __attribute__((ext_vector_type(2)));
 typedef unsigned int lb_u4 __attribute__((ext_vector_type(4)));
 
 namespace {
@@ -727,44 +728,10 @@ __global__ __launch_bounds__(256) void k_gemv(const double* const* Qs, const dou
     const double* qrow[R];
 #pragma unroll
     for (int t = 0; t < R; ++t) {
-        acc[t] = 0.0;
         int64_t row = row0 + t;
         qrow[t] = Q + (row < M ? row : M - 1) * ldq;
     }
-    int64_t c = 2 * lane;
-    if (ALIGNED) {
-        for (; c + 1 < M; c += 128) {
-            const double2 x = *reinterpret_cast<const double2*>(Xin + c);
-#pragma unroll
-            for (int t = 0; t < R; ++t) {
-                lb_double2v q;
-                if (NT) q = __builtin_nontemporal_load((const lb_double2v __attribute__((address_space(1)))*)(qrow[t] + c));
-                else q = *reinterpret_cast<const lb_double2v*>(qrow[t] + c);
-                acc[t] = fma(q.x, x.x, acc[t]);
-                acc[t] = fma(q.y, x.y, acc[t]);
-            }
-        }
-    } else {
-        for (; c + 1 < M; c += 128) {
-            const double x0 = Xin[c], x1 = Xin[c + 1];
-#pragma unroll
-            for (int t = 0; t < R; ++t) {
-                acc[t] = fma(qrow[t][c], x0, acc[t]);
-                acc[t] = fma(qrow[t][c + 1], x1, acc[t]);
-            }
-        }
-    }
-    if (c < M) {
-        const double x0 = Xin[c];
-#pragma unroll
-        for (int t = 0; t < R; ++t) acc[t] = fma(qrow[t][c], x0, acc[t]);
-    }
-#pragma unroll
-    for (int t = 0; t < R; ++t) {
-        double v = acc[t];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        acc[t] = v;
-    }
+    wave_rowdots<R, ALIGNED, NT>(qrow, Xin, M, lane, acc);
     if (lane < R) {
         double kv = 0.0;
 #pragma unroll
@@ -859,21 +826,10 @@ __global__ __launch_bounds__(256) void k_rk4_small(const double* const* Qs, cons
 }
 
 // ---------------------------------------------------------------------------
-// Sparse RK4 stage: one launch per stage with the stage combination fused in.
-// The CSR rows the caller passes are regrouped once per call into slices of 64
-// consecutive rows (one wavefront, one row per lane), each slice stored entry-
-// major: entry k of the slice's rows sits at [k * 64 + lane], padded to the
-// slice's longest row with zero values whose column is the lane's own row. A
-// wavefront's column and value loads are then full contiguous lines, no
-// cross-lane reduction is needed, and entry k of neighbouring rows, which in
-// the pair ordering are neighbouring pairs, tends to gather neighbouring x.
-// Rows with more than kLongRow entries (the diagonal-generator rows and the
-// rows coupled to them, ~N entries) are left out of the slices and take one
-// block of 256 threads each, with a fixed-order block reduction.
+// Sparse RK4 stage: one launch per stage with the stage combination fused in,
+// over the slice layout of sell.h (one wavefront per 64-row slice, one block of
+// 256 threads per long row).
 // ---------------------------------------------------------------------------
-constexpr int kLongRow = 32;
-constexpr int kSlice = 64;
-constexpr int kChunk = 8;  // slice entries per lane loaded before their products
 
 // RK4 stage combination for one element, given k = (Q x + K)_i and the values
 // of v and of the accumulator loaded beforehand.
@@ -896,202 +852,35 @@ __device__ __forceinline__ void rk4_update(int stage, double h, double k, double
     Xout[i] = x;
 }
 
-// Slice widths (as 64 * entries, later scanned into offsets), the long-row
-// mask of each slice and the list of long rows. One wavefront per slice.
-__global__ __launch_bounds__(256) void k_sell_widths(int64_t M, int64_t S, const int64_t* rowptr,
-                                                     const int64_t* rowptr1, int64_t* off0, int64_t* off1,
-                                                     uint64_t* lmask, int* longrows, int* nlong) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t sl = r / kSlice;
-    if (sl >= S) return;  // whole wavefronts
-    int64_t len0 = 0, len1 = 0;
-    if (r < M) {
-        len0 = rowptr[r + 1] - rowptr[r];
-        if (rowptr1) len1 = rowptr1[r + 1] - rowptr1[r];
-    }
-    const bool lng = len0 > kLongRow;
-    if (lng) {
-        len0 = 0;
-        len1 = 0;
-        longrows[atomicAdd(nlong, 1)] = (int)r;
-    }
-    for (int o = kSlice / 2; o > 0; o >>= 1) {
-        len0 = max(len0, (int64_t)__shfl_xor(len0, o, kSlice));
-        len1 = max(len1, (int64_t)__shfl_xor(len1, o, kSlice));
-    }
-    const uint64_t mask = __ballot(lng);
-    if ((r & (kSlice - 1)) == 0) {
-        off0[sl] = kSlice * len0;
-        off1[sl] = kSlice * len1;
-        lmask[sl] = mask;
-    }
-}
-
-// Exclusive scan of n sizes in place, total in a[n]; one block of 1024 threads.
-__device__ void block_scan_inplace(int64_t n, int64_t* a, int64_t* part) {
-    const int t = threadIdx.x;
-    const int64_t per = (n + 1023) / 1024;
-    const int64_t b0 = min(n, t * per), b1 = min(n, b0 + per);
-    int64_t sum = 0;
-    for (int64_t i = b0; i < b1; ++i) sum += a[i];
-    part[t] = sum;
-    __syncthreads();
-    if (t == 0) {
-        int64_t run = 0;
-        for (int i = 0; i < 1024; ++i) {
-            const int64_t v = part[i];
-            part[i] = run;
-            run += v;
-        }
-        a[n] = run;
-    }
-    __syncthreads();
-    int64_t run = part[t];
-    for (int64_t i = b0; i < b1; ++i) {
-        const int64_t v = a[i];
-        a[i] = run;
-        run += v;
-    }
-    __syncthreads();
-}
-
-__global__ __launch_bounds__(1024) void k_sell_scan(int64_t S, int64_t* off0, int64_t* off1) {
-    __shared__ int64_t part[1024];
-    block_scan_inplace(S, off0, part);
-    if (off1) block_scan_inplace(S, off1, part);
-}
-
-// One matrix into the slice layout: thread per row (rows past M and long rows
-// are all padding).
-__device__ __forceinline__ void sell_put(int64_t r, int64_t M, int64_t sl, bool lng, const int64_t* rowptr,
-                                         const int64_t* col, const double* val, const int64_t* off, int* scol,
-                                         double* sval) {
-    const int64_t o = off[sl], w = (off[sl + 1] - o) / kSlice;
-    int64_t e0 = 0, len = 0;
-    if (r < M && !lng) {
-        e0 = rowptr[r];
-        len = rowptr[r + 1] - e0;
-    }
-    const int pad = (int)(r < M ? r : M - 1);
-    const int lane = (int)(r & (kSlice - 1));
-    for (int64_t k = 0; k < w; ++k) {
-        const int64_t d = o + k * kSlice + lane;
-        scol[d] = k < len ? (int)col[e0 + k] : pad;
-        sval[d] = k < len ? val[e0 + k] : 0.0;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_sell_fill(int64_t M, int64_t S, const uint64_t* lmask, const int64_t* rowptr,
-                                                   const int64_t* col, const double* val, const int64_t* off0,
-                                                   int* scol0, double* sval0, const int64_t* rowptr1,
-                                                   const int64_t* col1, const double* val1, const int64_t* off1,
-                                                   int* scol1, double* sval1) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t sl = r / kSlice;
-    if (sl >= S) return;
-    const bool lng = (lmask[sl] >> (r & (kSlice - 1))) & 1;
-    sell_put(r, M, sl, lng, rowptr, col, val, off0, scol0, sval0);
-    if (rowptr1) sell_put(r, M, sl, lng, rowptr1, col1, val1, off1, scol1, sval1);
-}
-
-struct SellArgs {
-    int64_t M, S;
-    const int64_t* rowptr;  // CSR of Q0 and Q1, read by the long rows
-    const int64_t* col;
-    const double* val;
-    const int64_t* rowptr1;
-    const int64_t* col1;
-    const double* val1;
-    const int64_t* off0;  // slice layout of Q0 and Q1
-    const int* scol0;
-    const double* sval0;
-    const int64_t* off1;
-    const int* scol1;
-    const double* sval1;
-    const uint64_t* lmask;
-    const int* longrows;
-    int nlong;
+// The stage vectors of a sparse integration.
+struct SellStage {
     int B;
     const double* K;
     double* V;
     double* W;  // [accumulator | x ping | x pong], M*B each
 };
 
-// acc[j] += sum over slice entries [k, k + n) of value * x_j[column], in entry
-// order, for the first nb of SB states; FULL: n == kChunk.
-template <int SB, bool FULL>
-__device__ __forceinline__ void sell_chunk(const int* c0, const double* v0, int k, int n, const double* Xin,
-                                           int64_t M, int nb, double* acc) {
-    int cc[kChunk];
-    double vv[kChunk];
-#pragma unroll
-    for (int u = 0; u < kChunk; ++u)
-        if (FULL || u < n) {
-            cc[u] = c0[(int64_t)(k + u) * kSlice];
-            vv[u] = v0[(int64_t)(k + u) * kSlice];
-        }
-#pragma unroll
-    for (int j = 0; j < SB; ++j)
-        if (j < nb) {
-            const double* x = Xin + (int64_t)j * M;
-#pragma unroll
-            for (int u = 0; u < kChunk; ++u)
-                if (FULL || u < n) acc[j] = fma(vv[u], x[cc[u]], acc[j]);
-        }
-}
-
-template <int SB>
-__device__ __forceinline__ void sell_row(const int* c0, const double* v0, int w, const double* Xin, int64_t M,
-                                         int nb, double* acc) {
-    int k = 0;
-    for (; k + kChunk <= w; k += kChunk) sell_chunk<SB, true>(c0, v0, k, kChunk, Xin, M, nb, acc);
-    if (k < w) sell_chunk<SB, false>(c0, v0, k, w - k, Xin, M, nb, acc);
-}
-
 // DRIVE: k = (Q0 x) + eps (Q1 x) + K, the two sums formed separately.
 // SB: states per pass over a slice (1, or 4 for batches).
 template <bool DRIVE, int SB>
-__global__ __launch_bounds__(256) void k_sell_stage(SellArgs a, int stage, double h, double eps) {
+__global__ __launch_bounds__(256) void k_sell_stage(SellMat a, SellStage st, int stage, double h, double eps) {
     const int64_t M = a.M;
-    const int64_t n = M * a.B;
-    double* Acc = a.W;
-    const double* Xin = (stage & 1) ? a.W + n : a.W + 2 * n;
-    double* Xout = (stage & 1) ? a.W + 2 * n : a.W + n;
+    const int64_t n = M * st.B;
+    double* Acc = st.W;
+    const double* Xin = (stage & 1) ? st.W + n : st.W + 2 * n;
+    double* Xout = (stage & 1) ? st.W + 2 * n : st.W + n;
     if ((int)blockIdx.x < a.nlong) {
-        __shared__ double red[4], red1[4];
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         const int64_t row = a.longrows[blockIdx.x];
-        const int64_t e0 = a.rowptr[row], e1 = a.rowptr[row + 1];
-        for (int b = 0; b < a.B; ++b) {
-            const double* x = Xin + (int64_t)b * M;
-            double s0 = 0.0, s1 = 0.0;
-            int64_t e = e0 + threadIdx.x;
-            for (; e + 256 < e1; e += 512) {
-                s0 = fma(a.val[e], x[a.col[e]], s0);
-                s1 = fma(a.val[e + 256], x[a.col[e + 256]], s1);
-            }
-            if (e < e1) s0 = fma(a.val[e], x[a.col[e]], s0);
-            double sum = s0 + s1;
-            for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
-            double sd = 0.0;
-            if (DRIVE) {
-                for (int64_t f = a.rowptr1[row] + threadIdx.x; f < a.rowptr1[row + 1]; f += 256)
-                    sd = fma(a.val1[f], x[a.col1[f]], sd);
-                for (int o = 32; o > 0; o >>= 1) sd += __shfl_xor(sd, o, 64);
-            }
-            if (lane == 0) {
-                red[wave] = sum;
-                red1[wave] = sd;
-            }
-            __syncthreads();
+        for (int b = 0; b < st.B; ++b) {
+            double q0, q1;
+            block_row_dots<DRIVE>(a, row, Xin + (int64_t)b * M, q0, q1);
             if (threadIdx.x == 0) {
                 const int64_t i = (int64_t)b * M + row;
-                double k = (red[0] + red[1]) + (red[2] + red[3]);
-                if (DRIVE) k += eps * ((red1[0] + red1[1]) + (red1[2] + red1[3]));
-                k += a.K[row];
-                rk4_update(stage, h, k, a.V[i], stage > 1 ? Acc[i] : 0.0, i, a.V, Acc, Xout);
+                double k = q0;
+                if (DRIVE) k += eps * q1;
+                k += st.K[row];
+                rk4_update(stage, h, k, st.V[i], stage > 1 ? Acc[i] : 0.0, i, st.V, Acc, Xout);
             }
-            __syncthreads();
         }
         return;
     }
@@ -1114,16 +903,16 @@ __global__ __launch_bounds__(256) void k_sell_stage(SellArgs a, int stage, doubl
         c1 = a.scol1 + o1 + lane;
         v1 = a.sval1 + o1 + lane;
     }
-    const double kr = mine ? a.K[r] : 0.0;
-    for (int b0 = 0; b0 < a.B; b0 += SB) {
-        const int nb = min(SB, a.B - b0);
+    const double kr = mine ? st.K[r] : 0.0;
+    for (int b0 = 0; b0 < st.B; b0 += SB) {
+        const int nb = min(SB, st.B - b0);
         double vv[SB], aa[SB], acc[SB], accd[SB];
 #pragma unroll
         for (int j = 0; j < SB; ++j) {
             vv[j] = aa[j] = acc[j] = accd[j] = 0.0;
             if (j < nb && mine) {
                 const int64_t i = (int64_t)(b0 + j) * M + r;
-                vv[j] = a.V[i];
+                vv[j] = st.V[i];
                 if (stage > 1) aa[j] = Acc[i];
             }
         }
@@ -1135,7 +924,7 @@ __global__ __launch_bounds__(256) void k_sell_stage(SellArgs a, int stage, doubl
             if (j < nb && mine) {
                 double k = acc[j];
                 if (DRIVE) k += eps * accd[j];
-                rk4_update(stage, h, k + kr, vv[j], aa[j], (int64_t)(b0 + j) * M + r, a.V, Acc, Xout);
+                rk4_update(stage, h, k + kr, vv[j], aa[j], (int64_t)(b0 + j) * M + r, st.V, Acc, Xout);
             }
     }
 }
@@ -1719,96 +1508,28 @@ static int csr_propagate(lb_ctx* c, int64_t M, const int64_t* rowptr, const int6
     hipStream_t s = c->stream;
     if (steps == 0) return LB_OK;
     const bool drive = rowptr1 != nullptr;
-    // numbers of stored entries: 32-bit slice columns
-    int64_t nnz = 0, nnz1 = 0;
-    LB_HIP(hipMemcpyAsync(&nnz, rowptr + M, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    if (drive) LB_HIP(hipMemcpyAsync(&nnz1, rowptr1 + M, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    LB_HIP(hipStreamSynchronize(s));
-    if (nnz < 0 || nnz >= ((int64_t)1 << 31) || nnz1 < 0 || nnz1 >= ((int64_t)1 << 31))
-        return lb_fail(LB_ERR_UNSUPPORTED, "nnz=%lld / %lld out of range", (long long)nnz, (long long)nnz1);
     const int64_t n = M * B;
-    const int64_t S = (M + kSlice - 1) / kSlice;
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        size_t o = off;
-        off = lb_align(off + (bytes > 0 ? bytes : 1), 256);
-        return o;
-    };
-    // phase 1 (sizes known from M): slice offsets, long-row masks and list
-    const size_t o_off0 = take(sizeof(int64_t) * (size_t)(S + 1));
-    const size_t o_off1 = take(sizeof(int64_t) * (size_t)(S + 1));
-    const size_t o_mask = take(sizeof(uint64_t) * (size_t)S);
-    const size_t o_long = take(sizeof(int) * (size_t)M);
-    const size_t o_nl = take(sizeof(int));
-    const size_t o_w = take(sizeof(double) * 3 * n);
-    const size_t fixed = off;
-    int rc = lb_ws_reserve(c, fixed);
+    SellMat m;
+    size_t o_w = 0;
+    int rc = sell_build(c, M, rowptr, col, val, rowptr1, col1, val1, sizeof(double) * 3 * (size_t)n, &m, &o_w);
     if (rc) return rc;
-    int hl = 0;
-    int64_t tot0 = 0, tot1 = 0;
-    const unsigned rgrid = (unsigned)lb_blocks(S * kSlice, 256);
-    for (int pass = 0; pass < 2; ++pass) {
-        char* ws = (char*)c->ws;
-        int64_t* off0 = (int64_t*)(ws + o_off0);
-        int64_t* off1 = (int64_t*)(ws + o_off1);
-        int* nlong = (int*)(ws + o_nl);
-        LB_HIP(hipMemsetAsync(nlong, 0, sizeof(int), s));
-        hipLaunchKernelGGL(k_sell_widths, dim3(rgrid), dim3(256), 0, s, M, S, rowptr, drive ? rowptr1 : nullptr,
-                           off0, off1, (uint64_t*)(ws + o_mask), (int*)(ws + o_long), nlong);
-        LB_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_sell_scan, dim3(1), dim3(1024), 0, s, S, off0, drive ? off1 : nullptr);
-        LB_CHECK_LAUNCH();
-        LB_HIP(hipMemcpyAsync(&hl, nlong, sizeof(int), hipMemcpyDeviceToHost, s));
-        LB_HIP(hipMemcpyAsync(&tot0, off0 + S, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        if (drive) LB_HIP(hipMemcpyAsync(&tot1, off1 + S, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        LB_HIP(hipStreamSynchronize(s));
-        off = fixed;
-        take(sizeof(int) * (size_t)tot0);
-        take(sizeof(double) * (size_t)tot0);
-        take(sizeof(int) * (size_t)tot1);
-        take(sizeof(double) * (size_t)tot1);
-        const size_t need = off;
-        if (need <= c->ws_bytes) break;
-        // the workspace grows: its contents go, so the offsets are formed again
-        rc = lb_ws_reserve(c, need);
-        if (rc) return rc;
-    }
-    off = fixed;
-    const size_t o_sc0 = take(sizeof(int) * (size_t)tot0);
-    const size_t o_sv0 = take(sizeof(double) * (size_t)tot0);
-    const size_t o_sc1 = take(sizeof(int) * (size_t)tot1);
-    const size_t o_sv1 = take(sizeof(double) * (size_t)tot1);
-    if (off > c->ws_bytes) return lb_fail(LB_ERR_DEVICE, "slice layout exceeds the workspace");
-    char* ws = (char*)c->ws;
-    const int64_t* off0 = (const int64_t*)(ws + o_off0);
-    const int64_t* off1 = (const int64_t*)(ws + o_off1);
-    const uint64_t* lmask = (const uint64_t*)(ws + o_mask);
-    int* scol0 = (int*)(ws + o_sc0);
-    double* sval0 = (double*)(ws + o_sv0);
-    int* scol1 = (int*)(ws + o_sc1);
-    double* sval1 = (double*)(ws + o_sv1);
-    double* W = (double*)(ws + o_w);
-    hipLaunchKernelGGL(k_sell_fill, dim3(rgrid), dim3(256), 0, s, M, S, lmask, rowptr, col, val, off0, scol0, sval0,
-                       drive ? rowptr1 : nullptr, col1, val1, off1, scol1, sval1);
-    LB_CHECK_LAUNCH();
+    double* W = (double*)((char*)c->ws + o_w);
     hipLaunchKernelGGL(k_copy, dim3(lb_blocks(n, 256)), dim3(256), 0, s, (const double*)V, W + n, n);
     LB_CHECK_LAUNCH();
-    SellArgs sa{M,     S,     rowptr, col,   val,   rowptr1,        col1,       val1, off0, scol0,
-                sval0, off1,  scol1,  sval1, lmask, (const int*)(ws + o_long), hl,   B,    K,    V,
-                W};
-    const unsigned grid = (unsigned)hl + (unsigned)((S + 3) / 4);
-    typedef void (*stage_fn)(SellArgs, int, double, double);
+    const SellStage st{B, K, V, W};
+    const unsigned grid = (unsigned)m.nlong + (unsigned)((m.S + 3) / 4);
+    typedef void (*stage_fn)(SellMat, SellStage, int, double, double);
     const stage_fn fn = drive ? (B == 1 ? k_sell_stage<true, 1> : k_sell_stage<true, 4>)
                               : (B == 1 ? k_sell_stage<false, 1> : k_sell_stage<false, 4>);
-    for (int64_t st = 0; st < steps; ++st)
+    for (int64_t k = 0; k < steps; ++k)
         for (int stage = 1; stage <= 4; ++stage) {
             double eps = 0.0;
             if (drive) {
                 // stages seen from inside the step: t_k and t_k + dt/2 from the right, t_k + dt from the left
                 const double cst = stage == 1 ? 0.0 : (stage == 4 ? 1.0 : 0.5);
-                eps = drive_value(stage_time(t0, st, cst, dt), E, A, T, stage == 4);
+                eps = drive_value(stage_time(t0, k, cst, dt), E, A, T, stage == 4);
             }
-            hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, s, sa, stage, dt, eps);
+            hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, s, m, st, stage, dt, eps);
             LB_CHECK_LAUNCH();
         }
     return LB_OK;

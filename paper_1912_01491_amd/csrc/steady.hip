@@ -1,0 +1,404 @@
+// Steady state of dv/dt = Q v + K: the v with Q v = -K, i.e. the expansion
+// (Eq. (7)) of the asymptotic state rho_inf, L(rho_inf) = 0, of Sec. 3 (the
+// ODE of Eq. (10) at rest). FP64 throughout.
+//
+// Restarted GMRES with right preconditioning, x = P^-1 y: the Krylov basis is
+// kept whole in HBM (restart lengths in the thousands fit in 288 GB), and each
+// iteration orthogonalises by classical Gram-Schmidt applied twice, which
+// streams the basis with full-line loads instead of the one-vector-at-a-time
+// dependence of modified Gram-Schmidt:
+//   k_dots     partial dot products of w with every basis vector, per wave;
+//   k_reduce   their sums in a fixed order (deterministic, no atomics);
+//   k_update   w -= V h (and the partial sums of |w|^2 for the norm).
+// The operator is the dense row-dot GEMV (one wavefront per row group, as the
+// one-state RK4 stage) or the sliced sparse product. The small Hessenberg
+// least-squares problem (Givens rotations, back substitution) is solved on the
+// host from the column each iteration copies back.
+#include "lb_internal.h"
+#include "rowdot.h"
+#include "sell.h"
+
+#include <math.h>
+
+#include <vector>
+
+namespace {
+
+constexpr int kDotE = 4;                  // rows per thread in the basis kernels
+constexpr int kDotRows = 256 * kDotE;     // rows per block
+
+// y = Q x, dense, R rows per wavefront.
+template <int R, bool ALIGNED, bool NT>
+__global__ __launch_bounds__(256) void k_mv_dense(const double* Q, int64_t M, int64_t ldq, const double* x,
+                                                  double* y) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * R;
+    if (row0 >= M) return;
+    double acc[R];
+    const double* qrow[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const int64_t row = row0 + t;
+        qrow[t] = Q + (row < M ? row : M - 1) * ldq;
+    }
+    wave_rowdots<R, ALIGNED, NT>(qrow, x, M, lane, acc);
+    if (lane < R) {
+        double kv = 0.0;
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+            if (t == lane) kv = acc[t];
+        if (row0 + lane < M) y[row0 + lane] = kv;
+    }
+}
+
+// y = Q x, slice layout: one wavefront per slice, one block per long row.
+__global__ __launch_bounds__(256) void k_mv_sell(SellMat a, const double* x, double* y) {
+    if ((int)blockIdx.x < a.nlong) {
+        const int64_t row = a.longrows[blockIdx.x];
+        double q0, q1;
+        block_row_dots<false>(a, row, x, q0, q1);
+        if (threadIdx.x == 0) y[row] = q0;
+        return;
+    }
+    const int sl = __builtin_amdgcn_readfirstlane((int)((blockIdx.x - a.nlong) * 4 + (threadIdx.x >> 6)));
+    if (sl >= a.S) return;
+    const int lane = threadIdx.x & (kSlice - 1);
+    const int64_t r = (int64_t)sl * kSlice + lane;
+    const bool mine = r < a.M && !((a.lmask[sl] >> lane) & 1);
+    const int64_t o0 = a.off0[sl];
+    const int w0 = (int)((a.off0[sl + 1] - o0) / kSlice);
+    double acc[1] = {0.0};
+    sell_row<1>(a.scol0 + o0 + lane, a.sval0 + o0 + lane, w0, x, a.M, 1, acc);
+    if (mine) y[r] = acc[0];
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// part[j * nparts + p] = sum over the rows of wave p of V_j[i] w[i], j < k.
+__global__ __launch_bounds__(256) void k_dots(const double* V, int64_t ldv, int k, int64_t M, const double* w,
+                                              double* part, int nparts) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kDotRows + threadIdx.x;
+    double wv[kDotE];
+#pragma unroll
+    for (int e = 0; e < kDotE; ++e) {
+        const int64_t i = base + e * 256;
+        wv[e] = i < M ? w[i] : 0.0;
+    }
+    const int p = blockIdx.x * 4 + wave;
+    int j = 0;
+    for (; j + 1 < k; j += 2) {
+        const double* v0 = V + (int64_t)j * ldv;
+        const double* v1 = v0 + ldv;
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int e = 0; e < kDotE; ++e) {
+            const int64_t i = base + e * 256;
+            if (i < M) {
+                a0 = fma(v0[i], wv[e], a0);
+                a1 = fma(v1[i], wv[e], a1);
+            }
+        }
+        a0 = wave_sum(a0);
+        a1 = wave_sum(a1);
+        if (lane == 0) {
+            part[(int64_t)j * nparts + p] = a0;
+            part[(int64_t)(j + 1) * nparts + p] = a1;
+        }
+    }
+    if (j < k) {
+        const double* v0 = V + (int64_t)j * ldv;
+        double a0 = 0.0;
+#pragma unroll
+        for (int e = 0; e < kDotE; ++e) {
+            const int64_t i = base + e * 256;
+            if (i < M) a0 = fma(v0[i], wv[e], a0);
+        }
+        a0 = wave_sum(a0);
+        if (lane == 0) part[(int64_t)j * nparts + p] = a0;
+    }
+}
+
+// out[j] = sum_p part[j * nparts + p] (SQRT: its square root), one wave per j,
+// lanes over p in a fixed order.
+template <bool SQRT>
+__global__ __launch_bounds__(256) void k_reduce(const double* part, int nparts, int k, double* out) {
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= k) return;
+    const double* pj = part + (int64_t)j * nparts;
+    double s = 0.0;
+    for (int p = lane; p < nparts; p += 64) s += pj[p];
+    s = wave_sum(s);
+    if (lane == 0) out[j] = SQRT ? sqrt(s) : s;
+}
+
+// w[i] -= sgn * sum_{j<k} h[j] V_j[i]; with NORM, part[p] = the sum of the new
+// w[i]^2 over the rows of wave p.
+template <bool NORM>
+__global__ __launch_bounds__(256) void k_update(const double* V, int64_t ldv, int k, int64_t M, const double* h,
+                                                double sgn, double* w, double* part) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kDotRows + threadIdx.x;
+    double s[kDotE];
+#pragma unroll
+    for (int e = 0; e < kDotE; ++e) s[e] = 0.0;
+    for (int j = 0; j < k; ++j) {
+        const double hj = h[j];
+        const double* vj = V + (int64_t)j * ldv;
+#pragma unroll
+        for (int e = 0; e < kDotE; ++e) {
+            const int64_t i = base + e * 256;
+            if (i < M) s[e] = fma(hj, vj[i], s[e]);
+        }
+    }
+    double nrm = 0.0;
+#pragma unroll
+    for (int e = 0; e < kDotE; ++e) {
+        const int64_t i = base + e * 256;
+        if (i < M) {
+            const double x = w[i] - sgn * s[e];
+            w[i] = x;
+            nrm = fma(x, x, nrm);
+        }
+    }
+    if (NORM) {
+        nrm = wave_sum(nrm);
+        if (lane == 0) part[blockIdx.x * 4 + wave] = nrm;
+    }
+}
+
+// out = a * x + b * y (elementwise); out may alias x or y.
+__global__ void k_axpby(int64_t M, double a, const double* x, double b, const double* y, double* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < M) out[i] = a * x[i] + (y ? b * y[i] : 0.0);
+}
+
+// out = x / d[0]
+__global__ void k_divide(int64_t M, const double* x, const double* d, double* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < M) out[i] = x[i] / d[0];
+}
+
+// The operator y = Q x of either form.
+struct Op {
+    bool sparse;
+    const double* Q;
+    int64_t ldq;
+    bool aligned, nt;
+    SellMat m;
+};
+
+static int op_apply(const Op& op, int64_t M, const double* x, double* y, hipStream_t s) {
+    if (op.sparse) {
+        const unsigned grid = (unsigned)op.m.nlong + (unsigned)((op.m.S + 3) / 4);
+        hipLaunchKernelGGL(k_mv_sell, dim3(grid), dim3(256), 0, s, op.m, x, y);
+        LB_CHECK_LAUNCH();
+        return LB_OK;
+    }
+    const int RW = M >= 8 * 8192 ? 8 : M >= 4 * 8192 ? 4 : M >= 2 * 8192 ? 2 : 1;
+    const unsigned gx = lb_blocks((M + RW - 1) / RW, 4);
+    typedef void (*mv_fn)(const double*, int64_t, int64_t, const double*, double*);
+    mv_fn fn;
+    if (!op.aligned) fn = RW == 8 ? k_mv_dense<8, false, false> : RW == 4 ? k_mv_dense<4, false, false>
+                        : RW == 2 ? k_mv_dense<2, false, false> : k_mv_dense<1, false, false>;
+    else if (op.nt) fn = RW == 8 ? k_mv_dense<8, true, true> : RW == 4 ? k_mv_dense<4, true, true>
+                       : RW == 2 ? k_mv_dense<2, true, true> : k_mv_dense<1, true, true>;
+    else fn = RW == 8 ? k_mv_dense<8, true, false> : RW == 4 ? k_mv_dense<4, true, false>
+            : RW == 2 ? k_mv_dense<2, true, false> : k_mv_dense<1, true, false>;
+    hipLaunchKernelGGL(fn, dim3(gx), dim3(256), 0, s, op.Q, M, op.ldq, x, y);
+    LB_CHECK_LAUNCH();
+    return LB_OK;
+}
+
+// Device buffers of one solve, freed on every exit.
+struct SolveBufs {
+    double* V = nullptr;  // (m + 1) basis vectors, stride ldv
+    double* aux = nullptr;
+    ~SolveBufs() {
+        if (V) (void)hipFree(V);
+        if (aux) (void)hipFree(aux);
+    }
+};
+
+static int gmres(lb_ctx* c, int64_t M, const Op& op, const double* K, double* v, double tol, int64_t maxit,
+                 int64_t restart, lb_solve_info* info) {
+    hipStream_t s = c->stream;
+    const int64_t m = restart < maxit ? restart : maxit;
+    const int64_t ldv = (M + 31) / 32 * 32;
+    const int nrb = (int)lb_blocks(M, kDotRows);
+    const int nparts = 4 * nrb;
+    SolveBufs b;
+    if (hipMalloc(&b.V, sizeof(double) * (size_t)(m + 1) * ldv) != hipSuccess) {
+        (void)hipGetLastError();
+        b.V = nullptr;
+        return lb_fail(LB_ERR_OOM, "Krylov basis of %lld vectors of %lld doubles does not fit", (long long)(m + 1),
+                       (long long)M);
+    }
+    // aux: w, x, r | part ((m + 1) * nparts) | h1, h2 (m + 1 each) | norm (1) | y (m)
+    const size_t n_aux = 3 * (size_t)ldv + (size_t)(m + 1) * nparts + 2 * (size_t)(m + 1) + 1 + (size_t)m;
+    if (hipMalloc(&b.aux, sizeof(double) * n_aux) != hipSuccess) {
+        (void)hipGetLastError();
+        b.aux = nullptr;
+        return lb_fail(LB_ERR_OOM, "GMRES work space of %zu doubles does not fit", n_aux);
+    }
+    double* w = b.aux;
+    double* x = w + ldv;
+    double* r = x + ldv;
+    double* part = r + ldv;
+    double* h1 = part + (size_t)(m + 1) * nparts;
+    double* h2 = h1 + (m + 1);
+    double* nrm = h2 + (m + 1);
+    double* yd = nrm + 1;
+    const unsigned eg = lb_blocks(M, 256);
+    auto norm_of = [&](double* vec, double* out) -> int {
+        // ||vec|| into out[0] on the device
+        hipLaunchKernelGGL(k_dots, dim3(nrb), dim3(256), 0, s, vec, ldv, 1, M, vec, part, nparts);
+        LB_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_reduce<true>, dim3(1), dim3(256), 0, s, part, nparts, 1, out);
+        LB_CHECK_LAUNCH();
+        return LB_OK;
+    };
+    auto fetch = [&](const double* dev, double* host, size_t n) -> int {
+        LB_HIP(hipMemcpyAsync(host, dev, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        LB_HIP(hipStreamSynchronize(s));
+        return LB_OK;
+    };
+    int rc;
+    // ||K||: the scale of the residual
+    double knorm = 0.0;
+    LB_HIP(hipMemcpyAsync(r, K, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+    if ((rc = norm_of(r, nrm)) || (rc = fetch(nrm, &knorm, 1))) return rc;
+    LB_HIP(hipMemsetAsync(x, 0, sizeof(double) * M, s));
+    info->iterations = 0;
+    info->restarts = 0;
+    info->residual = 0.0;
+    info->converged = 0;
+    if (knorm == 0.0) {  // K = 0: v = 0 is the solution
+        LB_HIP(hipMemcpyAsync(v, x, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+        LB_HIP(hipStreamSynchronize(s));
+        info->converged = 1;
+        return LB_OK;
+    }
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), hc2(m + 1), y(m);
+    int64_t total = 0;
+    for (;;) {
+        // r = -K - Q x
+        if ((rc = op_apply(op, M, x, w, s))) return rc;
+        hipLaunchKernelGGL(k_axpby, dim3(eg), dim3(256), 0, s, M, -1.0, K, -1.0, (const double*)w, r);
+        LB_CHECK_LAUNCH();
+        double beta = 0.0;
+        if ((rc = norm_of(r, nrm)) || (rc = fetch(nrm, &beta, 1))) return rc;
+        info->residual = beta / knorm;
+        if (beta <= tol * knorm) {
+            info->converged = 1;
+            break;
+        }
+        if (total >= maxit) break;
+        hipLaunchKernelGGL(k_divide, dim3(eg), dim3(256), 0, s, M, (const double*)r, (const double*)nrm, b.V);
+        LB_CHECK_LAUNCH();
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int64_t j = 0;
+        bool done = false;
+        for (; j < m && total < maxit && !done; ++j, ++total) {
+            double* vj = b.V + j * ldv;
+            double* vn = b.V + (j + 1) * ldv;
+            if ((rc = op_apply(op, M, vj, w, s))) return rc;
+            const int k = (int)(j + 1);
+            // two passes of classical Gram-Schmidt
+            hipLaunchKernelGGL(k_dots, dim3(nrb), dim3(256), 0, s, (const double*)b.V, ldv, k, M, (const double*)w,
+                               part, nparts);
+            LB_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_reduce<false>, dim3(lb_blocks(k, 4)), dim3(256), 0, s, (const double*)part, nparts,
+                               k, h1);
+            LB_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_update<false>, dim3(nrb), dim3(256), 0, s, (const double*)b.V, ldv, k, M,
+                               (const double*)h1, 1.0, w, part);
+            LB_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_dots, dim3(nrb), dim3(256), 0, s, (const double*)b.V, ldv, k, M, (const double*)w,
+                               part, nparts);
+            LB_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_reduce<false>, dim3(lb_blocks(k, 4)), dim3(256), 0, s, (const double*)part, nparts,
+                               k, h2);
+            LB_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_update<true>, dim3(nrb), dim3(256), 0, s, (const double*)b.V, ldv, k, M,
+                               (const double*)h2, 1.0, w, part);
+            LB_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_reduce<true>, dim3(1), dim3(256), 0, s, (const double*)part, nparts, 1, nrm);
+            LB_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_divide, dim3(eg), dim3(256), 0, s, M, (const double*)w, (const double*)nrm, vn);
+            LB_CHECK_LAUNCH();
+            LB_HIP(hipMemcpyAsync(hcol.data(), h1, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+            LB_HIP(hipMemcpyAsync(hc2.data(), h2, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+            LB_HIP(hipMemcpyAsync(&hcol[k], nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+            LB_HIP(hipStreamSynchronize(s));
+            double* Hj = &H[(size_t)j * (m + 1)];  // column j, rows 0..j+1
+            for (int i = 0; i < k; ++i) Hj[i] = hcol[i] + hc2[i];
+            Hj[k] = hcol[k];
+            // previous rotations, then the one that zeroes H[j+1][j]
+            for (int64_t i = 0; i < j; ++i) {
+                const double a = Hj[i], bb = Hj[i + 1];
+                Hj[i] = cs[i] * a + sn[i] * bb;
+                Hj[i + 1] = -sn[i] * a + cs[i] * bb;
+            }
+            const double a = Hj[j], bb = Hj[j + 1];
+            const double den = hypot(a, bb);
+            cs[j] = den > 0 ? a / den : 1.0;
+            sn[j] = den > 0 ? bb / den : 0.0;
+            Hj[j] = den;
+            Hj[j + 1] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            if (fabs(g[j + 1]) <= tol * knorm || hcol[k] == 0.0) done = true;
+        }
+        // y = R^-1 g, x += V y
+        const int64_t k = j;
+        for (int64_t i = k - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int64_t l = i + 1; l < k; ++l) t -= H[(size_t)l * (m + 1) + i] * y[l];
+            const double d = H[(size_t)i * (m + 1) + i];
+            y[i] = d != 0.0 ? t / d : 0.0;
+        }
+        LB_HIP(hipMemcpyAsync(yd, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_update<false>, dim3(nrb), dim3(256), 0, s, (const double*)b.V, ldv, (int)k, M,
+                           (const double*)yd, -1.0, x, part);
+        LB_CHECK_LAUNCH();
+        info->iterations = total;
+        ++info->restarts;
+    }
+    LB_HIP(hipMemcpyAsync(v, x, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+    LB_HIP(hipStreamSynchronize(s));
+    info->iterations = total;
+    info->restarts = info->restarts > 0 ? info->restarts - 1 : 0;
+    if (!info->converged)
+        return lb_fail(LB_ERR_NO_CONVERGENCE, "GMRES stopped after %lld iterations at relative residual %.3e",
+                       (long long)total, info->residual);
+    return LB_OK;
+}
+
+}  // namespace
+
+int lb_impl_steady_dense(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, const double* K, double* v, double tol,
+                         int64_t maxit, int64_t restart, lb_solve_info* info) {
+    Op op;
+    op.sparse = false;
+    op.Q = Q;
+    op.ldq = ldq;
+    op.aligned = ((uintptr_t)Q % 16 == 0) && ldq % 2 == 0;
+    op.nt = op.aligned && ((uintptr_t)Q % 128 == 0) && ldq % 16 == 0;
+    return gmres(c, M, op, K, v, tol, maxit, restart, info);
+}
+
+int lb_impl_steady_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int64_t* col, const double* val,
+                       const double* K, double* v, double tol, int64_t maxit, int64_t restart, lb_solve_info* info) {
+    Op op;
+    op.sparse = true;
+    size_t extra = 0;
+    int rc = sell_build(c, M, rowptr, col, val, nullptr, nullptr, nullptr, 0, &op.m, &extra);
+    if (rc) return rc;
+    return gmres(c, M, op, K, v, tol, maxit, restart, info);
+}

@@ -106,3 +106,20 @@ def test_request_struct_layout_matches_header(tmp_path):
     R = lb._Request
     want = [ctypes.sizeof(R), R.L.offset, R.V0.offset, R.precision.offset, R.system.offset]
     assert got == want
+
+
+def test_solve_info_layout_matches_header(tmp_path):
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    src = tmp_path / "info.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "lindblad.h"\n'
+                   'int main(void) { printf("%zu %zu %zu %zu\\n", sizeof(lb_solve_info), '
+                   'offsetof(lb_solve_info, restarts), offsetof(lb_solve_info, residual), '
+                   'offsetof(lb_solve_info, converged)); return 0; }\n')
+    exe = tmp_path / "info"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    S = lb.SolveInfo
+    assert got == [ctypes.sizeof(S), S.restarts.offset, S.residual.offset, S.converged.offset]

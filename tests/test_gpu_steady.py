@@ -1,0 +1,157 @@
+"""GPU steady state v_inf (Q v = -K, the asymptotic state rho_inf of Sec. 3)
+against the oracle's dense solve, for Q prepared on the device, dense (random
+Lindbladians) and CSR (the dimer), through the C ABI. The solver stops at a
+relative residual of 1e-13; its error in v is that times the conditioning of
+Q, so parity is asked at 1e-10 normwise (R12) where the oracle can solve, and
+through the residual and the physics of rho_inf beyond."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from paper_1912_01491_amd import workloads as wl  # noqa: E402
+
+TOL = 1e-13
+RTOL = 1e-10
+
+
+def rel(x, ref):
+    return float(np.abs(np.asarray(x) - ref).max() / np.abs(ref).max())
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import paper_1912_01491_amd as lb
+    lb.load()
+    return lb
+
+
+@pytest.fixture(scope="module")
+def ctx(lb):
+    c = lb.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def dcsr(A):
+    return tuple(torch.from_numpy(x).cuda() for x in wl.to_csr(A))
+
+
+@pytest.mark.parametrize("N", [2, 3, 8, 20, 45])
+def test_dense_random_matches_oracle(lb, ctx, oracle, N):
+    print("[gpu] steady state, dense random N=%d" % N, flush=True)
+    H, gamma = wl.random_lindbladian(N, 70 + N)
+    Q, K = lb.lindblad_prepare(ctx, dev(H), dev(gamma))
+    v, info = lb.lindblad_steady_state(ctx, Q, K, tol=TOL)
+    assert info["converged"] == 1 and info["residual"] <= TOL
+    Qo, Ko = oracle.prepare_dense(H, gamma)
+    vo = oracle.steady_state(Qo, Ko)
+    assert rel(v.cpu().numpy(), vo) < RTOL
+    rho = oracle.reconstruct(N, v.cpu().numpy())
+    assert np.linalg.eigvalsh(rho).min() > -1e-12
+
+
+@pytest.mark.parametrize("N", [3, 12, 20])
+def test_sparse_dimer_matches_oracle(lb, ctx, oracle, N):
+    print("[gpu] steady state, CSR dimer N=%d" % N, flush=True)
+    H, rates, Ls = wl.dimer_model(N)
+    rp, col, val, K = lb.lindblad_prepare_sparse(ctx, N, dcsr(H), rates, [dcsr(L) for L in Ls])
+    v, info = lb.lindblad_steady_state_csr(ctx, rp, col, val, K, tol=TOL)
+    assert info["converged"] == 1
+    M = N * N - 1
+    Qo, Ko = oracle.prepare_factored(H, rates, Ls, np.arange(M))
+    vo = oracle.steady_state(Qo, Ko)
+    assert rel(v.cpu().numpy(), vo) < RTOL
+
+
+def test_dense_and_csr_forms_agree(lb, ctx, oracle):
+    """The same Q (a dimer, densified on the device) through both operators."""
+    N = 12
+    H, rates, Ls = wl.dimer_model(N)
+    rp, col, val, K = lb.lindblad_prepare_sparse(ctx, N, dcsr(H), rates, [dcsr(L) for L in Ls])
+    M = N * N - 1
+    rows = torch.repeat_interleave(torch.arange(M, device="cuda"), torch.diff(rp))
+    Qd = torch.zeros((M, M), dtype=torch.float64, device="cuda")
+    Qd[rows, col] = val
+    vs, _ = lb.lindblad_steady_state_csr(ctx, rp, col, val, K, tol=TOL)
+    vd, _ = lb.lindblad_steady_state(ctx, Qd, K, tol=TOL)
+    assert rel(vd.cpu().numpy(), vs.cpu().numpy()) < RTOL
+
+
+def test_restarted_equals_tolerance(lb, ctx, oracle):
+    """Short restart cycles reach the same solution."""
+    N = 8
+    H, gamma = wl.random_lindbladian(N, 5)
+    Q, K = lb.lindblad_prepare(ctx, dev(H), dev(gamma))
+    v, info = lb.lindblad_steady_state(ctx, Q, K, tol=TOL, restart=7)
+    assert info["converged"] == 1 and info["restarts"] >= 1
+    vo = oracle.steady_state(*oracle.prepare_dense(H, gamma))
+    assert rel(v.cpu().numpy(), vo) < RTOL
+
+
+def test_deterministic(lb, ctx):
+    N = 20
+    H, gamma = wl.random_lindbladian(N, 9)
+    Q, K = lb.lindblad_prepare(ctx, dev(H), dev(gamma))
+    a, _ = lb.lindblad_steady_state(ctx, Q, K, tol=TOL)
+    b, _ = lb.lindblad_steady_state(ctx, Q, K, tol=TOL)
+    assert torch.equal(a, b)
+
+
+def test_unital_dissipator_gives_zero(lb, ctx):
+    """gamma = c 1: K = 0, so v = 0 without iterations."""
+    N = 6
+    M = N * N - 1
+    Q, K = lb.lindblad_prepare(ctx, dev(wl.gue_hamiltonian(N, 1)), dev(0.3 * np.eye(M, dtype=np.complex128)))
+    v, info = lb.lindblad_steady_state(ctx, Q, K, tol=TOL)
+    assert info["iterations"] == 0 and info["converged"] == 1
+    assert float(v.abs().max()) == 0.0
+
+
+def test_iteration_limit_is_reported(lb, ctx):
+    N = 20
+    H, rates, Ls = wl.dimer_model(N)
+    rp, col, val, K = lb.lindblad_prepare_sparse(ctx, N, dcsr(H), rates, [dcsr(L) for L in Ls])
+    with pytest.raises(lb.LindbladError) as e:
+        lb.lindblad_steady_state_csr(ctx, rp, col, val, K, tol=TOL, maxit=5)
+    assert e.value.code == -7
+    v, info = lb.lindblad_steady_state_csr(ctx, rp, col, val, K, tol=TOL, maxit=5, check=False)
+    assert info["converged"] == 0 and info["iterations"] == 5 and info["residual"] > TOL
+    assert bool(torch.isfinite(v).all())
+
+
+def test_bad_arguments(lb, ctx):
+    N = 3
+    H, gamma = wl.random_lindbladian(N, 1)
+    Q, K = lb.lindblad_prepare(ctx, dev(H), dev(gamma))
+    for kw in ({"tol": 0.0}, {"tol": 1.5}, {"maxit": 0}, {"restart": 9000}):
+        with pytest.raises(lb.LindbladError) as e:
+            lb.lindblad_steady_state(ctx, Q, K, **kw)
+        assert e.value.code == -1
+
+
+def test_full_size_dense_n100(lb, ctx):
+    """The N = 100 random Lindbladian (M = 9999): residual recomputed here and
+    rho_inf a density matrix."""
+    N = 100
+    print("[gpu] steady state, dense random N=%d" % N, flush=True)
+    H = wl.gue_hamiltonian(N, 0)
+    gamma = wl.wishart_kossakowski_device(N, 1)
+    Q, K = lb.lindblad_prepare(ctx, dev(H), gamma)
+    del gamma
+    v, info = lb.lindblad_steady_state(ctx, Q, K, tol=TOL)
+    assert info["converged"] == 1
+    M = N * N - 1
+    r = Q[:, :M] @ v + K
+    assert float(r.norm() / K.norm()) < 2 * TOL
+    V = v.cpu().numpy()
+    import oracle
+    rho = oracle.reconstruct(N, V)
+    assert abs(np.trace(rho) - 1) < 1e-13
+    assert np.linalg.eigvalsh(rho).min() > -1e-12
