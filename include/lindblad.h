@@ -235,6 +235,36 @@ int lindblad_propagate_graph(lb_ctx* ctx, int64_t M, const double* Q, const floa
 /* Steady state (Sec. 3: the asymptotic state rho_inf, L(rho_inf) = 0) */
 /* ------------------------------------------------------------------ */
 
+/* Eigen-decomposition of a Hermitian matrix, A = Z diag(w) Z^H: the energy
+ * eigenbasis of H in which the steady-state preconditioner is diagonal. A is
+ * N x N complex (interleaved re, im), column-major with lda >= N, on the
+ * device, Hermitian on entry and overwritten (its diagonal ends as w); w
+ * receives N doubles (not sorted), Z the N x N eigenvectors (column-major,
+ * ldz >= N). Cyclic two-sided Jacobi in FP64 until the off-diagonal norm is
+ * below 1e-14 ||A||_F; *sweeps (may be NULL) receives the number of sweeps.
+ * Errors: LB_ERR_INVALID_ARG, LB_ERR_NO_CONVERGENCE (40 sweeps). */
+int lb_eigh(lb_ctx* ctx, int N, double* A, int lda, double* w, double* Z, int ldz, int* sweeps);
+
+/* Steady-state preconditioner for a Lindbladian given by H and jump operators
+ * L_p with rates g_p (the form of lindblad_prepare_sparse): the secular
+ * approximation of L in the energy eigenbasis of H, inverted exactly. There,
+ * each coherence X_ab (a != b) decays at -i(E_a - E_b) - (G_aa + G_bb)/2 +
+ * sum_p g_p L_p,aa conj(L_p,bb) with G = sum_p g_p L_p^H L_p, and the
+ * populations follow the rate equations with rates W_ab = sum_p g_p |L_p,ab|^2.
+ * It keeps GMRES iteration counts low where H's frequencies dwarf the
+ * dissipation (the dimer). Set-up: H and every L_p densified, H diagonalised
+ * (lb_eigh), two complex N x N GEMMs per jump operator, Gauss-Jordan inversion
+ * of the (N+1) x (N+1) bordered rate matrix; holds about 4 N^2 complex and
+ * (N+1)^2 real numbers of device memory until lindblad_secular_destroy. Each
+ * application costs four complex N x N GEMMs. H and L as for
+ * lindblad_prepare_sparse_count (device CSR, rates on the host). Errors:
+ * LB_ERR_INVALID_ARG (sizes, null pointers, a singular rate matrix),
+ * LB_ERR_OOM, LB_ERR_NO_CONVERGENCE (eigensolver), LB_ERR_DEVICE. */
+typedef struct lb_secular lb_secular;
+int lindblad_secular_create(lb_ctx* ctx, int N, const lb_csr_c128* H, int P, const double* rates,
+                            const lb_csr_c128* L, lb_secular** out);
+int lindblad_secular_destroy(lb_secular* pre);
+
 /* Outcome of an iterative solve. */
 typedef struct lb_solve_info {
     int64_t iterations; /* Krylov iterations (one operator application each) over all cycles */
@@ -253,15 +283,17 @@ typedef struct lb_solve_info {
  * `restart` iterations (1 <= restart <= 8192). Errors: LB_ERR_INVALID_ARG
  * (null pointers, sizes, tol not in (0, 1), maxit < 1), LB_ERR_OOM (basis does
  * not fit), LB_ERR_NO_CONVERGENCE (v holds the last iterate, *info filled).
- * info may be NULL. Results are deterministic (fixed-order reductions). */
+ * pre (may be NULL) is a preconditioner for the same system (M = N^2 - 1),
+ * applied on the right. info may be NULL. Results are deterministic
+ * (fixed-order reductions). */
 int lindblad_steady_state(lb_ctx* ctx, int64_t M, const double* Q, int64_t ldq, const double* K,
-                          double* v, double tol, int64_t maxit, int64_t restart,
-                          lb_solve_info* info);
+                          const lb_secular* pre, double* v, double tol, int64_t maxit,
+                          int64_t restart, lb_solve_info* info);
 
 /* The same for Q in CSR form (as written by lindblad_prepare_sparse_fill). */
 int lindblad_steady_state_csr(lb_ctx* ctx, int64_t M, const int64_t* rowptr, const int64_t* col,
-                              const double* val, const double* K, double* v, double tol,
-                              int64_t maxit, int64_t restart, lb_solve_info* info);
+                              const double* val, const double* K, const lb_secular* pre, double* v,
+                              double tol, int64_t maxit, int64_t restart, lb_solve_info* info);
 
 /* ------------------------------------------------------------------ */
 /* Tuning                                                             */

@@ -24,7 +24,7 @@ __all__ = [
     "lb_expand", "lb_expand_pure", "lb_reconstruct",
     "lindblad_prepare", "lindblad_q_to_f32", "lindblad_propagate", "lindblad_propagate_batched",
     "lindblad_propagate_graph", "lindblad_propagate_csr", "lindblad_prepare_sparse",
-    "lindblad_propagate_csr_drive", "lindblad_steady_state", "lindblad_steady_state_csr", "lindblad_autotune", "lindblad_tile_info", "lindblad_set_tile", "lindblad_time_stage", "Server",
+    "lindblad_propagate_csr_drive", "lb_eigh", "Secular", "lindblad_steady_state", "lindblad_steady_state_csr", "lindblad_autotune", "lindblad_tile_info", "lindblad_set_tile", "lindblad_time_stage", "Server",
     "FP64", "FP32", "CHECK_HERMITIAN",
 ]
 
@@ -101,8 +101,11 @@ def signatures():
         "lindblad_q_to_f32": [V, I64, V, I64, V],
         "lindblad_propagate_csr": [V, I64, V, V, V, V, V, I, D, I64],
         "lindblad_propagate_csr_drive": [V, I64, V, V, V, V, V, V, V, V, I, D, I64, D, D, D, D],
-        "lindblad_steady_state": [V, I64, V, I64, V, V, D, I64, I64, V],
-        "lindblad_steady_state_csr": [V, I64, V, V, V, V, V, D, I64, I64, V],
+        "lb_eigh": [V, I, V, I, V, V, I, V],
+        "lindblad_steady_state": [V, I64, V, I64, V, V, V, D, I64, I64, V],
+        "lindblad_steady_state_csr": [V, I64, V, V, V, V, V, V, D, I64, I64, V],
+        "lindblad_secular_create": [V, I, V, I, V, V, ctypes.POINTER(ctypes.c_void_p)],
+        "lindblad_secular_destroy": [V],
         "lindblad_propagate_batched": [V, I, I64, V, V, I64, V, V, I, D, I64, I],
         "lindblad_propagate_graph": [V, I64, V, V, I64, V, V, I, D, I64, I],
         "lindblad_autotune": [V, I64, V, V, I64, V, V, I, I],
@@ -138,6 +141,8 @@ def _need(t, dtype, name):
         raise ValueError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
     if not t.is_contiguous():
         raise ValueError("%s must be contiguous" % name)
+    if t.is_complex() and t.is_conj():
+        raise ValueError("%s is a lazy conjugate view (its memory is not conjugated); call resolve_conj()" % name)
 
 
 class Context:
@@ -401,6 +406,22 @@ def lindblad_propagate_csr(ctx: Context, rowptr, col, val, K, V, dt: float, step
     return V
 
 
+def lb_eigh(ctx: Context, A):
+    """Eigenvalues w (unsorted) and eigenvectors Z (columns) of the Hermitian
+    complex128 matrix A (device), A = Z diag(w) Z^H, by Jacobi on the device.
+    Returns (w, Z, sweeps); A is not modified."""
+    import torch
+    _need(A, torch.complex128, "A")
+    N = A.shape[0]
+    # the library works column-major: pass the memory of A^T, read Z back transposed
+    work = A.resolve_conj().transpose(0, 1).contiguous()
+    w = torch.empty(N, dtype=torch.float64, device=A.device)
+    Zc = torch.empty((N, N), dtype=torch.complex128, device=A.device)
+    sw = ctypes.c_int()
+    _check(load().lb_eigh(ctx.handle, N, _ptr(work), N, _ptr(w), _ptr(Zc), N, ctypes.byref(sw)))
+    return w, Zc.transpose(0, 1), sw.value
+
+
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("restarts", ctypes.c_int64), ("residual", ctypes.c_double),
                 ("converged", ctypes.c_int)]
@@ -417,24 +438,55 @@ def _steady_call(fn, args, check):
     return info.as_dict()
 
 
+class Secular:
+    """Steady-state preconditioner (secular approximation in the energy
+    eigenbasis of H) for the system of H and jump operators L_p (device CSR
+    tuples as for lindblad_prepare_sparse). Release with close()."""
+
+    def __init__(self, ctx: Context, N: int, H_csr, rates, L_csrs):
+        lib = load()
+        Hs = _csr_struct(*H_csr)
+        P = len(L_csrs)
+        Ls = (_CSR * max(P, 1))(*[_csr_struct(*l) for l in L_csrs])
+        r = (ctypes.c_double * max(P, 1))(*[float(x) for x in rates])
+        self._keep = (H_csr, L_csrs)
+        h = ctypes.c_void_p()
+        _check(lib.lindblad_secular_create(ctx.handle, N, ctypes.byref(Hs), P, r, Ls, ctypes.byref(h)))
+        self.handle = h
+        self.N = N
+
+    def close(self):
+        if self.handle:
+            load().lindblad_secular_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def lindblad_steady_state(ctx: Context, Q, K, tol: float = 1e-12, maxit: int = 4000, restart: int | None = None,
-                          check: bool = True):
-    """v with Q v = -K (dense Q, M x ldq), by FP64 GMRES on the device. Returns
-    (v, info) with info = {iterations, restarts, residual, converged}; a solve
-    that stops at maxit raises unless check is False."""
+                          check: bool = True, pre: Secular | None = None):
+    """v with Q v = -K (dense Q, M x ldq), by FP64 GMRES on the device (right-
+    preconditioned by pre, if given). Returns (v, info) with info = {iterations,
+    restarts, residual, converged}; a solve that stops at maxit raises unless
+    check is False."""
     import torch
     _need(Q, torch.float64, "Q")
     _need(K, torch.float64, "K")
     M = K.numel()
     v = torch.empty(M, dtype=torch.float64, device=K.device)
     info = _steady_call(load().lindblad_steady_state,
-                        (ctx.handle, M, _ptr(Q), Q.stride(0), _ptr(K), _ptr(v), float(tol), int(maxit),
+                        (ctx.handle, M, _ptr(Q), Q.stride(0), _ptr(K), pre.handle if pre else None, _ptr(v),
+                         float(tol), int(maxit),
                          int(restart or min(maxit, 8192))), check)
     return v, info
 
 
 def lindblad_steady_state_csr(ctx: Context, rowptr, col, val, K, tol: float = 1e-12, maxit: int = 4000,
-                              restart: int | None = None, check: bool = True):
+                              restart: int | None = None, check: bool = True, pre: Secular | None = None):
     """As lindblad_steady_state for Q in CSR form."""
     import torch
     _need(rowptr, torch.int64, "rowptr")
@@ -443,7 +495,8 @@ def lindblad_steady_state_csr(ctx: Context, rowptr, col, val, K, tol: float = 1e
     M = rowptr.numel() - 1
     v = torch.empty(M, dtype=torch.float64, device=K.device)
     info = _steady_call(load().lindblad_steady_state_csr,
-                        (ctx.handle, M, _ptr(rowptr), _ptr(col), _ptr(val), _ptr(K), _ptr(v), float(tol), int(maxit),
+                        (ctx.handle, M, _ptr(rowptr), _ptr(col), _ptr(val), _ptr(K), pre.handle if pre else None,
+                         _ptr(v), float(tol), int(maxit),
                          int(restart or min(maxit, 8192))), check)
     return v, info
 

@@ -324,6 +324,15 @@ int lindblad_propagate_csr_drive(lb_ctx* c, int64_t M, const int64_t* rowptr0, c
                                        T);
 }
 
+int lb_eigh(lb_ctx* c, int N, double* A, int lda, double* w, double* Z, int ldz, int* sweeps) {
+    CHECK_CTX(c);
+    CHECK_PTR(A);
+    CHECK_PTR(w);
+    CHECK_PTR(Z);
+    if (N < 1 || N > LB_MAX_N || lda < N || ldz < N) return lb_fail(LB_ERR_INVALID_ARG, "bad sizes");
+    return lb_impl_eigh(c, N, A, lda, w, Z, ldz, sweeps);
+}
+
 static int steady_args(int64_t M, const double* K, const double* v, double tol, int64_t maxit, int64_t restart) {
     if (!K || !v) return lb_fail(LB_ERR_INVALID_ARG, "null pointer");
     if (M < 3) return lb_fail(LB_ERR_INVALID_ARG, "M too small");
@@ -333,26 +342,50 @@ static int steady_args(int64_t M, const double* K, const double* v, double tol, 
     return LB_OK;
 }
 
-int lindblad_steady_state(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, const double* K, double* v, double tol,
-                          int64_t maxit, int64_t restart, lb_solve_info* info) {
+int lindblad_steady_state(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, const double* K, const lb_secular* pre,
+                          double* v, double tol, int64_t maxit, int64_t restart, lb_solve_info* info) {
     CHECK_CTX(c);
     CHECK_PTR(Q);
     int rc = steady_args(M, K, v, tol, maxit, restart);
     if (rc) return rc;
     if (ldq < M) return lb_fail(LB_ERR_INVALID_ARG, "ldq < M");
+    if (pre && lb_secular_size(pre) != M) return lb_fail(LB_ERR_INVALID_ARG, "preconditioner is for another M");
     lb_solve_info local;
-    return lb_impl_steady_dense(c, M, Q, ldq, K, v, tol, maxit, restart, info ? info : &local);
+    return lb_impl_steady_dense(c, M, Q, ldq, K, pre, v, tol, maxit, restart, info ? info : &local);
 }
 
 int lindblad_steady_state_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int64_t* col, const double* val,
-                              const double* K, double* v, double tol, int64_t maxit, int64_t restart,
-                              lb_solve_info* info) {
+                              const double* K, const lb_secular* pre, double* v, double tol, int64_t maxit,
+                              int64_t restart, lb_solve_info* info) {
     CHECK_CTX(c);
     CHECK_PTR(rowptr);
     int rc = steady_args(M, K, v, tol, maxit, restart);
     if (rc) return rc;
+    if (pre && lb_secular_size(pre) != M) return lb_fail(LB_ERR_INVALID_ARG, "preconditioner is for another M");
     lb_solve_info local;
-    return lb_impl_steady_csr(c, M, rowptr, col, val, K, v, tol, maxit, restart, info ? info : &local);
+    return lb_impl_steady_csr(c, M, rowptr, col, val, K, pre, v, tol, maxit, restart, info ? info : &local);
+}
+
+int lindblad_secular_create(lb_ctx* c, int N, const lb_csr_c128* H, int P, const double* rates, const lb_csr_c128* L,
+                            lb_secular** out) {
+    CHECK_CTX(c);
+    CHECK_PTR(H);
+    CHECK_PTR(out);
+    *out = nullptr;
+    if (N < 2 || N > LB_MAX_N) return lb_fail(LB_ERR_INVALID_ARG, "N=%d out of range", N);
+    if (P < 0 || (P > 0 && (!rates || !L))) return lb_fail(LB_ERR_INVALID_ARG, "bad jump operators");
+    if (!H->rowptr || (H->nnz > 0 && (!H->col || !H->val))) return lb_fail(LB_ERR_INVALID_ARG, "bad H");
+    for (int p = 0; p < P; ++p) {
+        if (!(rates[p] >= 0) || !isfinite(rates[p])) return lb_fail(LB_ERR_INVALID_ARG, "rate %d not >= 0", p);
+        if (!L[p].rowptr || (L[p].nnz > 0 && (!L[p].col || !L[p].val)))
+            return lb_fail(LB_ERR_INVALID_ARG, "bad jump operator %d", p);
+    }
+    return lb_impl_secular_create(c, N, H, P, rates, L, out);
+}
+
+int lindblad_secular_destroy(lb_secular* pre) {
+    lb_impl_secular_destroy(pre);
+    return LB_OK;
 }
 
 int lindblad_propagate_batched(lb_ctx* c, int R, int64_t M, const double* const* Q, const float* const* Q32,

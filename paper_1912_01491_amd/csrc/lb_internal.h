@@ -212,8 +212,15 @@ int lb_impl_propagate_csr_drive(lb_ctx* c, int64_t M, const int64_t* rowptr0, co
                                 const double* K, double* V, int B, double dt, int64_t steps, double t0, double E,
                                 double A, double T);
 int lb_impl_q_to_f32(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, float* Q32);
-int lb_impl_steady_dense(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, const double* K, double* v, double tol,
-                         int64_t maxit, int64_t restart, lb_solve_info* info);
+int lb_impl_eigh(lb_ctx* c, int N, double* A, int lda, double* w, double* Z, int ldz, int* sweeps);
+int lb_impl_steady_dense(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, const double* K, const lb_secular* pre,
+                         double* v, double tol, int64_t maxit, int64_t restart, lb_solve_info* info);
 int lb_impl_steady_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int64_t* col, const double* val,
-                       const double* K, double* v, double tol, int64_t maxit, int64_t restart, lb_solve_info* info);
+                       const double* K, const lb_secular* pre, double* v, double tol, int64_t maxit, int64_t restart,
+                       lb_solve_info* info);
+int lb_impl_secular_create(lb_ctx* c, int N, const lb_csr_c128* H, int P, const double* rates, const lb_csr_c128* L,
+                           lb_secular** out);
+int lb_impl_secular_apply(lb_ctx* c, const lb_secular* pre, const double* r, double* z);
+void lb_impl_secular_destroy(lb_secular* pre);
+int64_t lb_secular_size(const lb_secular* pre);  // M of the system it was built for
 lb_tile lb_default_tile(int64_t M, int Bp, int precision, int R);

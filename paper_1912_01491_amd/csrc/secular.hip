@@ -1,0 +1,399 @@
+// Preconditioner for the steady state Q v = -K of a Lindbladian given by a
+// Hamiltonian H and jump operators L_p with rates g_p: the secular (rotating-
+// wave) approximation of L in the energy eigenbasis H = U diag(E) U^H, which
+// it inverts exactly.
+//
+// In that basis (tildes), L(X) = A X + X A^H + sum_p g_p L_p X L_p^H with
+// A = -iH - 1/2 sum_p g_p L_p^H L_p. Keeping of A only its diagonal and of the
+// jump term only what maps a matrix unit to itself, a coherence X_ab (a != b)
+// is multiplied by
+//   den_ab = -i (E_a - E_b) - (gt_a + gt_b) / 2 + sum_p g_p Lt_p,aa conj(Lt_p,bb),
+//   gt_a = sum_b W_ba,  W_ab = sum_p g_p |Lt_p,ab|^2,
+// and the populations follow the rate equations dP/dt = (W - diag(gt)) P. On
+// traceless inputs the populations are solved together with sum_a P_a = 0
+// through the bordered matrix [[W - diag(gt), 1], [1^T, 0]], inverted once.
+// Applied to a coherence-vector residual r: R = sum_n r_n F_n (Eq. (7) without
+// the identity), Rt = U^H R U, Yt = the solution above, Y = U Yt U^H,
+// z_n = Tr(F_n Y) (Eq. (6)). The dimer's strongly oscillating coherences are
+// then inverted exactly, so GMRES iterates only on the coupling that the
+// approximation drops.
+//
+// Matrices are complex (interleaved re, im), column-major. The four N x N
+// basis changes per application are plain complex GEMMs (vendor BLAS); the
+// rest are the kernels below.
+#include "lb_internal.h"
+
+#include <math.h>
+#include <rocblas/rocblas.h>
+
+#include <vector>
+
+struct lb_secular {
+    int N = 0;
+    int64_t M = 0;
+    int device = 0;
+    double2* U = nullptr;    // eigenvectors of H, N x N
+    double2* den = nullptr;  // coherence denominators, N x N
+    double* Binv = nullptr;  // inverse bordered rate matrix, (N + 1) x (N + 1), row-major
+    double2* T1 = nullptr;   // scratch, N x N each
+    double2* T2 = nullptr;
+    double* pv = nullptr;    // 2 (N + 1): right-hand side and populations
+    rocblas_handle blas = nullptr;
+};
+
+namespace {
+
+__global__ void k_csr_dense_cm(int N, const int64_t* rowptr, const int64_t* col, const double2* val, double2* D) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) D[r + col[e] * N] = val[e];
+}
+
+// W += g |Lt|^2 elementwise; d = diag(Lt).
+__global__ void k_jump_accum(int N, double g, const double2* Lt, double* W, double2* d) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * N) return;
+    const double2 x = Lt[i];
+    W[i] += g * (x.x * x.x + x.y * x.y);
+    const int a = (int)(i % N), b = (int)(i / N);
+    if (a == b) d[a] = x;
+}
+
+// gt[a] = sum_b W_ba (column a of W, column-major).
+__global__ __launch_bounds__(256) void k_col_sums(int N, const double* W, double* gt) {
+    __shared__ double red[4];
+    const int a = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < N; b += blockDim.x) s += W[b + (int64_t)a * N];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) gt[a] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ void k_den(int N, const double* E, const double* gt, int P, const double* g, const double2* d,
+                      double2* den) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * N) return;
+    const int a = (int)(i % N), b = (int)(i / N);
+    double re = -0.5 * (gt[a] + gt[b]), im = -(E[a] - E[b]);
+    for (int p = 0; p < P; ++p) {
+        const double2 x = d[(int64_t)p * N + a], y = d[(int64_t)p * N + b];
+        re += g[p] * (x.x * y.x + x.y * y.y);  // x conj(y)
+        im += g[p] * (x.y * y.x - x.x * y.y);
+    }
+    den[i] = make_double2(re, im);
+}
+
+// aug (n x 2n, row-major) = [[W - diag(gt), 1], [1^T, 0] | I].
+__global__ void k_border(int N, const double* W, const double* gt, double* aug) {
+    const int n = N + 1;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * 2 * n) return;
+    const int r = (int)(i / (2 * n)), c = (int)(i % (2 * n));
+    double v;
+    if (c >= n) v = (c - n == r) ? 1.0 : 0.0;
+    else if (r < N && c < N) v = W[r + (int64_t)c * N] - (r == c ? gt[r] : 0.0);
+    else if (r == N && c == N) v = 0.0;
+    else v = 1.0;
+    aug[i] = v;
+}
+
+// Gauss-Jordan step k, part 1: the pivot row (largest |aug[r][k]|, r >= k) and
+// its value.
+__global__ __launch_bounds__(1024) void k_gj_pivot(int n, const double* aug, int k, int* piv, double* pval) {
+    __shared__ double bv[1024];
+    __shared__ int bi[1024];
+    double best = -1.0;
+    int bidx = k;
+    for (int r = k + threadIdx.x; r < n; r += blockDim.x) {
+        const double a = fabs(aug[(int64_t)r * 2 * n + k]);
+        if (a > best) {
+            best = a;
+            bidx = r;
+        }
+    }
+    bv[threadIdx.x] = best;
+    bi[threadIdx.x] = bidx;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            const double ov = bv[threadIdx.x + o];
+            const int oi = bi[threadIdx.x + o];
+            if (ov > bv[threadIdx.x] || (ov == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+                bv[threadIdx.x] = ov;
+                bi[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        piv[0] = bi[0];
+        pval[0] = aug[(int64_t)bi[0] * 2 * n + k];
+    }
+}
+
+// Part 2: swap rows k and piv, scale row k by 1/pivot; the thread of column k
+// then keeps column k (after the swap) as the elimination factors f.
+__global__ void k_gj_swap(int n, double* aug, int k, const int* piv, const double* pval, double* f) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= 2 * n) return;
+    const int p = piv[0];
+    const double inv = 1.0 / pval[0];
+    const double a = aug[(int64_t)k * 2 * n + c], b = aug[(int64_t)p * 2 * n + c];
+    aug[(int64_t)p * 2 * n + c] = a;
+    aug[(int64_t)k * 2 * n + c] = b * inv;
+    if (c == k)
+        for (int r = 0; r < n; ++r) f[r] = aug[(int64_t)r * 2 * n + k];
+}
+
+// Part 3: eliminate column k from every other row.
+__global__ void k_gj_elim(int n, double* aug, int k, const double* f) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * 2 * n) return;
+    const int r = (int)(i / (2 * n)), c = (int)(i % (2 * n));
+    if (r == k) return;
+    aug[i] -= f[r] * aug[(int64_t)k * 2 * n + c];
+}
+
+__global__ void k_take_inverse(int n, const double* aug, double* Binv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * n) return;
+    const int r = (int)(i / n), c = (int)(i % n);
+    Binv[i] = aug[(int64_t)r * 2 * n + n + c];
+}
+
+// R = sum_n r_n F_n (traceless Hermitian, column-major). Threads below P write
+// pair q's two entries, threads from P on write a diagonal element.
+__global__ void k_v_to_herm(int N, const double* v, double2* R) {
+    const int64_t P = lb_npairs(N);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double s2 = 0.70710678118654752440;
+    if (t < P) {
+        int cls, j, k;
+        lb_decode(N, t, cls, j, k);
+        const double s = v[t] * s2, a = v[P + t] * s2;
+        R[j + (int64_t)k * N] = make_double2(s, -a);  // (S - i J)/sqrt(2) at (j, k)
+        R[k + (int64_t)j * N] = make_double2(s, a);
+        return;
+    }
+    const int64_t x = t - P;
+    if (x >= N) return;
+    // D^l has 1 at positions < l and -l at position l (scaled by 1/sqrt(l(l+1)))
+    double d = 0.0;
+    for (int l = (int)x + 1; l < N; ++l) d += v[2 * P + l - 1] / sqrt((double)l * (l + 1));
+    if (x >= 1) d -= (double)x * v[2 * P + x - 1] / sqrt((double)x * (x + 1));
+    R[x + x * N] = make_double2(d, 0.0);
+}
+
+// z_n = Re Tr(F_n Y).
+__global__ void k_herm_to_v(int N, const double2* Y, double* z) {
+    const int64_t P = lb_npairs(N);
+    const int64_t M = (int64_t)N * N - 1;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= M) return;
+    const double s2 = 0.70710678118654752440;
+    int cls, j, k;
+    lb_decode(N, n, cls, j, k);
+    if (cls == 0) {
+        z[n] = (Y[k + (int64_t)j * N].x + Y[j + (int64_t)k * N].x) * s2;
+    } else if (cls == 1) {
+        z[n] = (Y[k + (int64_t)j * N].y - Y[j + (int64_t)k * N].y) * s2;
+    } else {
+        const int l = j;
+        double s = 0.0;
+        for (int x = 0; x < l; ++x) s += Y[x + (int64_t)x * N].x;
+        z[n] = (s - (double)l * Y[l + (int64_t)l * N].x) / sqrt((double)l * (l + 1));
+    }
+}
+
+__global__ void k_diag_rhs(int N, const double2* Rt, double* rhs) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < N) rhs[a] = Rt[a + (int64_t)a * N].x;
+    if (a == N) rhs[N] = 0.0;
+}
+
+// y = Binv x, (n x n row-major), one wavefront per row.
+__global__ __launch_bounds__(256) void k_small_gemv(int n, const double* B, const double* x, double* y) {
+    const int lane = threadIdx.x & 63;
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= n) return;
+    const double* row = B + (int64_t)r * n;
+    double s = 0.0;
+    for (int c = lane; c < n; c += 64) s = fma(row[c], x[c], s);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) y[r] = s;
+}
+
+// Yt = Rt / den off the diagonal, the populations on it.
+__global__ void k_apply_den(int N, double2* T, const double2* den, const double* pop) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * N) return;
+    const int a = (int)(i % N), b = (int)(i / N);
+    if (a == b) {
+        T[i] = make_double2(pop[a], 0.0);
+        return;
+    }
+    const double2 x = T[i], d = den[i];
+    const double q = d.x * d.x + d.y * d.y;
+    T[i] = make_double2((x.x * d.x + x.y * d.y) / q, (x.y * d.x - x.x * d.y) / q);
+}
+
+int blas_ok(rocblas_status st) {
+    return st == rocblas_status_success ? LB_OK : lb_fail(LB_ERR_DEVICE, "rocBLAS call failed (%d)", (int)st);
+}
+
+// C = op(A) op(B), N x N complex, column-major.
+int zgemm(rocblas_handle h, rocblas_operation oa, rocblas_operation ob, int N, const double2* A, const double2* B,
+          double2* C) {
+    const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+    return blas_ok(rocblas_zgemm(h, oa, ob, N, N, N, &one, (const rocblas_double_complex*)A, N,
+                                 (const rocblas_double_complex*)B, N, &zero, (rocblas_double_complex*)C, N));
+}
+
+void secular_free(lb_secular* p) {
+    if (!p) return;
+    for (void* q : {(void*)p->U, (void*)p->den, (void*)p->Binv, (void*)p->T1, (void*)p->T2, (void*)p->pv})
+        if (q) (void)hipFree(q);
+    if (p->blas) (void)rocblas_destroy_handle(p->blas);
+    delete p;
+}
+
+}  // namespace
+
+int lb_impl_secular_create(lb_ctx* c, int N, const lb_csr_c128* H, int P, const double* rates,
+                           const lb_csr_c128* L, lb_secular** out) {
+    hipStream_t s = c->stream;
+    const int64_t NN = (int64_t)N * N;
+    const int n = N + 1;
+    lb_secular* pre = new lb_secular();
+    pre->N = N;
+    pre->M = NN - 1;
+    pre->device = c->device;
+    auto dmalloc = [&](void** p, size_t bytes) -> int {
+        if (hipMalloc(p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            *p = nullptr;
+            return lb_fail(LB_ERR_OOM, "preconditioner allocation of %zu bytes failed", bytes);
+        }
+        return LB_OK;
+    };
+    // set-up temporaries: dense H / L, eigenvalues, W, gt, diagonals, rates, aug, f, pivot
+    double2* Hd = nullptr;
+    double *E = nullptr, *W = nullptr, *gt = nullptr, *gdev = nullptr, *aug = nullptr, *f = nullptr, *pval = nullptr;
+    double2* dg = nullptr;
+    int* piv = nullptr;
+    std::vector<void*> tmp;
+    auto cleanup = [&](int rc) {
+        (void)hipStreamSynchronize(s);
+        for (void* q : tmp)
+            if (q) (void)hipFree(q);
+        if (rc) secular_free(pre);
+        return rc;
+    };
+    int rc = LB_OK;
+    if ((rc = dmalloc((void**)&pre->U, sizeof(double2) * NN)) || (rc = dmalloc((void**)&pre->den, sizeof(double2) * NN)) ||
+        (rc = dmalloc((void**)&pre->Binv, sizeof(double) * (size_t)n * n)) ||
+        (rc = dmalloc((void**)&pre->T1, sizeof(double2) * NN)) || (rc = dmalloc((void**)&pre->T2, sizeof(double2) * NN)) ||
+        (rc = dmalloc((void**)&pre->pv, sizeof(double) * 2 * (size_t)n)))
+        return cleanup(rc);
+    const int Pm = P > 0 ? P : 1;
+    if ((rc = dmalloc((void**)&Hd, sizeof(double2) * NN)) || (rc = dmalloc((void**)&E, sizeof(double) * N)) ||
+        (rc = dmalloc((void**)&W, sizeof(double) * NN)) || (rc = dmalloc((void**)&gt, sizeof(double) * N)) ||
+        (rc = dmalloc((void**)&gdev, sizeof(double) * Pm)) || (rc = dmalloc((void**)&dg, sizeof(double2) * Pm * N)) ||
+        (rc = dmalloc((void**)&aug, sizeof(double) * (size_t)n * 2 * n)) || (rc = dmalloc((void**)&f, sizeof(double) * n)) ||
+        (rc = dmalloc((void**)&pval, sizeof(double))) || (rc = dmalloc((void**)&piv, sizeof(int)))) {
+        tmp = {Hd, E, W, gt, gdev, dg, aug, f, pval, piv};
+        return cleanup(rc);
+    }
+    tmp = {Hd, E, W, gt, gdev, dg, aug, f, pval, piv};
+    if (rocblas_create_handle(&pre->blas) != rocblas_status_success) {
+        pre->blas = nullptr;
+        return cleanup(lb_fail(LB_ERR_DEVICE, "rocBLAS handle creation failed"));
+    }
+    if ((rc = blas_ok(rocblas_set_stream(pre->blas, s)))) return cleanup(rc);
+    // energy eigenbasis of H
+    if (hipMemsetAsync(Hd, 0, sizeof(double2) * NN, s) != hipSuccess) return cleanup(lb_fail(LB_ERR_DEVICE, "memset"));
+    hipLaunchKernelGGL(k_csr_dense_cm, dim3(lb_blocks(N, 256)), dim3(256), 0, s, N, H->rowptr, H->col,
+                       (const double2*)H->val, Hd);
+    if (hipGetLastError() != hipSuccess) return cleanup(lb_fail(LB_ERR_DEVICE, "launch"));
+    if ((rc = lb_impl_eigh(c, N, (double*)Hd, N, E, (double*)pre->U, N, nullptr))) return cleanup(rc);
+    // jump operators in that basis: W, their diagonals
+    if (hipMemsetAsync(W, 0, sizeof(double) * NN, s) != hipSuccess) return cleanup(lb_fail(LB_ERR_DEVICE, "memset"));
+    for (int p = 0; p < P; ++p) {
+        if (hipMemsetAsync(Hd, 0, sizeof(double2) * NN, s) != hipSuccess)
+            return cleanup(lb_fail(LB_ERR_DEVICE, "memset"));
+        hipLaunchKernelGGL(k_csr_dense_cm, dim3(lb_blocks(N, 256)), dim3(256), 0, s, N, L[p].rowptr, L[p].col,
+                           (const double2*)L[p].val, Hd);
+        if ((rc = zgemm(pre->blas, rocblas_operation_none, rocblas_operation_none, N, Hd, pre->U, pre->T1)) ||
+            (rc = zgemm(pre->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, N, pre->U, pre->T1,
+                        pre->T2)))
+            return cleanup(rc);
+        hipLaunchKernelGGL(k_jump_accum, dim3(lb_blocks(NN, 256)), dim3(256), 0, s, N, rates[p],
+                           (const double2*)pre->T2, W, dg + (int64_t)p * N);
+    }
+    if (P > 0 && hipMemcpyAsync(gdev, rates, sizeof(double) * P, hipMemcpyHostToDevice, s) != hipSuccess)
+        return cleanup(lb_fail(LB_ERR_DEVICE, "copy of the rates failed"));
+    hipLaunchKernelGGL(k_col_sums, dim3(N), dim3(256), 0, s, N, (const double*)W, gt);
+    hipLaunchKernelGGL(k_den, dim3(lb_blocks(NN, 256)), dim3(256), 0, s, N, (const double*)E, (const double*)gt, P,
+                       (const double*)gdev, (const double2*)dg, pre->den);
+    // inverse of the bordered rate matrix, Gauss-Jordan with partial pivoting
+    const int64_t naug = (int64_t)n * 2 * n;
+    hipLaunchKernelGGL(k_border, dim3(lb_blocks(naug, 256)), dim3(256), 0, s, N, (const double*)W, (const double*)gt,
+                       aug);
+    for (int k = 0; k < n; ++k) {
+        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, s, n, (const double*)aug, k, piv, pval);
+        hipLaunchKernelGGL(k_gj_swap, dim3(lb_blocks(2 * n, 256)), dim3(256), 0, s, n, aug, k, (const int*)piv,
+                           (const double*)pval, f);
+        hipLaunchKernelGGL(k_gj_elim, dim3(lb_blocks(naug, 256)), dim3(256), 0, s, n, aug, k, (const double*)f);
+    }
+    hipLaunchKernelGGL(k_take_inverse, dim3(lb_blocks((int64_t)n * n, 256)), dim3(256), 0, s, n, (const double*)aug,
+                       pre->Binv);
+    if (hipGetLastError() != hipSuccess) return cleanup(lb_fail(LB_ERR_DEVICE, "preconditioner set-up launch failed"));
+    // a singular rate matrix shows as a zero or non-finite pivot
+    double last = 0.0;
+    if (hipMemcpyAsync(&last, pval, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return cleanup(lb_fail(LB_ERR_DEVICE, "preconditioner set-up failed"));
+    if (!(last != 0.0) || !isfinite(last)) return cleanup(lb_fail(LB_ERR_INVALID_ARG, "rate matrix is singular"));
+    *out = pre;
+    return cleanup(LB_OK);
+}
+
+int lb_impl_secular_apply(lb_ctx* c, const lb_secular* pre, const double* r, double* z) {
+    hipStream_t s = c->stream;
+    const int N = pre->N;
+    const int64_t NN = (int64_t)N * N;
+    const int n = N + 1;
+    const int64_t P = lb_npairs(N);
+    int rc;
+    if ((rc = blas_ok(rocblas_set_stream(pre->blas, s)))) return rc;
+    hipLaunchKernelGGL(k_v_to_herm, dim3(lb_blocks(P + N, 256)), dim3(256), 0, s, N, r, pre->T1);
+    LB_CHECK_LAUNCH();
+    if ((rc = zgemm(pre->blas, rocblas_operation_none, rocblas_operation_none, N, pre->T1, pre->U, pre->T2)) ||
+        (rc = zgemm(pre->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, N, pre->U, pre->T2,
+                    pre->T1)))
+        return rc;
+    hipLaunchKernelGGL(k_diag_rhs, dim3(lb_blocks(n, 256)), dim3(256), 0, s, N, (const double2*)pre->T1, pre->pv);
+    hipLaunchKernelGGL(k_small_gemv, dim3(lb_blocks(n, 4)), dim3(256), 0, s, n, (const double*)pre->Binv,
+                       (const double*)pre->pv, pre->pv + n);
+    hipLaunchKernelGGL(k_apply_den, dim3(lb_blocks(NN, 256)), dim3(256), 0, s, N, pre->T1, (const double2*)pre->den,
+                       (const double*)(pre->pv + n));
+    LB_CHECK_LAUNCH();
+    if ((rc = zgemm(pre->blas, rocblas_operation_none, rocblas_operation_conjugate_transpose, N, pre->T1, pre->U,
+                    pre->T2)) ||
+        (rc = zgemm(pre->blas, rocblas_operation_none, rocblas_operation_none, N, pre->U, pre->T2, pre->T1)))
+        return rc;
+    hipLaunchKernelGGL(k_herm_to_v, dim3(lb_blocks(NN - 1, 256)), dim3(256), 0, s, N, (const double2*)pre->T1, z);
+    LB_CHECK_LAUNCH();
+    return LB_OK;
+}
+
+int64_t lb_secular_size(const lb_secular* pre) { return pre->M; }
+
+void lb_impl_secular_destroy(lb_secular* pre) {
+    if (!pre) return;
+    (void)hipSetDevice(pre->device);
+    (void)hipDeviceSynchronize();
+    secular_free(pre);
+}

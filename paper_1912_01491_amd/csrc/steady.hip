@@ -11,7 +11,9 @@
 //   k_reduce   their sums in a fixed order (deterministic, no atomics);
 //   k_update   w -= V h (and the partial sums of |w|^2 for the norm).
 // The operator is the dense row-dot GEMV (one wavefront per row group, as the
-// one-state RK4 stage) or the sliced sparse product. The small Hessenberg
+// one-state RK4 stage) or the sliced sparse product; the optional
+// preconditioner is the secular approximation of the Lindbladian in the energy
+// eigenbasis (secular.hip). The small Hessenberg
 // least-squares problem (Givens rotations, back substitution) is solved on the
 // host from the column each iteration copies back.
 #include "lb_internal.h"
@@ -224,8 +226,8 @@ struct SolveBufs {
     }
 };
 
-static int gmres(lb_ctx* c, int64_t M, const Op& op, const double* K, double* v, double tol, int64_t maxit,
-                 int64_t restart, lb_solve_info* info) {
+static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, const double* K, double* v, double tol,
+                 int64_t maxit, int64_t restart, lb_solve_info* info) {
     hipStream_t s = c->stream;
     const int64_t m = restart < maxit ? restart : maxit;
     const int64_t ldv = (M + 31) / 32 * 32;
@@ -238,8 +240,8 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const double* K, double* v,
         return lb_fail(LB_ERR_OOM, "Krylov basis of %lld vectors of %lld doubles does not fit", (long long)(m + 1),
                        (long long)M);
     }
-    // aux: w, x, r | part ((m + 1) * nparts) | h1, h2 (m + 1 each) | norm (1) | y (m)
-    const size_t n_aux = 3 * (size_t)ldv + (size_t)(m + 1) * nparts + 2 * (size_t)(m + 1) + 1 + (size_t)m;
+    // aux: w, x, r, z, u | part ((m + 1) * nparts) | h1, h2 (m + 1 each) | norm (1) | y (m)
+    const size_t n_aux = 5 * (size_t)ldv + (size_t)(m + 1) * nparts + 2 * (size_t)(m + 1) + 1 + (size_t)m;
     if (hipMalloc(&b.aux, sizeof(double) * n_aux) != hipSuccess) {
         (void)hipGetLastError();
         b.aux = nullptr;
@@ -248,7 +250,9 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const double* K, double* v,
     double* w = b.aux;
     double* x = w + ldv;
     double* r = x + ldv;
-    double* part = r + ldv;
+    double* zb = r + ldv;
+    double* ub = zb + ldv;
+    double* part = ub + ldv;
     double* h1 = part + (size_t)(m + 1) * nparts;
     double* h2 = h1 + (m + 1);
     double* nrm = h2 + (m + 1);
@@ -307,7 +311,11 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const double* K, double* v,
         for (; j < m && total < maxit && !done; ++j, ++total) {
             double* vj = b.V + j * ldv;
             double* vn = b.V + (j + 1) * ldv;
-            if ((rc = op_apply(op, M, vj, w, s))) return rc;
+            if (pre) {  // right preconditioning: w = Q P^-1 v_j
+                if ((rc = lb_impl_secular_apply(c, pre, vj, zb)) || (rc = op_apply(op, M, zb, w, s))) return rc;
+            } else if ((rc = op_apply(op, M, vj, w, s))) {
+                return rc;
+            }
             const int k = (int)(j + 1);
             // two passes of classical Gram-Schmidt
             hipLaunchKernelGGL(k_dots, dim3(nrb), dim3(256), 0, s, (const double*)b.V, ldv, k, M, (const double*)w,
@@ -364,9 +372,20 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const double* K, double* v,
             y[i] = d != 0.0 ? t / d : 0.0;
         }
         LB_HIP(hipMemcpyAsync(yd, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_update<false>, dim3(nrb), dim3(256), 0, s, (const double*)b.V, ldv, (int)k, M,
-                           (const double*)yd, -1.0, x, part);
-        LB_CHECK_LAUNCH();
+        if (pre) {  // x += P^-1 V y
+            LB_HIP(hipMemsetAsync(ub, 0, sizeof(double) * M, s));
+            hipLaunchKernelGGL(k_update<false>, dim3(nrb), dim3(256), 0, s, (const double*)b.V, ldv, (int)k, M,
+                               (const double*)yd, -1.0, ub, part);
+            LB_CHECK_LAUNCH();
+            if ((rc = lb_impl_secular_apply(c, pre, ub, zb))) return rc;
+            hipLaunchKernelGGL(k_axpby, dim3(eg), dim3(256), 0, s, M, 1.0, (const double*)x, 1.0, (const double*)zb,
+                               x);
+            LB_CHECK_LAUNCH();
+        } else {
+            hipLaunchKernelGGL(k_update<false>, dim3(nrb), dim3(256), 0, s, (const double*)b.V, ldv, (int)k, M,
+                               (const double*)yd, -1.0, x, part);
+            LB_CHECK_LAUNCH();
+        }
         info->iterations = total;
         ++info->restarts;
     }
@@ -382,23 +401,24 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const double* K, double* v,
 
 }  // namespace
 
-int lb_impl_steady_dense(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, const double* K, double* v, double tol,
-                         int64_t maxit, int64_t restart, lb_solve_info* info) {
+int lb_impl_steady_dense(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, const double* K, const lb_secular* pre,
+                         double* v, double tol, int64_t maxit, int64_t restart, lb_solve_info* info) {
     Op op;
     op.sparse = false;
     op.Q = Q;
     op.ldq = ldq;
     op.aligned = ((uintptr_t)Q % 16 == 0) && ldq % 2 == 0;
     op.nt = op.aligned && ((uintptr_t)Q % 128 == 0) && ldq % 16 == 0;
-    return gmres(c, M, op, K, v, tol, maxit, restart, info);
+    return gmres(c, M, op, pre, K, v, tol, maxit, restart, info);
 }
 
 int lb_impl_steady_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int64_t* col, const double* val,
-                       const double* K, double* v, double tol, int64_t maxit, int64_t restart, lb_solve_info* info) {
+                       const double* K, const lb_secular* pre, double* v, double tol, int64_t maxit, int64_t restart,
+                       lb_solve_info* info) {
     Op op;
     op.sparse = true;
     size_t extra = 0;
     int rc = sell_build(c, M, rowptr, col, val, nullptr, nullptr, nullptr, 0, &op.m, &extra);
     if (rc) return rc;
-    return gmres(c, M, op, K, v, tol, maxit, restart, info);
+    return gmres(c, M, op, pre, K, v, tol, maxit, restart, info);
 }

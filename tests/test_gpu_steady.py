@@ -155,3 +155,70 @@ def test_full_size_dense_n100(lb, ctx):
     rho = oracle.reconstruct(N, V)
     assert abs(np.trace(rho) - 1) < 1e-13
     assert np.linalg.eigvalsh(rho).min() > -1e-12
+
+
+@pytest.mark.parametrize("N", [20, 40])
+def test_preconditioned_dimer_matches_oracle(lb, ctx, oracle, N):
+    """The secular preconditioner: same solution, far fewer iterations."""
+    print("[gpu] preconditioned steady state, dimer N=%d" % N, flush=True)
+    H, rates, Ls = wl.dimer_model(N)
+    Hc, Lc = dcsr(H), [dcsr(L) for L in Ls]
+    rp, col, val, K = lb.lindblad_prepare_sparse(ctx, N, Hc, rates, Lc)
+    pre = lb.Secular(ctx, N, Hc, rates, Lc)
+    v, info = lb.lindblad_steady_state_csr(ctx, rp, col, val, K, tol=TOL, pre=pre)
+    assert info["converged"] == 1 and info["iterations"] <= 60
+    _, plain = lb.lindblad_steady_state_csr(ctx, rp, col, val, K, tol=TOL)
+    assert info["iterations"] < plain["iterations"] / 4
+    M = N * N - 1
+    Qo, Ko = oracle.prepare_factored(H, rates, Ls, np.arange(M))
+    vo = oracle.steady_state(Qo, Ko)
+    assert rel(v.cpu().numpy(), vo) < RTOL
+    pre.close()
+
+
+def test_preconditioned_rocked_dimer_hamiltonian(lb, ctx, oracle):
+    """A frozen drive value (H0 + (E + A) H1) with the synchronising jump."""
+    N = 30
+    H0, H1, rates, Ls = wl.rocked_dimer_model(N)
+    H = H0 - 2.5 * H1
+    Hc, Lc = dcsr(H), [dcsr(L) for L in Ls]
+    rp, col, val, K = lb.lindblad_prepare_sparse(ctx, N, Hc, rates, Lc)
+    pre = lb.Secular(ctx, N, Hc, rates, Lc)
+    v, info = lb.lindblad_steady_state_csr(ctx, rp, col, val, K, tol=TOL, pre=pre)
+    assert info["converged"] == 1
+    M = N * N - 1
+    vo = oracle.steady_state(*oracle.prepare_factored(H, rates, Ls, np.arange(M)))
+    assert rel(v.cpu().numpy(), vo) < RTOL
+    pre.close()
+
+
+def test_preconditioned_dimer_n300(lb, ctx, oracle):
+    """M = 89999: residual recomputed from the CSR here, rho_inf a density matrix."""
+    N = 300
+    print("[gpu] preconditioned steady state, dimer N=%d" % N, flush=True)
+    H, rates, Ls = wl.dimer_model(N)
+    Hc, Lc = dcsr(H), [dcsr(L) for L in Ls]
+    rp, col, val, K = lb.lindblad_prepare_sparse(ctx, N, Hc, rates, Lc)
+    pre = lb.Secular(ctx, N, Hc, rates, Lc)
+    v, info = lb.lindblad_steady_state_csr(ctx, rp, col, val, K, tol=TOL, pre=pre)
+    assert info["converged"] == 1
+    M = N * N - 1
+    Qs = torch.sparse_csr_tensor(rp.cpu(), col.cpu(), val.cpu(), size=(M, M))
+    r = (Qs @ v.cpu()) + K.cpu()
+    assert float(r.norm() / K.cpu().norm()) < 2 * TOL
+    rho = oracle.reconstruct(N, v.cpu().numpy())
+    assert abs(np.trace(rho) - 1) < 1e-13
+    assert np.linalg.eigvalsh(rho).min() > -1e-12
+    pre.close()
+
+
+def test_preconditioner_for_another_size_is_rejected(lb, ctx):
+    N = 6
+    H, rates, Ls = wl.dimer_model(N)
+    Hc, Lc = dcsr(H), [dcsr(L) for L in Ls]
+    pre = lb.Secular(ctx, N + 1, dcsr(wl.dimer_model(N + 1)[0]), rates, [dcsr(wl.dimer_model(N + 1)[2][0])])
+    rp, col, val, K = lb.lindblad_prepare_sparse(ctx, N, Hc, rates, Lc)
+    with pytest.raises(lb.LindbladError) as e:
+        lb.lindblad_steady_state_csr(ctx, rp, col, val, K, pre=pre)
+    assert e.value.code == -1
+    pre.close()
