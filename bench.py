@@ -90,7 +90,7 @@ def parse():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle RK4 steps in the CPU sample")
-    ap.add_argument("--config", choices=["c1", "c2", "c2p", "c3", "c4", "c5", "c5r"], default="c4",
+    ap.add_argument("--config", choices=["c1", "c2", "c2p", "c3", "c4", "c5", "c5r", "c6", "c6s"], default="c4",
                     help="c4: the N=200 dense headline (default); c1: N=8 dense; c2: N=1000 sparse dimer; "
                          "c3: N=100 dense, 64 states, FP64 vs FP32; c5: serving mix (prepare per request); "
                          "c5r: serving mix on resident systems; c2p: the periodically rocked dimer (one period)")
@@ -102,6 +102,8 @@ def parse():
                     help="for rocprofv3 --pmc runs: one plain 4 GiB copy, then the C4 stage GEMM on stand-in Q")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--arrival", choices=["burst", "poisson"], default="burst")
+    ap.add_argument("--ss-N", type=int, default=1000, help="c6s: dimer size")
+    ap.add_argument("--ss-maxit", type=int, default=6000, help="c6s: GMRES iteration limit")
     ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrival rate (requests/s)")
     ap.add_argument("--slots", type=int, default=6)
     ap.add_argument("--max-batch", type=int, default=8)
@@ -490,6 +492,127 @@ def config_c2p(args):
     print(json.dumps(out), flush=True)
 
 
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def config_c6(args):
+    """Steady state of the N=100 random Lindbladian (M=9999): GUE H, Wishart
+    gamma drawn on the device, Q and K prepared on the device, then Q v = -K by
+    FP64 GMRES without preconditioner (the random model's spectrum keeps away
+    from zero). Each GMRES iteration streams Q once, so the solve is bound by
+    HBM like the one-state RK4 stage."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1912_01491_amd as lb
+    from paper_1912_01491_amd import workloads as wl
+
+    N, tol = 100, 1e-13
+    M = N * N - 1
+    ctx = lb.Context(0)
+    H = torch.from_numpy(wl.gue_hamiltonian(N, 0)).cuda()
+    gamma = wl.wishart_kossakowski_device(N, 1)
+    Q, K = lb.lindblad_prepare(ctx, H, gamma)
+    del gamma
+    torch.cuda.empty_cache()
+    lb.lindblad_steady_state(ctx, Q, K, tol=tol)
+    t, (v, info) = min((_timed(lambda: lb.lindblad_steady_state(ctx, Q, K, tol=tol)) for _ in range(3)),
+                       key=lambda x: x[0])
+    # operator applications: one residual per cycle start, one per iteration, one final residual
+    apps = info["iterations"] + info["restarts"] + 2
+    bytes_q = M * Q.stride(0) * 8
+    gbs = apps * bytes_q / t / 1e9
+    res = float(((Q[:, :M] @ v + K).norm() / K.norm()).item())
+    rho = oracle.reconstruct(N, v.cpu().numpy())
+    log("C6: N=%d steady state in %.2f ms, %d iterations (%d restarts), residual %.1e, %.0f GB/s over Q"
+        % (N, 1e3 * t, info["iterations"], info["restarts"], res, gbs))
+    # the oracle's dense solve of the same system on the host cores
+    Qh, Kh = Q[:, :M].cpu().numpy(), K.cpu().numpy()
+    oracle.steady_state(Qh[:8, :8] + np.eye(8), Kh[:8])
+    t0 = time.perf_counter()
+    vo = oracle.steady_state(Qh, Kh)
+    tc = time.perf_counter() - t0
+    err = float(np.abs(v.cpu().numpy() - vo).max() / np.abs(vo).max())
+    out = {"metric": "steady state: N=100 random Lindbladian, Q v = -K (FP64)", "value": 1.0 / t,
+           "unit": "solves/s (M=9999)", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "random Lindbladian N=100 (M=9999): GUE H seed 0, Wishart gamma seed 1 (Tr = N); "
+                                  "GMRES to ||Qv + K|| <= 1e-13 ||K||, no preconditioner"},
+           "solve_s": t, "iterations": info["iterations"], "restarts": info["restarts"],
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_mv_dense",
+                        "bytes_per_application": bytes_q, "applications": apps},
+           "cpu_baseline": {"value": 1.0 / tc, "unit": "solves/s (M=9999)", "cores": _blas_threads(),
+                            "kind": "oracle", "sample": "the whole solve: dense LU (LAPACK via numpy) of the same "
+                                                        "M=9999 system; %.2f s" % tc},
+           "checks": {"residual": res, "rel_err_vs_oracle": err, "trace_err": float(abs(np.trace(rho) - 1)),
+                      "min_eig_rho": float(np.linalg.eigvalsh(rho).min())}}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def config_c6s(args):
+    """Steady state of the static dimer (the sparse model of the configurations,
+    N=1000, M=999999) with the secular preconditioner: Q in CSR prepared on the
+    device, the preconditioner built on the device from H and the jump
+    operator (Jacobi eigenbasis of H, bordered rate matrix), then FP64 GMRES."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1912_01491_amd as lb
+    from paper_1912_01491_amd import workloads as wl
+
+    N, tol = args.ss_N, 1e-12
+    M = N * N - 1
+    ctx = lb.Context(0)
+    H, rates, Ls = wl.dimer_model(N)
+
+    def dev_csr(X):
+        return tuple(torch.from_numpy(x).cuda() for x in wl.to_csr(X))
+
+    Hc, Lc = dev_csr(H), [dev_csr(L) for L in Ls]
+    rp, col, val, K = lb.lindblad_prepare_sparse(ctx, N, Hc, rates, Lc)
+    t_pre, pre = _timed(lambda: lb.Secular(ctx, N, Hc, rates, Lc))
+    log("C6s: N=%d preconditioner set up in %.2f s" % (N, t_pre))
+    t, (v, info) = _timed(lambda: lb.lindblad_steady_state_csr(ctx, rp, col, val, K, tol=tol, maxit=args.ss_maxit,
+                                                               pre=pre))
+    log("C6s: solved in %.2f s, %d iterations, residual %.1e" % (t, info["iterations"], info["residual"]))
+    Qs = torch.sparse_csr_tensor(rp.cpu(), col.cpu(), val.cpu(), size=(M, M))
+    res = float(((Qs @ v.cpu()) + K.cpu()).norm() / K.cpu().norm())
+    rho = oracle.reconstruct(N, v.cpu().numpy())
+    n1 = float(np.real(np.sum(np.arange(N) * np.diag(rho))))
+    # the oracle's dense solve on a bounded sample: the same model at N=60
+    Ns = 60
+    Hs_, rs_, Ls_ = wl.dimer_model(Ns)
+    Qo, Ko = oracle.prepare_factored(Hs_, rs_, Ls_, np.arange(Ns * Ns - 1))
+    t0 = time.perf_counter()
+    oracle.steady_state(Qo, Ko)
+    tc = time.perf_counter() - t0
+    out = {"metric": "steady state: N=%d dimer, Q v = -K (FP64, preconditioned GMRES)" % N, "value": 1.0 / (t + t_pre),
+           "unit": "solves/s incl. preconditioner set-up (M=%d)" % M, "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "bosonic dimer N=%d (M=%d), J=1, U=0.5, L=b1^+ b2 at rate 0.1/%d; GMRES to "
+                                  "||Qv + K|| <= 1e-12 ||K||, secular preconditioner" % (N, M, N - 1)},
+           "setup_s": t_pre, "solve_s": t, "iterations": info["iterations"], "restarts": info["restarts"],
+           "cpu_baseline": {"value": 1.0 / tc, "unit": "solves/s (M=%d)" % (Ns * Ns - 1), "cores": _blas_threads(),
+                            "kind": "oracle",
+                            "sample": "dense LU of the same model at N=%d (M=%d), %.2f s; a dense N=%d system "
+                                      "(%.0f TB) is beyond the oracle" % (Ns, Ns * Ns - 1, tc, N, 8e-12 * M * M)},
+           "checks": {"residual": res, "trace_err": float(abs(np.trace(rho) - 1)),
+                      "herm_err": float(np.abs(rho - rho.conj().T).max()),
+                      "min_eig_rho": float(np.linalg.eigvalsh(rho).min()), "mean_n1": n1}}
+    pre.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def config_c3(args):
     """N=100 (M=9999) dense random Lindbladian, GUE H, Wishart gamma; 64 random
     pure states, 2000 RK4 steps dt=1e-3, FP64 (matrix cores) and FP32 matrix
@@ -589,8 +712,9 @@ def main():
         return pmc_probe(args)
     if args.serving or args.config in ("c5", "c5r"):
         return serving(args)
-    if args.config in ("c1", "c2", "c2p", "c3"):
-        return {"c1": config_c1, "c2": config_c2, "c2p": config_c2p, "c3": config_c3}[args.config](args)
+    if args.config in ("c1", "c2", "c2p", "c3", "c6", "c6s"):
+        return {"c1": config_c1, "c2": config_c2, "c2p": config_c2p, "c3": config_c3, "c6": config_c6,
+                "c6s": config_c6s}[args.config](args)
     import numpy as np
     import torch
 

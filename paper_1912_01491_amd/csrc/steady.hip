@@ -22,12 +22,13 @@
 
 #include <math.h>
 
+#include <algorithm>
 #include <vector>
 
 namespace {
 
-constexpr int kDotE = 4;                  // rows per thread in the basis kernels
-constexpr int kDotRows = 256 * kDotE;     // rows per block
+constexpr int kDotJ = 32;           // basis vectors per block of k_dots (second grid dimension)
+constexpr int64_t kSmallM = 262144;  // below: one row per thread and split updates, for enough blocks
 
 // y = Q x, dense, R rows per wavefront.
 template <int R, bool ALIGNED, bool NT>
@@ -79,25 +80,31 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// part[j * nparts + p] = sum over the rows of wave p of V_j[i] w[i], j < k.
+// Basis kernels work on row chunks of 256 E rows per block (E rows per thread,
+// 256 apart); partial sums are per wavefront, p = 4 * block + wave.
+
+// part[j * nparts + p] = sum over the rows of wave p of V_j[i] w[i], j < k;
+// block (x, y) takes row chunk x and basis vectors [y kDotJ, (y + 1) kDotJ).
+template <int E>
 __global__ __launch_bounds__(256) void k_dots(const double* V, int64_t ldv, int k, int64_t M, const double* w,
                                               double* part, int nparts) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * kDotRows + threadIdx.x;
-    double wv[kDotE];
+    const int64_t base = (int64_t)blockIdx.x * 256 * E + threadIdx.x;
+    double wv[E];
 #pragma unroll
-    for (int e = 0; e < kDotE; ++e) {
+    for (int e = 0; e < E; ++e) {
         const int64_t i = base + e * 256;
         wv[e] = i < M ? w[i] : 0.0;
     }
     const int p = blockIdx.x * 4 + wave;
-    int j = 0;
-    for (; j + 1 < k; j += 2) {
+    int j = blockIdx.y * kDotJ;
+    const int jend = min(k, j + kDotJ);
+    for (; j + 1 < jend; j += 2) {
         const double* v0 = V + (int64_t)j * ldv;
         const double* v1 = v0 + ldv;
         double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-        for (int e = 0; e < kDotE; ++e) {
+        for (int e = 0; e < E; ++e) {
             const int64_t i = base + e * 256;
             if (i < M) {
                 a0 = fma(v0[i], wv[e], a0);
@@ -111,11 +118,11 @@ __global__ __launch_bounds__(256) void k_dots(const double* V, int64_t ldv, int 
             part[(int64_t)(j + 1) * nparts + p] = a1;
         }
     }
-    if (j < k) {
+    if (j < jend) {
         const double* v0 = V + (int64_t)j * ldv;
         double a0 = 0.0;
 #pragma unroll
-        for (int e = 0; e < kDotE; ++e) {
+        for (int e = 0; e < E; ++e) {
             const int64_t i = base + e * 256;
             if (i < M) a0 = fma(v0[i], wv[e], a0);
         }
@@ -140,32 +147,69 @@ __global__ __launch_bounds__(256) void k_reduce(const double* part, int nparts, 
 
 // w[i] -= sgn * sum_{j<k} h[j] V_j[i]; with NORM, part[p] = the sum of the new
 // w[i]^2 over the rows of wave p.
-template <bool NORM>
+template <int E, bool NORM>
 __global__ __launch_bounds__(256) void k_update(const double* V, int64_t ldv, int k, int64_t M, const double* h,
                                                 double sgn, double* w, double* part) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * kDotRows + threadIdx.x;
-    double s[kDotE];
+    const int64_t base = (int64_t)blockIdx.x * 256 * E + threadIdx.x;
+    double s[E];
 #pragma unroll
-    for (int e = 0; e < kDotE; ++e) s[e] = 0.0;
+    for (int e = 0; e < E; ++e) s[e] = 0.0;
     for (int j = 0; j < k; ++j) {
         const double hj = h[j];
         const double* vj = V + (int64_t)j * ldv;
 #pragma unroll
-        for (int e = 0; e < kDotE; ++e) {
+        for (int e = 0; e < E; ++e) {
             const int64_t i = base + e * 256;
             if (i < M) s[e] = fma(hj, vj[i], s[e]);
         }
     }
     double nrm = 0.0;
 #pragma unroll
-    for (int e = 0; e < kDotE; ++e) {
+    for (int e = 0; e < E; ++e) {
         const int64_t i = base + e * 256;
         if (i < M) {
             const double x = w[i] - sgn * s[e];
             w[i] = x;
             nrm = fma(x, x, nrm);
         }
+    }
+    if (NORM) {
+        nrm = wave_sum(nrm);
+        if (lane == 0) part[blockIdx.x * 4 + wave] = nrm;
+    }
+}
+
+// Split form of k_update for small M (one row per thread): part2[y * ldp + i] =
+// sum over the basis vectors j of chunk y (of jc) of h[j] V_j[i] ...
+__global__ __launch_bounds__(256) void k_update_part(const double* V, int64_t ldv, int k, int jc, int64_t M,
+                                                     const double* h, double* part2, int64_t ldp) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= M) return;
+    const int j0 = blockIdx.y * jc, j1 = min(k, j0 + jc);
+    double s0 = 0.0, s1 = 0.0;
+    int j = j0;
+    for (; j + 1 < j1; j += 2) {
+        s0 = fma(h[j], V[(int64_t)j * ldv + i], s0);
+        s1 = fma(h[j + 1], V[(int64_t)(j + 1) * ldv + i], s1);
+    }
+    if (j < j1) s0 = fma(h[j], V[(int64_t)j * ldv + i], s0);
+    part2[blockIdx.y * ldp + i] = s0 + s1;
+}
+
+// ... and w[i] -= sgn * (the chunks' sums in chunk order); NORM as k_update.
+template <bool NORM>
+__global__ __launch_bounds__(256) void k_update_fin(int64_t M, const double* part2, int64_t ldp, int nch, double sgn,
+                                                    double* w, double* part) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double nrm = 0.0;
+    if (i < M) {
+        double t = 0.0;
+        for (int c = 0; c < nch; ++c) t += part2[c * ldp + i];
+        const double x = w[i] - sgn * t;
+        w[i] = x;
+        nrm = x * x;
     }
     if (NORM) {
         nrm = wave_sum(nrm);
@@ -231,7 +275,10 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
     hipStream_t s = c->stream;
     const int64_t m = restart < maxit ? restart : maxit;
     const int64_t ldv = (M + 31) / 32 * 32;
-    const int nrb = (int)lb_blocks(M, kDotRows);
+    // small systems: one row per thread and updates split over chunks of the basis
+    const bool small = M < kSmallM;
+    const int E = small ? 1 : 4;
+    const int nrb = (int)lb_blocks(M, 256 * E);
     const int nparts = 4 * nrb;
     SolveBufs b;
     if (hipMalloc(&b.V, sizeof(double) * (size_t)(m + 1) * ldv) != hipSuccess) {
@@ -240,8 +287,11 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
         return lb_fail(LB_ERR_OOM, "Krylov basis of %lld vectors of %lld doubles does not fit", (long long)(m + 1),
                        (long long)M);
     }
-    // aux: w, x, r, z, u | part ((m + 1) * nparts) | h1, h2 (m + 1 each) | norm (1) | y (m)
-    const size_t n_aux = 5 * (size_t)ldv + (size_t)(m + 1) * nparts + 2 * (size_t)(m + 1) + 1 + (size_t)m;
+    // split updates: at most 64 chunks of at least 16 basis vectors
+    const int nch_max = small ? (int)std::min<int64_t>(64, (m + 15) / 16) : 1;
+    // aux: w, x, r, z, u | part ((m + 1) * nparts) | hb (2 (m + 1) + 1) | norm (1) | y (m) | part2 (nch_max ldv)
+    const size_t n_aux = 5 * (size_t)ldv + (size_t)(m + 1) * nparts + 2 * (size_t)(m + 1) + 2 + (size_t)m +
+                         (nch_max > 1 ? (size_t)nch_max * ldv : 0);
     if (hipMalloc(&b.aux, sizeof(double) * n_aux) != hipSuccess) {
         (void)hipGetLastError();
         b.aux = nullptr;
@@ -253,14 +303,18 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
     double* zb = r + ldv;
     double* ub = zb + ldv;
     double* part = ub + ldv;
-    double* h1 = part + (size_t)(m + 1) * nparts;
-    double* h2 = h1 + (m + 1);
-    double* nrm = h2 + (m + 1);
+    double* hb = part + (size_t)(m + 1) * nparts;  // per iteration: h1 (k), h2 (k), |w| (1)
+    double* nrm = hb + 2 * (m + 1) + 1;
     double* yd = nrm + 1;
+    double* part2 = yd + m;
+    int rc = lb_host_reserve(c, sizeof(double) * (2 * (size_t)(m + 1) + 1));
+    if (rc) return rc;
+    double* hh = (double*)c->host;  // pinned copy of hb
     const unsigned eg = lb_blocks(M, 256);
     auto norm_of = [&](double* vec, double* out) -> int {
         // ||vec|| into out[0] on the device
-        hipLaunchKernelGGL(k_dots, dim3(nrb), dim3(256), 0, s, vec, ldv, 1, M, vec, part, nparts);
+        if (small) hipLaunchKernelGGL(k_dots<1>, dim3(nrb, 1), dim3(256), 0, s, vec, ldv, 1, M, vec, part, nparts);
+        else hipLaunchKernelGGL(k_dots<4>, dim3(nrb, 1), dim3(256), 0, s, vec, ldv, 1, M, vec, part, nparts);
         LB_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_reduce<true>, dim3(1), dim3(256), 0, s, part, nparts, 1, out);
         LB_CHECK_LAUNCH();
@@ -271,7 +325,39 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
         LB_HIP(hipStreamSynchronize(s));
         return LB_OK;
     };
-    int rc;
+    // w -= sgn V_[0,k) h, with the new |w|^2 partials in part when norm
+    auto update = [&](int k, const double* h, double sgn, double* out, bool norm) -> int {
+        if (!small) {
+            if (norm)
+                hipLaunchKernelGGL((k_update<4, true>), dim3(nrb), dim3(256), 0, s, (const double*)b.V, ldv, k, M, h,
+                                   sgn, out, part);
+            else
+                hipLaunchKernelGGL((k_update<4, false>), dim3(nrb), dim3(256), 0, s, (const double*)b.V, ldv, k, M, h,
+                                   sgn, out, part);
+            LB_CHECK_LAUNCH();
+            return LB_OK;
+        }
+        const int jc = std::max(16, (k + nch_max - 1) / nch_max);
+        const int used = (k + jc - 1) / jc;
+        hipLaunchKernelGGL(k_update_part, dim3(nrb, used), dim3(256), 0, s, (const double*)b.V, ldv, k, jc, M, h,
+                           part2, ldv);
+        LB_CHECK_LAUNCH();
+        if (norm)
+            hipLaunchKernelGGL(k_update_fin<true>, dim3(nrb), dim3(256), 0, s, M, (const double*)part2, ldv, used, sgn,
+                               out, part);
+        else
+            hipLaunchKernelGGL(k_update_fin<false>, dim3(nrb), dim3(256), 0, s, M, (const double*)part2, ldv, used,
+                               sgn, out, part);
+        LB_CHECK_LAUNCH();
+        return LB_OK;
+    };
+    auto dots = [&](int k, const double* vec) -> int {
+        const dim3 grid(nrb, (unsigned)((k + kDotJ - 1) / kDotJ));
+        if (small) hipLaunchKernelGGL(k_dots<1>, grid, dim3(256), 0, s, (const double*)b.V, ldv, k, M, vec, part, nparts);
+        else hipLaunchKernelGGL(k_dots<4>, grid, dim3(256), 0, s, (const double*)b.V, ldv, k, M, vec, part, nparts);
+        LB_CHECK_LAUNCH();
+        return LB_OK;
+    };
     // ||K||: the scale of the residual
     double knorm = 0.0;
     LB_HIP(hipMemcpyAsync(r, K, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
@@ -287,7 +373,7 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
         info->converged = 1;
         return LB_OK;
     }
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), hc2(m + 1), y(m);
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
     int64_t total = 0;
     for (;;) {
         // r = -K - Q x
@@ -318,35 +404,28 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
             }
             const int k = (int)(j + 1);
             // two passes of classical Gram-Schmidt
-            hipLaunchKernelGGL(k_dots, dim3(nrb), dim3(256), 0, s, (const double*)b.V, ldv, k, M, (const double*)w,
-                               part, nparts);
-            LB_CHECK_LAUNCH();
+            double* h1 = hb;
+            double* h2 = hb + k;
+            double* hn = hb + 2 * k;
+            if ((rc = dots(k, w))) return rc;
             hipLaunchKernelGGL(k_reduce<false>, dim3(lb_blocks(k, 4)), dim3(256), 0, s, (const double*)part, nparts,
                                k, h1);
             LB_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_update<false>, dim3(nrb), dim3(256), 0, s, (const double*)b.V, ldv, k, M,
-                               (const double*)h1, 1.0, w, part);
-            LB_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_dots, dim3(nrb), dim3(256), 0, s, (const double*)b.V, ldv, k, M, (const double*)w,
-                               part, nparts);
-            LB_CHECK_LAUNCH();
+            if ((rc = update(k, h1, 1.0, w, false))) return rc;
+            if ((rc = dots(k, w))) return rc;
             hipLaunchKernelGGL(k_reduce<false>, dim3(lb_blocks(k, 4)), dim3(256), 0, s, (const double*)part, nparts,
                                k, h2);
             LB_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_update<true>, dim3(nrb), dim3(256), 0, s, (const double*)b.V, ldv, k, M,
-                               (const double*)h2, 1.0, w, part);
+            if ((rc = update(k, h2, 1.0, w, true))) return rc;
+            hipLaunchKernelGGL(k_reduce<true>, dim3(1), dim3(256), 0, s, (const double*)part, nparts, 1, hn);
             LB_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_reduce<true>, dim3(1), dim3(256), 0, s, (const double*)part, nparts, 1, nrm);
+            hipLaunchKernelGGL(k_divide, dim3(eg), dim3(256), 0, s, M, (const double*)w, (const double*)hn, vn);
             LB_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_divide, dim3(eg), dim3(256), 0, s, M, (const double*)w, (const double*)nrm, vn);
-            LB_CHECK_LAUNCH();
-            LB_HIP(hipMemcpyAsync(hcol.data(), h1, sizeof(double) * k, hipMemcpyDeviceToHost, s));
-            LB_HIP(hipMemcpyAsync(hc2.data(), h2, sizeof(double) * k, hipMemcpyDeviceToHost, s));
-            LB_HIP(hipMemcpyAsync(&hcol[k], nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+            LB_HIP(hipMemcpyAsync(hh, hb, sizeof(double) * (2 * k + 1), hipMemcpyDeviceToHost, s));
             LB_HIP(hipStreamSynchronize(s));
             double* Hj = &H[(size_t)j * (m + 1)];  // column j, rows 0..j+1
-            for (int i = 0; i < k; ++i) Hj[i] = hcol[i] + hc2[i];
-            Hj[k] = hcol[k];
+            for (int i = 0; i < k; ++i) Hj[i] = hh[i] + hh[k + i];
+            Hj[k] = hh[2 * k];
             // previous rotations, then the one that zeroes H[j+1][j]
             for (int64_t i = 0; i < j; ++i) {
                 const double a = Hj[i], bb = Hj[i + 1];
@@ -361,7 +440,7 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
             Hj[j + 1] = 0.0;
             g[j + 1] = -sn[j] * g[j];
             g[j] = cs[j] * g[j];
-            if (fabs(g[j + 1]) <= tol * knorm || hcol[k] == 0.0) done = true;
+            if (fabs(g[j + 1]) <= tol * knorm || hh[2 * k] == 0.0) done = true;
         }
         // y = R^-1 g, x += V y
         const int64_t k = j;
@@ -374,17 +453,13 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
         LB_HIP(hipMemcpyAsync(yd, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
         if (pre) {  // x += P^-1 V y
             LB_HIP(hipMemsetAsync(ub, 0, sizeof(double) * M, s));
-            hipLaunchKernelGGL(k_update<false>, dim3(nrb), dim3(256), 0, s, (const double*)b.V, ldv, (int)k, M,
-                               (const double*)yd, -1.0, ub, part);
-            LB_CHECK_LAUNCH();
+            if ((rc = update((int)k, yd, -1.0, ub, false))) return rc;
             if ((rc = lb_impl_secular_apply(c, pre, ub, zb))) return rc;
             hipLaunchKernelGGL(k_axpby, dim3(eg), dim3(256), 0, s, M, 1.0, (const double*)x, 1.0, (const double*)zb,
                                x);
             LB_CHECK_LAUNCH();
         } else {
-            hipLaunchKernelGGL(k_update<false>, dim3(nrb), dim3(256), 0, s, (const double*)b.V, ldv, (int)k, M,
-                               (const double*)yd, -1.0, x, part);
-            LB_CHECK_LAUNCH();
+            if ((rc = update((int)k, yd, -1.0, x, false))) return rc;
         }
         info->iterations = total;
         ++info->restarts;
