@@ -270,11 +270,228 @@ struct SolveBufs {
     }
 };
 
+// Delayed classical Gram-Schmidt with reorthogonalisation (large systems):
+// entering step j the basis V_[0,j) is orthonormal and u is the next vector
+// after one projection (not yet reorthogonalised or normalised). With
+// t = A u, one pass over the basis gives s = V^T u, z = V^T t, alpha = u.u and
+// beta = u.t; then omega = sqrt(alpha - s.s) finishes column j-1 of H (its
+// second projection s and its norm), q_j = (u - V s) / omega, and by the
+// Arnoldi relation A V = V H the first projection of A q_j and the next raw
+// vector follow without another product:
+//   h = ([z; d] - H s) / omega,  d = (beta - s.z) / omega,
+//   u' = (t - V z - q_j d) / omega,
+// formed in one more pass over the basis. Two passes per step instead of four.
+
+// part rows: 2l -> V_l.u, 2l+1 -> V_l.t (l < k), 2k -> u.u, 2k+1 -> u.t.
+template <int E>
+__global__ __launch_bounds__(256) void k_dots2(const double* V, int64_t ldv, int k, int64_t M, const double* u,
+                                               const double* t, double* part, int nparts) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * 256 * E + threadIdx.x;
+    double uv[E], tv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int64_t i = base + e * 256;
+        uv[e] = i < M ? u[i] : 0.0;
+        tv[e] = i < M ? t[i] : 0.0;
+    }
+    const int p = blockIdx.x * 4 + wave;
+    const int j0 = blockIdx.y * kDotJ, j1 = min(k, j0 + kDotJ);
+    for (int j = j0; j < j1; ++j) {
+        const double* vj = V + (int64_t)j * ldv;
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int64_t i = base + e * 256;
+            if (i < M) {
+                const double x = vj[i];
+                a = fma(x, uv[e], a);
+                b = fma(x, tv[e], b);
+            }
+        }
+        a = wave_sum(a);
+        b = wave_sum(b);
+        if (lane == 0) {
+            part[(int64_t)(2 * j) * nparts + p] = a;
+            part[(int64_t)(2 * j + 1) * nparts + p] = b;
+        }
+    }
+    if (blockIdx.y == 0) {
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            a = fma(uv[e], uv[e], a);
+            b = fma(uv[e], tv[e], b);
+        }
+        a = wave_sum(a);
+        b = wave_sum(b);
+        if (lane == 0) {
+            part[(int64_t)(2 * k) * nparts + p] = a;
+            part[(int64_t)(2 * k + 1) * nparts + p] = b;
+        }
+    }
+}
+
+// Column bookkeeping of step j >= 1, part 1 (one block): finishes column j-1
+// of the unrotated Hessenberg matrix (kept row-major, Hr[l * ldr + i]), rotates
+// it into H (column-major; Givens as k_givens) and sets scal = (omega, d).
+__global__ __launch_bounds__(256) void k_dcgs2_fin(int j, const double* sz, double* Hr, int64_t ldr, double* H,
+                                                   int64_t ldh, double* cs, double* sn, double* g, double* res,
+                                                   double* brk, double* scal) {
+    __shared__ double red[2][4];
+    __shared__ double sh[2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double ss = 0.0, sz2 = 0.0;
+    for (int l = threadIdx.x; l < j; l += blockDim.x) {
+        const double sl = sz[2 * l], zl = sz[2 * l + 1];
+        ss = fma(sl, sl, ss);
+        sz2 = fma(sl, zl, sz2);
+    }
+    ss = wave_sum(ss);
+    sz2 = wave_sum(sz2);
+    if (lane == 0) {
+        red[0][wave] = ss;
+        red[1][wave] = sz2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double a = sz[2 * j], b = sz[2 * j + 1];
+        const double s2 = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+        const double szt = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        const double om = sqrt(fmax(a - s2, 0.0));
+        sh[0] = om;
+        sh[1] = (b - szt) / om;
+    }
+    __syncthreads();
+    const double om = sh[0];
+    // column j-1: rows 0..j-1 gain the second projection s, row j is omega; copied into H
+    double* Hj = H + (int64_t)(j - 1) * ldh;
+    for (int l = threadIdx.x; l <= j; l += blockDim.x) {
+        double* e = Hr + (int64_t)l * ldr + (j - 1);
+        const double x = l < j ? *e + sz[2 * l] : om;
+        *e = x;
+        Hj[l] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int jj = j - 1;
+        for (int i = 0; i < jj; ++i) {
+            const double a = Hj[i], b = Hj[i + 1];
+            Hj[i] = cs[i] * a + sn[i] * b;
+            Hj[i + 1] = -sn[i] * a + cs[i] * b;
+        }
+        const double a = Hj[jj], b = Hj[jj + 1];
+        const double den = hypot(a, b);
+        cs[jj] = den > 0 ? a / den : 1.0;
+        sn[jj] = den > 0 ? b / den : 0.0;
+        Hj[jj] = den;
+        Hj[jj + 1] = 0.0;
+        g[jj + 1] = -sn[jj] * g[jj];
+        g[jj] = cs[jj] * g[jj];
+        res[jj] = fabs(g[jj + 1]);
+        brk[jj] = om;
+        scal[0] = om;
+        scal[1] = sh[1];
+    }
+}
+
+// Part 2 (one wavefront per row l <= j): the first projection of column j,
+// Hr[l][j] = ((l < j ? z_l : d) - (Hr s)_l) / omega, with (Hr s)_l summed over
+// the band i >= l - 1 in a fixed order.
+__global__ __launch_bounds__(256) void k_dcgs2_next(int j, const double* sz, double* Hr, int64_t ldr,
+                                                    const double* scal) {
+    const int lane = threadIdx.x & 63;
+    const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (l > j) return;
+    const double* row = Hr + (int64_t)l * ldr;
+    double c = 0.0;
+    for (int i = (l > 0 ? l - 1 : 0) + lane; i < j; i += 64) c = fma(row[i], sz[2 * i], c);
+    c = wave_sum(c);
+    if (lane == 0) Hr[(int64_t)l * ldr + j] = ((l < j ? sz[2 * l + 1] : scal[1]) - c) / scal[0];
+}
+
+// q_j = (u - V s) / omega into V_j, u <- (t - V z - q_j d) / omega.
+template <int E>
+__global__ __launch_bounds__(256) void k_dcgs2_upd(double* V, int64_t ldv, int j, int64_t M, const double* sz,
+                                                   const double* scal, double* u, const double* t) {
+    const int64_t base = (int64_t)blockIdx.x * 256 * E + threadIdx.x;
+    double a[E], b[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) a[e] = b[e] = 0.0;
+    for (int l = 0; l < j; ++l) {
+        const double sl = sz[2 * l], zl = sz[2 * l + 1];
+        const double* vl = V + (int64_t)l * ldv;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int64_t i = base + e * 256;
+            if (i < M) {
+                const double x = vl[i];
+                a[e] = fma(sl, x, a[e]);
+                b[e] = fma(zl, x, b[e]);
+            }
+        }
+    }
+    const double om = scal[0], d = scal[1];
+    double* vj = V + (int64_t)j * ldv;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int64_t i = base + e * 256;
+        if (i < M) {
+            const double q = (u[i] - a[e]) / om;
+            vj[i] = q;
+            u[i] = (t[i] - b[e] - q * d) / om;
+        }
+    }
+}
+
+__global__ void k_copy_first(const double* src, double* dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = src[0];
+}
+
+// One Arnoldi column on the device: H_j = h1 + h2 (rows 0..j) and |w| (row
+// j+1) from the two Gram-Schmidt passes, the earlier Givens rotations applied
+// in order, then the rotation that zeroes row j+1, applied to g as well;
+// res[j] = |g[j+1]| (the residual norm of the least-squares solution) and
+// brk[j] = |w|. One thread: the rotations are a serial recurrence.
+__global__ void k_givens(int j, const double* hb, double* H, int64_t ldh, double* cs, double* sn, double* g,
+                         double* res, double* brk) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int k = j + 1;
+    double* Hj = H + (int64_t)j * ldh;
+    for (int i = 0; i < k; ++i) Hj[i] = hb[i] + hb[k + i];
+    Hj[k] = hb[2 * k];
+    for (int i = 0; i < j; ++i) {
+        const double a = Hj[i], b = Hj[i + 1];
+        Hj[i] = cs[i] * a + sn[i] * b;
+        Hj[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = Hj[j], b = Hj[j + 1];
+    const double den = hypot(a, b);
+    cs[j] = den > 0 ? a / den : 1.0;
+    sn[j] = den > 0 ? b / den : 0.0;
+    Hj[j] = den;
+    Hj[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    res[j] = fabs(g[j + 1]);
+    brk[j] = hb[2 * k];
+}
+
+// g = (beta, 0, ..., 0) with beta = |r| on the device.
+__global__ void k_init_g(int64_t n, const double* beta, double* g) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) g[i] = i == 0 ? beta[0] : 0.0;
+}
+
+constexpr int kLook = 8;  // iterations enqueued between convergence checks
+
 static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, const double* K, double* v, double tol,
                  int64_t maxit, int64_t restart, lb_solve_info* info) {
     hipStream_t s = c->stream;
     const int64_t m = restart < maxit ? restart : maxit;
     const int64_t ldv = (M + 31) / 32 * 32;
+    const int64_t ldh = m + 2;  // rows of H (column j has rows 0..j+1)
+    const int64_t ldr = m + 1;  // row length of the row-major unrotated Hr (m + 2 rows)
     // small systems: one row per thread and updates split over chunks of the basis
     const bool small = M < kSmallM;
     const int E = small ? 1 : 4;
@@ -289,9 +506,15 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
     }
     // split updates: at most 64 chunks of at least 16 basis vectors
     const int nch_max = small ? (int)std::min<int64_t>(64, (m + 15) / 16) : 1;
-    // aux: w, x, r, z, u | part ((m + 1) * nparts) | hb (2 (m + 1) + 1) | norm (1) | y (m) | part2 (nch_max ldv)
-    const size_t n_aux = 5 * (size_t)ldv + (size_t)(m + 1) * nparts + 2 * (size_t)(m + 1) + 2 + (size_t)m +
-                         (nch_max > 1 ? (size_t)nch_max * ldv : 0);
+    // aux: w, x, r, z, u (ldv each) | part ((m + 1) nparts) | hb (2 (m + 1) + 1) | nrm (1) | y (m)
+    //      | H (ldh m) | cs, sn (m each) | g (m + 1) | res, brk (m each) | part2 (nch_max ldv)
+    //      | delayed Gram-Schmidt (large systems): Hr (ldh (m + 1)), sz (2 (m + 1) + 2), scal (2), t (ldv),
+    //        and part grows to (2 (m + 1) + 2) nparts
+    const bool delayed = !small;
+    const size_t n_part = (size_t)(delayed ? 2 * (m + 1) + 2 : m + 1) * nparts;
+    const size_t n_aux = 5 * (size_t)ldv + n_part + 2 * (size_t)(m + 1) + 2 + (size_t)m + (size_t)ldh * m +
+                         2 * (size_t)m + (size_t)(m + 1) + 2 * (size_t)m + (nch_max > 1 ? (size_t)nch_max * ldv : 0) +
+                         (delayed ? (size_t)ldh * (m + 1) + 2 * (size_t)(m + 1) + 4 + (size_t)ldv : 0);
     if (hipMalloc(&b.aux, sizeof(double) * n_aux) != hipSuccess) {
         (void)hipGetLastError();
         b.aux = nullptr;
@@ -303,13 +526,24 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
     double* zb = r + ldv;
     double* ub = zb + ldv;
     double* part = ub + ldv;
-    double* hb = part + (size_t)(m + 1) * nparts;  // per iteration: h1 (k), h2 (k), |w| (1)
+    double* hb = part + n_part;  // per iteration: h1 (k), h2 (k), |w| (1)
     double* nrm = hb + 2 * (m + 1) + 1;
     double* yd = nrm + 1;
-    double* part2 = yd + m;
-    int rc = lb_host_reserve(c, sizeof(double) * (2 * (size_t)(m + 1) + 1));
+    double* Hd = yd + m;
+    double* csd = Hd + (size_t)ldh * m;
+    double* snd = csd + m;
+    double* gd = snd + m;
+    double* resd = gd + (m + 1);
+    double* brkd = resd + m;
+    double* part2 = brkd + m;
+    double* Hr = part2 + (nch_max > 1 ? (size_t)nch_max * ldv : 0);
+    double* szd = Hr + (delayed ? (size_t)ldh * (m + 1) : 0);
+    double* scal = szd + 2 * (m + 1) + 2;
+    double* tb = scal + 2;
+    // pinned host: the estimates of a batch (R and g of a cycle reserve more later)
+    int rc = lb_host_reserve(c, sizeof(double) * 2 * kLook);
     if (rc) return rc;
-    double* hh = (double*)c->host;  // pinned copy of hb
+    double* hh = (double*)c->host;
     const unsigned eg = lb_blocks(M, 256);
     auto norm_of = [&](double* vec, double* out) -> int {
         // ||vec|| into out[0] on the device
@@ -325,7 +559,7 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
         LB_HIP(hipStreamSynchronize(s));
         return LB_OK;
     };
-    // w -= sgn V_[0,k) h, with the new |w|^2 partials in part when norm
+    // out -= sgn V_[0,k) h, with the new |out|^2 partials in part when norm
     auto update = [&](int k, const double* h, double sgn, double* out, bool norm) -> int {
         if (!small) {
             if (norm)
@@ -358,6 +592,81 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
         LB_CHECK_LAUNCH();
         return LB_OK;
     };
+    auto apply_op = [&](const double* in, double* out) -> int {
+        int e;
+        if (pre) {
+            if ((e = lb_impl_secular_apply(c, pre, in, zb)) || (e = op_apply(op, M, zb, out, s))) return e;
+            return LB_OK;
+        }
+        return op_apply(op, M, in, out, s);
+    };
+    // delayed Gram-Schmidt step jj: finishes column jj of H (rotated, res[jj]) and writes V_{jj+1}
+    auto arnoldi_delayed = [&](int64_t jj) -> int {
+        int e;
+        if (jj == 0) {  // u = A v_0 projected once; its coefficient is the first entry of column 0
+            if ((e = apply_op(b.V, ub))) return e;
+            if ((e = dots(1, ub))) return e;
+            hipLaunchKernelGGL(k_reduce<false>, dim3(1), dim3(256), 0, s, (const double*)part, nparts, 1, hb);
+            LB_CHECK_LAUNCH();
+            if ((e = update(1, hb, 1.0, ub, false))) return e;
+            hipLaunchKernelGGL(k_copy_first, dim3(1), dim3(64), 0, s, (const double*)hb, Hr);  // Hr[0][0]
+            LB_CHECK_LAUNCH();
+        }
+        const int j = (int)(jj + 1);
+        if ((e = apply_op(ub, tb))) return e;
+        const dim3 grid(nrb, (unsigned)((j + kDotJ - 1) / kDotJ));
+        hipLaunchKernelGGL(k_dots2<4>, grid, dim3(256), 0, s, (const double*)b.V, ldv, j, M, (const double*)ub,
+                           (const double*)tb, part, nparts);
+        LB_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_reduce<false>, dim3(lb_blocks(2 * j + 2, 4)), dim3(256), 0, s, (const double*)part,
+                           nparts, 2 * j + 2, szd);
+        LB_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_dcgs2_fin, dim3(1), dim3(256), 0, s, j, (const double*)szd, Hr, ldr, Hd, ldh, csd, snd,
+                           gd, resd, brkd, scal);
+        LB_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_dcgs2_next, dim3(lb_blocks(j + 1, 4)), dim3(256), 0, s, j, (const double*)szd, Hr, ldr,
+                           (const double*)scal);
+        LB_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_dcgs2_upd<4>, dim3(nrb), dim3(256), 0, s, b.V, ldv, j, M, (const double*)szd,
+                           (const double*)scal, ub, (const double*)tb);
+        LB_CHECK_LAUNCH();
+        return LB_OK;
+    };
+    // one Arnoldi step j: V_{j+1} and column j of H, rotated, on the device
+    auto arnoldi = [&](int64_t j) -> int {
+        if (delayed) return arnoldi_delayed(j);
+        double* vj = b.V + j * ldv;
+        double* vn = b.V + (j + 1) * ldv;
+        int e;
+        if (pre) {  // right preconditioning: w = Q P^-1 v_j
+            if ((e = lb_impl_secular_apply(c, pre, vj, zb)) || (e = op_apply(op, M, zb, w, s))) return e;
+        } else if ((e = op_apply(op, M, vj, w, s))) {
+            return e;
+        }
+        const int k = (int)(j + 1);
+        double* h1 = hb;
+        double* h2 = hb + k;
+        double* hn = hb + 2 * k;
+        // two passes of classical Gram-Schmidt
+        if ((e = dots(k, w))) return e;
+        hipLaunchKernelGGL(k_reduce<false>, dim3(lb_blocks(k, 4)), dim3(256), 0, s, (const double*)part, nparts, k,
+                           h1);
+        LB_CHECK_LAUNCH();
+        if ((e = update(k, h1, 1.0, w, false))) return e;
+        if ((e = dots(k, w))) return e;
+        hipLaunchKernelGGL(k_reduce<false>, dim3(lb_blocks(k, 4)), dim3(256), 0, s, (const double*)part, nparts, k,
+                           h2);
+        LB_CHECK_LAUNCH();
+        if ((e = update(k, h2, 1.0, w, true))) return e;
+        hipLaunchKernelGGL(k_reduce<true>, dim3(1), dim3(256), 0, s, (const double*)part, nparts, 1, hn);
+        LB_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_divide, dim3(eg), dim3(256), 0, s, M, (const double*)w, (const double*)hn, vn);
+        LB_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, (int)j, (const double*)hb, Hd, ldh, csd, snd, gd, resd,
+                           brkd);
+        LB_CHECK_LAUNCH();
+        return LB_OK;
+    };
     // ||K||: the scale of the residual
     double knorm = 0.0;
     LB_HIP(hipMemcpyAsync(r, K, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
@@ -373,8 +682,9 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
         info->converged = 1;
         return LB_OK;
     }
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    std::vector<double> y(m);
     int64_t total = 0;
+    int64_t cycles = 0;
     for (;;) {
         // r = -K - Q x
         if ((rc = op_apply(op, M, x, w, s))) return rc;
@@ -388,86 +698,57 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
             break;
         }
         if (total >= maxit) break;
+        ++cycles;
         hipLaunchKernelGGL(k_divide, dim3(eg), dim3(256), 0, s, M, (const double*)r, (const double*)nrm, b.V);
+        hipLaunchKernelGGL(k_init_g, dim3(lb_blocks(m + 1, 256)), dim3(256), 0, s, m + 1, (const double*)nrm, gd);
         LB_CHECK_LAUNCH();
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
-        int64_t j = 0;
-        bool done = false;
-        for (; j < m && total < maxit && !done; ++j, ++total) {
-            double* vj = b.V + j * ldv;
-            double* vn = b.V + (j + 1) * ldv;
-            if (pre) {  // right preconditioning: w = Q P^-1 v_j
-                if ((rc = lb_impl_secular_apply(c, pre, vj, zb)) || (rc = op_apply(op, M, zb, w, s))) return rc;
-            } else if ((rc = op_apply(op, M, vj, w, s))) {
-                return rc;
-            }
-            const int k = (int)(j + 1);
-            // two passes of classical Gram-Schmidt
-            double* h1 = hb;
-            double* h2 = hb + k;
-            double* hn = hb + 2 * k;
-            if ((rc = dots(k, w))) return rc;
-            hipLaunchKernelGGL(k_reduce<false>, dim3(lb_blocks(k, 4)), dim3(256), 0, s, (const double*)part, nparts,
-                               k, h1);
-            LB_CHECK_LAUNCH();
-            if ((rc = update(k, h1, 1.0, w, false))) return rc;
-            if ((rc = dots(k, w))) return rc;
-            hipLaunchKernelGGL(k_reduce<false>, dim3(lb_blocks(k, 4)), dim3(256), 0, s, (const double*)part, nparts,
-                               k, h2);
-            LB_CHECK_LAUNCH();
-            if ((rc = update(k, h2, 1.0, w, true))) return rc;
-            hipLaunchKernelGGL(k_reduce<true>, dim3(1), dim3(256), 0, s, (const double*)part, nparts, 1, hn);
-            LB_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_divide, dim3(eg), dim3(256), 0, s, M, (const double*)w, (const double*)hn, vn);
-            LB_CHECK_LAUNCH();
-            LB_HIP(hipMemcpyAsync(hh, hb, sizeof(double) * (2 * k + 1), hipMemcpyDeviceToHost, s));
+        // Arnoldi steps in batches of kLook between reads of the residual estimates
+        const int64_t lim = std::min<int64_t>(m, maxit - total);
+        int64_t j = 0, used = 0;
+        while (j < lim && used == 0) {
+            const int64_t nb = std::min<int64_t>(kLook, lim - j);
+            for (int64_t t = 0; t < nb; ++t)
+                if ((rc = arnoldi(j + t))) return rc;
+            LB_HIP(hipMemcpyAsync(hh, resd + j, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+            LB_HIP(hipMemcpyAsync(hh + kLook, brkd + j, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
             LB_HIP(hipStreamSynchronize(s));
-            double* Hj = &H[(size_t)j * (m + 1)];  // column j, rows 0..j+1
-            for (int i = 0; i < k; ++i) Hj[i] = hh[i] + hh[k + i];
-            Hj[k] = hh[2 * k];
-            // previous rotations, then the one that zeroes H[j+1][j]
-            for (int64_t i = 0; i < j; ++i) {
-                const double a = Hj[i], bb = Hj[i + 1];
-                Hj[i] = cs[i] * a + sn[i] * bb;
-                Hj[i + 1] = -sn[i] * a + cs[i] * bb;
-            }
-            const double a = Hj[j], bb = Hj[j + 1];
-            const double den = hypot(a, bb);
-            cs[j] = den > 0 ? a / den : 1.0;
-            sn[j] = den > 0 ? bb / den : 0.0;
-            Hj[j] = den;
-            Hj[j + 1] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            if (fabs(g[j + 1]) <= tol * knorm || hh[2 * k] == 0.0) done = true;
+            for (int64_t t = 0; t < nb && used == 0; ++t)
+                if (hh[t] <= tol * knorm || hh[kLook + t] == 0.0) used = j + t + 1;
+            j += nb;
         }
-        // y = R^-1 g, x += V y
-        const int64_t k = j;
+        const int64_t k = used ? used : j;  // columns of the least-squares problem
+        total += k;
+        // y = R^-1 g (R: the leading k x k block of the rotated H), then x += P^-1 V y
+        if ((rc = lb_host_reserve(c, sizeof(double) * ((size_t)k * k + k + 2 * kLook)))) return rc;
+        hh = (double*)c->host;
+        double* Rh = hh;
+        double* gh = hh + (size_t)k * k;
+        LB_HIP(hipMemcpy2DAsync(Rh, sizeof(double) * k, Hd, sizeof(double) * ldh, sizeof(double) * k, k,
+                                hipMemcpyDeviceToHost, s));
+        LB_HIP(hipMemcpyAsync(gh, gd, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+        LB_HIP(hipStreamSynchronize(s));
         for (int64_t i = k - 1; i >= 0; --i) {
-            double t = g[i];
-            for (int64_t l = i + 1; l < k; ++l) t -= H[(size_t)l * (m + 1) + i] * y[l];
-            const double d = H[(size_t)i * (m + 1) + i];
+            double t = gh[i];
+            for (int64_t l = i + 1; l < k; ++l) t -= Rh[(size_t)l * k + i] * y[l];
+            const double d = Rh[(size_t)i * k + i];
             y[i] = d != 0.0 ? t / d : 0.0;
         }
         LB_HIP(hipMemcpyAsync(yd, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
-        if (pre) {  // x += P^-1 V y
+        if (pre) {
             LB_HIP(hipMemsetAsync(ub, 0, sizeof(double) * M, s));
             if ((rc = update((int)k, yd, -1.0, ub, false))) return rc;
             if ((rc = lb_impl_secular_apply(c, pre, ub, zb))) return rc;
             hipLaunchKernelGGL(k_axpby, dim3(eg), dim3(256), 0, s, M, 1.0, (const double*)x, 1.0, (const double*)zb,
                                x);
             LB_CHECK_LAUNCH();
-        } else {
-            if ((rc = update((int)k, yd, -1.0, x, false))) return rc;
+        } else if ((rc = update((int)k, yd, -1.0, x, false))) {
+            return rc;
         }
-        info->iterations = total;
-        ++info->restarts;
     }
     LB_HIP(hipMemcpyAsync(v, x, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
     LB_HIP(hipStreamSynchronize(s));
     info->iterations = total;
-    info->restarts = info->restarts > 0 ? info->restarts - 1 : 0;
+    info->restarts = cycles > 0 ? cycles - 1 : 0;
     if (!info->converged)
         return lb_fail(LB_ERR_NO_CONVERGENCE, "GMRES stopped after %lld iterations at relative residual %.3e",
                        (long long)total, info->residual);

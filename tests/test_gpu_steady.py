@@ -222,3 +222,30 @@ def test_preconditioner_for_another_size_is_rejected(lb, ctx):
         lb.lindblad_steady_state_csr(ctx, rp, col, val, K, pre=pre)
     assert e.value.code == -1
     pre.close()
+
+
+def test_preconditioned_dimer_large_delayed_gram_schmidt(lb, ctx, oracle):
+    """N = 520 (M = 270399, past the size where the solver switches to delayed
+    Gram-Schmidt with two basis passes per step): residual recomputed here,
+    rho_inf a density matrix, and the same populations as the solve at the
+    neighbouring size's structure would give (trace, Hermiticity, positivity)."""
+    N = 520
+    print("[gpu] preconditioned steady state (delayed Gram-Schmidt), dimer N=%d" % N, flush=True)
+    H, rates, Ls = wl.dimer_model(N)
+    Hc, Lc = dcsr(H), [dcsr(L) for L in Ls]
+    rp, col, val, K = lb.lindblad_prepare_sparse(ctx, N, Hc, rates, Lc)
+    pre = lb.Secular(ctx, N, Hc, rates, Lc)
+    v, info = lb.lindblad_steady_state_csr(ctx, rp, col, val, K, tol=1e-12, pre=pre)
+    assert info["converged"] == 1
+    M = N * N - 1
+    Qs = torch.sparse_csr_tensor(rp.cpu(), col.cpu(), val.cpu(), size=(M, M))
+    r = (Qs @ v.cpu()) + K.cpu()
+    assert float(r.norm() / K.cpu().norm()) < 2e-12
+    rho = oracle.reconstruct(N, v.cpu().numpy())
+    assert abs(np.trace(rho) - 1) < 1e-13
+    assert np.abs(rho - rho.conj().T).max() < 1e-14
+    assert np.linalg.eigvalsh(rho).min() > -1e-12
+    # deterministic
+    v2, info2 = lb.lindblad_steady_state_csr(ctx, rp, col, val, K, tol=1e-12, pre=pre)
+    assert torch.equal(v, v2) and info2["iterations"] == info["iterations"]
+    pre.close()
