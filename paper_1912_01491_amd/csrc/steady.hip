@@ -270,6 +270,44 @@ struct SolveBufs {
     }
 };
 
+// Applies the rotations 0..j-1 to column Hj (rows 0..j+1), then the rotation
+// that zeroes Hj[j+1], also applied to g; res = |g[j+1]|. One thread: the
+// rotations are a recurrence through the carried entry, so the loads of eight
+// steps are issued together.
+__device__ void givens_column(int j, double* __restrict__ Hj, double* __restrict__ cs, double* __restrict__ sn,
+                              double* __restrict__ g, double* res) {
+    double carry = Hj[0];
+    int i = 0;
+    for (; i + 8 <= j; i += 8) {
+        double b[8], c[8], s[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            b[u] = Hj[i + 1 + u];
+            c[u] = cs[i + u];
+            s[u] = sn[i + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            Hj[i + u] = c[u] * carry + s[u] * b[u];
+            carry = -s[u] * carry + c[u] * b[u];
+        }
+    }
+    for (; i < j; ++i) {
+        const double b = Hj[i + 1];
+        Hj[i] = cs[i] * carry + sn[i] * b;
+        carry = -sn[i] * carry + cs[i] * b;
+    }
+    const double a = carry, b = Hj[j + 1];
+    const double den = hypot(a, b);
+    cs[j] = den > 0 ? a / den : 1.0;
+    sn[j] = den > 0 ? b / den : 0.0;
+    Hj[j] = den;
+    Hj[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    *res = fabs(g[j + 1]);
+}
+
 // Delayed classical Gram-Schmidt with reorthogonalisation (large systems):
 // entering step j the basis V_[0,j) is orthonormal and u is the next vector
 // after one projection (not yet reorthogonalised or normalised). With
@@ -375,20 +413,7 @@ __global__ __launch_bounds__(256) void k_dcgs2_fin(int j, const double* sz, doub
     __syncthreads();
     if (threadIdx.x == 0) {
         const int jj = j - 1;
-        for (int i = 0; i < jj; ++i) {
-            const double a = Hj[i], b = Hj[i + 1];
-            Hj[i] = cs[i] * a + sn[i] * b;
-            Hj[i + 1] = -sn[i] * a + cs[i] * b;
-        }
-        const double a = Hj[jj], b = Hj[jj + 1];
-        const double den = hypot(a, b);
-        cs[jj] = den > 0 ? a / den : 1.0;
-        sn[jj] = den > 0 ? b / den : 0.0;
-        Hj[jj] = den;
-        Hj[jj + 1] = 0.0;
-        g[jj + 1] = -sn[jj] * g[jj];
-        g[jj] = cs[jj] * g[jj];
-        res[jj] = fabs(g[jj + 1]);
+        givens_column(jj, Hj, cs, sn, g, res + jj);
         brk[jj] = om;
         scal[0] = om;
         scal[1] = sh[1];
@@ -452,29 +477,19 @@ __global__ void k_copy_first(const double* src, double* dst) {
 // j+1) from the two Gram-Schmidt passes, the earlier Givens rotations applied
 // in order, then the rotation that zeroes row j+1, applied to g as well;
 // res[j] = |g[j+1]| (the residual norm of the least-squares solution) and
-// brk[j] = |w|. One thread: the rotations are a serial recurrence.
+// brk[j] = |w|. The wavefront fills the column; one thread rotates it.
 __global__ void k_givens(int j, const double* hb, double* H, int64_t ldh, double* cs, double* sn, double* g,
                          double* res, double* brk) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (blockIdx.x != 0) return;
     const int k = j + 1;
     double* Hj = H + (int64_t)j * ldh;
-    for (int i = 0; i < k; ++i) Hj[i] = hb[i] + hb[k + i];
-    Hj[k] = hb[2 * k];
-    for (int i = 0; i < j; ++i) {
-        const double a = Hj[i], b = Hj[i + 1];
-        Hj[i] = cs[i] * a + sn[i] * b;
-        Hj[i + 1] = -sn[i] * a + cs[i] * b;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) Hj[i] = hb[i] + hb[k + i];
+    if (threadIdx.x == 0) Hj[k] = hb[2 * k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        givens_column(j, Hj, cs, sn, g, res + j);
+        brk[j] = hb[2 * k];
     }
-    const double a = Hj[j], b = Hj[j + 1];
-    const double den = hypot(a, b);
-    cs[j] = den > 0 ? a / den : 1.0;
-    sn[j] = den > 0 ? b / den : 0.0;
-    Hj[j] = den;
-    Hj[j + 1] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
-    res[j] = fabs(g[j + 1]);
-    brk[j] = hb[2 * k];
 }
 
 // g = (beta, 0, ..., 0) with beta = |r| on the device.
