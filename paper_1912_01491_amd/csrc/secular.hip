@@ -46,7 +46,10 @@ namespace {
 __global__ void k_csr_dense_cm(int N, const int64_t* rowptr, const int64_t* col, const double2* val, double2* D) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= N) return;
-    for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) D[r + col[e] * N] = val[e];
+    for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {  // duplicate entries add up, as in the CSR's sum
+        double2& d = D[r + col[e] * N];
+        d = make_double2(d.x + val[e].x, d.y + val[e].y);
+    }
 }
 
 // W += g |Lt|^2 elementwise; d = diag(Lt).
