@@ -869,8 +869,10 @@ __global__ __launch_bounds__(256) void k_sell_stage(SellMat a, SellStage st, int
     double* Acc = st.W;
     const double* Xin = (stage & 1) ? st.W + n : st.W + 2 * n;
     double* Xout = (stage & 1) ? st.W + 2 * n : st.W + n;
-    if ((int)blockIdx.x < a.nlong) {
-        const int64_t row = a.longrows[blockIdx.x];
+    const int wk = sell_work(a);
+    if (wk < 0) return;
+    if (wk < a.nlong) {
+        const int64_t row = a.longrows[wk];
         for (int b = 0; b < st.B; ++b) {
             double q0, q1;
             block_row_dots<DRIVE>(a, row, Xin + (int64_t)b * M, q0, q1);
@@ -885,7 +887,7 @@ __global__ __launch_bounds__(256) void k_sell_stage(SellMat a, SellStage st, int
         return;
     }
     // one slice per wavefront; the slice index is wave-uniform
-    const int sl = __builtin_amdgcn_readfirstlane((int)((blockIdx.x - a.nlong) * 4 + (threadIdx.x >> 6)));
+    const int sl = __builtin_amdgcn_readfirstlane((wk - a.nlong) * 4 + (int)(threadIdx.x >> 6));
     if (sl >= a.S) return;
     const int lane = threadIdx.x & (kSlice - 1);
     const int64_t r = (int64_t)sl * kSlice + lane;
@@ -1517,7 +1519,7 @@ static int csr_propagate(lb_ctx* c, int64_t M, const int64_t* rowptr, const int6
     hipLaunchKernelGGL(k_copy, dim3(lb_blocks(n, 256)), dim3(256), 0, s, (const double*)V, W + n, n);
     LB_CHECK_LAUNCH();
     const SellStage st{B, K, V, W};
-    const unsigned grid = (unsigned)m.nlong + (unsigned)((m.S + 3) / 4);
+    const unsigned grid = (unsigned)m.nlong8 + 8u * (unsigned)m.per_xcd;
     typedef void (*stage_fn)(SellMat, SellStage, int, double, double);
     const stage_fn fn = drive ? (B == 1 ? k_sell_stage<true, 1> : k_sell_stage<true, 4>)
                               : (B == 1 ? k_sell_stage<false, 1> : k_sell_stage<false, 4>);

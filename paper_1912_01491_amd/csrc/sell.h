@@ -141,7 +141,24 @@ struct SellMat {
     const uint64_t* lmask;  // per slice: lanes whose row is long
     const int* longrows;
     int nlong;
+    int nlong8;   // long-row blocks padded to a multiple of 8
+    int per_xcd;  // slice groups (of four slices) per XCD; launch nlong8 + 8 * per_xcd blocks
+    int ngroups;  // slice groups
 };
+
+// Work item of this block: a long row (w < nlong) or the slice group
+// w - nlong; -1 for padding. Workgroups go to the 8 XCDs round robin by block
+// id. The long rows keep that order (they are the heavy items, spread over
+// all XCDs); the slice groups are remapped so that each XCD walks one
+// contiguous range of rows, whose gathers of x fall in a few windows of x
+// (the rows' own pairs, the partner block, the diagonal part).
+__device__ __forceinline__ int sell_work(const SellMat& m) {
+    const int b = blockIdx.x;
+    if (b < m.nlong8) return b < m.nlong ? b : -1;
+    const int sb = b - m.nlong8;
+    const int g = (sb & 7) * m.per_xcd + (sb >> 3);
+    return g < m.ngroups ? m.nlong + g : -1;
+}
 
 // acc[j] += sum over slice entries [k, k + n) of value * x_j[column], in entry
 // order, for the first nb of SB states; FULL: n == kChunk.
@@ -297,6 +314,9 @@ static int sell_build(lb_ctx* c, int64_t M, const int64_t* rowptr, const int64_t
     m.lmask = (const uint64_t*)(ws + o_mask);
     m.longrows = (const int*)(ws + o_long);
     m.nlong = hl;
+    m.nlong8 = (hl + 7) / 8 * 8;
+    m.ngroups = (int)((S + 3) / 4);
+    m.per_xcd = (m.ngroups + 7) / 8;
     hipLaunchKernelGGL(k_sell_fill, dim3(rgrid), dim3(256), 0, s, M, S, m.lmask, rowptr, col, val, m.off0,
                        (int*)(ws + o_sc0), (double*)(ws + o_sv0), two ? rowptr1 : nullptr, col1, val1, m.off1,
                        (int*)(ws + o_sc1), (double*)(ws + o_sv1));

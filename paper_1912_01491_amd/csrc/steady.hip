@@ -56,14 +56,16 @@ __global__ __launch_bounds__(256) void k_mv_dense(const double* Q, int64_t M, in
 
 // y = Q x, slice layout: one wavefront per slice, one block per long row.
 __global__ __launch_bounds__(256) void k_mv_sell(SellMat a, const double* x, double* y) {
-    if ((int)blockIdx.x < a.nlong) {
-        const int64_t row = a.longrows[blockIdx.x];
+    const int wk = sell_work(a);
+    if (wk < 0) return;
+    if (wk < a.nlong) {
+        const int64_t row = a.longrows[wk];
         double q0, q1;
         block_row_dots<false>(a, row, x, q0, q1);
         if (threadIdx.x == 0) y[row] = q0;
         return;
     }
-    const int sl = __builtin_amdgcn_readfirstlane((int)((blockIdx.x - a.nlong) * 4 + (threadIdx.x >> 6)));
+    const int sl = __builtin_amdgcn_readfirstlane((wk - a.nlong) * 4 + (int)(threadIdx.x >> 6));
     if (sl >= a.S) return;
     const int lane = threadIdx.x & (kSlice - 1);
     const int64_t r = (int64_t)sl * kSlice + lane;
@@ -240,7 +242,7 @@ struct Op {
 
 static int op_apply(const Op& op, int64_t M, const double* x, double* y, hipStream_t s) {
     if (op.sparse) {
-        const unsigned grid = (unsigned)op.m.nlong + (unsigned)((op.m.S + 3) / 4);
+        const unsigned grid = (unsigned)op.m.nlong8 + 8u * (unsigned)op.m.per_xcd;
         hipLaunchKernelGGL(k_mv_sell, dim3(grid), dim3(256), 0, s, op.m, x, y);
         LB_CHECK_LAUNCH();
         return LB_OK;
