@@ -144,19 +144,23 @@ struct SellMat {
     int nlong8;   // long-row blocks padded to a multiple of 8
     int per_xcd;  // slice groups (of four slices) per XCD; launch nlong8 + 8 * per_xcd blocks
     int ngroups;  // slice groups
+    int contig;   // slice groups in one contiguous range per XCD (sell_work)
 };
 
 // Work item of this block: a long row (w < nlong) or the slice group
 // w - nlong; -1 for padding. Workgroups go to the 8 XCDs round robin by block
 // id. The long rows keep that order (they are the heavy items, spread over
-// all XCDs); the slice groups are remapped so that each XCD walks one
-// contiguous range of rows, whose gathers of x fall in a few windows of x
-// (the rows' own pairs, the partner block, the diagonal part).
+// all XCDs). With contig the slice groups are remapped so that each XCD
+// walks one contiguous range of rows, whose gathers of x fall in three
+// windows of about M/8 doubles (the rows' own pairs, the partner block, the
+// diagonal part); that pays while those fit in the XCD's 4 MB L2 (M up to
+// about 1.4 million) and costs beyond, where the natural order, with all
+// XCDs on neighbouring rows at a time, shares one moving window instead.
 __device__ __forceinline__ int sell_work(const SellMat& m) {
     const int b = blockIdx.x;
     if (b < m.nlong8) return b < m.nlong ? b : -1;
     const int sb = b - m.nlong8;
-    const int g = (sb & 7) * m.per_xcd + (sb >> 3);
+    const int g = m.contig ? (sb & 7) * m.per_xcd + (sb >> 3) : sb;
     return g < m.ngroups ? m.nlong + g : -1;
 }
 
@@ -317,6 +321,7 @@ static int sell_build(lb_ctx* c, int64_t M, const int64_t* rowptr, const int64_t
     m.nlong8 = (hl + 7) / 8 * 8;
     m.ngroups = (int)((S + 3) / 4);
     m.per_xcd = (m.ngroups + 7) / 8;
+    m.contig = 3 * 8 * (M / 8) <= ((int64_t)4 << 20);  // three windows of M/8 doubles within 4 MB
     hipLaunchKernelGGL(k_sell_fill, dim3(rgrid), dim3(256), 0, s, M, S, m.lmask, rowptr, col, val, m.off0,
                        (int*)(ws + o_sc0), (double*)(ws + o_sv0), two ? rowptr1 : nullptr, col1, val1, m.off1,
                        (int*)(ws + o_sc1), (double*)(ws + o_sv1));
