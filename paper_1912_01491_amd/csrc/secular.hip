@@ -37,7 +37,7 @@ struct lb_secular {
     double* Binv = nullptr;  // inverse bordered rate matrix, (N + 1) x (N + 1), row-major
     double2* T1 = nullptr;   // scratch, N x N each
     double2* T2 = nullptr;
-    double* pv = nullptr;    // 2 (N + 1): right-hand side and populations
+    double* pv = nullptr;    // 2 (N + 1) + N: right-hand side, populations, diagonal scan
     rocblas_handle blas = nullptr;
 };
 
@@ -166,9 +166,44 @@ __global__ void k_take_inverse(int n, const double* aug, double* Binv) {
     Binv[i] = aug[(int64_t)r * 2 * n + n + c];
 }
 
+// Inclusive scans over the diagonal part, one block of 1024 threads (N <= 2048,
+// two entries per thread, a Hillis-Steele scan of the pair sums in LDS).
+// SUFFIX = false: out[x] = sum_{y <= x} Re Y_yy (prefix sums of the diagonal).
+// SUFFIX = true:  out[x] = sum_{l >= x} v_D(l) / sqrt(l (l + 1)) for l = 1..N-1,
+// the weight that D^l puts on every position below l.
+template <bool SUFFIX>
+__global__ __launch_bounds__(1024) void k_diag_scan(int N, const double2* Y, const double* v, double* out) {
+    __shared__ double sh[1024];
+    const int64_t P = lb_npairs(N);
+    const int t = threadIdx.x;
+    auto item = [&](int x) -> double {
+        if (x >= N) return 0.0;
+        if (!SUFFIX) return Y[x + (int64_t)x * N].x;
+        const int l = N - 1 - x;  // reversed order: suffix sums as prefix sums
+        return l >= 1 ? v[2 * P + l - 1] / sqrt((double)l * (l + 1)) : 0.0;
+    };
+    const double a = item(2 * t), b = item(2 * t + 1);
+    sh[t] = a + b;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const double add = t >= o ? sh[t - o] : 0.0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    const double before = t > 0 ? sh[t - 1] : 0.0;
+    auto put = [&](int x, double val) {
+        if (x >= N) return;
+        if (!SUFFIX) out[x] = val;
+        else out[N - 1 - x] = val;
+    };
+    put(2 * t, before + a);
+    put(2 * t + 1, before + a + b);
+}
+
 // R = sum_n r_n F_n (traceless Hermitian, column-major). Threads below P write
 // pair q's two entries, threads from P on write a diagonal element.
-__global__ void k_v_to_herm(int N, const double* v, double2* R) {
+__global__ void k_v_to_herm(int N, const double* v, const double* wsuf, double2* R) {
     const int64_t P = lb_npairs(N);
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const double s2 = 0.70710678118654752440;
@@ -182,15 +217,15 @@ __global__ void k_v_to_herm(int N, const double* v, double2* R) {
     }
     const int64_t x = t - P;
     if (x >= N) return;
-    // D^l has 1 at positions < l and -l at position l (scaled by 1/sqrt(l(l+1)))
-    double d = 0.0;
-    for (int l = (int)x + 1; l < N; ++l) d += v[2 * P + l - 1] / sqrt((double)l * (l + 1));
+    // D^l has 1 at positions < l and -l at position l (scaled by 1/sqrt(l(l+1)));
+    // wsuf[x + 1] = sum over l > x of the scaled coefficients
+    double d = x + 1 < N ? wsuf[x + 1] : 0.0;
     if (x >= 1) d -= (double)x * v[2 * P + x - 1] / sqrt((double)x * (x + 1));
     R[x + x * N] = make_double2(d, 0.0);
 }
 
 // z_n = Re Tr(F_n Y).
-__global__ void k_herm_to_v(int N, const double2* Y, double* z) {
+__global__ void k_herm_to_v(int N, const double2* Y, const double* dpre, double* z) {
     const int64_t P = lb_npairs(N);
     const int64_t M = (int64_t)N * N - 1;
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -203,10 +238,8 @@ __global__ void k_herm_to_v(int N, const double2* Y, double* z) {
     } else if (cls == 1) {
         z[n] = (Y[k + (int64_t)j * N].y - Y[j + (int64_t)k * N].y) * s2;
     } else {
-        const int l = j;
-        double s = 0.0;
-        for (int x = 0; x < l; ++x) s += Y[x + (int64_t)x * N].x;
-        z[n] = (s - (double)l * Y[l + (int64_t)l * N].x) / sqrt((double)l * (l + 1));
+        const int l = j;  // dpre[l - 1] = sum over x < l of Re Y_xx
+        z[n] = (dpre[l - 1] - (double)l * Y[l + (int64_t)l * N].x) / sqrt((double)l * (l + 1));
     }
 }
 
@@ -298,7 +331,7 @@ int lb_impl_secular_create(lb_ctx* c, int N, const lb_csr_c128* H, int P, const 
     if ((rc = dmalloc((void**)&pre->U, sizeof(double2) * NN)) || (rc = dmalloc((void**)&pre->den, sizeof(double2) * NN)) ||
         (rc = dmalloc((void**)&pre->Binv, sizeof(double) * (size_t)n * n)) ||
         (rc = dmalloc((void**)&pre->T1, sizeof(double2) * NN)) || (rc = dmalloc((void**)&pre->T2, sizeof(double2) * NN)) ||
-        (rc = dmalloc((void**)&pre->pv, sizeof(double) * 2 * (size_t)n)))
+        (rc = dmalloc((void**)&pre->pv, sizeof(double) * (2 * (size_t)n + N))))
         return cleanup(rc);
     const int Pm = P > 0 ? P : 1;
     if ((rc = dmalloc((void**)&Hd, sizeof(double2) * NN)) || (rc = dmalloc((void**)&E, sizeof(double) * N)) ||
@@ -371,7 +404,9 @@ int lb_impl_secular_apply(lb_ctx* c, const lb_secular* pre, const double* r, dou
     const int64_t P = lb_npairs(N);
     int rc;
     if ((rc = blas_ok(rocblas_set_stream(pre->blas, s)))) return rc;
-    hipLaunchKernelGGL(k_v_to_herm, dim3(lb_blocks(P + N, 256)), dim3(256), 0, s, N, r, pre->T1);
+    double* scan = pre->pv + 2 * n;
+    hipLaunchKernelGGL(k_diag_scan<true>, dim3(1), dim3(1024), 0, s, N, (const double2*)nullptr, r, scan);
+    hipLaunchKernelGGL(k_v_to_herm, dim3(lb_blocks(P + N, 256)), dim3(256), 0, s, N, r, (const double*)scan, pre->T1);
     LB_CHECK_LAUNCH();
     if ((rc = zgemm(pre->blas, rocblas_operation_none, rocblas_operation_none, N, pre->T1, pre->U, pre->T2)) ||
         (rc = zgemm(pre->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, N, pre->U, pre->T2,
@@ -387,7 +422,10 @@ int lb_impl_secular_apply(lb_ctx* c, const lb_secular* pre, const double* r, dou
                     pre->T2)) ||
         (rc = zgemm(pre->blas, rocblas_operation_none, rocblas_operation_none, N, pre->U, pre->T2, pre->T1)))
         return rc;
-    hipLaunchKernelGGL(k_herm_to_v, dim3(lb_blocks(NN - 1, 256)), dim3(256), 0, s, N, (const double2*)pre->T1, z);
+    hipLaunchKernelGGL(k_diag_scan<false>, dim3(1), dim3(1024), 0, s, N, (const double2*)pre->T1, (const double*)nullptr,
+                       scan);
+    hipLaunchKernelGGL(k_herm_to_v, dim3(lb_blocks(NN - 1, 256)), dim3(256), 0, s, N, (const double2*)pre->T1,
+                       (const double*)scan, z);
     LB_CHECK_LAUNCH();
     return LB_OK;
 }
