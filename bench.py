@@ -90,7 +90,7 @@ def parse():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle RK4 steps in the CPU sample")
-    ap.add_argument("--config", choices=["c1", "c2", "c2p", "c3", "c4", "c5", "c5r", "c6", "c6s"], default="c4",
+    ap.add_argument("--config", choices=["c1", "c2", "c2p", "c3", "c4", "c5", "c5r", "c6", "c6s", "c7"], default="c4",
                     help="c4: the N=200 dense headline (default); c1: N=8 dense; c2: N=1000 sparse dimer; "
                          "c3: N=100 dense, 64 states, FP64 vs FP32; c5: serving mix (prepare per request); "
                          "c5r: serving mix on resident systems; c2p: the periodically rocked dimer (one period)")
@@ -103,6 +103,7 @@ def parse():
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--arrival", choices=["burst", "poisson"], default="burst")
     ap.add_argument("--ss-N", type=int, default=1000, help="c6s: dimer size")
+    ap.add_argument("--persist-dir", default=None, help="c7: directory for the saved files (default: temp dir)")
     ap.add_argument("--ss-maxit", type=int, default=6000, help="c6s: GMRES iteration limit")
     ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrival rate (requests/s)")
     ap.add_argument("--slots", type=int, default=6)
@@ -613,6 +614,66 @@ def config_c6s(args):
     print(json.dumps(out), flush=True)
 
 
+def config_c7(args):
+    """Saving and loading prepared systems (the paper integrates from stored,
+    prepared data, Sec. 5): the N=100 dense random Lindbladian (Q 800 MB) and
+    the N=1000 sparse dimer (7.49 M stored entries) written to a file and read
+    back, the payload hash recomputed on load. The file system is the box's;
+    a file just written may still be in the page cache, so the load rate is
+    that of a warm read."""
+    import tempfile
+
+    import torch
+
+    import paper_1912_01491_amd as lb
+    from paper_1912_01491_amd import workloads as wl
+
+    ctx = lb.Context(0)
+    d = args.persist_dir or tempfile.gettempdir()
+    out = {}
+    N = 100
+    H = torch.from_numpy(wl.gue_hamiltonian(N, 0)).cuda()
+    gamma = wl.wishart_kossakowski_device(N, 1)
+    Q, K = lb.lindblad_prepare(ctx, H, gamma)
+    del gamma
+    torch.cuda.empty_cache()
+    path = os.path.join(d, "lb_c7_dense_%d.bin" % os.getpid())
+    t_save, _ = _timed(lambda: lb.save_system(ctx, path, N, K, Q=Q))
+    size = os.path.getsize(path)
+    t_load, (Q2, K2) = _timed(lambda: lb.load_system(ctx, path))
+    M = N * N - 1
+    same = bool(torch.equal(Q2[:, :M], Q[:, :M]) and torch.equal(K2, K))
+    os.remove(path)
+    log("C7: dense N=%d, %.0f MB: save %.3f s (%.2f GB/s), load %.3f s (%.2f GB/s), identical %s"
+        % (N, size / 1e6, t_save, size / t_save / 1e9, t_load, size / t_load / 1e9, same))
+    out["dense_n100"] = {"bytes": size, "save_s": t_save, "load_s": t_load, "identical": same}
+    del Q, Q2
+    torch.cuda.empty_cache()
+    N = 1000
+    Hs, rates, Ls = wl.dimer_model(N)
+
+    def dev_csr(X):
+        return tuple(torch.from_numpy(x).cuda() for x in wl.to_csr(X))
+
+    rp, col, val, K = lb.lindblad_prepare_sparse(ctx, N, dev_csr(Hs), rates, [dev_csr(L) for L in Ls])
+    path = os.path.join(d, "lb_c7_csr_%d.bin" % os.getpid())
+    t_save, _ = _timed(lambda: lb.save_system(ctx, path, N, K, csr=(rp, col, val)))
+    size2 = os.path.getsize(path)
+    t_load, ((rp2, col2, val2), K2) = _timed(lambda: lb.load_system(ctx, path))
+    same2 = bool(torch.equal(col2, col) and torch.equal(val2, val) and torch.equal(K2, K) and torch.equal(rp2, rp))
+    os.remove(path)
+    log("C7: sparse dimer N=%d, %.0f MB: save %.3f s (%.2f GB/s), load %.3f s (%.2f GB/s), identical %s"
+        % (N, size2 / 1e6, t_save, size2 / t_save / 1e9, t_load, size2 / t_load / 1e9, same2))
+    out["dimer_n1000"] = {"bytes": size2, "save_s": t_save, "load_s": t_load, "identical": same2}
+    res = {"metric": "saved systems: load rate of a prepared N=100 dense system", "value": size / out["dense_n100"]["load_s"] / 1e9,
+           "unit": "GB/s (file -> HBM, hash checked)", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+           "data": "synthetic", "config": {"workload": "save and load of the prepared N=100 dense random "
+                                                       "Lindbladian (Q, K) and the N=1000 sparse dimer (CSR, K)"},
+           "results": out}
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
 def config_c3(args):
     """N=100 (M=9999) dense random Lindbladian, GUE H, Wishart gamma; 64 random
     pure states, 2000 RK4 steps dt=1e-3, FP64 (matrix cores) and FP32 matrix
@@ -712,9 +773,9 @@ def main():
         return pmc_probe(args)
     if args.serving or args.config in ("c5", "c5r"):
         return serving(args)
-    if args.config in ("c1", "c2", "c2p", "c3", "c6", "c6s"):
+    if args.config in ("c1", "c2", "c2p", "c3", "c6", "c6s", "c7"):
         return {"c1": config_c1, "c2": config_c2, "c2p": config_c2p, "c3": config_c3, "c6": config_c6,
-                "c6s": config_c6s}[args.config](args)
+                "c6s": config_c6s, "c7": config_c7}[args.config](args)
     import numpy as np
     import torch
 

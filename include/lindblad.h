@@ -52,6 +52,8 @@ extern "C" {
 #define LB_ERR_ADMISSION (-6)     /* a serving request does not fit the server's memory budget */
 #define LB_ERR_NO_CONVERGENCE (-7) /* an iterative solve stopped at its iteration limit before its
                                       tolerance; the outputs hold the last iterate */
+#define LB_ERR_IO (-8)            /* a file could not be opened, read or written, or is not a valid
+                                     saved system (bad header, short, payload hash mismatch) */
 
 #define LB_MAX_N 2048             /* largest Hilbert-space dimension accepted (dense inputs of that
                                      size would not fit in memory; the sparse path reaches it) */
@@ -230,6 +232,47 @@ int lindblad_propagate_batched(lb_ctx* ctx, int R, int64_t M, const double* cons
  * afterwards; otherwise identical to lindblad_propagate. */
 int lindblad_propagate_graph(lb_ctx* ctx, int64_t M, const double* Q, const float* Q32, int64_t ldq,
                              const double* K, double* V, int B, double dt, int64_t steps, int precision);
+
+/* ------------------------------------------------------------------ */
+/* Saved systems (Sec. 5: the integration runs from prepared, stored data) */
+/* ------------------------------------------------------------------ */
+
+#define LB_SYSTEM_DENSE 0
+#define LB_SYSTEM_CSR 1
+
+/* A prepared system in device memory: dense Q and K as written by
+ * lindblad_prepare, or CSR Q and K as written by lindblad_prepare_sparse_fill. */
+typedef struct lb_system {
+    int kind;          /* LB_SYSTEM_DENSE or LB_SYSTEM_CSR */
+    int N;             /* Hilbert-space dimension, M = N*N - 1 */
+    int64_t ldq;       /* dense: leading dimension of Q (>= M) */
+    int64_t nnz;       /* CSR: stored entries */
+    double* Q;         /* dense: M x ldq, row-major */
+    int64_t* rowptr;   /* CSR: M + 1 */
+    int64_t* col;      /* CSR: nnz */
+    double* val;       /* CSR: nnz */
+    double* K;         /* M */
+} lb_system;
+
+/* Writes the system to a file: an 80-byte header (magic "LBSYSTEM", version,
+ * kind, N, M, nnz, a hash of the payload computed on the device), then Q (dense:
+ * M rows of M doubles, whatever ldq; CSR: rowptr, col, val) and K, in the
+ * host's (little-endian) byte order. Streams through pinned staging buffers;
+ * returns after the file is written and flushed. Errors: LB_ERR_INVALID_ARG
+ * (sizes, null pointers, CSR rowptr[M] != nnz), LB_ERR_IO, LB_ERR_OOM,
+ * LB_ERR_DEVICE. */
+int lindblad_save_system(lb_ctx* ctx, const char* path, const lb_system* sys);
+
+/* Reads only the header (host, no device work): fills kind, N and nnz of
+ * *sys, so that the caller can allocate the buffers; leaves the rest. */
+int lindblad_load_system_info(const char* path, lb_system* sys);
+
+/* Loads a saved system into caller-allocated device buffers described by *sys
+ * (kind, N, nnz must match the file; dense Q may have any ldq >= M, its padding
+ * columns are zeroed). The payload hash is recomputed on the device and
+ * compared: LB_ERR_IO if the file is not a valid saved system or is corrupt,
+ * LB_ERR_INVALID_ARG if the buffers describe another system. Synchronous. */
+int lindblad_load_system(lb_ctx* ctx, const char* path, lb_system* sys);
 
 /* ------------------------------------------------------------------ */
 /* Steady state (Sec. 3: the asymptotic state rho_inf, L(rho_inf) = 0) */

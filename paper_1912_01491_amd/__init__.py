@@ -24,7 +24,7 @@ __all__ = [
     "lb_expand", "lb_expand_pure", "lb_reconstruct",
     "lindblad_prepare", "lindblad_q_to_f32", "lindblad_propagate", "lindblad_propagate_batched",
     "lindblad_propagate_graph", "lindblad_propagate_csr", "lindblad_prepare_sparse",
-    "lindblad_propagate_csr_drive", "lb_eigh", "Secular", "lindblad_steady_state", "lindblad_steady_state_csr", "lindblad_autotune", "lindblad_tile_info", "lindblad_set_tile", "lindblad_time_stage", "Server",
+    "lindblad_propagate_csr_drive", "lb_eigh", "Secular", "save_system", "load_system", "load_system_info", "lindblad_steady_state", "lindblad_steady_state_csr", "lindblad_autotune", "lindblad_tile_info", "lindblad_set_tile", "lindblad_time_stage", "Server",
     "FP64", "FP32", "CHECK_HERMITIAN",
 ]
 
@@ -38,7 +38,7 @@ _LIB_PATH = os.path.join(_HERE, "_build", "liblindblad.so")
 _lib = None
 
 _ERRORS = {-1: "invalid argument", -2: "not Hermitian", -3: "out of memory", -4: "device error",
-           -5: "unsupported", -6: "admission", -7: "no convergence"}
+           -5: "unsupported", -6: "admission", -7: "no convergence", -8: "i/o"}
 
 
 class LibraryMissing(RuntimeError):
@@ -102,6 +102,9 @@ def signatures():
         "lindblad_propagate_csr": [V, I64, V, V, V, V, V, I, D, I64],
         "lindblad_propagate_csr_drive": [V, I64, V, V, V, V, V, V, V, V, I, D, I64, D, D, D, D],
         "lb_eigh": [V, I, V, I, V, V, I, V],
+        "lindblad_save_system": [V, ctypes.c_char_p, V],
+        "lindblad_load_system_info": [ctypes.c_char_p, V],
+        "lindblad_load_system": [V, ctypes.c_char_p, V],
         "lindblad_steady_state": [V, I64, V, I64, V, V, V, D, I64, I64, V],
         "lindblad_steady_state_csr": [V, I64, V, V, V, V, V, V, D, I64, I64, V],
         "lindblad_secular_create": [V, I, V, I, V, V, ctypes.POINTER(ctypes.c_void_p)],
@@ -420,6 +423,68 @@ def lb_eigh(ctx: Context, A):
     sw = ctypes.c_int()
     _check(load().lb_eigh(ctx.handle, N, _ptr(work), N, _ptr(w), _ptr(Zc), N, ctypes.byref(sw)))
     return w, Zc.transpose(0, 1), sw.value
+
+
+class _System(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("N", ctypes.c_int), ("ldq", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("Q", ctypes.c_void_p), ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("val", ctypes.c_void_p), ("K", ctypes.c_void_p)]
+
+
+SYSTEM_DENSE = 0
+SYSTEM_CSR = 1
+
+
+def save_system(ctx: Context, path: str, N: int, K, Q=None, csr=None):
+    """Writes a prepared system to `path`: dense Q (M x ldq) or csr = (rowptr,
+    col, val) as written by lindblad_prepare_sparse, and K (device tensors)."""
+    import torch
+    _need(K, torch.float64, "K")
+    s = _System()
+    s.N = N
+    s.K = K.data_ptr()
+    if Q is not None:
+        _need(Q, torch.float64, "Q")
+        s.kind, s.ldq, s.Q = SYSTEM_DENSE, Q.stride(0), Q.data_ptr()
+    else:
+        rp, col, val = csr
+        _need(rp, torch.int64, "rowptr")
+        _need(val, torch.float64, "val")
+        s.kind, s.nnz, s.rowptr, s.col, s.val = SYSTEM_CSR, col.numel(), rp.data_ptr(), col.data_ptr(), val.data_ptr()
+    _check(load().lindblad_save_system(ctx.handle, path.encode(), ctypes.byref(s)))
+
+
+def load_system_info(path: str):
+    """(kind, N, nnz) from the file's header (host only)."""
+    s = _System()
+    _check(load().lindblad_load_system_info(path.encode(), ctypes.byref(s)))
+    return s.kind, s.N, s.nnz
+
+
+def load_system(ctx: Context, path: str, ldq: int | None = None):
+    """Loads a saved system into new device tensors: (Q, K) for a dense file
+    (Q of shape (M, ldq), default ldq as lindblad_prepare), ((rowptr, col,
+    val), K) for a CSR file."""
+    import torch
+    kind, N, nnz = load_system_info(path)
+    M = N * N - 1
+    dev = _dev(ctx)
+    s = _System()
+    s.kind, s.N, s.nnz = kind, N, nnz
+    K = torch.empty(M, dtype=torch.float64, device=dev)
+    s.K = K.data_ptr()
+    if kind == SYSTEM_DENSE:
+        ldq = default_ldq(M) if ldq is None else int(ldq)
+        Q = torch.empty((M, ldq), dtype=torch.float64, device=dev)
+        s.ldq, s.Q = ldq, Q.data_ptr()
+        _check(load().lindblad_load_system(ctx.handle, path.encode(), ctypes.byref(s)))
+        return Q, K
+    rp = torch.empty(M + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(max(nnz, 1), dtype=torch.int64, device=dev)
+    val = torch.empty(max(nnz, 1), dtype=torch.float64, device=dev)
+    s.rowptr, s.col, s.val = rp.data_ptr(), col.data_ptr(), val.data_ptr()
+    _check(load().lindblad_load_system(ctx.handle, path.encode(), ctypes.byref(s)))
+    return (rp, col[:nnz], val[:nnz]), K
 
 
 class SolveInfo(ctypes.Structure):

@@ -324,6 +324,45 @@ int lindblad_propagate_csr_drive(lb_ctx* c, int64_t M, const int64_t* rowptr0, c
                                        T);
 }
 
+static int system_args(const lb_system* sys) {
+    if (!sys) return lb_fail(LB_ERR_INVALID_ARG, "null system");
+    if (sys->N < 2 || sys->N > LB_MAX_N) return lb_fail(LB_ERR_INVALID_ARG, "N=%d out of range", sys->N);
+    const int64_t M = (int64_t)sys->N * sys->N - 1;
+    if (!sys->K) return lb_fail(LB_ERR_INVALID_ARG, "null K");
+    if (sys->kind == LB_SYSTEM_DENSE) {
+        if (!sys->Q) return lb_fail(LB_ERR_INVALID_ARG, "null Q");
+        if (sys->ldq < M) return lb_fail(LB_ERR_INVALID_ARG, "ldq < M");
+    } else if (sys->kind == LB_SYSTEM_CSR) {
+        if (!sys->rowptr || sys->nnz < 0 || (sys->nnz > 0 && (!sys->col || !sys->val)))
+            return lb_fail(LB_ERR_INVALID_ARG, "bad CSR");
+    } else {
+        return lb_fail(LB_ERR_INVALID_ARG, "unknown kind %d", sys->kind);
+    }
+    return LB_OK;
+}
+
+int lindblad_save_system(lb_ctx* c, const char* path, const lb_system* sys) {
+    CHECK_CTX(c);
+    CHECK_PTR(path);
+    int rc = system_args(sys);
+    if (rc) return rc;
+    return lb_impl_save_system(c, path, sys);
+}
+
+int lindblad_load_system_info(const char* path, lb_system* sys) {
+    CHECK_PTR(path);
+    CHECK_PTR(sys);
+    return lb_impl_load_system_info(path, sys);
+}
+
+int lindblad_load_system(lb_ctx* c, const char* path, lb_system* sys) {
+    CHECK_CTX(c);
+    CHECK_PTR(path);
+    int rc = system_args(sys);
+    if (rc) return rc;
+    return lb_impl_load_system(c, path, sys);
+}
+
 int lb_eigh(lb_ctx* c, int N, double* A, int lda, double* w, double* Z, int ldz, int* sweeps) {
     CHECK_CTX(c);
     CHECK_PTR(A);

@@ -212,6 +212,9 @@ int lb_impl_propagate_csr_drive(lb_ctx* c, int64_t M, const int64_t* rowptr0, co
                                 const double* K, double* V, int B, double dt, int64_t steps, double t0, double E,
                                 double A, double T);
 int lb_impl_q_to_f32(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, float* Q32);
+int lb_impl_save_system(lb_ctx* c, const char* path, const lb_system* sys);
+int lb_impl_load_system_info(const char* path, lb_system* sys);
+int lb_impl_load_system(lb_ctx* c, const char* path, lb_system* sys);
 int lb_impl_eigh(lb_ctx* c, int N, double* A, int lda, double* w, double* Z, int ldz, int* sweeps);
 int lb_impl_steady_dense(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, const double* K, const lb_secular* pre,
                          double* v, double tol, int64_t maxit, int64_t restart, lb_solve_info* info);
