@@ -205,18 +205,21 @@ int lindblad_propagate_csr(lb_ctx* ctx, int64_t M, const int64_t* rowptr, const 
  * [T/2, T), period T. Q_H is linear in H and the drive adds nothing to K, so
  * the system is dv/dt = (Q0 + eps(t) Q1) v + K with Q0 (from H0 and the jump
  * operators) and Q1 (from H1 alone, no jump operators) as written by
- * lindblad_prepare_sparse_fill, and K that of Q0. Classic RK4 from time t0:
- * step k evaluates eps at t0 + k dt and t0 + (k + 1/2) dt from the right and at
- * t0 + (k + 1) dt as the limit from the left, i.e. each step sees the drive of
+ * lindblad_prepare_sparse_fill, and K that of Q0. Classic RK4 over steps k0,
+ * k0 + 1, ..., k0 + steps - 1 of the time grid t0 + k dt: step k evaluates eps
+ * at t0 + k dt and t0 + (k + 1/2) dt from the right and at t0 + (k + 1) dt as
+ * the limit from the left, i.e. each step sees the drive of
  * the interval it integrates, so steps that end on a switch (T/2 a multiple of
  * dt, as with 20000 steps per period) integrate one constant system and the
- * scheme keeps fourth order. FP64, B states in V (B*M), in place; errors as
- * lindblad_propagate_csr, plus LB_ERR_INVALID_ARG for a non-finite t0, E, A or
- * T <= 0. */
+ * scheme keeps fourth order. A run split at step k0 and continued with the
+ * same t0 and the step offset k0 is bit-identical to the uninterrupted run
+ * (every stage time is formed from t0 and the global step index). FP64, B
+ * states in V (B*M), in place; errors as lindblad_propagate_csr, plus
+ * LB_ERR_INVALID_ARG for a non-finite t0, E, A, T <= 0 or k0 < 0. */
 int lindblad_propagate_csr_drive(lb_ctx* ctx, int64_t M, const int64_t* rowptr0, const int64_t* col0,
                                  const double* val0, const int64_t* rowptr1, const int64_t* col1,
                                  const double* val1, const double* K, double* V, int B, double dt,
-                                 int64_t steps, double t0, double E, double A, double T);
+                                 int64_t steps, double t0, int64_t k0, double E, double A, double T);
 
 /* Batched variant: R independent systems of the same M (e.g. ensemble
  * realizations), Q[r], K[r], V[r] device pointers given in host arrays of

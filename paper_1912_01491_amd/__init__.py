@@ -100,7 +100,7 @@ def signatures():
         "lindblad_propagate": [V, I64, V, V, I64, V, V, I, D, I64, I],
         "lindblad_q_to_f32": [V, I64, V, I64, V],
         "lindblad_propagate_csr": [V, I64, V, V, V, V, V, I, D, I64],
-        "lindblad_propagate_csr_drive": [V, I64, V, V, V, V, V, V, V, V, I, D, I64, D, D, D, D],
+        "lindblad_propagate_csr_drive": [V, I64, V, V, V, V, V, V, V, V, I, D, I64, D, I64, D, D, D],
         "lb_eigh": [V, I, V, I, V, V, I, V],
         "lindblad_save_system": [V, ctypes.c_char_p, V],
         "lindblad_load_system_info": [ctypes.c_char_p, V],
@@ -567,9 +567,10 @@ def lindblad_steady_state_csr(ctx: Context, rowptr, col, val, K, tol: float = 1e
 
 
 def lindblad_propagate_csr_drive(ctx: Context, Q0, Q1, K, V, dt: float, steps: int, t0: float, E: float, A: float,
-                                 T: float):
+                                 T: float, k0: int = 0):
     """In place: RK4 of dv/dt = (Q0 + eps(t) Q1) v + K with the square-wave
-    drive eps(t) = E + A Theta(t); Q0, Q1 are (rowptr, col, val) CSR triples."""
+    drive eps(t) = E + A Theta(t) over steps k0 .. k0 + steps - 1 of the grid
+    t0 + k dt; Q0, Q1 are (rowptr, col, val) CSR triples."""
     import torch
     for name, (rp, c, v) in (("Q0", Q0), ("Q1", Q1)):
         _need(rp, torch.int64, name + " rowptr")
@@ -582,7 +583,7 @@ def lindblad_propagate_csr_drive(ctx: Context, Q0, Q1, K, V, dt: float, steps: i
         raise ValueError("Q0 and Q1 must have the same number of rows")
     _check(load().lindblad_propagate_csr_drive(ctx.handle, M, _ptr(Q0[0]), _ptr(Q0[1]), _ptr(Q0[2]), _ptr(Q1[0]),
                                                _ptr(Q1[1]), _ptr(Q1[2]), _ptr(K), _ptr(V), V.shape[0], float(dt),
-                                               int(steps), float(t0), float(E), float(A), float(T)))
+                                               int(steps), float(t0), int(k0), float(E), float(A), float(T)))
     return V
 
 

@@ -308,8 +308,8 @@ int lindblad_propagate_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const in
 
 int lindblad_propagate_csr_drive(lb_ctx* c, int64_t M, const int64_t* rowptr0, const int64_t* col0,
                                  const double* val0, const int64_t* rowptr1, const int64_t* col1, const double* val1,
-                                 const double* K, double* V, int B, double dt, int64_t steps, double t0, double E,
-                                 double A, double T) {
+                                 const double* K, double* V, int B, double dt, int64_t steps, double t0, int64_t k0,
+                                 double E, double A, double T) {
     CHECK_CTX(c);
     CHECK_PTR(rowptr0);
     CHECK_PTR(rowptr1);
@@ -318,10 +318,10 @@ int lindblad_propagate_csr_drive(lb_ctx* c, int64_t M, const int64_t* rowptr0, c
     if (M < 3) return lb_fail(LB_ERR_INVALID_ARG, "M too small");
     if (B < 1 || B > 64) return lb_fail(LB_ERR_INVALID_ARG, "B=%d out of range", B);
     if (!isfinite(dt) || steps < 0) return lb_fail(LB_ERR_INVALID_ARG, "bad dt/steps");
-    if (!isfinite(t0) || !isfinite(E) || !isfinite(A) || !(T > 0) || !isfinite(T))
-        return lb_fail(LB_ERR_INVALID_ARG, "drive needs finite t0, E, A and a period T > 0");
-    return lb_impl_propagate_csr_drive(c, M, rowptr0, col0, val0, rowptr1, col1, val1, K, V, B, dt, steps, t0, E, A,
-                                       T);
+    if (!isfinite(t0) || !isfinite(E) || !isfinite(A) || !(T > 0) || !isfinite(T) || k0 < 0)
+        return lb_fail(LB_ERR_INVALID_ARG, "drive needs finite t0, E, A, a period T > 0 and k0 >= 0");
+    return lb_impl_propagate_csr_drive(c, M, rowptr0, col0, val0, rowptr1, col1, val1, K, V, B, dt, steps, t0, k0, E,
+                                       A, T);
 }
 
 static int system_args(const lb_system* sys) {

@@ -209,8 +209,8 @@ int lb_impl_propagate_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int
                           int64_t steps);
 int lb_impl_propagate_csr_drive(lb_ctx* c, int64_t M, const int64_t* rowptr0, const int64_t* col0,
                                 const double* val0, const int64_t* rowptr1, const int64_t* col1, const double* val1,
-                                const double* K, double* V, int B, double dt, int64_t steps, double t0, double E,
-                                double A, double T);
+                                const double* K, double* V, int B, double dt, int64_t steps, double t0, int64_t k0,
+                                double E, double A, double T);
 int lb_impl_q_to_f32(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, float* Q32);
 int lb_impl_save_system(lb_ctx* c, const char* path, const lb_system* sys);
 int lb_impl_load_system_info(const char* path, lb_system* sys);

@@ -1506,7 +1506,7 @@ static double stage_time(double t0, int64_t k, double c, double dt) {
 
 static int csr_propagate(lb_ctx* c, int64_t M, const int64_t* rowptr, const int64_t* col, const double* val,
                          const int64_t* rowptr1, const int64_t* col1, const double* val1, const double* K, double* V,
-                         int B, double dt, int64_t steps, double t0, double E, double A, double T) {
+                         int B, double dt, int64_t steps, double t0, int64_t k0, double E, double A, double T) {
     hipStream_t s = c->stream;
     if (steps == 0) return LB_OK;
     const bool drive = rowptr1 != nullptr;
@@ -1529,7 +1529,7 @@ static int csr_propagate(lb_ctx* c, int64_t M, const int64_t* rowptr, const int6
             if (drive) {
                 // stages seen from inside the step: t_k and t_k + dt/2 from the right, t_k + dt from the left
                 const double cst = stage == 1 ? 0.0 : (stage == 4 ? 1.0 : 0.5);
-                eps = drive_value(stage_time(t0, k, cst, dt), E, A, T, stage == 4);
+                eps = drive_value(stage_time(t0, k0 + k, cst, dt), E, A, T, stage == 4);
             }
             hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, s, m, st, stage, dt, eps);
             LB_CHECK_LAUNCH();
@@ -1539,12 +1539,12 @@ static int csr_propagate(lb_ctx* c, int64_t M, const int64_t* rowptr, const int6
 
 int lb_impl_propagate_csr(lb_ctx* c, int64_t M, const int64_t* rowptr, const int64_t* col, const double* val,
                           const double* K, double* V, int B, double dt, int64_t steps) {
-    return csr_propagate(c, M, rowptr, col, val, nullptr, nullptr, nullptr, K, V, B, dt, steps, 0.0, 0.0, 0.0, 1.0);
+    return csr_propagate(c, M, rowptr, col, val, nullptr, nullptr, nullptr, K, V, B, dt, steps, 0.0, 0, 0.0, 0.0, 1.0);
 }
 
 int lb_impl_propagate_csr_drive(lb_ctx* c, int64_t M, const int64_t* rowptr0, const int64_t* col0,
                                 const double* val0, const int64_t* rowptr1, const int64_t* col1, const double* val1,
-                                const double* K, double* V, int B, double dt, int64_t steps, double t0, double E,
-                                double A, double T) {
-    return csr_propagate(c, M, rowptr0, col0, val0, rowptr1, col1, val1, K, V, B, dt, steps, t0, E, A, T);
+                                const double* K, double* V, int B, double dt, int64_t steps, double t0, int64_t k0,
+                                double E, double A, double T) {
+    return csr_propagate(c, M, rowptr0, col0, val0, rowptr1, col1, val1, K, V, B, dt, steps, t0, k0, E, A, T);
 }
