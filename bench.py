@@ -911,6 +911,16 @@ def main():
         "checks": {"max_abs_trace_err": tr_err, "max_herm_err": herm, "min_eig_rho": mineig,
                    "K_finite": finite},
     }
+    # the device's read-stream rate, measured after the timed region: the practical ceiling
+    # of the HBM-bound stage kernel next to the published peak
+    Qs.clear()
+    if Q32s is not None:
+        Q32s.clear()
+    torch.cuda.empty_cache()
+    read_gbs = lb.read_bandwidth(ctx, 4 << 30)
+    out["roofline"]["measured_read_gbs"] = read_gbs
+    out["roofline"]["frac_of_measured_read"] = achieved / read_gbs
+    log("read-stream probe: %.0f GB/s; stage kernel at %.1f %% of it" % (read_gbs, 100.0 * achieved / read_gbs))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(M, B, args.cpu_steps)
     ctx.close()

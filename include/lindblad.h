@@ -342,6 +342,17 @@ int lindblad_steady_state_csr(lb_ctx* ctx, int64_t M, const int64_t* rowptr, con
                               double tol, int64_t maxit, int64_t restart, lb_solve_info* info);
 
 /* ------------------------------------------------------------------ */
+/* Measurement                                                        */
+/* ------------------------------------------------------------------ */
+
+/* Read-stream bandwidth of the context's device in GB/s (1e9 bytes/s): a
+ * reduction over a buffer of `bytes` (allocated and freed by the call) with
+ * 16-byte nontemporal loads, timed with HIP events, the best of five grid
+ * sizes. The practical ceiling next to the published HBM peak for the
+ * bandwidth-bound kernels. Synchronous. */
+int lb_read_bandwidth(lb_ctx* ctx, size_t bytes, double* gbs);
+
+/* ------------------------------------------------------------------ */
 /* Tuning                                                             */
 /* ------------------------------------------------------------------ */
 

@@ -24,7 +24,7 @@ __all__ = [
     "lb_expand", "lb_expand_pure", "lb_reconstruct",
     "lindblad_prepare", "lindblad_q_to_f32", "lindblad_propagate", "lindblad_propagate_batched",
     "lindblad_propagate_graph", "lindblad_propagate_csr", "lindblad_prepare_sparse",
-    "lindblad_propagate_csr_drive", "lb_eigh", "Secular", "save_system", "load_system", "load_system_info", "lindblad_steady_state", "lindblad_steady_state_csr", "lindblad_autotune", "lindblad_tile_info", "lindblad_set_tile", "lindblad_time_stage", "Server",
+    "lindblad_propagate_csr_drive", "lb_eigh", "Secular", "read_bandwidth", "save_system", "load_system", "load_system_info", "lindblad_steady_state", "lindblad_steady_state_csr", "lindblad_autotune", "lindblad_tile_info", "lindblad_set_tile", "lindblad_time_stage", "Server",
     "FP64", "FP32", "CHECK_HERMITIAN",
 ]
 
@@ -102,6 +102,7 @@ def signatures():
         "lindblad_propagate_csr": [V, I64, V, V, V, V, V, I, D, I64],
         "lindblad_propagate_csr_drive": [V, I64, V, V, V, V, V, V, V, V, I, D, I64, D, I64, D, D, D],
         "lb_eigh": [V, I, V, I, V, V, I, V],
+        "lb_read_bandwidth": [V, ctypes.c_size_t, V],
         "lindblad_save_system": [V, ctypes.c_char_p, V],
         "lindblad_load_system_info": [ctypes.c_char_p, V],
         "lindblad_load_system": [V, ctypes.c_char_p, V],
@@ -423,6 +424,13 @@ def lb_eigh(ctx: Context, A):
     sw = ctypes.c_int()
     _check(load().lb_eigh(ctx.handle, N, _ptr(work), N, _ptr(w), _ptr(Zc), N, ctypes.byref(sw)))
     return w, Zc.transpose(0, 1), sw.value
+
+
+def read_bandwidth(ctx: Context, nbytes: int = 4 << 30) -> float:
+    """The device's read-stream bandwidth in GB/s (lb_read_bandwidth)."""
+    g = ctypes.c_double()
+    _check(load().lb_read_bandwidth(ctx.handle, int(nbytes), ctypes.byref(g)))
+    return g.value
 
 
 class _System(ctypes.Structure):

@@ -324,6 +324,13 @@ int lindblad_propagate_csr_drive(lb_ctx* c, int64_t M, const int64_t* rowptr0, c
                                        A, T);
 }
 
+int lb_read_bandwidth(lb_ctx* c, size_t bytes, double* gbs) {
+    CHECK_CTX(c);
+    CHECK_PTR(gbs);
+    if (bytes < ((size_t)1 << 20)) return lb_fail(LB_ERR_INVALID_ARG, "probe needs at least 1 MiB");
+    return lb_impl_read_bandwidth(c, bytes, gbs);
+}
+
 static int system_args(const lb_system* sys) {
     if (!sys) return lb_fail(LB_ERR_INVALID_ARG, "null system");
     if (sys->N < 2 || sys->N > LB_MAX_N) return lb_fail(LB_ERR_INVALID_ARG, "N=%d out of range", sys->N);

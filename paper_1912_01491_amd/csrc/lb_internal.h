@@ -215,6 +215,7 @@ int lb_impl_q_to_f32(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, float* 
 int lb_impl_save_system(lb_ctx* c, const char* path, const lb_system* sys);
 int lb_impl_load_system_info(const char* path, lb_system* sys);
 int lb_impl_load_system(lb_ctx* c, const char* path, lb_system* sys);
+int lb_impl_read_bandwidth(lb_ctx* c, size_t bytes, double* gbs);
 int lb_impl_eigh(lb_ctx* c, int N, double* A, int lda, double* w, double* Z, int ldz, int* sweeps);
 int lb_impl_steady_dense(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, const double* K, const lb_secular* pre,
                          double* v, double tol, int64_t maxit, int64_t restart, lb_solve_info* info);
