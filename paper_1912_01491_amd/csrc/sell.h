@@ -22,7 +22,7 @@ namespace {
 
 constexpr int kLongRow = 32;
 constexpr int kSlice = 64;
-constexpr int kChunk = 8;  // slice entries per lane loaded before their products
+constexpr int kChunk = 4;  // slice entries per lane loaded before their products
 
 // Slice widths (as 64 * entries, later scanned into offsets), the long-row
 // mask of each slice and the list of long rows. One wavefront per slice.
