@@ -337,7 +337,34 @@ __global__ __launch_bounds__(256) void k_dots2(const double* V, int64_t ldv, int
     }
     const int p = blockIdx.x * 4 + wave;
     const int j0 = blockIdx.y * kDotJ, j1 = min(k, j0 + kDotJ);
-    for (int j = j0; j < j1; ++j) {
+    int j = j0;
+    // four basis vectors per round: 4 E loads issued before the products and reductions
+    for (; j + 4 <= j1; j += 4) {
+        double x[4][E];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int64_t i = base + e * 256;
+                x[q][e] = i < M ? V[(int64_t)(j + q) * ldv + i] : 0.0;
+            }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double a = 0.0, b = 0.0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                a = fma(x[q][e], uv[e], a);
+                b = fma(x[q][e], tv[e], b);
+            }
+            a = wave_sum(a);
+            b = wave_sum(b);
+            if (lane == 0) {
+                part[(int64_t)(2 * (j + q)) * nparts + p] = a;
+                part[(int64_t)(2 * (j + q) + 1) * nparts + p] = b;
+            }
+        }
+    }
+    for (; j < j1; ++j) {
         const double* vj = V + (int64_t)j * ldv;
         double a = 0.0, b = 0.0;
 #pragma unroll
@@ -445,7 +472,31 @@ __global__ __launch_bounds__(256) void k_dcgs2_upd(double* V, int64_t ldv, int j
     double a[E], b[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) a[e] = b[e] = 0.0;
-    for (int l = 0; l < j; ++l) {
+    // four basis vectors per round: their coefficients and 4 E loads issued before the products
+    int l = 0;
+    for (; l + 4 <= j; l += 4) {
+        double sc[4], zc[4], x[4][E];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            sc[u] = sz[2 * (l + u)];
+            zc[u] = sz[2 * (l + u) + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int64_t i = base + e * 256;
+                x[u][e] = i < M ? V[(int64_t)(l + u) * ldv + i] : 0.0;
+            }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                a[e] = fma(sc[u], x[u][e], a[e]);
+                b[e] = fma(zc[u], x[u][e], b[e]);
+            }
+    }
+    for (; l < j; ++l) {
         const double sl = sz[2 * l], zl = sz[2 * l + 1];
         const double* vl = V + (int64_t)l * ldv;
 #pragma unroll
