@@ -21,6 +21,29 @@ __device__ __forceinline__ void wave_rowdots(const double* const* qrow, const do
     for (int t = 0; t < R; ++t) acc[t] = 0.0;
     int64_t c = 2 * lane;
     if (ALIGNED) {
+        // four column steps per round: their 4 (R + 1) loads issued before the products, which
+        // then run in the same order as one step at a time
+        for (; c + 3 * 128 + 1 < M; c += 4 * 128) {
+            double2 xv[4];
+            lb_double2v q[4][R];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                xv[u] = *reinterpret_cast<const double2*>(x + c + u * 128);
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    const double* a = qrow[t] + c + u * 128;
+                    if (NT) q[u][t] = __builtin_nontemporal_load((const lb_double2v __attribute__((address_space(1)))*)a);
+                    else q[u][t] = *reinterpret_cast<const lb_double2v*>(a);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    acc[t] = fma(q[u][t].x, xv[u].x, acc[t]);
+                    acc[t] = fma(q[u][t].y, xv[u].y, acc[t]);
+                }
+        }
         for (; c + 1 < M; c += 128) {
             const double2 xv = *reinterpret_cast<const double2*>(x + c);
 #pragma unroll
