@@ -19,10 +19,12 @@ Functions (all arrays numpy, complex matrices as complex128):
   rk4_dense, rk4_csr          classic RK4 for dv/dt = Qv + K (Eq. (10), step 3.1)
   drive, drive_left, rk4_drive   the rocked dimer's square-wave drive and its RK4 (Sec. 3)
   steady_state                Qv = -K, the asymptotic state rho_inf of Sec. 3 (dense solve)
+  spectrum, histogram         eigenvalues of Q and their counts on a grid (Sec. 5, Fig. 5)
 """
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -259,3 +261,30 @@ def steady_state(Q: np.ndarray, K: np.ndarray) -> np.ndarray:
     Q = _c(Q, np.float64)
     K = _c(K, np.float64)
     return np.linalg.solve(Q, -K)
+
+
+def spectrum(Q: np.ndarray) -> np.ndarray:
+    """Eigenvalues of the real generator Q of Eq. (10). With rho = 1/N + sum_n v_n F_n
+    (Eq. (7)) the Lindbladian acts on the coordinates (1, v) as the block matrix
+    [[0, 0], [K, Q]], so its spectrum is 0 together with the M = N^2 - 1 eigenvalues
+    of Q: the values histogrammed in Fig. 5. LAPACK's nonsymmetric eigenvalue
+    routine through numpy (a library primitive), complex128 in LAPACK's order."""
+    return np.linalg.eigvals(_c(Q, np.float64))
+
+
+def histogram(lam, re0: float, re1: float, im0: float, im1: float, nx: int, ny: int) -> np.ndarray:
+    """Eigenvalue counts on the nx x ny grid of Fig. 5 (100 x 100 cells there; the
+    figure divides each count by the cell area). A value lands in column
+    ix = floor((Re - re0) / dx), dx = (re1 - re0) / nx, and row iy = floor((Im - im0) / dy),
+    dy = (im1 - im0) / ny; it is counted when 0 <= (Re - re0) / dx < nx and
+    0 <= (Im - im0) / dy < ny (so the left and lower edges belong to the grid, the
+    right and upper ones do not, and NaN is never counted). Returns int64 (ny, nx)."""
+    dx = (float(re1) - float(re0)) / nx
+    dy = (float(im1) - float(im0)) / ny
+    out = np.zeros((ny, nx), np.int64)
+    for z in np.asarray(lam, np.complex128).ravel():
+        tx = (float(z.real) - float(re0)) / dx
+        ty = (float(z.imag) - float(im0)) / dy
+        if 0.0 <= tx < nx and 0.0 <= ty < ny:
+            out[int(math.floor(ty)), int(math.floor(tx))] += 1
+    return out
