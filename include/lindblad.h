@@ -342,6 +342,59 @@ int lindblad_steady_state_csr(lb_ctx* ctx, int64_t M, const int64_t* rowptr, con
                               double tol, int64_t maxit, int64_t restart, lb_solve_info* info);
 
 /* ------------------------------------------------------------------ */
+/* Spectrum of the generator (Sec. 5, Fig. 5)                         */
+/* ------------------------------------------------------------------ */
+
+/* Largest M accepted by lindblad_spectrum (N = 128): its QR stage runs in one
+ * workgroup, whose time grows as M^3. */
+#define LB_SPECTRUM_MAX_M 16383
+
+/* Reduces the real M x M matrix A (row-major, lda >= M, device) in place to
+ * upper Hessenberg form by an orthogonal similarity (Householder reflectors
+ * applied from both sides, one column at a time): entries below the
+ * subdiagonal are set to exactly zero, the eigenvalues are kept. The first
+ * stage of lindblad_spectrum, exported for tests. Errors: LB_ERR_INVALID_ARG
+ * (M < 1, M > LB_SPECTRUM_MAX_M, lda < M, null A), LB_ERR_OOM, LB_ERR_DEVICE.
+ * Asynchronous on the context stream. */
+int lb_hessenberg(lb_ctx* ctx, int64_t M, double* A, int64_t lda);
+
+typedef struct lb_spectrum_info {
+    int64_t sweeps;      /* QR sweeps over all blocks */
+    int64_t chain_steps; /* chain steps over all sweeps (each three barrier phases) */
+} lb_spectrum_info;
+
+/* Eigenvalues of the real generator Q of the ODE dv/dt = Qv + K (Eq. (10);
+ * M x M, row-major, ldq >= M, device, not modified). With rho = 1/N + sum
+ * v_n F_n (Eq. (7)) the Lindbladian acts on the coordinates (1, v) as
+ * [[0, 0], [K, Q]], so its spectrum is 0 and these M = N^2 - 1 values, the
+ * ones Fig. 5 histograms. lam receives M complex values (interleaved re, im:
+ * 2M doubles, device): complex-conjugate pairs adjacent with the positive
+ * imaginary part first, otherwise in no particular order. Works on a copy of Q
+ * in the context's workspace (M^2 doubles): Householder reduction to Hessenberg
+ * form, then Francis' implicit double-shift QR iteration (eigenvalues only)
+ * with chains of up to 16 bulges whose shifts are the eigenvalues of the
+ * trailing block; a block splits off where a subdiagonal entry falls below
+ * eps (|h_k-1,k-1| + |h_kk|), or below eps ||Q||_F once ten sweeps have passed
+ * without a split (clusters at the rounding floor). *info (may be NULL) receives the iteration
+ * counts. Synchronous. Errors: LB_ERR_INVALID_ARG (M < 1, M >
+ * LB_SPECTRUM_MAX_M, ldq < M, null pointers), LB_ERR_OOM,
+ * LB_ERR_NO_CONVERGENCE (120 sweeps without a split; lam is then not valid),
+ * LB_ERR_DEVICE. */
+int lindblad_spectrum(lb_ctx* ctx, int64_t M, const double* Q, int64_t ldq, double* lam, lb_spectrum_info* info);
+
+/* Counts of the n complex values lam (interleaved re, im, device) per cell of
+ * the nx x ny grid over [re0, re1) x [im0, im1) (Fig. 5: a 100 x 100 grid, each
+ * count divided by the cell area). A value lands in column
+ * floor((re - re0) / dx), dx = (re1 - re0) / nx, and row floor((im - im0) / dy),
+ * dy = (im1 - im0) / ny, and is counted when 0 <= (re - re0) / dx < nx and
+ * 0 <= (im - im0) / dy < ny; others (NaN included) are not. counts: ny x nx
+ * int64, row-major (row = imaginary cell), device, overwritten. Errors:
+ * LB_ERR_INVALID_ARG (n < 0, nx or ny < 1, nx * ny > 2^26, re1 <= re0,
+ * im1 <= im0, non-finite bounds, null pointers), LB_ERR_DEVICE. Asynchronous. */
+int lindblad_spectrum_histogram(lb_ctx* ctx, int64_t n, const double* lam, double re0, double re1, double im0,
+                                double im1, int nx, int ny, int64_t* counts);
+
+/* ------------------------------------------------------------------ */
 /* Measurement                                                        */
 /* ------------------------------------------------------------------ */
 

@@ -24,7 +24,8 @@ __all__ = [
     "lb_expand", "lb_expand_pure", "lb_reconstruct",
     "lindblad_prepare", "lindblad_q_to_f32", "lindblad_propagate", "lindblad_propagate_batched",
     "lindblad_propagate_graph", "lindblad_propagate_csr", "lindblad_prepare_sparse",
-    "lindblad_propagate_csr_drive", "lb_eigh", "Secular", "read_bandwidth", "save_system", "load_system", "load_system_info", "lindblad_steady_state", "lindblad_steady_state_csr", "lindblad_autotune", "lindblad_tile_info", "lindblad_set_tile", "lindblad_time_stage", "Server",
+    "lindblad_propagate_csr_drive", "lb_eigh", "Secular", "read_bandwidth", "lb_hessenberg", "lindblad_spectrum",
+    "lindblad_spectrum_histogram", "save_system", "load_system", "load_system_info", "lindblad_steady_state", "lindblad_steady_state_csr", "lindblad_autotune", "lindblad_tile_info", "lindblad_set_tile", "lindblad_time_stage", "Server",
     "FP64", "FP32", "CHECK_HERMITIAN",
 ]
 
@@ -103,6 +104,9 @@ def signatures():
         "lindblad_propagate_csr_drive": [V, I64, V, V, V, V, V, V, V, V, I, D, I64, D, I64, D, D, D],
         "lb_eigh": [V, I, V, I, V, V, I, V],
         "lb_read_bandwidth": [V, ctypes.c_size_t, V],
+        "lb_hessenberg": [V, I64, V, I64],
+        "lindblad_spectrum": [V, I64, V, I64, V, V],
+        "lindblad_spectrum_histogram": [V, I64, V, D, D, D, D, I, I, V],
         "lindblad_save_system": [V, ctypes.c_char_p, V],
         "lindblad_load_system_info": [ctypes.c_char_p, V],
         "lindblad_load_system": [V, ctypes.c_char_p, V],
@@ -424,6 +428,50 @@ def lb_eigh(ctx: Context, A):
     sw = ctypes.c_int()
     _check(load().lb_eigh(ctx.handle, N, _ptr(work), N, _ptr(w), _ptr(Zc), N, ctypes.byref(sw)))
     return w, Zc.transpose(0, 1), sw.value
+
+
+class SpectrumInfo(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("chain_steps", ctypes.c_int64)]
+
+
+def lb_hessenberg(ctx: Context, A):
+    """Reduces the square float64 matrix A (device, rows of M, or a column slice of
+    wider rows) in place to upper Hessenberg form by an orthogonal similarity."""
+    import torch
+    if not isinstance(A, torch.Tensor) or not A.is_cuda or A.dtype != torch.float64:
+        raise ValueError("A must be a float64 CUDA (HIP) tensor")
+    M = A.shape[0]
+    if A.dim() != 2 or A.shape[1] != M or A.stride(1) != 1:
+        raise ValueError("A must be M x M with unit column stride")
+    _check(load().lb_hessenberg(ctx.handle, M, _ptr(A), A.stride(0)))
+    return A
+
+
+def lindblad_spectrum(ctx: Context, Q):
+    """Eigenvalues of the generator Q (float64 M x M on the device, rows may be
+    padded: Q = buffer[:, :M]). Returns (lam, info): lam complex128 (M,) on the
+    device, conjugate pairs adjacent; info = {sweeps, chain_steps}."""
+    import torch
+    if not isinstance(Q, torch.Tensor) or not Q.is_cuda or Q.dtype != torch.float64:
+        raise ValueError("Q must be a float64 CUDA (HIP) tensor")
+    M = Q.shape[0]
+    if Q.dim() != 2 or Q.shape[1] != M or Q.stride(1) != 1:
+        raise ValueError("Q must be M x M with unit column stride")
+    lam = torch.empty(2 * M, dtype=torch.float64, device=Q.device)
+    info = SpectrumInfo()
+    _check(load().lindblad_spectrum(ctx.handle, M, _ptr(Q), Q.stride(0), _ptr(lam), ctypes.byref(info)))
+    return torch.view_as_complex(lam.view(M, 2)), {"sweeps": info.sweeps, "chain_steps": info.chain_steps}
+
+
+def lindblad_spectrum_histogram(ctx: Context, lam, re0: float, re1: float, im0: float, im1: float, nx: int, ny: int):
+    """Counts of the complex128 values lam (device) per cell of the nx x ny grid
+    over [re0, re1) x [im0, im1); int64 (ny, nx), row = imaginary cell."""
+    import torch
+    _need(lam, torch.complex128, "lam")
+    counts = torch.empty((ny, nx), dtype=torch.int64, device=lam.device)
+    _check(load().lindblad_spectrum_histogram(ctx.handle, lam.numel(), _ptr(torch.view_as_real(lam)), float(re0),
+                                              float(re1), float(im0), float(im1), int(nx), int(ny), _ptr(counts)))
+    return counts
 
 
 def read_bandwidth(ctx: Context, nbytes: int = 4 << 30) -> float:

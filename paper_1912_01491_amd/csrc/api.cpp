@@ -331,6 +331,42 @@ int lb_read_bandwidth(lb_ctx* c, size_t bytes, double* gbs) {
     return lb_impl_read_bandwidth(c, bytes, gbs);
 }
 
+int lb_hessenberg(lb_ctx* c, int64_t M, double* A, int64_t lda) {
+    CHECK_CTX(c);
+    CHECK_PTR(A);
+    if (M < 1 || M > LB_SPECTRUM_MAX_M) return lb_fail(LB_ERR_INVALID_ARG, "M out of range [1, %d]", LB_SPECTRUM_MAX_M);
+    if (lda < M) return lb_fail(LB_ERR_INVALID_ARG, "lda < M");
+    return lb_impl_hessenberg(c, (int)M, A, lda);
+}
+
+int lindblad_spectrum(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, double* lam, lb_spectrum_info* info) {
+    CHECK_CTX(c);
+    CHECK_PTR(Q);
+    CHECK_PTR(lam);
+    if (M < 1 || M > LB_SPECTRUM_MAX_M) return lb_fail(LB_ERR_INVALID_ARG, "M out of range [1, %d]", LB_SPECTRUM_MAX_M);
+    if (ldq < M) return lb_fail(LB_ERR_INVALID_ARG, "ldq < M");
+    int64_t sweeps = 0, steps = 0;
+    const int rc = lb_impl_spectrum(c, (int)M, Q, ldq, lam, &sweeps, &steps);
+    if (info) {
+        info->sweeps = sweeps;
+        info->chain_steps = steps;
+    }
+    return rc;
+}
+
+int lindblad_spectrum_histogram(lb_ctx* c, int64_t n, const double* lam, double re0, double re1, double im0,
+                                double im1, int nx, int ny, int64_t* counts) {
+    CHECK_CTX(c);
+    CHECK_PTR(counts);
+    if (n < 0 || (n > 0 && !lam)) return lb_fail(LB_ERR_INVALID_ARG, "bad n or null lam");
+    if (nx < 1 || ny < 1 || (int64_t)nx * ny > ((int64_t)1 << 26))
+        return lb_fail(LB_ERR_INVALID_ARG, "grid %d x %d out of range", nx, ny);
+    if (!std::isfinite(re0) || !std::isfinite(re1) || !std::isfinite(im0) || !std::isfinite(im1) || !(re1 > re0) ||
+        !(im1 > im0))
+        return lb_fail(LB_ERR_INVALID_ARG, "grid bounds must be finite with re1 > re0 and im1 > im0");
+    return lb_impl_spectrum_histogram(c, n, lam, re0, re1, im0, im1, nx, ny, counts);
+}
+
 static int system_args(const lb_system* sys) {
     if (!sys) return lb_fail(LB_ERR_INVALID_ARG, "null system");
     if (sys->N < 2 || sys->N > LB_MAX_N) return lb_fail(LB_ERR_INVALID_ARG, "N=%d out of range", sys->N);

@@ -1,0 +1,578 @@
+// Spectrum of the real generator Q (Sec. 5, Fig. 5): with rho = 1/N + sum v_n F_n the
+// Lindbladian acts on the coordinates (1, v) as [[0, 0], [K, Q]], so its spectrum is 0
+// and the M = N^2 - 1 eigenvalues of Q, which Fig. 5 histograms on a grid.
+//
+// Two stages on a copy of Q (row-major, leading dimension M):
+//  1. Householder reduction to upper Hessenberg form, one column j at a time. The
+//     reflector P = 1 - tau v v^T (v_0 = 1 on rows j+1..M-1) is applied from both
+//     sides in one rank-2 update, P A P = A - v w^T - (tau p) v^T with p = A v,
+//     q = A^T v, s = v^T p and w = tau q - tau^2 s v: a row-dot pass (p), a column
+//     pass (q, partial sums per row chunk reduced in fixed order), and the update.
+//  2. Francis' implicit double-shift QR iteration on the Hessenberg matrix,
+//     eigenvalues only (updates stay inside the active block), in one workgroup.
+//     A sweep chases a chain of up to kMaxBulges double-shift bulges spaced
+//     kSep = 4 rows apart: at that spacing no bulge's reflector reads what another
+//     bulge writes in the same step, and reflections from the two sides commute, so
+//     each chain step is three parallel phases (all reflectors, all row updates, all
+//     column updates) instead of three phases per bulge. The 2b shifts of a b-bulge
+//     chain are the eigenvalues of the trailing 2b x 2b block, found by the same
+//     iteration with one bulge on a copy in LDS. A block splits off where a
+//     subdiagonal entry falls below eps (|h_k-1,k-1| + |h_kk|), or below eps ||H||_F
+//     after ten sweeps without a split; 1 x 1 and 2 x 2 blocks give their eigenvalues
+//     directly. Every tenth sweep without a split takes an exceptional shift to break
+//     cycles; kMaxIts sweeps without one is an error.
+#include "lb_internal.h"
+
+#include <float.h>
+#include <math.h>
+
+namespace {
+
+constexpr int kQrThreads = 1024;
+constexpr int kMaxBulges = 16;              // 32 shifts per sweep
+constexpr int kSep = 4;                     // rows between neighbouring bulges
+constexpr int kShiftDim = 2 * kMaxBulges;   // trailing block solved for the shifts
+constexpr int kMaxIts = 120;                // sweeps without a split before giving up
+constexpr int kChunkRows = 256;             // row chunk of the column pass
+constexpr int kMaxChunks = 64;
+
+// ---------------------------------------------------------------------------
+// Stage 1: Hessenberg reduction
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double block_sum256(double x, double* red) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Reflector of column j: x = A[j+1.., j]; writes beta e_1 into the column, v (v_0 = 1)
+// and tau (0 when the column is already reduced).
+__global__ __launch_bounds__(256) void k_hh_house(double* A, int64_t ld, int M, int j, double* v, double* sc) {
+    __shared__ double red[4];
+    __shared__ double bc[2];
+    const int L = M - j - 1;
+    double s = 0.0;
+    for (int i = 1 + threadIdx.x; i < L; i += 256) {
+        const double x = A[(int64_t)(j + 1 + i) * ld + j];
+        s = fma(x, x, s);
+    }
+    const double sigma = block_sum256(s, red);
+    if (threadIdx.x == 0) {
+        const double alpha = A[(int64_t)(j + 1) * ld + j];
+        double tau = 0.0, scale = 0.0;
+        if (sigma > 0.0) {
+            const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+            tau = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+            A[(int64_t)(j + 1) * ld + j] = beta;
+        }
+        bc[0] = tau;
+        bc[1] = scale;
+        sc[0] = tau;
+        v[0] = 1.0;
+    }
+    __syncthreads();
+    const double tau = bc[0], scale = bc[1];
+    for (int i = 1 + threadIdx.x; i < L; i += 256) {
+        double* a = A + (int64_t)(j + 1 + i) * ld + j;
+        v[i] = tau != 0.0 ? *a * scale : 0.0;
+        if (tau != 0.0) *a = 0.0;
+    }
+}
+
+// p[r] = sum_{c > j} A[r][c] v[c - j - 1] for every row r: one wavefront per row.
+__global__ __launch_bounds__(256) void k_hh_p(const double* A, int64_t ld, int M, int j, const double* v, double* p) {
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= M) return;
+    const double* row = A + (int64_t)r * ld + j + 1;
+    const int L = M - j - 1;
+    double s = 0.0;
+    for (int c = lane; c < L; c += 64) s = fma(row[c], v[c], s);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) p[r] = s;
+}
+
+// Partial q over one chunk of rows: qpart[chunk][c] = sum_{r in chunk} v[r - j - 1] A[r][c].
+__global__ __launch_bounds__(256) void k_hh_q(const double* A, int64_t ld, int M, int j, const double* v, double* qpart,
+                                              int rows_per_chunk) {
+    const int c = j + 1 + blockIdx.x * 256 + threadIdx.x;
+    if (c >= M) return;
+    const int r0 = j + 1 + blockIdx.y * rows_per_chunk;
+    const int r1 = min(M, r0 + rows_per_chunk);
+    double s = 0.0;
+    for (int r = r0; r < r1; ++r) s = fma(v[r - j - 1], A[(int64_t)r * ld + c], s);
+    qpart[(int64_t)blockIdx.y * M + c] = s;
+}
+
+// q[c] = sum of the chunk partials (fixed order); the last block forms s = v^T p.
+__global__ __launch_bounds__(256) void k_hh_qfin(int M, int j, int nchunks, const double* qpart, const double* v,
+                                                 const double* p, double* q, double* sc) {
+    __shared__ double red[4];
+    if (blockIdx.x == gridDim.x - 1) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < M - j - 1; i += 256) s = fma(v[i], p[j + 1 + i], s);
+        s = block_sum256(s, red);
+        if (threadIdx.x == 0) sc[1] = s;
+        return;
+    }
+    const int c = j + 1 + blockIdx.x * 256 + threadIdx.x;
+    if (c >= M) return;
+    double s = 0.0;
+    for (int k = 0; k < nchunks; ++k) s += qpart[(int64_t)k * M + c];
+    q[c] = s;
+}
+
+// A[r][c] -= v_r w_c + tau p_r v_c over rows 0..M-1 and columns j+1..M-1
+// (v_r = 0 above row j+1), w_c = tau q_c - tau^2 s v_c. A block covers 64 columns x 16 rows.
+__global__ __launch_bounds__(256) void k_hh_update(double* A, int64_t ld, int M, int j, const double* v, const double* p,
+                                                   const double* q, const double* sc) {
+    const int c = j + 1 + blockIdx.x * 64 + (threadIdx.x & 63);
+    if (c >= M) return;
+    const double tau = sc[0];
+    if (tau == 0.0) return;
+    const double s = sc[1];
+    const double vc = v[c - j - 1];
+    const double wc = tau * q[c] - tau * tau * s * vc;
+    const int rbase = blockIdx.y * 16 + (threadIdx.x >> 6) * 4;
+    for (int i = 0; i < 4; ++i) {
+        const int r = rbase + i;
+        if (r >= M) break;
+        const double vr = r > j ? v[r - j - 1] : 0.0;
+        double* a = A + (int64_t)r * ld + c;
+        *a -= fma(vr, wc, tau * p[r] * vc);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stage 2: multishift QR, one workgroup
+// ---------------------------------------------------------------------------
+
+// Block-uniform control of one QR solve; thread 0 decides, the others read after a barrier.
+struct QrCtl {
+    int u, split, its, status, b, nested;
+    int64_t sweeps, steps;
+    double anorm;                                  // ||H||_F at the start
+    double s[kMaxBulges], t[kMaxBulges];           // shift pairs: sigma1 + sigma2, sigma1 sigma2
+    int k[kMaxBulges];                             // reflector position of each bulge this step (-1: idle)
+    double tau[kMaxBulges], w1[kMaxBulges], w2[kMaxBulges];
+};
+
+__device__ __forceinline__ double& at(double* H, int64_t ld, int r, int c) { return H[(int64_t)r * ld + c]; }
+
+// Eigenvalues of [[a, b], [c, d]], conjugate pairs with the positive imaginary part first.
+__device__ void eig2(double a, double b, double c, double d, double2* l1, double2* l2) {
+    const double p = 0.5 * (a - d);
+    const double disc = p * p + b * c;
+    if (disc >= 0.0) {
+        const double z = p + copysign(sqrt(disc), p);
+        if (z == 0.0) {
+            *l1 = make_double2(d, 0.0);
+            *l2 = make_double2(d, 0.0);
+        } else {
+            *l1 = make_double2(d + z, 0.0);
+            *l2 = make_double2(d - (b * c) / z, 0.0);
+        }
+    } else {
+        const double m = 0.5 * (a + d), im = sqrt(-disc);
+        *l1 = make_double2(m, im);
+        *l2 = make_double2(m, -im);
+    }
+}
+
+// Reflector 1 - tau w w^T with w = (1, w1, w2) mapping (x, y, z) to (beta, 0, 0).
+__device__ void house3(double x, double y, double z, double* tau, double* w1, double* w2, double* beta) {
+    const double sc = fabs(x) + fabs(y) + fabs(z);
+    if (sc == 0.0 || (y == 0.0 && z == 0.0)) {
+        *tau = 0.0;
+        *w1 = *w2 = 0.0;
+        *beta = x;
+        return;
+    }
+    const double xs = x / sc, ys = y / sc, zs = z / sc;
+    const double bs = -copysign(sqrt(xs * xs + ys * ys + zs * zs), xs);
+    *tau = (bs - xs) / bs;
+    const double d = xs - bs;
+    *w1 = ys / d;
+    *w2 = zs / d;
+    *beta = bs * sc;
+}
+
+// All threads of the block call this with the same arguments. H: n x n upper Hessenberg
+// (entries below the subdiagonal are never read), row-major with leading dimension ld,
+// in global memory or LDS; destroyed. lam receives the n eigenvalues. Returns 0, or 1
+// when kMaxIts sweeps pass without a split. BMAX > 1 takes its shifts from the trailing
+// block through a nested BMAX = 1 solve on sub (kShiftDim^2 doubles, LDS).
+template <int BMAX>
+__device__ int qr_eigs(double* H, int64_t ld, int n, double2* lam, QrCtl& C, QrCtl* inner, double* sub,
+                       double2* subev) {
+    const int tid = threadIdx.x;
+    const double eps = DBL_EPSILON;
+    // Frobenius norm of the Hessenberg part: the scale of the normwise split test
+    __shared__ double part[kQrThreads / 64];
+    double m = 0.0;
+    for (int64_t e = tid; e < (int64_t)n * n; e += kQrThreads) {
+        const int r = (int)(e / n), c = (int)(e % n);
+        if (r <= c + 1) {
+            const double h = H[(int64_t)r * ld + c];
+            m = fma(h, h, m);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) m += __shfl_xor(m, o, 64);
+    if ((tid & 63) == 0) part[tid >> 6] = m;
+    __syncthreads();
+    if (tid == 0) {
+        double a = 0.0;
+        for (int w = 0; w < kQrThreads / 64; ++w) a += part[w];
+        C.anorm = a > 0.0 ? sqrt(a) : 1.0;
+        C.u = n - 1;
+        C.its = 0;
+        C.status = 0;
+        C.sweeps = 0;
+        C.steps = 0;
+        C.split = 0;
+    }
+    __syncthreads();
+    for (;;) {
+        const int u = C.u;
+        if (u < 0 || C.status) break;
+        // Largest k in [1, u] whose subdiagonal entry is negligible (0 if none): below
+        // eps times its two diagonal neighbours, or, once ten sweeps have passed without
+        // a split (a cluster whose subdiagonal sits at the rounding floor), below eps
+        // ||H||_F, a normwise backward error of the size the reduction already makes.
+        const bool stalled = C.its >= 10;
+        for (int k = u - tid; k >= 1; k -= kQrThreads) {
+            const double sd = fabs(at(H, ld, k, k - 1));
+            double tst = fabs(at(H, ld, k - 1, k - 1)) + fabs(at(H, ld, k, k));
+            if (tst == 0.0 || stalled) tst = fmax(tst, C.anorm);
+            if (sd <= eps * tst) {
+                atomicMax(&C.split, k);
+                break;
+            }
+        }
+        __syncthreads();
+        const int l = C.split;
+        __syncthreads();
+        if (l == u || l == u - 1) {
+            if (tid == 0) {
+                if (l > 0) at(H, ld, l, l - 1) = 0.0;
+                if (l == u) {
+                    lam[u] = make_double2(at(H, ld, u, u), 0.0);
+                    C.u = u - 1;
+                } else {
+                    eig2(at(H, ld, u - 1, u - 1), at(H, ld, u - 1, u), at(H, ld, u, u - 1), at(H, ld, u, u),
+                         &lam[u - 1], &lam[u]);
+                    C.u = u - 2;
+                }
+                C.its = 0;
+                C.split = 0;
+            }
+            __syncthreads();
+            continue;
+        }
+        // a sweep over the unreduced block [l, u] (at least 3 x 3)
+        if (tid == 0) {
+            if (l > 0) at(H, ld, l, l - 1) = 0.0;
+            C.split = 0;
+            C.its += 1;
+            C.sweeps += 1;
+            if (C.its > kMaxIts) C.status = 1;
+            const int na = u - l + 1;
+            int b = BMAX > 1 ? min(BMAX, max(1, na / 16)) : 1;
+            const bool exceptional = (C.its % 10) == 0;
+            C.nested = 0;
+            if (exceptional) {
+                const double w = at(H, ld, u, u) +
+                                 0.75 * (fabs(at(H, ld, u, u - 1)) + fabs(at(H, ld, u - 1, u - 2)));
+                for (int i = 0; i < b; ++i) {
+                    C.s[i] = 2.0 * w;
+                    C.t[i] = w * w;
+                }
+            } else if (b == 1) {
+                const double a = at(H, ld, u - 1, u - 1), bb = at(H, ld, u - 1, u);
+                const double c = at(H, ld, u, u - 1), d = at(H, ld, u, u);
+                C.s[0] = a + d;
+                C.t[0] = a * d - bb * c;
+            } else {
+                C.nested = 1;
+            }
+            C.b = b;
+        }
+        __syncthreads();
+        if (C.status) break;
+        const int b = C.b;
+        if constexpr (BMAX > 1) {
+            if (C.nested) {
+                const int mm = 2 * b, o = u - mm + 1;
+                for (int e = tid; e < mm * mm; e += kQrThreads) {
+                    const int r = e / mm, c = e % mm;
+                    sub[e] = r <= c + 1 ? at(H, ld, o + r, o + c) : 0.0;
+                }
+                __syncthreads();
+                const int rc = qr_eigs<1>(sub, mm, mm, subev, *inner, nullptr, nullptr, nullptr);
+                if (tid == 0) {
+                    if (rc != 0) {  // keep the sweep going with the trailing 2 x 2 shift
+                        const double a = at(H, ld, u - 1, u - 1), bb = at(H, ld, u - 1, u);
+                        const double c = at(H, ld, u, u - 1), d = at(H, ld, u, u);
+                        for (int i = 0; i < b; ++i) {
+                            C.s[i] = a + d;
+                            C.t[i] = a * d - bb * c;
+                        }
+                    } else {
+                        // complex values with positive imaginary part give one pair each;
+                        // the real ones are sorted and paired neighbour with neighbour
+                        int np = 0;
+                        double re[kShiftDim];
+                        int nr = 0;
+                        for (int i = 0; i < mm; ++i) {
+                            const double2 z = subev[i];
+                            if (z.y > 0.0) {
+                                C.s[np] = 2.0 * z.x;
+                                C.t[np] = z.x * z.x + z.y * z.y;
+                                ++np;
+                            } else if (z.y == 0.0) {
+                                int q = nr++;
+                                while (q > 0 && re[q - 1] > z.x) {
+                                    re[q] = re[q - 1];
+                                    --q;
+                                }
+                                re[q] = z.x;
+                            }
+                        }
+                        for (int i = 0; i + 1 < nr && np < b; i += 2) {
+                            C.s[np] = re[i] + re[i + 1];
+                            C.t[np] = re[i] * re[i + 1];
+                            ++np;
+                        }
+                        for (int i = np; i < b; ++i) {  // unpaired leftovers: repeat the last pair
+                            C.s[i] = np ? C.s[np - 1] : 0.0;
+                            C.t[i] = np ? C.t[np - 1] : 0.0;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // the chain: bulge i sits at reflector position l + t - kSep i
+        const int T = kSep * (b - 1) + (u - l);
+        for (int t = 0; t < T; ++t) {
+            if (tid < b) {
+                const int k = l + t - kSep * tid;
+                int kk = -1;
+                double tau = 0.0, w1 = 0.0, w2 = 0.0;
+                if (k >= l && k <= u - 1) {
+                    double x, y, z;
+                    if (k == l) {
+                        const double h00 = at(H, ld, l, l), h01 = at(H, ld, l, l + 1);
+                        const double h10 = at(H, ld, l + 1, l), h11 = at(H, ld, l + 1, l + 1);
+                        const double h21 = at(H, ld, l + 2, l + 1);
+                        x = h00 * h00 + h01 * h10 - C.s[tid] * h00 + C.t[tid];
+                        y = h10 * (h00 + h11 - C.s[tid]);
+                        z = h10 * h21;
+                    } else {
+                        x = at(H, ld, k, k - 1);
+                        y = at(H, ld, k + 1, k - 1);
+                        z = k + 2 <= u ? at(H, ld, k + 2, k - 1) : 0.0;
+                    }
+                    double beta;
+                    house3(x, y, z, &tau, &w1, &w2, &beta);
+                    if (k > l && tau != 0.0) {
+                        at(H, ld, k, k - 1) = beta;
+                        at(H, ld, k + 1, k - 1) = 0.0;
+                        if (k + 2 <= u) at(H, ld, k + 2, k - 1) = 0.0;
+                    }
+                    if (tau != 0.0) kk = k;
+                }
+                C.k[tid] = kk;
+                C.tau[tid] = tau;
+                C.w1[tid] = w1;
+                C.w2[tid] = w2;
+            }
+            __syncthreads();
+            // from the left: rows k..k+2, columns k..u
+            for (int i = 0; i < b; ++i) {
+                const int k = C.k[i];
+                if (k < 0) continue;
+                const double tau = C.tau[i], w1 = C.w1[i], w2 = C.w2[i];
+                const bool three = k + 2 <= u;
+                for (int c = k + tid; c <= u; c += kQrThreads) {
+                    double& a0 = at(H, ld, k, c);
+                    double& a1 = at(H, ld, k + 1, c);
+                    if (three) {
+                        double& a2 = at(H, ld, k + 2, c);
+                        const double r = tau * (a0 + w1 * a1 + w2 * a2);
+                        a0 -= r;
+                        a1 -= r * w1;
+                        a2 -= r * w2;
+                    } else {
+                        const double r = tau * (a0 + w1 * a1);
+                        a0 -= r;
+                        a1 -= r * w1;
+                    }
+                }
+            }
+            __syncthreads();
+            // from the right: columns k..k+2, rows l..min(k+3, u)
+            for (int i = 0; i < b; ++i) {
+                const int k = C.k[i];
+                if (k < 0) continue;
+                const double tau = C.tau[i], w1 = C.w1[i], w2 = C.w2[i];
+                const bool three = k + 2 <= u;
+                const int rend = min(k + 3, u);
+                for (int r = l + tid; r <= rend; r += kQrThreads) {
+                    double* h = H + (int64_t)r * ld + k;
+                    if (three) {
+                        const double q = tau * (h[0] + w1 * h[1] + w2 * h[2]);
+                        h[0] -= q;
+                        h[1] -= q * w1;
+                        h[2] -= q * w2;
+                    } else {
+                        const double q = tau * (h[0] + w1 * h[1]);
+                        h[0] -= q;
+                        h[1] -= q * w1;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) C.steps += T;
+        __syncthreads();
+    }
+    __syncthreads();
+    return C.status;
+}
+
+struct QrOut {
+    int status;
+    int pad;
+    int64_t sweeps, steps;
+};
+
+__global__ __launch_bounds__(kQrThreads) void k_hqr(double* H, int64_t ld, int n, double2* lam, QrOut* out) {
+    __shared__ QrCtl outer, inner;
+    __shared__ double sub[kShiftDim * kShiftDim];
+    __shared__ double2 subev[kShiftDim];
+    const int rc = qr_eigs<kMaxBulges>(H, ld, n, lam, outer, &inner, sub, subev);
+    if (threadIdx.x == 0) {
+        out->status = rc;
+        out->sweeps = outer.sweeps;
+        out->steps = outer.steps;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Grid counts
+// ---------------------------------------------------------------------------
+
+__global__ void k_zero_i64(int64_t* x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0;
+}
+
+__global__ void k_hist(int64_t n, const double2* lam, double re0, double dx, double im0, double dy, int nx, int ny,
+                       unsigned long long* counts) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 z = lam[i];
+    const double tx = (z.x - re0) / dx;
+    const double ty = (z.y - im0) / dy;
+    if (tx >= 0.0 && tx < (double)nx && ty >= 0.0 && ty < (double)ny)
+        atomicAdd(&counts[(int64_t)(int)floor(ty) * nx + (int)floor(tx)], 1ull);
+}
+
+// Workspace of the reduction, from the start of the context's workspace: v, p, q
+// (M doubles each), tau and s, and the column pass's chunk partials.
+struct HessLayout {
+    size_t v, p, q, sc, qp, end;
+    explicit HessLayout(int M) {
+        const size_t vec = lb_align(sizeof(double) * (size_t)M, 256);
+        v = 0;
+        p = vec;
+        q = 2 * vec;
+        sc = 3 * vec;
+        qp = sc + 256;
+        end = lb_align(qp + sizeof(double) * (size_t)kMaxChunks * M, 256);
+    }
+};
+
+}  // namespace
+
+int lb_impl_hessenberg(lb_ctx* c, int M, double* A, int64_t lda) {
+    hipStream_t s = c->stream;
+    const HessLayout lay(M);
+    const size_t o_v = lay.v, o_p = lay.p, o_q = lay.q, o_sc = lay.sc, o_qp = lay.qp;
+    int rc = lb_ws_reserve(c, lay.end);
+    if (rc) return rc;
+    char* ws = (char*)c->ws;
+    double* v = (double*)(ws + o_v);
+    double* p = (double*)(ws + o_p);
+    double* q = (double*)(ws + o_q);
+    double* sc = (double*)(ws + o_sc);
+    double* qpart = (double*)(ws + o_qp);
+    for (int j = 0; j + 2 < M; ++j) {
+        const int L = M - j - 1;
+        hipLaunchKernelGGL(k_hh_house, dim3(1), dim3(256), 0, s, A, lda, M, j, v, sc);
+        LB_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_hh_p, dim3(lb_blocks(M, 4)), dim3(256), 0, s, (const double*)A, lda, M, j,
+                           (const double*)v, p);
+        LB_CHECK_LAUNCH();
+        const int cb = (int)lb_blocks(L, 256);
+        int nch = (int)lb_blocks(L, kChunkRows);
+        if (nch > kMaxChunks) nch = kMaxChunks;
+        const int rows_per_chunk = (L + nch - 1) / nch;
+        nch = (L + rows_per_chunk - 1) / rows_per_chunk;
+        hipLaunchKernelGGL(k_hh_q, dim3(cb, nch), dim3(256), 0, s, (const double*)A, lda, M, j, (const double*)v,
+                           qpart, rows_per_chunk);
+        LB_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_hh_qfin, dim3(cb + 1), dim3(256), 0, s, M, j, nch, (const double*)qpart,
+                           (const double*)v, (const double*)p, q, sc);
+        LB_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_hh_update, dim3(lb_blocks(L, 64), lb_blocks(M, 16)), dim3(256), 0, s, A, lda, M, j,
+                           (const double*)v, (const double*)p, (const double*)q, (const double*)sc);
+        LB_CHECK_LAUNCH();
+    }
+    return LB_OK;
+}
+
+int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam, int64_t* sweeps, int64_t* steps) {
+    hipStream_t s = c->stream;
+    // the working copy sits past the reduction's own scratch
+    const size_t o_h = HessLayout(M).end;
+    const size_t o_out = o_h + lb_align(sizeof(double) * (size_t)M * M, 256);
+    int rc = lb_ws_reserve(c, o_out + sizeof(QrOut));
+    if (rc) return rc;
+    double* H = (double*)((char*)c->ws + o_h);
+    QrOut* out = (QrOut*)((char*)c->ws + o_out);
+    LB_HIP(hipMemcpy2DAsync(H, sizeof(double) * M, Q, sizeof(double) * ldq, sizeof(double) * M, M,
+                            hipMemcpyDeviceToDevice, s));
+    rc = lb_impl_hessenberg(c, M, H, M);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_hqr, dim3(1), dim3(kQrThreads), 0, s, H, (int64_t)M, M, (double2*)lam, out);
+    LB_CHECK_LAUNCH();
+    rc = lb_host_reserve(c, sizeof(QrOut));
+    if (rc) return rc;
+    LB_HIP(hipMemcpyAsync(c->host, out, sizeof(QrOut), hipMemcpyDeviceToHost, s));
+    LB_HIP(hipStreamSynchronize(s));
+    const QrOut o = *(const QrOut*)c->host;
+    if (sweeps) *sweeps = o.sweeps;
+    if (steps) *steps = o.steps;
+    if (o.status) return lb_fail(LB_ERR_NO_CONVERGENCE, "QR iteration: %d sweeps without a split", kMaxIts);
+    return LB_OK;
+}
+
+int lb_impl_spectrum_histogram(lb_ctx* c, int64_t n, const double* lam, double re0, double re1, double im0,
+                               double im1, int nx, int ny, int64_t* counts) {
+    hipStream_t s = c->stream;
+    const int64_t cells = (int64_t)nx * ny;
+    hipLaunchKernelGGL(k_zero_i64, dim3(lb_blocks(cells, 256)), dim3(256), 0, s, counts, cells);
+    LB_CHECK_LAUNCH();
+    if (n == 0) return LB_OK;
+    const double dx = (re1 - re0) / nx, dy = (im1 - im0) / ny;
+    hipLaunchKernelGGL(k_hist, dim3(lb_blocks(n, 256)), dim3(256), 0, s, n, (const double2*)lam, re0, dx, im0, dy,
+                       nx, ny, (unsigned long long*)counts);
+    LB_CHECK_LAUNCH();
+    return LB_OK;
+}

@@ -6,7 +6,7 @@ which does not depend on the order either side lists its eigenvalues in.
 ``condition`` gives each eigenvalue's condition number 1 / |y^H x| (unit left
 and right eigenvectors y, x): by first-order perturbation theory a backward
 error E moves that eigenvalue by at most kappa ||E||, so two backward-stable
-computations on the same M x M matrix agree to about kappa M eps ||Q||_F."""
+computations on the same M x M matrix agree to about kappa max(M, 16) eps ||Q||_F."""
 import numpy as np
 import scipy.linalg as sl
 from scipy.optimize import linear_sum_assignment
@@ -31,6 +31,8 @@ def condition(Q):
 
 
 def bound(Q, kappa):
-    """Per-eigenvalue tolerance kappa_i * M * eps * ||Q||_F."""
+    """Per-eigenvalue tolerance kappa_i * max(M, 16) * eps * ||Q||_F: the backward
+    error of a Householder reduction and QR iteration grows like M eps ||Q|| with a
+    fixed constant of order ten that dominates for the smallest matrices."""
     M = np.asarray(Q).shape[0]
-    return kappa * M * np.finfo(float).eps * np.linalg.norm(Q)
+    return kappa * max(M, 16) * np.finfo(float).eps * np.linalg.norm(Q)

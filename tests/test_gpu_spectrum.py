@@ -1,0 +1,182 @@
+"""GPU spectrum of Q (Fig. 5) against the oracle's (LAPACK) spectrum, eigenvalue by
+eigenvalue after a minimum-cost pairing of the two unordered sets: each pair must
+agree within kappa_i * max(M, 16) * eps * ||Q||_F, kappa_i the condition number of that
+eigenvalue (two backward-stable computations on the same matrix; tests/spectra.py).
+Inputs are the oracle's Q of seeded random Lindbladians (GUE H, Wishart gamma, the
+random model of Sec. 3) and small matrices that exercise the edge paths (1 x 1,
+2 x 2, triangular, zero diagonals, a cyclic shift whose eigenvalues all share one
+modulus, clusters of repeated eigenvalues, padded rows). Grid counts are compared
+bit for bit on identical inputs."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import spectra  # noqa: E402
+from paper_1912_01491_amd import workloads as wl  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import paper_1912_01491_amd as lb
+    lb.load()
+    return lb
+
+
+@pytest.fixture(scope="module")
+def ctx(lb):
+    c = lb.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_spectrum(lb, ctx, Q, pad=0):
+    M = Q.shape[0]
+    buf = torch.zeros((M, M + pad), dtype=torch.float64, device="cuda")
+    buf[:, :M] = torch.from_numpy(np.ascontiguousarray(Q)).cuda()
+    lam, info = lb.lindblad_spectrum(ctx, buf[:, :M])
+    return lam.cpu().numpy(), info
+
+
+def check_against_oracle(Q, lam):
+    w, kappa = spectra.condition(Q)
+    i, j, d = spectra.pair_up(lam, w)
+    tol = spectra.bound(Q, kappa[j])
+    worst = float((d / tol).max())
+    assert np.all(d <= tol), "worst |d| / bound = %.3g" % worst
+    return worst
+
+
+def check_pairs_adjacent(lam):
+    """Conjugate pairs come adjacent, positive imaginary part first."""
+    k = 0
+    while k < len(lam):
+        if lam[k].imag != 0.0:
+            assert lam[k].imag > 0 and lam[k + 1] == np.conj(lam[k])
+            k += 2
+        else:
+            k += 1
+
+
+@pytest.mark.parametrize("N", [2, 3, 5, 8, 12, 16, 24])
+def test_spectrum_random_lindbladian(lb, ctx, oracle, N):
+    print("[gpu] spectrum random Lindbladian N=%d" % N, flush=True)
+    H, gamma = wl.random_lindbladian(N, 50 + N)
+    Q, _ = oracle.prepare_dense(H, gamma)
+    lam, info = gpu_spectrum(lb, ctx, Q)
+    check_against_oracle(Q, lam)
+    check_pairs_adjacent(lam)
+    assert abs(lam.sum() - np.trace(Q)) < 1e-12 * np.abs(Q).sum()
+    assert info["sweeps"] >= 1
+
+
+def test_spectrum_n32_with_padded_rows(lb, ctx, oracle):
+    """M = 1023: several hundred sweeps with chains of 16 bulges; rows padded to 1031."""
+    print("[gpu] spectrum N=32 padded", flush=True)
+    H, gamma = wl.random_lindbladian(32, 7)
+    Q, _ = oracle.prepare_dense(H, gamma)
+    lam, info = gpu_spectrum(lb, ctx, Q, pad=8)
+    check_against_oracle(Q, lam)
+    check_pairs_adjacent(lam)
+    assert lam.real.max() < 0
+
+
+@pytest.mark.parametrize("N,c", [(4, 0.3), (9, 0.05)])
+def test_spectrum_depolarising_closed_form(lb, ctx, oracle, N, c):
+    """gamma = c 1: the spectrum is {-cN - i(E_a - E_b) : a != b} and -cN (N - 1 times)."""
+    M = N * N - 1
+    H = wl.gue_hamiltonian(N, 80 + N)
+    E = np.linalg.eigvalsh(H)
+    Q, _ = oracle.prepare_dense(H, c * np.eye(M, dtype=complex))
+    lam, _ = gpu_spectrum(lb, ctx, Q)
+    want = [complex(-c * N, -(E[a] - E[b])) for a in range(N) for b in range(N) if a != b]
+    want += [complex(-c * N, 0.0)] * (N - 1)
+    _, _, d = spectra.pair_up(lam, want)
+    assert d.max() < 1e-11 * np.linalg.norm(Q)
+
+
+def edge_matrices():
+    g = wl.rng(91)
+    U, _ = np.linalg.qr(g.standard_normal((50, 50)))
+    out = {
+        "1x1": np.array([[3.5]]),
+        "2x2_complex": np.array([[0.0, -2.0], [1.0, 0.5]]),
+        "2x2_real": np.array([[1.0, 2.0], [3.0, 4.0]]),
+        "3x3": g.standard_normal((3, 3)),
+        "triangular_40": np.triu(g.standard_normal((40, 40))),
+        "zero_6": np.zeros((6, 6)),
+        "cyclic_5": np.roll(np.eye(5), 1, axis=1),
+        "cyclic_200": np.roll(np.eye(200), 1, axis=1),
+        "clusters_50": U @ np.diag(np.repeat([1.0, -2.0, 3.0, 0.5, 7.0], 10)) @ U.T,
+        "gauss_300": g.standard_normal((300, 300)),
+        "gauss_65": g.standard_normal((65, 65)),
+    }
+    return out
+
+
+@pytest.mark.parametrize("name", sorted(edge_matrices()))
+def test_spectrum_edge_matrices(lb, ctx, oracle, name):
+    print("[gpu] spectrum edge %s" % name, flush=True)
+    A = edge_matrices()[name]
+    lam, _ = gpu_spectrum(lb, ctx, A)
+    check_pairs_adjacent(lam)
+    if name.startswith("clusters") or name.startswith("zero") or name.startswith("cyclic"):
+        # defective or clustered: compare with the known values at a normwise level
+        if name.startswith("clusters"):
+            want = np.repeat([1.0, -2.0, 3.0, 0.5, 7.0], 10)
+        elif name.startswith("zero"):
+            want = np.zeros(6)
+        else:
+            n = A.shape[0]
+            want = np.exp(2j * np.pi * np.arange(n) / n)
+        _, _, d = spectra.pair_up(lam, want)
+        assert d.max() < 1e-12 * max(1.0, np.linalg.norm(A)) * A.shape[0]
+    else:
+        check_against_oracle(A, lam)
+
+
+@pytest.mark.parametrize("M", [3, 63, 200, 257])
+def test_hessenberg_is_an_orthogonal_similarity(lb, ctx, oracle, M):
+    """Exact zeros below the subdiagonal, the Frobenius norm kept, the spectrum kept."""
+    A = wl.rng(M).standard_normal((M, M))
+    T = torch.from_numpy(A.copy()).cuda()
+    lb.lb_hessenberg(ctx, T)
+    Hh = T.cpu().numpy()
+    assert np.count_nonzero(np.tril(Hh, -2)) == 0
+    assert abs(np.linalg.norm(Hh) - np.linalg.norm(A)) < 1e-13 * np.linalg.norm(A)
+    w, kappa = spectra.condition(A)
+    i, j, d = spectra.pair_up(oracle.spectrum(Hh), w)
+    assert np.all(d <= spectra.bound(A, kappa[j]))
+
+
+def test_histogram_bit_exact(lb, ctx, oracle):
+    """Same values on both sides, so the same cells: points at cell centres, on the
+    edges, outside the box, NaN, and random points."""
+    g = wl.rng(5)
+    re0, re1, im0, im1, nx, ny = -3.0, 0.5, -2.0, 2.0, 100, 100
+    z = g.standard_normal(20000) * 1.2 - 1.0 + 1j * g.standard_normal(20000)
+    dx, dy = (re1 - re0) / nx, (im1 - im0) / ny
+    extra = [complex(re0, im0), complex(re1, 0.0), complex(0.0, im1), complex(np.nan, 0.0),
+             complex(re0 + 37.5 * dx, im0 + 12.5 * dy), complex(re0 + 99 * dx, im0 + 99 * dy)]
+    z = np.concatenate([z, extra])
+    want = oracle.histogram(z, re0, re1, im0, im1, nx, ny)
+    got = lb.lindblad_spectrum_histogram(ctx, torch.from_numpy(z).cuda(), re0, re1, im0, im1, nx, ny)
+    assert np.array_equal(got.cpu().numpy(), want)
+    empty = lb.lindblad_spectrum_histogram(ctx, torch.zeros(0, dtype=torch.complex128, device="cuda"),
+                                           re0, re1, im0, im1, 3, 2)
+    assert np.array_equal(empty.cpu().numpy(), np.zeros((2, 3), np.int64))
+
+
+def test_spectrum_rejects_bad_arguments(lb, ctx):
+    Q = torch.zeros((4, 4), dtype=torch.float64, device="cuda")
+    rc = lb.load().lindblad_spectrum(ctx.handle, 16384, lb._ptr(Q), 16384, lb._ptr(Q), None)
+    assert rc == -1
+    rc = lb.load().lindblad_spectrum(ctx.handle, 4, lb._ptr(Q), 3, lb._ptr(Q), None)
+    assert rc == -1
+    lam = torch.zeros(4, dtype=torch.complex128, device="cuda")
+    with pytest.raises(lb.LindbladError):
+        lb.lindblad_spectrum_histogram(ctx, lam, 1.0, 1.0, 0.0, 1.0, 4, 4)
+    with pytest.raises(lb.LindbladError):
+        lb.lindblad_spectrum_histogram(ctx, lam, 0.0, 1.0, 0.0, float("inf"), 4, 4)
