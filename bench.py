@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Q,K assembly s + RK4 steps/s at N=200 dense; batched solves/s, p99 vs plain"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
 
 
 def log(msg):
@@ -90,10 +91,12 @@ def parse():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle RK4 steps in the CPU sample")
-    ap.add_argument("--config", choices=["c1", "c2", "c2p", "c3", "c4", "c5", "c5r", "c6", "c6s", "c7"], default="c4",
+    ap.add_argument("--config", choices=["c1", "c2", "c2p", "c3", "c4", "c5", "c5r", "c6", "c6s", "c7", "c8"],
+                    default="c4",
                     help="c4: the N=200 dense headline (default); c1: N=8 dense; c2: N=1000 sparse dimer; "
                          "c3: N=100 dense, 64 states, FP64 vs FP32; c5: serving mix (prepare per request); "
-                         "c5r: serving mix on resident systems; c2p: the periodically rocked dimer (one period)")
+                         "c5r: serving mix on resident systems; c2p: the periodically rocked dimer (one period); "
+                         "c6 / c6s: steady states; c7: saved systems; c8: spectrum of Q (Fig. 5)")
     ap.add_argument("--drive-N", type=int, default=1000, help="c2p: Hilbert-space dimension")
     ap.add_argument("--drive-steps", type=int, default=20000, help="c2p: RK4 steps per drive period")
     ap.add_argument("--serving", action="store_true", help="same as --config c5")
@@ -103,6 +106,7 @@ def parse():
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--arrival", choices=["burst", "poisson"], default="burst")
     ap.add_argument("--ss-N", type=int, default=1000, help="c6s: dimer size")
+    ap.add_argument("--spec-N", type=int, default=64, help="c8: Hilbert-space dimension of the spectrum")
     ap.add_argument("--persist-dir", default=None, help="c7: directory for the saved files (default: temp dir)")
     ap.add_argument("--ss-maxit", type=int, default=6000, help="c6s: GMRES iteration limit")
     ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrival rate (requests/s)")
@@ -558,6 +562,89 @@ def config_c6(args):
     print(json.dumps(out), flush=True)
 
 
+def _nearest(a, b, chunk=512):
+    """Largest distance from a value of a to its nearest value in b."""
+    import numpy as np
+    worst = 0.0
+    for i in range(0, len(a), chunk):
+        worst = max(worst, float(np.abs(a[i:i + chunk, None] - b[None, :]).min(axis=1).max()))
+    return worst
+
+
+def config_c8(args):
+    """Spectrum of one random Lindbladian (Fig. 5, at the sizes the one-workgroup QR
+    stage reaches): GUE H seed 0, Wishart gamma seed 1, Q prepared on the device,
+    all M eigenvalues of Q on the device (Householder reduction to Hessenberg form,
+    then the multishift QR iteration in one workgroup), and their counts on a
+    100 x 100 grid over the spectrum's bounding box, divided by the cell area as in
+    Fig. 5."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1912_01491_amd as lb
+    from paper_1912_01491_amd import workloads as wl
+
+    N = args.spec_N
+    M = N * N - 1
+    ctx = lb.Context(0)
+    H = torch.from_numpy(wl.gue_hamiltonian(N, 0)).cuda()
+    gamma = wl.wishart_kossakowski_device(N, 1)
+    Q, K = lb.lindblad_prepare(ctx, H, gamma)
+    del gamma
+    torch.cuda.empty_cache()
+    Qv = Q[:, :M]
+    A = Qv.contiguous()
+    t_hess, _ = _timed(lambda: lb.lb_hessenberg(ctx, A))
+    del A
+    log("C8: N=%d M=%d Hessenberg reduction %.3f s" % (N, M, t_hess))
+    t, (lam, info) = _timed(lambda: lb.lindblad_spectrum(ctx, Qv))
+    t_qr = t - t_hess
+    log("C8: spectrum in %.3f s (QR stage ~%.3f s): %d sweeps, %d chain steps, %d updates"
+        % (t, t_qr, info["sweeps"], info["chain_steps"], info["updates"]))
+    z = lam.cpu().numpy()
+    pad = 0.01
+    re0, re1 = z.real.min(), z.real.max()
+    im0, im1 = z.imag.min(), z.imag.max()
+    re0, re1 = re0 - pad * (re1 - re0), re1 + pad * (re1 - re0)
+    im0, im1 = im0 - pad * (im1 - im0), im1 + pad * (im1 - im0)
+    nx = ny = 100
+    t_hist, counts = _timed(lambda: lb.lindblad_spectrum_histogram(ctx, lam, re0, re1, im0, im1, nx, ny))
+    density = counts.cpu().numpy() / (((re1 - re0) / nx) * ((im1 - im0) / ny))
+    qr_tflops = 10.0 * info["updates"] / t_qr / 1e12
+    hess_flops = 10.0 / 3.0 * float(M) ** 3
+    # the oracle (LAPACK through numpy) on the same matrix, on the host cores
+    Qh = Qv.cpu().numpy()
+    oracle.spectrum(Qh[:16, :16])
+    t0 = time.perf_counter()
+    w = oracle.spectrum(Qh)
+    tc = time.perf_counter() - t0
+    near = max(_nearest(z, w), _nearest(w, z))
+    fro = float(np.linalg.norm(Qh))
+    log("C8: oracle %.2f s; largest nearest-value distance %.2e (||Q||_F %.1f)" % (tc, near, fro))
+    out = {"metric": "spectrum of Q: N=%d random Lindbladian, all M eigenvalues (FP64) and their 100 x 100 grid" % N,
+           "value": 1.0 / t, "unit": "spectra/s (M=%d)" % M, "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "random Lindbladian N=%d (M=%d): GUE H seed 0, Wishart gamma seed 1 (Tr = N); "
+                                  "eigenvalues of Q, counts on a 100 x 100 grid over their bounding box" % (N, M)},
+           "spectrum_s": t, "hessenberg_s": t_hess, "qr_s": t_qr, "histogram_s": t_hist,
+           "sweeps": info["sweeps"], "chain_steps": info["chain_steps"], "updates": info["updates"],
+           "roofline": {"bound": "alu", "achieved": qr_tflops, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                        "frac": qr_tflops / FP64_PEAK_TFS, "traffic": None, "kernel": "k_hqr",
+                        "flops": 10.0 * info["updates"],
+                        "note": "one workgroup on one of the 256 compute units: the bulge chain's three phases per "
+                                "step are block barriers"},
+           "hessenberg": {"flops": hess_flops, "tflops": hess_flops / t_hess / 1e12},
+           "cpu_baseline": {"value": 1.0 / tc, "unit": "spectra/s (M=%d)" % M, "cores": _blas_threads(),
+                            "kind": "oracle", "sample": "the whole spectrum of the same Q (LAPACK dgeev through "
+                                                        "numpy, eigenvalues only); %.2f s" % tc},
+           "checks": {"nearest_dist_max": near, "nearest_dist_over_eps_M_normF": near / (np.finfo(float).eps * M * fro),
+                      "trace_err": float(abs(z.sum() - np.trace(Qh))), "max_real": float(z.real.max()),
+                      "counted": int(counts.sum().item()), "density_max": float(density.max())}}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def config_c6s(args):
     """Steady state of the static dimer (the sparse model of the configurations,
     N=1000, M=999999) with the secular preconditioner: Q in CSR prepared on the
@@ -773,9 +860,9 @@ def main():
         return pmc_probe(args)
     if args.serving or args.config in ("c5", "c5r"):
         return serving(args)
-    if args.config in ("c1", "c2", "c2p", "c3", "c6", "c6s", "c7"):
+    if args.config in ("c1", "c2", "c2p", "c3", "c6", "c6s", "c7", "c8"):
         return {"c1": config_c1, "c2": config_c2, "c2p": config_c2p, "c3": config_c3, "c6": config_c6,
-                "c6s": config_c6s, "c7": config_c7}[args.config](args)
+                "c6s": config_c6s, "c7": config_c7, "c8": config_c8}[args.config](args)
     import numpy as np
     import torch
 

@@ -361,6 +361,9 @@ int lb_hessenberg(lb_ctx* ctx, int64_t M, double* A, int64_t lda);
 typedef struct lb_spectrum_info {
     int64_t sweeps;      /* QR sweeps over all blocks */
     int64_t chain_steps; /* chain steps over all sweeps (each three barrier phases) */
+    int64_t updates;     /* 2- or 3-entry row and column pieces the reflectors updated
+                            (10 flops each): b (na^2 + 3 na - 7) per b-bulge sweep
+                            over an na-row block */
 } lb_spectrum_info;
 
 /* Eigenvalues of the real generator Q of the ODE dv/dt = Qv + K (Eq. (10);

@@ -218,7 +218,8 @@ int lb_impl_load_system(lb_ctx* c, const char* path, lb_system* sys);
 int lb_impl_read_bandwidth(lb_ctx* c, size_t bytes, double* gbs);
 int lb_impl_eigh(lb_ctx* c, int N, double* A, int lda, double* w, double* Z, int ldz, int* sweeps);
 int lb_impl_hessenberg(lb_ctx* c, int M, double* A, int64_t lda);
-int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam, int64_t* sweeps, int64_t* steps);
+int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam, int64_t* sweeps, int64_t* steps,
+                     int64_t* work);
 int lb_impl_spectrum_histogram(lb_ctx* c, int64_t n, const double* lam, double re0, double re1, double im0,
                                double im1, int nx, int ny, int64_t* counts);
 int lb_impl_steady_dense(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, const double* K, const lb_secular* pre,

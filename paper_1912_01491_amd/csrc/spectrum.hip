@@ -33,6 +33,7 @@ constexpr int kMaxBulges = 16;              // 32 shifts per sweep
 constexpr int kSep = 4;                     // rows between neighbouring bulges
 constexpr int kShiftDim = 2 * kMaxBulges;   // trailing block solved for the shifts
 constexpr int kMaxIts = 120;                // sweeps without a split before giving up
+constexpr int kBatch = 1;                   // row / column pieces per thread with loads in flight together
 constexpr int kChunkRows = 256;             // row chunk of the column pass
 constexpr int kMaxChunks = 64;
 
@@ -155,10 +156,10 @@ __global__ __launch_bounds__(256) void k_hh_update(double* A, int64_t ld, int M,
 struct QrCtl {
     int u, split, its, status, b, nested;
     int64_t sweeps, steps;
+    int64_t work;                                  // row / column pieces updated (each 3 entries, 10 flops)
     double anorm;                                  // ||H||_F at the start
     double s[kMaxBulges], t[kMaxBulges];           // shift pairs: sigma1 + sigma2, sigma1 sigma2
-    int k[kMaxBulges];                             // reflector position of each bulge this step (-1: idle)
-    double tau[kMaxBulges], w1[kMaxBulges], w2[kMaxBulges];
+    double tau[2][kMaxBulges], w1[2][kMaxBulges], w2[2][kMaxBulges];  // reflectors, by step parity
 };
 
 __device__ __forceinline__ double& at(double* H, int64_t ld, int r, int c) { return H[(int64_t)r * ld + c]; }
@@ -201,6 +202,17 @@ __device__ void house3(double x, double y, double z, double* tau, double* w1, do
     *beta = bs * sc;
 }
 
+// First column of (H - sigma1)(H - sigma2) at the top of the block [l, ...]: the
+// input of a bulge's first reflector, with s = sigma1 + sigma2 and t = sigma1 sigma2.
+__device__ void intro_xyz(const double* H, int64_t ld, int l, double s, double t, double* x, double* y, double* z) {
+    const double h00 = H[(int64_t)l * ld + l], h01 = H[(int64_t)l * ld + l + 1];
+    const double h10 = H[(int64_t)(l + 1) * ld + l], h11 = H[(int64_t)(l + 1) * ld + l + 1];
+    const double h21 = H[(int64_t)(l + 2) * ld + l + 1];
+    *x = h00 * h00 + h01 * h10 - s * h00 + t;
+    *y = h10 * (h00 + h11 - s);
+    *z = h10 * h21;
+}
+
 // All threads of the block call this with the same arguments. H: n x n upper Hessenberg
 // (entries below the subdiagonal are never read), row-major with leading dimension ld,
 // in global memory or LDS; destroyed. lam receives the n eigenvalues. Returns 0, or 1
@@ -233,6 +245,7 @@ __device__ int qr_eigs(double* H, int64_t ld, int n, double2* lam, QrCtl& C, QrC
         C.status = 0;
         C.sweeps = 0;
         C.steps = 0;
+        C.work = 0;
         C.split = 0;
     }
     __syncthreads();
@@ -356,89 +369,150 @@ __device__ int qr_eigs(double* H, int64_t ld, int n, double2* lam, QrCtl& C, QrC
                 __syncthreads();
             }
         }
-        // the chain: bulge i sits at reflector position l + t - kSep i
+        // The chain: bulge i sits at reflector position l + t - kSep i in step t. A step
+        // is two phases: every reflector from the left (rows k..k+2, columns k..u),
+        // then every reflector from the right (columns k..k+2, rows l..min(k+3, u)).
+        // Rows k+1..k+3 of bulge i's right update belong to its owner thread i, which
+        // then holds column k of those rows, exactly the input of the bulge's next
+        // reflector (or builds the next bulge's first reflector from the leading 3 x 3
+        // block), so reflectors are ready after the second phase without a third.
+        // Reflectors of consecutive steps alternate between two buffers.
         const int T = kSep * (b - 1) + (u - l);
+        const int ld32 = (int)ld;  // n * ld < 2^31 (n <= 16383)
+        if (tid == 0) {
+            double x, y, z, beta;
+            intro_xyz(H, ld, l, C.s[0], C.t[0], &x, &y, &z);
+            house3(x, y, z, &C.tau[0][0], &C.w1[0][0], &C.w2[0][0], &beta);
+        }
+        __syncthreads();
         for (int t = 0; t < T; ++t) {
+            const int p = t & 1;
+            const int ihi = min(b - 1, t / kSep);
+            int ilo = 0;
+            while (ilo <= ihi && l + t - kSep * ilo > u - 1) ++ilo;
+            // from the left: pieces (bulge, column), bulge by bulge, columns consecutive
+            int total = 0;
+            for (int i = ilo; i <= ihi; ++i) total += u - (l + t - kSep * i) + 1;
+            for (int base = 0; base < total; base += kQrThreads * kBatch) {
+                double a0[kBatch], a1[kBatch], a2[kBatch];
+                int off[kBatch], bi[kBatch];
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) {
+                    bi[q] = -1;
+                    int e = base + q * kQrThreads + tid;
+                    if (e >= total) continue;
+                    int i = ilo;
+                    while (e >= u - (l + t - kSep * i) + 1) {
+                        e -= u - (l + t - kSep * i) + 1;
+                        ++i;
+                    }
+                    if (C.tau[p][i] == 0.0) continue;
+                    const int k = l + t - kSep * i;
+                    bi[q] = i;
+                    off[q] = k * ld32 + k + e;
+                    a0[q] = H[off[q]];
+                    a1[q] = H[off[q] + ld32];
+                    a2[q] = k + 2 <= u ? H[off[q] + 2 * ld32] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) {
+                    if (bi[q] < 0) continue;
+                    const int i = bi[q];
+                    const double tau = C.tau[p][i], w1 = C.w1[p][i], w2 = C.w2[p][i];
+                    const double r = tau * (a0[q] + w1 * a1[q] + w2 * a2[q]);
+                    H[off[q]] = a0[q] - r;
+                    H[off[q] + ld32] = a1[q] - r * w1;
+                    if (l + t - kSep * i + 2 <= u) H[off[q] + 2 * ld32] = a2[q] - r * w2;
+                }
+            }
+            __syncthreads();
+            // from the right: the owners' rows k+1..k+3 and the next reflectors first
             if (tid < b) {
-                const int k = l + t - kSep * tid;
-                int kk = -1;
-                double tau = 0.0, w1 = 0.0, w2 = 0.0;
-                if (k >= l && k <= u - 1) {
-                    double x, y, z;
-                    if (k == l) {
-                        const double h00 = at(H, ld, l, l), h01 = at(H, ld, l, l + 1);
-                        const double h10 = at(H, ld, l + 1, l), h11 = at(H, ld, l + 1, l + 1);
-                        const double h21 = at(H, ld, l + 2, l + 1);
-                        x = h00 * h00 + h01 * h10 - C.s[tid] * h00 + C.t[tid];
-                        y = h10 * (h00 + h11 - C.s[tid]);
-                        z = h10 * h21;
-                    } else {
-                        x = at(H, ld, k, k - 1);
-                        y = at(H, ld, k + 1, k - 1);
-                        z = k + 2 <= u ? at(H, ld, k + 2, k - 1) : 0.0;
+                const int i = tid;
+                const int k = l + t - kSep * i;
+                double tn = 0.0, w1n = 0.0, w2n = 0.0;
+                if (i >= ilo && i <= ihi) {
+                    const double tau = C.tau[p][i], w1 = C.w1[p][i], w2 = C.w2[p][i];
+                    const bool three = k + 2 <= u;
+                    double col[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int rr = 0; rr < 3; ++rr) {
+                        const int row = k + 1 + rr;
+                        if (row <= u) {
+                            double* h = H + row * ld32 + k;
+                            double h0 = h[0], h1 = h[1], h2 = three ? h[2] : 0.0;
+                            if (tau != 0.0) {
+                                const double q = tau * (h0 + w1 * h1 + w2 * h2);
+                                h0 -= q;
+                                h1 -= q * w1;
+                                h2 -= q * w2;
+                                h[1] = h1;
+                                if (three) h[2] = h2;
+                            }
+                            col[rr] = h0;
+                        }
                     }
-                    double beta;
-                    house3(x, y, z, &tau, &w1, &w2, &beta);
-                    if (k > l && tau != 0.0) {
-                        at(H, ld, k, k - 1) = beta;
-                        at(H, ld, k + 1, k - 1) = 0.0;
-                        if (k + 2 <= u) at(H, ld, k + 2, k - 1) = 0.0;
+                    const int kn = k + 1;
+                    double beta = 0.0;
+                    if (kn <= u - 1) house3(col[0], col[1], kn + 2 <= u ? col[2] : 0.0, &tn, &w1n, &w2n, &beta);
+#pragma unroll
+                    for (int rr = 0; rr < 3; ++rr) {
+                        const int row = k + 1 + rr;
+                        if (row <= u) H[row * ld32 + k] = tn != 0.0 ? (rr == 0 ? beta : 0.0) : col[rr];
                     }
-                    if (tau != 0.0) kk = k;
+                } else if (i >= 1 && t + 1 == kSep * i) {
+                    double x, y, z, beta;
+                    intro_xyz(H, ld, l, C.s[i], C.t[i], &x, &y, &z);
+                    house3(x, y, z, &tn, &w1n, &w2n, &beta);
                 }
-                C.k[tid] = kk;
-                C.tau[tid] = tau;
-                C.w1[tid] = w1;
-                C.w2[tid] = w2;
+                C.tau[p ^ 1][i] = tn;
+                C.w1[p ^ 1][i] = w1n;
+                C.w2[p ^ 1][i] = w2n;
             }
-            __syncthreads();
-            // from the left: rows k..k+2, columns k..u
-            for (int i = 0; i < b; ++i) {
-                const int k = C.k[i];
-                if (k < 0) continue;
-                const double tau = C.tau[i], w1 = C.w1[i], w2 = C.w2[i];
-                const bool three = k + 2 <= u;
-                for (int c = k + tid; c <= u; c += kQrThreads) {
-                    double& a0 = at(H, ld, k, c);
-                    double& a1 = at(H, ld, k + 1, c);
-                    if (three) {
-                        double& a2 = at(H, ld, k + 2, c);
-                        const double r = tau * (a0 + w1 * a1 + w2 * a2);
-                        a0 -= r;
-                        a1 -= r * w1;
-                        a2 -= r * w2;
-                    } else {
-                        const double r = tau * (a0 + w1 * a1);
-                        a0 -= r;
-                        a1 -= r * w1;
+            // the rest: pieces (bulge, row) for rows l..k
+            total = 0;
+            for (int i = ilo; i <= ihi; ++i) total += (l + t - kSep * i) - l + 1;
+            for (int base = 0; base < total; base += kQrThreads * kBatch) {
+                double a0[kBatch], a1[kBatch], a2[kBatch];
+                int off[kBatch], bi[kBatch];
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) {
+                    bi[q] = -1;
+                    int e = base + q * kQrThreads + tid;
+                    if (e >= total) continue;
+                    int i = ilo;
+                    while (e >= (l + t - kSep * i) - l + 1) {
+                        e -= (l + t - kSep * i) - l + 1;
+                        ++i;
                     }
+                    if (C.tau[p][i] == 0.0) continue;
+                    const int k = l + t - kSep * i;
+                    bi[q] = i;
+                    off[q] = (l + e) * ld32 + k;
+                    a0[q] = H[off[q]];
+                    a1[q] = H[off[q] + 1];
+                    a2[q] = k + 2 <= u ? H[off[q] + 2] : 0.0;
                 }
-            }
-            __syncthreads();
-            // from the right: columns k..k+2, rows l..min(k+3, u)
-            for (int i = 0; i < b; ++i) {
-                const int k = C.k[i];
-                if (k < 0) continue;
-                const double tau = C.tau[i], w1 = C.w1[i], w2 = C.w2[i];
-                const bool three = k + 2 <= u;
-                const int rend = min(k + 3, u);
-                for (int r = l + tid; r <= rend; r += kQrThreads) {
-                    double* h = H + (int64_t)r * ld + k;
-                    if (three) {
-                        const double q = tau * (h[0] + w1 * h[1] + w2 * h[2]);
-                        h[0] -= q;
-                        h[1] -= q * w1;
-                        h[2] -= q * w2;
-                    } else {
-                        const double q = tau * (h[0] + w1 * h[1]);
-                        h[0] -= q;
-                        h[1] -= q * w1;
-                    }
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) {
+                    if (bi[q] < 0) continue;
+                    const int i = bi[q];
+                    const double tau = C.tau[p][i], w1 = C.w1[p][i], w2 = C.w2[p][i];
+                    const double r = tau * (a0[q] + w1 * a1[q] + w2 * a2[q]);
+                    H[off[q]] = a0[q] - r;
+                    H[off[q] + 1] = a1[q] - r * w1;
+                    if (l + t - kSep * i + 2 <= u) H[off[q] + 2] = a2[q] - r * w2;
                 }
             }
             __syncthreads();
         }
-        if (tid == 0) C.steps += T;
+        // a bulge crossing na rows updates sum_k (u - k + 1) pieces from the left and
+        // sum_k (min(k + 3, u) - l + 1) from the right: na^2 + 3 na - 7 in all
+        if (tid == 0) {
+            const int64_t na = u - l + 1;
+            C.steps += T;
+            C.work += (int64_t)b * (na * na + 3 * na - 7);
+        }
         __syncthreads();
     }
     __syncthreads();
@@ -448,7 +522,7 @@ __device__ int qr_eigs(double* H, int64_t ld, int n, double2* lam, QrCtl& C, QrC
 struct QrOut {
     int status;
     int pad;
-    int64_t sweeps, steps;
+    int64_t sweeps, steps, work;
 };
 
 __global__ __launch_bounds__(kQrThreads) void k_hqr(double* H, int64_t ld, int n, double2* lam, QrOut* out) {
@@ -460,6 +534,7 @@ __global__ __launch_bounds__(kQrThreads) void k_hqr(double* H, int64_t ld, int n
         out->status = rc;
         out->sweeps = outer.sweeps;
         out->steps = outer.steps;
+        out->work = outer.work;
     }
 }
 
@@ -537,7 +612,8 @@ int lb_impl_hessenberg(lb_ctx* c, int M, double* A, int64_t lda) {
     return LB_OK;
 }
 
-int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam, int64_t* sweeps, int64_t* steps) {
+int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam, int64_t* sweeps, int64_t* steps,
+                     int64_t* work) {
     hipStream_t s = c->stream;
     // the working copy sits past the reduction's own scratch
     const size_t o_h = HessLayout(M).end;
@@ -559,6 +635,7 @@ int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam
     const QrOut o = *(const QrOut*)c->host;
     if (sweeps) *sweeps = o.sweeps;
     if (steps) *steps = o.steps;
+    if (work) *work = o.work;
     if (o.status) return lb_fail(LB_ERR_NO_CONVERGENCE, "QR iteration: %d sweeps without a split", kMaxIts);
     return LB_OK;
 }

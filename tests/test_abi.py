@@ -132,10 +132,11 @@ def test_spectrum_info_layout_matches_header(tmp_path):
         pytest.skip("no host C compiler")
     src = tmp_path / "spec.c"
     src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "lindblad.h"\n'
-                   'int main(void) { printf("%zu %zu %d\\n", sizeof(lb_spectrum_info), '
-                   'offsetof(lb_spectrum_info, chain_steps), LB_SPECTRUM_MAX_M); return 0; }\n')
+                   'int main(void) { printf("%zu %zu %zu %d\\n", sizeof(lb_spectrum_info), '
+                   'offsetof(lb_spectrum_info, chain_steps), offsetof(lb_spectrum_info, updates), '
+                   'LB_SPECTRUM_MAX_M); return 0; }\n')
     exe = tmp_path / "spec"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     S = lb.SpectrumInfo
-    assert got == [ctypes.sizeof(S), S.chain_steps.offset, 16383]
+    assert got == [ctypes.sizeof(S), S.chain_steps.offset, S.updates.offset, 16383]
