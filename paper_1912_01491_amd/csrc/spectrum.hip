@@ -24,6 +24,7 @@
 #include "lb_internal.h"
 
 #include <float.h>
+#include <algorithm>
 #include <math.h>
 
 namespace {
@@ -519,23 +520,283 @@ __device__ int qr_eigs(double* H, int64_t ld, int n, double2* lam, QrCtl& C, QrC
     return C.status;
 }
 
-struct QrOut {
-    int status;
-    int pad;
-    int64_t sweeps, steps, work;
+// ---------------------------------------------------------------------------
+// Stage 2 on the whole device: sweeps over large blocks, one launch per phase
+// ---------------------------------------------------------------------------
+
+// Blocks of at most kSmallBlock rows are finished by one workgroup (qr_eigs);
+// sweeps over larger blocks run each phase of each chain step as a launch over the
+// whole device, the kernel boundaries ordering the phases.
+constexpr int kSmallBlock = 256;
+constexpr int kWideBulges = 32;                 // bulges per device-wide sweep (64 shifts)
+constexpr int kWideShiftDim = 2 * kWideBulges;  // trailing block solved for their shifts
+
+// Device-side state of the host-driven iteration. The host reads the first eight
+// ints back after each decision.
+struct QrGlobal {
+    int u, split, its, status, action, l, b, pad;  // action: 0 = split or block done, 1 = sweep
+    int64_t sweeps, steps, work;                   // counts of the one-workgroup solves
+    double anorm;                                  // ||H||_F
+    double s[kWideBulges], t[kWideBulges];         // shift pairs of the current sweep
+    double tau[2][kWideBulges], w1[2][kWideBulges], w2[2][kWideBulges];  // reflectors by step parity
 };
 
-__global__ __launch_bounds__(kQrThreads) void k_hqr(double* H, int64_t ld, int n, double2* lam, QrOut* out) {
-    __shared__ QrCtl outer, inner;
-    __shared__ double sub[kShiftDim * kShiftDim];
-    __shared__ double2 subev[kShiftDim];
-    const int rc = qr_eigs<kMaxBulges>(H, ld, n, lam, outer, &inner, sub, subev);
-    if (threadIdx.x == 0) {
-        out->status = rc;
-        out->sweeps = outer.sweeps;
-        out->steps = outer.steps;
-        out->work = outer.work;
+__global__ __launch_bounds__(1024) void k_qr_init(const double* H, int64_t ld, int n, QrGlobal* g) {
+    __shared__ double part[16];
+    double m = 0.0;
+    for (int r = threadIdx.x >> 6; r < n; r += 16) {
+        const int c0 = r > 0 ? r - 1 : 0;
+        for (int c = c0 + (threadIdx.x & 63); c < n; c += 64) {
+            const double h = H[(int64_t)r * ld + c];
+            m = fma(h, h, m);
+        }
     }
+    for (int o = 32; o > 0; o >>= 1) m += __shfl_xor(m, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0;
+        for (int w = 0; w < 16; ++w) a += part[w];
+        g->anorm = a > 0.0 ? sqrt(a) : 1.0;
+        g->u = n - 1;
+        g->split = 0;
+        g->its = 0;
+        g->status = 0;
+        g->action = 0;
+        g->l = 0;
+        g->b = 0;
+        g->sweeps = g->steps = g->work = 0;
+    }
+}
+
+// The largest k in [1, u] with a negligible subdiagonal entry (the test of qr_eigs).
+__global__ void k_qr_scan(const double* H, int64_t ld, QrGlobal* g) {
+    const int k = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int u = g->u;
+    if (k > u) return;
+    const double sd = fabs(H[(int64_t)k * ld + k - 1]);
+    double tst = fabs(H[(int64_t)(k - 1) * ld + k - 1]) + fabs(H[(int64_t)k * ld + k]);
+    if (tst == 0.0 || g->its >= 10) tst = fmax(tst, g->anorm);
+    if (sd <= DBL_EPSILON * tst) atomicMax(&g->split, k);
+}
+
+// One decision on the bottom block [split, u]: the eigenvalues of a 1 x 1 or 2 x 2
+// block, a whole small block by qr_eigs, or the set-up of a device-wide sweep
+// (shifts from the trailing block, the first bulge's reflector).
+__global__ __launch_bounds__(kQrThreads) void k_qr_decide(double* H, int64_t ld, QrGlobal* g, double2* lam) {
+    __shared__ QrCtl outer, inner;
+    __shared__ double sub[kWideShiftDim * kWideShiftDim];
+    __shared__ double2 subev[kWideShiftDim];
+    __shared__ int sh_b, sh_exc, sh_u, sh_l;
+    const int tid = threadIdx.x;
+    // read once into LDS: thread 0 rewrites these fields below
+    if (tid == 0) {
+        sh_u = g->u;
+        sh_l = g->split;
+    }
+    __syncthreads();
+    const int u = sh_u, l = sh_l;
+    if (l >= u - 1) {
+        if (tid == 0) {
+            if (l > 0) H[(int64_t)l * ld + l - 1] = 0.0;
+            if (l == u) {
+                lam[u] = make_double2(H[(int64_t)u * ld + u], 0.0);
+                g->u = u - 1;
+            } else {
+                eig2(H[(int64_t)(u - 1) * ld + u - 1], H[(int64_t)(u - 1) * ld + u], H[(int64_t)u * ld + u - 1],
+                     H[(int64_t)u * ld + u], &lam[u - 1], &lam[u]);
+                g->u = u - 2;
+            }
+            g->its = 0;
+            g->split = 0;
+            g->action = 0;
+        }
+        return;
+    }
+    const int na = u - l + 1;
+    if (na <= kSmallBlock) {
+        if (tid == 0 && l > 0) H[(int64_t)l * ld + l - 1] = 0.0;
+        __syncthreads();
+        const int rc = qr_eigs<kMaxBulges>(H + (int64_t)l * ld + l, ld, na, lam + l, outer, &inner, sub, subev);
+        if (tid == 0) {
+            if (rc) g->status = 1;
+            g->sweeps += outer.sweeps;
+            g->steps += outer.steps;
+            g->work += outer.work;
+            g->u = l - 1;
+            g->its = 0;
+            g->split = 0;
+            g->action = 0;
+        }
+        return;
+    }
+    if (tid == 0) {
+        if (l > 0) H[(int64_t)l * ld + l - 1] = 0.0;
+        const int its = g->its + 1;
+        g->its = its;
+        if (its > kMaxIts) g->status = 1;
+        sh_b = min(kWideBulges, max(1, na / 16));
+        sh_exc = (its % 10) == 0;
+    }
+    __syncthreads();
+    const int b = sh_b;
+    if (sh_exc) {
+        if (tid == 0) {
+            const double w = H[(int64_t)u * ld + u] +
+                             0.75 * (fabs(H[(int64_t)u * ld + u - 1]) + fabs(H[(int64_t)(u - 1) * ld + u - 2]));
+            for (int i = 0; i < b; ++i) {
+                g->s[i] = 2.0 * w;
+                g->t[i] = w * w;
+            }
+        }
+    } else {
+        const int mm = 2 * b, o = u - mm + 1;
+        for (int e = tid; e < mm * mm; e += kQrThreads) {
+            const int r = e / mm, c = e % mm;
+            sub[e] = r <= c + 1 ? H[(int64_t)(o + r) * ld + o + c] : 0.0;
+        }
+        __syncthreads();
+        const int rc = qr_eigs<1>(sub, mm, mm, subev, inner, nullptr, nullptr, nullptr);
+        if (tid == 0) {
+            const double a = H[(int64_t)(u - 1) * ld + u - 1], bb = H[(int64_t)(u - 1) * ld + u];
+            const double c = H[(int64_t)u * ld + u - 1], d = H[(int64_t)u * ld + u];
+            int np = 0;
+            if (rc == 0) {
+                double re[kWideShiftDim];
+                int nr = 0;
+                for (int i = 0; i < mm; ++i) {
+                    const double2 z = subev[i];
+                    if (z.y > 0.0) {
+                        g->s[np] = 2.0 * z.x;
+                        g->t[np] = z.x * z.x + z.y * z.y;
+                        ++np;
+                    } else if (z.y == 0.0) {
+                        int q = nr++;
+                        while (q > 0 && re[q - 1] > z.x) {
+                            re[q] = re[q - 1];
+                            --q;
+                        }
+                        re[q] = z.x;
+                    }
+                }
+                for (int i = 0; i + 1 < nr && np < b; i += 2) {
+                    g->s[np] = re[i] + re[i + 1];
+                    g->t[np] = re[i] * re[i + 1];
+                    ++np;
+                }
+            }
+            for (int i = np; i < b; ++i) {  // a failed shift solve or unpaired leftovers: the trailing 2 x 2
+                g->s[i] = np ? g->s[np - 1] : a + d;
+                g->t[i] = np ? g->t[np - 1] : a * d - bb * c;
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double x, y, z, beta;
+        intro_xyz(H, ld, l, g->s[0], g->t[0], &x, &y, &z);
+        house3(x, y, z, &g->tau[0][0], &g->w1[0][0], &g->w2[0][0], &beta);
+        g->l = l;
+        g->b = b;
+        g->split = 0;
+        g->action = 1;
+    }
+}
+
+// Step t of a device-wide sweep over [l, u] with b bulges: reflectors from the left,
+// one (bulge, column) piece per thread.
+__global__ __launch_bounds__(256) void k_qr_left(double* H, int64_t ld, int l, int u, int b, int t, int ilo, int ihi,
+                                                 int total, const QrGlobal* g) {
+    int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= total) return;
+    const int p = t & 1;
+    int i = ilo;
+    while (i < ihi && e >= u - (l + t - kSep * i) + 1) {
+        e -= u - (l + t - kSep * i) + 1;
+        ++i;
+    }
+    if (e >= u - (l + t - kSep * i) + 1) return;
+    const double tau = g->tau[p][i];
+    if (tau == 0.0) return;
+    const double w1 = g->w1[p][i], w2 = g->w2[p][i];
+    const int k = l + t - kSep * i;
+    double* a = H + (int64_t)k * ld + k + e;
+    const bool three = k + 2 <= u;
+    const double a0 = a[0], a1 = a[ld], a2 = three ? a[2 * ld] : 0.0;
+    const double r = tau * (a0 + w1 * a1 + w2 * a2);
+    a[0] = a0 - r;
+    a[ld] = a1 - r * w1;
+    if (three) a[2 * ld] = a2 - r * w2;
+}
+
+// Step t, reflectors from the right: the owners (threads 0..b-1 of block 0) update
+// rows k+1..k+3 of their bulge and build its next reflector, or the first reflector
+// of the bulge that enters at step t + 1; every other thread one (bulge, row) piece
+// of rows l..k.
+__global__ __launch_bounds__(256) void k_qr_right(double* H, int64_t ld, int l, int u, int b, int t, int ilo, int ihi,
+                                                  int total, QrGlobal* g) {
+    const int p = t & 1;
+    if (blockIdx.x == 0 && threadIdx.x < b) {
+        const int i = threadIdx.x;
+        const int k = l + t - kSep * i;
+        double tn = 0.0, w1n = 0.0, w2n = 0.0;
+        if (i >= ilo && i <= ihi) {
+            const double tau = g->tau[p][i], w1 = g->w1[p][i], w2 = g->w2[p][i];
+            const bool three = k + 2 <= u;
+            double col[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int rr = 0; rr < 3; ++rr) {
+                const int row = k + 1 + rr;
+                if (row <= u) {
+                    double* h = H + (int64_t)row * ld + k;
+                    double h0 = h[0], h1 = h[1], h2 = three ? h[2] : 0.0;
+                    if (tau != 0.0) {
+                        const double q = tau * (h0 + w1 * h1 + w2 * h2);
+                        h0 -= q;
+                        h1 -= q * w1;
+                        h2 -= q * w2;
+                        h[1] = h1;
+                        if (three) h[2] = h2;
+                    }
+                    col[rr] = h0;
+                }
+            }
+            const int kn = k + 1;
+            double beta = 0.0;
+            if (kn <= u - 1) house3(col[0], col[1], kn + 2 <= u ? col[2] : 0.0, &tn, &w1n, &w2n, &beta);
+#pragma unroll
+            for (int rr = 0; rr < 3; ++rr) {
+                const int row = k + 1 + rr;
+                if (row <= u) H[(int64_t)row * ld + k] = tn != 0.0 ? (rr == 0 ? beta : 0.0) : col[rr];
+            }
+        } else if (i >= 1 && t + 1 == kSep * i) {
+            double x, y, z, beta;
+            intro_xyz(H, ld, l, g->s[i], g->t[i], &x, &y, &z);
+            house3(x, y, z, &tn, &w1n, &w2n, &beta);
+        }
+        g->tau[p ^ 1][i] = tn;
+        g->w1[p ^ 1][i] = w1n;
+        g->w2[p ^ 1][i] = w2n;
+    }
+    int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= total) return;
+    int i = ilo;
+    while (i < ihi && e >= (l + t - kSep * i) - l + 1) {
+        e -= (l + t - kSep * i) - l + 1;
+        ++i;
+    }
+    if (e >= (l + t - kSep * i) - l + 1) return;
+    const double tau = g->tau[p][i];
+    if (tau == 0.0) return;
+    const double w1 = g->w1[p][i], w2 = g->w2[p][i];
+    const int k = l + t - kSep * i;
+    double* h = H + (int64_t)(l + e) * ld + k;
+    const bool three = k + 2 <= u;
+    const double h0 = h[0], h1 = h[1], h2 = three ? h[2] : 0.0;
+    const double q = tau * (h0 + w1 * h1 + w2 * h2);
+    h[0] = h0 - q;
+    h[1] = h1 - q * w1;
+    if (three) h[2] = h2 - q * w2;
 }
 
 // ---------------------------------------------------------------------------
@@ -617,26 +878,70 @@ int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam
     hipStream_t s = c->stream;
     // the working copy sits past the reduction's own scratch
     const size_t o_h = HessLayout(M).end;
-    const size_t o_out = o_h + lb_align(sizeof(double) * (size_t)M * M, 256);
-    int rc = lb_ws_reserve(c, o_out + sizeof(QrOut));
+    const size_t o_g = o_h + lb_align(sizeof(double) * (size_t)M * M, 256);
+    int rc = lb_ws_reserve(c, o_g + sizeof(QrGlobal));
+    if (rc) return rc;
+    rc = lb_host_reserve(c, sizeof(QrGlobal));
     if (rc) return rc;
     double* H = (double*)((char*)c->ws + o_h);
-    QrOut* out = (QrOut*)((char*)c->ws + o_out);
+    QrGlobal* g = (QrGlobal*)((char*)c->ws + o_g);
+    const int64_t ld = M;
     LB_HIP(hipMemcpy2DAsync(H, sizeof(double) * M, Q, sizeof(double) * ldq, sizeof(double) * M, M,
                             hipMemcpyDeviceToDevice, s));
-    rc = lb_impl_hessenberg(c, M, H, M);
+    rc = lb_impl_hessenberg(c, M, H, ld);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_hqr, dim3(1), dim3(kQrThreads), 0, s, H, (int64_t)M, M, (double2*)lam, out);
+    hipLaunchKernelGGL(k_qr_init, dim3(1), dim3(1024), 0, s, (const double*)H, ld, M, g);
     LB_CHECK_LAUNCH();
-    rc = lb_host_reserve(c, sizeof(QrOut));
-    if (rc) return rc;
-    LB_HIP(hipMemcpyAsync(c->host, out, sizeof(QrOut), hipMemcpyDeviceToHost, s));
-    LB_HIP(hipStreamSynchronize(s));
-    const QrOut o = *(const QrOut*)c->host;
-    if (sweeps) *sweeps = o.sweeps;
-    if (steps) *steps = o.steps;
-    if (work) *work = o.work;
-    if (o.status) return lb_fail(LB_ERR_NO_CONVERGENCE, "QR iteration: %d sweeps without a split", kMaxIts);
+    int64_t n_sweeps = 0, n_steps = 0, n_work = 0;
+    QrGlobal* hg = (QrGlobal*)c->host;
+    int u = M - 1;
+    // every pass either lowers u or counts a sweep, and sweeps per split are capped
+    for (int64_t pass = 0; u >= 0; ++pass) {
+        if (u >= 1) {
+            hipLaunchKernelGGL(k_qr_scan, dim3(lb_blocks(u, 256)), dim3(256), 0, s, (const double*)H, ld, g);
+            LB_CHECK_LAUNCH();
+        }
+        hipLaunchKernelGGL(k_qr_decide, dim3(1), dim3(kQrThreads), 0, s, H, ld, g, (double2*)lam);
+        LB_CHECK_LAUNCH();
+        LB_HIP(hipMemcpyAsync(hg, g, 8 * sizeof(int) + 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        LB_HIP(hipStreamSynchronize(s));
+        if (hg->status) return lb_fail(LB_ERR_NO_CONVERGENCE, "QR iteration: %d sweeps without a split", kMaxIts);
+        if (hg->action == 1) {
+            const int l = hg->l, b = hg->b;
+            if (l < 0 || b < 1 || b > kWideBulges || u - l + 1 <= kSmallBlock)
+                return lb_fail(LB_ERR_DEVICE, "QR iteration: inconsistent sweep l=%d u=%d b=%d", l, u, b);
+            const int T = kSep * (b - 1) + (u - l);
+            const int64_t na = u - l + 1;
+            ++n_sweeps;
+            n_steps += T;
+            n_work += (int64_t)b * (na * na + 3 * na - 7);
+            for (int t = 0; t < T; ++t) {
+                const int ihi = std::min(b - 1, t / kSep);
+                int ilo = 0;
+                while (ilo <= ihi && l + t - kSep * ilo > u - 1) ++ilo;
+                int left = 0, right = 0;
+                for (int i = ilo; i <= ihi; ++i) {
+                    const int k = l + t - kSep * i;
+                    left += u - k + 1;
+                    right += k - l + 1;
+                }
+                if (left > 0) {
+                    hipLaunchKernelGGL(k_qr_left, dim3(lb_blocks(left, 256)), dim3(256), 0, s, H, ld, l, u, b, t, ilo,
+                                       ihi, left, (const QrGlobal*)g);
+                    LB_CHECK_LAUNCH();
+                }
+                hipLaunchKernelGGL(k_qr_right, dim3(std::max(1u, lb_blocks(right, 256))), dim3(256), 0, s, H, ld, l,
+                                   u, b, t, ilo, ihi, right, g);
+                LB_CHECK_LAUNCH();
+            }
+        } else if (hg->u >= u) {
+            return lb_fail(LB_ERR_DEVICE, "QR iteration: no progress at u=%d", u);
+        }
+        u = hg->u;
+    }
+    if (sweeps) *sweeps = n_sweeps + hg->sweeps;
+    if (steps) *steps = n_steps + hg->steps;
+    if (work) *work = n_work + hg->work;
     return LB_OK;
 }
 

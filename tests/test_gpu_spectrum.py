@@ -109,6 +109,7 @@ def edge_matrices():
         "zero_6": np.zeros((6, 6)),
         "cyclic_5": np.roll(np.eye(5), 1, axis=1),
         "cyclic_200": np.roll(np.eye(200), 1, axis=1),
+        "cyclic_300": np.roll(np.eye(300), 1, axis=1),
         "clusters_50": U @ np.diag(np.repeat([1.0, -2.0, 3.0, 0.5, 7.0], 10)) @ U.T,
         "gauss_300": g.standard_normal((300, 300)),
         "gauss_65": g.standard_normal((65, 65)),
