@@ -35,8 +35,8 @@ constexpr int kSep = 4;                     // rows between neighbouring bulges
 constexpr int kShiftDim = 2 * kMaxBulges;   // trailing block solved for the shifts
 constexpr int kMaxIts = 120;                // sweeps without a split before giving up
 constexpr int kBatch = 1;                   // row / column pieces per thread with loads in flight together
-constexpr int kChunkRows = 256;             // row chunk of the column pass
-constexpr int kMaxChunks = 64;
+constexpr int kChunkRows = 16;              // shortest row chunk of the column pass
+constexpr int kMaxChunks = 256;
 
 // ---------------------------------------------------------------------------
 // Stage 1: Hessenberg reduction
@@ -587,6 +587,8 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_decide(double* H, int64_t ld,
     __shared__ QrCtl outer, inner;
     __shared__ double sub[kWideShiftDim * kWideShiftDim];
     __shared__ double2 subev[kWideShiftDim];
+    __shared__ double sub2[kShiftDim * kShiftDim];
+    __shared__ double2 subev2[kShiftDim];
     __shared__ int sh_b, sh_exc, sh_u, sh_l;
     const int tid = threadIdx.x;
     // read once into LDS: thread 0 rewrites these fields below
@@ -617,7 +619,7 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_decide(double* H, int64_t ld,
     if (na <= kSmallBlock) {
         if (tid == 0 && l > 0) H[(int64_t)l * ld + l - 1] = 0.0;
         __syncthreads();
-        const int rc = qr_eigs<kMaxBulges>(H + (int64_t)l * ld + l, ld, na, lam + l, outer, &inner, sub, subev);
+        const int rc = qr_eigs<kMaxBulges>(H + (int64_t)l * ld + l, ld, na, lam + l, outer, &inner, sub2, subev2);
         if (tid == 0) {
             if (rc) g->status = 1;
             g->sweeps += outer.sweeps;
@@ -656,7 +658,7 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_decide(double* H, int64_t ld,
             sub[e] = r <= c + 1 ? H[(int64_t)(o + r) * ld + o + c] : 0.0;
         }
         __syncthreads();
-        const int rc = qr_eigs<1>(sub, mm, mm, subev, inner, nullptr, nullptr, nullptr);
+        const int rc = qr_eigs<kMaxBulges>(sub, mm, mm, subev, outer, &inner, sub2, subev2);
         if (tid == 0) {
             const double a = H[(int64_t)(u - 1) * ld + u - 1], bb = H[(int64_t)(u - 1) * ld + u];
             const double c = H[(int64_t)u * ld + u - 1], d = H[(int64_t)u * ld + u];
@@ -731,8 +733,8 @@ __global__ __launch_bounds__(256) void k_qr_left(double* H, int64_t ld, int l, i
 
 // Step t, reflectors from the right: the owners (threads 0..b-1 of block 0) update
 // rows k+1..k+3 of their bulge and build its next reflector, or the first reflector
-// of the bulge that enters at step t + 1; every other thread one (bulge, row) piece
-// of rows l..k.
+// of the bulge that enters at step t + 1; every thread one (row, bulge) piece of
+// rows l..k (total = rows l..k of the leading bulge times the active bulges).
 __global__ __launch_bounds__(256) void k_qr_right(double* H, int64_t ld, int l, int u, int b, int t, int ilo, int ihi,
                                                   int total, QrGlobal* g) {
     const int p = t & 1;
@@ -778,19 +780,18 @@ __global__ __launch_bounds__(256) void k_qr_right(double* H, int64_t ld, int l, 
         g->w1[p ^ 1][i] = w1n;
         g->w2[p ^ 1][i] = w2n;
     }
-    int e = blockIdx.x * 256 + threadIdx.x;
+    // pieces (row, bulge) with the bulge fastest: the strips of one row are adjacent
+    // (kSep columns apart), so a wavefront reads a contiguous stretch of few rows
+    const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= total) return;
-    int i = ilo;
-    while (i < ihi && e >= (l + t - kSep * i) - l + 1) {
-        e -= (l + t - kSep * i) - l + 1;
-        ++i;
-    }
-    if (e >= (l + t - kSep * i) - l + 1) return;
+    const int nb = ihi - ilo + 1;
+    const int row = l + e / nb, i = ilo + e % nb;
+    const int k = l + t - kSep * i;
+    if (row > k) return;  // rows k+1..k+3 are the owner's
     const double tau = g->tau[p][i];
     if (tau == 0.0) return;
     const double w1 = g->w1[p][i], w2 = g->w2[p][i];
-    const int k = l + t - kSep * i;
-    double* h = H + (int64_t)(l + e) * ld + k;
+    double* h = H + (int64_t)row * ld + k;
     const bool three = k + 2 <= u;
     const double h0 = h[0], h1 = h[1], h2 = three ? h[2] : 0.0;
     const double q = tau * (h0 + w1 * h1 + w2 * h2);
@@ -855,8 +856,9 @@ int lb_impl_hessenberg(lb_ctx* c, int M, double* A, int64_t lda) {
         hipLaunchKernelGGL(k_hh_p, dim3(lb_blocks(M, 4)), dim3(256), 0, s, (const double*)A, lda, M, j,
                            (const double*)v, p);
         LB_CHECK_LAUNCH();
+        // enough row chunks for about 2048 blocks, none shorter than kChunkRows rows
         const int cb = (int)lb_blocks(L, 256);
-        int nch = (int)lb_blocks(L, kChunkRows);
+        int nch = std::min((int)lb_blocks(L, kChunkRows), std::max(1, 2048 / cb));
         if (nch > kMaxChunks) nch = kMaxChunks;
         const int rows_per_chunk = (L + nch - 1) / nch;
         nch = (L + rows_per_chunk - 1) / rows_per_chunk;
@@ -919,12 +921,9 @@ int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam
                 const int ihi = std::min(b - 1, t / kSep);
                 int ilo = 0;
                 while (ilo <= ihi && l + t - kSep * ilo > u - 1) ++ilo;
-                int left = 0, right = 0;
-                for (int i = ilo; i <= ihi; ++i) {
-                    const int k = l + t - kSep * i;
-                    left += u - k + 1;
-                    right += k - l + 1;
-                }
+                int left = 0;
+                for (int i = ilo; i <= ihi; ++i) left += u - (l + t - kSep * i) + 1;
+                const int right = ilo <= ihi ? (l + t - kSep * ilo - l + 1) * (ihi - ilo + 1) : 0;
                 if (left > 0) {
                     hipLaunchKernelGGL(k_qr_left, dim3(lb_blocks(left, 256)), dim3(256), 0, s, H, ld, l, u, b, t, ilo,
                                        ihi, left, (const QrGlobal*)g);
