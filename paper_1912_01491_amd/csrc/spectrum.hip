@@ -528,7 +528,7 @@ __device__ int qr_eigs(double* H, int64_t ld, int n, double2* lam, QrCtl& C, QrC
 // sweeps over larger blocks run each phase of each chain step as a launch over the
 // whole device, the kernel boundaries ordering the phases.
 constexpr int kSmallBlock = 256;
-constexpr int kWideBulges = 32;                 // bulges per device-wide sweep (64 shifts)
+constexpr int kWideBulges = 64;                 // bulges per device-wide sweep (128 shifts)
 constexpr int kWideShiftDim = 2 * kWideBulges;  // trailing block solved for their shifts
 
 // Device-side state of the host-driven iteration. The host reads the first eight
