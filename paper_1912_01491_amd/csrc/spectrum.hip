@@ -110,10 +110,12 @@ __global__ __launch_bounds__(256) void k_hh_q(const double* A, int64_t ld, int M
     qpart[(int64_t)blockIdx.y * M + c] = s;
 }
 
-// q[c] = sum of the chunk partials (fixed order); the last block forms s = v^T p.
+// q[c] = sum of the chunk partials: a block covers 64 columns, its four wavefronts
+// every fourth chunk, combined in fixed order; the last block forms s = v^T p.
 __global__ __launch_bounds__(256) void k_hh_qfin(int M, int j, int nchunks, const double* qpart, const double* v,
                                                  const double* p, double* q, double* sc) {
     __shared__ double red[4];
+    __shared__ double part[4][64];
     if (blockIdx.x == gridDim.x - 1) {
         double s = 0.0;
         for (int i = threadIdx.x; i < M - j - 1; i += 256) s = fma(v[i], p[j + 1 + i], s);
@@ -121,11 +123,16 @@ __global__ __launch_bounds__(256) void k_hh_qfin(int M, int j, int nchunks, cons
         if (threadIdx.x == 0) sc[1] = s;
         return;
     }
-    const int c = j + 1 + blockIdx.x * 256 + threadIdx.x;
-    if (c >= M) return;
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int c = j + 1 + blockIdx.x * 64 + lane;
     double s = 0.0;
-    for (int k = 0; k < nchunks; ++k) s += qpart[(int64_t)k * M + c];
-    q[c] = s;
+    if (c < M) {
+#pragma unroll 8
+        for (int k = grp; k < nchunks; k += 4) s += qpart[(int64_t)k * M + c];
+    }
+    part[grp][lane] = s;
+    __syncthreads();
+    if (grp == 0 && c < M) q[c] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
 // A[r][c] -= v_r w_c + tau p_r v_c over rows 0..M-1 and columns j+1..M-1
@@ -865,7 +872,7 @@ int lb_impl_hessenberg(lb_ctx* c, int M, double* A, int64_t lda) {
         hipLaunchKernelGGL(k_hh_q, dim3(cb, nch), dim3(256), 0, s, (const double*)A, lda, M, j, (const double*)v,
                            qpart, rows_per_chunk);
         LB_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_hh_qfin, dim3(cb + 1), dim3(256), 0, s, M, j, nch, (const double*)qpart,
+        hipLaunchKernelGGL(k_hh_qfin, dim3(lb_blocks(L, 64) + 1), dim3(256), 0, s, M, j, nch, (const double*)qpart,
                            (const double*)v, (const double*)p, q, sc);
         LB_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_hh_update, dim3(lb_blocks(L, 64), lb_blocks(M, 16)), dim3(256), 0, s, A, lda, M, j,
