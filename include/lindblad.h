@@ -378,7 +378,8 @@ typedef struct lb_spectrum_info {
  * with chains of up to 16 bulges whose shifts are the eigenvalues of the
  * trailing block; a block splits off where a subdiagonal entry falls below
  * eps (|h_k-1,k-1| + |h_kk|), or below eps ||Q||_F once ten sweeps have passed
- * without a split (clusters at the rounding floor). *info (may be NULL) receives the iteration
+ * without a split and below sqrt(M) eps ||Q||_F after twenty (clusters at the
+ * rounding floor). *info (may be NULL) receives the iteration
  * counts. Synchronous. Errors: LB_ERR_INVALID_ARG (M < 1, M >
  * LB_SPECTRUM_MAX_M, ldq < M, null pointers), LB_ERR_OOM,
  * LB_ERR_NO_CONVERGENCE (120 sweeps without a split; lam is then not valid),

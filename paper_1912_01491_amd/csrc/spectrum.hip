@@ -9,16 +9,19 @@
 //     q = A^T v, s = v^T p and w = tau q - tau^2 s v: a row-dot pass (p), a column
 //     pass (q, partial sums per row chunk reduced in fixed order), and the update.
 //  2. Francis' implicit double-shift QR iteration on the Hessenberg matrix,
-//     eigenvalues only (updates stay inside the active block), in one workgroup.
-//     A sweep chases a chain of up to kMaxBulges double-shift bulges spaced
-//     kSep = 4 rows apart: at that spacing no bulge's reflector reads what another
-//     bulge writes in the same step, and reflections from the two sides commute, so
-//     each chain step is three parallel phases (all reflectors, all row updates, all
-//     column updates) instead of three phases per bulge. The 2b shifts of a b-bulge
-//     chain are the eigenvalues of the trailing 2b x 2b block, found by the same
-//     iteration with one bulge on a copy in LDS. A block splits off where a
-//     subdiagonal entry falls below eps (|h_k-1,k-1| + |h_kk|), or below eps ||H||_F
-//     after ten sweeps without a split; 1 x 1 and 2 x 2 blocks give their eigenvalues
+//     eigenvalues only (updates stay inside the active block). A sweep chases a
+//     chain of b double-shift bulges spaced kSep = 4 rows apart: at that spacing no
+//     bulge's reflector reads what another bulge writes in the same step, and
+//     reflections from the two sides commute, so a chain step is data-parallel over
+//     all b bulges at once. Blocks above kSmallBlock rows are swept over the whole
+//     device (up to kWideBulges bulges, one launch per chain step); smaller blocks,
+//     and the shift problems, by one workgroup (up to kMaxBulges bulges, two barrier
+//     phases per chain step). The 2b shifts of a b-bulge chain are the eigenvalues of
+//     the trailing 2b x 2b block, found by the same iteration on a copy in LDS
+//     (recursively, down to one bulge). A block splits off where a
+//     subdiagonal entry falls below eps (|h_k-1,k-1| + |h_kk|), below eps ||H||_F after
+//     ten sweeps without a split and below sqrt(n) eps ||H||_F after twenty (clusters at
+//     the rounding floor); 1 x 1 and 2 x 2 blocks give their eigenvalues
 //     directly. Every tenth sweep without a split takes an exceptional shift to break
 //     cycles; kMaxIts sweeps without one is an error.
 #include "lb_internal.h"
@@ -263,12 +266,13 @@ __device__ int qr_eigs(double* H, int64_t ld, int n, double2* lam, QrCtl& C, QrC
         // Largest k in [1, u] whose subdiagonal entry is negligible (0 if none): below
         // eps times its two diagonal neighbours, or, once ten sweeps have passed without
         // a split (a cluster whose subdiagonal sits at the rounding floor), below eps
-        // ||H||_F, a normwise backward error of the size the reduction already makes.
-        const bool stalled = C.its >= 10;
+        // ||H||_F, and after twenty below sqrt(n) eps ||H||_F: normwise backward errors of
+        // the size the Householder reduction itself leaves.
+        const double floor_scale = C.its >= 20 ? sqrt((double)n) * C.anorm : (C.its >= 10 ? C.anorm : 0.0);
         for (int k = u - tid; k >= 1; k -= kQrThreads) {
             const double sd = fabs(at(H, ld, k, k - 1));
             double tst = fabs(at(H, ld, k - 1, k - 1)) + fabs(at(H, ld, k, k));
-            if (tst == 0.0 || stalled) tst = fmax(tst, C.anorm);
+            tst = tst == 0.0 ? fmax(C.anorm, floor_scale) : fmax(tst, floor_scale);
             if (sd <= eps * tst) {
                 atomicMax(&C.split, k);
                 break;
@@ -576,14 +580,17 @@ __global__ __launch_bounds__(1024) void k_qr_init(const double* H, int64_t ld, i
     }
 }
 
-// The largest k in [1, u] with a negligible subdiagonal entry (the test of qr_eigs).
-__global__ void k_qr_scan(const double* H, int64_t ld, QrGlobal* g) {
+// The largest k in [1, u] with a negligible subdiagonal entry (the test of qr_eigs, n the
+// order of the whole matrix).
+__global__ void k_qr_scan(const double* H, int64_t ld, int n, QrGlobal* g) {
     const int k = 1 + blockIdx.x * blockDim.x + threadIdx.x;
     const int u = g->u;
     if (k > u) return;
     const double sd = fabs(H[(int64_t)k * ld + k - 1]);
     double tst = fabs(H[(int64_t)(k - 1) * ld + k - 1]) + fabs(H[(int64_t)k * ld + k]);
-    if (tst == 0.0 || g->its >= 10) tst = fmax(tst, g->anorm);
+    const int its = g->its;
+    const double floor_scale = its >= 20 ? sqrt((double)n) * g->anorm : (its >= 10 ? g->anorm : 0.0);
+    tst = tst == 0.0 ? fmax(g->anorm, floor_scale) : fmax(tst, floor_scale);
     if (sd <= DBL_EPSILON * tst) atomicMax(&g->split, k);
 }
 
@@ -712,24 +719,20 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_decide(double* H, int64_t ld,
     }
 }
 
-// Step t of a device-wide sweep over [l, u] with b bulges: reflectors from the left,
-// one (bulge, column) piece per thread.
-__global__ __launch_bounds__(256) void k_qr_left(double* H, int64_t ld, int l, int u, int b, int t, int ilo, int ihi,
-                                                 int total, const QrGlobal* g) {
-    int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= total) return;
-    const int p = t & 1;
-    int i = ilo;
-    while (i < ihi && e >= u - (l + t - kSep * i) + 1) {
-        e -= u - (l + t - kSep * i) + 1;
-        ++i;
-    }
-    if (e >= u - (l + t - kSep * i) + 1) return;
-    const double tau = g->tau[p][i];
-    if (tau == 0.0) return;
-    const double w1 = g->w1[p][i], w2 = g->w2[p][i];
-    const int k = l + t - kSep * i;
-    double* a = H + (int64_t)k * ld + k + e;
+// Index (q, m), 0 <= m < q, of entry e of the triangular enumeration q(q-1)/2 + m.
+__device__ __forceinline__ void tri_index(int e, int* q, int* m) {
+    int r = (int)((1.0 + sqrt(1.0 + 8.0 * (double)e)) * 0.5);
+    while (r * (r - 1) / 2 > e) --r;
+    while (r * (r + 1) / 2 <= e) ++r;
+    *q = r;
+    *m = e - r * (r - 1) / 2;
+}
+
+// Reflector of bulge i (positions k..k+2, two entries where k + 2 > u) applied from the
+// left to column c or from the right to row r.
+__device__ __forceinline__ void refl_left(double* H, int64_t ld, int k, int u, double tau, double w1, double w2,
+                                          int c) {
+    double* a = H + (int64_t)k * ld + c;
     const bool three = k + 2 <= u;
     const double a0 = a[0], a1 = a[ld], a2 = three ? a[2 * ld] : 0.0;
     const double r = tau * (a0 + w1 * a1 + w2 * a2);
@@ -738,13 +741,34 @@ __global__ __launch_bounds__(256) void k_qr_left(double* H, int64_t ld, int l, i
     if (three) a[2 * ld] = a2 - r * w2;
 }
 
-// Step t, reflectors from the right: the owners (threads 0..b-1 of block 0) update
-// rows k+1..k+3 of their bulge and build its next reflector, or the first reflector
-// of the bulge that enters at step t + 1; every thread one (row, bulge) piece of
-// rows l..k (total = rows l..k of the leading bulge times the active bulges).
-__global__ __launch_bounds__(256) void k_qr_right(double* H, int64_t ld, int l, int u, int b, int t, int ilo, int ihi,
-                                                  int total, QrGlobal* g) {
+__device__ __forceinline__ void refl_right(double* H, int64_t ld, int k, int u, double tau, double w1, double w2,
+                                           int row) {
+    double* h = H + (int64_t)row * ld + k;
+    const bool three = k + 2 <= u;
+    const double h0 = h[0], h1 = h[1], h2 = three ? h[2] : 0.0;
+    const double q = tau * (h0 + w1 * h1 + w2 * h2);
+    h[0] = h0 - q;
+    h[1] = h1 - q * w1;
+    if (three) h[2] = h2 - q * w2;
+}
+
+// Step t of a device-wide sweep over [l, u] with b bulges (bulge i at k_i = l + t - kSep i,
+// active for ilo <= i <= ihi), both sides in one launch. A left reflection of bulge i
+// (rows k_i..k_i+2, columns k_i..u) and a right one of bulge j (columns k_j..k_j+2, rows
+// l..k_j+3) meet only in the 3 x 3 block rows(i) x columns(j) with j <= i, where they
+// commute; one thread applies both there (left first), so every entry has one writer:
+//   left-only:  columns k_ilo+3..u of every active bulge (nb x tail pieces), and the gap
+//               columns k_i + 4m + 3 between deeper strips (triangular),
+//   right-only: rows l..k_ihi-1 of every active bulge (head x nb, bulge fastest: the strips
+//               of one row are adjacent), and the gap rows k_i + 3, i > j (triangular),
+//   crossings:  blocks (i, j), j < i (triangular),
+//   owners:     thread i of block 0 takes block (i, i) and row k_i + 3, then builds bulge
+//               i's next reflector from column k_i (or the first reflector of the bulge that
+//               enters at step t + 1).
+__global__ __launch_bounds__(256) void k_qr_step(double* H, int64_t ld, int l, int u, int b, int t, int ilo, int ihi,
+                                                 int tail, int head, int total, QrGlobal* g) {
     const int p = t & 1;
+    const int nb = ihi - ilo + 1;
     if (blockIdx.x == 0 && threadIdx.x < b) {
         const int i = threadIdx.x;
         const int k = l + t - kSep * i;
@@ -752,32 +776,42 @@ __global__ __launch_bounds__(256) void k_qr_right(double* H, int64_t ld, int l, 
         if (i >= ilo && i <= ihi) {
             const double tau = g->tau[p][i], w1 = g->w1[p][i], w2 = g->w2[p][i];
             const bool three = k + 2 <= u;
-            double col[3] = {0.0, 0.0, 0.0};
+            const int nr = k + 3 <= u ? 4 : (three ? 3 : 2);  // rows k.. (row k+3 takes the right side only)
+            double B[4][3];
 #pragma unroll
-            for (int rr = 0; rr < 3; ++rr) {
-                const int row = k + 1 + rr;
-                if (row <= u) {
-                    double* h = H + (int64_t)row * ld + k;
-                    double h0 = h[0], h1 = h[1], h2 = three ? h[2] : 0.0;
-                    if (tau != 0.0) {
-                        const double q = tau * (h0 + w1 * h1 + w2 * h2);
-                        h0 -= q;
-                        h1 -= q * w1;
-                        h2 -= q * w2;
-                        h[1] = h1;
-                        if (three) h[2] = h2;
-                    }
-                    col[rr] = h0;
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    B[r][c] = (r < nr && (c < 2 || three)) ? H[(int64_t)(k + r) * ld + k + c] : 0.0;
+            if (tau != 0.0) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double v = tau * (B[0][c] + w1 * B[1][c] + w2 * B[2][c]);
+                    B[0][c] -= v;
+                    B[1][c] -= v * w1;
+                    B[2][c] -= v * w2;
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double v = tau * (B[r][0] + w1 * B[r][1] + w2 * B[r][2]);
+                    B[r][0] -= v;
+                    B[r][1] -= v * w1;
+                    B[r][2] -= v * w2;
                 }
             }
             const int kn = k + 1;
             double beta = 0.0;
-            if (kn <= u - 1) house3(col[0], col[1], kn + 2 <= u ? col[2] : 0.0, &tn, &w1n, &w2n, &beta);
-#pragma unroll
-            for (int rr = 0; rr < 3; ++rr) {
-                const int row = k + 1 + rr;
-                if (row <= u) H[(int64_t)row * ld + k] = tn != 0.0 ? (rr == 0 ? beta : 0.0) : col[rr];
+            if (kn <= u - 1) house3(B[1][0], B[2][0], kn + 2 <= u ? B[3][0] : 0.0, &tn, &w1n, &w2n, &beta);
+            if (tn != 0.0) {
+                B[1][0] = beta;
+                B[2][0] = 0.0;
+                B[3][0] = 0.0;
             }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    if (r < nr && (c < 2 || three)) H[(int64_t)(k + r) * ld + k + c] = B[r][c];
         } else if (i >= 1 && t + 1 == kSep * i) {
             double x, y, z, beta;
             intro_xyz(H, ld, l, g->s[i], g->t[i], &x, &y, &z);
@@ -787,24 +821,58 @@ __global__ __launch_bounds__(256) void k_qr_right(double* H, int64_t ld, int l, 
         g->w1[p ^ 1][i] = w1n;
         g->w2[p ^ 1][i] = w2n;
     }
-    // pieces (row, bulge) with the bulge fastest: the strips of one row are adjacent
-    // (kSep columns apart), so a wavefront reads a contiguous stretch of few rows
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= total) return;
-    const int nb = ihi - ilo + 1;
-    const int row = l + e / nb, i = ilo + e % nb;
-    const int k = l + t - kSep * i;
-    if (row > k) return;  // rows k+1..k+3 are the owner's
-    const double tau = g->tau[p][i];
-    if (tau == 0.0) return;
-    const double w1 = g->w1[p][i], w2 = g->w2[p][i];
-    double* h = H + (int64_t)row * ld + k;
-    const bool three = k + 2 <= u;
-    const double h0 = h[0], h1 = h[1], h2 = three ? h[2] : 0.0;
-    const double q = tau * (h0 + w1 * h1 + w2 * h2);
-    h[0] = h0 - q;
-    h[1] = h1 - q * w1;
-    if (three) h[2] = h2 - q * w2;
+    int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= total || nb < 1) return;
+    const int kilo = l + t - kSep * ilo, kihi = l + t - kSep * ihi;
+    const int tri = nb * (nb - 1) / 2;
+    if (e < nb * tail) {  // left-only tail columns
+        const int i = ilo + e / tail, c = kilo + 3 + e % tail;
+        const double tau = g->tau[p][i];
+        if (tau != 0.0) refl_left(H, ld, l + t - kSep * i, u, tau, g->w1[p][i], g->w2[p][i], c);
+        return;
+    }
+    e -= nb * tail;
+    if (e < tri) {  // left-only gap columns
+        int q, m;
+        tri_index(e, &q, &m);
+        const int i = ilo + q, k = l + t - kSep * i;
+        const double tau = g->tau[p][i];
+        if (tau != 0.0) refl_left(H, ld, k, u, tau, g->w1[p][i], g->w2[p][i], k + kSep * m + 3);
+        return;
+    }
+    e -= tri;
+    if (e < head * nb) {  // right-only head rows
+        const int row = l + e / nb, j = ilo + e % nb;
+        const double tau = g->tau[p][j];
+        if (tau != 0.0) refl_right(H, ld, l + t - kSep * j, u, tau, g->w1[p][j], g->w2[p][j], row);
+        return;
+    }
+    e -= head * nb;
+    if (e < tri) {  // right-only gap rows k_i + 3 of bulge j < i
+        int q, m;
+        tri_index(e, &q, &m);
+        const int i = ilo + q, j = ilo + m;
+        const double tau = g->tau[p][j];
+        if (tau != 0.0) refl_right(H, ld, l + t - kSep * j, u, tau, g->w1[p][j], g->w2[p][j], l + t - kSep * i + 3);
+        return;
+    }
+    e -= tri;
+    if (e < tri) {  // crossing block rows(i) x columns(j), j < i: left of i, then right of j
+        int q, m;
+        tri_index(e, &q, &m);
+        const int i = ilo + q, j = ilo + m;
+        const int ki = l + t - kSep * i, kj = l + t - kSep * j;
+        const double ti = g->tau[p][i], tj = g->tau[p][j];
+        const bool cj3 = kj + 2 <= u;
+        if (ti != 0.0) {
+            const double w1 = g->w1[p][i], w2 = g->w2[p][i];
+            for (int c = 0; c < (cj3 ? 3 : 2); ++c) refl_left(H, ld, ki, u, ti, w1, w2, kj + c);
+        }
+        if (tj != 0.0) {
+            const double w1 = g->w1[p][j], w2 = g->w2[p][j];
+            for (int r = 0; r < 3; ++r) refl_right(H, ld, kj, u, tj, w1, w2, ki + r);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -907,7 +975,7 @@ int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam
     // every pass either lowers u or counts a sweep, and sweeps per split are capped
     for (int64_t pass = 0; u >= 0; ++pass) {
         if (u >= 1) {
-            hipLaunchKernelGGL(k_qr_scan, dim3(lb_blocks(u, 256)), dim3(256), 0, s, (const double*)H, ld, g);
+            hipLaunchKernelGGL(k_qr_scan, dim3(lb_blocks(u, 256)), dim3(256), 0, s, (const double*)H, ld, M, g);
             LB_CHECK_LAUNCH();
         }
         hipLaunchKernelGGL(k_qr_decide, dim3(1), dim3(kQrThreads), 0, s, H, ld, g, (double2*)lam);
@@ -928,16 +996,15 @@ int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam
                 const int ihi = std::min(b - 1, t / kSep);
                 int ilo = 0;
                 while (ilo <= ihi && l + t - kSep * ilo > u - 1) ++ilo;
-                int left = 0;
-                for (int i = ilo; i <= ihi; ++i) left += u - (l + t - kSep * i) + 1;
-                const int right = ilo <= ihi ? (l + t - kSep * ilo - l + 1) * (ihi - ilo + 1) : 0;
-                if (left > 0) {
-                    hipLaunchKernelGGL(k_qr_left, dim3(lb_blocks(left, 256)), dim3(256), 0, s, H, ld, l, u, b, t, ilo,
-                                       ihi, left, (const QrGlobal*)g);
-                    LB_CHECK_LAUNCH();
+                const int nb = ihi - ilo + 1;
+                int tail = 0, head = 0, total = 0;
+                if (nb >= 1) {
+                    tail = std::max(0, u - (l + t - kSep * ilo) - 2);
+                    head = (l + t - kSep * ihi) - l;
+                    total = nb * tail + head * nb + 3 * (nb * (nb - 1) / 2);
                 }
-                hipLaunchKernelGGL(k_qr_right, dim3(std::max(1u, lb_blocks(right, 256))), dim3(256), 0, s, H, ld, l,
-                                   u, b, t, ilo, ihi, right, g);
+                hipLaunchKernelGGL(k_qr_step, dim3(std::max(1u, lb_blocks(total, 256))), dim3(256), 0, s, H, ld, l, u,
+                                   b, t, ilo, ihi, tail, head, total, g);
                 LB_CHECK_LAUNCH();
             }
         } else if (hg->u >= u) {

@@ -5,7 +5,8 @@ eigenvalue (two backward-stable computations on the same matrix; tests/spectra.p
 Inputs are the oracle's Q of seeded random Lindbladians (GUE H, Wishart gamma, the
 random model of Sec. 3) and small matrices that exercise the edge paths (1 x 1,
 2 x 2, triangular, zero diagonals, a cyclic shift whose eigenvalues all share one
-modulus, clusters of repeated eigenvalues, padded rows). Grid counts are compared
+modulus, clusters of repeated eigenvalues on both sides of the 256-row switch between
+the one-workgroup and the device-wide sweeps, padded rows). Grid counts are compared
 bit for bit on identical inputs."""
 import numpy as np
 import pytest
@@ -100,6 +101,7 @@ def test_spectrum_depolarising_closed_form(lb, ctx, oracle, N, c):
 def edge_matrices():
     g = wl.rng(91)
     U, _ = np.linalg.qr(g.standard_normal((50, 50)))
+    V, _ = np.linalg.qr(g.standard_normal((260, 260)))
     out = {
         "1x1": np.array([[3.5]]),
         "2x2_complex": np.array([[0.0, -2.0], [1.0, 0.5]]),
@@ -111,6 +113,7 @@ def edge_matrices():
         "cyclic_200": np.roll(np.eye(200), 1, axis=1),
         "cyclic_300": np.roll(np.eye(300), 1, axis=1),
         "clusters_50": U @ np.diag(np.repeat([1.0, -2.0, 3.0, 0.5, 7.0], 10)) @ U.T,
+        "clusters_260": V @ np.diag(np.repeat([1.0, -2.0, 3.0, 7.0], 65)) @ V.T,
         "gauss_300": g.standard_normal((300, 300)),
         "gauss_65": g.standard_normal((65, 65)),
     }
@@ -125,8 +128,10 @@ def test_spectrum_edge_matrices(lb, ctx, oracle, name):
     check_pairs_adjacent(lam)
     if name.startswith("clusters") or name.startswith("zero") or name.startswith("cyclic"):
         # defective or clustered: compare with the known values at a normwise level
-        if name.startswith("clusters"):
+        if name == "clusters_50":
             want = np.repeat([1.0, -2.0, 3.0, 0.5, 7.0], 10)
+        elif name == "clusters_260":
+            want = np.repeat([1.0, -2.0, 3.0, 7.0], 65)
         elif name.startswith("zero"):
             want = np.zeros(6)
         else:
