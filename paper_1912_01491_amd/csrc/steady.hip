@@ -4,18 +4,22 @@
 //
 // Restarted GMRES with right preconditioning, x = P^-1 y: the Krylov basis is
 // kept whole in HBM (restart lengths in the thousands fit in 288 GB), and each
-// iteration orthogonalises by classical Gram-Schmidt applied twice, which
-// streams the basis with full-line loads instead of the one-vector-at-a-time
-// dependence of modified Gram-Schmidt:
-//   k_dots     partial dot products of w with every basis vector, per wave;
-//   k_reduce   their sums in a fixed order (deterministic, no atomics);
-//   k_update   w -= V h (and the partial sums of |w|^2 for the norm).
+// iteration orthogonalises by classical Gram-Schmidt applied twice in its
+// delayed form, which streams the basis with full-line loads, twice per step,
+// instead of the one-vector-at-a-time dependence of modified Gram-Schmidt:
+//   k_dots2      one pass over the basis for V^T [u, t], u.u and u.t, partial sums per wave;
+//   k_reduce     their sums in a fixed order (deterministic, no atomics);
+//   k_dcgs2_fin  the lagged column of the Hessenberg matrix (by the Arnoldi relation),
+//                rotated on the device by the earlier Givens rotations and a new one;
+//   k_dcgs2_next the coefficients of the next projection;
+//   k_dcgs2_upd  one pass over the basis that writes q_j and the next raw vector.
 // The operator is the dense row-dot GEMV (one wavefront per row group, as the
 // one-state RK4 stage) or the sliced sparse product; the optional
 // preconditioner is the secular approximation of the Lindbladian in the energy
-// eigenbasis (secular.hip). The small Hessenberg
-// least-squares problem (Givens rotations, back substitution) is solved on the
-// host from the column each iteration copies back.
+// eigenbasis (secular.hip). Residual estimates are read back every kLook steps;
+// at the end of a cycle the rotated triangle is copied to the host for the back
+// substitution and x += V y streams the basis once more (split over chunks of
+// basis vectors for small systems, for enough blocks).
 #include "lb_internal.h"
 #include "rowdot.h"
 #include "sell.h"
@@ -28,7 +32,7 @@
 namespace {
 
 constexpr int kDotJ = 32;           // basis vectors per block of k_dots (second grid dimension)
-constexpr int64_t kSmallM = 262144;  // below: one row per thread and split updates, for enough blocks
+constexpr int64_t kSmallM = 262144;  // below: one row per thread (and split x updates), for enough blocks
 
 // y = Q x, dense, R rows per wavefront.
 template <int R, bool ALIGNED, bool NT>
@@ -401,7 +405,8 @@ __global__ __launch_bounds__(256) void k_dots2(const double* V, int64_t ldv, int
 
 // Column bookkeeping of step j >= 1, part 1 (one block): finishes column j-1
 // of the unrotated Hessenberg matrix (kept row-major, Hr[l * ldr + i]), rotates
-// it into H (column-major; Givens as k_givens) and sets scal = (omega, d).
+// it into H (column-major; the earlier Givens rotations applied in order, then the
+// one that zeroes the subdiagonal entry, applied to g as well) and sets scal = (omega, d).
 __global__ __launch_bounds__(256) void k_dcgs2_fin(int j, const double* sz, double* Hr, int64_t ldr, double* H,
                                                    int64_t ldh, double* cs, double* sn, double* g, double* res,
                                                    double* brk, double* scal) {
@@ -526,25 +531,6 @@ __global__ void k_copy_first(const double* src, double* dst) {
     if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = src[0];
 }
 
-// One Arnoldi column on the device: H_j = h1 + h2 (rows 0..j) and |w| (row
-// j+1) from the two Gram-Schmidt passes, the earlier Givens rotations applied
-// in order, then the rotation that zeroes row j+1, applied to g as well;
-// res[j] = |g[j+1]| (the residual norm of the least-squares solution) and
-// brk[j] = |w|. The wavefront fills the column; one thread rotates it.
-__global__ void k_givens(int j, const double* hb, double* H, int64_t ldh, double* cs, double* sn, double* g,
-                         double* res, double* brk) {
-    if (blockIdx.x != 0) return;
-    const int k = j + 1;
-    double* Hj = H + (int64_t)j * ldh;
-    for (int i = threadIdx.x; i < k; i += blockDim.x) Hj[i] = hb[i] + hb[k + i];
-    if (threadIdx.x == 0) Hj[k] = hb[2 * k];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        givens_column(j, Hj, cs, sn, g, res + j);
-        brk[j] = hb[2 * k];
-    }
-}
-
 // g = (beta, 0, ..., 0) with beta = |r| on the device.
 __global__ void k_init_g(int64_t n, const double* beta, double* g) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -574,15 +560,14 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
     }
     // split updates: at most 64 chunks of at least 16 basis vectors
     const int nch_max = small ? (int)std::min<int64_t>(64, (m + 15) / 16) : 1;
-    // aux: w, x, r, z, u (ldv each) | part ((m + 1) nparts) | hb (2 (m + 1) + 1) | nrm (1) | y (m)
+    // aux: w, x, r, z, u (ldv each) | part | hb (2 (m + 1) + 1) | nrm (1) | y (m)
     //      | H (ldh m) | cs, sn (m each) | g (m + 1) | res, brk (m each) | part2 (nch_max ldv)
-    //      | delayed Gram-Schmidt (large systems): Hr (ldh (m + 1)), sz (2 (m + 1) + 2), scal (2), t (ldv),
-    //        and part grows to (2 (m + 1) + 2) nparts
-    const bool delayed = !small;
-    const size_t n_part = (size_t)(delayed ? 2 * (m + 1) + 2 : m + 1) * nparts;
+    //      | delayed Gram-Schmidt: Hr (ldh (m + 1)), sz (2 (m + 1) + 2), scal (2), t (ldv); part holds
+    //        (2 (m + 1) + 2) nparts
+    const size_t n_part = (size_t)(2 * (m + 1) + 2) * nparts;
     const size_t n_aux = 5 * (size_t)ldv + n_part + 2 * (size_t)(m + 1) + 2 + (size_t)m + (size_t)ldh * m +
                          2 * (size_t)m + (size_t)(m + 1) + 2 * (size_t)m + (nch_max > 1 ? (size_t)nch_max * ldv : 0) +
-                         (delayed ? (size_t)ldh * (m + 1) + 2 * (size_t)(m + 1) + 4 + (size_t)ldv : 0);
+                         (size_t)ldh * (m + 1) + 2 * (size_t)(m + 1) + 4 + (size_t)ldv;
     if (hipMalloc(&b.aux, sizeof(double) * n_aux) != hipSuccess) {
         (void)hipGetLastError();
         b.aux = nullptr;
@@ -594,7 +579,7 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
     double* zb = r + ldv;
     double* ub = zb + ldv;
     double* part = ub + ldv;
-    double* hb = part + n_part;  // per iteration: h1 (k), h2 (k), |w| (1)
+    double* hb = part + n_part;  // the first step's projection coefficient
     double* nrm = hb + 2 * (m + 1) + 1;
     double* yd = nrm + 1;
     double* Hd = yd + m;
@@ -605,7 +590,7 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
     double* brkd = resd + m;
     double* part2 = brkd + m;
     double* Hr = part2 + (nch_max > 1 ? (size_t)nch_max * ldv : 0);
-    double* szd = Hr + (delayed ? (size_t)ldh * (m + 1) : 0);
+    double* szd = Hr + (size_t)ldh * (m + 1);
     double* scal = szd + 2 * (m + 1) + 2;
     double* tb = scal + 2;
     // pinned host: the estimates of a batch (R and g of a cycle reserve more later)
@@ -683,8 +668,12 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
         const int j = (int)(jj + 1);
         if ((e = apply_op(ub, tb))) return e;
         const dim3 grid(nrb, (unsigned)((j + kDotJ - 1) / kDotJ));
-        hipLaunchKernelGGL(k_dots2<4>, grid, dim3(256), 0, s, (const double*)b.V, ldv, j, M, (const double*)ub,
-                           (const double*)tb, part, nparts);
+        if (small)
+            hipLaunchKernelGGL(k_dots2<1>, grid, dim3(256), 0, s, (const double*)b.V, ldv, j, M, (const double*)ub,
+                               (const double*)tb, part, nparts);
+        else
+            hipLaunchKernelGGL(k_dots2<4>, grid, dim3(256), 0, s, (const double*)b.V, ldv, j, M, (const double*)ub,
+                               (const double*)tb, part, nparts);
         LB_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_reduce<false>, dim3(lb_blocks(2 * j + 2, 4)), dim3(256), 0, s, (const double*)part,
                            nparts, 2 * j + 2, szd);
@@ -695,43 +684,12 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
         hipLaunchKernelGGL(k_dcgs2_next, dim3(lb_blocks(j + 1, 4)), dim3(256), 0, s, j, (const double*)szd, Hr, ldr,
                            (const double*)scal);
         LB_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_dcgs2_upd<4>, dim3(nrb), dim3(256), 0, s, b.V, ldv, j, M, (const double*)szd,
-                           (const double*)scal, ub, (const double*)tb);
-        LB_CHECK_LAUNCH();
-        return LB_OK;
-    };
-    // one Arnoldi step j: V_{j+1} and column j of H, rotated, on the device
-    auto arnoldi = [&](int64_t j) -> int {
-        if (delayed) return arnoldi_delayed(j);
-        double* vj = b.V + j * ldv;
-        double* vn = b.V + (j + 1) * ldv;
-        int e;
-        if (pre) {  // right preconditioning: w = Q P^-1 v_j
-            if ((e = lb_impl_secular_apply(c, pre, vj, zb)) || (e = op_apply(op, M, zb, w, s))) return e;
-        } else if ((e = op_apply(op, M, vj, w, s))) {
-            return e;
-        }
-        const int k = (int)(j + 1);
-        double* h1 = hb;
-        double* h2 = hb + k;
-        double* hn = hb + 2 * k;
-        // two passes of classical Gram-Schmidt
-        if ((e = dots(k, w))) return e;
-        hipLaunchKernelGGL(k_reduce<false>, dim3(lb_blocks(k, 4)), dim3(256), 0, s, (const double*)part, nparts, k,
-                           h1);
-        LB_CHECK_LAUNCH();
-        if ((e = update(k, h1, 1.0, w, false))) return e;
-        if ((e = dots(k, w))) return e;
-        hipLaunchKernelGGL(k_reduce<false>, dim3(lb_blocks(k, 4)), dim3(256), 0, s, (const double*)part, nparts, k,
-                           h2);
-        LB_CHECK_LAUNCH();
-        if ((e = update(k, h2, 1.0, w, true))) return e;
-        hipLaunchKernelGGL(k_reduce<true>, dim3(1), dim3(256), 0, s, (const double*)part, nparts, 1, hn);
-        LB_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_divide, dim3(eg), dim3(256), 0, s, M, (const double*)w, (const double*)hn, vn);
-        LB_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, (int)j, (const double*)hb, Hd, ldh, csd, snd, gd, resd,
-                           brkd);
+        if (small)
+            hipLaunchKernelGGL(k_dcgs2_upd<1>, dim3(nrb), dim3(256), 0, s, b.V, ldv, j, M, (const double*)szd,
+                               (const double*)scal, ub, (const double*)tb);
+        else
+            hipLaunchKernelGGL(k_dcgs2_upd<4>, dim3(nrb), dim3(256), 0, s, b.V, ldv, j, M, (const double*)szd,
+                               (const double*)scal, ub, (const double*)tb);
         LB_CHECK_LAUNCH();
         return LB_OK;
     };
@@ -776,7 +734,7 @@ static int gmres(lb_ctx* c, int64_t M, const Op& op, const lb_secular* pre, cons
         while (j < lim && used == 0) {
             const int64_t nb = std::min<int64_t>(kLook, lim - j);
             for (int64_t t = 0; t < nb; ++t)
-                if ((rc = arnoldi(j + t))) return rc;
+                if ((rc = arnoldi_delayed(j + t))) return rc;
             LB_HIP(hipMemcpyAsync(hh, resd + j, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
             LB_HIP(hipMemcpyAsync(hh + kLook, brkd + j, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
             LB_HIP(hipStreamSynchronize(s));
