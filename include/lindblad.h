@@ -87,6 +87,14 @@ int lb_sync(lb_ctx* ctx);
 const char* lb_last_error(void);
 /* Library version, e.g. 100 for 0.1.0. */
 int lb_version(void);
+/* Progress of long calls (lindblad_spectrum): fn(stage, fraction, user) is
+ * called from the calling thread, at most about every two seconds (and when a
+ * stage begins or ends), with the
+ * stage's name ("hessenberg": columns reduced; "qr": eigenvalues found) and
+ * the fraction done in [0, 1]. fn = NULL turns it off (the default). The
+ * callback must not call into the library. */
+typedef void (*lb_progress_fn)(const char* stage, double fraction, void* user);
+int lb_set_progress(lb_ctx* ctx, lb_progress_fn fn, void* user);
 
 /* ------------------------------------------------------------------ */
 /* Basis index generator (Sec. 2, Eqs. (3)-(5))                        */
@@ -345,9 +353,10 @@ int lindblad_steady_state_csr(lb_ctx* ctx, int64_t M, const int64_t* rowptr, con
 /* Spectrum of the generator (Sec. 5, Fig. 5)                         */
 /* ------------------------------------------------------------------ */
 
-/* Largest M accepted by lindblad_spectrum (N = 128): its QR stage runs in one
- * workgroup, whose time grows as M^3. */
-#define LB_SPECTRUM_MAX_M 16383
+/* Largest M accepted by lindblad_spectrum and lb_hessenberg: M^2 < 2^31 (the
+ * one-workgroup solver addresses blocks with 32-bit offsets). N = 200 gives
+ * M = 39999. */
+#define LB_SPECTRUM_MAX_M 46340
 
 /* Reduces the real M x M matrix A (row-major, lda >= M, device) in place to
  * upper Hessenberg form by an orthogonal similarity (Householder reflectors

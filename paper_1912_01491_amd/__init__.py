@@ -88,6 +88,7 @@ def signatures():
         "lb_set_stream": [V, V],
         "lb_sync": [V],
         "lb_version": [],
+        "lb_set_progress": [V, V, V],
         "lb_basis_index": [I, I64, V, V, V],
         "lb_basis_table": [V, I, V],
         "lb_fd_count": [V, I, I, V],
@@ -153,6 +154,9 @@ def _need(t, dtype, name):
         raise ValueError("%s is a lazy conjugate view (its memory is not conjugated); call resolve_conj()" % name)
 
 
+_PROGRESS = ctypes.CFUNCTYPE(None, ctypes.c_char_p, ctypes.c_double, ctypes.c_void_p)
+
+
 class Context:
     """A library context bound to a device and a stream (default: torch's
     current stream on that device)."""
@@ -178,6 +182,17 @@ class Context:
 
     def sync(self):
         _check(load().lb_sync(self._h))
+
+    def set_progress(self, fn=None):
+        """fn(stage: str, fraction: float) is called during long calls (the spectrum),
+        at most about every two seconds; None turns it off."""
+        if fn is None:
+            self._progress = None
+            _check(load().lb_set_progress(self._h, None, None))
+            return
+        cb = _PROGRESS(lambda stage, frac, user: fn(stage.decode(), frac))
+        self._progress = cb  # kept alive while set
+        _check(load().lb_set_progress(self._h, ctypes.cast(cb, ctypes.c_void_p), None))
 
     def close(self):
         if self._h:

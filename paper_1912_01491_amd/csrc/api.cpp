@@ -5,6 +5,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <chrono>
+
 #include "lb_internal.h"
 
 static thread_local char g_err[512] = "";
@@ -85,6 +87,17 @@ int lb_host_reserve(lb_ctx* c, size_t bytes) {
         if (!(p)) return lb_fail(LB_ERR_INVALID_ARG, "null pointer: %s", #p); \
     } while (0)
 
+void lb_report(lb_ctx* c, const char* stage, double fraction) {
+    static thread_local std::chrono::steady_clock::time_point last;
+    static thread_local const char* last_stage = nullptr;
+    if (!c->progress) return;
+    const auto now = std::chrono::steady_clock::now();
+    if (fraction < 1.0 && stage == last_stage && now - last < std::chrono::seconds(2)) return;
+    last = now;
+    last_stage = stage;
+    c->progress(stage, fraction, c->progress_user);
+}
+
 extern "C" {
 
 int lb_version(void) { return 100; }
@@ -120,6 +133,13 @@ int lb_set_stream(lb_ctx* c, void* stream) {
     CHECK_CTX(c);
     LB_HIP(hipStreamSynchronize(c->stream));
     c->stream = (hipStream_t)stream;
+    return LB_OK;
+}
+
+int lb_set_progress(lb_ctx* c, lb_progress_fn fn, void* user) {
+    CHECK_CTX(c);
+    c->progress = fn;
+    c->progress_user = user;
     return LB_OK;
 }
 

@@ -73,7 +73,14 @@ struct lb_ctx {
     bool cache_loaded = false;
     // captured propagate graphs
     std::map<lb_graph_key, struct lb_graph_entry*> graphs;
+    // progress of long calls (lb_set_progress)
+    lb_progress_fn progress = nullptr;
+    void* progress_user = nullptr;
 };
+
+// Calls the context's progress callback when one is set and about two seconds
+// have passed since the last call (always for fraction 1 and for a new stage).
+void lb_report(lb_ctx* c, const char* stage, double fraction);
 
 struct lb_graph_entry;
 void lb_graph_free(lb_graph_entry* g);

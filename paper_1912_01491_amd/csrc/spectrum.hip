@@ -390,7 +390,7 @@ __device__ int qr_eigs(double* H, int64_t ld, int n, double2* lam, QrCtl& C, QrC
         // block), so reflectors are ready after the second phase without a third.
         // Reflectors of consecutive steps alternate between two buffers.
         const int T = kSep * (b - 1) + (u - l);
-        const int ld32 = (int)ld;  // n * ld < 2^31 (n <= 16383)
+        const int ld32 = (int)ld;  // n * ld < 2^31: blocks of at most kSmallBlock rows, ld <= 46340
         if (tid == 0) {
             double x, y, z, beta;
             intro_xyz(H, ld, l, C.s[0], C.t[0], &x, &y, &z);
@@ -946,6 +946,7 @@ int lb_impl_hessenberg(lb_ctx* c, int M, double* A, int64_t lda) {
         hipLaunchKernelGGL(k_hh_update, dim3(lb_blocks(L, 64), lb_blocks(M, 16)), dim3(256), 0, s, A, lda, M, j,
                            (const double*)v, (const double*)p, (const double*)q, (const double*)sc);
         LB_CHECK_LAUNCH();
+        if ((j & 255) == 255) lb_report(c, "hessenberg", (double)(j + 1) / (M - 2));
     }
     return LB_OK;
 }
@@ -1011,7 +1012,9 @@ int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam
             return lb_fail(LB_ERR_DEVICE, "QR iteration: no progress at u=%d", u);
         }
         u = hg->u;
+        lb_report(c, "qr", (double)(M - 1 - u) / M);
     }
+    lb_report(c, "qr", 1.0);
     if (sweeps) *sweeps = n_sweeps + hg->sweeps;
     if (steps) *steps = n_steps + hg->steps;
     if (work) *work = n_work + hg->work;

@@ -139,4 +139,4 @@ def test_spectrum_info_layout_matches_header(tmp_path):
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     S = lb.SpectrumInfo
-    assert got == [ctypes.sizeof(S), S.chain_steps.offset, S.updates.offset, 16383]
+    assert got == [ctypes.sizeof(S), S.chain_steps.offset, S.updates.offset, 46340]

@@ -177,7 +177,7 @@ def test_histogram_bit_exact(lb, ctx, oracle):
 
 def test_spectrum_rejects_bad_arguments(lb, ctx):
     Q = torch.zeros((4, 4), dtype=torch.float64, device="cuda")
-    rc = lb.load().lindblad_spectrum(ctx.handle, 16384, lb._ptr(Q), 16384, lb._ptr(Q), None)
+    rc = lb.load().lindblad_spectrum(ctx.handle, 46341, lb._ptr(Q), 46341, lb._ptr(Q), None)
     assert rc == -1
     rc = lb.load().lindblad_spectrum(ctx.handle, 4, lb._ptr(Q), 3, lb._ptr(Q), None)
     assert rc == -1
