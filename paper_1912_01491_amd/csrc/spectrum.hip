@@ -1012,7 +1012,7 @@ int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam
             return lb_fail(LB_ERR_DEVICE, "QR iteration: no progress at u=%d", u);
         }
         u = hg->u;
-        lb_report(c, "qr", (double)(M - 1 - u) / M);
+        if (u >= 0) lb_report(c, "qr", (double)(M - 1 - u) / M);
     }
     lb_report(c, "qr", 1.0);
     if (sweeps) *sweeps = n_sweeps + hg->sweeps;

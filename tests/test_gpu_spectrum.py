@@ -186,3 +186,21 @@ def test_spectrum_rejects_bad_arguments(lb, ctx):
         lb.lindblad_spectrum_histogram(ctx, lam, 1.0, 1.0, 0.0, 1.0, 4, 4)
     with pytest.raises(lb.LindbladError):
         lb.lindblad_spectrum_histogram(ctx, lam, 0.0, 1.0, 0.0, float("inf"), 4, 4)
+
+
+def test_progress_reports(lb, ctx, oracle):
+    """lb_set_progress: both stages report, fractions stay in [0, 1], the last report is the QR stage done."""
+    H, gamma = wl.random_lindbladian(20, 3)
+    Q, _ = oracle.prepare_dense(H, gamma)
+    seen = []
+    ctx.set_progress(lambda stage, frac: seen.append((stage, frac)))
+    try:
+        gpu_spectrum(lb, ctx, Q)
+    finally:
+        ctx.set_progress(None)
+    assert {s for s, _ in seen} == {"hessenberg", "qr"}
+    assert all(0.0 <= f <= 1.0 for _, f in seen)
+    assert seen[-1] == ("qr", 1.0)
+    n = len(seen)
+    gpu_spectrum(lb, ctx, Q)
+    assert len(seen) == n  # off again
