@@ -26,6 +26,8 @@
 //     cycles; kMaxIts sweeps without one is an error.
 #include "lb_internal.h"
 
+#include <rocblas/rocblas.h>
+
 #include <float.h>
 #include <algorithm>
 #include <math.h>
@@ -40,6 +42,8 @@ constexpr int kMaxIts = 120;                // sweeps without a split before giv
 constexpr int kBatch = 1;                   // row / column pieces per thread with loads in flight together
 constexpr int kChunkRows = 16;              // shortest row chunk of the column pass
 constexpr int kMaxChunks = 256;
+constexpr int kPanel = 32;                  // reflectors per panel of the blocked reduction
+constexpr int kBlockedMin = 1000;           // M from which the reduction is blocked
 
 // ---------------------------------------------------------------------------
 // Stage 1: Hessenberg reduction
@@ -897,6 +901,154 @@ __global__ void k_hist(int64_t n, const double2* lam, double re0, double dx, dou
 
 // Workspace of the reduction, from the start of the context's workspace: v, p, q
 // (M doubles each), tau and s, and the column pass's chunk partials.
+// ---------------------------------------------------------------------------
+// Stage 1, blocked: panels of kPanel reflectors in compact WY form, Q = 1 - V T V^T.
+// Inside a panel only its columns are brought up to date (from the matrix A at the
+// panel's start: col = A e_c - Y V^T e_c, then col -= V T^T V^T col), and Y = A V T
+// grows by one GEMV over A per reflector, y_i = tau_i (A v_i - Y V^T v_i); after the
+// panel the whole trailing matrix takes A - Y V^T from the right and
+// (1 - V T^T V^T) from the left as four GEMMs, and the panel's entries below the
+// subdiagonal are set to exactly zero. The matrix is read once per column instead of
+// three times.
+// ---------------------------------------------------------------------------
+
+// col[r] = A[r][c] - sum_{k<i} Y[k][r] V[k][c]
+__global__ __launch_bounds__(256) void k_bh_col(const double* A, int64_t lda, int M, int c, int i, const double* V,
+                                                const double* Y, double* col) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= M) return;
+    double s = A[(int64_t)r * lda + c];
+    for (int k = 0; k < i; ++k) s -= Y[(int64_t)k * M + r] * V[(int64_t)k * M + c];
+    col[r] = s;
+}
+
+// out[k] = sum_{r >= r0} V[k][r] x[r] for k < gridDim.x (a block per k, fixed order)
+__global__ __launch_bounds__(256) void k_bh_dots(const double* V, int M, int r0, const double* x, double* out) {
+    __shared__ double red[4];
+    const double* vk = V + (int64_t)blockIdx.x * M;
+    double s = 0.0;
+    for (int r = r0 + threadIdx.x; r < M; r += 256) s = fma(vk[r], x[r], s);
+    s = block_sum256(s, red);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// col[r] -= sum_{m<i} V[m][r] z[m], z = T^T w, for rows r > j0
+__global__ __launch_bounds__(256) void k_bh_left(const double* V, int M, int i, int j0, const double* T,
+                                                 const double* w, double* col) {
+    __shared__ double z[kPanel];
+    if (threadIdx.x < i) {
+        double t = 0.0;
+        for (int k = 0; k <= (int)threadIdx.x; ++k) t = fma(T[k + threadIdx.x * kPanel], w[k], t);
+        z[threadIdx.x] = t;
+    }
+    __syncthreads();
+    const int r = j0 + 1 + blockIdx.x * 256 + threadIdx.x;
+    if (r >= M) return;
+    double s = col[r];
+    for (int m = 0; m < i; ++m) s -= V[(int64_t)m * M + r] * z[m];
+    col[r] = s;
+}
+
+// Reflector i of the panel from col[c+1..M-1]: V[i] (zero above row c+1, 1 at c+1), tau, beta.
+__global__ __launch_bounds__(256) void k_bh_house(const double* col, int M, int c, int i, double* V, double* taus,
+                                                  double* betas) {
+    __shared__ double red[4];
+    __shared__ double bc[2];
+    double s = 0.0;
+    for (int r = c + 2 + threadIdx.x; r < M; r += 256) s = fma(col[r], col[r], s);
+    const double sigma = block_sum256(s, red);
+    double* vi = V + (int64_t)i * M;
+    if (threadIdx.x == 0) {
+        const double alpha = col[c + 1];
+        double tau = 0.0, scale = 0.0, beta = alpha;
+        if (sigma > 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+            tau = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        bc[0] = scale;
+        taus[i] = tau;
+        betas[i] = beta;
+        vi[c + 1] = 1.0;
+    }
+    __syncthreads();
+    const double scale = bc[0];
+    for (int r = c + 2 + threadIdx.x; r < M; r += 256) vi[r] = col[r] * scale;
+}
+
+// y[r] = sum_{cc > c} A[r][cc] v[cc]: one wavefront per row
+__global__ __launch_bounds__(256) void k_bh_gemv(const double* A, int64_t lda, int M, int c, const double* v,
+                                                 double* y) {
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= M) return;
+    const double* row = A + (int64_t)r * lda;
+    double s = 0.0;
+    for (int cc = c + 1 + lane; cc < M; cc += 64) s = fma(row[cc], v[cc], s);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) y[r] = s;
+}
+
+// Y[i][r] = tau (y[r] - sum_{k<i} Y[k][r] u[k]); block 0 also writes column i of T:
+// T[m][i] = -tau sum_{m<=k<i} T[m][k] u[k], T[i][i] = tau.
+__global__ __launch_bounds__(256) void k_bh_ycol(int M, int i, const double* y, const double* u, const double* taus,
+                                                 double* Y, double* T) {
+    const double tau = taus[i];
+    if (blockIdx.x == 0 && threadIdx.x <= (unsigned)i) {
+        const int m = threadIdx.x;
+        if (m == i) {
+            T[i + i * kPanel] = tau;
+        } else {
+            double t = 0.0;
+            for (int k = m; k < i; ++k) t = fma(T[m + k * kPanel], u[k], t);
+            T[m + i * kPanel] = -tau * t;
+        }
+    }
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= M) return;
+    double s = y[r];
+    for (int k = 0; k < i; ++k) s -= Y[(int64_t)k * M + r] * u[k];
+    Y[(int64_t)i * M + r] = tau * s;
+}
+
+// Panel columns j0..j0+ib-1: beta on the subdiagonal, exact zeros below it.
+__global__ void k_bh_fix(double* A, int64_t lda, int M, int j0, const double* betas) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    const int c = j0 + blockIdx.y;
+    if (r < c + 1 || r >= M) return;
+    A[(int64_t)r * lda + c] = r == c + 1 ? betas[blockIdx.y] : 0.0;
+}
+
+__global__ void k_bh_zero(double* x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) x[i] = 0.0;
+}
+
+// Workspace of the blocked reduction (from the start of the workspace): the panel's
+// reflectors V, Y = A V T and the two GEMM temporaries (M x kPanel each, column-major
+// with leading dimension M), the current column and the GEMV result (M each), T
+// (kPanel x kPanel, column-major), small vectors (w, u, tau, beta).
+struct BlockedLayout {
+    size_t V, Y, W, W2, col, y, T, w, u, tau, beta, end;
+    explicit BlockedLayout(int M) {
+        const size_t mat = lb_align(sizeof(double) * (size_t)M * kPanel, 256);
+        const size_t vec = lb_align(sizeof(double) * (size_t)M, 256);
+        const size_t sm = lb_align(sizeof(double) * kPanel, 256);
+        V = 0;
+        Y = mat;
+        W = 2 * mat;
+        W2 = 3 * mat;
+        col = 4 * mat;
+        y = col + vec;
+        T = y + vec;
+        w = T + lb_align(sizeof(double) * kPanel * kPanel, 256);
+        u = w + sm;
+        tau = u + sm;
+        beta = tau + sm;
+        end = beta + sm;
+    }
+};
+
 struct HessLayout {
     size_t v, p, q, sc, qp, end;
     explicit HessLayout(int M) {
@@ -906,15 +1058,113 @@ struct HessLayout {
         q = 2 * vec;
         sc = 3 * vec;
         qp = sc + 256;
-        end = lb_align(qp + sizeof(double) * (size_t)kMaxChunks * M, 256);
+        end = std::max(lb_align(qp + sizeof(double) * (size_t)kMaxChunks * M, 256), BlockedLayout(M).end);
     }
 };
+
+}  // namespace
+
+namespace {
+
+int blas_check(rocblas_status st) {
+    return st == rocblas_status_success ? LB_OK : lb_fail(LB_ERR_DEVICE, "rocBLAS call failed (%d)", (int)st);
+}
+
+// The blocked reduction. rocBLAS works column-major: the row-major A is the column-major
+// X = A^T with leading dimension lda, so A[:, j0:] -= Y V^T is X[j0:, :] -= V Y^T, and the
+// left update of A[j0+1:, j0:] is X[j0:, j0+1:] -= (X[j0:, j0+1:] V T) V^T over rows j0+1..
+// of V.
+int hessenberg_blocked(lb_ctx* c, int M, double* A, int64_t lda, rocblas_handle h) {
+    hipStream_t s = c->stream;
+    const BlockedLayout lay(M);
+    char* ws = (char*)c->ws;
+    double* V = (double*)(ws + lay.V);
+    double* Y = (double*)(ws + lay.Y);
+    double* W = (double*)(ws + lay.W);
+    double* W2 = (double*)(ws + lay.W2);
+    double* col = (double*)(ws + lay.col);
+    double* y = (double*)(ws + lay.y);
+    double* T = (double*)(ws + lay.T);
+    double* w = (double*)(ws + lay.w);
+    double* u = (double*)(ws + lay.u);
+    double* taus = (double*)(ws + lay.tau);
+    double* betas = (double*)(ws + lay.beta);
+    const double one = 1.0, mone = -1.0, zero = 0.0;
+    const int ldl = (int)lda;
+    for (int j0 = 0; j0 + 2 < M; j0 += kPanel) {
+        const int ib = std::min(kPanel, M - 2 - j0);
+        hipLaunchKernelGGL(k_bh_zero, dim3(lb_blocks((int64_t)M * kPanel, 256)), dim3(256), 0, s, V,
+                           (int64_t)M * kPanel);
+        LB_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_bh_zero, dim3(lb_blocks(kPanel * kPanel, 256)), dim3(256), 0, s, T,
+                           (int64_t)kPanel * kPanel);
+        LB_CHECK_LAUNCH();
+        for (int i = 0; i < ib; ++i) {
+            const int cc = j0 + i;
+            hipLaunchKernelGGL(k_bh_col, dim3(lb_blocks(M, 256)), dim3(256), 0, s, (const double*)A, lda, M, cc, i,
+                               (const double*)V, (const double*)Y, col);
+            LB_CHECK_LAUNCH();
+            if (i > 0) {
+                hipLaunchKernelGGL(k_bh_dots, dim3(i), dim3(256), 0, s, (const double*)V, M, j0 + 1,
+                                   (const double*)col, w);
+                LB_CHECK_LAUNCH();
+                hipLaunchKernelGGL(k_bh_left, dim3(lb_blocks(M - j0 - 1, 256)), dim3(256), 0, s, (const double*)V, M,
+                                   i, j0, (const double*)T, (const double*)w, col);
+                LB_CHECK_LAUNCH();
+            }
+            hipLaunchKernelGGL(k_bh_house, dim3(1), dim3(256), 0, s, (const double*)col, M, cc, i, V, taus, betas);
+            LB_CHECK_LAUNCH();
+            if (i > 0) {
+                hipLaunchKernelGGL(k_bh_dots, dim3(i), dim3(256), 0, s, (const double*)V, M, cc + 1,
+                                   (const double*)(V + (int64_t)i * M), u);
+                LB_CHECK_LAUNCH();
+            }
+            hipLaunchKernelGGL(k_bh_gemv, dim3(lb_blocks(M, 4)), dim3(256), 0, s, (const double*)A, lda, M, cc,
+                               (const double*)(V + (int64_t)i * M), y);
+            LB_CHECK_LAUNCH();
+            hipLaunchKernelGGL(k_bh_ycol, dim3(lb_blocks(M, 256)), dim3(256), 0, s, M, i, (const double*)y,
+                               (const double*)u, (const double*)taus, Y, T);
+            LB_CHECK_LAUNCH();
+        }
+        int rc;
+        // A[:, j0:] -= Y V^T
+        if ((rc = blas_check(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, M - j0, M, ib,
+                                           &mone, V + j0, M, Y, M, &one, A + j0, ldl))))
+            return rc;
+        // W^T = X[j0:, j0+1:] V[j0+1:], W2^T = W^T T, X[j0:, j0+1:] -= W2^T V[j0+1:]^T
+        double* Xb = A + j0 + (int64_t)(j0 + 1) * lda;
+        if ((rc = blas_check(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, M - j0, ib, M - j0 - 1,
+                                           &one, Xb, ldl, V + j0 + 1, M, &zero, W, M))) ||
+            (rc = blas_check(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, M - j0, ib, ib, &one, W,
+                                           M, T, kPanel, &zero, W2, M))) ||
+            (rc = blas_check(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, M - j0,
+                                           M - j0 - 1, ib, &mone, W2, M, V + j0 + 1, M, &one, Xb, ldl))))
+            return rc;
+        hipLaunchKernelGGL(k_bh_fix, dim3(lb_blocks(M, 256), ib), dim3(256), 0, s, A, lda, M, j0,
+                           (const double*)betas);
+        LB_CHECK_LAUNCH();
+        lb_report(c, "hessenberg", (double)(j0 + ib) / (M - 2));
+    }
+    return LB_OK;
+}
 
 }  // namespace
 
 int lb_impl_hessenberg(lb_ctx* c, int M, double* A, int64_t lda) {
     hipStream_t s = c->stream;
     const HessLayout lay(M);
+    if (M >= kBlockedMin) {
+        int rc = lb_ws_reserve(c, lay.end);
+        if (rc) return rc;
+        rocblas_handle h = nullptr;
+        if (rocblas_create_handle(&h) != rocblas_status_success)
+            return lb_fail(LB_ERR_DEVICE, "rocblas_create_handle failed");
+        rc = blas_check(rocblas_set_stream(h, s));
+        if (!rc) rc = blas_check(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host));
+        if (!rc) rc = hessenberg_blocked(c, M, A, lda, h);
+        (void)rocblas_destroy_handle(h);
+        return rc;
+    }
     const size_t o_v = lay.v, o_p = lay.p, o_q = lay.q, o_sc = lay.sc, o_qp = lay.qp;
     int rc = lb_ws_reserve(c, lay.end);
     if (rc) return rc;
