@@ -8,6 +8,8 @@
 //     sides in one rank-2 update, P A P = A - v w^T - (tau p) v^T with p = A v,
 //     q = A^T v, s = v^T p and w = tau q - tau^2 s v: a row-dot pass (p), a column
 //     pass (q, partial sums per row chunk reduced in fixed order), and the update.
+//     From M = kBlockedMin the reduction is blocked instead (compact WY panels, one
+//     GEMV over the matrix per column, the panel's two-sided update as GEMMs).
 //  2. Francis' implicit double-shift QR iteration on the Hessenberg matrix,
 //     eigenvalues only (updates stay inside the active block). A sweep chases a
 //     chain of b double-shift bulges spaced kSep = 4 rows apart: at that spacing no
