@@ -5,23 +5,27 @@ Workload (default): dense random Lindbladians with N = 200 (M = N^2 - 1 =
 39999): 8 ensemble realizations (seeds 0..7), each with a GUE Hamiltonian and
 a Wishart Kossakowski matrix gamma = N W W^+ / Tr(W W^+) (W complex Ginibre,
 M x M, 25.6 GB in complex128), assembled into Q (12.8 GB, FP64) and K and held
-on the device, then 16 pure initial states per realization propagated by 1000
-classic RK4 steps of dt = 1e-3 in one batched launch sequence.
+on the device, then 16 pure initial states per realization propagated by
+classic RK4 with dt = 1e-3, all 8 x 16 states in one batched launch sequence.
 
-One timed "step" of this script is the whole job: for every realization the
-dense preparation (Q, K from H and gamma, with gamma resident in HBM when its
-timer starts), then the expansion of the 128 initial states, the batched RK4
-integration and the reconstruction of rho(T). gamma matrices are drawn on the
-device before each preparation's timed region (they do not all fit in HBM at
-once next to the 8 resident Q); only the library calls are timed, each
-bracketed by device synchronization.
+One "step" of this script is one batched RK4 step: 4 stage products over the
+8 resident systems (8 x 4 passes over a 12.8 GB Q) advancing 8 x 16 states by
+dt. After the inputs are prepared, --warmup untimed steps run, then exactly
+--steps timed steps in one call, bracketed by device synchronization (and HIP
+events on the library's stream). value = realizations x steps / timed seconds:
+RK4 steps per second of one 16-state block. The whole 1000-step job of the
+configuration runs with --full-job.
 
-value = realizations x RK4 steps / total timed seconds, i.e. RK4 steps per
-second of one 16-state block including its share of the assembly.
+Each realization's assembly (lindblad_prepare with gamma resident in HBM) is
+timed once, before the RK4 steps, and reported as assembly_s_per_realization;
+gamma is drawn on the device outside that timer (the 8 gamma matrices, 205 GB,
+do not fit in HBM next to the 8 resident Q).
 
 The JSON line also carries the roofline of the dominant kernel (the RK4 stage
 GEMM over all 8 systems, timed with HIP events on the stream it runs on) and
-the CPU oracle timed on a bounded sample of the same workload.
+the CPU oracle timed on a bounded sample of the same workload: RK4 steps of a
+16-state block on realization 0's Q, and the assembly of sampled rows of every
+class of realization 0 (all diagonal rows), scaled to the whole Q.
 """
 from __future__ import annotations
 
@@ -79,8 +83,18 @@ def measured_traffic(M, R, B, tile):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1, help="timed passes over the whole job")
-    ap.add_argument("--warmup", type=int, default=0, help="untimed passes over the whole job")
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed steps (default config: batched RK4 steps over all realizations and states)")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed steps before the timed ones")
+    ap.add_argument("--full-job", action="store_true",
+                    help="default config: time the configuration's whole job (--rk4-steps batched RK4 steps, "
+                         "no warmup) instead of --steps")
+    ap.add_argument("--check-psd", action="store_true",
+                    help="default config: Cholesky factorisation of realization 0's gamma (positive definite to "
+                         "FP64 rounding)")
+    ap.add_argument("--cpu-rows", type=int, default=256,
+                    help="default config: sampled S rows (and the J rows of the same pairs) in the oracle's "
+                         "assembly sample")
     ap.add_argument("--N", type=int, default=200)
     ap.add_argument("--realizations", type=int, default=8)
     ap.add_argument("--states", type=int, default=16)
@@ -275,29 +289,69 @@ def serving(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(M: int, B: int, steps: int):
-    """The oracle's RK4 (plain C, OpenMP over rows) on a bounded sample: `steps`
-    RK4 steps of a B-state block at the full M, on a stand-in Q of the same
-    shape (values do not affect its time)."""
+def cpu_baseline(Q0, K0, V0, steps: int, N: int, H0=None, gamma0=None, nrows: int = 64):
+    """The oracle (plain C, OpenMP over rows) on a bounded sample of the default
+    workload, realization 0:
+      * RK4: `steps` RK4 steps of the 16-state block V0 on the host copy Q0 of
+        the realization's Q (the same matrix the GPU integrates);
+      * assembly (when gamma0 is given): Q rows sampled from every class --
+        `nrows` random S rows with the J rows of the same pairs, and all N - 1
+        diagonal rows -- and K, timed per class and scaled by the class sizes
+        to the whole Q; the oracle's fixed cost (its f/d table and K) is timed once
+        with no rows and counted once. The sampled rows and K are compared
+        with the GPU's (Q0, K0, host copies): normwise relative error over the
+        sample.
+    """
     import numpy as np
 
     import oracle
 
     oracle.build()
-    log("cpu baseline: allocating stand-in Q (%.1f GB)" % (8.0 * M * M / 1e9))
-    Q = np.full((M, M), 1e-7)
-    K = np.full(M, 1e-7)
-    V = np.full((B, M), 1e-3)
-    oracle.rk4_dense(Q[:64, :64].copy(), K[:64], V[:, :64], 1e-3, 1)  # load / warm the library
+    M = N * N - 1
+    B = V0.shape[0]
+    oracle.rk4_dense(Q0[:64, :64].copy(), np.zeros(64), V0[:, :64].copy(), 1e-3, 1)  # load / warm the library
     t0 = time.perf_counter()
-    oracle.rk4_dense(Q, K, V, 1e-3, steps)
+    oracle.rk4_dense(Q0, np.zeros(M), V0, 1e-3, steps)
     dt = time.perf_counter() - t0
-    del Q
     rate = steps / dt
-    return {"value": rate, "unit": "RK4 steps/s (16-state block, N=200)", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "%d RK4 steps of a %d-state block at M=%d (full row length) on a stand-in Q of the "
-                      "same shape; assembly not included; %.2f s" % (steps, B, M, dt)}
+    out = {"value": rate, "unit": "RK4 steps/s per 16-state block (N=200)", "cores": oracle.num_threads(),
+           "kind": "oracle",
+           "sample": "%d RK4 steps of a %d-state block on realization 0's Q (M=%d, the full workload's matrix); "
+                     "%.2f s" % (steps, B, M, dt)}
+    if gamma0 is None:
+        return out
+    P = N * (N - 1) // 2
+    g = np.random.default_rng(7)
+    rs = np.sort(g.choice(P, nrows, replace=False))
+    groups = {"pair": np.concatenate([rs, P + rs]), "D": np.arange(2 * P, M)}
+    sizes = {"pair": 2 * P, "D": N - 1}
+    log("cpu baseline: oracle assembly sample (%d S, %d J, %d D rows) at N=%d" % (nrows, nrows, N - 1, N))
+    t = time.perf_counter()
+    _, K_or = oracle.prepare_dense(H0, gamma0, rows=np.arange(0))
+    t_fixed = time.perf_counter() - t
+    est = t_fixed
+    per = {}
+    err_q = 0.0
+    qref = 0.0
+    for cls, rows in groups.items():
+        t = time.perf_counter()
+        Qr, _ = oracle.prepare_dense(H0, gamma0, rows=rows)
+        tc = time.perf_counter() - t
+        per[cls] = tc
+        est += max(tc - t_fixed, 0.0) * sizes[cls] / len(rows)
+        err_q = max(err_q, float(np.abs(Q0[rows] - Qr).max()))
+        qref = max(qref, float(np.abs(Qr).max()))
+        log("cpu baseline: %s rows %.2f s (fixed part %.2f s)" % (cls, tc, t_fixed))
+    err_k = float(np.abs(K0 - K_or).max() / np.abs(K_or).max())
+    out["assembly_s_per_realization"] = est
+    out["assembly_sample"] = (
+        "oracle rows of realization 0: %d random S rows with the %d J rows of the same pairs (%.2f s), all %d "
+        "diagonal rows (%.2f s), each call including the oracle's fixed part (its f/d table and K, %.2f s alone); "
+        "whole Q estimated as fixed + sum over the two classes of (call - fixed) x class size / rows sampled"
+        % (nrows, nrows, per["pair"], N - 1, per["D"], t_fixed))
+    out["assembly_parity"] = {"rows": int(sum(len(r) for r in groups.values())),
+                              "rel_err_Q_rows": err_q / qref, "rel_err_K": err_k}
+    return out
 
 
 def _timed(fn):
@@ -905,19 +959,29 @@ def main():
     if args.config in ("c1", "c2", "c2p", "c3", "c6", "c6s", "c7", "c8"):
         return {"c1": config_c1, "c2": config_c2, "c2p": config_c2p, "c3": config_c3, "c6": config_c6,
                 "c6s": config_c6s, "c7": config_c7, "c8": config_c8}[args.config](args)
+    return config_c4(args)
+
+
+def config_c4(args):
+    """The headline configuration: N = 200 dense random Lindbladians, 8
+    realizations assembled once and held resident, 16 pure states each, one
+    timed step = one batched RK4 step over the 8 x 16 states."""
     import numpy as np
     import torch
 
     import paper_1912_01491_amd as lb
     from paper_1912_01491_amd import workloads as wl
 
-    N, R, B, S, dt = args.N, args.realizations, args.states, args.rk4_steps, args.dt
+    N, R, B, dt = args.N, args.realizations, args.states, args.dt
     M = N * N - 1
     ldq = lb.default_ldq(M)
     prec = lb.FP32 if args.precision == "fp32" else lb.FP64
+    K_steps, W_steps = (args.rk4_steps, 0) if args.full_job else (args.steps, args.warmup)
+    want_cpu = not args.no_cpu_baseline
     dev = torch.device("cuda", 0)
     ctx = lb.Context(0)
-    log("N=%d M=%d realizations=%d states=%d rk4_steps=%d precision=%s" % (N, M, R, B, S, args.precision))
+    log("N=%d M=%d realizations=%d states=%d precision=%s: %d warmup + %d timed batched RK4 steps"
+        % (N, M, R, B, args.precision, W_steps, K_steps))
 
     Hs = [torch.from_numpy(wl.gue_hamiltonian(N, r)).to(dev) for r in range(R)]
     psis = [torch.from_numpy(wl.random_pure_states(N, B, 100 + r)).to(dev) for r in range(R)]
@@ -925,64 +989,74 @@ def main():
     Ks = [torch.empty(M, dtype=torch.float64, device=dev) for _ in range(R)]
     Q32s = [torch.empty((M, ldq), dtype=torch.float32, device=dev) for _ in range(R)] if prec == lb.FP32 else None
 
-    def sync():
+    # assembly: each realization once, gamma resident when the timer starts
+    t_prep, t_prep_ev, t_draw = [], [], []
+    gamma0_host = None
+    psd = None
+    for r in range(R):
+        t = time.perf_counter()
+        gamma = wl.wishart_kossakowski_device(N, 1000 + r, device=dev)
         torch.cuda.synchronize()
-
-    def job():
-        t_prep = []
-        for r in range(R):
-            gamma = wl.wishart_kossakowski_device(N, 1000 + r, device=dev)
-            sync()
-            t0 = time.perf_counter()
-            lb.lindblad_prepare(ctx, Hs[r], gamma, ldq=ldq, Q=Qs[r], K=Ks[r])
-            if Q32s is not None:
-                Q32s[r].copy_(lb.lindblad_q_to_f32(ctx, Qs[r]))
-            sync()
-            t_prep.append(time.perf_counter() - t0)
-            del gamma
-            torch.cuda.empty_cache()
-            log("prepared realization %d in %.2f ms" % (r, 1e3 * t_prep[-1]))
-        sync()
+        t_draw.append(time.perf_counter() - t)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        Vs = [lb.lb_expand_pure(ctx, psis[r]) for r in range(R)]
-        if args.graph:
-            for r in range(R):
-                lb.lindblad_propagate_graph(ctx, Qs[r] if prec == lb.FP64 else None, Ks[r], Vs[r], dt, S,
-                                            precision=prec, Q32=Q32s[r] if Q32s else None)
-        else:
-            lb.lindblad_propagate_batched(ctx, Qs if prec == lb.FP64 else None, Ks, Vs, dt, S, precision=prec,
-                                          Q32s=Q32s)
-        rhos = [lb.lb_reconstruct(ctx, Vs[r], N) for r in range(R)]
-        sync()
-        t_prop = time.perf_counter() - t0
-        log("propagated %d x %d states x %d steps in %.2f s" % (R, B, S, t_prop))
-        return t_prep, t_prop, rhos
+        e0.record()
+        lb.lindblad_prepare(ctx, Hs[r], gamma, ldq=ldq, Q=Qs[r], K=Ks[r])
+        e1.record()
+        torch.cuda.synchronize()
+        t_prep.append(time.perf_counter() - t0)
+        t_prep_ev.append(e0.elapsed_time(e1) * 1e-3)
+        if Q32s is not None:
+            Q32s[r].copy_(lb.lindblad_q_to_f32(ctx, Qs[r]))
+        if r == 0 and args.check_psd:
+            _, info = torch.linalg.cholesky_ex(gamma)
+            torch.cuda.synchronize()
+            psd = {"cholesky_info": int(info.item()), "realization": 0}
+            log("gamma of realization 0: Cholesky info %d (0 = positive definite to FP64 rounding)" % psd["cholesky_info"])
+        if r == 0 and want_cpu:
+            gamma0_host = gamma.cpu().numpy()
+        del gamma
+        torch.cuda.empty_cache()
+        log("realization %d: gamma drawn in %.1f s, prepared in %.2f ms (%.2f ms HIP events)"
+            % (r, t_draw[-1], 1e3 * t_prep[-1], 1e3 * t_prep_ev[-1]))
 
     if args.autotune:
-        V = torch.zeros((B, M), dtype=torch.float64, device=dev)
-        gamma = wl.wishart_kossakowski_device(N, 1000, device=dev)
-        lb.lindblad_prepare(ctx, Hs[0], gamma, ldq=ldq, Q=Qs[0], K=Ks[0])
-        del gamma
         lb.lindblad_autotune(ctx, Qs[0] if prec == lb.FP64 else None, Ks[0], B, precision=prec,
-                             Q32=lb.lindblad_q_to_f32(ctx, Qs[0]) if prec == lb.FP32 else None)
+                             Q32=Q32s[0] if Q32s else None)
         log("autotuned tile: %s" % lb.lindblad_tile_info(ctx, M, B, prec))
+    Vs = [lb.lb_expand_pure(ctx, psis[r]) for r in range(R)]
+    V0_host = Vs[0].cpu().numpy() if want_cpu else None
+    torch.cuda.synchronize()
 
-    for w in range(args.warmup):
-        log("warmup pass %d" % w)
-        job()
-    sync()
-    results = []
-    for k in range(args.steps):
-        log("timed pass %d" % k)
-        results.append(job())
-    t_prep_all = [t for res in results for t in res[0]]
-    t_prop_all = [res[1] for res in results]
-    total = sum(t_prep_all) + sum(t_prop_all)
-    ms_per_step = 1e3 * total / args.steps
-    value = R * S * args.steps / total
+    def run(steps):
+        if steps == 0:
+            return
+        if args.graph:
+            for r in range(R):
+                lb.lindblad_propagate_graph(ctx, Qs[r] if prec == lb.FP64 else None, Ks[r], Vs[r], dt, steps,
+                                            precision=prec, Q32=Q32s[r] if Q32s else None)
+        else:
+            lb.lindblad_propagate_batched(ctx, Qs if prec == lb.FP64 else None, Ks, Vs, dt, steps, precision=prec,
+                                          Q32s=Q32s)
 
-    # checks on rho(T) of the last pass: unit trace, Hermitian, positive
-    rhos = results[-1][2]
+    run(W_steps)
+    torch.cuda.synchronize()
+    log("%d warmup steps done; timing %d batched RK4 steps" % (W_steps, K_steps))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    run(K_steps)
+    e1.record()
+    torch.cuda.synchronize()
+    t_timed = time.perf_counter() - t0
+    t_events = e0.elapsed_time(e1) * 1e-3
+    log("timed: %.3f s wall, %.3f s HIP events, %.2f ms per batched step" % (t_timed, t_events, 1e3 * t_timed / K_steps))
+    value = R * K_steps / t_timed
+
+    # checks on rho(t) after W + K steps: unit trace, Hermitian, positive
+    rhos = [lb.lb_reconstruct(ctx, Vs[r], N) for r in range(R)]
     rho = torch.cat(rhos).cpu().numpy()
     tr_err = float(np.abs(np.einsum("bii->b", rho) - 1).max())
     herm = float(np.abs(rho - rho.conj().transpose(0, 2, 1)).max())
@@ -991,34 +1065,34 @@ def main():
 
     # dominant kernel: RK4 stage GEMM over all R systems, HIP events on its stream
     Vt = [torch.zeros((B, M), dtype=torch.float64, device=dev) for _ in range(R)]
-    iters = 5
-    avg_ms = lb.lindblad_time_stage(ctx, Qs if prec == lb.FP64 else None, Ks, Vt, iters=iters, precision=prec,
+    avg_ms = lb.lindblad_time_stage(ctx, Qs if prec == lb.FP64 else None, Ks, Vt, iters=5, precision=prec,
                                     Q32s=Q32s)
+    del Vt
     qbytes = 8 if prec == lb.FP64 else 4
     alg_bytes = R * M * M * qbytes
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     tile = lb.lindblad_tile_info(ctx, M, B, prec)
     log("stage GEMM: %.3f ms per launch over %d systems -> %.0f GB/s" % (avg_ms, R, achieved))
 
-    t_prep_mean = sum(t_prep_all) / len(t_prep_all)
+    t_prep_mean = sum(t_prep) / len(t_prep)
     asm_bytes = 16.0 * M * M  # independent reals of gamma + Q, 8 bytes each
     out = {
         "metric": METRIC,
         "value": value,
-        "unit": "RK4 steps/s (one 16-state block at N=200, assembly included)",
+        "unit": "RK4 steps/s per 16-state block (N=200; %d blocks advanced per batched step)" % R,
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "steps": K_steps,
+        "warmup": W_steps,
+        "ms_per_step": 1e3 * t_timed / K_steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if prec == lb.FP64 else "f32-mfma/f64",
         "data": "synthetic",
         "config": {
-            "workload": "dense random Lindbladian N=%d (M=%d), %d realizations x %d pure states, "
-                        "%d RK4 steps dt=%g" % (N, M, R, B, S, dt),
-            "N": N, "M": M, "realizations": R, "states": B, "rk4_steps": S, "dt": dt,
+            "workload": "dense random Lindbladian N=%d (M=%d), %d realizations x %d pure states resident, "
+                        "one step = one batched RK4 step (dt=%g) over all of them" % (N, M, R, B, dt),
+            "N": N, "M": M, "realizations": R, "states": B, "dt": dt, "full_job": bool(args.full_job),
             "precision": args.precision, "ldq": ldq, "graph": bool(args.graph), "tile": tile,
         },
         "roofline": {
@@ -1033,15 +1107,21 @@ def main():
             "avg_ms": avg_ms,
             "bytes_per_launch": alg_bytes,
         },
+        "timed_s_hip_events": t_events,
         "assembly_s_per_realization": t_prep_mean,
+        "assembly_s_hip_events": sum(t_prep_ev) / len(t_prep_ev),
+        "assembly_s_all": t_prep,
         "assembly_gbs": asm_bytes / t_prep_mean / 1e9,
-        "rk4_steps_per_s": R * S * args.steps / sum(t_prop_all),
-        "solves_per_s": R * B * args.steps / total,
+        "assembly_frac_hbm": asm_bytes / t_prep_mean / 1e9 / HBM_PEAK_GBS,
+        "gamma_draw_s": sum(t_draw) / len(t_draw),
+        "solves_per_s": R * B / (t_prep_mean * R + t_timed / K_steps * args.rk4_steps),
         "checks": {"max_abs_trace_err": tr_err, "max_herm_err": herm, "min_eig_rho": mineig,
-                   "K_finite": finite},
+                   "K_finite": finite, "gamma_psd": psd},
     }
     # the device's read-stream rate, measured after the timed region: the practical ceiling
     # of the HBM-bound stage kernel next to the published peak
+    Q0_host = np.ascontiguousarray(Qs[0].cpu().numpy()[:, :M]) if want_cpu else None
+    K0_host = Ks[0].cpu().numpy() if want_cpu else None
     Qs.clear()
     if Q32s is not None:
         Q32s.clear()
@@ -1050,8 +1130,9 @@ def main():
     out["roofline"]["measured_read_gbs"] = read_gbs
     out["roofline"]["frac_of_measured_read"] = achieved / read_gbs
     log("read-stream probe: %.0f GB/s; stage kernel at %.1f %% of it" % (read_gbs, 100.0 * achieved / read_gbs))
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(M, B, args.cpu_steps)
+    if want_cpu:
+        out["cpu_baseline"] = cpu_baseline(Q0_host, K0_host, V0_host, args.cpu_steps, N,
+                                           H0=Hs[0].cpu().numpy(), gamma0=gamma0_host, nrows=args.cpu_rows)
     ctx.close()
     print(json.dumps(out), flush=True)
 

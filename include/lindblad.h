@@ -54,6 +54,7 @@ extern "C" {
                                       tolerance; the outputs hold the last iterate */
 #define LB_ERR_IO (-8)            /* a file could not be opened, read or written, or is not a valid
                                      saved system (bad header, short, payload hash mismatch) */
+#define LB_ERR_CANCELLED (-9)     /* a serving request was still queued when its server was destroyed */
 
 #define LB_MAX_N 2048             /* largest Hilbert-space dimension accepted (dense inputs of that
                                      size would not fit in memory; the sparse path reaches it) */
@@ -223,7 +224,10 @@ int lindblad_propagate_csr(lb_ctx* ctx, int64_t M, const int64_t* rowptr, const 
  * same t0 and the step offset k0 is bit-identical to the uninterrupted run
  * (every stage time is formed from t0 and the global step index). FP64, B
  * states in V (B*M), in place; errors as lindblad_propagate_csr, plus
- * LB_ERR_INVALID_ARG for a non-finite t0, E, A, T <= 0 or k0 < 0. */
+ * LB_ERR_INVALID_ARG for a non-finite t0, E, A, T <= 0 or k0 < 0, and (when
+ * steps > 0) unless every switch lies on the step grid: T/(2 dt) and t0/dt
+ * must be integers within a relative 1e-9, so no step straddles a switch and
+ * the result does not depend on how a stage at a switch would be evaluated. */
 int lindblad_propagate_csr_drive(lb_ctx* ctx, int64_t M, const int64_t* rowptr0, const int64_t* col0,
                                  const double* val0, const int64_t* rowptr1, const int64_t* col1,
                                  const double* val1, const double* K, double* V, int B, double dt,
@@ -495,7 +499,10 @@ typedef struct lb_server lb_server;
 int lindblad_server_create(int device, size_t hbm_budget_bytes, int max_slots, int max_batch, int max_N,
                            lb_server** srv);
 /* Queues a request (thread-safe; copies the descriptor, not the data).
- * LB_ERR_ADMISSION if its footprint can never fit in the budget. */
+ * LB_ERR_ADMISSION if its footprint cannot fit in the budget next to the
+ * registered systems. A queued request that a later registration has left
+ * without room is failed with LB_ERR_ADMISSION (lindblad_server_wait
+ * returns it) instead of blocking the requests behind it. */
 int lindblad_server_submit(lb_server* srv, const lb_request* req, int64_t* ticket);
 /* Resident systems: many initial states integrated on the same Lindbladian
  * (an ensemble of initial conditions). Prepares Q and K of the Lindbladian in
@@ -508,7 +515,8 @@ int lindblad_server_submit(lb_server* srv, const lb_request* req, int64_t* ticke
  * always run the 16-state matrix-core path, sparse ones the CSR kernel, whose
  * per-state arithmetic does not depend on the other states).
  * LB_ERR_ADMISSION when the system cannot fit in the budget next to the
- * systems already registered (it waits while running requests hold memory). */
+ * systems already registered and the largest queued request (it waits while
+ * running requests hold memory). */
 int lindblad_server_register(lb_server* srv, const lb_request* req, int64_t* system);
 /* Releases a registered system; its memory is freed once no queued or
  * running request uses it. Further requests on it fail with LB_ERR_INVALID_ARG. */
@@ -522,7 +530,10 @@ int lindblad_server_times(lb_server* srv, int64_t ticket, double* t_submit, doub
 /* Completed requests, peak budget use (bytes), batches run, requests that ran in batches of > 1. */
 int lindblad_server_stats(lb_server* srv, int64_t* completed, size_t* peak_bytes, int64_t* batches,
                           int64_t* batched_requests);
-/* Waits for every submitted request, then releases the server. */
+/* Cancels the requests still queued (their status becomes LB_ERR_CANCELLED),
+ * waits for the running ones, frees the registered systems and releases the
+ * server. No other call on the server may run concurrently with it, and its
+ * tickets are invalid afterwards. */
 int lindblad_server_destroy(lb_server* srv);
 
 #ifdef __cplusplus

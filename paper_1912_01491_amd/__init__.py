@@ -39,7 +39,7 @@ _LIB_PATH = os.path.join(_HERE, "_build", "liblindblad.so")
 _lib = None
 
 _ERRORS = {-1: "invalid argument", -2: "not Hermitian", -3: "out of memory", -4: "device error",
-           -5: "unsupported", -6: "admission", -7: "no convergence", -8: "i/o"}
+           -5: "unsupported", -6: "admission", -7: "no convergence", -8: "i/o", -9: "cancelled"}
 
 
 class LibraryMissing(RuntimeError):

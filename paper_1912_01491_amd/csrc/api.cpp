@@ -340,6 +340,17 @@ int lindblad_propagate_csr_drive(lb_ctx* c, int64_t M, const int64_t* rowptr0, c
     if (!isfinite(dt) || steps < 0) return lb_fail(LB_ERR_INVALID_ARG, "bad dt/steps");
     if (!isfinite(t0) || !isfinite(E) || !isfinite(A) || !(T > 0) || !isfinite(T) || k0 < 0)
         return lb_fail(LB_ERR_INVALID_ARG, "drive needs finite t0, E, A, a period T > 0 and k0 >= 0");
+    if (steps > 0) {
+        // the drive switches at every multiple of T/2; each must fall on the step
+        // grid t0 + k dt, so that every RK4 step integrates one constant system
+        const double h = 0.5 * T / dt, ph = t0 / dt;
+        const double rh = nearbyint(h), rph = nearbyint(ph);
+        if (!(dt != 0) || !isfinite(h) || fabs(rh) < 1 || !(fabs(h - rh) <= 1e-9 * fabs(h)) ||
+            !(fabs(ph - rph) <= 1e-9 * fmax(1.0, fabs(ph))))
+            return lb_fail(LB_ERR_INVALID_ARG,
+                           "the drive's switches (multiples of T/2) must fall on the step grid t0 + k dt: "
+                           "T/(2 dt) = %.17g and t0/dt = %.17g must be integers (relative tolerance 1e-9)", h, ph);
+    }
     return lb_impl_propagate_csr_drive(c, M, rowptr0, col0, val0, rowptr1, col1, val1, K, V, B, dt, steps, t0, k0, E,
                                        A, T);
 }

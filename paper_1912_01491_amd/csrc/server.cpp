@@ -2,13 +2,15 @@
 // memory footprint, keeps each request's Q and K resident while it runs, and
 // batches propagations of same-shape requests.
 //
-// Structure:
+// Structure (the queue, admission and worker threads are the device-free
+// scheduling core in serve_sched.h; this file is its device side and the C API):
 //   * a FIFO of submitted requests (thread-safe submit from any thread);
 //   * `slots` worker threads, each with its own HIP stream and library
 //     context (workspace pre-sized for the largest N at creation);
 //   * admission: a free slot takes the queue head if its footprint fits in the
 //     remaining budget (head-of-line order is kept: a head that does not fit
-//     waits for memory to be released), then also takes up to max_batch-1
+//     waits for memory to be released; one that can never fit next to the
+//     registered systems is failed), then also takes up to max_batch-1
 //     further queued dense requests with the same (N, B, dt, steps,
 //     precision) that fit, and runs them as one batch: one preparation per
 //     request, then a single batched RK4 integration (one launch per stage for
@@ -35,44 +37,16 @@
 #include <string.h>
 
 #include <algorithm>
-#include <chrono>
-#include <condition_variable>
-#include <deque>
-#include <map>
 #include <mutex>
-#include <thread>
 #include <vector>
 
 #include "lb_internal.h"
+#include "serve_sched.h"
+
+using lb_sched::System;
+using lb_sched::Ticket;
 
 namespace {
-
-double now_s() {
-    using namespace std::chrono;
-    return duration_cast<duration<double>>(steady_clock::now().time_since_epoch()).count();
-}
-
-struct System {
-    int64_t id = 0;
-    int kind = LB_REQ_DENSE;
-    int N = 0, precision = LB_FP64;
-    int64_t M = 0, ldq = 0, nnz = 0;
-    void *Q = nullptr, *Q32 = nullptr, *K = nullptr;  // dense
-    void *rp = nullptr, *col = nullptr, *val = nullptr;  // sparse (K shared)
-    size_t bytes = 0;
-    int refs = 0;  // queued or running requests
-    bool released = false;
-};
-
-struct Ticket {
-    lb_request req;
-    int64_t id = 0;
-    size_t footprint = 0;
-    System* sys = nullptr;
-    int status = 1;  // 1 = pending, 0 = ok, < 0 = error
-    bool done = false;
-    double t_submit = 0, t_start = 0, t_end = 0;
-};
 
 void system_free(System* y) {
     void* ps[] = {y->Q, y->Q32, y->K, y->rp, y->col, y->val};
@@ -83,27 +57,27 @@ void system_free(System* y) {
 
 }  // namespace
 
+struct lb_server;
+
+// The device side of the serving loop: one library context and stream per
+// slot; the scheduling core calls run() on the slot's worker thread.
+struct ServerExec : lb_sched::Executor {
+    lb_server* s = nullptr;
+    void thread_init(int slot) override;
+    int run(int slot, std::vector<Ticket*>& batch) override;
+    void free_system(System* y) override { system_free(y); }
+};
+
 struct lb_server {
     int device = 0;
-    size_t budget = 0, used = 0, peak = 0;
+    size_t budget = 0;
     int max_batch = 1;
     int max_N = 0;
-    std::mutex mu;
-    std::condition_variable cv_work;  // slots wait for admissible work
-    std::condition_variable cv_done;  // waiters wait for completions
-    std::deque<Ticket*> queue;
-    std::map<int64_t, Ticket*> tickets;
-    int64_t next_id = 1;
-    int64_t completed = 0, batches = 0, batched_requests = 0;
-    bool stop = false;
-    std::vector<std::thread> workers;
+    lb_sched::Core* core = nullptr;
+    ServerExec exec;
     std::vector<lb_ctx*> ctxs;
     std::vector<hipStream_t> streams;
-    // resident systems
-    std::map<int64_t, System*> systems;
-    int64_t next_system = 1;
-    size_t registered = 0;          // bytes held by registered systems
-    std::mutex reg_mu;              // serializes registrations (one context)
+    std::mutex reg_mu;  // serializes registrations (one context)
     lb_ctx* reg_ctx = nullptr;
     hipStream_t reg_stream = nullptr;
 };
@@ -127,21 +101,6 @@ static size_t sparse_q_bytes(int N) {
 // Staging of a system batch's states: input and output blocks of up to
 // LB_SYSTEM_BATCH states.
 static size_t system_stage_bytes(int64_t M) { return sizeof(double) * 2 * (size_t)LB_SYSTEM_BATCH * M; }
-
-static size_t footprint(const lb_request& r, const System* y) {
-    if (r.kind == LB_REQ_SYSTEM) return system_stage_bytes(y->M);
-    return r.kind == LB_REQ_DENSE ? dense_q_bytes(r.N, r.precision) : sparse_q_bytes(r.N);
-}
-
-static bool same_shape(const lb_request& a, const lb_request& b) {
-    return a.kind == LB_REQ_DENSE && b.kind == LB_REQ_DENSE && a.N == b.N && a.B == b.B && a.dt == b.dt &&
-           a.steps == b.steps && a.precision == b.precision;
-}
-
-static bool same_system_pass(const lb_request& a, const lb_request& b) {
-    return a.kind == LB_REQ_SYSTEM && b.kind == LB_REQ_SYSTEM && a.system == b.system && a.dt == b.dt &&
-           a.steps == b.steps && a.precision == b.precision;
-}
 
 // One pass over a registered system for the states of every request in `batch`.
 static int run_system_batch(lb_server* s, int slot, std::vector<Ticket*>& batch) {
@@ -253,80 +212,24 @@ static int run_batch(lb_server* s, int slot, std::vector<Ticket*>& batch) {
     return rc;
 }
 
-static void worker(lb_server* s, int slot) {
+void ServerExec::thread_init(int slot) {
+    (void)slot;
     (void)hipSetDevice(s->device);
-    for (;;) {
-        std::vector<Ticket*> batch;
-        {
-            std::unique_lock<std::mutex> lk(s->mu);
-            for (;;) {
-                if (!s->queue.empty()) {
-                    Ticket* h = s->queue.front();
-                    if (s->used + h->footprint <= s->budget) break;
-                }
-                if (s->stop && s->queue.empty()) return;
-                s->cv_work.wait(lk);
-            }
-            Ticket* h = s->queue.front();
-            s->queue.pop_front();
-            s->used += h->footprint;
-            batch.push_back(h);
-            if (h->req.kind == LB_REQ_SYSTEM) {
-                int states = h->req.B;
-                for (auto it = s->queue.begin(); it != s->queue.end() && (int)batch.size() < s->max_batch;) {
-                    Ticket* t = *it;
-                    if (same_system_pass(h->req, t->req) && states + t->req.B <= LB_SYSTEM_BATCH &&
-                        s->used + t->footprint <= s->budget) {
-                        s->used += t->footprint;
-                        states += t->req.B;
-                        batch.push_back(t);
-                        it = s->queue.erase(it);
-                    } else {
-                        ++it;
-                    }
-                }
-            } else if (h->req.kind == LB_REQ_DENSE) {
-                for (auto it = s->queue.begin(); it != s->queue.end() && (int)batch.size() < s->max_batch;) {
-                    Ticket* t = *it;
-                    if (same_shape(h->req, t->req) && s->used + t->footprint <= s->budget) {
-                        s->used += t->footprint;
-                        batch.push_back(t);
-                        it = s->queue.erase(it);
-                    } else {
-                        ++it;
-                    }
-                }
-            }
-            if (s->used > s->peak) s->peak = s->used;
-            const double t0 = now_s();
-            for (Ticket* t : batch) t->t_start = t0;
-            s->batches += 1;
-            if (batch.size() > 1) s->batched_requests += (int64_t)batch.size();
-        }
-        const int rc = run_batch(s, slot, batch);
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            const double t1 = now_s();
-            for (Ticket* t : batch) {
-                t->status = rc;
-                t->done = true;
-                t->t_end = t1;
-                s->used -= t->footprint;
-                s->completed += 1;
-                if (System* y = t->sys) {
-                    if (--y->refs == 0 && y->released) {
-                        s->used -= y->bytes;
-                        s->registered -= y->bytes;
-                        s->systems.erase(y->id);
-                        system_free(y);
-                    }
-                }
-            }
-        }
-        s->cv_done.notify_all();
-        s->cv_work.notify_all();
-    }
 }
+
+int ServerExec::run(int slot, std::vector<Ticket*>& batch) { return run_batch(s, slot, batch); }
+
+static void server_free(lb_server* s) {
+    for (size_t k = 0; k < s->ctxs.size(); ++k) {
+        lb_destroy(s->ctxs[k]);
+        (void)hipStreamDestroy(s->streams[k]);
+    }
+    if (s->reg_ctx) lb_destroy(s->reg_ctx);
+    if (s->reg_stream) (void)hipStreamDestroy(s->reg_stream);
+    delete s;
+}
+
+static int sched_fail(int rc, const char* why) { return rc ? lb_fail(rc, "%s", why ? why : "serving error") : rc; }
 
 extern "C" {
 
@@ -338,16 +241,14 @@ int lindblad_server_create(int device, size_t hbm_budget_bytes, int max_slots, i
     if (max_batch < 1 || max_batch > 64) return lb_fail(LB_ERR_INVALID_ARG, "max_batch must be in [1, 64]");
     if (max_N < 2 || max_N > LB_MAX_N) return lb_fail(LB_ERR_INVALID_ARG, "max_N out of range");
     if (hbm_budget_bytes == 0) return lb_fail(LB_ERR_INVALID_ARG, "zero budget");
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return lb_fail(LB_ERR_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
     lb_server* s = new lb_server();
     s->device = device;
     s->budget = hbm_budget_bytes;
     s->max_batch = max_batch;
     s->max_N = max_N;
-    hipError_t e = hipSetDevice(device);
-    if (e != hipSuccess) {
-        delete s;
-        return lb_fail(LB_ERR_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
-    }
+    s->exec.s = s;
     // keep released pool memory cached so that per-request allocations are cheap
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
@@ -361,11 +262,7 @@ int lindblad_server_create(int device, size_t hbm_budget_bytes, int max_slots, i
         int rc = e == hipSuccess ? lb_create(&c, device, st) : LB_ERR_DEVICE;
         if (rc) {
             if (e == hipSuccess) (void)hipStreamDestroy(st);
-            for (size_t k = 0; k < s->ctxs.size(); ++k) {
-                lb_destroy(s->ctxs[k]);
-                (void)hipStreamDestroy(s->streams[k]);
-            }
-            delete s;
+            server_free(s);
             return lb_fail(LB_ERR_DEVICE, "slot %d creation failed", i);
         }
         s->streams.push_back(st);
@@ -383,58 +280,25 @@ int lindblad_server_create(int device, size_t hbm_budget_bytes, int max_slots, i
         for (auto* c : s->ctxs) (void)lb_ws_reserve(c, want);
     }
     e = hipStreamCreateWithFlags(&s->reg_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) s->reg_stream = nullptr;
     if (e != hipSuccess || lb_create(&s->reg_ctx, device, s->reg_stream) != LB_OK) {
-        if (e == hipSuccess) (void)hipStreamDestroy(s->reg_stream);
-        for (size_t k = 0; k < s->ctxs.size(); ++k) {
-            lb_destroy(s->ctxs[k]);
-            (void)hipStreamDestroy(s->streams[k]);
-        }
-        delete s;
+        server_free(s);
         return lb_fail(LB_ERR_DEVICE, "registration context creation failed");
     }
-    for (int i = 0; i < max_slots; ++i) s->workers.emplace_back(worker, s, i);
+    s->core = new lb_sched::Core(hbm_budget_bytes, max_batch);
+    s->core->start(max_slots, &s->exec);
     *out = s;
-    return LB_OK;
-}
-
-static int submit_system(lb_server* s, const lb_request* r, int64_t* ticket) {
-    if (!r->V0 || !r->Vout || r->B < 1 || r->B > LB_SYSTEM_BATCH || r->steps < 0 || !(r->dt == r->dt))
-        return lb_fail(LB_ERR_INVALID_ARG, "bad states (1 <= B <= %d) / steps / dt", LB_SYSTEM_BATCH);
-    Ticket* t = new Ticket();
-    t->req = *r;
-    t->t_submit = now_s();
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        auto it = s->systems.find(r->system);
-        if (it == s->systems.end() || it->second->released) {
-            delete t;
-            return lb_fail(LB_ERR_INVALID_ARG, "unknown or released system %lld", (long long)r->system);
-        }
-        System* y = it->second;
-        if (r->precision != LB_FP64 && !(r->precision == LB_FP32 && y->Q32)) {
-            delete t;
-            return lb_fail(LB_ERR_INVALID_ARG, "system %lld has no FP32 copy", (long long)r->system);
-        }
-        t->sys = y;
-        t->req.N = y->N;
-        t->footprint = footprint(t->req, y);
-        if (t->footprint + s->registered > s->budget) {
-            delete t;
-            return lb_fail(LB_ERR_ADMISSION, "no budget left for the states of a request");
-        }
-        y->refs += 1;
-        t->id = s->next_id++;
-        s->tickets[t->id] = t;
-        s->queue.push_back(t);
-    }
-    *ticket = t->id;
-    s->cv_work.notify_all();
     return LB_OK;
 }
 
 int lindblad_server_submit(lb_server* s, const lb_request* r, int64_t* ticket) {
     if (!s || !r || !ticket) return lb_fail(LB_ERR_INVALID_ARG, "null argument");
-    if (r->kind == LB_REQ_SYSTEM) return submit_system(s, r, ticket);
+    const char* why = nullptr;
+    if (r->kind == LB_REQ_SYSTEM) {
+        if (!r->V0 || !r->Vout || r->B < 1 || r->B > LB_SYSTEM_BATCH || r->steps < 0 || !(r->dt == r->dt))
+            return lb_fail(LB_ERR_INVALID_ARG, "bad states (1 <= B <= %d) / steps / dt", LB_SYSTEM_BATCH);
+        return sched_fail(s->core->submit_system(*r, ticket, &why), why);
+    }
     if (r->N < 2 || r->N > s->max_N) return lb_fail(LB_ERR_INVALID_ARG, "N=%d outside [2, %d]", r->N, s->max_N);
     if (r->kind != LB_REQ_DENSE && r->kind != LB_REQ_SPARSE) return lb_fail(LB_ERR_INVALID_ARG, "unknown kind");
     if (!r->V0 || !r->Vout || r->B < 1 || r->B > 64 || r->steps < 0 || !(r->dt == r->dt))
@@ -444,22 +308,8 @@ int lindblad_server_submit(lb_server* s, const lb_request* r, int64_t* ticket) {
         return lb_fail(LB_ERR_INVALID_ARG, "unknown precision");
     if (r->kind == LB_REQ_SPARSE && (r->P < 0 || r->P > LB_REQ_MAX_JUMPS || !r->Hs.rowptr))
         return lb_fail(LB_ERR_INVALID_ARG, "sparse request needs H and at most %d jump operators", LB_REQ_MAX_JUMPS);
-    const size_t fp = footprint(*r, nullptr);
-    if (fp > s->budget)
-        return lb_fail(LB_ERR_ADMISSION, "request footprint %zu bytes exceeds the server budget %zu", fp, s->budget);
-    Ticket* t = new Ticket();
-    t->req = *r;
-    t->footprint = fp;
-    t->t_submit = now_s();
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        t->id = s->next_id++;
-        s->tickets[t->id] = t;
-        s->queue.push_back(t);
-    }
-    *ticket = t->id;
-    s->cv_work.notify_all();
-    return LB_OK;
+    const size_t fp = r->kind == LB_REQ_DENSE ? dense_q_bytes(r->N, r->precision) : sparse_q_bytes(r->N);
+    return sched_fail(s->core->submit(*r, fp, ticket, &why), why);
 }
 
 int lindblad_server_register(lb_server* s, const lb_request* r, int64_t* system) {
@@ -484,6 +334,7 @@ int lindblad_server_register(lb_server* s, const lb_request* r, int64_t* system)
     y->N = r->N;
     y->precision = r->kind == LB_REQ_DENSE ? r->precision : LB_FP64;
     y->M = (int64_t)r->N * r->N - 1;
+    y->stage_bytes = system_stage_bytes(y->M);
     const int64_t M = y->M;
     // footprint: dense from the shape; sparse after the count phase
     if (r->kind == LB_REQ_DENSE) {
@@ -499,17 +350,11 @@ int lindblad_server_register(lb_server* s, const lb_request* r, int64_t* system)
         y->bytes = sizeof(int64_t) * (M + 1) + (sizeof(int64_t) + sizeof(double)) * (size_t)std::max<int64_t>(y->nnz, 1) +
                    sizeof(double) * M;
     }
-    {
-        std::unique_lock<std::mutex> lk(s->mu);
-        if (s->registered + y->bytes > s->budget) {
-            delete y;
-            return lb_fail(LB_ERR_ADMISSION, "system of %zu bytes does not fit next to %zu registered bytes (budget %zu)",
-                           y->bytes, s->registered, s->budget);
-        }
-        s->cv_done.wait(lk, [&] { return s->used + y->bytes <= s->budget; });
-        s->used += y->bytes;
-        s->registered += y->bytes;
-        if (s->used > s->peak) s->peak = s->used;
+    const char* why = nullptr;
+    rc = s->core->reserve_system(y->bytes, &why);
+    if (rc) {
+        delete y;
+        return sched_fail(rc, why);
     }
     auto dalloc = [&](size_t bytes, void** p) -> int {
         if (hipMalloc(p, bytes) != hipSuccess) {
@@ -536,99 +381,59 @@ int lindblad_server_register(lb_server* s, const lb_request* r, int64_t* system)
     }
     hipError_t e = hipStreamSynchronize(st);
     if (!rc && e != hipSuccess) rc = lb_fail(LB_ERR_DEVICE, "registration stream: %s", hipGetErrorString(e));
-    std::lock_guard<std::mutex> lk(s->mu);
     if (rc) {
-        s->used -= y->bytes;
-        s->registered -= y->bytes;
+        const size_t bytes = y->bytes;
         system_free(y);
-        s->cv_work.notify_all();
+        s->core->cancel_reservation(bytes);
         return rc;
     }
-    y->id = s->next_system++;
-    s->systems[y->id] = y;
-    *system = y->id;
+    *system = s->core->commit_system(y);
     return LB_OK;
 }
 
 int lindblad_server_release(lb_server* s, int64_t system) {
     if (!s) return lb_fail(LB_ERR_INVALID_ARG, "null server");
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        auto it = s->systems.find(system);
-        if (it == s->systems.end() || it->second->released)
-            return lb_fail(LB_ERR_INVALID_ARG, "unknown or released system %lld", (long long)system);
-        System* y = it->second;
-        y->released = true;
-        if (y->refs == 0) {
-            s->used -= y->bytes;
-            s->registered -= y->bytes;
-            s->systems.erase(it);
-            system_free(y);
-        }
-    }
-    s->cv_work.notify_all();
-    s->cv_done.notify_all();
-    return LB_OK;
+    const char* why = nullptr;
+    const int rc = s->core->release(system, &why);
+    return rc ? lb_fail(rc, "%s %lld", why, (long long)system) : LB_OK;
 }
 
 int lindblad_server_poll(lb_server* s, int64_t ticket, int* done) {
     if (!s || !done) return lb_fail(LB_ERR_INVALID_ARG, "null argument");
-    std::lock_guard<std::mutex> lk(s->mu);
-    auto it = s->tickets.find(ticket);
-    if (it == s->tickets.end()) return lb_fail(LB_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
-    *done = it->second->done ? 1 : 0;
+    if (s->core->poll(ticket, done)) return lb_fail(LB_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
     return LB_OK;
 }
 
 int lindblad_server_wait(lb_server* s, int64_t ticket) {
     if (!s) return lb_fail(LB_ERR_INVALID_ARG, "null server");
-    std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->tickets.find(ticket);
-    if (it == s->tickets.end()) return lb_fail(LB_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
-    Ticket* t = it->second;
-    s->cv_done.wait(lk, [&] { return t->done; });
-    return t->status;
+    bool known = false;
+    const int rc = s->core->wait(ticket, &known);
+    if (!known) return lb_fail(LB_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
+    if (rc == LB_ERR_ADMISSION) return lb_fail(rc, "request %lld can no longer fit next to the registered systems",
+                                               (long long)ticket);
+    if (rc == LB_ERR_CANCELLED) return lb_fail(rc, "request %lld was cancelled", (long long)ticket);
+    return rc;
 }
 
 int lindblad_server_times(lb_server* s, int64_t ticket, double* t_submit, double* t_start, double* t_end) {
     if (!s) return lb_fail(LB_ERR_INVALID_ARG, "null server");
-    std::lock_guard<std::mutex> lk(s->mu);
-    auto it = s->tickets.find(ticket);
-    if (it == s->tickets.end()) return lb_fail(LB_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
-    if (t_submit) *t_submit = it->second->t_submit;
-    if (t_start) *t_start = it->second->t_start;
-    if (t_end) *t_end = it->second->t_end;
+    if (s->core->times(ticket, t_submit, t_start, t_end))
+        return lb_fail(LB_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
     return LB_OK;
 }
 
 int lindblad_server_stats(lb_server* s, int64_t* completed, size_t* peak_bytes, int64_t* batches,
                           int64_t* batched_requests) {
     if (!s) return lb_fail(LB_ERR_INVALID_ARG, "null server");
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (completed) *completed = s->completed;
-    if (peak_bytes) *peak_bytes = s->peak;
-    if (batches) *batches = s->batches;
-    if (batched_requests) *batched_requests = s->batched_requests;
+    s->core->stats(completed, peak_bytes, batches, batched_requests);
     return LB_OK;
 }
 
 int lindblad_server_destroy(lb_server* s) {
     if (!s) return LB_OK;
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->stop = true;
-    }
-    s->cv_work.notify_all();
-    for (auto& w : s->workers) w.join();
-    for (size_t k = 0; k < s->ctxs.size(); ++k) {
-        lb_destroy(s->ctxs[k]);
-        (void)hipStreamDestroy(s->streams[k]);
-    }
-    lb_destroy(s->reg_ctx);
-    (void)hipStreamDestroy(s->reg_stream);
-    for (auto& kv : s->systems) system_free(kv.second);
-    for (auto& kv : s->tickets) delete kv.second;
-    delete s;
+    s->core->shutdown();
+    delete s->core;
+    server_free(s);
     return LB_OK;
 }
 

@@ -165,30 +165,37 @@ def to_csr(A: np.ndarray):
 def wishart_kossakowski_device(N: int, seed: int, device="cuda", block: int = 4096):
     """gamma = N W W^dagger / Tr(W W^dagger) drawn on the GPU (torch), complex128.
 
-    W is drawn in complex64 and W W^dagger is formed by the vendor GEMM; the
-    product is promoted to complex128 and Hermitized block by block so that
-    gamma is exactly Hermitian. Deterministic for a given seed and device.
+    W is drawn in complex128 and W W^dagger is formed in complex128 by torch's
+    GEMM: input synthesis only, never the library under test, so the oracle's
+    inputs do not come from the path it checks. FP64 keeps gamma positive
+    semidefinite to FP64 rounding: a square complex Ginibre W has eigenvalues of
+    W W^dagger down to about 1/M of its mean, which FP32 rounding would push
+    below zero at N = 200. The product is made exactly Hermitian in place, block
+    by block (X = (A_ij + A_ji^dagger)/2 stored at (i, j) and X^dagger at (j, i)),
+    and scaled by a real factor, which keeps gamma_kj == conj(gamma_jk) bit for
+    bit. Deterministic for a given seed and device.
     """
     import torch
 
     M = N * N - 1
     gen = torch.Generator(device=device)
     gen.manual_seed(int(seed))
-    W = torch.randn(M, M, dtype=torch.complex64, device=device, generator=gen)
+    W = torch.randn(M, M, dtype=torch.complex128, device=device, generator=gen)
     Wh = W.mH.contiguous()  # materialized conjugate transpose as the right operand
     A = W @ Wh
     del W, Wh
-    out = torch.empty(M, M, dtype=torch.complex128, device=device)
     for i0 in range(0, M, block):
         i1 = min(M, i0 + block)
-        top = A[i0:i1, :].to(torch.complex128)
-        left = A[:, i0:i1].mH.to(torch.complex128)
-        out[i0:i1, :] = (top + left) * 0.5
-        del top, left
-    del A
-    tr = out.diagonal().real.sum()
-    out *= (N / tr)
-    return out
+        for j0 in range(i0, M, block):
+            j1 = min(M, j0 + block)
+            X = (A[i0:i1, j0:j1] + A[j0:j1, i0:i1].mH) * 0.5
+            A[i0:i1, j0:j1] = X
+            if j0 != i0:
+                A[j0:j1, i0:i1] = X.mH
+            del X
+    tr = A.diagonal().real.sum()
+    A *= (N / tr)
+    return A
 
 
 def random_dense_device(M: int, ldq: int, seed: int, scale: float = 1.0, device="cuda"):

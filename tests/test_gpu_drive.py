@@ -61,11 +61,13 @@ def initial(oracle, N, B, seed):
     return np.array([oracle.expand(np.outer(p, p.conj())).real for p in psis])
 
 
-@pytest.mark.parametrize("N,B,steps,t0", [(5, 1, 230, 0.0), (9, 3, 130, 0.37), (9, 2, 60, math.pi - 0.5)])
-def test_drive_matches_oracle(lb, ctx, oracle, N, B, steps, t0):
-    """dt = T/200: the switches at T/2 and T fall on step boundaries for t0 = 0."""
-    print("[gpu] rocked dimer N=%d B=%d steps=%d t0=%.3f" % (N, B, steps, t0), flush=True)
+@pytest.mark.parametrize("N,B,steps,k_t0", [(5, 1, 230, 0), (9, 3, 130, 12), (9, 2, 60, 84)])
+def test_drive_matches_oracle(lb, ctx, oracle, N, B, steps, k_t0):
+    """dt = T/200, t0 = k_t0 dt: the switches at multiples of T/2 fall on step
+    boundaries (the start at 84 dt crosses T/2 after 16 steps)."""
     dt = T / 200
+    t0 = k_t0 * dt
+    print("[gpu] rocked dimer N=%d B=%d steps=%d t0=%.3f" % (N, B, steps, t0), flush=True)
     Q0, Q1, K, K1 = gpu_system(lb, ctx, N)
     assert np.abs(K1.cpu().numpy()).max() == 0.0
     Q0o, Q1o, Ko = oracle_system(oracle, N)
@@ -96,10 +98,11 @@ def test_zero_drive_is_the_static_integrator(lb, ctx, oracle):
     N = 9
     Q0, Q1, K, _ = gpu_system(lb, ctx, N)
     V0 = torch.from_numpy(initial(oracle, N, 2, 8)).cuda()
+    dt = T / 5000
     a = V0.clone()
-    lb.lindblad_propagate_csr_drive(ctx, Q0, Q1, K, a, 1e-3, 50, 0.0, 0.0, 0.0, T)
+    lb.lindblad_propagate_csr_drive(ctx, Q0, Q1, K, a, dt, 50, 0.0, 0.0, 0.0, T)
     b = V0.clone()
-    lb.lindblad_propagate_csr(ctx, Q0[0], Q0[1], Q0[2], K, b, 1e-3, 50)
+    lb.lindblad_propagate_csr(ctx, Q0[0], Q0[1], Q0[2], K, b, dt, 50)
     assert torch.equal(a, b)
 
 
@@ -127,3 +130,19 @@ def test_drive_rejects_bad_period(lb, ctx):
     V = torch.zeros((1, N * N - 1), dtype=torch.float64, device="cuda")
     with pytest.raises(lb.LindbladError):
         lb.lindblad_propagate_csr_drive(ctx, Q0, Q1, K, V, 1e-3, 5, 0.0, E, A, 0.0)
+
+
+@pytest.mark.parametrize("dt,t0", [(1e-3, 0.0), (2 * math.pi / 200, 0.37), (2 * math.pi / 199, 0.0)])
+def test_drive_rejects_switches_off_the_step_grid(lb, ctx, dt, t0):
+    """A switch inside a step (T/(2 dt) or t0/dt not an integer) is refused:
+    the paper fixes no way to evaluate RK4 stages across a discontinuity."""
+    N = 5
+    Q0, Q1, K, _ = gpu_system(lb, ctx, N)
+    V = torch.zeros((1, N * N - 1), dtype=torch.float64, device="cuda")
+    before = V.clone()
+    with pytest.raises(lb.LindbladError) as e:
+        lb.lindblad_propagate_csr_drive(ctx, Q0, Q1, K, V, dt, 5, t0, E, A, T)
+    assert e.value.code == -1
+    assert torch.equal(V, before)
+    # zero steps touch nothing and are accepted
+    lb.lindblad_propagate_csr_drive(ctx, Q0, Q1, K, V, dt, 0, t0, E, A, T)
