@@ -200,6 +200,22 @@ int lindblad_prepare_sparse_fill(lb_ctx* ctx, int N, const lb_csr_c128* H, int P
 int lindblad_propagate(lb_ctx* ctx, int64_t M, const double* Q, const float* Q32, int64_t ldq,
                        const double* K, double* V, int B, double dt, int64_t steps, int precision);
 
+/* Allocation-free variant of lindblad_propagate, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation). Same arguments, layout, ownership and
+ * result (the same kernels and tile: bit for bit), but the integration's
+ * buffers live in one static device array of LB_NOALLOC_SCRATCH_BYTES per GPU,
+ * held from module load until the process ends; the call allocates no device
+ * or pinned host memory and does not synchronize. Limit: the buffers must fit
+ * the array -- 2 M doubles of packed states, stage vectors and split-K
+ * partials (one state up to M = 699000; 16 states up to M of about 5000, i.e.
+ * N = 70) -- else LB_ERR_UNSUPPORTED. Every call on a GPU uses that GPU's one array: calls
+ * that overlap on one GPU (other streams or threads) race and must be
+ * serialized by the caller. Other errors as lindblad_propagate. */
+#define LB_NOALLOC_SCRATCH_BYTES (16u << 20)
+int lindblad_propagate_noalloc(lb_ctx* ctx, int64_t M, const double* Q, const float* Q32, int64_t ldq,
+                               const double* K, double* V, int B, double dt, int64_t steps, int precision);
+
 /* Q32[i*ldq + j] = (float)Q[i*ldq + j] for i < M, j < ldq (device buffers). */
 int lindblad_q_to_f32(lb_ctx* ctx, int64_t M, const double* Q, int64_t ldq, float* Q32);
 

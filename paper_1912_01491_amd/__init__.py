@@ -22,7 +22,8 @@ __all__ = [
     "LibraryMissing", "LindbladError", "Context", "library_path", "load",
     "lb_basis_index", "lb_basis_table", "lb_fd_count", "lb_fd_enumerate",
     "lb_expand", "lb_expand_pure", "lb_reconstruct",
-    "lindblad_prepare", "lindblad_q_to_f32", "lindblad_propagate", "lindblad_propagate_batched",
+    "lindblad_prepare", "lindblad_q_to_f32", "lindblad_propagate", "lindblad_propagate_noalloc",
+    "lindblad_propagate_batched",
     "lindblad_propagate_graph", "lindblad_propagate_csr", "lindblad_prepare_sparse",
     "lindblad_propagate_csr_drive", "lb_eigh", "Secular", "read_bandwidth", "lb_hessenberg", "lindblad_spectrum",
     "lindblad_spectrum_histogram", "save_system", "load_system", "load_system_info", "lindblad_steady_state", "lindblad_steady_state_csr", "lindblad_autotune", "lindblad_tile_info", "lindblad_set_tile", "lindblad_time_stage", "Server",
@@ -100,6 +101,7 @@ def signatures():
         "lindblad_prepare_sparse_count": [V, I, V, I, V, V, V],
         "lindblad_prepare_sparse_fill": [V, I, V, I, V, V, I64, V, V, V, V],
         "lindblad_propagate": [V, I64, V, V, I64, V, V, I, D, I64, I],
+        "lindblad_propagate_noalloc": [V, I64, V, V, I64, V, V, I, D, I64, I],
         "lindblad_q_to_f32": [V, I64, V, I64, V],
         "lindblad_propagate_csr": [V, I64, V, V, V, V, V, I, D, I64],
         "lindblad_propagate_csr_drive": [V, I64, V, V, V, V, V, V, V, V, I, D, I64, D, I64, D, D, D],
@@ -389,6 +391,16 @@ def lindblad_propagate(ctx: Context, Q, K, V, dt: float, steps: int, precision: 
     _check(load().lindblad_propagate(ctx.handle, M, _ptr(Q) if Q is not None else None,
                                      _ptr(Q32) if Q32 is not None else None, ldq, _ptr(K), _ptr(V),
                                      V.shape[0], float(dt), int(steps), int(precision)))
+    return V
+
+
+def lindblad_propagate_noalloc(ctx: Context, Q, K, V, dt: float, steps: int, precision: int = FP64, Q32=None):
+    """lindblad_propagate without any allocation: the buffers live in the
+    library's static per-GPU array (calls on one GPU must not overlap)."""
+    M, ldq = _prop_args(Q, Q32, K, V, precision)
+    _check(load().lindblad_propagate_noalloc(ctx.handle, M, _ptr(Q) if Q is not None else None,
+                                             _ptr(Q32) if Q32 is not None else None, ldq, _ptr(K), _ptr(V),
+                                             V.shape[0], float(dt), int(steps), int(precision)))
     return V
 
 

@@ -111,6 +111,8 @@ int lb_create(lb_ctx** out, int device, void* stream) {
     LB_HIP(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return lb_fail(LB_ERR_INVALID_ARG, "device %d not present (%d devices)", device, n);
     LB_HIP(hipSetDevice(device));
+    const int rc = lb_scratch_init(device);  // the allocation-free propagate's static array, once per device
+    if (rc) return rc;
     lb_ctx* c = new lb_ctx();
     c->device = device;
     c->stream = (hipStream_t)stream;  // NULL: the device's default stream
@@ -304,6 +306,19 @@ int lindblad_propagate(lb_ctx* c, int64_t M, const double* Q, const float* Q32, 
     else CHECK_PTR(Q32);
     lb_prop_sys s{Q, Q32, K, V};
     return lb_impl_propagate(c, 1, M, &s, ldq, B, dt, steps, precision, nullptr);
+}
+
+int lindblad_propagate_noalloc(lb_ctx* c, int64_t M, const double* Q, const float* Q32, int64_t ldq,
+                               const double* K, double* V, int B, double dt, int64_t steps, int precision) {
+    CHECK_CTX(c);
+    int rc = check_prop(M, ldq, B, dt, steps, precision);
+    if (rc) return rc;
+    CHECK_PTR(K);
+    CHECK_PTR(V);
+    if (precision == LB_FP64) CHECK_PTR(Q);
+    else CHECK_PTR(Q32);
+    lb_prop_sys s{Q, Q32, K, V};
+    return lb_impl_propagate_noalloc(c, M, &s, ldq, B, dt, steps, precision);
 }
 
 int lindblad_q_to_f32(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, float* Q32) {

@@ -204,6 +204,9 @@ struct lb_prop_sys {
     double* V;
 };
 
+int lb_scratch_init(int device);
+int lb_impl_propagate_noalloc(lb_ctx* c, int64_t M, const lb_prop_sys* sys, int64_t ldq, int B, double dt,
+                              int64_t steps, int precision);
 int lb_impl_propagate(lb_ctx* c, int R, int64_t M, const lb_prop_sys* sys, int64_t ldq, int B,
                       double dt, int64_t steps, int precision, const lb_tile* force_tile);
 int lb_impl_time_stage(lb_ctx* c, int R, int64_t M, const lb_prop_sys* sys, int64_t ldq, int B, int precision,

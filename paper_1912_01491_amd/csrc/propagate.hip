@@ -20,6 +20,8 @@
 // the 16-byte load a lane issues holds two consecutive k of one state -- the
 // B-operand of two MFMAs whose A-operand is the two consecutive Q columns the
 // same lane loaded. The FP32 path interleaves by four.
+#include <mutex>
+
 #include "lb_internal.h"
 #include "rowdot.h"
 #include "sell.h"
@@ -1161,9 +1163,9 @@ static int plan_make(Plan& p, int R, int64_t M, int64_t ldq, int B, int precisio
     return LB_OK;
 }
 
-// Binds the plan to device memory `base` (p.bytes) and uploads the per-system
-// pointer arrays through the context's pinned staging buffer. Synchronizes.
-static int plan_bind(lb_ctx* c, Plan& p, char* base, const lb_prop_sys* sys) {
+// Kernel choice that depends on the operands' alignment (the LDS-staged
+// forms need 128-byte rows); rejects Q that is not 16-byte aligned.
+static int plan_align(Plan& p, const lb_prop_sys* sys) {
     const int R = p.R;
     const int64_t es = p.precision == LB_FP32 ? 4 : 8;
     p.staged = (p.kind == PATH_MFMA || p.kind == PATH_GEMV) && (p.ldq * es) % 128 == 0;
@@ -1176,7 +1178,29 @@ static int plan_bind(lb_ctx* c, Plan& p, char* base, const lb_prop_sys* sys) {
         const int RT = p.tile.rows / 16, CT = p.Bp / 16;
         if (p.precision == LB_FP64 ? pick64s(RT, CT) == nullptr : pick32s(RT, CT) == nullptr) p.staged = false;
     }
-    int rc = lb_host_reserve(c, sizeof(void*) * 5 * R);
+    return LB_OK;
+}
+
+// Points the plan's buffers into device memory `base` (p.bytes).
+static void plan_buffers(Plan& p, char* base) {
+    p.d = (const void**)(base + p.o_ptr);
+    if (p.kind == PATH_GEMV) p.W = (double*)(base + p.o_w);
+    if (p.kind == PATH_MFMA) {
+        p.V = (double*)(base + p.o_v);
+        p.Acc = (double*)(base + p.o_acc);
+        p.X = (double*)(base + p.o_x);
+        p.X32 = p.precision == LB_FP32 ? (float*)(base + p.o_x32) : nullptr;
+        p.Part = (double*)(base + p.o_part);
+    }
+}
+
+// Binds the plan to device memory `base` (p.bytes) and uploads the per-system
+// pointer arrays through the context's pinned staging buffer. Synchronizes.
+static int plan_bind(lb_ctx* c, Plan& p, char* base, const lb_prop_sys* sys) {
+    const int R = p.R;
+    int rc = plan_align(p, sys);
+    if (rc) return rc;
+    rc = lb_host_reserve(c, sizeof(void*) * 5 * R);
     if (rc) return rc;
     LB_HIP(hipStreamSynchronize(c->stream));
     const void** h = (const void**)c->host;
@@ -1189,15 +1213,7 @@ static int plan_bind(lb_ctx* c, Plan& p, char* base, const lb_prop_sys* sys) {
     }
     LB_HIP(hipMemcpyAsync(base + p.o_ptr, h, sizeof(void*) * 5 * R, hipMemcpyHostToDevice, c->stream));
     LB_HIP(hipStreamSynchronize(c->stream));
-    p.d = (const void**)(base + p.o_ptr);
-    if (p.kind == PATH_GEMV) p.W = (double*)(base + p.o_w);
-    if (p.kind == PATH_MFMA) {
-        p.V = (double*)(base + p.o_v);
-        p.Acc = (double*)(base + p.o_acc);
-        p.X = (double*)(base + p.o_x);
-        p.X32 = p.precision == LB_FP32 ? (float*)(base + p.o_x32) : nullptr;
-        p.Part = (double*)(base + p.o_part);
-    }
+    plan_buffers(p, base);
     return LB_OK;
 }
 
@@ -1373,6 +1389,75 @@ int lb_impl_time_stage(lb_ctx* c, int R, int64_t M, const lb_prop_sys* sys, int6
     int rc = plan_for(c, p, R, M, sys, ldq, B, precision, force_tile, false);
     if (rc) return rc;
     return plan_time(c, p, iters, ms);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free propagation (one system): the plan's buffers -- packed
+// states, stage accumulators, split-K partials, the pointer table -- live in a
+// static device array instead of the context workspace, and the pointer table
+// is written by a kernel instead of a staged host copy, so the call allocates
+// nothing (no device, no pinned host memory) and never synchronizes. Each GPU
+// holds its own copy of the array from module load until the process ends;
+// every call on a GPU shares it (nothing in it must start at zero: the plan
+// writes every element it reads), so calls that overlap on one GPU race.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)LB_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices];  // device address of `scratch` on each GPU
+
+__global__ void k_set_ptrs(const void** d, const void* q, const void* q32, const void* k, void* v) {
+    if (threadIdx.x == 0) {
+        d[0] = q;
+        d[1] = q32;
+        d[2] = k;
+        d[3] = v;
+        d[4] = v;
+    }
+}
+
+}  // namespace
+
+// Looks up the array's device address once per device; `device` must be current.
+int lb_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return lb_fail(LB_ERR_UNSUPPORTED, "device %d beyond %d", device, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return LB_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return lb_fail(LB_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    g_scratch[device] = ptr;
+    return LB_OK;
+}
+
+int lb_impl_propagate_noalloc(lb_ctx* c, int64_t M, const lb_prop_sys* sys, int64_t ldq, int B, double dt,
+                              int64_t steps, int precision) {
+    if (steps == 0) return LB_OK;
+    void* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        base = c->device >= 0 && c->device < kMaxDevices ? g_scratch[c->device] : nullptr;
+    }
+    if (!base) return lb_fail(LB_ERR_DEVICE, "the static scratch of device %d is not set up", c->device);
+    Plan p;
+    int rc = plan_make(p, 1, M, ldq, B, precision, choose_tile(c, M, bpad(B), precision, 1), true);
+    if (rc) return rc;
+    if (p.bytes > kScratchBytes)
+        return lb_fail(LB_ERR_UNSUPPORTED,
+                       "M=%lld with %d states needs %zu bytes of scratch; the allocation-free propagate holds %zu",
+                       (long long)M, B, p.bytes, kScratchBytes);
+    rc = plan_align(p, sys);
+    if (rc) return rc;
+    plan_buffers(p, (char*)base);
+    hipLaunchKernelGGL(k_set_ptrs, dim3(1), dim3(64), 0, c->stream, p.d, (const void*)sys->Q, (const void*)sys->Q32,
+                       (const void*)sys->K, (void*)sys->V);
+    LB_CHECK_LAUNCH();
+    return plan_launch(p, c->stream, dt, steps);
 }
 
 struct lb_graph_entry {
