@@ -448,6 +448,13 @@ def config_c2(args):
     gbs = S * bytes_step / t_prop / 1e9
     rho = lb.lb_reconstruct(ctx, V, N)[0].cpu().numpy()
     tr = abs(np.trace(rho) - 1)
+    # positivity of rho(T): classic RK4 at this dt (spectral radius x dt ~ 2) is not positivity
+    # preserving; the smallest eigenvalue is reported, with one run at half the step for comparison
+    mineig = float(np.linalg.eigvalsh(0.5 * (rho + rho.conj().T)).min())
+    Vh = V0.clone()
+    lb.lindblad_propagate_csr(ctx, rp, col, val, K, Vh, 0.5 * dt, 2 * S)
+    rho_h = lb.lb_reconstruct(ctx, Vh, N)[0].cpu().numpy()
+    mineig_half = float(np.linalg.eigvalsh(0.5 * (rho_h + rho_h.conj().T)).min())
     # oracle parity on sampled rows
     rows = np.array([0, 1, 777, 499499, 499500, 998999, 999000, M - 1])
     Qo, Ko = oracle.prepare_factored(H, rates, Ls, rows)
@@ -467,7 +474,8 @@ def config_c2(args):
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sell_stage<false, 1>",
                         "bytes_per_step": bytes_step},
-           "checks": {"trace_err": float(tr), "sampled_rows_rel_err_vs_oracle": err}}
+           "checks": {"trace_err": float(tr), "sampled_rows_rel_err_vs_oracle": err,
+                      "min_eig_rho_T": mineig, "min_eig_rho_T_half_dt": mineig_half}}
     ctx.close()
     print(json.dumps(out), flush=True)
 

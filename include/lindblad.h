@@ -260,7 +260,10 @@ int lindblad_propagate_batched(lb_ctx* ctx, int R, int64_t M, const double* cons
 
 /* Records the RK4 stage launches of `steps` steps into a HIP graph on first
  * use for a given (M, B, ldq, precision, buffers, dt, steps) and replays it
- * afterwards; otherwise identical to lindblad_propagate. */
+ * afterwards; otherwise identical to lindblad_propagate. A captured graph
+ * keeps the raw Q, K and V pointers and its own device buffers; a context
+ * keeps at most 8 graphs and frees the least recently used one (after
+ * synchronizing its stream) when a ninth is captured. */
 int lindblad_propagate_graph(lb_ctx* ctx, int64_t M, const double* Q, const float* Q32, int64_t ldq,
                              const double* K, double* V, int B, double dt, int64_t steps, int precision);
 

@@ -71,8 +71,9 @@ struct lb_ctx {
     // tuned tile shapes: key (M, Bp, precision)
     std::map<std::tuple<int64_t, int, int>, lb_tile> tuned;
     bool cache_loaded = false;
-    // captured propagate graphs
+    // captured propagate graphs (at most 8, least recently used evicted)
     std::map<lb_graph_key, struct lb_graph_entry*> graphs;
+    uint64_t graph_clock = 0;
     // progress of long calls (lb_set_progress)
     lb_progress_fn progress = nullptr;
     void* progress_user = nullptr;

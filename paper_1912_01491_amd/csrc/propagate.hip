@@ -1464,7 +1464,12 @@ struct lb_graph_entry {
     Plan plan;
     void* mem = nullptr;
     hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
 };
+
+// Captured graphs kept per context (least recently used evicted first): each
+// holds its plan buffers and the raw operand pointers it was captured with.
+constexpr size_t kMaxGraphs = 8;
 
 void lb_graph_free(lb_graph_entry* g) {
     if (!g) return;
@@ -1479,6 +1484,14 @@ int lb_impl_propagate_graph(lb_ctx* c, int64_t M, const lb_prop_sys* sys, int64_
     lb_graph_key key{M, ldq, B, precision, sys->Q, sys->Q32, sys->K, sys->V, dt, steps};
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
+        if (c->graphs.size() >= kMaxGraphs) {
+            auto lru = c->graphs.begin();
+            for (auto jt = c->graphs.begin(); jt != c->graphs.end(); ++jt)
+                if (jt->second->last_use < lru->second->last_use) lru = jt;
+            LB_HIP(hipStreamSynchronize(c->stream));  // its last launch may still run
+            lb_graph_free(lru->second);
+            c->graphs.erase(lru);
+        }
         lb_graph_entry* g = new lb_graph_entry();
         const lb_tile tile = choose_tile(c, M, bpad(B), precision, 1);
         int rc = plan_make(g->plan, 1, M, ldq, B, precision, tile, true);
@@ -1524,6 +1537,7 @@ int lb_impl_propagate_graph(lb_ctx* c, int64_t M, const lb_prop_sys* sys, int64_
         }
         it = c->graphs.emplace(key, g).first;
     }
+    it->second->last_use = ++c->graph_clock;
     LB_HIP(hipGraphLaunch(it->second->exec, c->stream));
     return LB_OK;
 }

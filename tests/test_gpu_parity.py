@@ -337,6 +337,28 @@ def test_propagate_graph_replays(lb, ctx, oracle, N, B):
     assert rel(V.cpu().numpy(), Vo) < RTOL
 
 
+def test_graph_cache_is_bounded(lb, oracle):
+    """Twelve distinct captures on one context (fresh state buffers each time):
+    the cache keeps at most eight graphs, evicting the least recently used,
+    and every replay, old or new, equals the eager integration."""
+    N, B = 8, 2
+    c = lb.Context(0)
+    H, gamma = wl.random_lindbladian(N, 91)
+    Q, K = lb.lindblad_prepare(c, dev(H), dev(gamma))
+    psis = wl.random_pure_states(N, B, 9)
+    V0 = dev(np.array([oracle.expand(np.outer(p, p.conj())).real for p in psis]))
+    ref = V0.clone()
+    lb.lindblad_propagate(c, Q, K, ref, 1e-3, 6)
+    bufs = [V0.clone() for _ in range(12)]
+    for rep in range(2):
+        for V in bufs + bufs[:3]:
+            V.copy_(V0)
+            lb.lindblad_propagate_graph(c, Q, K, V, 1e-3, 6)
+            c.sync()
+            assert torch.equal(V, ref)
+    c.close()
+
+
 def test_autotune_then_propagate(lb, ctx, oracle):
     N = 30
     print("[gpu] autotune N=%d" % N, flush=True)
