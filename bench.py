@@ -80,6 +80,24 @@ def measured_traffic(M, R, B, tile):
     return rec["fetch_bytes"] + rec["write_bytes"]
 
 
+def assembly_traffic(N, M, ldq):
+    """Measured HBM bytes of one dense preparation (all assembly kernels) from the
+    FETCH_SIZE / WRITE_SIZE runs summarised under profiles/, scaled by the copy
+    factors recorded there; None unless the assembly source and the shape are those
+    of the counter runs."""
+    path = os.path.join(ROOT, "profiles", "k_quad_assembly_N200_dense.md")
+    try:
+        line = next(x for x in open(path) if x.startswith("traffic-record:"))
+    except (OSError, StopIteration):
+        return None
+    rec = json.loads(line.split(":", 1)[1])
+    src = open(os.path.join(ROOT, "paper_1912_01491_amd", "csrc", "prepare_dense.hip")).read()
+    digest = hashlib.sha256(src.encode()).hexdigest()[:16]
+    if (rec["N"], rec["M"], rec["ldq"]) != (N, M, ldq) or rec["source_digest"] != digest:
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +135,8 @@ def parse():
     ap.add_argument("--resident", action="store_true", help="with --serving: same as --config c5r")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for rocprofv3 --pmc runs: one plain 4 GiB copy, then the C4 stage GEMM on stand-in Q")
+    ap.add_argument("--pmc-assembly", action="store_true",
+                    help="for rocprofv3 --pmc runs: one plain 4 GiB copy, then one dense preparation at --N")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--arrival", choices=["burst", "poisson"], default="burst")
     ap.add_argument("--ss-N", type=int, default=1000, help="c6s: dimer size")
@@ -954,6 +974,35 @@ def pmc_probe(args):
     ctx.close()
 
 
+def pmc_assembly(args):
+    """Kernels for the assembly's HBM traffic counters: a plain copy of 4 GiB
+    (the scale for FETCH_SIZE / WRITE_SIZE), then one dense preparation at
+    N (default 200) with gamma drawn beforehand (the draw's kernels are not
+    the library's and are told apart by name)."""
+    import torch
+
+    import paper_1912_01491_amd as lb
+    from paper_1912_01491_amd import workloads as wl
+
+    n = 1 << 29  # doubles: 4 GiB
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    N = args.N
+    ctx = lb.Context(0)
+    H = torch.from_numpy(wl.gue_hamiltonian(N, 0)).cuda()
+    gamma = wl.wishart_kossakowski_device(N, 1000, device="cuda")
+    torch.cuda.synchronize()
+    log("gamma drawn; preparing N=%d" % N)
+    Q, K = lb.lindblad_prepare(ctx, H, gamma)
+    ctx.sync()
+    log("copy 4 GiB done; one preparation at N=%d done" % N)
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -962,6 +1011,8 @@ def main():
         sys.exit(2)
     if args.pmc_probe:
         return pmc_probe(args)
+    if args.pmc_assembly:
+        return pmc_assembly(args)
     if args.serving or args.config in ("c5", "c5r"):
         return serving(args)
     if args.config in ("c1", "c2", "c2p", "c3", "c6", "c6s", "c7", "c8"):
@@ -1121,6 +1172,17 @@ def config_c4(args):
         "assembly_s_all": t_prep,
         "assembly_gbs": asm_bytes / t_prep_mean / 1e9,
         "assembly_frac_hbm": asm_bytes / t_prep_mean / 1e9 / HBM_PEAK_GBS,
+        "assembly_roofline": {
+            "bound": "hbm",
+            "kernel": "k_quad (+ side kernels on a second stream)",
+            "achieved": asm_bytes / t_prep_mean / 1e9,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": asm_bytes / t_prep_mean / 1e9 / HBM_PEAK_GBS,
+            "bytes_per_preparation": asm_bytes,
+            "design_bytes": 24.0 * M * M,
+            "traffic": assembly_traffic(N, M, ldq),
+        },
         "gamma_draw_s": sum(t_draw) / len(t_draw),
         "solves_per_s": R * B / (t_prep_mean * R + t_timed / K_steps * args.rk4_steps),
         "checks": {"max_abs_trace_err": tr_err, "max_herm_err": herm, "min_eig_rho": mineig,

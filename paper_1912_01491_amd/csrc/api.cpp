@@ -125,6 +125,12 @@ int lb_destroy(lb_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (auto& kv : c->graphs) lb_graph_free(kv.second);
+    if (c->aux) {
+        (void)hipStreamSynchronize(c->aux);
+        (void)hipStreamDestroy(c->aux);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->ws) (void)hipFree(c->ws);
     if (c->host) (void)hipHostFree(c->host);
     delete c;

@@ -71,6 +71,10 @@ struct lb_ctx {
     // tuned tile shapes: key (M, Bp, precision)
     std::map<std::tuple<int64_t, int, int>, lb_tile> tuned;
     bool cache_loaded = false;
+    // auxiliary stream for work that overlaps the context stream's (dense
+    // preparation), joined back with events; created on first use
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // captured propagate graphs (at most 8, least recently used evicted)
     std::map<lb_graph_key, struct lb_graph_entry*> graphs;
     uint64_t graph_clock = 0;

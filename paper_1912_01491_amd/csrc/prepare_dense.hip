@@ -21,17 +21,25 @@
 // Kernels, in launch order:
 //   k_pt       Pt[a][k] = sum_l w_l(a) gamma[D^l][k]              (N x M)
 //   k_cdd      Cdd[a][c] = C(a,a,c,c)                              (N x N)
-//   k_gtheta   G, Theta = sum_jk gamma_jk F_j F_k, Z, Lambda = L(1) (N x N)
+//   k_gth_a/c  partial sums over chunks of b of G and Theta from the 2x2
+//              gamma blocks of pairs sharing a vertex (coalesced along a or c)
+//   k_gth_fin  G, Theta, Z = -iH - G/2, Lambda = L(1)               (N x N)
 //   k_expand   K_s = Tr(F_s Lambda)/N
-//   k_fourset  Q[pair][pair] for disjoint pairs (the bulk: ~M^2 elements),
-//              mirror half into a transposed scratch
-//   k_mirror   transposes the mirror half into Q
-//   k_pp_shared Q[pair][pair] for pairs sharing a vertex
+//   then, concurrently on two streams:
+//   k_quad     Q[pair][pair] for disjoint pairs (the bulk: ~M^2 elements) and
+//              the shared-vertex elements inside the segments it owns; one
+//              workgroup per pair (a, c) reads gamma at exactly the positions
+//              of Q it writes, so gamma is read once and Q written once
+//   k_segpp    shared-vertex elements in a row pair's own-vertex segments
 //   k_drows    Q[D][pair]          (prefix sums over the diagonal)
 //   k_dcols    Q[pair][D]
 //   k_dd1/2    Q[D][D]
+//   k_zero_pad the padding columns of Q
 // gamma is read assuming exact Hermiticity: an entry may be read from
 // either triangle, whichever keeps the wavefront's loads contiguous.
+#include <algorithm>
+#include <vector>
+
 #include "lb_internal.h"
 
 namespace {
@@ -138,40 +146,12 @@ __global__ void k_cdd(GV v, double* Cdd) {
     cstore(Cdd, t, s);
 }
 
-// G_ac = sum_b C(b,c,a,b), Theta_ac = sum_b C(a,b,b,c);
-// Z = -iH - G/2 and Lambda = Theta - G = L(1).
-__global__ void k_gtheta(GV v, const double* H, double* Z, double* Lam) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int N = v.N;
-    if (t >= (int64_t)N * N) return;
-    const int a = (int)(t / N), c = (int)(t % N);
-    cd G = cmk(0, 0), Th = cmk(0, 0);
-    for (int b = 0; b < N; ++b) {
-        G = cadd(G, chat(v, b, c, a, b));
-        Th = cadd(Th, chat(v, a, b, b, c));
-    }
-    const cd h = cload(H, t);
-    // -i h = (h.im, -h.re)
-    cstore(Z, t, cmk(h.im - 0.5 * G.re, -h.re - 0.5 * G.im));
-    cstore(Lam, t, csub(Th, G));
-}
-
 // ---------------------------------------------------------------------------
-// Pair x pair block
+// Pair x pair elements
 // ---------------------------------------------------------------------------
 // An element with row pair {u,v} (u < v) and column pair {x,y} (x < y) on four
 // distinct vertices needs two 2x2 blocks of gamma: B1 between the pairs {u,x}
-// and {v,y}, B2 between {u,y} and {v,x}. Grouping the elements by their vertex
-// set {a < b < c < d}: its three pairings {ab|cd}, {ac|bd}, {ad|bc} give three
-// blocks G1, G2, G3 of gamma (one of each Hermitian pair), and the six elements
-// whose row and column pairs partition the set each use two of them. k_fourset
-// gives every set to one lane (lanes along d: each block read and the three
-// "direct" elements, whose column pair holds d, are contiguous in memory) and
-// writes the three "mirror" elements (row pair holds d) transposed into a
-// scratch matrix T; k_mirror moves them to their place with a tiled
-// transpose. Every disjoint element is written once, gamma's blocks are read
-// once each. Elements whose pairs share a vertex are O(N^3) and come from
-// k_pp_shared.
+// and {v,y}, B2 between {u,y} and {v,x}.
 
 // A 2x2 block of gamma between a row pair and a column pair: entries (S,S),
 // (S,J), (J,S), (J,J).
@@ -187,13 +167,16 @@ __device__ __forceinline__ Blk blk_load(const GV& v, int64_t pr, int64_t pc) {
 __device__ __forceinline__ Blk blk_t(const Blk& b) { return Blk{cconj(b.ss), cconj(b.as), cconj(b.sa), cconj(b.aa)}; }
 
 // Four outputs (S|J row) x (S|J column) of the disjoint element ({u,v}, {x,y})
-// from B1 (pairs {u,x} x {v,y}) and B2 (pairs {u,y} x {v,x}).
-__device__ __forceinline__ Acc4 pp_disjoint(int u, int vv, int x, int y, const Blk& B1, const Blk& B2) {
+// from B1 (pairs {u,x} x {v,y}) and B2 (pairs {u,y} x {v,x}). The vertex order
+// is fixed at each call site, so the signs are template arguments:
+// S1 = sigma(u,x), S2 = sigma(y,v), T1 = sigma(u,y), T2 = sigma(x,v).
+template <int S1, int S2, int T1, int T2>
+__device__ __forceinline__ Acc4 pp_disjoint(const Blk& B1, const Blk& B2) {
     // C(u,x,y,v) from B1; C(v,y,x,u) from B1^H; C(u,y,x,v) from B2; C(v,x,y,u) from B2^H
-    const cd c_uxyv = blk_c(B1.ss, B1.sa, B1.as, B1.aa, sgn(u, x), sgn(y, vv));
-    const cd c_vyxu = blk_c(cconj(B1.ss), cconj(B1.as), cconj(B1.sa), cconj(B1.aa), sgn(vv, y), sgn(x, u));
-    const cd c_uyxv = blk_c(B2.ss, B2.sa, B2.as, B2.aa, sgn(u, y), sgn(x, vv));
-    const cd c_vxyu = blk_c(cconj(B2.ss), cconj(B2.as), cconj(B2.sa), cconj(B2.aa), sgn(vv, x), sgn(y, u));
+    const cd c_uxyv = blk_c(B1.ss, B1.sa, B1.as, B1.aa, S1, S2);
+    const cd c_vyxu = blk_c(cconj(B1.ss), cconj(B1.as), cconj(B1.sa), cconj(B1.aa), -S2, -S1);
+    const cd c_uyxv = blk_c(B2.ss, B2.sa, B2.as, B2.aa, T1, T2);
+    const cd c_vxyu = blk_c(cconj(B2.ss), cconj(B2.as), cconj(B2.sa), cconj(B2.aa), -T2, -T1);
     // (d,a) = (u,v): s_da = +1; (v,u): -1. (b,c) = (x,y): +1; (y,x): -1. Term C(a,b,c,d).
     Acc4 acc;
     acc.add(+1, +1, c_vxyu);
@@ -201,116 +184,6 @@ __device__ __forceinline__ Acc4 pp_disjoint(int u, int vv, int x, int y, const B
     acc.add(-1, +1, c_uxyv);
     acc.add(-1, -1, c_uyxv);
     return acc;
-}
-
-__device__ __forceinline__ void pp_store(double* Q, int64_t ldq, int64_t P, int64_t rs, int64_t cn, const Acc4& acc) {
-    __builtin_nontemporal_store(0.5 * acc.ss, Q + rs * ldq + cn);
-    __builtin_nontemporal_store(0.5 * acc.sa, Q + rs * ldq + P + cn);
-    __builtin_nontemporal_store(0.5 * acc.as, Q + (P + rs) * ldq + cn);
-    __builtin_nontemporal_store(0.5 * acc.aa, Q + (P + rs) * ldq + P + cn);
-}
-
-// The element at Q[(rs, cn)] stored at T's transposed position: T[j][i] = Q[i][j].
-__device__ __forceinline__ void pp_store_t(double* T, int64_t ldt, int64_t P, int64_t rs, int64_t cn, const Acc4& acc) {
-    __builtin_nontemporal_store(0.5 * acc.ss, T + cn * ldt + rs);
-    __builtin_nontemporal_store(0.5 * acc.sa, T + (P + cn) * ldt + rs);
-    __builtin_nontemporal_store(0.5 * acc.as, T + cn * ldt + P + rs);
-    __builtin_nontemporal_store(0.5 * acc.aa, T + (P + cn) * ldt + P + rs);
-}
-
-// Block (blockIdx.x = pair index of {a,b}, blockIdx.y = chunk of kFourChunk
-// column pairs); lane q runs over the pairs {c,d} with b < c < d, which are the
-// pair indices from p(b+1, b+2) to P-1.
-constexpr int kFourChunk = 4096;
-
-__global__ __launch_bounds__(256) void k_fourset(GV v, const int2* pairs, double* Q, int64_t ldq, double* T,
-                                                 int64_t ldt) {
-    const int64_t pab = blockIdx.x;
-    const int a = pairs[pab].x, b = pairs[pab].y;
-    const int N = v.N;
-    if (b > N - 3) return;
-    const int64_t P = v.P;
-    const int64_t qb = lb_pair(N, b + 1, b + 2) + (int64_t)blockIdx.y * kFourChunk;
-    const int64_t qe = qb + kFourChunk < P ? qb + kFourChunk : P;
-    for (int64_t q = qb + threadIdx.x; q < qe; q += blockDim.x) {
-        const int c = pairs[q].x, d = pairs[q].y;
-        const int64_t pac = lb_pair(N, a, c), pbd = lb_pair(N, b, d);
-        const int64_t pbc = lb_pair(N, b, c), pad = lb_pair(N, a, d);
-        const Blk G1 = blk_load(v, pab, q);    // {a,b} x {c,d}
-        const Blk G2 = blk_load(v, pac, pbd);  // {a,c} x {b,d}
-        const Blk G3 = blk_load(v, pbc, pad);  // {b,c} x {a,d}
-        const Blk G2t = blk_t(G2), G3t = blk_t(G3);
-        pp_store(Q, ldq, P, pab, q, pp_disjoint(a, b, c, d, G2, G3t));
-        pp_store(Q, ldq, P, pac, pbd, pp_disjoint(a, c, b, d, G1, G3t));
-        pp_store(Q, ldq, P, pbc, pad, pp_disjoint(b, c, a, d, G1, G2t));
-        pp_store_t(T, ldt, P, q, pab, pp_disjoint(c, d, a, b, G2, G3));
-        pp_store_t(T, ldt, P, pbd, pac, pp_disjoint(b, d, a, c, G1, G3));
-        pp_store_t(T, ldt, P, pad, pbc, pp_disjoint(a, d, b, c, G1, G2));
-    }
-}
-
-// Q[i][j] = T[j][i] for i, j < 2P whose pairs are disjoint with the larger
-// vertex in the row pair (the mirror elements). 64 x 64 tiles through LDS,
-// 16-byte loads along T's rows and 16-byte stores along Q's rows; the tile's
-// row and column pairs are read once into LDS. Tiles whose rows' largest
-// vertex never exceeds its columns' smallest are skipped (ymax/ymin: per run
-// of 64 indices).
-constexpr int kMirrorTile = 64;
-
-__global__ __launch_bounds__(256) void k_mirror(const double* T, int64_t ldt, const int2* pairs, const int* ymin,
-                                                const int* ymax, int64_t P, double* Q, int64_t ldq) {
-    __shared__ double tile[kMirrorTile][kMirrorTile + 1];
-    __shared__ int2 rp[kMirrorTile], cp[kMirrorTile];
-    const int64_t ti = blockIdx.x, tj = blockIdx.y;  // row tile of Q, column tile of Q
-    if (ymax[ti] <= ymin[tj]) return;
-    const int64_t n2 = 2 * P;
-    const int64_t i0 = ti * kMirrorTile, j0 = tj * kMirrorTile;
-    const int t = threadIdx.x;
-    if (t < kMirrorTile) {
-        const int64_t i = i0 + t;
-        rp[t] = i < n2 ? pairs[i < P ? i : i - P] : make_int2(-1, -1);
-    } else if (t < 2 * kMirrorTile) {
-        const int64_t j = j0 + t - kMirrorTile;
-        cp[t - kMirrorTile] = j < n2 ? pairs[j < P ? j : j - P] : make_int2(-2, 1 << 30);  // never below a row pair
-    }
-    __syncthreads();
-    // mirror element: disjoint pairs, larger vertex in the row pair; the padding
-    // pairs (row: upper vertex -1, column: upper vertex 2^30) never qualify, so
-    // nothing past row or column 2P - 1 of T or Q is touched
-    auto mirror = [](int2 R, int2 C) { return R.x != C.x && R.x != C.y && R.y != C.x && R.y != C.y && R.y > C.y; };
-    const int c2 = 2 * (t & 31), r0 = t >> 5;  // column pair within a row, first row
-    // T rows j0.. (Q columns), two consecutive i per thread; only mirror elements
-    // are loaded, so lines of T outside the mirror region are not fetched
-    for (int r = r0; r < kMirrorTile; r += 8) {
-        const int64_t j = j0 + r, i = i0 + c2;
-        const int2 C = cp[r];
-        const bool m0 = mirror(rp[c2], C), m1 = mirror(rp[c2 + 1], C);
-        const double* src = T + j * ldt + i;
-        double2 x = make_double2(0.0, 0.0);
-        if (m0 && m1 && (((uintptr_t)src) & 15) == 0) {
-            x = *reinterpret_cast<const double2*>(src);
-        } else {
-            if (m0) x.x = src[0];
-            if (m1) x.y = src[1];
-        }
-        tile[r][c2] = x.x;
-        tile[r][c2 + 1] = x.y;
-    }
-    __syncthreads();
-    for (int r = r0; r < kMirrorTile; r += 8) {
-        const int64_t i = i0 + r, j = j0 + c2;
-        if (i >= n2 || j >= n2) continue;
-        const int2 R = rp[r];
-        const bool m0 = mirror(R, cp[c2]);
-        const bool m1 = mirror(R, cp[c2 + 1]);
-        double* q = Q + i * ldq + j;
-        if (m0 && m1 && (((uintptr_t)q) & 15) == 0) {
-            *reinterpret_cast<double2*>(q) = make_double2(tile[c2][r], tile[c2 + 1][r]);
-        } else {
-            if (m0) q[0] = tile[c2][r];
-            if (m1) q[1] = tile[c2 + 1][r];
-        }
-    }
 }
 
 // Elements whose row pair {u,v} and column pair {x,y} share a vertex
@@ -346,31 +219,316 @@ __device__ __forceinline__ void pp_store_plain(double* Q, int64_t ldq, int64_t P
     Q[(P + rs) * ldq + P + cn] = 0.5 * acc.aa;
 }
 
-// Elements of pairs sharing a vertex, grouped by vertex set {a<b<c}: its
-// pairs ab, ac, bc give the six off-diagonal elements, which read the same
-// three gamma blocks and Pt entries. One wavefront per pair {a,b}, lanes
-// along c; lane 0 also writes the pair's diagonal element. All six values
-// are formed before any store, so repeated reads need not be issued twice.
-__global__ __launch_bounds__(256) void k_pp_shared(GV v, const double* Zm, const int2* pairs, double* Q,
-                                                   int64_t ldq) {
+// ---------------------------------------------------------------------------
+// G and Theta from the blocks of pairs that share a vertex
+// ---------------------------------------------------------------------------
+// G_ac = sum_b C(b,c,a,b) and Theta_ca = sum_b C(c,b,b,a). For b outside {a,c}
+// both terms come from one 2x2 block of gamma, beta = gamma[{b,c}][{a,b}] (rows:
+// pair {b,c}; columns: pair {a,b}), read in whichever orientation keeps a
+// wavefront's loads contiguous:
+//   b < a            beta itself: row {b,c} fixed per c, columns p(b,a) along a
+//   a < b < c        beta = (gamma[{a,b}][{b,c}])^H: row p(a,b), columns p(b,c) along c
+//   b > max(a,c)     beta itself (strided: columns p(a,b) of different segments)
+// k_gth_a (lanes along a) takes the first and last ranges, k_gth_c (lanes along
+// c) the middle one; both split b into chunks of kGthChunk and write one partial
+// sum per chunk; k_gth_fin adds the chunks in order of b, then the b = a and
+// b = c terms. Partial layout: Gp[k][a][c] (G_ac), Tp[k][x][y] (Theta_xy).
+constexpr int kGthChunk = 16;
+
+__device__ __forceinline__ void gth_add(cd& g, cd& th, const Blk& B, int a, int b, int c) {
+    g = cadd(g, blk_c(B.ss, B.sa, B.as, B.aa, sgn(b, c), sgn(a, b)));
+    th = cadd(th, blk_c(B.ss, B.sa, B.as, B.aa, sgn(c, b), sgn(b, a)));
+}
+
+__global__ void k_gth_a(GV v, double* Gp, double* Tp) {
+    const int N = v.N;
+    const int64_t NN = (int64_t)N * N;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= NN) return;
+    const int a = (int)(t % N), c = (int)(t / N);
+    const int b0 = (int)blockIdx.y * kGthChunk, b1 = min(N, b0 + kGthChunk);
+    const int hi = a > c ? a : c;
+    cd g = cmk(0, 0), th = cmk(0, 0);
+    for (int b = b0; b < b1; ++b) {
+        if (b == a || b == c || (b > a && b < hi)) continue;
+        gth_add(g, th, blk_load(v, lb_upair(N, b, c), lb_upair(N, a, b)), a, b, c);
+    }
+    const int64_t k = blockIdx.y;
+    cstore(Gp, k * NN + (int64_t)a * N + c, g);
+    cstore(Tp, k * NN + (int64_t)c * N + a, th);
+}
+
+__global__ void k_gth_c(GV v, double* Gp, double* Tp) {
+    const int N = v.N;
+    const int64_t NN = (int64_t)N * N;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= NN) return;
+    const int c = (int)(t % N), a = (int)(t / N);
+    const int k0 = (int)blockIdx.y * kGthChunk;
+    const int b0 = max(k0, a + 1), b1 = min(min(N, k0 + kGthChunk), c);
+    cd g = cmk(0, 0), th = cmk(0, 0);
+    for (int b = b0; b < b1; ++b)
+        gth_add(g, th, blk_t(blk_load(v, lb_pair(N, a, b), lb_pair(N, b, c))), a, b, c);
+    const int64_t k = blockIdx.y;
+    cstore(Gp, k * NN + (int64_t)a * N + c, g);
+    cstore(Tp, k * NN + (int64_t)c * N + a, th);
+}
+
+// Z = -iH - G/2 and Lambda = Theta - G = L(1).
+__global__ void k_gth_fin(GV v, const double* H, const double* GpA, const double* TpA, const double* GpC,
+                          const double* TpC, int nch, double* Z, double* Lam) {
+    const int N = v.N;
+    const int64_t NN = (int64_t)N * N;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= NN) return;
+    const int a = (int)(t / N), c = (int)(t % N);
+    cd G = cmk(0, 0), Th = cmk(0, 0);
+    for (int k = 0; k < nch; ++k) {
+        G = cadd(G, cadd(cload(GpA, k * NN + t), cload(GpC, k * NN + t)));
+        Th = cadd(Th, cadd(cload(TpA, k * NN + t), cload(TpC, k * NN + t)));
+    }
+    if (a == c) {
+        G = cadd(G, chat(v, a, a, a, a));
+        Th = cadd(Th, chat(v, a, a, a, a));
+    } else {
+        G = cadd(G, chat(v, a, c, a, a));   // b = a
+        G = cadd(G, chat(v, c, c, a, c));   // b = c
+        Th = cadd(Th, chat(v, a, a, a, c));  // b = a
+        Th = cadd(Th, chat(v, a, c, c, c));  // b = c
+    }
+    const cd h = cload(H, t);
+    cstore(Z, t, cmk(h.im - 0.5 * G.re, -h.re - 0.5 * G.im));
+    cstore(Lam, t, csub(Th, G));
+}
+
+// ---------------------------------------------------------------------------
+// Pair x pair elements by whole row segments
+// ---------------------------------------------------------------------------
+// Segment w of pair row {x<y} is the run of columns p(w, z), z > w (in both the
+// S and the J column blocks). Workgroup (a, c), a < c, computes and writes these
+// segments whole:
+//   R  rows {w,c}, a < w < c, segment a: R[w][w'] = Q[{w,c}][{a,w'}] for w' in
+//      (a, c) (w' = w is a shared-vertex element), then w' = c (shared vertex)
+//      and w' > c;
+//   S  row {a,c}, segments x, a < x < c: S[x][z] = Q[{a,c}][{x,z}] for z in
+//      (x, c), then z = c (shared vertex) and z > c;
+//   T  rows {a,x}, a < x < c, segment c: Q[{a,x}][{c,d}], d > c.
+// A vertex set {a < x < z < c} gives R[z][x], R[x][z] and S[x][z], each from
+// the gamma blocks at the same three positions (read transposed: gamma is
+// Hermitian); a set {a < x < c < d} gives the d-th entries of T, of S's
+// segment x and of R's row {x,c}, from the blocks at those positions. Every
+// disjoint block of gamma is read once in each orientation, and every segment
+// is produced by one workgroup at one time, so Q is written in whole runs.
+// The shared-vertex elements outside these segments (segments x and y of row
+// {x,y}) come from k_segpp.
+//
+// The square R is processed in 16 x 16 tiles (x block X, z block Z, X <= Z);
+// block boundaries are placed so that a block's columns in segment a start a
+// 128-byte line of Q. The transposed tile R[z][x] goes through LDS. The sets
+// {a < x < c < d} of an x block follow its tiles (lanes along d), so that the
+// S and R segments end right after their tiles.
+constexpr int kQuadPad = 17;
+
+// Pair position in 32-bit arithmetic (the dense path holds M^2 complex values,
+// so N stays far below the 46341 where P would leave int).
+__device__ __forceinline__ int qpair(int N, int j, int k) { return j * N - ((j * (j + 1)) >> 1) + k - j - 1; }
+
+// Block loads and output stores with the J offsets of gamma and Q precomputed.
+struct QuadPtr {
+    const double* g;  // gamma
+    double* Q;
+    int64_t M;        // gamma row length (complex entries)
+    int64_t gjr;      // doubles from a gamma S row to the J row of the same pair
+    int64_t ldq;
+    int64_t qjr;      // doubles from a Q S row to the J row of the same pair
+    int P;
+};
+
+__device__ __forceinline__ Blk quad_blk(const QuadPtr& w, int pr, int pc) {
+    const double* p = w.g + 2 * ((int64_t)pr * w.M + pc);
+    const int oc = 2 * w.P;
+    return Blk{cload(p, 0), cload(p + oc, 0), cload(p + w.gjr, 0), cload(p + w.gjr + oc, 0)};
+}
+
+__device__ __forceinline__ void quad_put(const QuadPtr& w, int rs, int cn, const Acc4& acc) {
+    double* q = w.Q + (int64_t)rs * w.ldq + cn;
+    q[0] = 0.5 * acc.ss;
+    q[w.P] = 0.5 * acc.sa;
+    q[w.qjr] = 0.5 * acc.as;
+    q[w.qjr + w.P] = 0.5 * acc.aa;
+}
+
+__device__ __forceinline__ void quad_stage_put(double (*hb)[16][kQuadPad], int tx, int tz, const Blk& B) {
+    hb[0][tx][tz] = B.ss.re; hb[1][tx][tz] = B.ss.im;
+    hb[2][tx][tz] = B.sa.re; hb[3][tx][tz] = B.sa.im;
+    hb[4][tx][tz] = B.as.re; hb[5][tx][tz] = B.as.im;
+    hb[6][tx][tz] = B.aa.re; hb[7][tx][tz] = B.aa.im;
+}
+
+__device__ __forceinline__ Blk quad_stage_get(double (*hb)[16][kQuadPad], int zl, int xl) {
+    return Blk{cmk(hb[0][zl][xl], hb[1][zl][xl]), cmk(hb[2][zl][xl], hb[3][zl][xl]),
+               cmk(hb[4][zl][xl], hb[5][zl][xl]), cmk(hb[6][zl][xl], hb[7][zl][xl])};
+}
+
+// One workgroup per pair (a, c) of the work order (entries with a < 0 pad the
+// order to whole groups). Latency is hidden by occupancy rather than by
+// register prefetch: one LDS buffer per tile, two barriers per tile.
+__global__ __launch_bounds__(256) void k_quad(GV v, const double* Zm, const int2* order, double* Q, int64_t ldq) {
+    __shared__ double h[8][16][kQuadPad];  // gamma blocks at positions R[z][x], staged [z][x]
+    __shared__ double e[4][16][kQuadPad];  // outputs R[z][x], staged [z][x]
+    __shared__ double sb[4][16][33];       // line windows of the S row, one per x of the block
+    const int a = order[blockIdx.x].x, c = order[blockIdx.x].y;
+    if (a < 0) return;
+    const int L = c - a - 1;
+    if (L <= 0) return;
+    const int N = v.N;
+    QuadPtr w;
+    w.g = v.g;
+    w.Q = Q;
+    w.M = v.M;
+    w.gjr = 2 * v.P * v.M;
+    w.ldq = ldq;
+    w.qjr = v.P * ldq;
+    w.P = (int)v.P;
+    const int base = qpair(N, a, a + 1);  // column of segment a's first entry
+    const int r0 = base & 15;
+    const int J = (L + r0 + 15) >> 4;
+    const int pac = qpair(N, a, c);
+    const int t = threadIdx.x;
+    const int tx = t >> 4, tz = t & 15;
+    for (int jx = 0; jx < J; ++jx) {
+        const int ox = 16 * jx - r0 + tx;   // x offset of this thread's sets
+        const int ox2 = 16 * jx - r0 + tz;  // x offset of its staging role
+        // S[x][z] sits at column scol0 + oz of row {a,c}. Each x row of the block
+        // has a window of 32 slots in LDS, slot k = column sline + k with sline a
+        // multiple of 16: a tile's 16 values land in slots sphi .. sphi + 15, slots
+        // 0..15 (one whole 128-byte line) are written out after the tile and slots
+        // 16..31 carried to the next tile.
+        const int scol0 = qpair(N, a + 1 + ox, a + 2 + ox) - ox - 1;
+        const int ct = scol0 + 16 * jx - r0;
+        const int sphi = ((ct % 16) + 16) % 16;
+        int sline = ct - sphi;
+        for (int jz = jx; jz < J; ++jz) {
+            const int oz = 16 * jz - r0 + tz, oz2 = 16 * jz - r0 + tx;
+            const bool own = ox >= 0 && oz < L && ox < oz;
+            const bool stg = ox2 >= 0 && oz2 < L && ox2 < oz2;
+            Blk h2, h3;
+            const int x = a + 1 + ox, z = a + 1 + oz;
+            const int pxc = ox >= 0 && ox < L ? qpair(N, x, c) : 0;
+            if (own) {
+                h2 = quad_blk(w, pxc, base + oz);
+                h3 = quad_blk(w, pac, qpair(N, x, z));
+            }
+            if (stg) quad_stage_put(h, tx, tz, quad_blk(w, qpair(N, a + 1 + oz2, c), base + ox2));
+            __syncthreads();
+            if (own) {
+                const Blk G1 = blk_t(quad_stage_get(h, tz, tx)), G2 = blk_t(h2), G3 = blk_t(h3);
+                const Acc4 e4 = pp_disjoint<-1, 1, -1, 1>(G2, G3);  // R[z][x]: ({z,c}, {a,x})
+                e[0][tz][tx] = e4.ss; e[1][tz][tx] = e4.sa; e[2][tz][tx] = e4.as; e[3][tz][tx] = e4.aa;
+                quad_put(w, pxc, base + oz, pp_disjoint<-1, 1, 1, 1>(G1, G3));  // R[x][z]: ({x,c}, {a,z})
+                const Acc4 sv = pp_disjoint<1, 1, 1, 1>(G1, G2);  // S[x][z]: ({a,c}, {x,z})
+                const int k = sphi + tz;
+                sb[0][tx][k] = sv.ss; sb[1][tx][k] = sv.sa; sb[2][tx][k] = sv.as; sb[3][tx][k] = sv.aa;
+            } else if (ox >= 0 && ox == oz && oz < L) {
+                quad_put(w, pxc, base + ox, pp_shared(v, Zm, x, c, a, x));  // R[x][x]: ({x,c}, {a,x})
+            }
+            __syncthreads();
+            if (stg) {
+                const Acc4 r{e[0][tx][tz], e[1][tx][tz], e[2][tx][tz], e[3][tx][tz]};
+                quad_put(w, qpair(N, a + 1 + oz2, c), base + ox2, r);  // R[z][x]
+            }
+            {
+                const int oz3 = sline - scol0 + tz;
+                if (ox >= 0 && ox < oz3 && oz3 < L)
+                    quad_put(w, pac, sline + tz, Acc4{sb[0][tx][tz], sb[1][tx][tz], sb[2][tx][tz], sb[3][tx][tz]});
+#pragma unroll
+                for (int q = 0; q < 4; ++q) sb[q][tx][tz] = sb[q][tx][16 + tz];
+                sline += 16;
+            }
+        }
+        {  // the carried part of each S line
+            const int oz3 = sline - scol0 + tz;
+            if (ox >= 0 && ox < oz3 && oz3 < L)
+                quad_put(w, pac, sline + tz, Acc4{sb[0][tx][tz], sb[1][tx][tz], sb[2][tx][tz], sb[3][tx][tz]});
+        }
+        // sets {a < x < c < d} of this x block and the shared-vertex entries at
+        // d = c, items (x, d) flattened over the workgroup, lanes along d
+        const int lo = max(0, 16 * jx - r0), hi = min(L, 16 * jx - r0 + 16);
+        const int nd = N - c;
+        const int nitems = (hi - lo) * nd;
+        for (int i = t; i < nitems; i += 256) {
+            const int xi = i / nd;
+            const int x = a + 1 + lo + xi, d = c + (i - xi * nd);
+            const int pxc = qpair(N, x, c);
+            if (d == c) {
+                quad_put(w, pac, pxc, pp_shared(v, Zm, a, c, x, c));  // ({a,c}, {x,c})
+                quad_put(w, pxc, pac, pp_shared(v, Zm, x, c, a, c));  // ({x,c}, {a,c})
+                continue;
+            }
+            const int pax = qpair(N, a, x), pcd = qpair(N, c, d), pxd = qpair(N, x, d), pad = qpair(N, a, d);
+            const Blk G1 = quad_blk(w, pax, pcd);  // {a,x} x {c,d}
+            const Blk G2 = quad_blk(w, pac, pxd);  // {a,c} x {x,d}
+            const Blk G3 = quad_blk(w, pxc, pad);  // {x,c} x {a,d}
+            const Blk G2t = blk_t(G2), G3t = blk_t(G3);
+            quad_put(w, pax, pcd, pp_disjoint<1, -1, 1, -1>(G2, G3t));  // ({a,x}, {c,d})
+            quad_put(w, pac, pxd, pp_disjoint<1, -1, 1, 1>(G1, G3t));   // ({a,c}, {x,d})
+            quad_put(w, pxc, pad, pp_disjoint<-1, -1, 1, 1>(G1, G2t));  // ({x,c}, {a,d})
+        }
+    }
+}
+
+// C(a,b,c,d) where the pairs {u,vv} (= s) and {x,y} (= n) share a vertex and
+// sn = gamma[s][n]: block terms from sn or its transpose, diagonal terms (the
+// projections Pt) as in chat.
+__device__ __forceinline__ cd chat_pre(const GV& v, int a, int b, int c, int d, int u, int vv, const Blk& sn) {
+    if (a != b && c != d) {
+        const bool rows_s = (a == u && b == vv) || (a == vv && b == u);
+        const Blk B = rows_s ? sn : blk_t(sn);
+        return blk_c(B.ss, B.sa, B.as, B.aa, sgn(a, b), sgn(c, d));
+    }
+    return chat(v, a, b, c, d);
+}
+
+// pp_shared with the gamma block of (row pair, column pair) already loaded.
+__device__ __forceinline__ Acc4 pp_shared_pre(const GV& v, const double* Zm, int u, int vv, int x, int y,
+                                              const Blk& sn) {
+    const int N = v.N;
+    Acc4 acc;
+    const int sv[2][2] = {{u, vv}, {vv, u}};  // (d, a)
+    const int nv[2][2] = {{x, y}, {y, x}};    // (b, c)
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            const int d = sv[i][0], a = sv[i][1], b = nv[j][0], c = nv[j][1];
+            acc.add(sgn(d, a), sgn(b, c), chat_pre(v, a, b, c, d, u, vv, sn));
+        }
+    const int sv2[2] = {u, vv}, nv2[2] = {x, y};
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            if (sv2[i] != nv2[j]) continue;
+            const int wv = sv2[i], so = sv2[1 - i], no = nv2[1 - j];
+            acc.add(sgn(wv, so), sgn(no, wv), cload(Zm, (int64_t)so * N + no));
+            acc.add(sgn(so, wv), sgn(wv, no), cconj(cload(Zm, (int64_t)so * N + no)));
+        }
+    return acc;
+}
+
+// Segments x and y of pair row {x,y}: the elements whose column pair shares a
+// vertex with the row pair (and the diagonal element). One wavefront per row
+// pair, lanes along the column pair's second vertex.
+__global__ __launch_bounds__(256) void k_segpp(GV v, const double* Zm, const int2* pairs, double* Q, int64_t ldq) {
     const int N = v.N;
     const int64_t P = v.P;
-    const int64_t pab = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t ps = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (pab >= P) return;
-    const int a = pairs[pab].x, b = pairs[pab].y;
-    if (lane == 0) pp_store_plain(Q, ldq, P, pab, pab, pp_shared(v, Zm, a, b, a, b));
-    for (int c = b + 1 + lane; c < N; c += 64) {
-        const int64_t pac = lb_pair(N, a, c), pbc = lb_pair(N, b, c);
-        const Acc4 e1 = pp_shared(v, Zm, a, b, a, c), e2 = pp_shared(v, Zm, a, b, b, c);
-        const Acc4 e3 = pp_shared(v, Zm, a, c, a, b), e4 = pp_shared(v, Zm, a, c, b, c);
-        const Acc4 e5 = pp_shared(v, Zm, b, c, a, b), e6 = pp_shared(v, Zm, b, c, a, c);
-        pp_store_plain(Q, ldq, P, pab, pac, e1);
-        pp_store_plain(Q, ldq, P, pab, pbc, e2);
-        pp_store_plain(Q, ldq, P, pac, pab, e3);
-        pp_store_plain(Q, ldq, P, pac, pbc, e4);
-        pp_store_plain(Q, ldq, P, pbc, pab, e5);
-        pp_store_plain(Q, ldq, P, pbc, pac, e6);
+    if (ps >= P) return;
+    const int x = pairs[ps].x, y = pairs[ps].y;
+    for (int z = x + 1 + lane; z < N; z += 64) {
+        const int64_t pn = lb_pair(N, x, z);
+        pp_store_plain(Q, ldq, P, ps, pn, pp_shared_pre(v, Zm, x, y, x, z, blk_load(v, ps, pn)));
+    }
+    for (int z = y + 1 + lane; z < N; z += 64) {
+        const int64_t pn = lb_pair(N, y, z);
+        pp_store_plain(Q, ldq, P, ps, pn, pp_shared_pre(v, Zm, x, y, y, z, blk_load(v, ps, pn)));
     }
 }
 
@@ -660,16 +818,62 @@ int lb_impl_hermitian_check(lb_ctx* c, int64_t n, const double* A, double* maxde
     return LB_OK;
 }
 
+// Launch order of k_quad's workgroups (a, c): consecutive c of one a are
+// grouped (kQuadGroup at a time) and dispatched together on one XCD (block i
+// runs on XCD i mod 8), so that the segment boundaries they share are written
+// at about the same time; groups go to the XCDs largest first, each to the
+// least loaded one. Unused slots hold (-1, -1).
+constexpr int kQuadGroup = 8;
+
+static int64_t quad_order(int N, std::vector<int2>& out) {
+    struct Group {
+        int a, c0, c1;
+        double w;
+    };
+    std::vector<Group> groups;
+    for (int a = 0; a + 2 < N; ++a)
+        for (int c0 = a + 2; c0 < N; c0 += kQuadGroup) {
+            const int c1 = std::min(N, c0 + kQuadGroup);
+            double w = 0;
+            for (int cc = c0; cc < c1; ++cc) {
+                const double L = cc - a - 1;
+                w += L * (N - cc - 1) + 0.5 * L * (L + 1) + 1.0;
+            }
+            groups.push_back(Group{a, c0, c1, w});
+        }
+    std::stable_sort(groups.begin(), groups.end(), [](const Group& x, const Group& y) { return x.w > y.w; });
+    std::vector<std::vector<int2>> lists(8);
+    double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (const Group& g : groups) {
+        int best = 0;
+        for (int k = 1; k < 8; ++k)
+            if (load[k] < load[best]) best = k;
+        load[best] += g.w;
+        for (int cc = g.c0; cc < g.c1; ++cc) lists[best].push_back(make_int2(g.a, cc));
+    }
+    size_t per = 0;
+    for (auto& l : lists) per = std::max(per, l.size());
+    out.assign(8 * per, make_int2(-1, -1));
+    for (int k = 0; k < 8; ++k)
+        for (size_t j = 0; j < lists[k].size(); ++j) out[8 * j + k] = lists[k][j];
+    return (int64_t)out.size();
+}
+
+static int aux_stream(lb_ctx* c) {
+    if (c->aux) return LB_OK;
+    LB_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    LB_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    LB_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    return LB_OK;
+}
+
 int lb_impl_prepare_dense(lb_ctx* c, int N, const double* H, const double* gamma, double* Q, int64_t ldq,
                           double* K) {
     const int64_t M = (int64_t)N * N - 1;
     const int64_t P = lb_npairs(N);
-    // pair list, and per run of 64 pair-block indices (0..2P-1) the smallest and
-    // largest upper vertex, for the mirror transpose's tile skipping
-    const int64_t n2 = 2 * P;
-    const int64_t nt = (n2 + kMirrorTile - 1) / kMirrorTile;
-    const int64_t ldt = (n2 + 31) / 32 * 32;
-    if (nt > 65535) return lb_fail(LB_ERR_UNSUPPORTED, "N=%d too large for the mirror grid", N);
+    std::vector<int2> order;
+    const int64_t norder = N >= 3 ? quad_order(N, order) : 0;
+    const int nch = (N + kGthChunk - 1) / kGthChunk;
     // workspace layout
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -682,11 +886,13 @@ int lb_impl_prepare_dense(lb_ctx* c, int N, const double* H, const double* gamma
     const size_t o_z = take(sizeof(double) * 2 * (size_t)N * N);
     const size_t o_lam = take(sizeof(double) * 2 * (size_t)N * N);
     const size_t o_t = take(sizeof(double) * 2 * (size_t)N * N);
-    const size_t o_pairs = take(sizeof(int2) * (size_t)P + sizeof(int) * 2 * (size_t)nt + 8);  // pairs, ymin, ymax
-    const size_t o_mt = take(sizeof(double) * (size_t)n2 * ldt);
+    const size_t o_gp = take(sizeof(double) * 2 * 4 * (size_t)nch * N * N);  // GpA, TpA, GpC, TpC
+    const size_t o_pairs = take(sizeof(int2) * ((size_t)P + (size_t)norder) + 8);  // pairs, then the quad order
     int rc = lb_ws_reserve(c, off);
     if (rc) return rc;
-    const size_t hb = sizeof(int2) * P + sizeof(int) * 2 * nt;
+    rc = aux_stream(c);
+    if (rc) return rc;
+    const size_t hb = sizeof(int2) * ((size_t)P + (size_t)norder);
     rc = lb_host_reserve(c, hb);
     if (rc) return rc;
     char* ws = (char*)c->ws;
@@ -696,17 +902,7 @@ int lb_impl_prepare_dense(lb_ctx* c, int N, const double* H, const double* gamma
     int64_t hp = 0;
     for (int a = 0; a + 1 < N; ++a)
         for (int b = a + 1; b < N; ++b) h[hp++] = make_int2(a, b);
-    int* hy = (int*)(h + P);
-    for (int64_t t = 0; t < nt; ++t) {
-        int lo = N, hi = -1;
-        for (int64_t i = kMirrorTile * t; i < kMirrorTile * (t + 1) && i < n2; ++i) {
-            const int y = h[i < P ? i : i - P].y;
-            lo = y < lo ? y : lo;
-            hi = y > hi ? y : hi;
-        }
-        hy[t] = lo;
-        hy[nt + t] = hi;
-    }
+    for (int64_t i = 0; i < norder; ++i) h[P + i] = order[i];
     LB_HIP(hipMemcpyAsync(ws + o_pairs, h, hb, hipMemcpyHostToDevice, c->stream));
 
     GV v;
@@ -720,44 +916,56 @@ int lb_impl_prepare_dense(lb_ctx* c, int N, const double* H, const double* gamma
     double* Lam = (double*)(ws + o_lam);
     double* T = (double*)(ws + o_t);
     const int2* pd = (const int2*)(ws + o_pairs);
-    const int* ymin = (const int*)(ws + o_pairs + sizeof(int2) * P);
-    const int* ymax = ymin + nt;
-    double* MT = (double*)(ws + o_mt);
+    const int2* od = pd + P;
+    const size_t part = (size_t)2 * nch * N * N;  // doubles per partial array
+    double* GpA = (double*)(ws + o_gp);
+    double* TpA = GpA + part;
+    double* GpC = TpA + part;
+    double* TpC = GpC + part;
     hipStream_t s = c->stream;
 
     hipLaunchKernelGGL(k_pt, dim3(lb_blocks(M, 256)), dim3(256), 0, s, v, (double*)(ws + o_pt));
     LB_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_cdd, dim3(lb_blocks((int64_t)N * N, 256)), dim3(256), 0, s, v, (double*)(ws + o_cdd));
     LB_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_gtheta, dim3(lb_blocks((int64_t)N * N, 64)), dim3(64), 0, s, v, H, Zm, Lam);
+    const dim3 ggrid(lb_blocks((int64_t)N * N, 256), (unsigned)nch);
+    hipLaunchKernelGGL(k_gth_a, ggrid, dim3(256), 0, s, v, GpA, TpA);
+    LB_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_gth_c, ggrid, dim3(256), 0, s, v, GpC, TpC);
+    LB_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_gth_fin, dim3(lb_blocks((int64_t)N * N, 256)), dim3(256), 0, s, v, H, (const double*)GpA,
+                       (const double*)TpA, (const double*)GpC, (const double*)TpC, nch, Zm, Lam);
     LB_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_expand, dim3(lb_blocks(M, 256)), dim3(256), 0, s, N, 1, (const double*)Lam, K, 1.0 / N);
     LB_CHECK_LAUNCH();
-    if (P > 0) {
-        if (N >= 4) {
-            hipLaunchKernelGGL(k_fourset, dim3((unsigned)P, (unsigned)((P + kFourChunk - 1) / kFourChunk)), dim3(256),
-                               0, s, v, pd, Q, ldq, MT, ldt);
-            LB_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_mirror, dim3((unsigned)nt, (unsigned)nt), dim3(256), 0, s, (const double*)MT, ldt, pd,
-                               ymin, ymax, P, Q, ldq);
-            LB_CHECK_LAUNCH();
-        }
-        hipLaunchKernelGGL(k_pp_shared, dim3(lb_blocks(P * 64, 256)), dim3(256), 0, s, v, (const double*)Zm, pd, Q,
-                           ldq);
-        LB_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_drows, dim3(lb_blocks(P, 64)), dim3(64), 0, s, v, (const double*)Zm, pd, Q, ldq);
-        LB_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_dcols, dim3(lb_blocks(P, 64)), dim3(64), 0, s, v, (const double*)Zm, pd, Q, ldq);
+    // the segments of pair rows on this stream; the shared-vertex segments, the
+    // rows and columns of the diagonal generators and the padding on the
+    // auxiliary stream, concurrently (they write other elements of Q)
+    LB_HIP(hipEventRecord(c->ev_fork, s));
+    LB_HIP(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+    hipStream_t s2 = c->aux;
+    if (norder > 0) {
+        hipLaunchKernelGGL(k_quad, dim3((unsigned)norder), dim3(256), 0, s, v, (const double*)Zm, od, Q, ldq);
         LB_CHECK_LAUNCH();
     }
-    hipLaunchKernelGGL(k_dd1, dim3(lb_blocks((int64_t)N * (N - 1), 64)), dim3(64), 0, s, v, (const double*)Zm, T);
+    if (P > 0) {
+        hipLaunchKernelGGL(k_segpp, dim3(lb_blocks(P * 64, 256)), dim3(256), 0, s2, v, (const double*)Zm, pd, Q, ldq);
+        LB_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_drows, dim3(lb_blocks(P, 64)), dim3(64), 0, s2, v, (const double*)Zm, pd, Q, ldq);
+        LB_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_dcols, dim3(lb_blocks(P, 64)), dim3(64), 0, s2, v, (const double*)Zm, pd, Q, ldq);
+        LB_CHECK_LAUNCH();
+    }
+    hipLaunchKernelGGL(k_dd1, dim3(lb_blocks((int64_t)N * (N - 1), 64)), dim3(64), 0, s2, v, (const double*)Zm, T);
     LB_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_dd2, dim3(lb_blocks((int64_t)(N - 1) * (N - 1), 64)), dim3(64), 0, s, v,
+    hipLaunchKernelGGL(k_dd2, dim3(lb_blocks((int64_t)(N - 1) * (N - 1), 64)), dim3(64), 0, s2, v,
                        (const double*)T, Q, ldq);
     LB_CHECK_LAUNCH();
     if (ldq > M) {
-        hipLaunchKernelGGL(k_zero_pad, dim3(lb_blocks(M * (ldq - M), 256)), dim3(256), 0, s, Q, M, ldq);
+        hipLaunchKernelGGL(k_zero_pad, dim3(lb_blocks(M * (ldq - M), 256)), dim3(256), 0, s2, Q, M, ldq);
         LB_CHECK_LAUNCH();
     }
+    LB_HIP(hipEventRecord(c->ev_join, s2));
+    LB_HIP(hipStreamWaitEvent(s, c->ev_join, 0));
     return LB_OK;
 }
