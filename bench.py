@@ -1170,6 +1170,7 @@ def config_c4(args):
         "assembly_s_per_realization": t_prep_mean,
         "assembly_s_hip_events": sum(t_prep_ev) / len(t_prep_ev),
         "assembly_s_all": t_prep,
+        "assembly_s_median": sorted(t_prep)[len(t_prep) // 2],
         "assembly_gbs": asm_bytes / t_prep_mean / 1e9,
         "assembly_frac_hbm": asm_bytes / t_prep_mean / 1e9 / HBM_PEAK_GBS,
         "assembly_roofline": {
