@@ -434,6 +434,29 @@ int lindblad_spectrum_histogram(lb_ctx* ctx, int64_t n, const double* lam, doubl
 /* Measurement                                                        */
 /* ------------------------------------------------------------------ */
 
+/* Dense FP64 products on the matrix cores, the building block of the
+ * preconditioner's basis changes and the blocked Hessenberg reduction; exported
+ * for tests. All matrices are column-major device arrays with leading
+ * dimensions (elements), asynchronous on the context stream, no allocation.
+ * lb_gemm_f64: C = alpha op(A) op(B) + beta C, C m x n, op(A) m x k, op(B) k x n;
+ * op is the transpose when trans_a / trans_b is nonzero (then A is stored k x m,
+ * B n x k). With beta = 0, C is not read.
+ * lb_gemm_c128: C = op(A) op(B) on complex128 (interleaved re, im; leading
+ * dimensions in complex elements); op is the conjugate transpose when conj_a /
+ * conj_b is nonzero. work (may be NULL) is caller-owned device scratch of
+ * work_elems complex values: when the grid of 64 x 64 tiles of C is small, k
+ * is split into up to 8 slices whose dense m x n partial products go there and
+ * are then summed in slice order (as many slices as the scratch holds; none
+ * without it). The result depends on the slicing only through rounding.
+ * Errors: LB_ERR_INVALID_ARG (negative sizes, leading dimension below the
+ * stored rows, null operands with nonzero sizes, work_elems < 0 or a NULL
+ * work with work_elems > 0). */
+int lb_gemm_f64(lb_ctx* ctx, int trans_a, int trans_b, int64_t m, int64_t n, int64_t k, double alpha,
+                const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc);
+int lb_gemm_c128(lb_ctx* ctx, int conj_a, int conj_b, int64_t m, int64_t n, int64_t k, const double* A,
+                 int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc, double* work,
+                 int64_t work_elems);
+
 /* Read-stream bandwidth of the context's device in GB/s (1e9 bytes/s): a
  * reduction over a buffer of `bytes` (allocated and freed by the call) with
  * 16-byte nontemporal loads, timed with HIP events, the best of five grid

@@ -25,7 +25,7 @@ __all__ = [
     "lindblad_prepare", "lindblad_q_to_f32", "lindblad_propagate", "lindblad_propagate_noalloc",
     "lindblad_propagate_batched",
     "lindblad_propagate_graph", "lindblad_propagate_csr", "lindblad_prepare_sparse",
-    "lindblad_propagate_csr_drive", "lb_eigh", "Secular", "read_bandwidth", "lb_hessenberg", "lindblad_spectrum",
+    "lindblad_propagate_csr_drive", "lb_eigh", "Secular", "read_bandwidth", "gemm_f64", "gemm_c128", "lb_hessenberg", "lindblad_spectrum",
     "lindblad_spectrum_histogram", "save_system", "load_system", "load_system_info", "lindblad_steady_state", "lindblad_steady_state_csr", "lindblad_autotune", "lindblad_tile_info", "lindblad_set_tile", "lindblad_time_stage", "Server",
     "FP64", "FP32", "CHECK_HERMITIAN",
 ]
@@ -107,6 +107,8 @@ def signatures():
         "lindblad_propagate_csr_drive": [V, I64, V, V, V, V, V, V, V, V, I, D, I64, D, I64, D, D, D],
         "lb_eigh": [V, I, V, I, V, V, I, V],
         "lb_read_bandwidth": [V, ctypes.c_size_t, V],
+        "lb_gemm_f64": [V, I, I, I64, I64, I64, D, V, I64, V, I64, D, V, I64],
+        "lb_gemm_c128": [V, I, I, I64, I64, I64, V, I64, V, I64, V, I64, V, I64],
         "lb_hessenberg": [V, I64, V, I64],
         "lindblad_spectrum": [V, I64, V, I64, V, V],
         "lindblad_spectrum_histogram": [V, I64, V, D, D, D, D, I, I, V],
@@ -500,6 +502,55 @@ def lindblad_spectrum_histogram(ctx: Context, lam, re0: float, re1: float, im0: 
     _check(load().lindblad_spectrum_histogram(ctx.handle, lam.numel(), _ptr(torch.view_as_real(lam)), float(re0),
                                               float(re1), float(im0), float(im1), int(nx), int(ny), _ptr(counts)))
     return counts
+
+
+def _need_cover(t, dtype, name, rows, cols, ld):
+    """t must be a contiguous device tensor holding a column-major rows x cols
+    matrix with leading dimension ld."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype:
+        raise ValueError("%s must be a CUDA (HIP) %s tensor" % (name, dtype))
+    if not t.is_contiguous() or (t.is_complex() and t.is_conj()):
+        raise ValueError("%s must be contiguous (and not a lazily conjugated view)" % name)
+    if ld < max(1, rows):
+        raise ValueError("%s: leading dimension %d below its %d rows" % (name, ld, rows))
+    if rows > 0 and cols > 0 and t.numel() < (cols - 1) * ld + rows:
+        raise ValueError("%s holds %d elements, fewer than a %d x %d matrix with leading dimension %d"
+                         % (name, t.numel(), rows, cols, ld))
+
+
+def gemm_f64(ctx: Context, m: int, n: int, k: int, A, lda: int, B, ldb: int, C, ldc: int, alpha: float = 1.0,
+             beta: float = 0.0, trans_a: bool = False, trans_b: bool = False):
+    """C = alpha op(A) op(B) + beta C (lb_gemm_f64): float64 device tensors
+    holding column-major matrices with leading dimensions; C is m x n, op(A)
+    m x k, op(B) k x n, op the transpose when trans_a / trans_b (A then stored
+    k x m, B n x k)."""
+    import torch
+    _need_cover(A, torch.float64, "A", k if trans_a else m, m if trans_a else k, lda)
+    _need_cover(B, torch.float64, "B", n if trans_b else k, k if trans_b else n, ldb)
+    _need_cover(C, torch.float64, "C", m, n, ldc)
+    _check(load().lb_gemm_f64(ctx.handle, int(trans_a), int(trans_b), m, n, k, float(alpha), _ptr(A), lda,
+                              _ptr(B), ldb, float(beta), _ptr(C), ldc))
+    return C
+
+
+def gemm_c128(ctx: Context, m: int, n: int, k: int, A, lda: int, B, ldb: int, C, ldc: int, conj_a: bool = False,
+              conj_b: bool = False, work=None):
+    """C = op(A) op(B) (lb_gemm_c128) on complex128 device tensors holding
+    column-major matrices (leading dimensions in complex elements); op is the
+    conjugate transpose when conj_a / conj_b. work: optional complex128 device
+    scratch for splitting k (see lb_gemm_c128)."""
+    import torch
+    _need_cover(A, torch.complex128, "A", k if conj_a else m, m if conj_a else k, lda)
+    _need_cover(B, torch.complex128, "B", n if conj_b else k, k if conj_b else n, ldb)
+    _need_cover(C, torch.complex128, "C", m, n, ldc)
+    wp, wn = None, 0
+    if work is not None:
+        _need_cover(work, torch.complex128, "work", work.numel(), 1, work.numel())
+        wp, wn = _ptr(work), work.numel()
+    _check(load().lb_gemm_c128(ctx.handle, int(conj_a), int(conj_b), m, n, k, _ptr(A), lda, _ptr(B), ldb, _ptr(C),
+                               ldc, wp, wn))
+    return C
 
 
 def read_bandwidth(ctx: Context, nbytes: int = 4 << 30) -> float:

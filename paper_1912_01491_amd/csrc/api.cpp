@@ -383,6 +383,18 @@ int lb_read_bandwidth(lb_ctx* c, size_t bytes, double* gbs) {
     return lb_impl_read_bandwidth(c, bytes, gbs);
 }
 
+int lb_gemm_f64(lb_ctx* c, int trans_a, int trans_b, int64_t m, int64_t n, int64_t k, double alpha, const double* A,
+                int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc) {
+    CHECK_CTX(c);
+    return lb_impl_gemm_f64(c->stream, trans_a != 0, trans_b != 0, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+int lb_gemm_c128(lb_ctx* c, int conj_a, int conj_b, int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
+                 const double* B, int64_t ldb, double* C, int64_t ldc, double* work, int64_t work_elems) {
+    CHECK_CTX(c);
+    return lb_impl_gemm_c128(c->stream, conj_a != 0, conj_b != 0, m, n, k, A, lda, B, ldb, C, ldc, work, work_elems);
+}
+
 int lb_hessenberg(lb_ctx* c, int64_t M, double* A, int64_t lda) {
     CHECK_CTX(c);
     CHECK_PTR(A);

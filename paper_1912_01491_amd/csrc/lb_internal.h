@@ -233,6 +233,17 @@ int lb_impl_load_system(lb_ctx* c, const char* path, lb_system* sys);
 int lb_impl_read_bandwidth(lb_ctx* c, size_t bytes, double* gbs);
 int lb_impl_eigh(lb_ctx* c, int N, double* A, int lda, double* w, double* Z, int ldz, int* sweeps);
 int lb_impl_hessenberg(lb_ctx* c, int M, double* A, int64_t lda);
+// FP64 matrix-core products (gemm.hip), column-major, asynchronous on s.
+int lb_impl_gemm_f64(hipStream_t s, bool ta, bool tb, int64_t m, int64_t n, int64_t k, double alpha,
+                     const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                     int64_t ldc);
+// work: optional device scratch of work_elems complex values; when it holds S
+// partial products (S = lb_gemm_c128_splits, fewer if it does not) k is split
+// over S slices that are summed in order.
+int lb_impl_gemm_c128(hipStream_t s, bool ca, bool cb, int64_t m, int64_t n, int64_t k, const double* A,
+                      int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc, double* work,
+                      int64_t work_elems);
+int lb_gemm_c128_splits(int64_t m, int64_t n, int64_t k);
 int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam, int64_t* sweeps, int64_t* steps,
                      int64_t* work);
 int lb_impl_spectrum_histogram(lb_ctx* c, int64_t n, const double* lam, double re0, double re1, double im0,

@@ -24,7 +24,6 @@
 #include "lb_internal.h"
 
 #include <math.h>
-#include <rocblas/rocblas.h>
 
 #include <vector>
 
@@ -38,7 +37,8 @@ struct lb_secular {
     double2* T1 = nullptr;   // scratch, N x N each
     double2* T2 = nullptr;
     double* pv = nullptr;    // 2 (N + 1) + N: right-hand side, populations, diagonal scan
-    rocblas_handle blas = nullptr;
+    double2* part = nullptr;  // partial products of the split-k basis changes
+    int64_t part_elems = 0;
 };
 
 namespace {
@@ -275,23 +275,18 @@ __global__ void k_apply_den(int N, double2* T, const double2* den, const double*
     T[i] = make_double2((x.x * d.x + x.y * d.y) / q, (x.y * d.x - x.x * d.y) / q);
 }
 
-int blas_ok(rocblas_status st) {
-    return st == rocblas_status_success ? LB_OK : lb_fail(LB_ERR_DEVICE, "rocBLAS call failed (%d)", (int)st);
-}
-
-// C = op(A) op(B), N x N complex, column-major.
-int zgemm(rocblas_handle h, rocblas_operation oa, rocblas_operation ob, int N, const double2* A, const double2* B,
+// C = op(A) op(B), N x N complex, column-major; op = conjugate transpose when ca / cb.
+int zgemm(hipStream_t s, const lb_secular* pre, bool ca, bool cb, int N, const double2* A, const double2* B,
           double2* C) {
-    const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
-    return blas_ok(rocblas_zgemm(h, oa, ob, N, N, N, &one, (const rocblas_double_complex*)A, N,
-                                 (const rocblas_double_complex*)B, N, &zero, (rocblas_double_complex*)C, N));
+    return lb_impl_gemm_c128(s, ca, cb, N, N, N, (const double*)A, N, (const double*)B, N, (double*)C, N,
+                             (double*)pre->part, pre->part_elems);
 }
 
 void secular_free(lb_secular* p) {
     if (!p) return;
-    for (void* q : {(void*)p->U, (void*)p->den, (void*)p->Binv, (void*)p->T1, (void*)p->T2, (void*)p->pv})
+    for (void* q : {(void*)p->U, (void*)p->den, (void*)p->Binv, (void*)p->T1, (void*)p->T2, (void*)p->pv,
+                    (void*)p->part})
         if (q) (void)hipFree(q);
-    if (p->blas) (void)rocblas_destroy_handle(p->blas);
     delete p;
 }
 
@@ -333,6 +328,13 @@ int lb_impl_secular_create(lb_ctx* c, int N, const lb_csr_c128* H, int P, const 
         (rc = dmalloc((void**)&pre->T1, sizeof(double2) * NN)) || (rc = dmalloc((void**)&pre->T2, sizeof(double2) * NN)) ||
         (rc = dmalloc((void**)&pre->pv, sizeof(double) * (2 * (size_t)n + N))))
         return cleanup(rc);
+    {
+        const int S = lb_gemm_c128_splits(N, N, N);
+        if (S > 1) {
+            pre->part_elems = (int64_t)S * NN;
+            if ((rc = dmalloc((void**)&pre->part, sizeof(double2) * (size_t)pre->part_elems))) return cleanup(rc);
+        }
+    }
     const int Pm = P > 0 ? P : 1;
     if ((rc = dmalloc((void**)&Hd, sizeof(double2) * NN)) || (rc = dmalloc((void**)&E, sizeof(double) * N)) ||
         (rc = dmalloc((void**)&W, sizeof(double) * NN)) || (rc = dmalloc((void**)&gt, sizeof(double) * N)) ||
@@ -343,11 +345,6 @@ int lb_impl_secular_create(lb_ctx* c, int N, const lb_csr_c128* H, int P, const 
         return cleanup(rc);
     }
     tmp = {Hd, E, W, gt, gdev, dg, aug, f, pval, piv};
-    if (rocblas_create_handle(&pre->blas) != rocblas_status_success) {
-        pre->blas = nullptr;
-        return cleanup(lb_fail(LB_ERR_DEVICE, "rocBLAS handle creation failed"));
-    }
-    if ((rc = blas_ok(rocblas_set_stream(pre->blas, s)))) return cleanup(rc);
     // energy eigenbasis of H
     if (hipMemsetAsync(Hd, 0, sizeof(double2) * NN, s) != hipSuccess) return cleanup(lb_fail(LB_ERR_DEVICE, "memset"));
     hipLaunchKernelGGL(k_csr_dense_cm, dim3(lb_blocks(N, 256)), dim3(256), 0, s, N, H->rowptr, H->col,
@@ -361,9 +358,8 @@ int lb_impl_secular_create(lb_ctx* c, int N, const lb_csr_c128* H, int P, const 
             return cleanup(lb_fail(LB_ERR_DEVICE, "memset"));
         hipLaunchKernelGGL(k_csr_dense_cm, dim3(lb_blocks(N, 256)), dim3(256), 0, s, N, L[p].rowptr, L[p].col,
                            (const double2*)L[p].val, Hd);
-        if ((rc = zgemm(pre->blas, rocblas_operation_none, rocblas_operation_none, N, Hd, pre->U, pre->T1)) ||
-            (rc = zgemm(pre->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, N, pre->U, pre->T1,
-                        pre->T2)))
+        if ((rc = zgemm(s, pre, false, false, N, Hd, pre->U, pre->T1)) ||
+            (rc = zgemm(s, pre, true, false, N, pre->U, pre->T1, pre->T2)))
             return cleanup(rc);
         hipLaunchKernelGGL(k_jump_accum, dim3(lb_blocks(NN, 256)), dim3(256), 0, s, N, rates[p],
                            (const double2*)pre->T2, W, dg + (int64_t)p * N);
@@ -403,14 +399,11 @@ int lb_impl_secular_apply(lb_ctx* c, const lb_secular* pre, const double* r, dou
     const int n = N + 1;
     const int64_t P = lb_npairs(N);
     int rc;
-    if ((rc = blas_ok(rocblas_set_stream(pre->blas, s)))) return rc;
     double* scan = pre->pv + 2 * n;
     hipLaunchKernelGGL(k_diag_scan<true>, dim3(1), dim3(1024), 0, s, N, (const double2*)nullptr, r, scan);
     hipLaunchKernelGGL(k_v_to_herm, dim3(lb_blocks(P + N, 256)), dim3(256), 0, s, N, r, (const double*)scan, pre->T1);
     LB_CHECK_LAUNCH();
-    if ((rc = zgemm(pre->blas, rocblas_operation_none, rocblas_operation_none, N, pre->T1, pre->U, pre->T2)) ||
-        (rc = zgemm(pre->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, N, pre->U, pre->T2,
-                    pre->T1)))
+    if ((rc = zgemm(s, pre, false, false, N, pre->T1, pre->U, pre->T2)) || (rc = zgemm(s, pre, true, false, N, pre->U, pre->T2, pre->T1)))
         return rc;
     hipLaunchKernelGGL(k_diag_rhs, dim3(lb_blocks(n, 256)), dim3(256), 0, s, N, (const double2*)pre->T1, pre->pv);
     hipLaunchKernelGGL(k_small_gemv, dim3(lb_blocks(n, 4)), dim3(256), 0, s, n, (const double*)pre->Binv,
@@ -418,9 +411,7 @@ int lb_impl_secular_apply(lb_ctx* c, const lb_secular* pre, const double* r, dou
     hipLaunchKernelGGL(k_apply_den, dim3(lb_blocks(NN, 256)), dim3(256), 0, s, N, pre->T1, (const double2*)pre->den,
                        (const double*)(pre->pv + n));
     LB_CHECK_LAUNCH();
-    if ((rc = zgemm(pre->blas, rocblas_operation_none, rocblas_operation_conjugate_transpose, N, pre->T1, pre->U,
-                    pre->T2)) ||
-        (rc = zgemm(pre->blas, rocblas_operation_none, rocblas_operation_none, N, pre->U, pre->T2, pre->T1)))
+    if ((rc = zgemm(s, pre, false, true, N, pre->T1, pre->U, pre->T2)) || (rc = zgemm(s, pre, false, false, N, pre->U, pre->T2, pre->T1)))
         return rc;
     hipLaunchKernelGGL(k_diag_scan<false>, dim3(1), dim3(1024), 0, s, N, (const double2*)pre->T1, (const double*)nullptr,
                        scan);

@@ -28,7 +28,6 @@
 //     cycles; kMaxIts sweeps without one is an error.
 #include "lb_internal.h"
 
-#include <rocblas/rocblas.h>
 
 #include <float.h>
 #include <algorithm>
@@ -1068,15 +1067,11 @@ struct HessLayout {
 
 namespace {
 
-int blas_check(rocblas_status st) {
-    return st == rocblas_status_success ? LB_OK : lb_fail(LB_ERR_DEVICE, "rocBLAS call failed (%d)", (int)st);
-}
-
-// The blocked reduction. rocBLAS works column-major: the row-major A is the column-major
+// The blocked reduction. The products work column-major: the row-major A is the column-major
 // X = A^T with leading dimension lda, so A[:, j0:] -= Y V^T is X[j0:, :] -= V Y^T, and the
 // left update of A[j0+1:, j0:] is X[j0:, j0+1:] -= (X[j0:, j0+1:] V T) V^T over rows j0+1..
 // of V.
-int hessenberg_blocked(lb_ctx* c, int M, double* A, int64_t lda, rocblas_handle h) {
+int hessenberg_blocked(lb_ctx* c, int M, double* A, int64_t lda) {
     hipStream_t s = c->stream;
     const BlockedLayout lay(M);
     char* ws = (char*)c->ws;
@@ -1091,8 +1086,6 @@ int hessenberg_blocked(lb_ctx* c, int M, double* A, int64_t lda, rocblas_handle 
     double* u = (double*)(ws + lay.u);
     double* taus = (double*)(ws + lay.tau);
     double* betas = (double*)(ws + lay.beta);
-    const double one = 1.0, mone = -1.0, zero = 0.0;
-    const int ldl = (int)lda;
     for (int j0 = 0; j0 + 2 < M; j0 += kPanel) {
         const int ib = std::min(kPanel, M - 2 - j0);
         hipLaunchKernelGGL(k_bh_zero, dim3(lb_blocks((int64_t)M * kPanel, 256)), dim3(256), 0, s, V,
@@ -1130,17 +1123,15 @@ int hessenberg_blocked(lb_ctx* c, int M, double* A, int64_t lda, rocblas_handle 
         }
         int rc;
         // A[:, j0:] -= Y V^T
-        if ((rc = blas_check(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, M - j0, M, ib,
-                                           &mone, V + j0, M, Y, M, &one, A + j0, ldl))))
+        if ((rc = lb_impl_gemm_f64(s, false, true, M - j0, M, ib, -1.0, V + j0, M, Y, M, 1.0, A + j0, lda)))
             return rc;
         // W^T = X[j0:, j0+1:] V[j0+1:], W2^T = W^T T, X[j0:, j0+1:] -= W2^T V[j0+1:]^T
         double* Xb = A + j0 + (int64_t)(j0 + 1) * lda;
-        if ((rc = blas_check(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, M - j0, ib, M - j0 - 1,
-                                           &one, Xb, ldl, V + j0 + 1, M, &zero, W, M))) ||
-            (rc = blas_check(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, M - j0, ib, ib, &one, W,
-                                           M, T, kPanel, &zero, W2, M))) ||
-            (rc = blas_check(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, M - j0,
-                                           M - j0 - 1, ib, &mone, W2, M, V + j0 + 1, M, &one, Xb, ldl))))
+        if ((rc = lb_impl_gemm_f64(s, false, false, M - j0, ib, M - j0 - 1, 1.0, Xb, lda, V + j0 + 1, M, 0.0, W,
+                                   M)) ||
+            (rc = lb_impl_gemm_f64(s, false, false, M - j0, ib, ib, 1.0, W, M, T, kPanel, 0.0, W2, M)) ||
+            (rc = lb_impl_gemm_f64(s, false, true, M - j0, M - j0 - 1, ib, -1.0, W2, M, V + j0 + 1, M, 1.0, Xb,
+                                   lda)))
             return rc;
         hipLaunchKernelGGL(k_bh_fix, dim3(lb_blocks(M, 256), ib), dim3(256), 0, s, A, lda, M, j0,
                            (const double*)betas);
@@ -1158,14 +1149,7 @@ int lb_impl_hessenberg(lb_ctx* c, int M, double* A, int64_t lda) {
     if (M >= kBlockedMin) {
         int rc = lb_ws_reserve(c, lay.end);
         if (rc) return rc;
-        rocblas_handle h = nullptr;
-        if (rocblas_create_handle(&h) != rocblas_status_success)
-            return lb_fail(LB_ERR_DEVICE, "rocblas_create_handle failed");
-        rc = blas_check(rocblas_set_stream(h, s));
-        if (!rc) rc = blas_check(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host));
-        if (!rc) rc = hessenberg_blocked(c, M, A, lda, h);
-        (void)rocblas_destroy_handle(h);
-        return rc;
+        return hessenberg_blocked(c, M, A, lda);
     }
     const size_t o_v = lay.v, o_p = lay.p, o_q = lay.q, o_sc = lay.sc, o_qp = lay.qp;
     int rc = lb_ws_reserve(c, lay.end);
