@@ -61,6 +61,8 @@ struct Ticket {
     lb_request req;
     int64_t id = 0;
     size_t footprint = 0;
+    size_t join_footprint = 0;  // its footprint when it shares an earlier request's preparation
+    int group = 0;              // index of its preparation within the batch
     System* sys = nullptr;
     int status = 1;  // 1 = pending, 0 = ok, < 0 = error
     bool done = false;
@@ -79,9 +81,28 @@ class Executor {
     virtual void free_system(System* y) = 0;
 };
 
-inline bool same_shape(const lb_request& a, const lb_request& b) {
-    return a.kind == LB_REQ_DENSE && b.kind == LB_REQ_DENSE && a.N == b.N && a.B == b.B && a.dt == b.dt &&
-           a.steps == b.steps && a.precision == b.precision;
+// Dense requests that may be integrated in one pass over several prepared
+// systems (one launch per stage for all of them).
+inline bool same_pass(const lb_request& a, const lb_request& b) {
+    return a.kind == LB_REQ_DENSE && b.kind == LB_REQ_DENSE && a.N == b.N && a.dt == b.dt && a.steps == b.steps &&
+           a.precision == b.precision;
+}
+
+inline bool same_csr(const lb_csr_c128& a, const lb_csr_c128& b) {
+    return a.rowptr == b.rowptr && a.col == b.col && a.val == b.val && a.nnz == b.nnz;
+}
+
+// Requests whose preparation is the same: dense or sparse, the same N, the
+// same input arrays (device pointers; for sparse requests also the same
+// rates), dt, steps and precision. They share one preparation and one pass.
+inline bool same_inputs(const lb_request& a, const lb_request& b) {
+    if (a.kind != b.kind || a.N != b.N || a.dt != b.dt || a.steps != b.steps || a.precision != b.precision)
+        return false;
+    if (a.kind == LB_REQ_DENSE) return a.H == b.H && a.gamma == b.gamma;
+    if (a.kind != LB_REQ_SPARSE || a.P != b.P || !same_csr(a.Hs, b.Hs)) return false;
+    for (int p = 0; p < a.P; ++p)
+        if (!(a.rates[p] == b.rates[p]) || !same_csr(a.L[p], b.L[p])) return false;
+    return true;
 }
 
 inline bool same_system_pass(const lb_request& a, const lb_request& b) {
@@ -101,11 +122,13 @@ class Core {
         for (int i = 0; i < slots; ++i) workers_.emplace_back(&Core::worker, this, i);
     }
 
-    // Queues a dense or sparse request of footprint fp bytes.
-    int submit(const lb_request& r, size_t fp, int64_t* ticket, const char** why) {
+    // Queues a dense or sparse request of footprint fp bytes (join_fp when it
+    // shares the preparation of an earlier request in its batch).
+    int submit(const lb_request& r, size_t fp, size_t join_fp, int64_t* ticket, const char** why) {
         Ticket* t = new Ticket();
         t->req = r;
         t->footprint = fp;
+        t->join_footprint = join_fp < fp ? join_fp : fp;
         t->t_submit = now_s();
         {
             std::lock_guard<std::mutex> lk(mu_);
@@ -399,16 +422,38 @@ class Core {
                     ++it;
                 }
             }
-        } else if (h->req.kind == LB_REQ_DENSE) {
-            for (auto it = queue_.begin(); it != queue_.end() && (int)batch.size() < max_batch_;) {
+        } else {
+            // queued requests with the same inputs as a group of the batch join
+            // it (one preparation, at most LB_SYSTEM_BATCH states, footprint of
+            // their states only); dense requests of the same pass shape on other
+            // inputs open further groups, at most max_batch_ groups. A request
+            // of more than LB_SYSTEM_BATCH states runs alone.
+            h->group = 0;
+            std::vector<const lb_request*> reps(1, &h->req);
+            std::vector<int> states(1, h->req.B);
+            const bool solo = h->req.B > LB_SYSTEM_BATCH;
+            for (auto it = queue_.begin(); !solo && it != queue_.end();) {
                 Ticket* t = *it;
-                if (same_shape(h->req, t->req) && used_ + t->footprint <= budget_) {
-                    used_ += t->footprint;
-                    batch.push_back(t);
-                    it = queue_.erase(it);
+                int g = -1;
+                if (t->req.B <= LB_SYSTEM_BATCH)
+                    for (size_t i = 0; i < reps.size() && g < 0; ++i)
+                        if (same_inputs(*reps[i], t->req) && states[i] + t->req.B <= LB_SYSTEM_BATCH) g = (int)i;
+                if (g >= 0 && used_ + t->join_footprint <= budget_) {
+                    t->footprint = t->join_footprint;
+                } else if (g < 0 && t->req.B <= LB_SYSTEM_BATCH && same_pass(h->req, t->req) &&
+                           (int)reps.size() < max_batch_ && used_ + t->footprint <= budget_) {
+                    g = (int)reps.size();
+                    reps.push_back(&t->req);
+                    states.push_back(0);
                 } else {
                     ++it;
+                    continue;
                 }
+                used_ += t->footprint;
+                states[g] += t->req.B;
+                t->group = g;
+                batch.push_back(t);
+                it = queue_.erase(it);
             }
         }
         if (used_ > peak_) peak_ = used_;

@@ -10,18 +10,21 @@
 //   * admission: a free slot takes the queue head if its footprint fits in the
 //     remaining budget (head-of-line order is kept: a head that does not fit
 //     waits for memory to be released; one that can never fit next to the
-//     registered systems is failed), then also takes up to max_batch-1
-//     further queued dense requests with the same (N, B, dt, steps,
-//     precision) that fit, and runs them as one batch: one preparation per
-//     request, then a single batched RK4 integration (one launch per stage for
-//     all of them);
+//     registered systems is failed), then the queued requests that can share
+//     its batch: those with the same inputs (the same H, gamma or CSR arrays,
+//     dt, steps, precision) join a group that is prepared once and whose states
+//     are packed into one block of at most 16, and dense requests with the same
+//     (N, dt, steps, precision) on other inputs open further groups, up to
+//     max_batch; the batch is integrated with one launch per stage for all its
+//     groups;
 //   * per-request buffers (Q, K, CSR arrays) come from the stream-ordered
 //     allocator of the slot's stream and are released when the batch ends.
 // Requests arriving while others run are admitted as soon as a slot and
 // memory are free, so their work overlaps on the device. Every kernel used
-// here is deterministic for a fixed launch configuration and the tile choice
-// does not depend on the batch size, so a request's result is the same alone
-// and in a mix.
+// here is deterministic for a fixed launch configuration, dense blocks always
+// run the 16-state matrix-core path with its default tile (a request of more
+// than 16 states runs alone on the path of its size) and the CSR kernel treats
+// states independently, so a request's result is the same alone and in a mix.
 //
 // Resident systems: lindblad_server_register prepares a Lindbladian's Q and K
 // once (on a registration context of its own) and keeps them until released;
@@ -98,6 +101,13 @@ static size_t sparse_q_bytes(int N) {
            sizeof(double) * M;
 }
 
+// Share of a request's states in the state block of its group: a group's block
+// holds at most LB_SYSTEM_BATCH states (a larger request runs alone).
+static size_t request_stage_bytes(int N, int B) {
+    const int64_t M = (int64_t)N * N - 1;
+    return sizeof(double) * (size_t)std::max(B, LB_SYSTEM_BATCH) * M;
+}
+
 // Staging of a system batch's states: input and output blocks of up to
 // LB_SYSTEM_BATCH states.
 static size_t system_stage_bytes(int64_t M) { return sizeof(double) * 2 * (size_t)LB_SYSTEM_BATCH * M; }
@@ -169,28 +179,67 @@ static int run_batch(lb_server* s, int slot, std::vector<Ticket*>& batch) {
         allocs.push_back(*p);
         return LB_OK;
     };
+    // groups: one preparation each; their requests' states packed into one block
+    int G = 0;
+    for (Ticket* t : batch) G = std::max(G, t->group + 1);
+    std::vector<int> gstates(G, 0);
+    std::vector<const lb_request*> rep(G, nullptr);
+    for (Ticket* t : batch) {
+        gstates[t->group] += t->req.B;
+        if (!rep[t->group]) rep[t->group] = &t->req;
+    }
+    const bool solo = G == 1 && gstates[0] > LB_SYSTEM_BATCH;
+    // dense blocks: at least 2 states, the same count in every group (padding
+    // states are zero); sparse blocks: the group's states
+    int Brun = 2;
+    for (int g = 0; g < G; ++g) Brun = std::max(Brun, gstates[g]);
+    if (r0.kind == LB_REQ_SPARSE) Brun = gstates[0];
+    std::vector<double*> X(G, nullptr);
+    for (int g = 0; g < G && !rc; ++g) {
+        void* p = nullptr;
+        rc = dalloc(sizeof(double) * (size_t)Brun * M, &p);
+        X[g] = (double*)p;
+    }
+    std::vector<int64_t> off(batch.size(), 0);
+    {
+        std::vector<int64_t> fill(G, 0);
+        for (size_t i = 0; i < batch.size() && !rc; ++i) {
+            const lb_request& r = batch[i]->req;
+            const int g = batch[i]->group;
+            off[i] = fill[g];
+            if (hipMemcpyAsync(X[g] + fill[g], r.V0, sizeof(double) * (size_t)r.B * M, hipMemcpyDeviceToDevice,
+                               st) != hipSuccess)
+                rc = lb_fail(LB_ERR_DEVICE, "copy of the initial states failed");
+            fill[g] += (int64_t)r.B * M;
+        }
+        for (int g = 0; g < G && !rc; ++g)
+            if (fill[g] < (int64_t)Brun * M &&
+                hipMemsetAsync(X[g] + fill[g], 0, sizeof(double) * (size_t)((int64_t)Brun * M - fill[g]), st) !=
+                    hipSuccess)
+                rc = lb_fail(LB_ERR_DEVICE, "clearing the padding states failed");
+    }
     if (r0.kind == LB_REQ_DENSE) {
         const int64_t ldq = lb_default_ldq(M);
-        const int R = (int)batch.size();
-        std::vector<lb_prop_sys> sys(R);
-        for (int i = 0; i < R && !rc; ++i) {
-            const lb_request& r = batch[i]->req;
+        std::vector<lb_prop_sys> sys(G);
+        for (int g = 0; g < G && !rc; ++g) {
+            const lb_request& r = *rep[g];
             void *Q = nullptr, *K = nullptr, *Q32 = nullptr;
             rc = dalloc(sizeof(double) * (size_t)M * ldq, &Q);
             if (!rc) rc = dalloc(sizeof(double) * M, &K);
             if (!rc && r.precision == LB_FP32) rc = dalloc(sizeof(float) * (size_t)M * ldq, &Q32);
             if (!rc) rc = lb_impl_prepare_dense(c, N, r.H, r.gamma, (double*)Q, ldq, (double*)K);
             if (!rc && r.precision == LB_FP32) rc = lb_impl_q_to_f32(c, M, (double*)Q, ldq, (float*)Q32);
-            if (!rc && hipMemcpyAsync(r.Vout, r.V0, sizeof(double) * (size_t)r.B * M, hipMemcpyDeviceToDevice, st) !=
-                           hipSuccess)
-                rc = lb_fail(LB_ERR_DEVICE, "copy of the initial states failed");
-            sys[i] = lb_prop_sys{(const double*)Q, (const float*)Q32, (const double*)K, r.Vout};
+            sys[g] = lb_prop_sys{(const double*)Q, (const float*)Q32, (const double*)K, X[g]};
         }
-        if (!rc) rc = lb_impl_propagate(c, R, M, sys.data(), ldq, r0.B, r0.dt, r0.steps, r0.precision, nullptr);
+        // the 16-state matrix-core path with its default tile whatever the
+        // batch holds, so that every state column is summed in the same order
+        const lb_tile tile = lb_default_tile(M, 16, r0.precision, 1);
+        if (!rc) rc = lb_impl_propagate(c, G, M, sys.data(), ldq, Brun, r0.dt, r0.steps, r0.precision,
+                                        solo ? nullptr : &tile);
     } else {
         const lb_request& r = r0;
         int64_t nnz = 0;
-        rc = lb_impl_sparse(c, N, &r.Hs, r.P, r.rates, r.L, &nnz, nullptr, nullptr, nullptr, nullptr);
+        if (!rc) rc = lb_impl_sparse(c, N, &r.Hs, r.P, r.rates, r.L, &nnz, nullptr, nullptr, nullptr, nullptr);
         void *rp = nullptr, *col = nullptr, *val = nullptr, *K = nullptr;
         if (!rc) rc = dalloc(sizeof(int64_t) * (M + 1), &rp);
         if (!rc) rc = dalloc(sizeof(int64_t) * (nnz > 0 ? nnz : 1), &col);
@@ -199,12 +248,15 @@ static int run_batch(lb_server* s, int slot, std::vector<Ticket*>& batch) {
         if (!rc)
             rc = lb_impl_sparse(c, N, &r.Hs, r.P, r.rates, r.L, &nnz, (int64_t*)rp, (int64_t*)col, (double*)val,
                                 (double*)K);
-        if (!rc && hipMemcpyAsync(r.Vout, r.V0, sizeof(double) * (size_t)r.B * M, hipMemcpyDeviceToDevice, st) !=
-                       hipSuccess)
-            rc = lb_fail(LB_ERR_DEVICE, "copy of the initial states failed");
         if (!rc)
             rc = lb_impl_propagate_csr(c, M, (const int64_t*)rp, (const int64_t*)col, (const double*)val,
-                                       (const double*)K, r.Vout, r.B, r.dt, r.steps);
+                                       (const double*)K, X[0], Brun, r.dt, r.steps);
+    }
+    for (size_t i = 0; i < batch.size() && !rc; ++i) {
+        const lb_request& r = batch[i]->req;
+        if (hipMemcpyAsync(r.Vout, X[batch[i]->group] + off[i], sizeof(double) * (size_t)r.B * M,
+                           hipMemcpyDeviceToDevice, st) != hipSuccess)
+            rc = lb_fail(LB_ERR_DEVICE, "copy of the results failed");
     }
     for (void* p : allocs) (void)hipFreeAsync(p, st);
     hipError_t e = hipStreamSynchronize(st);
@@ -308,8 +360,9 @@ int lindblad_server_submit(lb_server* s, const lb_request* r, int64_t* ticket) {
         return lb_fail(LB_ERR_INVALID_ARG, "unknown precision");
     if (r->kind == LB_REQ_SPARSE && (r->P < 0 || r->P > LB_REQ_MAX_JUMPS || !r->Hs.rowptr))
         return lb_fail(LB_ERR_INVALID_ARG, "sparse request needs H and at most %d jump operators", LB_REQ_MAX_JUMPS);
-    const size_t fp = r->kind == LB_REQ_DENSE ? dense_q_bytes(r->N, r->precision) : sparse_q_bytes(r->N);
-    return sched_fail(s->core->submit(*r, fp, ticket, &why), why);
+    const size_t stage = request_stage_bytes(r->N, r->B);
+    const size_t fp = (r->kind == LB_REQ_DENSE ? dense_q_bytes(r->N, r->precision) : sparse_q_bytes(r->N)) + stage;
+    return sched_fail(s->core->submit(*r, fp, stage, ticket, &why), why);
 }
 
 int lindblad_server_register(lb_server* s, const lb_request* r, int64_t* system) {

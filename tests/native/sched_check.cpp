@@ -16,6 +16,11 @@
 //   shutdown   shutdown with queued requests cancels them and returns
 //   oom        an injected allocation failure is reported on its ticket and
 //              its footprint is returned to the budget
+//   group      queued requests with the same inputs share their head's
+//              preparation (at most 16 states per group, footprint of their
+//              states only), other inputs of the same pass shape open further
+//              groups up to max_batch, a request of more than 16 states runs
+//              alone
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -53,17 +58,46 @@ struct Stub : lb_sched::Executor {
     std::atomic<int> at_gate{0};
     unsigned sleep_us = 0;
 
+    std::mutex last_mu;
+    std::vector<std::pair<int, int>> last;  // (group, B) of each ticket of the latest batch
+
     int run(int slot, std::vector<Ticket*>& b) override {
         (void)slot;
         runs++;
         int64_t fp = 0;
         int states = 0;
         const lb_request& h = b[0]->req;
-        if ((int)b.size() > max_batch) bad = true;
+        if (h.kind == LB_REQ_SYSTEM) {
+            if ((int)b.size() > max_batch) bad = true;
+            for (Ticket* t : b)
+                if (t != b[0] && !lb_sched::same_system_pass(h, t->req)) bad = true;
+        } else {
+            // groups: every member shares its group's first request's inputs, at
+            // most 16 states per group (unless the request runs alone), groups of
+            // one pass shape, at most max_batch of them
+            std::vector<const Ticket*> rep;
+            std::vector<int> gs;
+            for (Ticket* t : b) {
+                if (t->group < 0 || t->group > (int)rep.size()) bad = true;
+                if (t->group == (int)rep.size()) {
+                    rep.push_back(t);
+                    gs.push_back(0);
+                    if (t != b[0] && !lb_sched::same_pass(h, t->req)) bad = true;
+                } else if (t->group >= 0 && !lb_sched::same_inputs(rep[t->group]->req, t->req)) {
+                    bad = true;
+                }
+                if (t->group >= 0 && t->group < (int)gs.size()) gs[t->group] += t->req.B;
+            }
+            if ((int)rep.size() > max_batch) bad = true;
+            for (int x : gs)
+                if (x > LB_SYSTEM_BATCH && b.size() > 1) bad = true;
+            std::lock_guard<std::mutex> lk(last_mu);
+            last.clear();
+            for (Ticket* t : b) last.push_back({t->group, t->req.B});
+        }
         for (Ticket* t : b) {
             fp += (int64_t)t->footprint;
             states += t->req.B;
-            if (t != b[0] && !(lb_sched::same_shape(h, t->req) || lb_sched::same_system_pass(h, t->req))) bad = true;
         }
         if (h.kind == LB_REQ_SYSTEM && states > LB_SYSTEM_BATCH) bad = true;
         const int64_t now = inflight.fetch_add(fp) + fp;
@@ -98,7 +132,11 @@ struct Stub : lb_sched::Executor {
     }
 };
 
-static lb_request plain(int kind, int N, int B, int64_t steps) {
+// Input arrays are only compared, never read: a request gets addresses of its
+// own (plain) or those of a shared key (shared).
+static std::atomic<uintptr_t> g_next_input{0x10000};
+
+static lb_request with_inputs(int kind, int N, int B, int64_t steps, uintptr_t base) {
     lb_request r;
     memset(&r, 0, sizeof(r));
     r.kind = kind;
@@ -107,7 +145,23 @@ static lb_request plain(int kind, int N, int B, int64_t steps) {
     r.dt = 1e-3;
     r.steps = steps;
     r.precision = LB_FP64;
+    if (kind == LB_REQ_DENSE) {
+        r.H = (const double*)base;
+        r.gamma = (const double*)(base + 8);
+    } else if (kind == LB_REQ_SPARSE) {
+        r.Hs.rowptr = (const int64_t*)base;
+        r.Hs.col = (const int64_t*)(base + 8);
+        r.Hs.val = (const double*)(base + 16);
+    }
     return r;
+}
+
+static lb_request plain(int kind, int N, int B, int64_t steps) {
+    return with_inputs(kind, N, B, steps, g_next_input.fetch_add(64));
+}
+
+static lb_request shared(int kind, int N, int B, int64_t steps, int key) {
+    return with_inputs(kind, N, B, steps, 0x100 + 64 * (uintptr_t)key);
 }
 
 static lb_request on_system(int64_t sid, int B, int64_t steps) {
@@ -158,9 +212,15 @@ static void scenario_stress() {
                     int rc;
                     if (k < 6) {
                         const int N = 4 + (int)(g() % 3);
-                        rc = core.submit(plain(LB_REQ_DENSE, N, 1 + (int)(g() % 2), steps), 100 * (size_t)N - 300, &t, &why);
+                        rc = core.submit(plain(LB_REQ_DENSE, N, 1 + (int)(g() % 2), steps), 100 * (size_t)N - 300, 20, &t, &why);
+                    } else if (k < 7) {
+                        rc = core.submit(plain(LB_REQ_SPARSE, 5, 1, steps), 150, 20, &t, &why);
                     } else if (k < 8) {
-                        rc = core.submit(plain(LB_REQ_SPARSE, 5, 1, steps), 150, &t, &why);
+                        // shared inputs: grouped with queued requests on the same key
+                        const int key = (int)(g() % 3);
+                        rc = core.submit(shared(key == 2 ? LB_REQ_SPARSE : LB_REQ_DENSE, 5, 1 + (int)(g() % 6), steps,
+                                                key),
+                                         200, 30, &t, &why);
                     } else {
                         const int64_t sid = sys_ids[g() % 3].load();
                         if (!sid) continue;
@@ -227,20 +287,20 @@ static void scenario_registered() {
     int64_t sid = 0, t = 0;
     CHECK(register_sys(core, ex, 900, 50, &sid) == LB_OK);
     const char* why = nullptr;
-    CHECK(core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 200, &t, &why) == LB_ERR_ADMISSION);
+    CHECK(core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 200, 200, &t, &why) == LB_ERR_ADMISSION);
     std::vector<int64_t> ts;
     for (int i = 0; i < 8; ++i) {
         CHECK(core.submit_system(on_system(sid, 1, 10), &t, &why) == LB_OK);
         ts.push_back(t);
     }
-    CHECK(core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 90, &t, &why) == LB_OK);
+    CHECK(core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 90, 90, &t, &why) == LB_OK);
     ts.push_back(t);
     for (int64_t x : ts) {
         bool known = false;
         CHECK(core.wait(x, &known) == LB_OK);
     }
     CHECK(core.release(sid, &why) == LB_OK);
-    CHECK(core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 200, &t, &why) == LB_OK);
+    CHECK(core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 200, 200, &t, &why) == LB_OK);
     bool known = false;
     CHECK(core.wait(t, &known) == LB_OK);
     printf("registered: plain request refused next to a full system, system requests ran\n");
@@ -255,11 +315,11 @@ static void scenario_late() {
         ex.close_gate();
         const char* why = nullptr;
         int64_t a = 0, b = 0, sid = 0;
-        CHECK(core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 700, &a, &why) == LB_OK);
+        CHECK(core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 700, 700, &a, &why) == LB_OK);
         ex.wait_at_gate(1);
         std::thread reg([&] { CHECK(register_sys(core, ex, 400, 10, &sid) == LB_OK); });
         std::this_thread::sleep_for(std::chrono::microseconds(200));
-        const int rb = core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 700, &b, &why);
+        const int rb = core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 700, 700, &b, &why);
         CHECK(rb == LB_OK || rb == LB_ERR_ADMISSION);  // refused if the reservation already counts
         if (rb != LB_OK) b = 0;
         ex.open_gate();
@@ -283,9 +343,9 @@ static void scenario_refuse() {
     ex.close_gate();
     const char* why = nullptr;
     int64_t a = 0, b = 0, sid = 0;
-    CHECK(core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 500, &a, &why) == LB_OK);
+    CHECK(core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 500, 500, &a, &why) == LB_OK);
     ex.wait_at_gate(1);
-    CHECK(core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 600, &b, &why) == LB_OK);  // queued behind a
+    CHECK(core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 600, 600, &b, &why) == LB_OK);  // queued behind a
     CHECK(register_sys(core, ex, 500, 10, &sid) == LB_ERR_ADMISSION);  // 500 + 600 > 1000
     CHECK(register_sys(core, ex, 300, 10, &sid) == LB_OK);             // 300 + 600 fits
     ex.open_gate();
@@ -304,11 +364,11 @@ static void scenario_shutdown() {
     core->start(1, &ex);
     ex.close_gate();
     const char* why = nullptr;
-    CHECK(core->submit(plain(LB_REQ_DENSE, 6, 1, 10), 600, &first, &why) == LB_OK);
+    CHECK(core->submit(plain(LB_REQ_DENSE, 6, 1, 10), 600, 600, &first, &why) == LB_OK);
     ex.wait_at_gate(1);
     for (int i = 0; i < 10; ++i) {
         int64_t t = 0;
-        CHECK(core->submit(plain(LB_REQ_DENSE, 7, 1, 10), 600, &t, &why) == LB_OK);
+        CHECK(core->submit(plain(LB_REQ_DENSE, 7, 1, 10), 600, 600, &t, &why) == LB_OK);
         queued.push_back(t);
     }
     std::atomic<int> cancelled{0};
@@ -335,13 +395,51 @@ static void scenario_oom() {
     core.start(2, &ex);
     const char* why = nullptr;
     int64_t bad = 0, good = 0;
-    CHECK(core.submit(plain(LB_REQ_SPARSE, 6, 1, kFailSteps), 900, &bad, &why) == LB_OK);
-    CHECK(core.submit(plain(LB_REQ_SPARSE, 6, 1, 10), 900, &good, &why) == LB_OK);
+    CHECK(core.submit(plain(LB_REQ_SPARSE, 6, 1, kFailSteps), 900, 900, &bad, &why) == LB_OK);
+    CHECK(core.submit(plain(LB_REQ_SPARSE, 6, 1, 10), 900, 900, &good, &why) == LB_OK);
     bool known = false;
     CHECK(core.wait(bad, &known) == LB_ERR_OOM);
     CHECK(core.wait(good, &known) == LB_OK);
     CHECK(core.used_bytes() == 0);
     printf("oom: injected allocation failure reported, budget returned\n");
+}
+
+static void scenario_group() {
+    Stub ex;
+    ex.budget = 10000;
+    ex.max_batch = 2;
+    Core core(10000, 2);
+    core.start(1, &ex);
+    ex.close_gate();
+    const char* why = nullptr;
+    int64_t t = 0;
+    std::vector<int64_t> all;
+    CHECK(core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 500, 50, &t, &why) == LB_OK);  // runs first, holds the slot
+    all.push_back(t);
+    ex.wait_at_gate(1);
+    // head of the next batch and four more on its inputs: 4 + 4 + 4 + 4 states
+    // fill group 0, the fifth opens group 1 (same inputs, group full)
+    for (int i = 0; i < 5; ++i) {
+        CHECK(core.submit(shared(LB_REQ_DENSE, 6, 4, 10, 7), 500, 50, &t, &why) == LB_OK);
+        all.push_back(t);
+    }
+    CHECK(core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 500, 50, &t, &why) == LB_OK);   // a third group: over max_batch
+    all.push_back(t);
+    CHECK(core.submit(plain(LB_REQ_DENSE, 6, 20, 10), 500, 50, &t, &why) == LB_OK);  // more than 16 states: alone
+    all.push_back(t);
+    ex.open_gate();
+    bool known = false;
+    for (int64_t x : all) CHECK(core.wait(x, &known) == LB_OK);
+    CHECK(core.used_bytes() == 0);
+    int64_t completed = 0, batches = 0, batched = 0;
+    size_t peak = 0;
+    core.stats(&completed, &peak, &batches, &batched);
+    // batches: the first request, {group 0: 4 requests, group 1: 1}, the plain one, the 20-state one
+    CHECK(batches == 4);
+    CHECK(batched == 5);
+    // peak: the second batch, two preparations (500 each) and three joiners (50 each)
+    CHECK(peak == 500 + 3 * 50 + 500);
+    printf("group: same-input requests shared one preparation, footprints of joiners counted as states only\n");
 }
 
 int main(int argc, char** argv) {
@@ -352,6 +450,7 @@ int main(int argc, char** argv) {
     if (s == "refuse" || s == "all") scenario_refuse();
     if (s == "shutdown" || s == "all") scenario_shutdown();
     if (s == "oom" || s == "all") scenario_oom();
+    if (s == "group" || s == "all") scenario_group();
     printf("OK\n");
     return 0;
 }

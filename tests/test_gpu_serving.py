@@ -22,7 +22,10 @@ def dcsr(A):
     return (torch.from_numpy(rp).cuda(), torch.from_numpy(c).cuda(), torch.from_numpy(v).cuda())
 
 
-def make_mix(lb, n_req=30, seed=0):
+FP32_TOL = 2e-5  # served FP32 requests against the FP64 oracle, normwise relative
+
+
+def make_mix(lb, n_req=30, seed=0, fp32_share=0.0):
     g = wl.rng(seed)
     ctx = lb.Context(0)
     pool = {}
@@ -38,38 +41,51 @@ def make_mix(lb, n_req=30, seed=0):
             if key not in pool:
                 H, gamma = wl.random_lindbladian(N, 10 * N + key[1])
                 pool[key] = (torch.from_numpy(H).cuda(), torch.from_numpy(gamma).cuda(), H, gamma)
-            reqs.append(("dense", N, pool[key], V0, steps))
+            prec = lb.FP32 if g.random() < fp32_share else lb.FP64
+            reqs.append(("dense", N, pool[key], V0, steps, prec))
         else:
             H, rates, Ls = wl.dimer_model(N)
-            reqs.append(("sparse", N, (dcsr(H), rates, [dcsr(L) for L in Ls], H, Ls), V0, steps))
+            reqs.append(("sparse", N, (dcsr(H), rates, [dcsr(L) for L in Ls], H, Ls), V0, steps, lb.FP64))
     torch.cuda.synchronize()
     return ctx, reqs
 
 
-def run_alone(lb, ctx, req, dt=1e-3):
-    kind, N, sysd, V0, steps = req
-    V = V0.clone()
-    if kind == "dense":
-        Q, K = lb.lindblad_prepare(ctx, sysd[0], sysd[1])
-        lb.lindblad_propagate(ctx, Q, K, V, dt, steps)
-    else:
-        rp, col, val, K = lb.lindblad_prepare_sparse(ctx, N, sysd[0], sysd[1], sysd[2])
-        lb.lindblad_propagate_csr(ctx, rp, col, val, K, V, dt, steps)
-    ctx.sync()
-    return V
-
-
 def submit(srv, req, dt=1e-3):
-    kind, N, sysd, V0, steps = req
+    kind, N, sysd, V0, steps, prec = req
     if kind == "dense":
-        return srv.submit_dense(sysd[0], sysd[1], V0, dt, steps)
+        return srv.submit_dense(sysd[0], sysd[1], V0, dt, steps, precision=prec)
     return srv.submit_sparse(N, sysd[0], sysd[1], sysd[2], V0, dt, steps)
 
 
+def run_each_alone(lb, reqs):
+    """Every request through a one-slot server without batching, one at a time."""
+    srv = lb.Server(0, budget_bytes=1 << 30, slots=1, max_batch=1, max_N=32)
+    outs = []
+    for r in reqs:
+        t, V = submit(srv, r)
+        srv.wait(t)
+        outs.append(V)
+    srv.close()
+    return outs
+
+
+def oracle_result(oracle, req, dt=1e-3):
+    kind, N, sysd, V0, steps, _ = req
+    M = N * N - 1
+    if kind == "dense":
+        Qo, Ko = oracle.prepare_dense(sysd[2], sysd[3])
+    else:
+        Qo, Ko = oracle.prepare_factored(sysd[3], sysd[1], sysd[4], np.arange(M))
+    return oracle.rk4_dense(Qo, Ko, V0.cpu().numpy(), dt, steps)
+
+
 def test_mix_equals_alone(lb):
+    """FP64 and FP32 (30 %) dense and sparse requests: each result is the same
+    bit for bit in a concurrent mix (requests on the same inputs sharing one
+    preparation and one pass, several systems per launch) as run alone."""
     print("[gpu] serving mix vs alone", flush=True)
-    ctx, reqs = make_mix(lb)
-    alone = [run_alone(lb, ctx, r) for r in reqs]
+    ctx, reqs = make_mix(lb, fp32_share=0.3)
+    alone = run_each_alone(lb, reqs)
     srv = lb.Server(0, budget_bytes=1 << 30, slots=3, max_batch=4, max_N=32)
     tickets = [submit(srv, r) for r in reqs]
     for t, _ in tickets:
@@ -83,34 +99,65 @@ def test_mix_equals_alone(lb):
     ctx.close()
 
 
+def test_same_inputs_share_one_preparation(lb, oracle):
+    """Requests on the same (H, gamma) queued together are prepared once and
+    integrated in one pass (up to 16 states); results equal the requests run
+    alone and the oracle."""
+    ctx = lb.Context(0)
+    N = 9
+    H, gamma = wl.random_lindbladian(N, 77)
+    Hd, gd = torch.from_numpy(H).cuda(), torch.from_numpy(gamma).cuda()
+    reqs = []
+    for i in range(10):
+        V0 = lb.lb_expand_pure(ctx, torch.from_numpy(wl.random_pure_states(N, 1 + i % 3, 900 + i)).cuda())
+        reqs.append(("dense", N, (Hd, gd, H, gamma), V0, 50, lb.FP64))
+    torch.cuda.synchronize()
+    alone = run_each_alone(lb, reqs)
+    srv = lb.Server(0, budget_bytes=1 << 30, slots=1, max_batch=4, max_N=32)
+    tickets = [submit(srv, r) for r in reqs]
+    for t, _ in tickets:
+        srv.wait(t)
+    st = srv.stats()
+    srv.close()
+    assert st["batched_requests"] >= 2 and st["batches"] < len(reqs)
+    for (t, Vout), ref, req in zip(tickets, alone, reqs):
+        assert torch.equal(Vout, ref)
+        Vo = oracle_result(oracle, req)
+        assert np.abs(Vout.cpu().numpy() - Vo).max() / np.abs(Vo).max() < 1e-10
+    ctx.close()
+
+
 def test_served_results_match_oracle(lb, oracle):
-    ctx, reqs = make_mix(lb, n_req=8, seed=3)
+    """FP64 requests within 1e-10 of the oracle, FP32 opt-in requests within
+    FP32_TOL (normwise relative)."""
+    ctx, reqs = make_mix(lb, n_req=10, seed=3, fp32_share=0.4)
     srv = lb.Server(0, budget_bytes=1 << 30, slots=2, max_batch=4, max_N=32)
     tickets = [submit(srv, r) for r in reqs]
+    nfp32 = 0
     for (t, Vout), req in zip(tickets, reqs):
         srv.wait(t)
-        kind, N, sysd, V0, steps = req
-        M = N * N - 1
-        if kind == "dense":
-            Qo, Ko = oracle.prepare_dense(sysd[2], sysd[3])
-        else:
-            Qo, Ko = oracle.prepare_factored(sysd[3], sysd[1], sysd[4], np.arange(M))
-        Vo = oracle.rk4_dense(Qo, Ko, V0.cpu().numpy(), 1e-3, steps)
+        Vo = oracle_result(oracle, req)
         err = np.abs(Vout.cpu().numpy() - Vo).max() / np.abs(Vo).max()
-        assert err < 1e-10, (kind, N, err)
+        if req[5] == lb.FP32:
+            nfp32 += 1
+            assert err < FP32_TOL, (req[0], req[1], err)
+        else:
+            assert err < 1e-10, (req[0], req[1], err)
+    assert nfp32 > 0
     srv.close()
     ctx.close()
 
 
 def test_budget_respected_and_admission(lb):
     ctx, reqs = make_mix(lb, n_req=16, seed=5)
-    # room for about two of the largest dense requests at a time
+    # room for about two of the largest dense requests at a time (Q, K and a
+    # 16-state block each)
     N = 18
     M = N * N - 1
     ldq = lb.default_ldq(M)
-    budget = 2 * (8 * M * ldq + 8 * M) + 1024
+    budget = 2 * (8 * M * ldq + 8 * M + 16 * 8 * M) + 1024
     srv = lb.Server(0, budget_bytes=budget, slots=4, max_batch=2, max_N=32)
-    tickets = [submit(srv, r) for r in reqs if r[0] == "dense"]
+    tickets = [submit(srv, r) for r in reqs if r[0] == "dense"]  # FP64 only (fp32_share 0)
     for t, _ in tickets:
         srv.wait(t)
     st = srv.stats()

@@ -36,7 +36,7 @@ def binaries(tmp_path_factory):
 
 
 @pytest.mark.parametrize("san", sorted(SANITIZERS))
-@pytest.mark.parametrize("scenario", ["stress", "registered", "late", "refuse", "shutdown", "oom"])
+@pytest.mark.parametrize("scenario", ["stress", "registered", "late", "refuse", "shutdown", "oom", "group"])
 def test_scheduler_under_sanitizer(binaries, san, scenario):
     env = dict(os.environ)
     env["TSAN_OPTIONS"] = "halt_on_error=1"
