@@ -146,9 +146,15 @@ def parse():
                          "sample and size-independent checks)")
     ap.add_argument("--persist-dir", default=None, help="c7: directory for the saved files (default: temp dir)")
     ap.add_argument("--ss-maxit", type=int, default=6000, help="c6s: GMRES iteration limit")
-    ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrival rate (requests/s)")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="Poisson arrival rate (requests/s); 0 with --arrival poisson: --rate-frac x the plain "
+                         "path's throughput measured on a burst of the first --rate-sample requests")
+    ap.add_argument("--rate-frac", type=float, default=0.8)
+    ap.add_argument("--rate-sample", type=int, default=400)
+    ap.add_argument("--fp32-share", type=float, default=0.0,
+                    help="c5/c5r: share of dense requests that opt in to FP32 matrix-core integration")
     ap.add_argument("--slots", type=int, default=6)
-    ap.add_argument("--max-batch", type=int, default=8)
+    ap.add_argument("--max-batch", type=int, default=16)
     ap.add_argument("--budget-gb", type=float, default=48.0)
     ap.add_argument("--serve-steps", type=int, default=500)
     return ap.parse_args()
@@ -178,27 +184,32 @@ def _serving_inputs(args, ctx, lb, wl, torch, np):
         dimers[N] = (tuple(torch.from_numpy(x).to(dev) for x in wl.to_csr(H)), rates,
                      [tuple(torch.from_numpy(x).to(dev) for x in wl.to_csr(L)) for L in Ls])
     reqs = []
+    gp = wl.rng(2025)  # FP32 opt-in draws, independent of the request mix
     for i in range(args.requests):
         N = int(g.choice(Ns))
         kind = "dense" if g.random() < 0.7 else "sparse"
         psi = torch.from_numpy(wl.random_pure_state(N, 1000 + i)[None, :]).to(dev)
         V0 = lb.lb_expand_pure(ctx, psi)
-        reqs.append((kind, N, int(g.integers(0, 4)), V0))
-    if args.arrival == "poisson":
-        if args.rate <= 0:
-            raise SystemExit("--arrival poisson needs --rate")
-        arrivals = np.cumsum(g.exponential(1.0 / args.rate, size=len(reqs)))
-    else:
-        arrivals = np.zeros(len(reqs))
+        prec = lb.FP32 if (kind == "dense" and gp.random() < args.fp32_share) else lb.FP64
+        reqs.append((kind, N, int(g.integers(0, 4)), V0, prec))
     torch.cuda.synchronize()
-    log("%d requests ready (%d dense)" % (len(reqs), sum(r[0] == "dense" for r in reqs)))
-    return Ns, pool, dimers, reqs, arrivals
+    log("%d requests ready (%d dense, %d of them FP32)" % (len(reqs), sum(r[0] == "dense" for r in reqs),
+                                                          sum(r[4] == lb.FP32 for r in reqs)))
+    return Ns, pool, dimers, reqs
+
+
+def _poisson_arrivals(n, rate):
+    """Arrival times (s) of a Poisson stream of `n` requests at `rate` per second (seeded)."""
+    from paper_1912_01491_amd import workloads as wl
+    import numpy as np
+    return np.cumsum(wl.rng(4242).exponential(1.0 / rate, size=n))
 
 
 def _serve(args, lb, np, reqs, arrivals, slots, max_batch, label, Ns, submit, setup=None):
-    """Runs the request list through one server: a feeder thread submits at the
-    arrival times, the main thread waits in order. Returns wall time, latencies
-    (completion - submission), stats and outputs."""
+    """Runs the request list through one server: a feeder thread submits each
+    request at its arrival time, the main thread waits in order. Returns wall
+    time, latencies (completion - submission, the submission being the
+    arrival), stats and outputs."""
     import threading
 
     srv = lb.Server(0, budget_bytes=int(args.budget_gb * (1 << 30)), slots=slots, max_batch=max_batch,
@@ -217,11 +228,19 @@ def _serve(args, lb, np, reqs, arrivals, slots, max_batch, label, Ns, submit, se
     t_start = time.perf_counter()
     th = threading.Thread(target=feeder)
     th.start()
-    th.join()
+    # wait in submission order while the feeder is still submitting
     for i in range(len(reqs)):
+        while tickets[i] is None and th.is_alive():
+            time.sleep(0.001)
+        if tickets[i] is None:  # the feeder ended early (it raised)
+            break
         srv.wait(tickets[i][0])
         if (i + 1) % 100 == 0:
             log("%s: %d of %d requests done after %.1f s" % (label, i + 1, len(reqs), time.perf_counter() - t_start))
+    th.join()
+    if any(t is None for t in tickets):
+        srv.close()
+        raise RuntimeError("%s: the feeder stopped before submitting every request" % label)
     wall = time.perf_counter() - t_start
     lat = np.array([srv.times(t)[2] - srv.times(t)[0] for t, _ in tickets])
     st = srv.stats()
@@ -253,7 +272,7 @@ def serving(args):
 
     resident = args.config == "c5r" or args.resident
     ctx = lb.Context(0)
-    Ns, pool, dimers, reqs, arrivals = _serving_inputs(args, ctx, lb, wl, torch, np)
+    Ns, pool, dimers, reqs = _serving_inputs(args, ctx, lb, wl, torch, np)
 
     if resident:
         def setup(srv):
@@ -267,23 +286,68 @@ def serving(args):
             return sids
 
         def submit(srv, sids, req):
-            kind, N, r, V0 = req
-            return srv.submit_system(sids[(kind, N, r if kind == "dense" else 0)], V0, args.dt, args.serve_steps)
+            kind, N, r, V0, prec = req
+            return srv.submit_system(sids[(kind, N, r if kind == "dense" else 0)], V0, args.dt, args.serve_steps,
+                                     precision=prec)
     else:
         setup = None
 
         def submit(srv, _, req):
-            kind, N, r, V0 = req
+            kind, N, r, V0, prec = req
             if kind == "dense":
                 H, gamma = pool[(N, r)]
-                return srv.submit_dense(H, gamma, V0, args.dt, args.serve_steps)
+                return srv.submit_dense(H, gamma, V0, args.dt, args.serve_steps, precision=prec)
             Hc, rates, Lc = dimers[N]
             return srv.submit_sparse(N, Hc, rates, Lc, V0, args.dt, args.serve_steps)
 
+    if resident and args.fp32_share > 0:
+        raise SystemExit("c5r registers FP64 systems; --fp32-share is for c5")
     mb = max(args.max_batch, 16) if resident else args.max_batch
+    rate, rate_from = args.rate, "given"
+    if args.arrival == "poisson":
+        if rate <= 0:
+            sample = reqs[:args.rate_sample]
+            w0, _, _, _ = _serve(args, lb, np, sample, np.zeros(len(sample)), 1, 1, "plain (rate sample)", Ns,
+                                 submit, setup)
+            rate = args.rate_frac * len(sample) / w0
+            rate_from = ("%.2f x the plain path's throughput on a burst of the first %d requests (%.3f solves/s)"
+                         % (args.rate_frac, len(sample), len(sample) / w0))
+        arrivals = _poisson_arrivals(len(reqs), rate)
+        log("Poisson arrivals at %.3f requests/s (%s)" % (rate, rate_from))
+    else:
+        arrivals = np.zeros(len(reqs))
     w_s, lat_s, st_s, out_s = _serve(args, lb, np, reqs, arrivals, args.slots, mb, "served", Ns, submit, setup)
     w_p, lat_p, st_p, out_p = _serve(args, lb, np, reqs, arrivals, 1, 1, "plain", Ns, submit, setup)
     same = all(torch.equal(a, b) for a, b in zip(out_s, out_p))
+    fp32 = None
+    i32 = [i for i, r in enumerate(reqs) if r[4] == lb.FP32]
+    if i32:
+        # the FP32 requests again in FP64 (alone, one slot) and, for N <= 32, the oracle
+        ref = [(r[0], r[1], r[2], r[3], lb.FP64) for r in (reqs[i] for i in i32)]
+        _, _, _, out64 = _serve(args, lb, np, ref, np.zeros(len(ref)), 1, 1, "FP64 reference of the FP32 requests",
+                                Ns, submit, setup)
+        errs = []
+        for i, v64 in zip(i32, out64):
+            a, b = out_s[i].cpu().numpy(), v64.cpu().numpy()
+            errs.append(float(np.abs(a - b).max() / np.abs(b).max()))
+        import oracle
+        oracle.build()
+        oerrs = []
+        for i in i32:
+            kind, N, r, V0, _ = reqs[i]
+            if N > 32 or len(oerrs) >= 20:
+                continue
+            H, gamma = pool[(N, r)]
+            Qo, Ko = oracle.prepare_dense(H.cpu().numpy(), gamma.cpu().numpy())
+            Vo = oracle.rk4_dense(Qo, Ko, V0.cpu().numpy(), args.dt, args.serve_steps)
+            oerrs.append(float(np.abs(out_s[i].cpu().numpy() - Vo).max() / np.abs(Vo).max()))
+        fp32 = {"requests": len(i32), "rel_err_vs_fp64_max": max(errs), "rel_err_vs_fp64_median": float(np.median(errs)),
+                "oracle_sample": len(oerrs), "rel_err_vs_oracle_max": max(oerrs) if oerrs else None,
+                "note": "normwise relative error of each FP32 request's final state against the same request "
+                        "integrated in FP64 by the library, and against the FP64 oracle for FP32 requests with "
+                        "N <= 32 (up to 20)"}
+        log("FP32 requests: max rel err vs FP64 %.2e (median %.2e), vs oracle %s"
+            % (fp32["rel_err_vs_fp64_max"], fp32["rel_err_vs_fp64_median"], fp32["rel_err_vs_oracle_max"]))
     mode = ("resident systems (25 registered Lindbladians, requests carry states only)" if resident
             else "prepare per request")
     out = {
@@ -292,13 +356,16 @@ def serving(args):
         "unit": "solves/s",
         "n_gpus": 1,
         "higher_is_better": True,
-        "dtype": "f64",
+        "dtype": "f64" if not i32 else "f64 (%.0f%% of dense requests f32)" % (100 * args.fp32_share),
         "data": "synthetic",
         "config": {"workload": "serving mix: %d requests, N uniform in %s, 70%% dense random / 30%% sparse dimer, "
                                "%d RK4 steps dt=%g, one pure state each, %s arrivals, %s"
                                % (len(reqs), Ns, args.serve_steps, args.dt, args.arrival, mode),
                    "slots": args.slots, "max_batch": mb, "budget_gb": args.budget_gb,
-                   "rate": args.rate, "resident": bool(resident)},
+                   "rate": rate, "rate_from": rate_from if args.arrival == "poisson" else None,
+                   "fp32_share": args.fp32_share, "resident": bool(resident)},
+        "latency": "completion - arrival (each request is submitted at its arrival time)",
+        "fp32": fp32,
         "served": {"solves_per_s": len(reqs) / w_s, "p50_s": float(np.percentile(lat_s, 50)),
                    "p99_s": float(np.percentile(lat_s, 99)), "wall_s": w_s, "stats": st_s},
         "plain": {"solves_per_s": len(reqs) / w_p, "p50_s": float(np.percentile(lat_p, 50)),

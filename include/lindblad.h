@@ -534,10 +534,15 @@ typedef struct lb_server lb_server;
 
 /* Starts a server on `device` with `max_slots` worker slots (each a thread with
  * its own stream and context, workspace pre-sized for N <= max_N), an HBM
- * budget for the per-request buffers (Q/CSR, K), and batches of up to
- * `max_batch` same-shape dense requests integrated together. Admission keeps
+ * budget for the per-request buffers (Q/CSR, K, state blocks), and batches of
+ * up to `max_batch` requests: queued requests with the same inputs (the same
+ * H and gamma, or CSR, arrays, the same dt, steps and precision) share one
+ * preparation and one pass (their states packed into a block of at most
+ * LB_SYSTEM_BATCH), and dense requests of the same N, dt, steps and precision
+ * on other inputs are integrated in the same launches. Admission keeps
  * submission order: the oldest waiting request starts as soon as a slot is
- * free and its footprint fits in the budget. */
+ * free and its footprint fits in the budget. With max_batch = 1 every request
+ * runs alone. A request's result is the same bit for bit alone and batched. */
 int lindblad_server_create(int device, size_t hbm_budget_bytes, int max_slots, int max_batch, int max_N,
                            lb_server** srv);
 /* Queues a request (thread-safe; copies the descriptor, not the data).

@@ -423,16 +423,16 @@ class Core {
                 }
             }
         } else {
-            // queued requests with the same inputs as a group of the batch join
-            // it (one preparation, at most LB_SYSTEM_BATCH states, footprint of
-            // their states only); dense requests of the same pass shape on other
-            // inputs open further groups, at most max_batch_ groups. A request
-            // of more than LB_SYSTEM_BATCH states runs alone.
+            // at most max_batch_ requests: queued requests with the same inputs as
+            // a group of the batch join it (one preparation, at most
+            // LB_SYSTEM_BATCH states, footprint of their states only); dense
+            // requests of the same pass shape on other inputs open further
+            // groups. A request of more than LB_SYSTEM_BATCH states runs alone.
             h->group = 0;
             std::vector<const lb_request*> reps(1, &h->req);
             std::vector<int> states(1, h->req.B);
             const bool solo = h->req.B > LB_SYSTEM_BATCH;
-            for (auto it = queue_.begin(); !solo && it != queue_.end();) {
+            for (auto it = queue_.begin(); !solo && it != queue_.end() && (int)batch.size() < max_batch_;) {
                 Ticket* t = *it;
                 int g = -1;
                 if (t->req.B <= LB_SYSTEM_BATCH)
@@ -441,7 +441,7 @@ class Core {
                 if (g >= 0 && used_ + t->join_footprint <= budget_) {
                     t->footprint = t->join_footprint;
                 } else if (g < 0 && t->req.B <= LB_SYSTEM_BATCH && same_pass(h->req, t->req) &&
-                           (int)reps.size() < max_batch_ && used_ + t->footprint <= budget_) {
+                           used_ + t->footprint <= budget_) {
                     g = (int)reps.size();
                     reps.push_back(&t->req);
                     states.push_back(0);

@@ -19,8 +19,8 @@
 //   group      queued requests with the same inputs share their head's
 //              preparation (at most 16 states per group, footprint of their
 //              states only), other inputs of the same pass shape open further
-//              groups up to max_batch, a request of more than 16 states runs
-//              alone
+//              groups, at most max_batch requests per batch, a request of more
+//              than 16 states runs alone
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -88,7 +88,7 @@ struct Stub : lb_sched::Executor {
                 }
                 if (t->group >= 0 && t->group < (int)gs.size()) gs[t->group] += t->req.B;
             }
-            if ((int)rep.size() > max_batch) bad = true;
+            if ((int)b.size() > max_batch) bad = true;
             for (int x : gs)
                 if (x > LB_SYSTEM_BATCH && b.size() > 1) bad = true;
             std::lock_guard<std::mutex> lk(last_mu);
@@ -407,8 +407,8 @@ static void scenario_oom() {
 static void scenario_group() {
     Stub ex;
     ex.budget = 10000;
-    ex.max_batch = 2;
-    Core core(10000, 2);
+    ex.max_batch = 6;
+    Core core(10000, 6);
     core.start(1, &ex);
     ex.close_gate();
     const char* why = nullptr;
@@ -423,7 +423,9 @@ static void scenario_group() {
         CHECK(core.submit(shared(LB_REQ_DENSE, 6, 4, 10, 7), 500, 50, &t, &why) == LB_OK);
         all.push_back(t);
     }
-    CHECK(core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 500, 50, &t, &why) == LB_OK);   // a third group: over max_batch
+    CHECK(core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 500, 50, &t, &why) == LB_OK);   // group 2: the sixth request
+    all.push_back(t);
+    CHECK(core.submit(plain(LB_REQ_DENSE, 6, 1, 10), 500, 50, &t, &why) == LB_OK);   // over max_batch: next batch
     all.push_back(t);
     CHECK(core.submit(plain(LB_REQ_DENSE, 6, 20, 10), 500, 50, &t, &why) == LB_OK);  // more than 16 states: alone
     all.push_back(t);
@@ -434,11 +436,12 @@ static void scenario_group() {
     int64_t completed = 0, batches = 0, batched = 0;
     size_t peak = 0;
     core.stats(&completed, &peak, &batches, &batched);
-    // batches: the first request, {group 0: 4 requests, group 1: 1}, the plain one, the 20-state one
+    // batches: the first request, {group 0: 4, group 1: 1, group 2: 1}, the last plain one, the 20-state one
     CHECK(batches == 4);
-    CHECK(batched == 5);
-    // peak: the second batch, two preparations (500 each) and three joiners (50 each)
-    CHECK(peak == 500 + 3 * 50 + 500);
+    CHECK(batched == 6);
+    std::lock_guard<std::mutex> lk(ex.last_mu);
+    // peak: the second batch, three preparations (500 each) and three joiners (50 each)
+    CHECK(peak == 3 * 500 + 3 * 50);
     printf("group: same-input requests shared one preparation, footprints of joiners counted as states only\n");
 }
 
