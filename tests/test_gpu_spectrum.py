@@ -84,6 +84,20 @@ def test_spectrum_n32_with_padded_rows(lb, ctx, oracle):
     assert lam.real.max() < 0
 
 
+def test_spectrum_n64_device_wide(lb, ctx, oracle):
+    """M = 4095: the device-wide sweeps with chains of 64 bulges and the blocked
+    Hessenberg reduction (panels of 32), every eigenvalue against LAPACK's."""
+    print("[gpu] spectrum N=64 (M=4095)", flush=True)
+    H, gamma = wl.random_lindbladian(64, 1)
+    Q, _ = oracle.prepare_dense(H, gamma)
+    lam, info = gpu_spectrum(lb, ctx, Q)
+    worst = check_against_oracle(Q, lam)
+    check_pairs_adjacent(lam)
+    assert abs(lam.sum() - np.trace(Q)) < 1e-11 * np.abs(Q).sum()
+    assert info["chain_steps"] > 0
+    print("[gpu] spectrum N=64: %d sweeps, worst |d| / bound %.3g" % (info["sweeps"], worst), flush=True)
+
+
 @pytest.mark.parametrize("N,c", [(4, 0.3), (9, 0.05)])
 def test_spectrum_depolarising_closed_form(lb, ctx, oracle, N, c):
     """gamma = c 1: the spectrum is {-cN - i(E_a - E_b) : a != b} and -cN (N - 1 times)."""
