@@ -1002,6 +1002,7 @@ gemm64_fn pick64s(int RT, int CT) {
     } else if (CT == 4) {
         if (RT == 1) return k_gemm64s<1, 4>;
         if (RT == 2) return k_gemm64s<2, 4>;
+        if (RT == 4) return k_gemm64s<4, 4>;
     }
     return nullptr;
 }
@@ -1018,6 +1019,7 @@ gemm32_fn pick32s(int RT, int CT) {
     } else if (CT == 4) {
         if (RT == 1) return k_gemm32s<1, 4>;
         if (RT == 2) return k_gemm32s<2, 4>;
+        if (RT == 4) return k_gemm32s<4, 4>;
     }
     return nullptr;
 }
