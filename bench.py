@@ -135,6 +135,9 @@ def parse():
     ap.add_argument("--resident", action="store_true", help="with --serving: same as --config c5r")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for rocprofv3 --pmc runs: one plain 4 GiB copy, then the C4 stage GEMM on stand-in Q")
+    ap.add_argument("--pmc-c3", action="store_true",
+                    help="for rocprofv3 --pmc runs: C3's stage GEMM (N=100, 64 states), 10 launches in FP64 then 10 in "
+                         "FP32, default tiles")
     ap.add_argument("--pmc-assembly", action="store_true",
                     help="for rocprofv3 --pmc runs: one plain 4 GiB copy, then one dense preparation at --N")
     ap.add_argument("--requests", type=int, default=2000)
@@ -1041,6 +1044,31 @@ def pmc_probe(args):
     ctx.close()
 
 
+def pmc_c3(args):
+    """Kernels for the matrix-core counters of C3: the stage GEMM over C3's Q
+    (N=100, M=9999, 64 states) launched 10 times in FP64 and 10 times in FP32."""
+    import torch
+
+    import paper_1912_01491_amd as lb
+    from paper_1912_01491_amd import workloads as wl
+
+    N, B = 100, 64
+    M = N * N - 1
+    H, gamma = wl.random_lindbladian(N, 0)
+    ctx = lb.Context(0)
+    Q, K = lb.lindblad_prepare(ctx, torch.from_numpy(H).cuda(), torch.from_numpy(gamma).cuda())
+    Q32 = lb.lindblad_q_to_f32(ctx, Q)
+    V = torch.zeros((B, M), dtype=torch.float64, device="cuda")
+    out = {}
+    for name, prec in (("fp64", lb.FP64), ("fp32", lb.FP32)):
+        ms = lb.lindblad_time_stage(ctx, [Q] if prec == lb.FP64 else None, [K], [V], iters=10, precision=prec,
+                                    Q32s=[Q32] if prec == lb.FP32 else None)
+        out[name] = {"ms": ms, "tflops": 2.0 * M * M * B / ms / 1e9, "tile": lb.lindblad_tile_info(ctx, M, B, prec)}
+        log("C3 stage GEMM %s: %.3f ms per launch, %.1f TFLOP/s" % (name, ms, out[name]["tflops"]))
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def pmc_assembly(args):
     """Kernels for the assembly's HBM traffic counters: a plain copy of 4 GiB
     (the scale for FETCH_SIZE / WRITE_SIZE), then one dense preparation at
@@ -1080,6 +1108,8 @@ def main():
         return pmc_probe(args)
     if args.pmc_assembly:
         return pmc_assembly(args)
+    if args.pmc_c3:
+        return pmc_c3(args)
     if args.serving or args.config in ("c5", "c5r"):
         return serving(args)
     if args.config in ("c1", "c2", "c2p", "c3", "c6", "c6s", "c7", "c8"):
