@@ -267,6 +267,11 @@ int lindblad_propagate_batched(lb_ctx* ctx, int R, int64_t M, const double* cons
 int lindblad_propagate_graph(lb_ctx* ctx, int64_t M, const double* Q, const float* Q32, int64_t ldq,
                              const double* K, double* V, int B, double dt, int64_t steps, int precision);
 
+/* Frees every graph the context has captured (after synchronizing its stream)
+ * and their buffers; *freed (may be NULL) receives how many. Call it before
+ * freeing the Q, K or V buffers of captured graphs. */
+int lindblad_graph_clear(lb_ctx* ctx, int* freed);
+
 /* ------------------------------------------------------------------ */
 /* Saved systems (Sec. 5: the integration runs from prepared, stored data) */
 /* ------------------------------------------------------------------ */

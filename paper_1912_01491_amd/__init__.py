@@ -24,7 +24,7 @@ __all__ = [
     "lb_expand", "lb_expand_pure", "lb_reconstruct",
     "lindblad_prepare", "lindblad_q_to_f32", "lindblad_propagate", "lindblad_propagate_noalloc",
     "lindblad_propagate_batched",
-    "lindblad_propagate_graph", "lindblad_propagate_csr", "lindblad_prepare_sparse",
+    "lindblad_propagate_graph", "lindblad_graph_clear", "lindblad_propagate_csr", "lindblad_prepare_sparse",
     "lindblad_propagate_csr_drive", "lb_eigh", "Secular", "read_bandwidth", "gemm_f64", "gemm_c128", "lb_hessenberg", "lindblad_spectrum",
     "lindblad_spectrum_histogram", "save_system", "load_system", "load_system_info", "lindblad_steady_state", "lindblad_steady_state_csr", "lindblad_autotune", "lindblad_tile_info", "lindblad_set_tile", "lindblad_time_stage", "Server",
     "FP64", "FP32", "CHECK_HERMITIAN",
@@ -107,6 +107,7 @@ def signatures():
         "lindblad_propagate_csr_drive": [V, I64, V, V, V, V, V, V, V, V, I, D, I64, D, I64, D, D, D],
         "lb_eigh": [V, I, V, I, V, V, I, V],
         "lb_read_bandwidth": [V, ctypes.c_size_t, V],
+        "lindblad_graph_clear": [V, V],
         "lb_gemm_f64": [V, I, I, I64, I64, I64, D, V, I64, V, I64, D, V, I64],
         "lb_gemm_c128": [V, I, I, I64, I64, I64, V, I64, V, I64, V, I64, V, I64],
         "lb_hessenberg": [V, I64, V, I64],
@@ -729,6 +730,13 @@ def lindblad_autotune(ctx: Context, Q, K, B: int, precision: int = FP64, Q32=Non
     V = torch.zeros((B, M), dtype=torch.float64, device=K.device)
     _check(load().lindblad_autotune(ctx.handle, M, _ptr(Q) if Q is not None else None,
                                     _ptr(Q32) if Q32 is not None else None, ldq, _ptr(K), _ptr(V), B, precision))
+
+
+def lindblad_graph_clear(ctx: Context) -> int:
+    """Frees the context's captured graphs; returns how many there were."""
+    n = ctypes.c_int()
+    _check(load().lindblad_graph_clear(ctx.handle, ctypes.byref(n)))
+    return n.value
 
 
 def lindblad_set_tile(ctx: Context, M: int, B: int, rows: int, kslab: int, waves: int, precision: int = FP64):

@@ -569,6 +569,17 @@ int lindblad_propagate_graph(lb_ctx* c, int64_t M, const double* Q, const float*
     return lb_impl_propagate_graph(c, M, &s, ldq, B, dt, steps, precision);
 }
 
+int lindblad_graph_clear(lb_ctx* c, int* freed) {
+    CHECK_CTX(c);
+    LB_HIP(hipSetDevice(c->device));
+    LB_HIP(hipStreamSynchronize(c->stream));  // a cached graph's last launch may still run
+    const int n = (int)c->graphs.size();
+    for (auto& kv : c->graphs) lb_graph_free(kv.second);
+    c->graphs.clear();
+    if (freed) *freed = n;
+    return LB_OK;
+}
+
 int lindblad_autotune(lb_ctx* c, int64_t M, const double* Q, const float* Q32, int64_t ldq, const double* K,
                       double* V, int B, int precision) {
     CHECK_CTX(c);

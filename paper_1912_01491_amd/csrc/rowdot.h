@@ -56,6 +56,27 @@ __device__ __forceinline__ void wave_rowdots(const double* const* qrow, const do
             }
         }
     } else {
+        // the same rounds with 8-byte loads
+        for (; c + 3 * 128 + 1 < M; c += 4 * 128) {
+            double xv[4][2], q[4][R][2];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                xv[u][0] = x[c + u * 128];
+                xv[u][1] = x[c + u * 128 + 1];
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    q[u][t][0] = qrow[t][c + u * 128];
+                    q[u][t][1] = qrow[t][c + u * 128 + 1];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    acc[t] = fma(q[u][t][0], xv[u][0], acc[t]);
+                    acc[t] = fma(q[u][t][1], xv[u][1], acc[t]);
+                }
+        }
         for (; c + 1 < M; c += 128) {
             const double x0 = x[c], x1 = x[c + 1];
 #pragma unroll

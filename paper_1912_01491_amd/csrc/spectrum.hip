@@ -27,6 +27,7 @@
 //     directly. Every tenth sweep without a split takes an exceptional shift to break
 //     cycles; kMaxIts sweeps without one is an error.
 #include "lb_internal.h"
+#include "rowdot.h"
 
 
 #include <float.h>
@@ -977,17 +978,21 @@ __global__ __launch_bounds__(256) void k_bh_house(const double* col, int M, int 
     for (int r = c + 2 + threadIdx.x; r < M; r += 256) vi[r] = col[r] * scale;
 }
 
-// y[r] = sum_{cc > c} A[r][cc] v[cc]: one wavefront per row
+// y[r] = sum_{cc > c} A[r][cc] v[cc]: one wavefront per row, the row-dot loop of
+// the one-state GEMV. The dot starts at the even column c0 <= c + 1 so that,
+// with 16-byte aligned rows (ALIGNED), every lane reads 16-byte pieces; v is
+// zero above c + 1, so the extra column adds nothing.
+template <bool ALIGNED>
 __global__ __launch_bounds__(256) void k_bh_gemv(const double* A, int64_t lda, int M, int c, const double* v,
                                                  double* y) {
     const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (r >= M) return;
-    const double* row = A + (int64_t)r * lda;
-    double s = 0.0;
-    for (int cc = c + 1 + lane; cc < M; cc += 64) s = fma(row[cc], v[cc], s);
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) y[r] = s;
+    const int c0 = (c + 1) & ~1;
+    const double* row[1] = {A + (int64_t)r * lda + c0};
+    double s[1];
+    wave_rowdots<1, ALIGNED, true>(row, v + c0, M - c0, lane, s);
+    if (lane == 0) y[r] = s[0];
 }
 
 // Y[i][r] = tau (y[r] - sum_{k<i} Y[k][r] u[k]); block 0 also writes column i of T:
@@ -1074,6 +1079,8 @@ namespace {
 int hessenberg_blocked(lb_ctx* c, int M, double* A, int64_t lda) {
     hipStream_t s = c->stream;
     const BlockedLayout lay(M);
+    // rows 16-byte aligned: the GEMV reads 16-byte pieces (V's rows start on 256 bytes)
+    const bool aligned = (lda % 2) == 0 && ((uintptr_t)A % 16) == 0 && (M % 2) == 0;
     char* ws = (char*)c->ws;
     double* V = (double*)(ws + lay.V);
     double* Y = (double*)(ws + lay.Y);
@@ -1114,8 +1121,12 @@ int hessenberg_blocked(lb_ctx* c, int M, double* A, int64_t lda) {
                                    (const double*)(V + (int64_t)i * M), u);
                 LB_CHECK_LAUNCH();
             }
-            hipLaunchKernelGGL(k_bh_gemv, dim3(lb_blocks(M, 4)), dim3(256), 0, s, (const double*)A, lda, M, cc,
-                               (const double*)(V + (int64_t)i * M), y);
+            if (aligned)
+                hipLaunchKernelGGL(k_bh_gemv<true>, dim3(lb_blocks(M, 4)), dim3(256), 0, s, (const double*)A, lda, M,
+                                   cc, (const double*)(V + (int64_t)i * M), y);
+            else
+                hipLaunchKernelGGL(k_bh_gemv<false>, dim3(lb_blocks(M, 4)), dim3(256), 0, s, (const double*)A, lda, M,
+                                   cc, (const double*)(V + (int64_t)i * M), y);
             LB_CHECK_LAUNCH();
             hipLaunchKernelGGL(k_bh_ycol, dim3(lb_blocks(M, 256)), dim3(256), 0, s, M, i, (const double*)y,
                                (const double*)u, (const double*)taus, Y, T);
@@ -1191,16 +1202,19 @@ int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam
                      int64_t* work) {
     hipStream_t s = c->stream;
     // the working copy sits past the reduction's own scratch
+    // the working copy's rows padded to 16 doubles (128 bytes) while M * ld keeps
+    // within 32-bit element offsets
+    int64_t ld = (M + 15) / 16 * 16;
+    if ((int64_t)M * ld > (int64_t)INT32_MAX) ld = M;
     const size_t o_h = HessLayout(M).end;
-    const size_t o_g = o_h + lb_align(sizeof(double) * (size_t)M * M, 256);
+    const size_t o_g = o_h + lb_align(sizeof(double) * (size_t)M * ld, 256);
     int rc = lb_ws_reserve(c, o_g + sizeof(QrGlobal));
     if (rc) return rc;
     rc = lb_host_reserve(c, sizeof(QrGlobal));
     if (rc) return rc;
     double* H = (double*)((char*)c->ws + o_h);
     QrGlobal* g = (QrGlobal*)((char*)c->ws + o_g);
-    const int64_t ld = M;
-    LB_HIP(hipMemcpy2DAsync(H, sizeof(double) * M, Q, sizeof(double) * ldq, sizeof(double) * M, M,
+    LB_HIP(hipMemcpy2DAsync(H, sizeof(double) * ld, Q, sizeof(double) * ldq, sizeof(double) * M, M,
                             hipMemcpyDeviceToDevice, s));
     rc = lb_impl_hessenberg(c, M, H, ld);
     if (rc) return rc;

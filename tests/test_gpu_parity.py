@@ -356,6 +356,13 @@ def test_graph_cache_is_bounded(lb, oracle):
             lb.lindblad_propagate_graph(c, Q, K, V, 1e-3, 6)
             c.sync()
             assert torch.equal(V, ref)
+    # the cache holds at most eight; clearing frees them all, and a new capture works
+    assert lb.lindblad_graph_clear(c) == 8
+    assert lb.lindblad_graph_clear(c) == 0
+    V = V0.clone()
+    lb.lindblad_propagate_graph(c, Q, K, V, 1e-3, 6)
+    c.sync()
+    assert torch.equal(V, ref)
     c.close()
 
 

@@ -157,10 +157,11 @@ def test_spectrum_edge_matrices(lb, ctx, oracle, name):
         check_against_oracle(A, lam)
 
 
-@pytest.mark.parametrize("M", [3, 63, 200, 257, 1100])
+@pytest.mark.parametrize("M", [3, 63, 200, 257, 1001, 1100])
 def test_hessenberg_is_an_orthogonal_similarity(lb, ctx, oracle, M):
     """Exact zeros below the subdiagonal, the Frobenius norm kept, the spectrum kept
-    (M = 1100: the blocked reduction, 34 panels of 32 reflectors and a last one of 10)."""
+    (M = 1100: the blocked reduction, 34 panels of 32 reflectors and a last one of 10,
+    16-byte aligned rows; M = 1001: the blocked reduction on rows of odd length)."""
     A = wl.rng(M).standard_normal((M, M))
     T = torch.from_numpy(A.copy()).cuda()
     lb.lb_hessenberg(ctx, T)
