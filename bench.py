@@ -107,9 +107,9 @@ def parse():
     ap.add_argument("--full-job", action="store_true",
                     help="default config: time the configuration's whole job (--rk4-steps batched RK4 steps, "
                          "no warmup) instead of --steps")
-    ap.add_argument("--check-psd", action="store_true",
-                    help="default config: Cholesky factorisation of realization 0's gamma (positive definite to "
-                         "FP64 rounding)")
+    ap.add_argument("--no-check-psd", dest="check_psd", action="store_false",
+                    help="default config: skip the Cholesky factorisation of realization 0's gamma (the check that "
+                         "it is positive definite to FP64 rounding, untimed)")
     ap.add_argument("--cpu-rows", type=int, default=256,
                     help="default config: sampled S rows (and the J rows of the same pairs) in the oracle's "
                          "assembly sample")
