@@ -318,15 +318,19 @@ __global__ void k_gth_fin(GV v, const double* H, const double* GpA, const double
 // Hermitian); a set {a < x < c < d} gives the d-th entries of T, of S's
 // segment x and of R's row {x,c}, from the blocks at those positions. Every
 // disjoint block of gamma is read once in each orientation, and every segment
-// is produced by one workgroup at one time, so Q is written in whole runs.
-// The shared-vertex elements outside these segments (segments x and y of row
-// {x,y}) come from k_segpp.
+// is produced by one workgroup, so Q's lines are written whole except where a
+// segment starts or ends inside a line (the rest of that line belongs to the
+// neighbouring segment, written by another workgroup). The shared-vertex
+// elements outside these segments (segments x and y of row {x,y}) come from
+// k_segpp.
 //
 // The square R is processed in 16 x 16 tiles (x block X, z block Z, X <= Z);
 // block boundaries are placed so that a block's columns in segment a start a
-// 128-byte line of Q. The transposed tile R[z][x] goes through LDS. The sets
-// {a < x < c < d} of an x block follow its tiles (lanes along d), so that the
-// S and R segments end right after their tiles.
+// 128-byte line of Q. The transposed tile R[z][x] goes through LDS, and so does
+// row {a,c}, whose segments are not aligned with the tiles: per x row a window
+// of two lines collects the tile's values and each complete line is written
+// at once. The sets {a < x < c < d} of an x block follow its tiles (lanes along
+// d), so that the S and R segments end right after their tiles.
 constexpr int kQuadPad = 17;
 
 // Pair position in 32-bit arithmetic (the dense path holds M^2 complex values,
