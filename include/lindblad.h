@@ -396,11 +396,15 @@ int lindblad_steady_state_csr(lb_ctx* ctx, int64_t M, const int64_t* rowptr, con
 int lb_hessenberg(lb_ctx* ctx, int64_t M, double* A, int64_t lda);
 
 typedef struct lb_spectrum_info {
-    int64_t sweeps;      /* QR sweeps over all blocks */
-    int64_t chain_steps; /* chain steps over all sweeps (each three barrier phases) */
-    int64_t updates;     /* 2- or 3-entry row and column pieces the reflectors updated
-                            (10 flops each): b (na^2 + 3 na - 7) per b-bulge sweep
-                            over an na-row block */
+    int64_t sweeps;        /* QR sweeps over all blocks */
+    int64_t chain_steps;   /* chain steps over all sweeps */
+    int64_t updates;       /* 2- or 3-entry row and column pieces the reflectors update
+                              (10 flops each): b (na^2 + 3 na - 7) per b-bulge sweep
+                              over an na-row block */
+    int64_t rounds;        /* windowed rounds of the sweeps over blocks above 256 rows */
+    int64_t product_flops; /* flops of those rounds' matrix products outside the windows:
+                              2 w^2 per row or column of the block a w-row window
+                              updates */
 } lb_spectrum_info;
 
 /* Eigenvalues of the real generator Q of the ODE dv/dt = Qv + K (Eq. (10);
@@ -412,8 +416,11 @@ typedef struct lb_spectrum_info {
  * imaginary part first, otherwise in no particular order. Works on a copy of Q
  * in the context's workspace (M^2 doubles): Householder reduction to Hessenberg
  * form, then Francis' implicit double-shift QR iteration (eigenvalues only)
- * with chains of up to 16 bulges whose shifts are the eigenvalues of the
- * trailing block; a block splits off where a subdiagonal entry falls below
+ * whose shifts are the eigenvalues of the trailing block: sweeps over blocks
+ * above 256 rows move up to 64 bulges as chains of 8, each chased inside a
+ * 96 x 96 window with the rest of the block updated by matrix products, and
+ * blocks of at most 256 rows are finished by one workgroup (up to 16 bulges
+ * per sweep); a block splits off where a subdiagonal entry falls below
  * eps (|h_k-1,k-1| + |h_kk|), or below eps ||Q||_F once ten sweeps have passed
  * without a split and below sqrt(M) eps ||Q||_F after twenty (clusters at the
  * rounding floor). *info (may be NULL) receives the iteration

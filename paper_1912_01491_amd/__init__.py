@@ -461,7 +461,8 @@ def lb_eigh(ctx: Context, A):
 
 
 class SpectrumInfo(ctypes.Structure):
-    _fields_ = [("sweeps", ctypes.c_int64), ("chain_steps", ctypes.c_int64), ("updates", ctypes.c_int64)]
+    _fields_ = [("sweeps", ctypes.c_int64), ("chain_steps", ctypes.c_int64), ("updates", ctypes.c_int64),
+                ("rounds", ctypes.c_int64), ("product_flops", ctypes.c_int64)]
 
 
 def lb_hessenberg(ctx: Context, A):
@@ -480,7 +481,8 @@ def lb_hessenberg(ctx: Context, A):
 def lindblad_spectrum(ctx: Context, Q):
     """Eigenvalues of the generator Q (float64 M x M on the device, rows may be
     padded: Q = buffer[:, :M]). Returns (lam, info): lam complex128 (M,) on the
-    device, conjugate pairs adjacent; info = {sweeps, chain_steps, updates}."""
+    device, conjugate pairs adjacent; info = {sweeps, chain_steps, updates, rounds,
+    product_flops}."""
     import torch
     if not isinstance(Q, torch.Tensor) or not Q.is_cuda or Q.dtype != torch.float64:
         raise ValueError("Q must be a float64 CUDA (HIP) tensor")
@@ -491,7 +493,8 @@ def lindblad_spectrum(ctx: Context, Q):
     info = SpectrumInfo()
     _check(load().lindblad_spectrum(ctx.handle, M, _ptr(Q), Q.stride(0), _ptr(lam), ctypes.byref(info)))
     return torch.view_as_complex(lam.view(M, 2)), {"sweeps": info.sweeps, "chain_steps": info.chain_steps,
-                                                   "updates": info.updates}
+                                                   "updates": info.updates, "rounds": info.rounds,
+                                                   "product_flops": info.product_flops}
 
 
 def lindblad_spectrum_histogram(ctx: Context, lam, re0: float, re1: float, im0: float, im1: float, nx: int, ny: int):

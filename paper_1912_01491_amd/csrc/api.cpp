@@ -409,13 +409,9 @@ int lindblad_spectrum(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, double
     CHECK_PTR(lam);
     if (M < 1 || M > LB_SPECTRUM_MAX_M) return lb_fail(LB_ERR_INVALID_ARG, "M out of range [1, %d]", LB_SPECTRUM_MAX_M);
     if (ldq < M) return lb_fail(LB_ERR_INVALID_ARG, "ldq < M");
-    int64_t sweeps = 0, steps = 0, work = 0;
-    const int rc = lb_impl_spectrum(c, (int)M, Q, ldq, lam, &sweeps, &steps, &work);
-    if (info) {
-        info->sweeps = sweeps;
-        info->chain_steps = steps;
-        info->updates = work;
-    }
+    lb_spectrum_info counts = {};
+    const int rc = lb_impl_spectrum(c, (int)M, Q, ldq, lam, &counts);
+    if (info) *info = counts;
     return rc;
 }
 

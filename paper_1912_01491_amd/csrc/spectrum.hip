@@ -16,14 +16,17 @@
 //     bulge's reflector reads what another bulge writes in the same step, and
 //     reflections from the two sides commute, so a chain step is data-parallel over
 //     all b bulges at once. Blocks above kSmallBlock rows are swept over the whole
-//     device (up to kWideBulges bulges, one launch per chain step); smaller blocks,
-//     and the shift problems, by one workgroup (up to kMaxBulges bulges, two barrier
-//     phases per chain step). The 2b shifts of a b-bulge chain are the eigenvalues of
+//     device (up to kWideBulges bulges in chains of kChain, each chain chased inside an
+//     LDS window by one workgroup, the rest of the block updated by matrix-core
+//     products of the window's orthogonal factor); smaller blocks, and the shift
+//     problems, by one workgroup (up to kMaxBulges bulges, two barrier phases per
+//     chain step). The 2b shifts of a b-bulge chain are the eigenvalues of
 //     the trailing 2b x 2b block, found by the same iteration on a copy in LDS
 //     (recursively, down to one bulge). A block splits off where a
 //     subdiagonal entry falls below eps (|h_k-1,k-1| + |h_kk|), below eps ||H||_F after
 //     ten sweeps without a split and below sqrt(n) eps ||H||_F after twenty (clusters at
-//     the rounding floor); 1 x 1 and 2 x 2 blocks give their eigenvalues
+//     the rounding floor; ||H||_F of the whole matrix, also for its diagonal blocks);
+//     1 x 1 and 2 x 2 blocks give their eigenvalues
 //     directly. Every tenth sweep without a split takes an exceptional shift to break
 //     cycles; kMaxIts sweeps without one is an error.
 #include "lb_internal.h"
@@ -201,7 +204,10 @@ __device__ void eig2(double a, double b, double c, double d, double2* l1, double
     }
 }
 
-// Reflector 1 - tau w w^T with w = (1, w1, w2) mapping (x, y, z) to (beta, 0, 0).
+// Reflector 1 - tau w w^T with w = (1, w1, w2) mapping (x, y, z) to (beta, 0, 0). The
+// entries are scaled by their 1-norm; with d = xs - bs (no cancellation: bs has the
+// sign opposite to xs) one reciprocal 1 / (bs d) gives both tau = (bs - xs) / bs = -d / bs
+// and 1 / d, so the reflector costs two divisions and a square root.
 __device__ void house3(double x, double y, double z, double* tau, double* w1, double* w2, double* beta) {
     const double sc = fabs(x) + fabs(y) + fabs(z);
     if (sc == 0.0 || (y == 0.0 && z == 0.0)) {
@@ -210,12 +216,15 @@ __device__ void house3(double x, double y, double z, double* tau, double* w1, do
         *beta = x;
         return;
     }
-    const double xs = x / sc, ys = y / sc, zs = z / sc;
+    const double rs = 1.0 / sc;
+    const double xs = x * rs, ys = y * rs, zs = z * rs;
     const double bs = -copysign(sqrt(xs * xs + ys * ys + zs * zs), xs);
-    *tau = (bs - xs) / bs;
     const double d = xs - bs;
-    *w1 = ys / d;
-    *w2 = zs / d;
+    const double r = 1.0 / (bs * d);
+    const double rd = bs * r;
+    *tau = -d * d * r;
+    *w1 = ys * rd;
+    *w2 = zs * rd;
     *beta = bs * sc;
 }
 
@@ -234,10 +243,13 @@ __device__ void intro_xyz(const double* H, int64_t ld, int l, double s, double t
 // (entries below the subdiagonal are never read), row-major with leading dimension ld,
 // in global memory or LDS; destroyed. lam receives the n eigenvalues. Returns 0, or 1
 // when kMaxIts sweeps pass without a split. BMAX > 1 takes its shifts from the trailing
-// block through a nested BMAX = 1 solve on sub (kShiftDim^2 doubles, LDS).
+// block through a nested BMAX = 1 solve on sub (kShiftDim^2 doubles, LDS). The normwise
+// split tests scale with max(||H||_F, norm_floor): a diagonal block of a larger matrix
+// passes that matrix's norm, so a block cut out of a cluster (a tiny norm of its own)
+// deflates at the backward error the whole matrix allows.
 template <int BMAX>
 __device__ int qr_eigs(double* H, int64_t ld, int n, double2* lam, QrCtl& C, QrCtl* inner, double* sub,
-                       double2* subev) {
+                       double2* subev, double norm_floor) {
     const int tid = threadIdx.x;
     const double eps = DBL_EPSILON;
     // Frobenius norm of the Hessenberg part: the scale of the normwise split test
@@ -256,7 +268,7 @@ __device__ int qr_eigs(double* H, int64_t ld, int n, double2* lam, QrCtl& C, QrC
     if (tid == 0) {
         double a = 0.0;
         for (int w = 0; w < kQrThreads / 64; ++w) a += part[w];
-        C.anorm = a > 0.0 ? sqrt(a) : 1.0;
+        C.anorm = fmax(a > 0.0 ? sqrt(a) : 1.0, norm_floor);
         C.u = n - 1;
         C.its = 0;
         C.status = 0;
@@ -343,7 +355,7 @@ __device__ int qr_eigs(double* H, int64_t ld, int n, double2* lam, QrCtl& C, QrC
                     sub[e] = r <= c + 1 ? at(H, ld, o + r, o + c) : 0.0;
                 }
                 __syncthreads();
-                const int rc = qr_eigs<1>(sub, mm, mm, subev, *inner, nullptr, nullptr, nullptr);
+                const int rc = qr_eigs<1>(sub, mm, mm, subev, *inner, nullptr, nullptr, nullptr, 0.0);
                 if (tid == 0) {
                     if (rc != 0) {  // keep the sweep going with the trailing 2 x 2 shift
                         const double a = at(H, ld, u - 1, u - 1), bb = at(H, ld, u - 1, u);
@@ -538,12 +550,11 @@ __device__ int qr_eigs(double* H, int64_t ld, int n, double2* lam, QrCtl& C, QrC
 }
 
 // ---------------------------------------------------------------------------
-// Stage 2 on the whole device: sweeps over large blocks, one launch per phase
+// Stage 2 on the whole device: the host-driven iteration
 // ---------------------------------------------------------------------------
 
 // Blocks of at most kSmallBlock rows are finished by one workgroup (qr_eigs);
-// sweeps over larger blocks run each phase of each chain step as a launch over the
-// whole device, the kernel boundaries ordering the phases.
+// sweeps over larger blocks run as windowed rounds over the whole device (below).
 constexpr int kSmallBlock = 256;
 constexpr int kWideBulges = 64;                 // bulges per device-wide sweep (128 shifts)
 constexpr int kWideShiftDim = 2 * kWideBulges;  // trailing block solved for their shifts
@@ -639,7 +650,8 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_decide(double* H, int64_t ld,
     if (na <= kSmallBlock) {
         if (tid == 0 && l > 0) H[(int64_t)l * ld + l - 1] = 0.0;
         __syncthreads();
-        const int rc = qr_eigs<kMaxBulges>(H + (int64_t)l * ld + l, ld, na, lam + l, outer, &inner, sub2, subev2);
+        const int rc = qr_eigs<kMaxBulges>(H + (int64_t)l * ld + l, ld, na, lam + l, outer, &inner, sub2, subev2,
+                                            g->anorm);
         if (tid == 0) {
             if (rc) g->status = 1;
             g->sweeps += outer.sweeps;
@@ -678,7 +690,7 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_decide(double* H, int64_t ld,
             sub[e] = r <= c + 1 ? H[(int64_t)(o + r) * ld + o + c] : 0.0;
         }
         __syncthreads();
-        const int rc = qr_eigs<kMaxBulges>(sub, mm, mm, subev, outer, &inner, sub2, subev2);
+        const int rc = qr_eigs<kMaxBulges>(sub, mm, mm, subev, outer, &inner, sub2, subev2, 0.0);
         if (tid == 0) {
             const double a = H[(int64_t)(u - 1) * ld + u - 1], bb = H[(int64_t)(u - 1) * ld + u];
             const double c = H[(int64_t)u * ld + u - 1], d = H[(int64_t)u * ld + u];
@@ -725,160 +737,310 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_decide(double* H, int64_t ld,
     }
 }
 
-// Index (q, m), 0 <= m < q, of entry e of the triangular enumeration q(q-1)/2 + m.
-__device__ __forceinline__ void tri_index(int e, int* q, int* m) {
-    int r = (int)((1.0 + sqrt(1.0 + 8.0 * (double)e)) * 0.5);
-    while (r * (r - 1) / 2 > e) --r;
-    while (r * (r + 1) / 2 <= e) ++r;
-    *q = r;
-    *m = e - r * (r - 1) / 2;
+// ---------------------------------------------------------------------------
+// Stage 2, level 3: sweeps as chains of bulges chased inside windows
+// ---------------------------------------------------------------------------
+//
+// The b bulges of a device-wide sweep travel as chains of kChain bulges, kSep rows
+// apart inside a chain; chain c enters kChainGap steps after chain c - 1, far enough
+// that the windows of two chains never overlap. A round advances every chain by
+// kAdvance steps. One workgroup per chain loads into LDS the kWin x kWin diagonal
+// window holding every row and column its bulges touch in these steps, chases the
+// chain there (the reflectors and the order of the direct sweep: left sides, then
+// right sides, step by step) and accumulates the window's orthogonal factor U as
+// U^T, one reflector at a time from the left. The rest of the active block gets
+// the round at once: the window's rows to its right, X <- U^T X, and its columns
+// above it, Y <- Y U, as FP64 matrix-core products. Left and right products
+// commute, so where one chain's rows cross another chain's columns both apply in
+// either order; the row products of all chains run in one launch, the column
+// products in the next. Per round a chain moves kChain kAdvance bulge steps for
+// 4 kWin^2 flop per row of the block, instead of 3 entries read and written per
+// row and bulge step.
+constexpr int kWin = 96;                            // window rows and columns
+constexpr int kWinLd = kWin + 1;                    // LDS row stride of a window
+constexpr int kChain = 8;                           // bulges per chain
+constexpr int kAdvance = kWin + 1 - kSep * kChain;  // chain steps per round
+constexpr int kChainGap = kWin + 1;                 // steps between the entries of two chains
+constexpr int kWinThreads = 512;
+constexpr int kWinCols = 16 * (kWinThreads / 64);   // columns (rows) of the block per product workgroup
+
+typedef double qr_gd4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ qr_gd4 mfma_f64(double a, double b, qr_gd4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Reflector of bulge i (positions k..k+2, two entries where k + 2 > u) applied from the
-// left to column c or from the right to row r.
-__device__ __forceinline__ void refl_left(double* H, int64_t ld, int k, int u, double tau, double w1, double w2,
-                                          int c) {
-    double* a = H + (int64_t)k * ld + c;
-    const bool three = k + 2 <= u;
-    const double a0 = a[0], a1 = a[ld], a2 = three ? a[2 * ld] : 0.0;
+struct WinGeom {
+    int ws, we, active;
+};
+
+// Window [ws, we] of chain c in the round of steps t0 .. t0 + kAdvance - 1 of a sweep over
+// [l, u] with b bulges; bulge j of the chain sits at row l + t - c kChainGap - kSep j in
+// step t and is active while that row lies in [l, u - 1]. The window spans the last
+// bulge's row at the first step to three rows past the lead bulge's at the last step:
+// kAdvance - 1 + kSep (kChain - 1) + 4 = kWin rows at most.
+__host__ __device__ inline WinGeom win_geom(int l, int u, int b, int c, int t0) {
+    const int left = b - c * kChain;
+    const int nbc = left < kChain ? left : kChain;
+    const int rel = t0 - c * kChainGap;
+    const int klead = l + rel + kAdvance - 1;
+    const int ktail = l + rel - kSep * (nbc - 1);
+    WinGeom g;
+    g.active = klead >= l && ktail <= u - 1;
+    g.ws = ktail > l ? ktail : l;
+    g.we = klead + 3 < u ? klead + 3 : u;
+    return g;
+}
+
+// One round of chain blockIdx.x: load the window, chase kAdvance steps, store the
+// window, U^T (kWin x kWin, rows of length kWin, at Ut_all + c kWin^2) and the
+// reflectors pending for the next step (g->tau[0] etc., by bulge). Wave j carries bulge
+// j: its left side (lanes along the window columns, then along the columns of U^T) and
+// its right side (lanes along the rows above the bulge); every lane of the wave applies
+// the right side to the bulge's own three rows below it and builds the next reflector
+// from column K, so the reflector stays in registers. Two barriers per step order the
+// sides of neighbouring bulges where they cross. A wave's pieces of one side are at most
+// two per lane (wc <= 128): both are loaded before either is computed.
+__device__ __forceinline__ void win_refl3(double* a, int ld, bool three, double tau, double w1, double w2, double a0,
+                                          double a1, double a2) {
     const double r = tau * (a0 + w1 * a1 + w2 * a2);
     a[0] = a0 - r;
     a[ld] = a1 - r * w1;
     if (three) a[2 * ld] = a2 - r * w2;
 }
 
-__device__ __forceinline__ void refl_right(double* H, int64_t ld, int k, int u, double tau, double w1, double w2,
-                                           int row) {
-    double* h = H + (int64_t)row * ld + k;
-    const bool three = k + 2 <= u;
-    const double h0 = h[0], h1 = h[1], h2 = three ? h[2] : 0.0;
-    const double q = tau * (h0 + w1 * h1 + w2 * h2);
-    h[0] = h0 - q;
-    h[1] = h1 - q * w1;
-    if (three) h[2] = h2 - q * w2;
-}
-
-// Step t of a device-wide sweep over [l, u] with b bulges (bulge i at k_i = l + t - kSep i,
-// active for ilo <= i <= ihi), both sides in one launch. A left reflection of bulge i
-// (rows k_i..k_i+2, columns k_i..u) and a right one of bulge j (columns k_j..k_j+2, rows
-// l..k_j+3) meet only in the 3 x 3 block rows(i) x columns(j) with j <= i, where they
-// commute; one thread applies both there (left first), so every entry has one writer:
-//   left-only:  columns k_ilo+3..u of every active bulge (nb x tail pieces), and the gap
-//               columns k_i + 4m + 3 between deeper strips (triangular),
-//   right-only: rows l..k_ihi-1 of every active bulge (head x nb, bulge fastest: the strips
-//               of one row are adjacent), and the gap rows k_i + 3, i > j (triangular),
-//   crossings:  blocks (i, j), j < i (triangular),
-//   owners:     thread i of block 0 takes block (i, i) and row k_i + 3, then builds bulge
-//               i's next reflector from column k_i (or the first reflector of the bulge that
-//               enters at step t + 1).
-__global__ __launch_bounds__(256) void k_qr_step(double* H, int64_t ld, int l, int u, int b, int t, int ilo, int ihi,
-                                                 int tail, int head, int total, QrGlobal* g) {
-    const int p = t & 1;
-    const int nb = ihi - ilo + 1;
-    if (blockIdx.x == 0 && threadIdx.x < b) {
-        const int i = threadIdx.x;
-        const int k = l + t - kSep * i;
-        double tn = 0.0, w1n = 0.0, w2n = 0.0;
-        if (i >= ilo && i <= ihi) {
-            const double tau = g->tau[p][i], w1 = g->w1[p][i], w2 = g->w2[p][i];
-            const bool three = k + 2 <= u;
-            const int nr = k + 3 <= u ? 4 : (three ? 3 : 2);  // rows k.. (row k+3 takes the right side only)
-            double B[4][3];
+__global__ __launch_bounds__(kWinThreads) void k_win_chase(double* H, int64_t ld, int l, int u, int b, int t0,
+                                                           QrGlobal* g, double* Ut_all) {
+    __shared__ double Hw[kWin * kWinLd];
+    __shared__ double Uw[kWin * kWinLd];
+    constexpr int kRowsPerWave = kWin / (kWinThreads / 64);
+    const int c = blockIdx.x;
+    const WinGeom G = win_geom(l, u, b, c, t0);
+    if (!G.active) return;
+    const int ws = G.ws, wc = G.we - G.ws + 1;
+    const int nbc = min(kChain, b - c * kChain), i0 = c * kChain;
+    const int lu = u - ws, ll = l - ws;  // the block's last and first rows in window coordinates
+    const int lane = threadIdx.x & 63, j = threadIdx.x >> 6;
+    {
+        // wave j loads window rows j, j + 8, ...: all its loads in flight together; entries
+        // more than three below the diagonal are zero (Hessenberg plus bulges)
+        double v[kRowsPerWave][2];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+        for (int i = 0; i < kRowsPerWave; ++i)
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    B[r][c] = (r < nr && (c < 2 || three)) ? H[(int64_t)(k + r) * ld + k + c] : 0.0;
+            for (int h = 0; h < 2; ++h) {
+                const int r = j + i * (kWinThreads / 64), q = lane + 64 * h;
+                v[i][h] = (r < wc && q < wc && r <= q + 3) ? H[(int64_t)(ws + r) * ld + ws + q] : 0.0;
+            }
+#pragma unroll
+        for (int i = 0; i < kRowsPerWave; ++i)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int r = j + i * (kWinThreads / 64), q = lane + 64 * h;
+                if (r < wc && q < wc) {
+                    Hw[r * kWinLd + q] = v[i][h];
+                    Uw[r * kWinLd + q] = r == q ? 1.0 : 0.0;
+                }
+            }
+    }
+    const bool mine = j < nbc;
+    double tau = 0.0, w1 = 0.0, w2 = 0.0;
+    if (mine) {
+        tau = g->tau[0][i0 + j];
+        w1 = g->w1[0][i0 + j];
+        w2 = g->w2[0][i0 + j];
+    }
+    __syncthreads();
+    for (int s = 0; s < kAdvance; ++s) {
+        const int rel = t0 + s - c * kChainGap;  // bulge j at block row l + rel - kSep j
+        // some bulge of the chain active in this step (the same answer in every wave)
+        const int jhi = rel < 0 ? -1 : min(nbc - 1, rel / kSep);
+        const int over = rel - (u - 1 - l);
+        const int jlo = over > 0 ? (over + kSep - 1) / kSep : 0;
+        if (jlo > jhi) continue;
+        const int K = ll + rel - kSep * j;  // window row of bulge j's reflector
+        const bool act = mine && j >= jlo && j <= jhi;
+        if (act && rel == kSep * j) {
+            // bulge j enters at the top of the block (then ws == l): its first reflector
+            double x, y, z, beta;
+            intro_xyz(Hw, kWinLd, ll, g->s[i0 + j], g->t[i0 + j], &x, &y, &z);
+            house3(x, y, z, &tau, &w1, &w2, &beta);
+        }
+        const bool three = K + 2 <= lu;
+        // left side: rows K..K+2 of window columns K..wc-1, and of U^T (all wc columns)
+        if (act && tau != 0.0) {
+            const int q0 = K + lane, q1 = K + lane + 64, u0 = lane, u1 = lane + 64;
+            const bool h0 = q0 < wc, h1 = q1 < wc, g0 = u0 < wc, g1 = u1 < wc;
+            double* pa = Hw + K * kWinLd + q0;
+            double* pb = Hw + K * kWinLd + q1;
+            double* pc = Uw + K * kWinLd + u0;
+            double* pd = Uw + K * kWinLd + u1;
+            double a[4][3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const bool row = m < 2 || three;
+                a[0][m] = (h0 && row) ? pa[m * kWinLd] : 0.0;
+                a[1][m] = (h1 && row) ? pb[m * kWinLd] : 0.0;
+                a[2][m] = (g0 && row) ? pc[m * kWinLd] : 0.0;
+                a[3][m] = (g1 && row) ? pd[m * kWinLd] : 0.0;
+            }
+            if (h0) win_refl3(pa, kWinLd, three, tau, w1, w2, a[0][0], a[0][1], a[0][2]);
+            if (h1) win_refl3(pb, kWinLd, three, tau, w1, w2, a[1][0], a[1][1], a[1][2]);
+            if (g0) win_refl3(pc, kWinLd, three, tau, w1, w2, a[2][0], a[2][1], a[2][2]);
+            if (g1) win_refl3(pd, kWinLd, three, tau, w1, w2, a[3][0], a[3][1], a[3][2]);
+        }
+        __syncthreads();
+        // right side: rows 0..K of columns K..K+2, then (every lane) rows K+1..K+3 and the
+        // next reflector from column K
+        if (act) {
+            const bool r0 = tau != 0.0 && lane <= K, r1 = tau != 0.0 && lane + 64 <= K;
+            double* pa = Hw + lane * kWinLd + K;
+            double* pb = Hw + (lane + 64) * kWinLd + K;
+            double a[2][3], hr[3][3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const bool col = m < 2 || three;
+                a[0][m] = (r0 && col) ? pa[m] : 0.0;
+                a[1][m] = (r1 && col) ? pb[m] : 0.0;
+            }
+#pragma unroll
+            for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc)
+                    hr[rr][cc] = (K + 1 + rr <= lu && (cc < 2 || three)) ? Hw[(K + 1 + rr) * kWinLd + K + cc] : 0.0;
+            if (r0) win_refl3(pa, 1, three, tau, w1, w2, a[0][0], a[0][1], a[0][2]);
+            if (r1) win_refl3(pb, 1, three, tau, w1, w2, a[1][0], a[1][1], a[1][2]);
             if (tau != 0.0) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const double v = tau * (B[0][c] + w1 * B[1][c] + w2 * B[2][c]);
-                    B[0][c] -= v;
-                    B[1][c] -= v * w1;
-                    B[2][c] -= v * w2;
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const double v = tau * (B[r][0] + w1 * B[r][1] + w2 * B[r][2]);
-                    B[r][0] -= v;
-                    B[r][1] -= v * w1;
-                    B[r][2] -= v * w2;
+                for (int rr = 0; rr < 3; ++rr) {
+                    const double q = tau * (hr[rr][0] + w1 * hr[rr][1] + w2 * hr[rr][2]);
+                    hr[rr][0] -= q;
+                    hr[rr][1] -= q * w1;
+                    hr[rr][2] -= q * w2;
                 }
             }
-            const int kn = k + 1;
-            double beta = 0.0;
-            if (kn <= u - 1) house3(B[1][0], B[2][0], kn + 2 <= u ? B[3][0] : 0.0, &tn, &w1n, &w2n, &beta);
+            const int kn = K + 1;
+            double tn = 0.0, w1n = 0.0, w2n = 0.0, beta = 0.0;
+            if (kn <= lu - 1) house3(hr[0][0], hr[1][0], kn + 2 <= lu ? hr[2][0] : 0.0, &tn, &w1n, &w2n, &beta);
             if (tn != 0.0) {
-                B[1][0] = beta;
-                B[2][0] = 0.0;
-                B[3][0] = 0.0;
+                hr[0][0] = beta;
+                hr[1][0] = 0.0;
+                hr[2][0] = 0.0;
             }
+            // every lane stores the same values
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int rr = 0; rr < 3; ++rr)
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    if (r < nr && (c < 2 || three)) H[(int64_t)(k + r) * ld + k + c] = B[r][c];
-        } else if (i >= 1 && t + 1 == kSep * i) {
-            double x, y, z, beta;
-            intro_xyz(H, ld, l, g->s[i], g->t[i], &x, &y, &z);
-            house3(x, y, z, &tn, &w1n, &w2n, &beta);
+                for (int cc = 0; cc < 3; ++cc)
+                    if (K + 1 + rr <= lu && (cc < 2 || three)) Hw[(K + 1 + rr) * kWinLd + K + cc] = hr[rr][cc];
+            tau = tn;
+            w1 = w1n;
+            w2 = w2n;
         }
-        g->tau[p ^ 1][i] = tn;
-        g->w1[p ^ 1][i] = w1n;
-        g->w2[p ^ 1][i] = w2n;
+        __syncthreads();
     }
-    int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= total || nb < 1) return;
-    const int kilo = l + t - kSep * ilo, kihi = l + t - kSep * ihi;
-    const int tri = nb * (nb - 1) / 2;
-    if (e < nb * tail) {  // left-only tail columns
-        const int i = ilo + e / tail, c = kilo + 3 + e % tail;
-        const double tau = g->tau[p][i];
-        if (tau != 0.0) refl_left(H, ld, l + t - kSep * i, u, tau, g->w1[p][i], g->w2[p][i], c);
-        return;
-    }
-    e -= nb * tail;
-    if (e < tri) {  // left-only gap columns
-        int q, m;
-        tri_index(e, &q, &m);
-        const int i = ilo + q, k = l + t - kSep * i;
-        const double tau = g->tau[p][i];
-        if (tau != 0.0) refl_left(H, ld, k, u, tau, g->w1[p][i], g->w2[p][i], k + kSep * m + 3);
-        return;
-    }
-    e -= tri;
-    if (e < head * nb) {  // right-only head rows
-        const int row = l + e / nb, j = ilo + e % nb;
-        const double tau = g->tau[p][j];
-        if (tau != 0.0) refl_right(H, ld, l + t - kSep * j, u, tau, g->w1[p][j], g->w2[p][j], row);
-        return;
-    }
-    e -= head * nb;
-    if (e < tri) {  // right-only gap rows k_i + 3 of bulge j < i
-        int q, m;
-        tri_index(e, &q, &m);
-        const int i = ilo + q, j = ilo + m;
-        const double tau = g->tau[p][j];
-        if (tau != 0.0) refl_right(H, ld, l + t - kSep * j, u, tau, g->w1[p][j], g->w2[p][j], l + t - kSep * i + 3);
-        return;
-    }
-    e -= tri;
-    if (e < tri) {  // crossing block rows(i) x columns(j), j < i: left of i, then right of j
-        int q, m;
-        tri_index(e, &q, &m);
-        const int i = ilo + q, j = ilo + m;
-        const int ki = l + t - kSep * i, kj = l + t - kSep * j;
-        const double ti = g->tau[p][i], tj = g->tau[p][j];
-        const bool cj3 = kj + 2 <= u;
-        if (ti != 0.0) {
-            const double w1 = g->w1[p][i], w2 = g->w2[p][i];
-            for (int c = 0; c < (cj3 ? 3 : 2); ++c) refl_left(H, ld, ki, u, ti, w1, w2, kj + c);
+    double* Ut = Ut_all + (size_t)c * kWin * kWin;
+    for (int r = j; r < wc; r += kWinThreads / 64)
+        for (int q = lane; q < wc; q += 64) {
+            if (r <= q + 3) H[(int64_t)(ws + r) * ld + ws + q] = Hw[r * kWinLd + q];
+            Ut[r * kWin + q] = Uw[r * kWinLd + q];
         }
-        if (tj != 0.0) {
-            const double w1 = g->w1[p][j], w2 = g->w2[p][j];
-            for (int r = 0; r < 3; ++r) refl_right(H, ld, kj, u, tj, w1, w2, ki + r);
-        }
+    if (mine && lane == 0) {
+        g->tau[0][i0 + j] = tau;
+        g->w1[0][i0 + j] = w1;
+        g->w2[0][i0 + j] = w2;
     }
+}
+
+// U^T of chain blockIdx.y into LDS (kWin x kWin, zero outside the window's wc x wc).
+__device__ __forceinline__ void win_stage_u(double* Us, const double* Ut_all, int c, int wc) {
+    const double* Ut = Ut_all + (size_t)c * kWin * kWin;
+    for (int e = threadIdx.x; e < kWin * kWin; e += kWinThreads) {
+        const int r = e / kWin, q = e - r * kWin;
+        Us[r * kWinLd + q] = (r < wc && q < wc) ? Ut[r * kWin + q] : 0.0;
+    }
+}
+
+// X <- U^T X on the window's rows right of it (columns we+1..u). A wave owns 16 columns:
+// it loads their wc window rows (matrix-core B operand), multiplies, and stores them back,
+// so the product is in place. D = U^T X in 16 x 16 tiles: lane l holds rows 4v + l/16 of
+// column l % 16.
+__global__ __launch_bounds__(kWinThreads) void k_win_rows(double* H, int64_t ld, int l, int u, int b, int t0,
+                                                          const double* Ut_all) {
+    __shared__ double Us[kWin * kWinLd];
+    const int c = blockIdx.y;
+    const WinGeom G = win_geom(l, u, b, c, t0);
+    if (!G.active) return;
+    const int ws = G.ws, wc = G.we - G.ws + 1;
+    const int cbeg = G.we + 1 + blockIdx.x * kWinCols;
+    if (cbeg > u) return;
+    win_stage_u(Us, Ut_all, c, wc);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const int col = cbeg + (threadIdx.x >> 6) * 16 + lr;
+    const bool cok = col <= u;
+    double xb[kWin / 4];
+#pragma unroll
+    for (int kk = 0; kk < kWin / 4; ++kk) {
+        const int k = 4 * kk + lk;
+        xb[kk] = (cok && k < wc) ? H[(int64_t)(ws + k) * ld + col] : 0.0;
+    }
+    qr_gd4 acc[kWin / 16];
+#pragma unroll
+    for (int ri = 0; ri < kWin / 16; ++ri) acc[ri] = qr_gd4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < kWin / 4; ++kk)
+#pragma unroll
+        for (int ri = 0; ri < kWin / 16; ++ri)
+            acc[ri] = mfma_f64(Us[(16 * ri + lr) * kWinLd + 4 * kk + lk], xb[kk], acc[ri]);
+    if (!cok) return;
+#pragma unroll
+    for (int ri = 0; ri < kWin / 16; ++ri)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 16 * ri + 4 * v + lk;
+            if (r < wc) H[(int64_t)(ws + r) * ld + col] = acc[ri][v];
+        }
+}
+
+// Y <- Y U on the window's columns above it (rows l..ws-1). A wave owns 16 rows: it loads
+// their wc window columns (matrix-core A operand), multiplies, and stores them back.
+// D = Y U in 16 x 16 tiles: lane l holds rows 4v + l/16 of column l % 16.
+__global__ __launch_bounds__(kWinThreads) void k_win_cols(double* H, int64_t ld, int l, int u, int b, int t0,
+                                                          const double* Ut_all) {
+    __shared__ double Us[kWin * kWinLd];
+    const int c = blockIdx.y;
+    const WinGeom G = win_geom(l, u, b, c, t0);
+    if (!G.active) return;
+    const int ws = G.ws, wc = G.we - G.ws + 1;
+    const int rbeg = l + blockIdx.x * kWinCols;
+    if (rbeg >= ws) return;
+    win_stage_u(Us, Ut_all, c, wc);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const int r0 = rbeg + (threadIdx.x >> 6) * 16;
+    const int row = r0 + lr;
+    double ya[kWin / 4];
+#pragma unroll
+    for (int kk = 0; kk < kWin / 4; ++kk) {
+        const int k = 4 * kk + lk;
+        ya[kk] = (row < ws && k < wc) ? H[(int64_t)row * ld + ws + k] : 0.0;
+    }
+    qr_gd4 acc[kWin / 16];
+#pragma unroll
+    for (int ci = 0; ci < kWin / 16; ++ci) acc[ci] = qr_gd4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < kWin / 4; ++kk)
+#pragma unroll
+        for (int ci = 0; ci < kWin / 16; ++ci)
+            acc[ci] = mfma_f64(ya[kk], Us[(16 * ci + lr) * kWinLd + 4 * kk + lk], acc[ci]);
+#pragma unroll
+    for (int ci = 0; ci < kWin / 16; ++ci)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + 4 * v + lk, q = 16 * ci + lr;
+            if (r < ws && q < wc) H[(int64_t)r * ld + ws + q] = acc[ci][v];
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -1198,8 +1360,7 @@ int lb_impl_hessenberg(lb_ctx* c, int M, double* A, int64_t lda) {
     return LB_OK;
 }
 
-int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam, int64_t* sweeps, int64_t* steps,
-                     int64_t* work) {
+int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam, lb_spectrum_info* info) {
     hipStream_t s = c->stream;
     // the working copy sits past the reduction's own scratch
     // the working copy's rows padded to 16 doubles (128 bytes) while M * ld keeps
@@ -1208,19 +1369,22 @@ int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam
     if ((int64_t)M * ld > (int64_t)INT32_MAX) ld = M;
     const size_t o_h = HessLayout(M).end;
     const size_t o_g = o_h + lb_align(sizeof(double) * (size_t)M * ld, 256);
-    int rc = lb_ws_reserve(c, o_g + sizeof(QrGlobal));
+    const size_t o_u = o_g + lb_align(sizeof(QrGlobal), 256);
+    const size_t n_u = (size_t)(kWideBulges / kChain) * kWin * kWin;  // U^T of every chain of a sweep
+    int rc = lb_ws_reserve(c, o_u + sizeof(double) * n_u);
     if (rc) return rc;
     rc = lb_host_reserve(c, sizeof(QrGlobal));
     if (rc) return rc;
     double* H = (double*)((char*)c->ws + o_h);
     QrGlobal* g = (QrGlobal*)((char*)c->ws + o_g);
+    double* Ut = (double*)((char*)c->ws + o_u);
     LB_HIP(hipMemcpy2DAsync(H, sizeof(double) * ld, Q, sizeof(double) * ldq, sizeof(double) * M, M,
                             hipMemcpyDeviceToDevice, s));
     rc = lb_impl_hessenberg(c, M, H, ld);
     if (rc) return rc;
     hipLaunchKernelGGL(k_qr_init, dim3(1), dim3(1024), 0, s, (const double*)H, ld, M, g);
     LB_CHECK_LAUNCH();
-    int64_t n_sweeps = 0, n_steps = 0, n_work = 0;
+    int64_t n_sweeps = 0, n_steps = 0, n_work = 0, n_rounds = 0, n_flops = 0;
     QrGlobal* hg = (QrGlobal*)c->host;
     int u = M - 1;
     // every pass either lowers u or counts a sweep, and sweeps per split are capped
@@ -1238,25 +1402,41 @@ int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam
             const int l = hg->l, b = hg->b;
             if (l < 0 || b < 1 || b > kWideBulges || u - l + 1 <= kSmallBlock)
                 return lb_fail(LB_ERR_DEVICE, "QR iteration: inconsistent sweep l=%d u=%d b=%d", l, u, b);
-            const int T = kSep * (b - 1) + (u - l);
+            const int nch = (b + kChain - 1) / kChain;
+            const int nbl = b - (nch - 1) * kChain;
+            // chain steps until the last chain's last bulge has left the block
+            const int T = (nch - 1) * kChainGap + kSep * (nbl - 1) + (u - l);
             const int64_t na = u - l + 1;
             ++n_sweeps;
             n_steps += T;
             n_work += (int64_t)b * (na * na + 3 * na - 7);
-            for (int t = 0; t < T; ++t) {
-                const int ihi = std::min(b - 1, t / kSep);
-                int ilo = 0;
-                while (ilo <= ihi && l + t - kSep * ilo > u - 1) ++ilo;
-                const int nb = ihi - ilo + 1;
-                int tail = 0, head = 0, total = 0;
-                if (nb >= 1) {
-                    tail = std::max(0, u - (l + t - kSep * ilo) - 2);
-                    head = (l + t - kSep * ihi) - l;
-                    total = nb * tail + head * nb + 3 * (nb * (nb - 1) / 2);
+            for (int t0 = 0; t0 < T; t0 += kAdvance) {
+                int right = 0, above = 0, below_ws = u + 1;  // first row of the next chain's window (ahead)
+                for (int ch = 0; ch < nch; ++ch) {
+                    const WinGeom G = win_geom(l, u, b, ch, t0);
+                    if (!G.active) continue;
+                    if (G.ws < l || G.we >= below_ws || G.we - G.ws + 1 > kWin)
+                        return lb_fail(LB_ERR_DEVICE, "QR iteration: window [%d, %d] of chain %d in [%d, %d]", G.ws, G.we,
+                                       ch, l, u);
+                    below_ws = G.ws;
+                    right = std::max(right, u - G.we);
+                    above = std::max(above, G.ws - l);
+                    const int64_t wc = G.we - G.ws + 1;
+                    n_flops += 2 * wc * wc * (int64_t)((u - G.we) + (G.ws - l));
                 }
-                hipLaunchKernelGGL(k_qr_step, dim3(std::max(1u, lb_blocks(total, 256))), dim3(256), 0, s, H, ld, l, u,
-                                   b, t, ilo, ihi, tail, head, total, g);
+                ++n_rounds;
+                hipLaunchKernelGGL(k_win_chase, dim3(nch), dim3(kWinThreads), 0, s, H, ld, l, u, b, t0, g, Ut);
                 LB_CHECK_LAUNCH();
+                if (right > 0) {
+                    hipLaunchKernelGGL(k_win_rows, dim3(lb_blocks(right, kWinCols), nch), dim3(kWinThreads), 0, s, H, ld,
+                                       l, u, b, t0, (const double*)Ut);
+                    LB_CHECK_LAUNCH();
+                }
+                if (above > 0) {
+                    hipLaunchKernelGGL(k_win_cols, dim3(lb_blocks(above, kWinCols), nch), dim3(kWinThreads), 0, s, H, ld,
+                                       l, u, b, t0, (const double*)Ut);
+                    LB_CHECK_LAUNCH();
+                }
             }
         } else if (hg->u >= u) {
             return lb_fail(LB_ERR_DEVICE, "QR iteration: no progress at u=%d", u);
@@ -1265,9 +1445,11 @@ int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam
         if (u >= 0) lb_report(c, "qr", (double)(M - 1 - u) / M);
     }
     lb_report(c, "qr", 1.0);
-    if (sweeps) *sweeps = n_sweeps + hg->sweeps;
-    if (steps) *steps = n_steps + hg->steps;
-    if (work) *work = n_work + hg->work;
+    info->sweeps = n_sweeps + hg->sweeps;
+    info->chain_steps = n_steps + hg->steps;
+    info->updates = n_work + hg->work;
+    info->rounds = n_rounds;
+    info->product_flops = n_flops;
     return LB_OK;
 }
 

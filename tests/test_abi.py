@@ -132,11 +132,13 @@ def test_spectrum_info_layout_matches_header(tmp_path):
         pytest.skip("no host C compiler")
     src = tmp_path / "spec.c"
     src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "lindblad.h"\n'
-                   'int main(void) { printf("%zu %zu %zu %d\\n", sizeof(lb_spectrum_info), '
+                   'int main(void) { printf("%zu %zu %zu %zu %zu %d\\n", sizeof(lb_spectrum_info), '
                    'offsetof(lb_spectrum_info, chain_steps), offsetof(lb_spectrum_info, updates), '
+                   'offsetof(lb_spectrum_info, rounds), offsetof(lb_spectrum_info, product_flops), '
                    'LB_SPECTRUM_MAX_M); return 0; }\n')
     exe = tmp_path / "spec"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     S = lb.SpectrumInfo
-    assert got == [ctypes.sizeof(S), S.chain_steps.offset, S.updates.offset, 46340]
+    assert got == [ctypes.sizeof(S), S.chain_steps.offset, S.updates.offset, S.rounds.offset,
+                   S.product_flops.offset, 46340]
