@@ -245,6 +245,8 @@ int lb_impl_gemm_c128(hipStream_t s, bool ca, bool cb, int64_t m, int64_t n, int
                       int64_t work_elems);
 int lb_gemm_c128_splits(int64_t m, int64_t n, int64_t k);
 int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam, lb_spectrum_info* info);
+// Creates the context's auxiliary stream and its fork/join events on first use.
+int lb_aux_stream(lb_ctx* c);
 int lb_impl_spectrum_histogram(lb_ctx* c, int64_t n, const double* lam, double re0, double re1, double im0,
                                double im1, int nx, int ny, int64_t* counts);
 int lb_impl_steady_dense(lb_ctx* c, int64_t M, const double* Q, int64_t ldq, const double* K, const lb_secular* pre,

@@ -863,7 +863,7 @@ static int64_t quad_order(int N, std::vector<int2>& out) {
     return (int64_t)out.size();
 }
 
-static int aux_stream(lb_ctx* c) {
+int lb_aux_stream(lb_ctx* c) {
     if (c->aux) return LB_OK;
     LB_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
     LB_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
@@ -894,7 +894,7 @@ int lb_impl_prepare_dense(lb_ctx* c, int N, const double* H, const double* gamma
     const size_t o_pairs = take(sizeof(int2) * ((size_t)P + (size_t)norder) + 8);  // pairs, then the quad order
     int rc = lb_ws_reserve(c, off);
     if (rc) return rc;
-    rc = aux_stream(c);
+    rc = lb_aux_stream(c);
     if (rc) return rc;
     const size_t hb = sizeof(int2) * ((size_t)P + (size_t)norder);
     rc = lb_host_reserve(c, hb);

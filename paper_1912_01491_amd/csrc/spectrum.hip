@@ -961,38 +961,61 @@ __device__ __forceinline__ void win_stage_u(double* Us, const double* Ut_all, in
     }
 }
 
-// X <- U^T X on the window's rows right of it (columns we+1..u). A wave owns 16 columns:
-// it loads their wc window rows (matrix-core B operand), multiplies, and stores them back,
-// so the product is in place. D = U^T X in 16 x 16 tiles: lane l holds rows 4v + l/16 of
-// column l % 16.
+// Last column of the near part of chain c's row product: the columns the next round's
+// chase of chain c reads (kAdvance past the window), extended to the end of the window of
+// the chain ahead (c - 1), so that the block where chain c's rows cross that window's
+// columns takes the whole left product before either part of that chain's column product
+// (a left product split by columns, or a right one split by rows, is exact only if the
+// other one does not fall between its parts).
+__host__ __device__ inline int win_row_split(int l, int u, int b, int c, int t0, int we) {
+    int nb = we + kAdvance;
+    if (c > 0) {
+        const WinGeom Ga = win_geom(l, u, b, c - 1, t0);
+        if (Ga.active && Ga.we > nb) nb = Ga.we;
+    }
+    return nb < u ? nb : u;
+}
+
+// X <- U^T X on the window's rows right of it: the near columns we+1..nb (far = 0) or the
+// far columns nb+1..u (far = 1), nb = win_row_split. A wave owns 16 columns: it loads their
+// wc window rows (matrix-core B operand), multiplies, and stores them back, so the product
+// is in place. D = U^T X in 16 x 16 tiles: lane l holds rows 4v + l/16 of column l % 16.
 __global__ __launch_bounds__(kWinThreads) void k_win_rows(double* H, int64_t ld, int l, int u, int b, int t0,
-                                                          const double* Ut_all) {
+                                                          const double* Ut_all, int far) {
     __shared__ double Us[kWin * kWinLd];
     const int c = blockIdx.y;
     const WinGeom G = win_geom(l, u, b, c, t0);
     if (!G.active) return;
     const int ws = G.ws, wc = G.we - G.ws + 1;
-    const int cbeg = G.we + 1 + blockIdx.x * kWinCols;
-    if (cbeg > u) return;
+    const int nb = win_row_split(l, u, b, c, t0, G.we);
+    const int cend = far ? u : nb;  // last column
+    const int cbeg = (far ? nb + 1 : G.we + 1) + blockIdx.x * kWinCols;
+    if (cbeg > cend) return;
     win_stage_u(Us, Ut_all, c, wc);
     __syncthreads();
     const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
     const int col = cbeg + (threadIdx.x >> 6) * 16 + lr;
-    const bool cok = col <= u;
-    double xb[kWin / 4];
-#pragma unroll
-    for (int kk = 0; kk < kWin / 4; ++kk) {
-        const int k = 4 * kk + lk;
-        xb[kk] = (cok && k < wc) ? H[(int64_t)(ws + k) * ld + col] : 0.0;
-    }
+    const bool cok = col <= cend;
+    // the window rows in two halves (fewer registers, two workgroups per compute unit);
+    // every load precedes every store, so the product stays in place
+    constexpr int KH = kWin / 8;
     qr_gd4 acc[kWin / 16];
 #pragma unroll
     for (int ri = 0; ri < kWin / 16; ++ri) acc[ri] = qr_gd4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int kk = 0; kk < kWin / 4; ++kk)
+    for (int half = 0; half < 2; ++half) {
+        double xb[KH];
 #pragma unroll
-        for (int ri = 0; ri < kWin / 16; ++ri)
-            acc[ri] = mfma_f64(Us[(16 * ri + lr) * kWinLd + 4 * kk + lk], xb[kk], acc[ri]);
+        for (int kk = 0; kk < KH; ++kk) {
+            const int k = 4 * (kk + KH * half) + lk;
+            xb[kk] = (cok && k < wc) ? H[(int64_t)(ws + k) * ld + col] : 0.0;
+        }
+#pragma unroll
+        for (int kk = 0; kk < KH; ++kk)
+#pragma unroll
+            for (int ri = 0; ri < kWin / 16; ++ri)
+                acc[ri] = mfma_f64(Us[(16 * ri + lr) * kWinLd + 4 * (kk + KH * half) + lk], xb[kk], acc[ri]);
+    }
     if (!cok) return;
 #pragma unroll
     for (int ri = 0; ri < kWin / 16; ++ri)
@@ -1003,43 +1026,62 @@ __global__ __launch_bounds__(kWinThreads) void k_win_rows(double* H, int64_t ld,
         }
 }
 
-// Y <- Y U on the window's columns above it (rows l..ws-1). A wave owns 16 rows: it loads
-// their wc window columns (matrix-core A operand), multiplies, and stores them back.
-// D = Y U in 16 x 16 tiles: lane l holds rows 4v + l/16 of column l % 16.
+// First row of chain c's column block above its window that the next round's chase of
+// chain c + 1 (the chain behind it) reads: rows from there to ws form the near part of
+// the column product, rows l.. up to there the far part. Chains further behind never
+// reach these columns within a round (their windows end more than kAdvance columns
+// before ws).
+__host__ __device__ inline int win_split(int l, int u, int b, int c, int t0, int ws) {
+    if ((c + 1) * kChain >= b) return ws;
+    const WinGeom Gn = win_geom(l, u, b, c + 1, t0 + kAdvance);
+    if (!Gn.active) return ws;
+    return Gn.ws < ws ? Gn.ws : ws;
+}
+
+// Y <- Y U on the window's columns above it: the near rows split..ws-1 (far = 0) or the far
+// rows l..split-1 (far = 1). A wave owns 16 rows: it loads their wc window columns
+// (matrix-core A operand), multiplies, and stores them back. D = Y U in 16 x 16 tiles:
+// lane l holds rows 4v + l/16 of column l % 16.
 __global__ __launch_bounds__(kWinThreads) void k_win_cols(double* H, int64_t ld, int l, int u, int b, int t0,
-                                                          const double* Ut_all) {
+                                                          const double* Ut_all, int far) {
     __shared__ double Us[kWin * kWinLd];
     const int c = blockIdx.y;
     const WinGeom G = win_geom(l, u, b, c, t0);
     if (!G.active) return;
     const int ws = G.ws, wc = G.we - G.ws + 1;
-    const int rbeg = l + blockIdx.x * kWinCols;
-    if (rbeg >= ws) return;
+    const int split = win_split(l, u, b, c, t0, ws);
+    const int rfirst = far ? l : split, rend = far ? split : ws;  // rows rfirst .. rend-1
+    const int rbeg = rfirst + blockIdx.x * kWinCols;
+    if (rbeg >= rend) return;
     win_stage_u(Us, Ut_all, c, wc);
     __syncthreads();
     const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
     const int r0 = rbeg + (threadIdx.x >> 6) * 16;
     const int row = r0 + lr;
-    double ya[kWin / 4];
-#pragma unroll
-    for (int kk = 0; kk < kWin / 4; ++kk) {
-        const int k = 4 * kk + lk;
-        ya[kk] = (row < ws && k < wc) ? H[(int64_t)row * ld + ws + k] : 0.0;
-    }
+    constexpr int KH = kWin / 8;
     qr_gd4 acc[kWin / 16];
 #pragma unroll
     for (int ci = 0; ci < kWin / 16; ++ci) acc[ci] = qr_gd4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int kk = 0; kk < kWin / 4; ++kk)
+    for (int half = 0; half < 2; ++half) {
+        double ya[KH];
 #pragma unroll
-        for (int ci = 0; ci < kWin / 16; ++ci)
-            acc[ci] = mfma_f64(ya[kk], Us[(16 * ci + lr) * kWinLd + 4 * kk + lk], acc[ci]);
+        for (int kk = 0; kk < KH; ++kk) {
+            const int k = 4 * (kk + KH * half) + lk;
+            ya[kk] = (row < rend && k < wc) ? H[(int64_t)row * ld + ws + k] : 0.0;
+        }
+#pragma unroll
+        for (int kk = 0; kk < KH; ++kk)
+#pragma unroll
+            for (int ci = 0; ci < kWin / 16; ++ci)
+                acc[ci] = mfma_f64(ya[kk], Us[(16 * ci + lr) * kWinLd + 4 * (kk + KH * half) + lk], acc[ci]);
+    }
 #pragma unroll
     for (int ci = 0; ci < kWin / 16; ++ci)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = r0 + 4 * v + lk, q = 16 * ci + lr;
-            if (r < ws && q < wc) H[(int64_t)r * ld + ws + q] = acc[ci][v];
+            if (r < rend && q < wc) H[(int64_t)r * ld + ws + q] = acc[ci][v];
         }
 }
 
@@ -1370,7 +1412,8 @@ int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam
     const size_t o_h = HessLayout(M).end;
     const size_t o_g = o_h + lb_align(sizeof(double) * (size_t)M * ld, 256);
     const size_t o_u = o_g + lb_align(sizeof(QrGlobal), 256);
-    const size_t n_u = (size_t)(kWideBulges / kChain) * kWin * kWin;  // U^T of every chain of a sweep
+    const size_t n_u1 = (size_t)(kWideBulges / kChain) * kWin * kWin;  // U^T of every chain of a round
+    const size_t n_u = 2 * n_u1;  // two rounds: the far products of one overlap the next round's chase
     int rc = lb_ws_reserve(c, o_u + sizeof(double) * n_u);
     if (rc) return rc;
     rc = lb_host_reserve(c, sizeof(QrGlobal));
@@ -1378,6 +1421,9 @@ int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam
     double* H = (double*)((char*)c->ws + o_h);
     QrGlobal* g = (QrGlobal*)((char*)c->ws + o_g);
     double* Ut = (double*)((char*)c->ws + o_u);
+    rc = lb_aux_stream(c);
+    if (rc) return rc;
+    hipStream_t s2 = c->aux;
     LB_HIP(hipMemcpy2DAsync(H, sizeof(double) * ld, Q, sizeof(double) * ldq, sizeof(double) * M, M,
                             hipMemcpyDeviceToDevice, s));
     rc = lb_impl_hessenberg(c, M, H, ld);
@@ -1410,8 +1456,15 @@ int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam
             ++n_sweeps;
             n_steps += T;
             n_work += (int64_t)b * (na * na + 3 * na - 7);
-            for (int t0 = 0; t0 < T; t0 += kAdvance) {
-                int right = 0, above = 0, below_ws = u + 1;  // first row of the next chain's window (ahead)
+            // Round r: the chase, then on this stream the near parts of the products (what the next
+            // round's chases read: win_row_split, win_split), then on the auxiliary stream the far
+            // parts, which touch no window of the next round and so run during its chase. The near
+            // parts of a round wait for the far parts of the one before (they share rows and
+            // columns); the window factors alternate between two buffers.
+            for (int t0 = 0, r = 0; t0 < T; t0 += kAdvance, ++r) {
+                double* Ur = Ut + (size_t)(r & 1) * n_u1;
+                int near_right = 0, far_right = 0, near_above = 0, far_above = 0;
+                int below_ws = u + 1;  // first row of the chain ahead's window
                 for (int ch = 0; ch < nch; ++ch) {
                     const WinGeom G = win_geom(l, u, b, ch, t0);
                     if (!G.active) continue;
@@ -1419,25 +1472,44 @@ int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam
                         return lb_fail(LB_ERR_DEVICE, "QR iteration: window [%d, %d] of chain %d in [%d, %d]", G.ws, G.we,
                                        ch, l, u);
                     below_ws = G.ws;
-                    right = std::max(right, u - G.we);
-                    above = std::max(above, G.ws - l);
+                    const int split = win_split(l, u, b, ch, t0, G.ws);
+                    const int nb = win_row_split(l, u, b, ch, t0, G.we);
+                    near_right = std::max(near_right, nb - G.we);
+                    far_right = std::max(far_right, u - nb);
+                    near_above = std::max(near_above, G.ws - split);
+                    far_above = std::max(far_above, split - l);
                     const int64_t wc = G.we - G.ws + 1;
                     n_flops += 2 * wc * wc * (int64_t)((u - G.we) + (G.ws - l));
                 }
                 ++n_rounds;
-                hipLaunchKernelGGL(k_win_chase, dim3(nch), dim3(kWinThreads), 0, s, H, ld, l, u, b, t0, g, Ut);
+                hipLaunchKernelGGL(k_win_chase, dim3(nch), dim3(kWinThreads), 0, s, H, ld, l, u, b, t0, g, Ur);
                 LB_CHECK_LAUNCH();
-                if (right > 0) {
-                    hipLaunchKernelGGL(k_win_rows, dim3(lb_blocks(right, kWinCols), nch), dim3(kWinThreads), 0, s, H, ld,
-                                       l, u, b, t0, (const double*)Ut);
+                LB_HIP(hipStreamWaitEvent(s, c->ev_join, 0));
+                if (near_right > 0) {
+                    hipLaunchKernelGGL(k_win_rows, dim3(lb_blocks(near_right, kWinCols), nch), dim3(kWinThreads), 0, s,
+                                       H, ld, l, u, b, t0, (const double*)Ur, 0);
                     LB_CHECK_LAUNCH();
                 }
-                if (above > 0) {
-                    hipLaunchKernelGGL(k_win_cols, dim3(lb_blocks(above, kWinCols), nch), dim3(kWinThreads), 0, s, H, ld,
-                                       l, u, b, t0, (const double*)Ut);
+                if (near_above > 0) {
+                    hipLaunchKernelGGL(k_win_cols, dim3(lb_blocks(near_above, kWinCols), nch), dim3(kWinThreads), 0, s,
+                                       H, ld, l, u, b, t0, (const double*)Ur, 0);
                     LB_CHECK_LAUNCH();
                 }
+                LB_HIP(hipEventRecord(c->ev_fork, s));
+                LB_HIP(hipStreamWaitEvent(s2, c->ev_fork, 0));
+                if (far_right > 0) {
+                    hipLaunchKernelGGL(k_win_rows, dim3(lb_blocks(far_right, kWinCols), nch), dim3(kWinThreads), 0, s2,
+                                       H, ld, l, u, b, t0, (const double*)Ur, 1);
+                    LB_CHECK_LAUNCH();
+                }
+                if (far_above > 0) {
+                    hipLaunchKernelGGL(k_win_cols, dim3(lb_blocks(far_above, kWinCols), nch), dim3(kWinThreads), 0, s2,
+                                       H, ld, l, u, b, t0, (const double*)Ur, 1);
+                    LB_CHECK_LAUNCH();
+                }
+                LB_HIP(hipEventRecord(c->ev_join, s2));
             }
+            LB_HIP(hipStreamWaitEvent(s, c->ev_join, 0));
         } else if (hg->u >= u) {
             return lb_fail(LB_ERR_DEVICE, "QR iteration: no progress at u=%d", u);
         }
