@@ -1118,20 +1118,21 @@ __global__ void k_hist(int64_t n, const double2* lam, double re0, double dx, dou
 // three times.
 // ---------------------------------------------------------------------------
 
-// col[r] = A[r][c] - sum_{k<i} Y[k][r] V[k][c]
+// col[r] = A[r][c] - sum_{k<i} Y[k][r] V[k][c] (V's columns ldv apart)
 __global__ __launch_bounds__(256) void k_bh_col(const double* A, int64_t lda, int M, int c, int i, const double* V,
-                                                const double* Y, double* col) {
+                                                int ldv, const double* Y, double* col) {
     const int r = blockIdx.x * 256 + threadIdx.x;
     if (r >= M) return;
     double s = A[(int64_t)r * lda + c];
-    for (int k = 0; k < i; ++k) s -= Y[(int64_t)k * M + r] * V[(int64_t)k * M + c];
+    for (int k = 0; k < i; ++k) s -= Y[(int64_t)k * M + r] * V[(int64_t)k * ldv + c];
     col[r] = s;
 }
 
 // out[k] = sum_{r >= r0} V[k][r] x[r] for k < gridDim.x (a block per k, fixed order)
-__global__ __launch_bounds__(256) void k_bh_dots(const double* V, int M, int r0, const double* x, double* out) {
+__global__ __launch_bounds__(256) void k_bh_dots(const double* V, int ldv, int M, int r0, const double* x,
+                                                 double* out) {
     __shared__ double red[4];
-    const double* vk = V + (int64_t)blockIdx.x * M;
+    const double* vk = V + (int64_t)blockIdx.x * ldv;
     double s = 0.0;
     for (int r = r0 + threadIdx.x; r < M; r += 256) s = fma(vk[r], x[r], s);
     s = block_sum256(s, red);
@@ -1139,7 +1140,7 @@ __global__ __launch_bounds__(256) void k_bh_dots(const double* V, int M, int r0,
 }
 
 // col[r] -= sum_{m<i} V[m][r] z[m], z = T^T w, for rows r > j0
-__global__ __launch_bounds__(256) void k_bh_left(const double* V, int M, int i, int j0, const double* T,
+__global__ __launch_bounds__(256) void k_bh_left(const double* V, int ldv, int M, int i, int j0, const double* T,
                                                  const double* w, double* col) {
     __shared__ double z[kPanel];
     if (threadIdx.x < i) {
@@ -1151,19 +1152,19 @@ __global__ __launch_bounds__(256) void k_bh_left(const double* V, int M, int i, 
     const int r = j0 + 1 + blockIdx.x * 256 + threadIdx.x;
     if (r >= M) return;
     double s = col[r];
-    for (int m = 0; m < i; ++m) s -= V[(int64_t)m * M + r] * z[m];
+    for (int m = 0; m < i; ++m) s -= V[(int64_t)m * ldv + r] * z[m];
     col[r] = s;
 }
 
 // Reflector i of the panel from col[c+1..M-1]: V[i] (zero above row c+1, 1 at c+1), tau, beta.
-__global__ __launch_bounds__(256) void k_bh_house(const double* col, int M, int c, int i, double* V, double* taus,
-                                                  double* betas) {
+__global__ __launch_bounds__(256) void k_bh_house(const double* col, int M, int c, int i, double* V, int ldv,
+                                                  double* taus, double* betas) {
     __shared__ double red[4];
     __shared__ double bc[2];
     double s = 0.0;
     for (int r = c + 2 + threadIdx.x; r < M; r += 256) s = fma(col[r], col[r], s);
     const double sigma = block_sum256(s, red);
-    double* vi = V + (int64_t)i * M;
+    double* vi = V + (int64_t)i * ldv;
     if (threadIdx.x == 0) {
         const double alpha = col[c + 1];
         double tau = 0.0, scale = 0.0, beta = alpha;
@@ -1241,7 +1242,7 @@ __global__ void k_bh_zero(double* x, int64_t n) {
 struct BlockedLayout {
     size_t V, Y, W, W2, col, y, T, w, u, tau, beta, end;
     explicit BlockedLayout(int M) {
-        const size_t mat = lb_align(sizeof(double) * (size_t)M * kPanel, 256);
+        const size_t mat = lb_align(sizeof(double) * (size_t)(M + 1) * kPanel, 256);  // V's columns: M rounded to even
         const size_t vec = lb_align(sizeof(double) * (size_t)M, 256);
         const size_t sm = lb_align(sizeof(double) * kPanel, 256);
         V = 0;
@@ -1284,7 +1285,10 @@ int hessenberg_blocked(lb_ctx* c, int M, double* A, int64_t lda) {
     hipStream_t s = c->stream;
     const BlockedLayout lay(M);
     // rows 16-byte aligned: the GEMV reads 16-byte pieces (V's rows start on 256 bytes)
-    const bool aligned = (lda % 2) == 0 && ((uintptr_t)A % 16) == 0 && (M % 2) == 0;
+    // V's columns ldv apart, ldv even: every v_i starts on 16 bytes, so the GEMV reads 16-byte pieces
+    // of A and v whenever A's rows do
+    const int ldv = M + (M & 1);
+    const bool aligned = (lda % 2) == 0 && ((uintptr_t)A % 16) == 0;
     char* ws = (char*)c->ws;
     double* V = (double*)(ws + lay.V);
     double* Y = (double*)(ws + lay.Y);
@@ -1299,8 +1303,8 @@ int hessenberg_blocked(lb_ctx* c, int M, double* A, int64_t lda) {
     double* betas = (double*)(ws + lay.beta);
     for (int j0 = 0; j0 + 2 < M; j0 += kPanel) {
         const int ib = std::min(kPanel, M - 2 - j0);
-        hipLaunchKernelGGL(k_bh_zero, dim3(lb_blocks((int64_t)M * kPanel, 256)), dim3(256), 0, s, V,
-                           (int64_t)M * kPanel);
+        hipLaunchKernelGGL(k_bh_zero, dim3(lb_blocks((int64_t)ldv * kPanel, 256)), dim3(256), 0, s, V,
+                           (int64_t)ldv * kPanel);
         LB_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_bh_zero, dim3(lb_blocks(kPanel * kPanel, 256)), dim3(256), 0, s, T,
                            (int64_t)kPanel * kPanel);
@@ -1308,29 +1312,30 @@ int hessenberg_blocked(lb_ctx* c, int M, double* A, int64_t lda) {
         for (int i = 0; i < ib; ++i) {
             const int cc = j0 + i;
             hipLaunchKernelGGL(k_bh_col, dim3(lb_blocks(M, 256)), dim3(256), 0, s, (const double*)A, lda, M, cc, i,
-                               (const double*)V, (const double*)Y, col);
+                               (const double*)V, ldv, (const double*)Y, col);
             LB_CHECK_LAUNCH();
             if (i > 0) {
-                hipLaunchKernelGGL(k_bh_dots, dim3(i), dim3(256), 0, s, (const double*)V, M, j0 + 1,
+                hipLaunchKernelGGL(k_bh_dots, dim3(i), dim3(256), 0, s, (const double*)V, ldv, M, j0 + 1,
                                    (const double*)col, w);
                 LB_CHECK_LAUNCH();
-                hipLaunchKernelGGL(k_bh_left, dim3(lb_blocks(M - j0 - 1, 256)), dim3(256), 0, s, (const double*)V, M,
-                                   i, j0, (const double*)T, (const double*)w, col);
+                hipLaunchKernelGGL(k_bh_left, dim3(lb_blocks(M - j0 - 1, 256)), dim3(256), 0, s, (const double*)V, ldv,
+                                   M, i, j0, (const double*)T, (const double*)w, col);
                 LB_CHECK_LAUNCH();
             }
-            hipLaunchKernelGGL(k_bh_house, dim3(1), dim3(256), 0, s, (const double*)col, M, cc, i, V, taus, betas);
+            hipLaunchKernelGGL(k_bh_house, dim3(1), dim3(256), 0, s, (const double*)col, M, cc, i, V, ldv, taus,
+                               betas);
             LB_CHECK_LAUNCH();
             if (i > 0) {
-                hipLaunchKernelGGL(k_bh_dots, dim3(i), dim3(256), 0, s, (const double*)V, M, cc + 1,
-                                   (const double*)(V + (int64_t)i * M), u);
+                hipLaunchKernelGGL(k_bh_dots, dim3(i), dim3(256), 0, s, (const double*)V, ldv, M, cc + 1,
+                                   (const double*)(V + (int64_t)i * ldv), u);
                 LB_CHECK_LAUNCH();
             }
             if (aligned)
                 hipLaunchKernelGGL(k_bh_gemv<true>, dim3(lb_blocks(M, 4)), dim3(256), 0, s, (const double*)A, lda, M,
-                                   cc, (const double*)(V + (int64_t)i * M), y);
+                                   cc, (const double*)(V + (int64_t)i * ldv), y);
             else
                 hipLaunchKernelGGL(k_bh_gemv<false>, dim3(lb_blocks(M, 4)), dim3(256), 0, s, (const double*)A, lda, M,
-                                   cc, (const double*)(V + (int64_t)i * M), y);
+                                   cc, (const double*)(V + (int64_t)i * ldv), y);
             LB_CHECK_LAUNCH();
             hipLaunchKernelGGL(k_bh_ycol, dim3(lb_blocks(M, 256)), dim3(256), 0, s, M, i, (const double*)y,
                                (const double*)u, (const double*)taus, Y, T);
@@ -1338,14 +1343,14 @@ int hessenberg_blocked(lb_ctx* c, int M, double* A, int64_t lda) {
         }
         int rc;
         // A[:, j0:] -= Y V^T
-        if ((rc = lb_impl_gemm_f64(s, false, true, M - j0, M, ib, -1.0, V + j0, M, Y, M, 1.0, A + j0, lda)))
+        if ((rc = lb_impl_gemm_f64(s, false, true, M - j0, M, ib, -1.0, V + j0, ldv, Y, M, 1.0, A + j0, lda)))
             return rc;
         // W^T = X[j0:, j0+1:] V[j0+1:], W2^T = W^T T, X[j0:, j0+1:] -= W2^T V[j0+1:]^T
         double* Xb = A + j0 + (int64_t)(j0 + 1) * lda;
-        if ((rc = lb_impl_gemm_f64(s, false, false, M - j0, ib, M - j0 - 1, 1.0, Xb, lda, V + j0 + 1, M, 0.0, W,
+        if ((rc = lb_impl_gemm_f64(s, false, false, M - j0, ib, M - j0 - 1, 1.0, Xb, lda, V + j0 + 1, ldv, 0.0, W,
                                    M)) ||
             (rc = lb_impl_gemm_f64(s, false, false, M - j0, ib, ib, 1.0, W, M, T, kPanel, 0.0, W2, M)) ||
-            (rc = lb_impl_gemm_f64(s, false, true, M - j0, M - j0 - 1, ib, -1.0, W2, M, V + j0 + 1, M, 1.0, Xb,
+            (rc = lb_impl_gemm_f64(s, false, true, M - j0, M - j0 - 1, ib, -1.0, W2, M, V + j0 + 1, ldv, 1.0, Xb,
                                    lda)))
             return rc;
         hipLaunchKernelGGL(k_bh_fix, dim3(lb_blocks(M, 256), ib), dim3(256), 0, s, A, lda, M, j0,
