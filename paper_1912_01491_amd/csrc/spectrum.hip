@@ -762,7 +762,9 @@ constexpr int kChain = 8;                           // bulges per chain
 constexpr int kAdvance = kWin + 1 - kSep * kChain;  // chain steps per round
 constexpr int kChainGap = kWin + 1;                 // steps between the entries of two chains
 constexpr int kWinThreads = 512;
-constexpr int kWinCols = 16 * (kWinThreads / 64);   // columns (rows) of the block per product workgroup
+constexpr int kWinCols = 16 * (kWinThreads / 64);   // columns (rows) of the block per product pass
+constexpr int kRowPasses = 1;                       // passes of a row-product workgroup over one staged U^T
+constexpr int kColPasses = 2;                       // passes of a column-product workgroup (fewer registers)
 
 typedef double qr_gd4 __attribute__((ext_vector_type(4)));
 
@@ -952,13 +954,27 @@ __global__ __launch_bounds__(kWinThreads) void k_win_chase(double* H, int64_t ld
     }
 }
 
-// U^T of chain blockIdx.y into LDS (kWin x kWin, zero outside the window's wc x wc).
+// U^T of chain c into LDS (kWin x kWin, zero outside the window's wc x wc): wave w takes rows
+// w, w + 8, ..., lanes along the row, all its loads in flight before the stores.
 __device__ __forceinline__ void win_stage_u(double* Us, const double* Ut_all, int c, int wc) {
+    constexpr int RPW = kWin / (kWinThreads / 64);
     const double* Ut = Ut_all + (size_t)c * kWin * kWin;
-    for (int e = threadIdx.x; e < kWin * kWin; e += kWinThreads) {
-        const int r = e / kWin, q = e - r * kWin;
-        Us[r * kWinLd + q] = (r < wc && q < wc) ? Ut[r * kWin + q] : 0.0;
-    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double v[RPW][2];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = w + i * (kWinThreads / 64), q = lane + 64 * h;
+            v[i][h] = (r < wc && q < wc) ? Ut[r * kWin + q] : 0.0;
+        }
+#pragma unroll
+    for (int i = 0; i < RPW; ++i)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = w + i * (kWinThreads / 64), q = lane + 64 * h;
+            if (q < kWin) Us[r * kWinLd + q] = v[i][h];
+        }
 }
 
 // Last column of the near part of chain c's row product: the columns the next round's
@@ -989,41 +1005,45 @@ __global__ __launch_bounds__(kWinThreads) void k_win_rows(double* H, int64_t ld,
     const int ws = G.ws, wc = G.we - G.ws + 1;
     const int nb = win_row_split(l, u, b, c, t0, G.we);
     const int cend = far ? u : nb;  // last column
-    const int cbeg = (far ? nb + 1 : G.we + 1) + blockIdx.x * kWinCols;
-    if (cbeg > cend) return;
+    const int cfirst = (far ? nb + 1 : G.we + 1) + blockIdx.x * (kWinCols * kRowPasses);
+    if (cfirst > cend) return;
     win_stage_u(Us, Ut_all, c, wc);
     __syncthreads();
     const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
-    const int col = cbeg + (threadIdx.x >> 6) * 16 + lr;
-    const bool cok = col <= cend;
-    // the window rows in two halves (fewer registers, two workgroups per compute unit);
-    // every load precedes every store, so the product stays in place
-    constexpr int KH = kWin / 8;
-    qr_gd4 acc[kWin / 16];
+    for (int pass = 0; pass < kRowPasses; ++pass) {
+        const int col = cfirst + pass * kWinCols + (threadIdx.x >> 6) * 16 + lr;
+        if (col - lr > cend) break;  // the wave's 16 columns all past the end
+        const bool cok = col <= cend;
+        // the window rows in two halves (fewer registers, two workgroups per compute unit);
+        // every load precedes every store, so the product stays in place
+        constexpr int KH = kWin / 8;
+        qr_gd4 acc[kWin / 16];
 #pragma unroll
-    for (int ri = 0; ri < kWin / 16; ++ri) acc[ri] = qr_gd4{0.0, 0.0, 0.0, 0.0};
+        for (int ri = 0; ri < kWin / 16; ++ri) acc[ri] = qr_gd4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        double xb[KH];
+        for (int half = 0; half < 2; ++half) {
+            double xb[KH];
 #pragma unroll
-        for (int kk = 0; kk < KH; ++kk) {
-            const int k = 4 * (kk + KH * half) + lk;
-            xb[kk] = (cok && k < wc) ? H[(int64_t)(ws + k) * ld + col] : 0.0;
+            for (int kk = 0; kk < KH; ++kk) {
+                const int k = 4 * (kk + KH * half) + lk;
+                xb[kk] = (cok && k < wc) ? H[(int64_t)(ws + k) * ld + col] : 0.0;
+            }
+#pragma unroll
+            for (int kk = 0; kk < KH; ++kk)
+#pragma unroll
+                for (int ri = 0; ri < kWin / 16; ++ri)
+                    acc[ri] = mfma_f64(Us[(16 * ri + lr) * kWinLd + 4 * (kk + KH * half) + lk], xb[kk], acc[ri]);
         }
-#pragma unroll
-        for (int kk = 0; kk < KH; ++kk)
+        if (cok) {
 #pragma unroll
             for (int ri = 0; ri < kWin / 16; ++ri)
-                acc[ri] = mfma_f64(Us[(16 * ri + lr) * kWinLd + 4 * (kk + KH * half) + lk], xb[kk], acc[ri]);
-    }
-    if (!cok) return;
 #pragma unroll
-    for (int ri = 0; ri < kWin / 16; ++ri)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = 16 * ri + 4 * v + lk;
-            if (r < wc) H[(int64_t)(ws + r) * ld + col] = acc[ri][v];
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * ri + 4 * v + lk;
+                    if (r < wc) H[(int64_t)(ws + r) * ld + col] = acc[ri][v];
+                }
         }
+    }
 }
 
 // First row of chain c's column block above its window that the next round's chase of
@@ -1051,38 +1071,41 @@ __global__ __launch_bounds__(kWinThreads) void k_win_cols(double* H, int64_t ld,
     const int ws = G.ws, wc = G.we - G.ws + 1;
     const int split = win_split(l, u, b, c, t0, ws);
     const int rfirst = far ? l : split, rend = far ? split : ws;  // rows rfirst .. rend-1
-    const int rbeg = rfirst + blockIdx.x * kWinCols;
+    const int rbeg = rfirst + blockIdx.x * (kWinCols * kColPasses);
     if (rbeg >= rend) return;
     win_stage_u(Us, Ut_all, c, wc);
     __syncthreads();
     const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
-    const int r0 = rbeg + (threadIdx.x >> 6) * 16;
-    const int row = r0 + lr;
-    constexpr int KH = kWin / 8;
-    qr_gd4 acc[kWin / 16];
+    for (int pass = 0; pass < kColPasses; ++pass) {
+        const int r0 = rbeg + pass * kWinCols + (threadIdx.x >> 6) * 16;
+        if (r0 >= rend) break;
+        const int row = r0 + lr;
+        constexpr int KH = kWin / 8;
+        qr_gd4 acc[kWin / 16];
 #pragma unroll
-    for (int ci = 0; ci < kWin / 16; ++ci) acc[ci] = qr_gd4{0.0, 0.0, 0.0, 0.0};
+        for (int ci = 0; ci < kWin / 16; ++ci) acc[ci] = qr_gd4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        double ya[KH];
+        for (int half = 0; half < 2; ++half) {
+            double ya[KH];
 #pragma unroll
-        for (int kk = 0; kk < KH; ++kk) {
-            const int k = 4 * (kk + KH * half) + lk;
-            ya[kk] = (row < rend && k < wc) ? H[(int64_t)row * ld + ws + k] : 0.0;
+            for (int kk = 0; kk < KH; ++kk) {
+                const int k = 4 * (kk + KH * half) + lk;
+                ya[kk] = (row < rend && k < wc) ? H[(int64_t)row * ld + ws + k] : 0.0;
+            }
+#pragma unroll
+            for (int kk = 0; kk < KH; ++kk)
+#pragma unroll
+                for (int ci = 0; ci < kWin / 16; ++ci)
+                    acc[ci] = mfma_f64(ya[kk], Us[(16 * ci + lr) * kWinLd + 4 * (kk + KH * half) + lk], acc[ci]);
         }
 #pragma unroll
-        for (int kk = 0; kk < KH; ++kk)
+        for (int ci = 0; ci < kWin / 16; ++ci)
 #pragma unroll
-            for (int ci = 0; ci < kWin / 16; ++ci)
-                acc[ci] = mfma_f64(ya[kk], Us[(16 * ci + lr) * kWinLd + 4 * (kk + KH * half) + lk], acc[ci]);
+            for (int v = 0; v < 4; ++v) {
+                const int r = r0 + 4 * v + lk, q = 16 * ci + lr;
+                if (r < rend && q < wc) H[(int64_t)r * ld + ws + q] = acc[ci][v];
+            }
     }
-#pragma unroll
-    for (int ci = 0; ci < kWin / 16; ++ci)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = r0 + 4 * v + lk, q = 16 * ci + lr;
-            if (r < rend && q < wc) H[(int64_t)r * ld + ws + q] = acc[ci][v];
-        }
 }
 
 // ---------------------------------------------------------------------------
@@ -1491,24 +1514,24 @@ int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam
                 LB_CHECK_LAUNCH();
                 LB_HIP(hipStreamWaitEvent(s, c->ev_join, 0));
                 if (near_right > 0) {
-                    hipLaunchKernelGGL(k_win_rows, dim3(lb_blocks(near_right, kWinCols), nch), dim3(kWinThreads), 0, s,
+                    hipLaunchKernelGGL(k_win_rows, dim3(lb_blocks(near_right, kWinCols * kRowPasses), nch), dim3(kWinThreads), 0, s,
                                        H, ld, l, u, b, t0, (const double*)Ur, 0);
                     LB_CHECK_LAUNCH();
                 }
                 if (near_above > 0) {
-                    hipLaunchKernelGGL(k_win_cols, dim3(lb_blocks(near_above, kWinCols), nch), dim3(kWinThreads), 0, s,
+                    hipLaunchKernelGGL(k_win_cols, dim3(lb_blocks(near_above, kWinCols * kColPasses), nch), dim3(kWinThreads), 0, s,
                                        H, ld, l, u, b, t0, (const double*)Ur, 0);
                     LB_CHECK_LAUNCH();
                 }
                 LB_HIP(hipEventRecord(c->ev_fork, s));
                 LB_HIP(hipStreamWaitEvent(s2, c->ev_fork, 0));
                 if (far_right > 0) {
-                    hipLaunchKernelGGL(k_win_rows, dim3(lb_blocks(far_right, kWinCols), nch), dim3(kWinThreads), 0, s2,
+                    hipLaunchKernelGGL(k_win_rows, dim3(lb_blocks(far_right, kWinCols * kRowPasses), nch), dim3(kWinThreads), 0, s2,
                                        H, ld, l, u, b, t0, (const double*)Ur, 1);
                     LB_CHECK_LAUNCH();
                 }
                 if (far_above > 0) {
-                    hipLaunchKernelGGL(k_win_cols, dim3(lb_blocks(far_above, kWinCols), nch), dim3(kWinThreads), 0, s2,
+                    hipLaunchKernelGGL(k_win_cols, dim3(lb_blocks(far_above, kWinCols * kColPasses), nch), dim3(kWinThreads), 0, s2,
                                        H, ld, l, u, b, t0, (const double*)Ur, 1);
                     LB_CHECK_LAUNCH();
                 }
