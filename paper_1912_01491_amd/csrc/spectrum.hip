@@ -43,8 +43,8 @@ constexpr int kQrThreads = 1024;
 constexpr int kMaxBulges = 16;              // 32 shifts per sweep
 constexpr int kSep = 4;                     // rows between neighbouring bulges
 constexpr int kShiftDim = 2 * kMaxBulges;   // trailing block solved for the shifts
+static_assert(kQrThreads / 64 >= kMaxBulges, "the one-workgroup sweep gives each bulge a wave");
 constexpr int kMaxIts = 120;                // sweeps without a split before giving up
-constexpr int kBatch = 1;                   // row / column pieces per thread with loads in flight together
 constexpr int kChunkRows = 16;              // shortest row chunk of the column pass
 constexpr int kMaxChunks = 256;
 constexpr int kPanel = 32;                  // reflectors per panel of the blocked reduction
@@ -420,39 +420,23 @@ __device__ int qr_eigs(double* H, int64_t ld, int n, double2* lam, QrCtl& C, QrC
             const int ihi = min(b - 1, t / kSep);
             int ilo = 0;
             while (ilo <= ihi && l + t - kSep * ilo > u - 1) ++ilo;
-            // from the left: pieces (bulge, column), bulge by bulge, columns consecutive
-            int total = 0;
-            for (int i = ilo; i <= ihi; ++i) total += u - (l + t - kSep * i) + 1;
-            for (int base = 0; base < total; base += kQrThreads * kBatch) {
-                double a0[kBatch], a1[kBatch], a2[kBatch];
-                int off[kBatch], bi[kBatch];
-#pragma unroll
-                for (int q = 0; q < kBatch; ++q) {
-                    bi[q] = -1;
-                    int e = base + q * kQrThreads + tid;
-                    if (e >= total) continue;
-                    int i = ilo;
-                    while (e >= u - (l + t - kSep * i) + 1) {
-                        e -= u - (l + t - kSep * i) + 1;
-                        ++i;
-                    }
-                    if (C.tau[p][i] == 0.0) continue;
+            // from the left: wave i - ilo takes bulge i, lanes along its columns k..u
+            const int wv = tid >> 6, lane = tid & 63;
+            if (ilo + wv <= ihi) {
+                const int i = ilo + wv;
+                const double tau = C.tau[p][i];
+                if (tau != 0.0) {
                     const int k = l + t - kSep * i;
-                    bi[q] = i;
-                    off[q] = k * ld32 + k + e;
-                    a0[q] = H[off[q]];
-                    a1[q] = H[off[q] + ld32];
-                    a2[q] = k + 2 <= u ? H[off[q] + 2 * ld32] : 0.0;
-                }
-#pragma unroll
-                for (int q = 0; q < kBatch; ++q) {
-                    if (bi[q] < 0) continue;
-                    const int i = bi[q];
-                    const double tau = C.tau[p][i], w1 = C.w1[p][i], w2 = C.w2[p][i];
-                    const double r = tau * (a0[q] + w1 * a1[q] + w2 * a2[q]);
-                    H[off[q]] = a0[q] - r;
-                    H[off[q] + ld32] = a1[q] - r * w1;
-                    if (l + t - kSep * i + 2 <= u) H[off[q] + 2 * ld32] = a2[q] - r * w2;
+                    const double w1 = C.w1[p][i], w2 = C.w2[p][i];
+                    const bool three = k + 2 <= u;
+                    for (int c = k + lane; c <= u; c += 64) {
+                        const int off = k * ld32 + c;
+                        const double a0 = H[off], a1 = H[off + ld32], a2 = three ? H[off + 2 * ld32] : 0.0;
+                        const double r = tau * (a0 + w1 * a1 + w2 * a2);
+                        H[off] = a0 - r;
+                        H[off + ld32] = a1 - r * w1;
+                        if (three) H[off + 2 * ld32] = a2 - r * w2;
+                    }
                 }
             }
             __syncthreads();
@@ -499,39 +483,22 @@ __device__ int qr_eigs(double* H, int64_t ld, int n, double2* lam, QrCtl& C, QrC
                 C.w1[p ^ 1][i] = w1n;
                 C.w2[p ^ 1][i] = w2n;
             }
-            // the rest: pieces (bulge, row) for rows l..k
-            total = 0;
-            for (int i = ilo; i <= ihi; ++i) total += (l + t - kSep * i) - l + 1;
-            for (int base = 0; base < total; base += kQrThreads * kBatch) {
-                double a0[kBatch], a1[kBatch], a2[kBatch];
-                int off[kBatch], bi[kBatch];
-#pragma unroll
-                for (int q = 0; q < kBatch; ++q) {
-                    bi[q] = -1;
-                    int e = base + q * kQrThreads + tid;
-                    if (e >= total) continue;
-                    int i = ilo;
-                    while (e >= (l + t - kSep * i) - l + 1) {
-                        e -= (l + t - kSep * i) - l + 1;
-                        ++i;
-                    }
-                    if (C.tau[p][i] == 0.0) continue;
+            // the rest: wave i - ilo takes bulge i's rows l..k
+            if (ilo + wv <= ihi) {
+                const int i = ilo + wv;
+                const double tau = C.tau[p][i];
+                if (tau != 0.0) {
                     const int k = l + t - kSep * i;
-                    bi[q] = i;
-                    off[q] = (l + e) * ld32 + k;
-                    a0[q] = H[off[q]];
-                    a1[q] = H[off[q] + 1];
-                    a2[q] = k + 2 <= u ? H[off[q] + 2] : 0.0;
-                }
-#pragma unroll
-                for (int q = 0; q < kBatch; ++q) {
-                    if (bi[q] < 0) continue;
-                    const int i = bi[q];
-                    const double tau = C.tau[p][i], w1 = C.w1[p][i], w2 = C.w2[p][i];
-                    const double r = tau * (a0[q] + w1 * a1[q] + w2 * a2[q]);
-                    H[off[q]] = a0[q] - r;
-                    H[off[q] + 1] = a1[q] - r * w1;
-                    if (l + t - kSep * i + 2 <= u) H[off[q] + 2] = a2[q] - r * w2;
+                    const double w1 = C.w1[p][i], w2 = C.w2[p][i];
+                    const bool three = k + 2 <= u;
+                    for (int row = l + lane; row <= k; row += 64) {
+                        const int off = row * ld32 + k;
+                        const double a0 = H[off], a1 = H[off + 1], a2 = three ? H[off + 2] : 0.0;
+                        const double r = tau * (a0 + w1 * a1 + w2 * a2);
+                        H[off] = a0 - r;
+                        H[off + 1] = a1 - r * w1;
+                        if (three) H[off + 2] = a2 - r * w2;
+                    }
                 }
             }
             __syncthreads();
