@@ -837,9 +837,10 @@ def config_c8(args):
            "roofline": {"bound": "mfma", "achieved": prod_tfs, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
                         "frac": prod_tfs / FP64_PEAK_TFS, "traffic": None, "kernel": "k_win_rows + k_win_cols",
                         "flops": info["product_flops"], "rounds": info["rounds"],
-                        "note": "matrix-core flops of the window products over the QR stage's wall time, which "
-                                "also holds the windowed chase and the one-workgroup solves; a direct sweep "
-                                "would move 48 B per update (updates x 48 B)"},
+                        "note": "flops of the window products (dense 2 w^2 per row or column; the kernels skip the "
+                                "30 % of the window factor's 16 x 4 blocks that are zero by its band structure) "
+                                "over the QR stage's wall time, which also holds the windowed chase and the "
+                                "one-workgroup solves; a direct sweep would move 48 B per update (updates x 48 B)"},
            "hessenberg": {"flops": hess_flops, "tflops": hess_flops / t_hess / 1e12},
            "cpu_baseline": base,
            "checks": checks}

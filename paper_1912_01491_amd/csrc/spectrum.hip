@@ -735,6 +735,17 @@ constexpr int kColPasses = 2;                       // passes of a column-produc
 
 typedef double qr_gd4 __attribute__((ext_vector_type(4)));
 
+// Band of a round's window factor: U^T[r][q] = 0 unless -(kAdvance + 1) <= q - r <= 2 kChain.
+// A reflector mixes three consecutive rows. A bulge moves one row down per step, so it
+// carries an entry at most kAdvance + 1 rows down within a round and at most two rows up
+// (its next reflector starts one row lower); an entry moved up is picked up by the next
+// bulge of the chain, kSep rows higher, two steps later, so the chain moves it at most
+// 2 kChain rows up. The products skip the 16 x 4 blocks of U^T outside the band (30 % of
+// them): their terms are exact zeros.
+__host__ __device__ constexpr bool win_live(int tile, int kstep) {
+    return 4 * kstep - (16 * tile + 15) <= 2 * kChain && 4 * kstep + 3 - 16 * tile >= -(kAdvance + 1);
+}
+
 __device__ __forceinline__ qr_gd4 mfma_f64(double a, double b, qr_gd4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -999,7 +1010,8 @@ __global__ __launch_bounds__(kWinThreads) void k_win_rows(double* H, int64_t ld,
             for (int kk = 0; kk < KH; ++kk)
 #pragma unroll
                 for (int ri = 0; ri < kWin / 16; ++ri)
-                    acc[ri] = mfma_f64(Us[(16 * ri + lr) * kWinLd + 4 * (kk + KH * half) + lk], xb[kk], acc[ri]);
+                    if (win_live(ri, kk + KH * half))
+                        acc[ri] = mfma_f64(Us[(16 * ri + lr) * kWinLd + 4 * (kk + KH * half) + lk], xb[kk], acc[ri]);
         }
         if (cok) {
 #pragma unroll
@@ -1060,10 +1072,13 @@ __global__ __launch_bounds__(kWinThreads) void k_win_cols(double* H, int64_t ld,
                 ya[kk] = (row < rend && k < wc) ? H[(int64_t)row * ld + ws + k] : 0.0;
             }
 #pragma unroll
-            for (int kk = 0; kk < KH; ++kk)
+            for (int kk = 0; kk < KH; ++kk) {
 #pragma unroll
                 for (int ci = 0; ci < kWin / 16; ++ci)
-                    acc[ci] = mfma_f64(ya[kk], Us[(16 * ci + lr) * kWinLd + 4 * (kk + KH * half) + lk], acc[ci]);
+                    if (win_live(ci, kk + KH * half))
+                        acc[ci] = mfma_f64(ya[kk], Us[(16 * ci + lr) * kWinLd + 4 * (kk + KH * half) + lk], acc[ci]);
+                __builtin_amdgcn_sched_barrier(0);  // keep each step's operand reads next to its products
+            }
         }
 #pragma unroll
         for (int ci = 0; ci < kWin / 16; ++ci)
