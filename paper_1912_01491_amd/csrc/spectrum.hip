@@ -1123,13 +1123,13 @@ __global__ void k_hist(int64_t n, const double2* lam, double re0, double dx, dou
 // three times.
 // ---------------------------------------------------------------------------
 
-// col[r] = A[r][c] - sum_{k<i} Y[k][r] V[k][c] (V's columns ldv apart)
+// col[r] = A[r][c] - sum_{k<i} Y[k][r] V[k][c] (the columns of Y and V ldv apart)
 __global__ __launch_bounds__(256) void k_bh_col(const double* A, int64_t lda, int M, int c, int i, const double* V,
                                                 int ldv, const double* Y, double* col) {
     const int r = blockIdx.x * 256 + threadIdx.x;
     if (r >= M) return;
     double s = A[(int64_t)r * lda + c];
-    for (int k = 0; k < i; ++k) s -= Y[(int64_t)k * M + r] * V[(int64_t)k * ldv + c];
+    for (int k = 0; k < i; ++k) s -= Y[(int64_t)k * ldv + r] * V[(int64_t)k * ldv + c];
     col[r] = s;
 }
 
@@ -1208,7 +1208,7 @@ __global__ __launch_bounds__(256) void k_bh_gemv(const double* A, int64_t lda, i
 // Y[i][r] = tau (y[r] - sum_{k<i} Y[k][r] u[k]); block 0 also writes column i of T:
 // T[m][i] = -tau sum_{m<=k<i} T[m][k] u[k], T[i][i] = tau.
 __global__ __launch_bounds__(256) void k_bh_ycol(int M, int i, const double* y, const double* u, const double* taus,
-                                                 double* Y, double* T) {
+                                                 double* Y, int ldv, double* T) {
     const double tau = taus[i];
     if (blockIdx.x == 0 && threadIdx.x <= (unsigned)i) {
         const int m = threadIdx.x;
@@ -1223,8 +1223,8 @@ __global__ __launch_bounds__(256) void k_bh_ycol(int M, int i, const double* y, 
     const int r = blockIdx.x * 256 + threadIdx.x;
     if (r >= M) return;
     double s = y[r];
-    for (int k = 0; k < i; ++k) s -= Y[(int64_t)k * M + r] * u[k];
-    Y[(int64_t)i * M + r] = tau * s;
+    for (int k = 0; k < i; ++k) s -= Y[(int64_t)k * ldv + r] * u[k];
+    Y[(int64_t)i * ldv + r] = tau * s;
 }
 
 // Panel columns j0..j0+ib-1: beta on the subdiagonal, exact zeros below it.
@@ -1245,19 +1245,21 @@ __global__ void k_bh_zero(double* x, int64_t n) {
 // with leading dimension M), the current column and the GEMV result (M each), T
 // (kPanel x kPanel, column-major), small vectors (w, u, tau, beta).
 struct BlockedLayout {
-    size_t V, Y, W, W2, col, y, T, w, u, tau, beta, end;
+    size_t YVW, W, col, y, T, G, w, u, tau, beta, end;
     explicit BlockedLayout(int M) {
-        const size_t mat = lb_align(sizeof(double) * (size_t)(M + 1) * kPanel, 256);  // V's columns: M rounded to even
+        // Y, V and W2 side by side, kPanel columns each, columns M rounded up to even apart
+        const size_t blk = lb_align(sizeof(double) * (size_t)(M + 1) * 3 * kPanel, 256);
+        const size_t mat = lb_align(sizeof(double) * (size_t)M * kPanel, 256);
         const size_t vec = lb_align(sizeof(double) * (size_t)M, 256);
         const size_t sm = lb_align(sizeof(double) * kPanel, 256);
-        V = 0;
-        Y = mat;
-        W = 2 * mat;
-        W2 = 3 * mat;
-        col = 4 * mat;
+        const size_t sq = lb_align(sizeof(double) * kPanel * kPanel, 256);
+        YVW = 0;
+        W = blk;
+        col = W + mat;
         y = col + vec;
         T = y + vec;
-        w = T + lb_align(sizeof(double) * kPanel * kPanel, 256);
+        G = T + sq;
+        w = G + sq;
         u = w + sm;
         tau = u + sm;
         beta = tau + sm;
@@ -1283,22 +1285,24 @@ struct HessLayout {
 namespace {
 
 // The blocked reduction. The products work column-major: the row-major A is the column-major
-// X = A^T with leading dimension lda, so A[:, j0:] -= Y V^T is X[j0:, :] -= V Y^T, and the
-// left update of A[j0+1:, j0:] is X[j0:, j0+1:] -= (X[j0:, j0+1:] V T) V^T over rows j0+1..
-// of V.
+// X = A^T with leading dimension lda. A panel's two-sided update, A - Y V^T from the right and
+// then A[j0+1:, j0:] -= V W2^T from the left with W2 = W T, W[c] = sum_{r > j0} A1[r][c] V[r]
+// taken on the right-updated A1, is one rank-2 kPanel update A[:, j0:] -= [Y V] [V W2]^T: W is
+// formed from the panel-start A as W0 - V[j0:] G, G = Y[j0+1:]^T V[j0+1:], so the trailing
+// matrix is read once for W0 and read and written once for the update.
 int hessenberg_blocked(lb_ctx* c, int M, double* A, int64_t lda) {
     hipStream_t s = c->stream;
     const BlockedLayout lay(M);
-    // rows 16-byte aligned: the GEMV reads 16-byte pieces (V's rows start on 256 bytes)
-    // V's columns ldv apart, ldv even: every v_i starts on 16 bytes, so the GEMV reads 16-byte pieces
-    // of A and v whenever A's rows do
+    // Y, V and W2 (kPanel columns each) side by side, columns ldv apart, ldv even: every v_i starts
+    // on 16 bytes, so the GEMV reads 16-byte pieces of A and v whenever A's rows do
     const int ldv = M + (M & 1);
     const bool aligned = (lda % 2) == 0 && ((uintptr_t)A % 16) == 0;
     char* ws = (char*)c->ws;
-    double* V = (double*)(ws + lay.V);
-    double* Y = (double*)(ws + lay.Y);
+    double* Y = (double*)(ws + lay.YVW);
+    double* V = Y + (size_t)kPanel * ldv;
+    double* W2 = Y + (size_t)2 * kPanel * ldv;
     double* W = (double*)(ws + lay.W);
-    double* W2 = (double*)(ws + lay.W2);
+    double* G = (double*)(ws + lay.G);
     double* col = (double*)(ws + lay.col);
     double* y = (double*)(ws + lay.y);
     double* T = (double*)(ws + lay.T);
@@ -1308,8 +1312,9 @@ int hessenberg_blocked(lb_ctx* c, int M, double* A, int64_t lda) {
     double* betas = (double*)(ws + lay.beta);
     for (int j0 = 0; j0 + 2 < M; j0 += kPanel) {
         const int ib = std::min(kPanel, M - 2 - j0);
-        hipLaunchKernelGGL(k_bh_zero, dim3(lb_blocks((int64_t)ldv * kPanel, 256)), dim3(256), 0, s, V,
-                           (int64_t)ldv * kPanel);
+        // Y, V, W2 start at zero: a last panel of ib < kPanel reflectors leaves its other columns zero
+        hipLaunchKernelGGL(k_bh_zero, dim3(lb_blocks((int64_t)ldv * 3 * kPanel, 256)), dim3(256), 0, s, Y,
+                           (int64_t)ldv * 3 * kPanel);
         LB_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_bh_zero, dim3(lb_blocks(kPanel * kPanel, 256)), dim3(256), 0, s, T,
                            (int64_t)kPanel * kPanel);
@@ -1343,19 +1348,20 @@ int hessenberg_blocked(lb_ctx* c, int M, double* A, int64_t lda) {
                                    cc, (const double*)(V + (int64_t)i * ldv), y);
             LB_CHECK_LAUNCH();
             hipLaunchKernelGGL(k_bh_ycol, dim3(lb_blocks(M, 256)), dim3(256), 0, s, M, i, (const double*)y,
-                               (const double*)u, (const double*)taus, Y, T);
+                               (const double*)u, (const double*)taus, Y, ldv, T);
             LB_CHECK_LAUNCH();
         }
         int rc;
-        // A[:, j0:] -= Y V^T
-        if ((rc = lb_impl_gemm_f64(s, false, true, M - j0, M, ib, -1.0, V + j0, ldv, Y, M, 1.0, A + j0, lda)))
-            return rc;
-        // W^T = X[j0:, j0+1:] V[j0+1:], W2^T = W^T T, X[j0:, j0+1:] -= W2^T V[j0+1:]^T
+        // W0 = X[j0:, j0+1:] V[j0+1:] on the panel-start matrix, G = Y[j0+1:]^T V[j0+1:],
+        // W = W0 - V[j0:] G, W2[j0:] = W T, then X[j0:, :] -= [V W2][j0:] [Y V]^T
         double* Xb = A + j0 + (int64_t)(j0 + 1) * lda;
         if ((rc = lb_impl_gemm_f64(s, false, false, M - j0, ib, M - j0 - 1, 1.0, Xb, lda, V + j0 + 1, ldv, 0.0, W,
                                    M)) ||
-            (rc = lb_impl_gemm_f64(s, false, false, M - j0, ib, ib, 1.0, W, M, T, kPanel, 0.0, W2, M)) ||
-            (rc = lb_impl_gemm_f64(s, false, true, M - j0, M - j0 - 1, ib, -1.0, W2, M, V + j0 + 1, ldv, 1.0, Xb,
+            (rc = lb_impl_gemm_f64(s, true, false, ib, ib, M - j0 - 1, 1.0, Y + j0 + 1, ldv, V + j0 + 1, ldv, 0.0, G,
+                                   kPanel)) ||
+            (rc = lb_impl_gemm_f64(s, false, false, M - j0, ib, ib, -1.0, V + j0, ldv, G, kPanel, 1.0, W, M)) ||
+            (rc = lb_impl_gemm_f64(s, false, false, M - j0, ib, ib, 1.0, W, M, T, kPanel, 0.0, W2 + j0, ldv)) ||
+            (rc = lb_impl_gemm_f64(s, false, true, M - j0, M, 2 * kPanel, -1.0, V + j0, ldv, Y, ldv, 1.0, A + j0,
                                    lda)))
             return rc;
         hipLaunchKernelGGL(k_bh_fix, dim3(lb_blocks(M, 256), ib), dim3(256), 0, s, A, lda, M, j0,
