@@ -533,7 +533,7 @@ struct QrGlobal {
     int64_t sweeps, steps, work;                   // counts of the one-workgroup solves
     double anorm;                                  // ||H||_F
     double s[kWideBulges], t[kWideBulges];         // shift pairs of the current sweep
-    double tau[2][kWideBulges], w1[2][kWideBulges], w2[2][kWideBulges];  // reflectors by step parity
+    double tau[kWideBulges], w1[kWideBulges], w2[kWideBulges];  // each bulge's reflector for its next step
 };
 
 __global__ __launch_bounds__(1024) void k_qr_init(const double* H, int64_t ld, int n, QrGlobal* g) {
@@ -580,7 +580,7 @@ __global__ void k_qr_scan(const double* H, int64_t ld, int n, QrGlobal* g) {
 
 // One decision on the bottom block [split, u]: the eigenvalues of a 1 x 1 or 2 x 2
 // block, a whole small block by qr_eigs, or the set-up of a device-wide sweep
-// (shifts from the trailing block, the first bulge's reflector).
+// (the shifts, eigenvalues of the trailing block).
 __global__ __launch_bounds__(kQrThreads) void k_qr_decide(double* H, int64_t ld, QrGlobal* g, double2* lam) {
     __shared__ QrCtl outer, inner;
     __shared__ double sub[kWideShiftDim * kWideShiftDim];
@@ -693,10 +693,7 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_decide(double* H, int64_t ld,
         }
     }
     __syncthreads();
-    if (tid == 0) {
-        double x, y, z, beta;
-        intro_xyz(H, ld, l, g->s[0], g->t[0], &x, &y, &z);
-        house3(x, y, z, &g->tau[0][0], &g->w1[0][0], &g->w2[0][0], &beta);
+    if (tid == 0) {  // the bulges' first reflectors are built by the chase as they enter
         g->l = l;
         g->b = b;
         g->split = 0;
@@ -774,7 +771,7 @@ __host__ __device__ inline WinGeom win_geom(int l, int u, int b, int c, int t0) 
 
 // One round of chain blockIdx.x: load the window, chase kAdvance steps, store the
 // window, U^T (kWin x kWin, rows of length kWin, at Ut_all + c kWin^2) and the
-// reflectors pending for the next step (g->tau[0] etc., by bulge). Wave j carries bulge
+// reflectors pending for the next step (g->tau etc., by bulge). Wave j carries bulge
 // j: its left side (lanes along the window columns, then along the columns of U^T) and
 // its right side (lanes along the rows above the bulge); every lane of the wave applies
 // the right side to the bulge's own three rows below it and builds the next reflector
@@ -826,9 +823,9 @@ __global__ __launch_bounds__(kWinThreads) void k_win_chase(double* H, int64_t ld
     const bool mine = j < nbc;
     double tau = 0.0, w1 = 0.0, w2 = 0.0;
     if (mine) {
-        tau = g->tau[0][i0 + j];
-        w1 = g->w1[0][i0 + j];
-        w2 = g->w2[0][i0 + j];
+        tau = g->tau[i0 + j];
+        w1 = g->w1[i0 + j];
+        w2 = g->w2[i0 + j];
     }
     __syncthreads();
     for (int s = 0; s < kAdvance; ++s) {
@@ -926,9 +923,9 @@ __global__ __launch_bounds__(kWinThreads) void k_win_chase(double* H, int64_t ld
             Ut[r * kWin + q] = Uw[r * kWinLd + q];
         }
     if (mine && lane == 0) {
-        g->tau[0][i0 + j] = tau;
-        g->w1[0][i0 + j] = w1;
-        g->w2[0][i0 + j] = w2;
+        g->tau[i0 + j] = tau;
+        g->w1[i0 + j] = w1;
+        g->w2[i0 + j] = w2;
     }
 }
 
