@@ -47,6 +47,10 @@ constexpr int kMaxBulges = 16;              // 32 shifts per sweep
 constexpr int kShiftDim = 2 * kMaxBulges;   // trailing block solved for the shifts
 static_assert(kQrThreads / 64 >= kMaxBulges, "the one-workgroup sweep gives each bulge a wave");
 constexpr int kMaxIts = 120;                // sweeps without a split before giving up
+// Split tolerance of the shift problems (the trailing block whose eigenvalues become the next
+// sweep's shifts): shifts need not be eigenvalues to the last bit, and a relative 1e-10 is far
+// below the separations that set the convergence of the sweep they drive.
+constexpr double kShiftTol = 1e-10;
 constexpr int kChunkRows = 16;              // shortest row chunk of the column pass
 constexpr int kMaxChunks = 256;
 constexpr int kPanel = 32;                  // reflectors per panel of the blocked reduction
@@ -248,12 +252,13 @@ __device__ void intro_xyz(const double* H, int64_t ld, int l, double s, double t
 // block through a nested BMAX = 1 solve on sub (kShiftDim^2 doubles, LDS). The normwise
 // split tests scale with max(||H||_F, norm_floor): a diagonal block of a larger matrix
 // passes that matrix's norm, so a block cut out of a cluster (a tiny norm of its own)
-// deflates at the backward error the whole matrix allows.
+// deflates at the backward error the whole matrix allows. tol replaces eps in the split
+// tests: DBL_EPSILON for blocks whose eigenvalues are results, kShiftTol for shift problems.
 template <int BMAX>
 __device__ int qr_eigs(double* H, int64_t ld, int n, double2* lam, QrCtl& C, QrCtl* inner, double* sub,
-                       double2* subev, double norm_floor) {
+                       double2* subev, double norm_floor, double tol) {
     const int tid = threadIdx.x;
-    const double eps = DBL_EPSILON;
+    const double eps = tol;
     // Frobenius norm of the Hessenberg part: the scale of the normwise split test
     __shared__ double part[kQrThreads / 64];
     double m = 0.0;
@@ -357,7 +362,7 @@ __device__ int qr_eigs(double* H, int64_t ld, int n, double2* lam, QrCtl& C, QrC
                     sub[e] = r <= c + 1 ? at(H, ld, o + r, o + c) : 0.0;
                 }
                 __syncthreads();
-                const int rc = qr_eigs<1>(sub, mm, mm, subev, *inner, nullptr, nullptr, nullptr, 0.0);
+                const int rc = qr_eigs<1>(sub, mm, mm, subev, *inner, nullptr, nullptr, nullptr, 0.0, kShiftTol);
                 if (tid == 0) {
                     if (rc != 0) {  // keep the sweep going with the trailing 2 x 2 shift
                         const double a = at(H, ld, u - 1, u - 1), bb = at(H, ld, u - 1, u);
@@ -620,7 +625,7 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_decide(double* H, int64_t ld,
         if (tid == 0 && l > 0) H[(int64_t)l * ld + l - 1] = 0.0;
         __syncthreads();
         const int rc = qr_eigs<kMaxBulges>(H + (int64_t)l * ld + l, ld, na, lam + l, outer, &inner, sub2, subev2,
-                                            g->anorm);
+                                            g->anorm, DBL_EPSILON);
         if (tid == 0) {
             if (rc) g->status = 1;
             g->sweeps += outer.sweeps;
@@ -659,7 +664,7 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_decide(double* H, int64_t ld,
             sub[e] = r <= c + 1 ? H[(int64_t)(o + r) * ld + o + c] : 0.0;
         }
         __syncthreads();
-        const int rc = qr_eigs<kMaxBulges>(sub, mm, mm, subev, outer, &inner, sub2, subev2, 0.0);
+        const int rc = qr_eigs<kMaxBulges>(sub, mm, mm, subev, outer, &inner, sub2, subev2, 0.0, kShiftTol);
         if (tid == 0) {
             const double a = H[(int64_t)(u - 1) * ld + u - 1], bb = H[(int64_t)(u - 1) * ld + u];
             const double c = H[(int64_t)u * ld + u - 1], d = H[(int64_t)u * ld + u];
