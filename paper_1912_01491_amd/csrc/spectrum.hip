@@ -1127,24 +1127,28 @@ __global__ __launch_bounds__(256) void k_bh_house(const double* col, int M, int 
     for (int r = c + 2 + threadIdx.x; r < M; r += 256) vi[r] = col[r] * scale;
 }
 
-// y[r] = sum_{cc > c} A[r][cc] v[cc]: one wavefront per two rows, the row-dot loop of
+// y[r] = sum_{cc > c} A[r][cc] v[cc]: one wavefront per kGemvRows rows, the row-dot loop of
 // the one-state GEMV. The dot starts at the even column c0 <= c + 1 so that,
 // with 16-byte aligned rows (ALIGNED), every lane reads 16-byte pieces; v is
 // zero above c + 1, so the extra column adds nothing.
+constexpr int kGemvRows = 2;  // rows per wavefront: their streams in flight together, v read once (4 measured no faster)
+
 template <bool ALIGNED>
 __global__ __launch_bounds__(256) void k_bh_gemv(const double* A, int64_t lda, int M, int c, const double* v,
                                                  double* y) {
-    const int r = 2 * (blockIdx.x * 4 + (threadIdx.x >> 6));
+    const int r = kGemvRows * (blockIdx.x * 4 + (threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     if (r >= M) return;
     const int c0 = (c + 1) & ~1;
-    const int r1 = r + 1 < M ? r + 1 : r;
-    const double* row[2] = {A + (int64_t)r * lda + c0, A + (int64_t)r1 * lda + c0};
-    double s[2];
-    wave_rowdots<2, ALIGNED, true>(row, v + c0, M - c0, lane, s);
+    const double* row[kGemvRows];
+#pragma unroll
+    for (int t = 0; t < kGemvRows; ++t) row[t] = A + (int64_t)(r + t < M ? r + t : r) * lda + c0;
+    double s[kGemvRows];
+    wave_rowdots<kGemvRows, ALIGNED, true>(row, v + c0, M - c0, lane, s);
     if (lane == 0) {
-        y[r] = s[0];
-        if (r + 1 < M) y[r + 1] = s[1];
+#pragma unroll
+        for (int t = 0; t < kGemvRows; ++t)
+            if (r + t < M) y[r + t] = s[t];
     }
 }
 
@@ -1284,10 +1288,10 @@ int hessenberg_blocked(lb_ctx* c, int M, double* A, int64_t lda) {
                 LB_CHECK_LAUNCH();
             }
             if (aligned)
-                hipLaunchKernelGGL(k_bh_gemv<true>, dim3(lb_blocks(M, 8)), dim3(256), 0, s, (const double*)A, lda, M,
+                hipLaunchKernelGGL(k_bh_gemv<true>, dim3(lb_blocks(M, 4 * kGemvRows)), dim3(256), 0, s, (const double*)A, lda, M,
                                    cc, (const double*)(V + (int64_t)i * ldv), y);
             else
-                hipLaunchKernelGGL(k_bh_gemv<false>, dim3(lb_blocks(M, 8)), dim3(256), 0, s, (const double*)A, lda, M,
+                hipLaunchKernelGGL(k_bh_gemv<false>, dim3(lb_blocks(M, 4 * kGemvRows)), dim3(256), 0, s, (const double*)A, lda, M,
                                    cc, (const double*)(V + (int64_t)i * ldv), y);
             LB_CHECK_LAUNCH();
             hipLaunchKernelGGL(k_bh_ycol, dim3(lb_blocks(M, 256)), dim3(256), 0, s, M, i, (const double*)y,
