@@ -26,6 +26,14 @@ __host__ __device__ constexpr bool win_live(int tile, int kstep) {
     return 4 * kstep - (16 * tile + 15) <= 2 * kChain && 4 * kstep + 3 - 16 * tile >= -(kAdvance + 1);
 }
 
+// Columns where rows K..K+2 of U^T can be nonzero while a round runs (the band above for
+// those rows; the zero pattern only grows within a round): a reflector at window row K
+// changes U^T only there. With the window's columns K.. that is at most
+// kWin + 2 kChain + 3 columns for one chase step's left side, two per lane of a wavefront.
+__host__ __device__ constexpr int win_ut_lo(int K) { return K > kAdvance + 1 ? K - (kAdvance + 1) : 0; }
+__host__ __device__ constexpr int win_ut_hi(int K, int wc) { return K + 2 + 2 * kChain < wc - 1 ? K + 2 + 2 * kChain : wc - 1; }
+static_assert(kWin + 2 * kChain + 3 <= 128, "a chase step's left side fits two columns per lane");
+
 struct WinGeom {
     int ws, we, active;
 };

@@ -741,12 +741,16 @@ __device__ __forceinline__ qr_gd4 mfma_f64(double a, double b, qr_gd4 c) {
 // One round of chain blockIdx.x: load the window, chase kAdvance steps, store the
 // window, U^T (kWin x kWin, rows of length kWin, at Ut_all + c kWin^2) and the
 // reflectors pending for the next step (g->tau etc., by bulge). Wave j carries bulge
-// j: its left side (lanes along the window columns, then along the columns of U^T) and
-// its right side (lanes along the rows above the bulge); every lane of the wave applies
-// the right side to the bulge's own three rows below it and builds the next reflector
-// from column K, so the reflector stays in registers. Two barriers per step order the
-// sides of neighbouring bulges where they cross. A wave's pieces of one side are at most
-// two per lane (wc <= 128): both are loaded before either is computed.
+// j: its left side (lanes along the window columns K.., then along the columns of U^T's
+// band for rows K..K+2: at most two columns per lane) and its right side (lanes along the
+// rows above the bulge); every lane of the wave applies the right side to the bulge's own
+// three rows below it and builds the next reflector from column K, so the reflector stays
+// in registers. Two barriers per step order the sides of neighbouring bulges where they
+// cross. The bulge index, its rows and its reflector are the same in every lane of a wave
+// (read from the first lane), so each step's conditions are scalar branches; every load
+// of a step is issued unconditionally from inside the LDS array (the array has a tail for
+// the rows and columns an idle lane would read past the window) and only the stores are
+// masked.
 __device__ __forceinline__ void win_refl3(double* a, int ld, bool three, double tau, double w1, double w2, double a0,
                                           double a1, double a2) {
     const double r = tau * (a0 + w1 * a1 + w2 * a2);
@@ -755,10 +759,19 @@ __device__ __forceinline__ void win_refl3(double* a, int ld, bool three, double 
     if (three) a[2 * ld] = a2 - r * w2;
 }
 
+__device__ __forceinline__ double wave_first(double x) {
+    const long long v = __double_as_longlong(x);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((int)v), hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+constexpr int kWinLds = 2 * kWin * kWinLd + kWin;  // window, U^T, and the tail past U^T's last row
+
 __global__ __launch_bounds__(kWinThreads) void k_win_chase(double* H, int64_t ld, int l, int u, int b, int t0,
                                                            QrGlobal* g, double* Ut_all) {
-    __shared__ double Hw[kWin * kWinLd];
-    __shared__ double Uw[kWin * kWinLd];
+    __shared__ double lds[kWinLds];
+    double* const Hw = lds;
+    double* const Uw = lds + kWin * kWinLd;
     constexpr int kRowsPerWave = kWin / (kWinThreads / 64);
     const int c = blockIdx.x;
     const WinGeom G = win_geom(l, u, b, c, t0);
@@ -766,7 +779,8 @@ __global__ __launch_bounds__(kWinThreads) void k_win_chase(double* H, int64_t ld
     const int ws = G.ws, wc = G.we - G.ws + 1;
     const int nbc = min(kChain, b - c * kChain), i0 = c * kChain;
     const int lu = u - ws, ll = l - ws;  // the block's last and first rows in window coordinates
-    const int lane = threadIdx.x & 63, j = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int j = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     {
         // wave j loads window rows j, j + 8, ...: all its loads in flight together; entries
         // more than three below the diagonal are zero (Hessenberg plus bulges)
@@ -811,52 +825,68 @@ __global__ __launch_bounds__(kWinThreads) void k_win_chase(double* H, int64_t ld
             double x, y, z, beta;
             intro_xyz(Hw, kWinLd, ll, g->s[i0 + j], g->t[i0 + j], &x, &y, &z);
             house3(x, y, z, &tau, &w1, &w2, &beta);
+            tau = wave_first(tau);
+            w1 = wave_first(w1);
+            w2 = wave_first(w2);
         }
         const bool three = K + 2 <= lu;
-        // left side: rows K..K+2 of window columns K..wc-1, and of U^T (all wc columns)
+        // left side: rows K..K+2 of window columns K..wc-1, then of U^T's columns lo..hi
         if (act && tau != 0.0) {
-            const int q0 = K + lane, q1 = K + lane + 64, u0 = lane, u1 = lane + 64;
-            const bool h0 = q0 < wc, h1 = q1 < wc, g0 = u0 < wc, g1 = u1 < wc;
-            double* pa = Hw + K * kWinLd + q0;
-            double* pb = Hw + K * kWinLd + q1;
-            double* pc = Uw + K * kWinLd + u0;
-            double* pd = Uw + K * kWinLd + u1;
-            double a[4][3];
+            const int nh = wc - K, lo = win_ut_lo(K), n = nh + win_ut_hi(K, wc) - lo + 1;
+            double* p[2];
+            double a[2][3];
 #pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                const bool row = m < 2 || three;
-                a[0][m] = (h0 && row) ? pa[m * kWinLd] : 0.0;
-                a[1][m] = (h1 && row) ? pb[m * kWinLd] : 0.0;
-                a[2][m] = (g0 && row) ? pc[m * kWinLd] : 0.0;
-                a[3][m] = (g1 && row) ? pd[m * kWinLd] : 0.0;
+            for (int h = 0; h < 2; ++h) {
+                // window column K + t, else U^T column lo + t - nh (idle lanes: lo or hi)
+                const int t = lane + 64 * h;
+                const int cu = lo + min(max(t - nh, 0), n - nh - 1);
+                const int off = t < nh ? K + t : kWin * kWinLd + cu;
+                p[h] = lds + K * kWinLd + off;
             }
-            if (h0) win_refl3(pa, kWinLd, three, tau, w1, w2, a[0][0], a[0][1], a[0][2]);
-            if (h1) win_refl3(pb, kWinLd, three, tau, w1, w2, a[1][0], a[1][1], a[1][2]);
-            if (g0) win_refl3(pc, kWinLd, three, tau, w1, w2, a[2][0], a[2][1], a[2][2]);
-            if (g1) win_refl3(pd, kWinLd, three, tau, w1, w2, a[3][0], a[3][1], a[3][2]);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                a[h][0] = p[h][0];
+                a[h][1] = p[h][kWinLd];
+                const double x2 = p[h][2 * kWinLd];
+                a[h][2] = three ? x2 : 0.0;
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                if (lane + 64 * h < n) win_refl3(p[h], kWinLd, three, tau, w1, w2, a[h][0], a[h][1], a[h][2]);
         }
         __syncthreads();
         // right side: rows 0..K of columns K..K+2, then (every lane) rows K+1..K+3 and the
         // next reflector from column K
         if (act) {
-            const bool r0 = tau != 0.0 && lane <= K, r1 = tau != 0.0 && lane + 64 <= K;
+            const bool hi_rows = K >= 64;
             double* pa = Hw + lane * kWinLd + K;
             double* pb = Hw + (lane + 64) * kWinLd + K;
             double a[2][3], hr[3][3];
-#pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                const bool col = m < 2 || three;
-                a[0][m] = (r0 && col) ? pa[m] : 0.0;
-                a[1][m] = (r1 && col) ? pb[m] : 0.0;
+            a[0][0] = pa[0];
+            a[0][1] = pa[1];
+            const double x02 = pa[2];
+            a[0][2] = three ? x02 : 0.0;
+            if (hi_rows) {
+                a[1][0] = pb[0];
+                a[1][1] = pb[1];
+                const double x12 = pb[2];
+                a[1][2] = three ? x12 : 0.0;
             }
+            const bool full = K + 3 <= lu;  // all three rows below the bulge inside the block
 #pragma unroll
             for (int rr = 0; rr < 3; ++rr)
 #pragma unroll
-                for (int cc = 0; cc < 3; ++cc)
-                    hr[rr][cc] = (K + 1 + rr <= lu && (cc < 2 || three)) ? Hw[(K + 1 + rr) * kWinLd + K + cc] : 0.0;
-            if (r0) win_refl3(pa, 1, three, tau, w1, w2, a[0][0], a[0][1], a[0][2]);
-            if (r1) win_refl3(pb, 1, three, tau, w1, w2, a[1][0], a[1][1], a[1][2]);
+                for (int cc = 0; cc < 3; ++cc) hr[rr][cc] = Hw[(K + 1 + rr) * kWinLd + K + cc];
+            if (!full) {
+#pragma unroll
+                for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc)
+                        if (!(K + 1 + rr <= lu && (cc < 2 || three))) hr[rr][cc] = 0.0;
+            }
             if (tau != 0.0) {
+                if (lane <= K) win_refl3(pa, 1, three, tau, w1, w2, a[0][0], a[0][1], a[0][2]);
+                if (hi_rows && lane + 64 <= K) win_refl3(pb, 1, three, tau, w1, w2, a[1][0], a[1][1], a[1][2]);
 #pragma unroll
                 for (int rr = 0; rr < 3; ++rr) {
                     const double q = tau * (hr[rr][0] + w1 * hr[rr][1] + w2 * hr[rr][2]);
@@ -868,20 +898,22 @@ __global__ __launch_bounds__(kWinThreads) void k_win_chase(double* H, int64_t ld
             const int kn = K + 1;
             double tn = 0.0, w1n = 0.0, w2n = 0.0, beta = 0.0;
             if (kn <= lu - 1) house3(hr[0][0], hr[1][0], kn + 2 <= lu ? hr[2][0] : 0.0, &tn, &w1n, &w2n, &beta);
-            if (tn != 0.0) {
+            tau = wave_first(tn);
+            w1 = wave_first(w1n);
+            w2 = wave_first(w2n);
+            if (tau != 0.0) {
                 hr[0][0] = beta;
                 hr[1][0] = 0.0;
                 hr[2][0] = 0.0;
             }
-            // every lane stores the same values
+            if (lane == 0) {
 #pragma unroll
-            for (int rr = 0; rr < 3; ++rr)
+                for (int rr = 0; rr < 3; ++rr)
 #pragma unroll
-                for (int cc = 0; cc < 3; ++cc)
-                    if (K + 1 + rr <= lu && (cc < 2 || three)) Hw[(K + 1 + rr) * kWinLd + K + cc] = hr[rr][cc];
-            tau = tn;
-            w1 = w1n;
-            w2 = w2n;
+                    for (int cc = 0; cc < 3; ++cc)
+                        if (full || (K + 1 + rr <= lu && (cc < 2 || three)))
+                            Hw[(K + 1 + rr) * kWinLd + K + cc] = hr[rr][cc];
+            }
         }
         __syncthreads();
     }

@@ -11,7 +11,8 @@
 //    with the other one falling between its parts (order: near rows, near columns, far
 //    rows, far columns);
 //  - the zero pattern of a window's orthogonal factor, propagated through the round's
-//    reflector positions, stays inside the band the products skip outside of.
+//    reflector positions, stays inside the band the products skip outside of, and the
+//    rows a reflector mixes are zero outside the columns the chase updates.
 #include <algorithm>
 #include <cstdio>
 #include <vector>
@@ -129,6 +130,14 @@ static void check_band(int l, int u, int b) {
                     const int k = l + rel - kSep * j;
                     if (k < l || k > u - 1) continue;
                     const int K = k - ws, n = k + 2 <= u ? 3 : 2;
+                    const int lo = win_ut_lo(K), hi = win_ut_hi(K, wc);
+                    CHECK((wc - K) + (hi - lo + 1) <= 128, "left side of %d columns at K %d", (wc - K) + (hi - lo + 1), K);
+                    for (int q = 0; q < wc; ++q)
+                        if (q < lo || q > hi)
+                            for (int m = 0; m < n; ++m)
+                                CHECK(!P[(K + m) * kWin + q],
+                                      "factor row %d nonzero in column %d outside [%d, %d] (chain %d, t0 %d, s %d)",
+                                      K + m, q, lo, hi, c, t0, s);
                     for (int q = 0; q < wc; ++q) {
                         unsigned char v = 0;
                         for (int m = 0; m < n; ++m) v |= P[(K + m) * kWin + q];
