@@ -34,6 +34,14 @@ __host__ __device__ constexpr int win_ut_lo(int K) { return K > kAdvance + 1 ? K
 __host__ __device__ constexpr int win_ut_hi(int K, int wc) { return K + 2 + 2 * kChain < wc - 1 ? K + 2 + 2 * kChain : wc - 1; }
 static_assert(kWin + 2 * kChain + 3 <= 128, "a chase step's left side fits two columns per lane");
 
+// LDS of one chain's chase, in doubles: the window and U^T (kWin rows of stride kWinLd
+// each) and a tail of kWin past U^T's last row. A step issues its loads unmasked, lanes
+// without work included: the left side reads rows K..K+2 of window columns up to kWin - 1
+// and of U^T columns up to kWin - 1 (K <= kWin - 2, so up to row kWin of U^T), the right
+// side rows up to 127 of columns K..K+2 and rows K+1..K+3 of those columns; all of it
+// lies below kWinLds.
+constexpr int kWinLds = 2 * kWin * kWinLd + kWin;
+
 struct WinGeom {
     int ws, we, active;
 };

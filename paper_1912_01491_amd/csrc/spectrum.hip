@@ -765,8 +765,6 @@ __device__ __forceinline__ double wave_first(double x) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-constexpr int kWinLds = 2 * kWin * kWinLd + kWin;  // window, U^T, and the tail past U^T's last row
-
 __global__ __launch_bounds__(kWinThreads) void k_win_chase(double* H, int64_t ld, int l, int u, int b, int t0,
                                                            QrGlobal* g, double* Ut_all) {
     __shared__ double lds[kWinLds];

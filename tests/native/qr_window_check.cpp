@@ -12,7 +12,9 @@
 //    rows, far columns);
 //  - the zero pattern of a window's orthogonal factor, propagated through the round's
 //    reflector positions, stays inside the band the products skip outside of, and the
-//    rows a reflector mixes are zero outside the columns the chase updates.
+//    rows a reflector mixes are zero outside the columns the chase updates;
+//  - every LDS load a chase step issues (unmasked, idle lanes included) lies inside the
+//    chase's LDS array.
 #include <algorithm>
 #include <cstdio>
 #include <vector>
@@ -132,6 +134,14 @@ static void check_band(int l, int u, int b) {
                     const int K = k - ws, n = k + 2 <= u ? 3 : 2;
                     const int lo = win_ut_lo(K), hi = win_ut_hi(K, wc);
                     CHECK((wc - K) + (hi - lo + 1) <= 128, "left side of %d columns at K %d", (wc - K) + (hi - lo + 1), K);
+                    // the chase's unmasked LDS loads of this step (window at 0, U^T at kWin kWinLd):
+                    // left side rows K..K+2 of window columns K..wc-1 and of U^T columns lo..hi;
+                    // right side rows 0..63 (and 64..127 once K >= 64) of columns K..K+2, and
+                    // rows K+1..K+3 of those columns
+                    const int last_left = std::max((K + 2) * kWinLd + wc - 1, kWin * kWinLd + (K + 2) * kWinLd + hi);
+                    const int last_right = std::max((K >= 64 ? 127 : 63) * kWinLd + K + 2, (K + 3) * kWinLd + K + 2);
+                    CHECK(K >= 0 && K <= wc - 2 && std::max(last_left, last_right) < kWinLds,
+                          "chase LDS read at %d of %d (K %d, wc %d)", std::max(last_left, last_right), kWinLds, K, wc);
                     for (int q = 0; q < wc; ++q)
                         if (q < lo || q > hi)
                             for (int m = 0; m < n; ++m)
