@@ -571,24 +571,28 @@ __global__ __launch_bounds__(1024) void k_qr_init(const double* H, int64_t ld, i
     }
 }
 
-// The largest k in [1, u] with a negligible subdiagonal entry (the test of qr_eigs, n the
-// order of the whole matrix).
+// Whether subdiagonal entry k is negligible (the test of qr_eigs, n the order of the whole
+// matrix, its the sweeps since the last split).
+__device__ bool qr_negligible(const double* H, int64_t ld, int k, int n, int its, double anorm) {
+    const double sd = fabs(H[(int64_t)k * ld + k - 1]);
+    double tst = fabs(H[(int64_t)(k - 1) * ld + k - 1]) + fabs(H[(int64_t)k * ld + k]);
+    const double floor_scale = its >= 20 ? sqrt((double)n) * anorm : (its >= 10 ? anorm : 0.0);
+    tst = tst == 0.0 ? fmax(anorm, floor_scale) : fmax(tst, floor_scale);
+    return sd <= DBL_EPSILON * tst;
+}
+
+// The largest k in [1, u] with a negligible subdiagonal entry.
 __global__ void k_qr_scan(const double* H, int64_t ld, int n, QrGlobal* g) {
     const int k = 1 + blockIdx.x * blockDim.x + threadIdx.x;
     const int u = g->u;
     if (k > u) return;
-    const double sd = fabs(H[(int64_t)k * ld + k - 1]);
-    double tst = fabs(H[(int64_t)(k - 1) * ld + k - 1]) + fabs(H[(int64_t)k * ld + k]);
-    const int its = g->its;
-    const double floor_scale = its >= 20 ? sqrt((double)n) * g->anorm : (its >= 10 ? g->anorm : 0.0);
-    tst = tst == 0.0 ? fmax(g->anorm, floor_scale) : fmax(tst, floor_scale);
-    if (sd <= DBL_EPSILON * tst) atomicMax(&g->split, k);
+    if (qr_negligible(H, ld, k, n, g->its, g->anorm)) atomicMax(&g->split, k);
 }
 
 // One decision on the bottom block [split, u]: the eigenvalues of a 1 x 1 or 2 x 2
 // block, a whole small block by qr_eigs, or the set-up of a device-wide sweep
 // (the shifts, eigenvalues of the trailing block).
-__global__ __launch_bounds__(kQrThreads) void k_qr_decide(double* H, int64_t ld, QrGlobal* g, double2* lam) {
+__global__ __launch_bounds__(kQrThreads) void k_qr_decide(double* H, int64_t ld, int n, QrGlobal* g, double2* lam) {
     __shared__ QrCtl outer, inner;
     __shared__ double sub[kWideShiftDim * kWideShiftDim];
     __shared__ double2 subev[kWideShiftDim];
@@ -605,15 +609,32 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_decide(double* H, int64_t ld,
     const int u = sh_u, l = sh_l;
     if (l >= u - 1) {
         if (tid == 0) {
-            if (l > 0) H[(int64_t)l * ld + l - 1] = 0.0;
-            if (l == u) {
-                lam[u] = make_double2(H[(int64_t)u * ld + u], 0.0);
-                g->u = u - 1;
-            } else {
-                eig2(H[(int64_t)(u - 1) * ld + u - 1], H[(int64_t)(u - 1) * ld + u], H[(int64_t)u * ld + u - 1],
-                     H[(int64_t)u * ld + u], &lam[u - 1], &lam[u]);
-                g->u = u - 2;
+            // the bottom 1 x 1 or 2 x 2 block, then the next ones for as long as the new bottom
+            // splits off again: the passes a scan and this branch would make next (after a
+            // deflation its = 0, and the largest negligible k in [1, v] is v or v - 1 exactly
+            // when these tests pass), taken here without a round trip to the host
+            int v = u, k = l;
+            for (;;) {
+                if (k > 0) H[(int64_t)k * ld + k - 1] = 0.0;
+                if (k == v) {
+                    lam[v] = make_double2(H[(int64_t)v * ld + v], 0.0);
+                } else {
+                    eig2(H[(int64_t)(v - 1) * ld + v - 1], H[(int64_t)(v - 1) * ld + v], H[(int64_t)v * ld + v - 1],
+                         H[(int64_t)v * ld + v], &lam[v - 1], &lam[v]);
+                }
+                v = k - 1;
+                if (v <= 0) {
+                    k = 0;  // rows 0..v: a 1 x 1 block (v = 0) or nothing left (v < 0)
+                    if (v < 0) break;
+                } else if (qr_negligible(H, ld, v, n, 0, g->anorm)) {
+                    k = v;
+                } else if (v == 1 || qr_negligible(H, ld, v - 1, n, 0, g->anorm)) {
+                    k = v - 1;
+                } else {
+                    break;
+                }
             }
+            g->u = v;
             g->its = 0;
             g->split = 0;
             g->action = 0;
@@ -1432,7 +1453,7 @@ int lb_impl_spectrum(lb_ctx* c, int M, const double* Q, int64_t ldq, double* lam
             hipLaunchKernelGGL(k_qr_scan, dim3(lb_blocks(u, 256)), dim3(256), 0, s, (const double*)H, ld, M, g);
             LB_CHECK_LAUNCH();
         }
-        hipLaunchKernelGGL(k_qr_decide, dim3(1), dim3(kQrThreads), 0, s, H, ld, g, (double2*)lam);
+        hipLaunchKernelGGL(k_qr_decide, dim3(1), dim3(kQrThreads), 0, s, H, ld, M, g, (double2*)lam);
         LB_CHECK_LAUNCH();
         LB_HIP(hipMemcpyAsync(hg, g, 8 * sizeof(int) + 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
         LB_HIP(hipStreamSynchronize(s));
