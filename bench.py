@@ -1110,7 +1110,7 @@ def pmc_assembly(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d requested)"
+        print("bench.py measures one GPU only: the library has no multi-GPU path (--gpus %d requested)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.pmc_probe:
