@@ -48,7 +48,7 @@ extern "C" {
 #define LB_ERR_NOT_HERMITIAN (-2) /* LB_CHECK_HERMITIAN was set and an input is not Hermitian */
 #define LB_ERR_OOM (-3)           /* the context workspace could not be allocated */
 #define LB_ERR_DEVICE (-4)        /* a HIP call failed; see lb_last_error() */
-#define LB_ERR_UNSUPPORTED (-5)   /* valid request this build cannot serve (e.g. too large) */
+#define LB_ERR_UNSUPPORTED (-5)   /* valid request the library cannot serve (e.g. too large) */
 #define LB_ERR_ADMISSION (-6)     /* a serving request does not fit the server's memory budget */
 #define LB_ERR_NO_CONVERGENCE (-7) /* an iterative solve stopped at its iteration limit before its
                                       tolerance; the outputs hold the last iterate */
