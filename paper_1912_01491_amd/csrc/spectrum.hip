@@ -780,6 +780,8 @@ __device__ __forceinline__ void win_refl3(double* a, int ld, bool three, double 
     if (three) a[2 * ld] = a2 - r * w2;
 }
 
+// x as the wave's first active lane holds it, in scalar registers from here on; callers
+// pass a value that is already the same in every lane (all lanes compute it alike).
 __device__ __forceinline__ double wave_first(double x) {
     const long long v = __double_as_longlong(x);
     const unsigned lo = __builtin_amdgcn_readfirstlane((int)v), hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
